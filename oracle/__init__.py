@@ -1,0 +1,219 @@
+"""FP64 CPU oracle for stochastic texture filtering -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never calls it, and
+it shares no code with the HIP path.
+
+This module is argument marshalling around ``liboracle.so`` (compiled from the
+C sources next to it by ``oracle/build.py``); all arithmetic is in C.
+Every function states the passage of the paper it follows in the C source.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+# storage formats / filters / modes (the oracle's own numbering)
+F32, F16, BF16, FP8_E4M3, U8 = 0, 1, 2, 3, 4
+LINEAR, CUBIC = 0, 1
+DET, STOCH, STOCH_REUSE = 0, 1, 2
+BAD_INDEX = -(2 ** 31)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError("oracle/liboracle.so is not built; run oracle/build.py")
+        _lib = C.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _declare(L):
+    vp, i32, i64, u32, u64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+    L.orc_pcg.argtypes, L.orc_pcg.restype = [u32], u32
+    L.orc_seed_key.argtypes, L.orc_seed_key.restype = [u64], u32
+    L.orc_uniform.argtypes, L.orc_uniform.restype = [u64, u32, u32], C.c_float
+    L.orc_decode.argtypes, L.orc_decode.restype = [i32, vp, i64], dbl
+    L.orc_kernel_tent.argtypes, L.orc_kernel_tent.restype = [dbl], dbl
+    L.orc_kernel_bspline.argtypes, L.orc_kernel_bspline.restype = [dbl], dbl
+    L.orc_axis_weights.argtypes, L.orc_axis_weights.restype = [i32, dbl, vp], None
+    L.orc_select.argtypes, L.orc_select.restype = [i32, C.c_float, C.c_float], i32
+    L.orc_max_threads.argtypes, L.orc_max_threads.restype = [], i32
+    L.orc_filter2d.argtypes = [vp, i32, i32, i32, i32, vp, i64, i32, i32, u64, vp, vp, i32]
+    L.orc_filter2d.restype = i32
+    L.orc_filter2d_brute.argtypes = [vp, i32, i32, i32, i32, vp, i64, i32, vp]
+    L.orc_filter2d_brute.restype = i32
+    L.orc_grid_create.argtypes = [i32, i32, i32, i32, i64, vp, vp, dbl]
+    L.orc_grid_create.restype = vp
+    L.orc_grid_destroy.argtypes, L.orc_grid_destroy.restype = [vp], None
+    L.orc_grid_texel.argtypes, L.orc_grid_texel.restype = [vp, i32, i32, i32], dbl
+    L.orc_filter3d.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, i32]
+    L.orc_filter3d.restype = i32
+    L.orc_filter3d_at.argtypes = [vp, vp, vp, i64, i32, i32, u64, vp, vp, i32]
+    L.orc_filter3d_at.restype = i32
+    L.orc_filter3d_brute.argtypes = [vp, vp, i64, i32, vp]
+    L.orc_filter3d_brute.restype = i32
+    L.orc_filter3d_moments.argtypes = [vp, vp, i64, i32, vp, vp, i32]
+    L.orc_filter3d_moments.restype = i32
+    if hasattr(L, "orc_shade"):
+        _declare_shade(L)
+    if hasattr(L, "orc_ntex_decode"):
+        _declare_neural(L)
+
+
+def _declare_shade(L):
+    pass
+
+
+def _declare_neural(L):
+    pass
+
+
+# ----------------------------------------------------------------------------
+# scalar helpers
+# ----------------------------------------------------------------------------
+def pcg(x: int) -> int:
+    return lib().orc_pcg(x & 0xFFFFFFFF)
+
+
+def uniform(seed: int, qid: int, axis: int) -> float:
+    return lib().orc_uniform(seed, qid, axis)
+
+
+def kernel_tent(d: float) -> float:
+    return lib().orc_kernel_tent(d)
+
+
+def kernel_bspline(d: float) -> float:
+    return lib().orc_kernel_bspline(d)
+
+
+def axis_weights(filt: int, t: float) -> np.ndarray:
+    w = np.zeros(4, np.float64)
+    lib().orc_axis_weights(filt, float(t), _p(w))
+    return w
+
+
+def select(filt: int, t: float, u: float) -> int:
+    return lib().orc_select(filt, float(np.float32(t)), float(np.float32(u)))
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()
+
+
+def decode(fmt: int, raw: np.ndarray) -> np.ndarray:
+    raw = np.ascontiguousarray(raw)
+    out = np.empty(raw.size, np.float64)
+    L = lib()
+    for k in range(raw.size):
+        out[k] = L.orc_decode(fmt, _p(raw), k)
+    return out.reshape(raw.shape)
+
+
+# ----------------------------------------------------------------------------
+# 2D textures
+# ----------------------------------------------------------------------------
+def filter2d(tex: np.ndarray, fmt: int, uv: np.ndarray, filt: int, mode: int, seed: int = 0,
+             want_index: bool = True, nthreads: int = 0):
+    """tex: (H, W, C) raw texels of the storage format; uv: (n, 2) float32.
+    Returns (values (n, C) float64, indices (n, 2) int32 or None)."""
+    tex = np.ascontiguousarray(tex)
+    H, W, Ch = tex.shape
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    n = uv.shape[0]
+    out = np.empty((n, Ch), np.float64)
+    idx = np.empty((n, 2), np.int32) if (want_index and mode != DET) else None
+    rc = lib().orc_filter2d(_p(tex), W, H, Ch, fmt, _p(uv), n, filt, mode, seed, _p(out), _p(idx), nthreads)
+    if rc != 0:
+        raise ValueError("orc_filter2d rejected its arguments")
+    return out, idx
+
+
+def filter2d_brute(tex: np.ndarray, fmt: int, uv: np.ndarray, filt: int) -> np.ndarray:
+    tex = np.ascontiguousarray(tex)
+    H, W, Ch = tex.shape
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    out = np.empty((uv.shape[0], Ch), np.float64)
+    lib().orc_filter2d_brute(_p(tex), W, H, Ch, fmt, _p(uv), uv.shape[0], filt, _p(out))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# 3D sparse grids
+# ----------------------------------------------------------------------------
+class Grid:
+    """Oracle view of a sparse grid: leaf origins (n, 3) int32 and leaf values
+    (n, 8, 8, 8) raw storage (z, y, x order, x fastest)."""
+
+    def __init__(self, dims, fmt: int, origins: np.ndarray, values: np.ndarray, background: float = 0.0):
+        self.origins = np.ascontiguousarray(origins, dtype=np.int32)
+        self.values = np.ascontiguousarray(values)
+        self.fmt = fmt
+        self.dims = tuple(int(d) for d in dims)
+        h = lib().orc_grid_create(self.dims[0], self.dims[1], self.dims[2], fmt, self.origins.shape[0],
+                                  _p(self.origins), _p(self.values), float(background))
+        if not h:
+            raise ValueError("orc_grid_create rejected the leaf list")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_grid_destroy(h)
+            self._h = None
+
+    def texel(self, x: int, y: int, z: int) -> float:
+        return lib().orc_grid_texel(self._h, x, y, z)
+
+    def filter(self, p: np.ndarray, filt: int, mode: int, seed: int = 0, want_index: bool = True,
+               nthreads: int = 0):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        n = p.shape[0]
+        out = np.empty(n, np.float64)
+        idx = np.empty((n, 3), np.int32) if (want_index and mode != DET) else None
+        rc = lib().orc_filter3d(self._h, _p(p), n, filt, mode, seed, _p(out), _p(idx), nthreads)
+        if rc != 0:
+            raise ValueError("orc_filter3d failed")
+        return out, idx
+
+    def filter_at(self, p: np.ndarray, qids: np.ndarray, filt: int, mode: int, seed: int = 0,
+                  nthreads: int = 0):
+        """Filter the queries p[qids] as members of the whole batch p (the
+        random draw of a query depends on its index in the batch)."""
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        qids = np.ascontiguousarray(qids, dtype=np.int64)
+        m = qids.shape[0]
+        out = np.empty(m, np.float64)
+        idx = np.empty((m, 3), np.int32) if mode != DET else None
+        rc = lib().orc_filter3d_at(self._h, _p(p), _p(qids), m, filt, mode, seed, _p(out), _p(idx), nthreads)
+        if rc != 0:
+            raise ValueError("orc_filter3d_at failed")
+        return out, idx
+
+    def filter_brute(self, p: np.ndarray, filt: int) -> np.ndarray:
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        out = np.empty(p.shape[0], np.float64)
+        lib().orc_filter3d_brute(self._h, _p(p), p.shape[0], filt, _p(out))
+        return out
+
+    def moments(self, p: np.ndarray, filt: int, nthreads: int = 0):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        n = p.shape[0]
+        mean = np.empty(n, np.float64)
+        var = np.empty(n, np.float64)
+        lib().orc_filter3d_moments(self._h, _p(p), n, filt, _p(mean), _p(var), nthreads)
+        return mean, var

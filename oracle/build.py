@@ -1,0 +1,29 @@
+"""Compile the C oracle into oracle/liboracle.so (test infrastructure only).
+
+The sampling decisions are pinned binary32 arithmetic, so the file is built
+without floating-point contraction and without fast-math.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["oracle.c", "shade.c", "neural.c"]
+TARGET = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+           "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard",
+           "-Wall", "-Wextra", "-Wno-unused-parameter",
+           "-o", TARGET + ".tmp"] + srcs + ["-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(TARGET + ".tmp", TARGET)
+    return TARGET
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

@@ -1,0 +1,549 @@
+/*
+ * oracle.c -- plain, slow, obviously-correct CPU reference for stochastic
+ * texture filtering (Fajardo, Wronski, Salvi, Pharr, "Stochastic Texture
+ * Filtering", 2023).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no code, header, table or constant
+ * generator with the HIP path.
+ *
+ * Arithmetic conventions
+ *   - Every filtered *value* (weights, sums, variances) is computed in IEEE
+ *     binary64 from the exact binary32 query coordinate.
+ *   - Every sampling *decision* (which tap is taken) is computed in pinned
+ *     binary32: each operation rounded to nearest-even, no fused multiply-add
+ *     (this file is compiled with -ffp-contract=off), subnormals kept.  The
+ *     decision therefore has one unique answer for a given query and seed.
+ *   - Texels are decoded exactly from their storage format.
+ *
+ * Conventions where the paper leaves a choice (each is listed with its reason
+ * in the design notes of the repository):
+ *   - 2D raster position x = fl32(fl32(uv * W) - 0.5): texel centres sit at
+ *     half-integers of uv*W, as in the paper's discrete Gaussian listing
+ *     (supplement, "Real-time discrete and filter importance sampling").
+ *   - 3D positions are already in voxel index space, voxel k centred at k, as
+ *     in the tricubic listing (supplement, "Sampling a cubic B-spline kernel
+ *     in 3D").
+ *   - Cubic B-spline taps of cell i are i-1..i+2 (Eq. bicubic-bspline-texfilt
+ *     read with the offset K_bs(x - (i+k)) that the weight polynomials of the
+ *     bicubic listing imply).
+ *   - One fresh uniform per axis from a counter-based hash (no sample reuse;
+ *     reuse, Eq. uniform-sample-reuse, is an optimisation of the same
+ *     distribution and is kept here as the `reuse' variant for distribution
+ *     tests only).
+ *   - 2D addressing clamps each tap to the texture; 3D addressing returns the
+ *     grid's background value outside the domain and in inactive leaves.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* storage formats */
+enum { ORC_F32 = 0, ORC_F16 = 1, ORC_BF16 = 2, ORC_FP8_E4M3 = 3, ORC_U8 = 4 };
+/* filters and modes */
+enum { ORC_LINEAR = 0, ORC_CUBIC = 1 };
+enum { ORC_DET = 0, ORC_STOCH = 1, ORC_STOCH_REUSE = 2 };
+
+#define ORC_BAD_INDEX ((int32_t)0x80000000)
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based random numbers.                                             */
+/* The paper draws its per-lookup uniforms from white or blue noise (Results, */
+/* real-time section).  A counter-based generator makes the draw a pure       */
+/* function of (seed, query, axis): the one-round PCG hash "pcg" published by */
+/* Jarzynski and Olano (JCGT 9(3), 2020), chained as                          */
+/*   s = pcg(seed_lo ^ pcg(seed_hi)),  b = pcg(s ^ qid),  h_a = pcg(b + a),  */
+/*   u_a = (h_a >> 8) * 2^-24  in [0, 1 - 2^-24].                             */
+/* ------------------------------------------------------------------------ */
+uint32_t orc_pcg(uint32_t x)
+{
+    uint32_t state = x * 747796405u + 2891336453u;
+    uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+uint32_t orc_seed_key(uint64_t seed)
+{
+    return orc_pcg((uint32_t)seed ^ orc_pcg((uint32_t)(seed >> 32)));
+}
+
+float orc_uniform(uint64_t seed, uint32_t qid, uint32_t axis)
+{
+    uint32_t b = orc_pcg(orc_seed_key(seed) ^ qid);
+    uint32_t h = orc_pcg(b + axis);
+    return (float)(h >> 8) * 0x1p-24f;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact texel decoding from the storage format to binary64.                 */
+/* ------------------------------------------------------------------------ */
+static double orc_half_to_double(uint16_t h)
+{
+    int sign = (h >> 15) & 1, e = (h >> 10) & 31, m = h & 1023;
+    double v;
+    if (e == 0)
+        v = ldexp((double)m, -24);                 /* subnormal: m * 2^-24 */
+    else if (e == 31)
+        v = m ? NAN : INFINITY;
+    else
+        v = ldexp((double)(1024 + m), e - 25);     /* (1 + m/1024) * 2^(e-15) */
+    return sign ? -v : v;
+}
+
+static double orc_bf16_to_double(uint16_t b)
+{
+    /* bfloat16 is the upper half of a binary32 word */
+    uint32_t w = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &w, 4);
+    return (double)f;
+}
+
+static double orc_e4m3_to_double(uint8_t q)
+{
+    /* OCP 8-bit E4M3 ("FN"): bias 7, no infinities, S.1111.111 is NaN */
+    int sign = (q >> 7) & 1, e = (q >> 3) & 15, m = q & 7;
+    double v;
+    if (e == 15 && m == 7)
+        v = NAN;
+    else if (e == 0)
+        v = ldexp((double)m, -9);                  /* m/8 * 2^-6 */
+    else
+        v = ldexp((double)(8 + m), e - 10);        /* (1 + m/8) * 2^(e-7) */
+    return sign ? -v : v;
+}
+
+double orc_decode(int fmt, const void* base, int64_t i)
+{
+    switch (fmt) {
+    case ORC_F32: { float f; memcpy(&f, (const char*)base + 4 * i, 4); return (double)f; }
+    case ORC_F16: { uint16_t h; memcpy(&h, (const char*)base + 2 * i, 2); return orc_half_to_double(h); }
+    case ORC_BF16: { uint16_t h; memcpy(&h, (const char*)base + 2 * i, 2); return orc_bf16_to_double(h); }
+    case ORC_FP8_E4M3: return orc_e4m3_to_double(((const uint8_t*)base)[i]);
+    case ORC_U8: return (double)((const uint8_t*)base)[i] / 255.0;   /* UNORM */
+    }
+    return NAN;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Filter kernels (supplement, "Filter Kernels"), binary64.                  */
+/* ------------------------------------------------------------------------ */
+double orc_kernel_tent(double d)   /* K_1 */
+{
+    d = fabs(d);
+    return d < 1.0 ? 1.0 - d : 0.0;
+}
+
+double orc_kernel_bspline(double d)   /* K_bs, Eq. cubic-bspline */
+{
+    d = fabs(d);
+    if (d <= 1.0) return (4.0 - 3.0 * d * d * (2.0 - d)) / 6.0;
+    if (d <= 2.0) return (2.0 - d) * (2.0 - d) * (2.0 - d) / 6.0;
+    return 0.0;
+}
+
+/* Per-axis weights of the taps of cell i for the fractional offset t.
+ * Linear: taps i, i+1 with (1-t, t) -- the lerp of section "Linear Filters".
+ * Cubic:  taps i-1..i+2 with the B-spline weights of the bicubic listing,
+ * i.e. K_bs(t+1), K_bs(t), K_bs(1-t), K_bs(2-t); the first is written as
+ * (1-t)^3/6 rather than the listing's expanded polynomial (same value). */
+void orc_axis_weights(int filter, double t, double w[4])
+{
+    if (filter == ORC_LINEAR) {
+        w[0] = 1.0 - t; w[1] = t; w[2] = 0.0; w[3] = 0.0;
+    } else {
+        double t2 = t * t, t3 = t2 * t, s = 1.0 - t;
+        w[0] = s * s * s / 6.0;
+        w[1] = (3.0 * t3 - 6.0 * t2 + 4.0) / 6.0;
+        w[2] = (-3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0) / 6.0;
+        w[3] = t3 / 6.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cell of a binary32 coordinate.  A coordinate that is NaN, infinite or has */
+/* magnitude >= 2^24 has no cell (the query then yields NaN and the index    */
+/* INT32_MIN).  Otherwise i = floor(x) and t = x - floor(x) in binary32.     */
+/* ------------------------------------------------------------------------ */
+static int orc_cell(float x, int* i, float* t)
+{
+    if (!(fabsf(x) < 16777216.0f)) return 0;
+    float f = floorf(x);
+    *i = (int)f;
+    *t = x - f;
+    return 1;
+}
+
+/* Pinned binary32 tap choice on one axis: the "sampling arrays" rule of the  */
+/* Sampling Techniques section -- the first j whose cumulative weight exceeds */
+/* u -- applied to the per-axis filter weights.                               */
+/*   Linear: the upper tap iff u < t (the strict comparison of the bilinear   */
+/*           listing; P(upper) = t, Eq. stochastic-lerp).                     */
+/*   Cubic:  breakpoints c1 = w0, c2 = w0 + w1, c3 = 1 - w3, with            */
+/*           6*w0 = s^3, 6*w1 = 1 + 3s(1 + st), 6*w3 = t^3 (s = 1 - t),      */
+/*           i.e. the B-spline weights of Eq. cubic-bspline in a form whose   */
+/*           terms are all non-negative; j = [u>=c1] + [u>=c2] + [u>=c3].     */
+/* Returns the offset of the chosen tap from cell i (0/1 linear, -1..2 cubic).*/
+int orc_select(int filter, float t, float u)
+{
+    if (filter == ORC_LINEAR)
+        return (u < t) ? 1 : 0;
+    const float K6 = 0x1.555556p-3f;   /* (float)(1/6) */
+    float s = 1.0f - t;
+    float a0 = (s * s) * s;
+    float a1 = 1.0f + (3.0f * s) * (1.0f + s * t);
+    float a3 = (t * t) * t;
+    float c1 = a0 * K6;
+    float c2 = (a0 + a1) * K6;
+    float c3 = 1.0f - a3 * K6;
+    int j = (u >= c1) + (u >= c2) + (u >= c3);
+    return j - 1;
+}
+
+/* The paper's own sampler, for distribution tests only: the weights are     */
+/* visited in order with weighted reservoir sampling and the single uniform  */
+/* is re-used from axis to axis by the remapping of Eq.                      */
+/* uniform-sample-reuse (tricubic listing; for two taps this reduces to the  */
+/* bilinear listing).  The remapped uniform is kept below 1, which the       */
+/* binary32 remap otherwise reaches by rounding.  Arithmetic is binary32.    */
+static int orc_select_reuse(int filter, float t, float* u)
+{
+    float w[4];
+    int n, k, chosen;
+    if (filter == ORC_LINEAR) {
+        /* two taps: upper with probability t */
+        float p = t;
+        if (*u < p) { chosen = 1; *u = *u / p; }
+        else { chosen = 0; *u = (*u - p) / (1.0f - p); }
+        if (!(*u < 1.0f)) *u = 0x1.fffffep-1f;
+        return chosen;
+    }
+    float t2 = t * t;
+    w[0] = (1.0f / 6.0f) * (-t * t2 + 3 * t2 - 3 * t + 1);
+    w[1] = (1.0f / 6.0f) * (3 * t * t2 - 6 * t2 + 4);
+    w[2] = (1.0f / 6.0f) * (-3 * t * t2 + 3 * t2 + 3 * t + 1);
+    w[3] = (1.0f / 6.0f) * t * t2;
+    n = 4;
+    float sum = w[0];
+    chosen = 0;
+    for (k = 1; k < n; ++k) {
+        sum += w[k];
+        float p = w[k] / sum;
+        if (*u < p) { chosen = k; *u = *u / p; }
+        else *u = (*u - p) / (1.0f - p);
+        if (!(*u < 1.0f)) *u = 0x1.fffffep-1f;
+        if (!(*u >= 0.0f)) *u = 0.0f;
+    }
+    return chosen - 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2D textures: row-major texels, channels interleaved; tap indices clamped. */
+/* ------------------------------------------------------------------------ */
+static int orc_clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static double orc_texel2d(const void* tex, int W, int H, int C, int fmt, int x, int y, int c)
+{
+    x = orc_clampi(x, 0, W - 1);
+    y = orc_clampi(y, 0, H - 1);
+    return orc_decode(fmt, tex, ((int64_t)y * W + x) * C + c);
+}
+
+static int orc_raster2d(const float* uv, int W, int H, float* x, float* y)
+{
+    *x = uv[0] * (float)W - 0.5f;   /* two binary32 roundings, no fma */
+    *y = uv[1] * (float)H - 0.5f;
+    return 1;
+}
+
+static void orc_nan_out(double* out, int C, int32_t* idx, int dims)
+{
+    for (int c = 0; c < C; ++c) out[c] = NAN;
+    if (idx) for (int a = 0; a < dims; ++a) idx[a] = ORC_BAD_INDEX;
+}
+
+/* One 2D query.  mode: ORC_DET (separable weighted sum, Eq. filtered-texture
+ * with the tensor-product weights), ORC_STOCH (one tap per Eq.
+ * stochastic-sum), ORC_STOCH_REUSE (paper listing sampler). */
+static void orc_query2d(const void* tex, int W, int H, int C, int fmt, const float* uv,
+                        int filter, int mode, uint64_t seed, uint32_t qid, double* out, int32_t* idx)
+{
+    float x, y, tx, ty;
+    int ix, iy;
+    orc_raster2d(uv, W, H, &x, &y);
+    if (!orc_cell(x, &ix, &tx) || !orc_cell(y, &iy, &ty)) { orc_nan_out(out, C, idx, 2); return; }
+    int base = (filter == ORC_CUBIC) ? -1 : 0;
+    int ntap = (filter == ORC_CUBIC) ? 4 : 2;
+    if (mode == ORC_DET) {
+        double wx[4], wy[4];
+        orc_axis_weights(filter, (double)x - floor((double)x), wx);
+        orc_axis_weights(filter, (double)y - floor((double)y), wy);
+        for (int c = 0; c < C; ++c) {
+            double acc = 0.0;
+            for (int b = 0; b < ntap; ++b) {
+                double row = 0.0;
+                for (int a = 0; a < ntap; ++a)
+                    row += wx[a] * orc_texel2d(tex, W, H, C, fmt, ix + base + a, iy + base + b, c);
+                acc += wy[b] * row;
+            }
+            out[c] = acc;
+        }
+        return;
+    }
+    int jx, jy;
+    if (mode == ORC_STOCH) {
+        jx = orc_select(filter, tx, orc_uniform(seed, qid, 0));
+        jy = orc_select(filter, ty, orc_uniform(seed, qid, 1));
+    } else {
+        float u = orc_uniform(seed, qid, 0);
+        jx = orc_select_reuse(filter, tx, &u);
+        jy = orc_select_reuse(filter, ty, &u);
+    }
+    int sx = orc_clampi(ix + jx, 0, W - 1), sy = orc_clampi(iy + jy, 0, H - 1);
+    for (int c = 0; c < C; ++c) out[c] = orc_texel2d(tex, W, H, C, fmt, sx, sy, c);
+    if (idx) { idx[0] = sx; idx[1] = sy; }
+}
+
+static int orc_threads(int nthreads)
+{
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+int orc_max_threads(void) { return orc_threads(0); }
+
+int orc_filter2d(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n,
+                 int filter, int mode, uint64_t seed, double* out, int32_t* idx, int nthreads)
+{
+    if (W <= 0 || H <= 0 || C <= 0 || C > 4 || n < 0) return -1;
+    int nt = orc_threads(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t q = 0; q < n; ++q)
+        orc_query2d(tex, W, H, C, fmt, uv + 2 * q, filter, mode, seed, (uint32_t)q,
+                    out + q * C, idx ? idx + 2 * q : NULL);
+    return 0;
+}
+
+/* Brute-force deterministic 2D filter: every texel of a 6x6 window around the
+ * cell, weighted by the kernel itself evaluated at the texel's distance
+ * (Eq. filter-function restricted to texel centres); kernels with zero weight
+ * contribute nothing.  Independent of orc_axis_weights. */
+int orc_filter2d_brute(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n,
+                       int filter, double* out)
+{
+    for (int64_t q = 0; q < n; ++q) {
+        float x, y;
+        orc_raster2d(uv + 2 * q, W, H, &x, &y);
+        double* o = out + q * C;
+        if (!(fabsf(x) < 16777216.0f) || !(fabsf(y) < 16777216.0f)) { orc_nan_out(o, C, NULL, 0); continue; }
+        int ix = (int)floor((double)x), iy = (int)floor((double)y);
+        for (int c = 0; c < C; ++c) {
+            double acc = 0.0;
+            for (int b = iy - 2; b <= iy + 3; ++b)
+                for (int a = ix - 2; a <= ix + 3; ++a) {
+                    double w = (filter == ORC_CUBIC)
+                        ? orc_kernel_bspline((double)x - a) * orc_kernel_bspline((double)y - b)
+                        : orc_kernel_tent((double)x - a) * orc_kernel_tent((double)y - b);
+                    if (w != 0.0) acc += w * orc_texel2d(tex, W, H, C, fmt, a, b, c);
+                }
+            o[c] = acc;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3D sparse grids.  The oracle keeps the simplest possible structure: a     */
+/* dense table, one entry per 8^3 brick of the domain, holding the index of  */
+/* the stored leaf or -1.                                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct orc_grid {
+    int dim[3];
+    int nb[3];             /* bricks per axis */
+    int fmt;
+    double background;
+    int32_t* brick;        /* nb[0]*nb[1]*nb[2] entries */
+    const void* values;    /* leaf values, 512 per leaf, x fastest (borrowed) */
+} orc_grid;
+
+orc_grid* orc_grid_create(int dx, int dy, int dz, int fmt, int64_t nleaves,
+                          const int32_t* origins, const void* values, double background)
+{
+    if (dx <= 0 || dy <= 0 || dz <= 0 || nleaves < 0) return NULL;
+    orc_grid* g = (orc_grid*)calloc(1, sizeof(orc_grid));
+    if (!g) return NULL;
+    g->dim[0] = dx; g->dim[1] = dy; g->dim[2] = dz;
+    for (int a = 0; a < 3; ++a) g->nb[a] = (g->dim[a] + 7) / 8;
+    g->fmt = fmt;
+    g->background = background;
+    g->values = values;
+    int64_t nbt = (int64_t)g->nb[0] * g->nb[1] * g->nb[2];
+    g->brick = (int32_t*)malloc(sizeof(int32_t) * (size_t)nbt);
+    if (!g->brick) { free(g); return NULL; }
+    for (int64_t k = 0; k < nbt; ++k) g->brick[k] = -1;
+    for (int64_t l = 0; l < nleaves; ++l) {
+        int bx = origins[3 * l] / 8, by = origins[3 * l + 1] / 8, bz = origins[3 * l + 2] / 8;
+        if (origins[3 * l] % 8 || origins[3 * l + 1] % 8 || origins[3 * l + 2] % 8 ||
+            bx < 0 || by < 0 || bz < 0 || bx >= g->nb[0] || by >= g->nb[1] || bz >= g->nb[2]) {
+            free(g->brick); free(g); return NULL;
+        }
+        int64_t k = ((int64_t)bz * g->nb[1] + by) * g->nb[0] + bx;
+        if (g->brick[k] >= 0) { free(g->brick); free(g); return NULL; }
+        g->brick[k] = (int32_t)l;
+    }
+    return g;
+}
+
+void orc_grid_destroy(orc_grid* g)
+{
+    if (g) { free(g->brick); free(g); }
+}
+
+/* Texel at integer voxel (x,y,z): background outside the domain or in an
+ * inactive brick. */
+double orc_grid_texel(const orc_grid* g, int x, int y, int z)
+{
+    if (x < 0 || y < 0 || z < 0 || x >= g->dim[0] || y >= g->dim[1] || z >= g->dim[2])
+        return g->background;
+    int64_t k = ((int64_t)(z / 8) * g->nb[1] + (y / 8)) * g->nb[0] + (x / 8);
+    int32_t l = g->brick[k];
+    if (l < 0) return g->background;
+    return orc_decode(g->fmt, g->values, (int64_t)l * 512 + ((z % 8) * 8 + (y % 8)) * 8 + (x % 8));
+}
+
+static void orc_query3d(const orc_grid* g, const float* p, int filter, int mode, uint64_t seed,
+                        uint32_t qid, double* out, int32_t* idx)
+{
+    int i[3];
+    float t[3];
+    for (int a = 0; a < 3; ++a)
+        if (!orc_cell(p[a], &i[a], &t[a])) { orc_nan_out(out, 1, idx, 3); return; }
+    int base = (filter == ORC_CUBIC) ? -1 : 0;
+    int ntap = (filter == ORC_CUBIC) ? 4 : 2;
+    if (mode == ORC_DET) {
+        double w[3][4];
+        for (int a = 0; a < 3; ++a) orc_axis_weights(filter, (double)p[a] - floor((double)p[a]), w[a]);
+        double acc = 0.0;
+        for (int cz = 0; cz < ntap; ++cz) {
+            double plane = 0.0;
+            for (int cy = 0; cy < ntap; ++cy) {
+                double row = 0.0;
+                for (int cx = 0; cx < ntap; ++cx)
+                    row += w[0][cx] * orc_grid_texel(g, i[0] + base + cx, i[1] + base + cy, i[2] + base + cz);
+                plane += w[1][cy] * row;
+            }
+            acc += w[2][cz] * plane;
+        }
+        out[0] = acc;
+        return;
+    }
+    int v[3];
+    if (mode == ORC_STOCH) {
+        for (int a = 0; a < 3; ++a) v[a] = i[a] + orc_select(filter, t[a], orc_uniform(seed, qid, (uint32_t)a));
+    } else {
+        float u = orc_uniform(seed, qid, 0);
+        for (int a = 0; a < 3; ++a) v[a] = i[a] + orc_select_reuse(filter, t[a], &u);
+    }
+    out[0] = orc_grid_texel(g, v[0], v[1], v[2]);
+    if (idx) { idx[0] = v[0]; idx[1] = v[1]; idx[2] = v[2]; }
+}
+
+int orc_filter3d(const orc_grid* g, const float* p, int64_t n, int filter, int mode, uint64_t seed,
+                 double* out, int32_t* idx, int nthreads)
+{
+    if (!g || n < 0) return -1;
+    int nt = orc_threads(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t q = 0; q < n; ++q)
+        orc_query3d(g, p + 3 * q, filter, mode, seed, (uint32_t)q, out + q, idx ? idx + 3 * q : NULL);
+    return 0;
+}
+
+/* Stochastic samples for an explicit list of query ids (used to check a     */
+/* large GPU batch at sampled positions: the draw depends on the query's     */
+/* index within its batch).                                                   */
+int orc_filter3d_at(const orc_grid* g, const float* p, const int64_t* qids, int64_t m, int filter,
+                    int mode, uint64_t seed, double* out, int32_t* idx, int nthreads)
+{
+    if (!g || m < 0) return -1;
+    int nt = orc_threads(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t k = 0; k < m; ++k)
+        orc_query3d(g, p + 3 * qids[k], filter, mode, seed, (uint32_t)qids[k], out + k,
+                    idx ? idx + 3 * k : NULL);
+    return 0;
+}
+
+/* Brute-force deterministic 3D filter over a 6^3 window with the kernel
+ * evaluated at each voxel's distance. */
+int orc_filter3d_brute(const orc_grid* g, const float* p, int64_t n, int filter, double* out)
+{
+    for (int64_t q = 0; q < n; ++q) {
+        const float* pq = p + 3 * q;
+        if (!(fabsf(pq[0]) < 16777216.0f) || !(fabsf(pq[1]) < 16777216.0f) || !(fabsf(pq[2]) < 16777216.0f)) {
+            out[q] = NAN; continue;
+        }
+        int i0 = (int)floor((double)pq[0]), i1 = (int)floor((double)pq[1]), i2 = (int)floor((double)pq[2]);
+        double acc = 0.0;
+        for (int z = i2 - 2; z <= i2 + 3; ++z)
+            for (int y = i1 - 2; y <= i1 + 3; ++y)
+                for (int x = i0 - 2; x <= i0 + 3; ++x) {
+                    double w = (filter == ORC_CUBIC)
+                        ? orc_kernel_bspline((double)pq[0] - x) * orc_kernel_bspline((double)pq[1] - y) *
+                          orc_kernel_bspline((double)pq[2] - z)
+                        : orc_kernel_tent((double)pq[0] - x) * orc_kernel_tent((double)pq[1] - y) *
+                          orc_kernel_tent((double)pq[2] - z);
+                    if (w != 0.0) acc += w * orc_grid_texel(g, x, y, z);
+                }
+        out[q] = acc;
+    }
+    return 0;
+}
+
+/* Exact mean and variance of the single-tap estimator for each query:       */
+/* E = sum w t  (the deterministic value), Var = sum w t^2 - E^2, with the    */
+/* tensor-product tap probabilities equal to the normalised weights          */
+/* (Eqs. filtered-texture and stochastic-sum).                               */
+int orc_filter3d_moments(const orc_grid* g, const float* p, int64_t n, int filter,
+                         double* mean, double* var, int nthreads)
+{
+    if (!g || n < 0) return -1;
+    int nt = orc_threads(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t q = 0; q < n; ++q) {
+        const float* pq = p + 3 * q;
+        int i[3];
+        float t[3];
+        int ok = 1;
+        for (int a = 0; a < 3; ++a) ok &= orc_cell(pq[a], &i[a], &t[a]);
+        if (!ok) { mean[q] = NAN; var[q] = NAN; continue; }
+        double w[3][4];
+        for (int a = 0; a < 3; ++a) orc_axis_weights(filter, (double)pq[a] - floor((double)pq[a]), w[a]);
+        int base = (filter == ORC_CUBIC) ? -1 : 0, ntap = (filter == ORC_CUBIC) ? 4 : 2;
+        double m1 = 0.0, m2 = 0.0;
+        for (int cz = 0; cz < ntap; ++cz)
+            for (int cy = 0; cy < ntap; ++cy)
+                for (int cx = 0; cx < ntap; ++cx) {
+                    double wt = w[0][cx] * w[1][cy] * w[2][cz];
+                    double v = orc_grid_texel(g, i[0] + base + cx, i[1] + base + cy, i[2] + base + cz);
+                    m1 += wt * v;
+                    m2 += wt * v * v;
+                }
+        mean[q] = m1;
+        var[q] = m2 - m1 * m1;
+    }
+    return 0;
+}

@@ -1,0 +1,269 @@
+"""Seeded synthetic inputs for the filtering workloads.
+
+This module produces *inputs only* -- texels, sparse-grid leaves and query
+positions -- with numpy's own seeded generator.  It holds none of the
+filtering method's arithmetic (no filter weights, no tap selection, no
+random draws of the method), and it is the only code that the GPU path and the
+CPU oracle both consume.
+
+Workloads (sizes are the defaults; tests pass smaller ones):
+  texture2d    W x H x C texels, i.i.d. uniform [0, 1), with uniform uv
+               queries in [0, 1)^2.
+  fbm_grid     a sparse 3D voxel grid: 5-octave value-noise fBm (lacunarity 2,
+               gain 0.5) thresholded at 0.55; density = max(noise - 0.55, 0);
+               an 8^3 leaf is stored iff one of its voxels has density > 0.
+  ray_queries  query positions along random rays through the grid's bounds:
+               uniform origin in the box, uniform direction, clipped to the
+               box, n_samples stratified-jittered samples per ray, ray-major.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+# ----------------------------------------------------------------------------
+# storage-format conversion of generated values (input preparation)
+# ----------------------------------------------------------------------------
+
+
+def to_f16(x: np.ndarray) -> np.ndarray:
+    return np.asarray(x, np.float32).astype(np.float16)
+
+
+def to_bf16_bits(x: np.ndarray) -> np.ndarray:
+    """binary32 -> bfloat16 bit patterns, round to nearest even (no NaNs in
+    generated data)."""
+    b = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    rounded = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
+    return rounded.astype(np.uint16)
+
+
+def to_e4m3_bits(x: np.ndarray) -> np.ndarray:
+    """binary32 -> OCP E4M3 ("FN") bit patterns, round to nearest even,
+    saturating at +-448.  Exhaustive: picks the nearest of the 254 finite
+    codes (ties to the even mantissa)."""
+    x = np.asarray(x, np.float32).ravel()
+    codes = np.arange(256, dtype=np.uint8)
+    s = (codes >> 7) & 1
+    e = (codes >> 3) & 15
+    m = codes & 7
+    val = np.where(e == 0, m.astype(np.float64) * 2.0 ** -9,
+                   (8 + m).astype(np.float64) * np.exp2(e.astype(np.float64) - 10))
+    val = np.where(s == 1, -val, val)
+    finite = ~((e == 15) & (m == 7))
+    pos = codes[(s == 0) & finite]
+    pos_val = val[(s == 0) & finite]
+    order = np.argsort(pos_val)
+    pos, pos_val = pos[order], pos_val[order]
+    a = np.minimum(np.abs(x.astype(np.float64)), 448.0)
+    k = np.searchsorted(pos_val, a)          # pos_val[k-1] < a <= pos_val[k]
+    k = np.clip(k, 1, len(pos_val) - 1)
+    lo, hi = pos_val[k - 1], pos_val[k]
+    pick_hi = (a - lo > hi - a) | ((a - lo == hi - a) & ((pos[k] & 1) == 0))
+    pick_hi |= a == hi
+    code = np.where(pick_hi, pos[k], pos[k - 1]).astype(np.uint8)
+    code = np.where(a == 0.0, np.uint8(0), code)
+    neg = np.signbit(x) & (code != 0)
+    code = np.where(neg, code | np.uint8(0x80), code)
+    return code.astype(np.uint8)
+
+
+def to_u8(x: np.ndarray) -> np.ndarray:
+    """[0,1] -> UNORM8 (round to nearest)."""
+    return np.clip(np.rint(np.asarray(x, np.float64) * 255.0), 0, 255).astype(np.uint8)
+
+
+FORMAT_NAMES = ("f32", "f16", "bf16", "fp8_e4m3", "u8")
+
+
+def encode(x: np.ndarray, fmt: str) -> np.ndarray:
+    if fmt == "f32":
+        return np.asarray(x, np.float32)
+    if fmt == "f16":
+        return to_f16(x).view(np.uint16)
+    if fmt == "bf16":
+        return to_bf16_bits(x).reshape(np.shape(x))
+    if fmt == "fp8_e4m3":
+        return to_e4m3_bits(x).reshape(np.shape(x))
+    if fmt == "u8":
+        return to_u8(x)
+    raise ValueError(fmt)
+
+
+# ----------------------------------------------------------------------------
+# 2D texture workload
+# ----------------------------------------------------------------------------
+def texture2d(width: int = 256, height: int = 256, channels: int = 4, seed: int = 1) -> np.ndarray:
+    """(H, W, C) float32 texels i.i.d. uniform in [0, 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.random((height, width, channels), dtype=np.float32)
+
+
+def uv_queries(n: int = 65536, seed: int = 2) -> np.ndarray:
+    """(n, 2) float32 texture coordinates uniform in [0, 1)^2."""
+    rng = np.random.default_rng(seed)
+    return rng.random((n, 2), dtype=np.float32)
+
+
+# ----------------------------------------------------------------------------
+# fBm value noise and the sparse grid built from it
+# ----------------------------------------------------------------------------
+def _axis_interp(n_vox: int, period: float, offset: float):
+    """Lattice cell and smoothstep-faded weight of each voxel along one axis."""
+    x = (np.arange(n_vox, dtype=np.float64) + offset) / period
+    cell = np.floor(x).astype(np.int64)
+    f = x - cell
+    w = f * f * (3.0 - 2.0 * f)
+    return cell, w.astype(np.float32)
+
+
+class _FbmOctaves:
+    """fBm value noise on voxels.  Octave o has lattice period
+    base_period / 2^o, amplitude 0.5^o and its own lattice (seeded from seed
+    and o); lattice values are uniform in [-1, 1); interpolation is trilinear
+    with a smoothstep fade; octave o is weighted by amp0 * 0.5^o (amp0 = 0.65
+    puts about 6% of the 8^3 leaves above the 0.55 threshold at a base period
+    of 64 voxels).  The x and y interpolation passes are
+    done once per octave; z slabs are then produced on demand (with torch's
+    multi-threaded CPU element-wise ops, each op rounded separately)."""
+
+    def __init__(self, dims, base_period: float, seed: int, octaves: int = 5, amp0: float = 0.65):
+        dx, dy, dz = dims
+        self.dims = dims
+        self.parts = []
+        for o in range(octaves):
+            period = base_period / (2.0 ** o)
+            amp = amp0 * 0.5 ** o
+            rng = np.random.default_rng(seed * 1000003 + o)
+            off = rng.random(3) * period   # breaks lattice alignment across octaves
+            cx, wx = _axis_interp(dx, period, off[0])
+            cy, wy = _axis_interp(dy, period, off[1])
+            cz, wz = _axis_interp(dz, period, off[2])
+            lat = rng.random((int(cz[-1]) + 2, int(cy[-1]) + 2, int(cx[-1]) + 2), dtype=np.float32) * 2.0 - 1.0
+            a = lat[:, :, cx] * (1.0 - wx) + lat[:, :, cx + 1] * wx
+            b = a[:, cy, :] * (1.0 - wy)[None, :, None] + a[:, cy + 1, :] * wy[None, :, None]
+            self.parts.append((float(amp), torch.from_numpy(cz), torch.from_numpy(wz),
+                               torch.from_numpy(np.ascontiguousarray(b, np.float32))))
+
+    def slab(self, z0: int, z1: int) -> np.ndarray:
+        dx, dy, _ = self.dims
+        out = torch.zeros((z1 - z0, dy, dx), dtype=torch.float32)
+        for amp, cz, wz, b in self.parts:
+            c, w = cz[z0:z1], wz[z0:z1][:, None, None]
+            lo = b.index_select(0, c) * (1.0 - w)
+            hi = b.index_select(0, c + 1) * w
+            out += (lo + hi) * amp
+        return out.numpy()
+
+
+def fbm3d(dims=(512, 512, 512), base_period: float = 64.0, seed: int = 3, octaves: int = 5) -> np.ndarray:
+    """fBm value noise on all voxels, float32 array (z, y, x)."""
+    return _FbmOctaves(dims, base_period, seed, octaves).slab(0, dims[2])
+
+
+class SparseGrid:
+    """Leaves of a sparse voxel grid as plain arrays.
+
+    origins: (n, 3) int32 voxel coordinates (x, y, z) of each leaf's corner,
+             multiples of 8, sorted by (z, y, x).
+    values:  (n, 8, 8, 8) float32 densities, index [z][y][x] within the leaf.
+    dims:    domain size (x, y, z) in voxels.
+    """
+
+    def __init__(self, dims, origins, values):
+        self.dims = tuple(int(d) for d in dims)
+        self.origins = np.ascontiguousarray(origins, np.int32)
+        self.values = np.ascontiguousarray(values, np.float32)
+
+    @property
+    def n_leaves(self) -> int:
+        return int(self.origins.shape[0])
+
+    def occupancy(self) -> float:
+        nb = np.prod([(d + 7) // 8 for d in self.dims])
+        return self.n_leaves / float(nb)
+
+    def encoded(self, fmt: str) -> np.ndarray:
+        return np.ascontiguousarray(encode(self.values, fmt)).reshape(self.values.shape)
+
+    def dense(self) -> np.ndarray:
+        """(z, y, x) float32 dense field, zero where no leaf is stored."""
+        dx, dy, dz = self.dims
+        nb = [(d + 7) // 8 for d in self.dims]
+        d = np.zeros((nb[2] * 8, nb[1] * 8, nb[0] * 8), np.float32)
+        for (ox, oy, oz), v in zip(self.origins, self.values):
+            d[oz:oz + 8, oy:oy + 8, ox:ox + 8] = v
+        return d[:dz, :dy, :dx]
+
+
+def grid_from_field(field: np.ndarray, threshold: float = 0.55, z_offset: int = 0):
+    """Leaves of density max(field - threshold, 0) whose maximum is > 0.
+    field: (z, y, x) float32, every extent a multiple of 8."""
+    nz, ny, nx = field.shape
+    assert nz % 8 == 0 and ny % 8 == 0 and nx % 8 == 0
+    bz, by, bx = nz // 8, ny // 8, nx // 8
+    dens = np.maximum(field - np.float32(threshold), np.float32(0.0))
+    leaves = dens.reshape(bz, 8, by, 8, bx, 8).transpose(0, 2, 4, 1, 3, 5)
+    active = leaves.reshape(bz, by, bx, 512).max(axis=3) > 0
+    kz, ky, kx = np.nonzero(active)
+    origins = np.stack([kx * 8, ky * 8, kz * 8 + z_offset], axis=1).astype(np.int32)
+    values = np.ascontiguousarray(leaves[kz, ky, kx])
+    return origins, values
+
+
+def fbm_grid(dims=(512, 512, 512), base_period: float = 64.0, seed: int = 3, threshold: float = 0.55,
+             slab: int = 32) -> SparseGrid:
+    """Sparse grid of the thresholded fBm field, built slab by slab in z."""
+    dx, dy, dz = dims
+    assert dx % 8 == 0 and dy % 8 == 0 and dz % 8 == 0 and slab % 8 == 0
+    noise = _FbmOctaves(dims, base_period, seed)
+    origins, values = [], []
+    for z0 in range(0, dz, slab):
+        z1 = min(z0 + slab, dz)
+        o, v = grid_from_field(noise.slab(z0, z1), threshold, z_offset=z0)
+        origins.append(o)
+        values.append(v)
+    return SparseGrid(dims, np.concatenate(origins), np.concatenate(values))
+
+
+def ray_queries(dims=(512, 512, 512), n_rays: int = 65536, samples_per_ray: int = 256, seed: int = 4,
+                shuffle: bool = False) -> np.ndarray:
+    """(n_rays * samples_per_ray, 3) float32 positions in voxel index space
+    (voxel k centred at k), ray-major.  Each ray: origin uniform in the box
+    [0, dim - 1]^3, direction uniform on the sphere; the full chord of that
+    line through the box is sampled at t0 + (k + xi) (t1 - t0) / n with one
+    jitter xi per ray."""
+    rng = np.random.default_rng(seed)
+    hi = np.asarray(dims, np.float64) - 1.0
+    o = rng.random((n_rays, 3)) * hi
+    z = rng.random(n_rays) * 2.0 - 1.0
+    phi = rng.random(n_rays) * 2.0 * np.pi
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    d = np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+    d = np.where(np.abs(d) < 1e-12, 1e-12, d)
+    ta = (0.0 - o) / d
+    tb = (hi - o) / d
+    t0 = np.max(np.minimum(ta, tb), axis=1)
+    t1 = np.min(np.maximum(ta, tb), axis=1)
+    xi = rng.random(n_rays)
+    k = np.arange(samples_per_ray, dtype=np.float64)
+    out = np.empty((n_rays, samples_per_ray, 3), np.float32)
+    step = (t1 - t0) / samples_per_ray
+    for a in range(3):
+        tt = t0[:, None] + (k[None, :] + xi[:, None]) * step[:, None]
+        out[:, :, a] = (o[:, a:a + 1] + tt * d[:, a:a + 1]).astype(np.float32)
+    out = out.reshape(-1, 3)
+    np.minimum(out, hi.astype(np.float32), out=out)
+    np.maximum(out, np.float32(0.0), out=out)
+    if shuffle:
+        out = out[rng.permutation(out.shape[0])]
+    return np.ascontiguousarray(out)
+
+
+def uniform_box_queries(dims, n: int, seed: int = 5, margin: float = 2.0) -> np.ndarray:
+    """(n, 3) float32 positions uniform in [-margin, dim - 1 + margin] per
+    axis, covering the boundary and the background outside the domain."""
+    rng = np.random.default_rng(seed)
+    lo = -margin
+    hi = np.asarray(dims, np.float64) - 1.0 + margin
+    return (lo + rng.random((n, 3)) * (hi - lo)).astype(np.float32)
