@@ -1,0 +1,199 @@
+/*
+ * stf.h -- C ABI of libstf, stochastic texture filtering on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library implements the filtered texture lookup of Fajardo, Wronski,
+ * Salvi and Pharr, "Stochastic Texture Filtering" (2023): a filter is a
+ * weighted sum of texels (Eq. filtered-texture); the stochastic estimator
+ * draws one texel with probability equal to its normalised weight and returns
+ * it unweighted (Eq. stochastic-sum).  Both are provided for the linear
+ * (tent, Eq. stochastic-lerp / stochastic-bilerp) and cubic B-spline
+ * (Eq. cubic-bspline, Eq. bicubic-bspline-texfilt) filters, on dense 2D
+ * textures and on sparse 3D voxel grids, plus the filter-after-shading
+ * variant of section "Effect of Texture Filtering on Rendering"
+ * (Eqs. traditional-lighting-integral and our-lighting-integral).
+ *
+ * General rules
+ *   - Every entry point returns stf_status.  On failure nothing is launched
+ *     and stf_last_error() describes the problem.
+ *   - Query and output buffers are device memory owned by the caller.  The
+ *     library reads/writes them only from work enqueued on the caller's HIP
+ *     stream (`hip_stream`, a hipStream_t; NULL = the null stream) and keeps
+ *     no reference after the call returns.  Calls return after enqueueing;
+ *     the caller synchronises.
+ *   - Host arrays passed to create functions are copied before the call
+ *     returns and may be freed afterwards.
+ *   - Textures are owned by the library from create until stf_destroy.
+ *     Destroying a texture while work that reads it is still in flight on a
+ *     stream is a caller error.
+ *   - n == 0 is a valid no-op.  n must be < 2^31 per call.
+ *   - Random numbers: the uniform for axis a of query q (its index within the
+ *     call) is a pure function of (seed, q, a):
+ *        pcg(x): state = x*747796405 + 2891336453;
+ *                word  = ((state >> ((state >> 28) + 4)) ^ state) * 277803737;
+ *                return (word >> 22) ^ word          (all arithmetic mod 2^32)
+ *        s = pcg(lo32(seed) ^ pcg(hi32(seed)));  b = pcg(s ^ q);
+ *        u_a = (pcg(b + a) >> 8) * 2^-24             (a = 0, 1, 2 for x, y, z)
+ *     so results do not depend on launch shape, ordering or other work.
+ *   - Tap choice (stochastic mode), per axis, with i = floor(x), t = x - i in
+ *     binary32:  linear: upper tap i+1 iff u < t, else i.  Cubic: with
+ *     s = 1-t, a0 = (s*s)*s, a1 = 1 + (3*s)*(1 + s*t), a3 = (t*t)*t,
+ *     K6 = 0x1.555556p-3f: c1 = a0*K6, c2 = (a0 + a1)*K6, c3 = 1 - a3*K6,
+ *     tap = i - 1 + [u >= c1] + [u >= c2] + [u >= c3].  Every operation is a
+ *     single binary32 rounding (no fused multiply-add), so the chosen tap is
+ *     reproducible bit for bit.  ("Sampling arrays", section "Sampling
+ *     Techniques", applied per axis as in section "B-Spline and Anisotropic
+ *     Filters".)
+ *   - A query coordinate that is NaN, infinite, or of magnitude >= 2^24 after
+ *     the raster transform yields NaN in every output channel and INT32_MIN
+ *     in every index component.  It is not an error.
+ */
+#ifndef STF_H
+#define STF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stf_texture stf_texture;   /* opaque, library-owned */
+
+typedef enum {
+    STF_OK = 0,
+    STF_E_INVALID = -1,      /* bad argument; nothing launched */
+    STF_E_OOM = -2,          /* device or host allocation failed */
+    STF_E_UNSUPPORTED = -3,  /* valid request this build does not implement */
+    STF_E_DEVICE = -4,       /* a HIP runtime call failed */
+    STF_E_BUSY = -5,         /* serving: no admission possible right now */
+    STF_E_CANCELLED = -6     /* serving: request was cancelled */
+} stf_status;
+
+/* Texel storage formats.  Texels are decoded exactly to binary32 before any
+ * arithmetic (U8 is UNORM: v / 255.0f correctly rounded).  Weights and
+ * accumulation are binary32 on the device. */
+typedef enum {
+    STF_FMT_F32 = 0,
+    STF_FMT_F16 = 1,       /* IEEE binary16 */
+    STF_FMT_BF16 = 2,      /* bfloat16 */
+    STF_FMT_FP8_E4M3 = 3,  /* OCP E4M3 "FN": bias 7, no infinity, 0x7f/0xff NaN */
+    STF_FMT_U8 = 4         /* UNORM8 */
+} stf_format;
+
+typedef enum {
+    STF_LINEAR = 0,          /* bilinear (2D, 4 taps) / trilinear (3D, 8 taps) */
+    STF_CUBIC_BSPLINE = 1    /* bicubic (16 taps) / tricubic (64 taps) B-spline */
+} stf_filter_kind;
+
+typedef enum {
+    STF_DETERMINISTIC = 0,   /* weighted sum over all taps (Eq. filtered-texture) */
+    STF_STOCHASTIC = 1       /* one tap drawn with probability = weight (Eq. stochastic-sum) */
+} stf_mode;
+
+typedef enum {
+    STF_SHADE_AFTER_FILTER = 0,   /* filter the material, shade once (Eq. traditional-lighting-integral) */
+    STF_FILTER_AFTER_SHADE = 1,   /* shade every tap, filter the results (Eq. our-lighting-integral) */
+    STF_SHADE_STOCHASTIC = 2      /* shade the one sampled tap (Eq. our-lighting-integral, sampled) */
+} stf_shade_mode;
+
+/* ---------------------------------------------------------------------- */
+/* Texture creation                                                        */
+/* ---------------------------------------------------------------------- */
+
+/* Dense 2D texture with `levels` >= 1 levels.  Level l has size
+ * max(1, width >> l) x max(1, height >> l); level_texels_host[l] points to
+ * its texels, row-major (x fastest), `channels` (1..4) interleaved values
+ * per texel in format `fmt`.  Queries are normalised uv in texture space;
+ * raster position x = uv.x * W - 0.5 (binary32, two roundings), so texel
+ * centres lie at half-integers of uv * W.  Taps are clamped to the level
+ * (clamp addressing). */
+stf_status stf_create_texture2d(int32_t width, int32_t height, int32_t channels, stf_format fmt,
+                                int32_t levels, const void* const* level_texels_host,
+                                stf_texture** out);
+
+/* Material texture for stf_shade_filter: 8-byte texels, bytes 0..2 albedo
+ * RGB (UNORM8, linear), byte 3 roughness (UNORM8), bytes 4..5 and 6..7 the
+ * tangent-space normal x and y as binary16.  Levels as for
+ * stf_create_texture2d; level l must be supplied by the caller. */
+stf_status stf_create_material2d(int32_t width, int32_t height, int32_t levels,
+                                 const void* const* level_texels_host, stf_texture** out);
+
+/* Sparse 3D voxel grid over the domain [0,dim_x) x [0,dim_y) x [0,dim_z)
+ * (each dim in 1..32768).  The grid is a set of dense 8^3 leaves; leaf k has
+ * its corner at leaf_origins_host[3k..3k+2] = (x, y, z), each a multiple of 8
+ * inside the domain, no two leaves alike, and its 512 values at
+ * leaf_values_host + 512*k*sizeof(texel), x fastest, then y, then z.
+ * Voxels not covered by a leaf, and positions outside the domain, read as
+ * `background`.  Queries are positions in voxel index space (voxel (i,j,k)
+ * centred at (i,j,k)), 3 binary32 per query. */
+stf_status stf_create_sparse_grid3d(int32_t dim_x, int32_t dim_y, int32_t dim_z, stf_format fmt,
+                                    int64_t n_leaves, const int32_t* leaf_origins_host,
+                                    const void* leaf_values_host, float background,
+                                    stf_texture** out);
+
+void stf_destroy(stf_texture* tex);
+
+/* Device bytes held by a texture (texels + index structures). */
+stf_status stf_texture_bytes(const stf_texture* tex, int64_t* bytes);
+
+/* ---------------------------------------------------------------------- */
+/* Filtering                                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Filter n queries.
+ *   queries_dev:   n x 2 binary32 uv (2D textures, level 0) or n x 3 binary32
+ *                  index-space positions (3D grids); 4-byte aligned.
+ *   out_dev:       n x channels binary32 results (channels = 1 for grids).
+ *   out_index_dev: NULL, or (stochastic mode only) n x dims int32: the texel
+ *                  that was read -- clamped (x, y) for 2D, (x, y, z) for 3D
+ *                  (may lie outside the domain, which reads as background).
+ *   flags:         0.
+ * Deterministic results carry binary32 weight and accumulation error only;
+ * stochastic results are the decoded texel exactly. */
+stf_status stf_filter(const stf_texture* tex, const float* queries_dev, int64_t n,
+                      stf_filter_kind filter, stf_mode mode, uint64_t seed,
+                      float* out_dev, int32_t* out_index_dev, uint32_t flags, void* hip_stream);
+
+/* Per-query first and second moments of the stochastic estimator over
+ * n_seeds draws (seeds seed_base .. seed_base + n_seeds - 1), accumulated in
+ * binary64 on the device: sum_dev[q] = sum_k v_k, sumsq_dev[q] = sum_k v_k^2,
+ * where v_k is exactly what stf_filter(..., STF_STOCHASTIC, seed_base + k)
+ * returns for query q (channel 0 of 2D textures).  This is the statistic of
+ * the unbiasedness claim of Eq. stochastic-sum. */
+stf_status stf_filter_moments(const stf_texture* tex, const float* queries_dev, int64_t n,
+                              stf_filter_kind filter, uint64_t seed_base, int32_t n_seeds,
+                              double* sum_dev, double* sumsq_dev, void* hip_stream);
+
+/* Shading with a filtered material (section "Effect of Texture Filtering on
+ * Rendering").  Each query is 9 binary32: uv (2), footprint scale s in
+ * texels (1), outgoing direction wo (3), incident direction wi (3), both
+ * unit vectors in the tangent frame (z = geometric normal).  The level is
+ * l = [s >= 1.41421354f] + [s >= 2.82842708f], capped at levels-1.  The
+ * filter is the B-spline (`filter` = STF_CUBIC_BSPLINE) or linear one on
+ * that level.  Shading f^ = BSDF * cos is a GGX microfacet model:
+ *   albedo = rgb/255, alpha = max(r^2, 1e-3) with r = roughness/255,
+ *   n = normalize-free (x, y, sqrt(max(0, 1 - x^2 - y^2))),
+ *   h = normalize(wo + wi), D = alpha^2 / (pi (c^2 alpha^2 + |n x h|^2)^2)
+ *   with c = n.h, G2 = 1/(1 + L(wo) + L(wi)),
+ *   L(w) = (-1 + sqrt(1 + alpha^2 tan^2)) / 2 with tan^2 = |n x w|^2/(n.w)^2,
+ *   F = 0.04 + 0.96 (1 - wi.h)^5,
+ *   f^ = (albedo/pi + D G2 F / (4 (n.wo)(n.wi))) (n.wi), 0 if n.wo <= 0
+ *   or n.wi <= 0.
+ * out_rgb_dev: n x 3 binary32.  out_index_dev: NULL or, in stochastic mode,
+ * n x 3 int32 (x, y, level). */
+stf_status stf_shade_filter(const stf_texture* material, const float* shade_queries_dev, int64_t n,
+                            stf_filter_kind filter, stf_shade_mode mode, uint64_t seed,
+                            float* out_rgb_dev, int32_t* out_index_dev, void* hip_stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* stf_last_error(void);
+
+/* Library version string. */
+const char* stf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STF_H */

@@ -1,0 +1,215 @@
+"""Python binding of libstf (stochastic texture filtering on MI355X).
+
+Argument marshalling only: every call goes straight to the C ABI declared in
+``include/stf.h`` with the same name.  Device buffers are torch tensors on the
+GPU; host arrays are numpy arrays.  The binding has no compute path of its own:
+if ``libstf.so`` is missing it raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstf.so")
+
+# enums of include/stf.h
+STF_OK, STF_E_INVALID, STF_E_OOM, STF_E_UNSUPPORTED, STF_E_DEVICE, STF_E_BUSY, STF_E_CANCELLED = 0, -1, -2, -3, -4, -5, -6
+STF_FMT_F32, STF_FMT_F16, STF_FMT_BF16, STF_FMT_FP8_E4M3, STF_FMT_U8 = 0, 1, 2, 3, 4
+STF_LINEAR, STF_CUBIC_BSPLINE = 0, 1
+STF_DETERMINISTIC, STF_STOCHASTIC = 0, 1
+STF_SHADE_AFTER_FILTER, STF_FILTER_AFTER_SHADE, STF_SHADE_STOCHASTIC = 0, 1, 2
+
+FORMATS = {"f32": STF_FMT_F32, "f16": STF_FMT_F16, "bf16": STF_FMT_BF16, "fp8_e4m3": STF_FMT_FP8_E4M3,
+           "u8": STF_FMT_U8}
+FORMAT_BYTES = {STF_FMT_F32: 4, STF_FMT_F16: 2, STF_FMT_BF16: 2, STF_FMT_FP8_E4M3: 1, STF_FMT_U8: 1}
+
+_STATUS = {0: "STF_OK", -1: "STF_E_INVALID", -2: "STF_E_OOM", -3: "STF_E_UNSUPPORTED", -4: "STF_E_DEVICE",
+           -5: "STF_E_BUSY", -6: "STF_E_CANCELLED"}
+
+
+class STFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libstf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
+                              "python paper_2305_05810_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _declare(L):
+    vp, i32, i64, u32, u64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
+    L.stf_last_error.restype = C.c_char_p
+    L.stf_last_error.argtypes = []
+    L.stf_version.restype = C.c_char_p
+    L.stf_version.argtypes = []
+    L.stf_create_texture2d.argtypes = [i32, i32, i32, i32, i32, C.POINTER(vp), C.POINTER(vp)]
+    L.stf_create_material2d.argtypes = [i32, i32, i32, C.POINTER(vp), C.POINTER(vp)]
+    L.stf_create_sparse_grid3d.argtypes = [i32, i32, i32, i32, i64, vp, vp, f32, C.POINTER(vp)]
+    L.stf_destroy.argtypes = [vp]
+    L.stf_destroy.restype = None
+    L.stf_texture_bytes.argtypes = [vp, C.POINTER(i64)]
+    L.stf_filter.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, u32, vp]
+    L.stf_filter_moments.argtypes = [vp, vp, i64, i32, u64, i32, vp, vp, vp]
+    L.stf_shade_filter.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, vp]
+    for name in ("stf_create_texture2d", "stf_create_material2d", "stf_create_sparse_grid3d",
+                 "stf_texture_bytes", "stf_filter", "stf_filter_moments", "stf_shade_filter"):
+        getattr(L, name).restype = i32
+
+
+def _check(status: int):
+    if status != STF_OK:
+        raise STFError(status, stf_last_error())
+
+
+def stf_last_error() -> str:
+    return lib().stf_last_error().decode()
+
+
+def stf_version() -> str:
+    return lib().stf_version().decode()
+
+
+class Texture:
+    """Owning handle of an stf_texture (freed by stf_destroy)."""
+
+    def __init__(self, handle: int, kind: str, channels: int, dims: int):
+        self.handle = handle
+        self.kind = kind
+        self.channels = channels
+        self.dims = dims
+
+    def destroy(self):
+        if self.handle:
+            lib().stf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.destroy()
+
+
+def _host(a: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(a)
+
+
+def stf_create_texture2d(width: int, height: int, channels: int, fmt: int,
+                         level_texels: Sequence[np.ndarray]) -> Texture:
+    """level_texels[l]: raw texels of level l (any dtype whose bytes are the
+    storage format), row-major, channels interleaved."""
+    lv = [_host(a) for a in level_texels]
+    arr = (C.c_void_p * len(lv))(*[a.ctypes.data for a in lv])
+    h = C.c_void_p()
+    _check(lib().stf_create_texture2d(width, height, channels, fmt, len(lv), arr, C.byref(h)))
+    return Texture(h.value, "tex2d", channels, 2)
+
+
+def stf_create_material2d(width: int, height: int, level_texels: Sequence[np.ndarray]) -> Texture:
+    lv = [_host(a) for a in level_texels]
+    arr = (C.c_void_p * len(lv))(*[a.ctypes.data for a in lv])
+    h = C.c_void_p()
+    _check(lib().stf_create_material2d(width, height, len(lv), arr, C.byref(h)))
+    return Texture(h.value, "material", 3, 2)
+
+
+def stf_create_sparse_grid3d(dims, fmt: int, leaf_origins: np.ndarray, leaf_values: np.ndarray,
+                             background: float = 0.0) -> Texture:
+    """leaf_origins: (n, 3) int32; leaf_values: n*512 values in storage format."""
+    o = _host(np.asarray(leaf_origins, np.int32))
+    v = _host(leaf_values)
+    n = o.shape[0]
+    if v.nbytes != n * 512 * FORMAT_BYTES[fmt]:
+        raise ValueError("leaf_values has the wrong size for the format")
+    h = C.c_void_p()
+    _check(lib().stf_create_sparse_grid3d(int(dims[0]), int(dims[1]), int(dims[2]), fmt, n,
+                                          o.ctypes.data if n else None, v.ctypes.data if n else None,
+                                          float(background), C.byref(h)))
+    return Texture(h.value, "grid3d", 1, 3)
+
+
+def stf_destroy(tex: Texture):
+    tex.destroy()
+
+
+def stf_texture_bytes(tex: Texture) -> int:
+    b = C.c_int64()
+    _check(lib().stf_texture_bytes(tex.handle, C.byref(b)))
+    return b.value
+
+
+def _dev_ptr(t, name):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def stf_filter(tex: Texture, queries, filter: int, mode: int, seed: int, out, out_index=None, flags: int = 0,
+               stream=None):
+    """queries: (n, 2|3) float32 GPU tensor; out: (n, channels) float32 GPU
+    tensor; out_index: None or (n, dims) int32 GPU tensor (stochastic)."""
+    n = queries.shape[0]
+    _check(lib().stf_filter(tex.handle, _dev_ptr(queries, "queries"), n, filter, mode, seed & (2 ** 64 - 1),
+                            _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"), flags, _stream(stream)))
+
+
+def stf_filter_moments(tex: Texture, queries, filter: int, seed_base: int, n_seeds: int, sum_out, sumsq_out,
+                       stream=None):
+    n = queries.shape[0]
+    _check(lib().stf_filter_moments(tex.handle, _dev_ptr(queries, "queries"), n, filter, seed_base, n_seeds,
+                                    _dev_ptr(sum_out, "sum"), _dev_ptr(sumsq_out, "sumsq"), _stream(stream)))
+
+
+def stf_shade_filter(material: Texture, queries, filter: int, mode: int, seed: int, out_rgb, out_index=None,
+                     stream=None):
+    n = queries.shape[0]
+    _check(lib().stf_shade_filter(material.handle, _dev_ptr(queries, "queries"), n, filter, mode,
+                                  seed & (2 ** 64 - 1), _dev_ptr(out_rgb, "out_rgb"),
+                                  _dev_ptr(out_index, "out_index"), _stream(stream)))
+
+
+# ----------------------------------------------------------------------------
+# conveniences over the calls above (allocation of outputs only)
+# ----------------------------------------------------------------------------
+def filter(tex: Texture, queries, filter: int, mode: int, seed: int = 0, want_index: bool = False, stream=None):
+    import torch
+    n = queries.shape[0]
+    out = torch.empty((n, tex.channels), dtype=torch.float32, device=queries.device)
+    idx = None
+    if want_index and mode == STF_STOCHASTIC:
+        idx = torch.empty((n, tex.dims), dtype=torch.int32, device=queries.device)
+    stf_filter(tex, queries, filter, mode, seed, out, idx, 0, stream)
+    return out, idx

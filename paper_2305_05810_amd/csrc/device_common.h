@@ -1,0 +1,150 @@
+// device_common.h -- device-side building blocks of the filtering kernels:
+// the counter-based uniform of each query axis, the per-axis cell and tap
+// choice, the per-axis weights, and exact texel decoding.
+//
+// Every file that includes this header is compiled with -ffp-contract=off, so
+// each binary32 expression below rounds after every operation exactly as
+// written; fused multiply-adds appear only where __builtin_fmaf is spelled out
+// (deterministic accumulation, which carries a stated tolerance instead of
+// bit-exactness).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stf {
+
+enum Fmt : int { F32 = 0, F16 = 1, BF16 = 2, FP8_E4M3 = 3, U8 = 4 };
+
+// Bytes per stored value.
+__host__ __device__ constexpr int fmt_bytes(int fmt)
+{
+    return fmt == F32 ? 4 : (fmt == F16 || fmt == BF16) ? 2 : 1;
+}
+
+// One-round PCG hash (Jarzynski & Olano, JCGT 2020).  Integer arithmetic
+// mod 2^32.
+__host__ __device__ __forceinline__ uint32_t pcg(uint32_t x)
+{
+    uint32_t state = x * 747796405u + 2891336453u;
+    uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+// Per-call key of a 64-bit seed.
+__host__ __device__ __forceinline__ uint32_t seed_key(uint64_t seed)
+{
+    return pcg((uint32_t)seed ^ pcg((uint32_t)(seed >> 32)));
+}
+
+// Uniform in [0, 1 - 2^-24] on the 2^-24 grid for axis `a` of a query whose
+// per-query hash is b = pcg(key ^ q).
+__device__ __forceinline__ float axis_uniform(uint32_t b, uint32_t a)
+{
+    return (float)(pcg(b + a) >> 8) * 0x1p-24f;
+}
+
+// Cell of one binary32 coordinate: i = floor(x), t = x - floor(x).  Returns
+// false for NaN, infinities and |x| >= 2^24 (no representable cell).
+__device__ __forceinline__ bool cell_of(float x, int& i, float& t)
+{
+    if (!(__builtin_fabsf(x) < 16777216.0f)) return false;
+    float f = __builtin_floorf(x);
+    i = (int)f;
+    t = x - f;
+    return true;
+}
+
+constexpr float K6 = 0x1.555556p-3f;   // (float)(1/6)
+
+// Six times the four cubic B-spline weights of the taps i-1..i+2 for the
+// fractional offset t (Eq. cubic-bspline at distances t+1, t, 1-t, 2-t),
+// written so every term is non-negative:
+//   6 w0 = s^3, 6 w1 = 1 + 3s(1 + st), 6 w2 = 1 + 3t(1 + st), 6 w3 = t^3,
+// with s = 1 - t.  They sum to 6.
+struct Cubic6 {
+    float a0, a1, a2, a3;
+};
+
+__device__ __forceinline__ Cubic6 cubic6(float t)
+{
+    float s = 1.0f - t;
+    float st = s * t;
+    Cubic6 w;
+    w.a0 = (s * s) * s;
+    w.a1 = 1.0f + (3.0f * s) * (1.0f + st);
+    w.a2 = 1.0f + (3.0f * t) * (1.0f + st);
+    w.a3 = (t * t) * t;
+    return w;
+}
+
+// Tap offset from cell i chosen by the uniform u on one axis ("sampling
+// arrays": the first tap whose cumulative weight exceeds u).
+//   linear: +1 iff u < t (strict comparison), else 0;
+//   cubic:  -1 + [u >= c1] + [u >= c2] + [u >= c3] with the binary32
+//           breakpoints c1 = a0 K6, c2 = (a0 + a1) K6, c3 = 1 - a3 K6.
+__device__ __forceinline__ int choose_linear(float t, float u)
+{
+    return (u < t) ? 1 : 0;
+}
+
+__device__ __forceinline__ int choose_cubic(float t, float u)
+{
+    float s = 1.0f - t;
+    float a0 = (s * s) * s;
+    float a1 = 1.0f + (3.0f * s) * (1.0f + s * t);
+    float a3 = (t * t) * t;
+    float c1 = a0 * K6;
+    float c2 = (a0 + a1) * K6;
+    float c3 = 1.0f - a3 * K6;
+    return (int)(u >= c1) + (int)(u >= c2) + (int)(u >= c3) - 1;
+}
+
+// ---------------------------------------------------------------------------
+// exact decoding of stored values to binary32
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dec_f16(uint16_t h)
+{
+    return (float)__builtin_bit_cast(_Float16, h);
+}
+
+__device__ __forceinline__ float dec_bf16(uint16_t h)
+{
+    return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+__device__ __forceinline__ float dec_e4m3(uint32_t q)
+{
+    // OCP E4M3 "FN": bias 7, subnormals m * 2^-9, no infinity, S.1111.111 NaN.
+    uint32_t mag = q & 0x7fu;
+    uint32_t sign = (q & 0x80u) << 24;
+    float v;
+    if (mag >= 8u) {
+        // normal: exponent field e >= 1 -> binary32 exponent e - 7 + 127
+        v = __builtin_bit_cast(float, (mag << 20) + (120u << 23));
+        if (mag == 0x7fu) v = __builtin_nanf("");
+    } else {
+        v = (float)mag * 0x1p-9f;
+    }
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) | sign);
+}
+
+__device__ __forceinline__ float dec_u8(uint32_t v)
+{
+    return (float)v / 255.0f;   // correctly rounded binary32 division
+}
+
+template <int FMT>
+__device__ __forceinline__ float load_texel(const void* __restrict__ base, int64_t i)
+{
+    if constexpr (FMT == F32) return reinterpret_cast<const float*>(base)[i];
+    if constexpr (FMT == F16) return dec_f16(reinterpret_cast<const uint16_t*>(base)[i]);
+    if constexpr (FMT == BF16) return dec_bf16(reinterpret_cast<const uint16_t*>(base)[i]);
+    if constexpr (FMT == FP8_E4M3) return dec_e4m3(reinterpret_cast<const uint8_t*>(base)[i]);
+    if constexpr (FMT == U8) return dec_u8(reinterpret_cast<const uint8_t*>(base)[i]);
+    return 0.0f;
+}
+
+constexpr int32_t BAD_INDEX = (int32_t)0x80000000;
+
+}  // namespace stf

@@ -1,0 +1,272 @@
+// filter2d.hip -- bilinear / bicubic B-spline filtering of dense 2D textures,
+// deterministic (all 4 / 16 taps, Eq. filtered-texture with tensor-product
+// weights) and stochastic (one tap per query, Eq. stochastic-sum with the
+// per-axis draw of Eq. stochastic-bilerp / the bicubic sampling of section
+// "B-Spline and Anisotropic Filters").
+//
+// Raster position: x = uv.x * W - 0.5 (texel centres at half-integers of
+// uv * W); taps are clamped to the texture.
+#include <math.h>
+
+#include "device_common.h"
+#include "stf_internal.h"
+
+using namespace stf;
+
+namespace {
+
+constexpr int BLOCK = 256;
+
+__device__ __forceinline__ int clampi(int v, int hi)
+{
+    return v < 0 ? 0 : (v > hi ? hi : v);
+}
+
+// All C channels of texel (x, y) (already clamped).
+template <int FMT, int C>
+__device__ __forceinline__ void load_rgba(const TexLevel& L, int x, int y, float (&v)[C])
+{
+    int64_t e = ((int64_t)y * L.w + x) * C;
+    if constexpr (FMT == F32 && C == 4) {
+        float4 f = reinterpret_cast<const float4*>(L.texels)[e >> 2];
+        v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+    } else if constexpr (FMT == F32 && C == 2) {
+        float2 f = reinterpret_cast<const float2*>(L.texels)[e >> 1];
+        v[0] = f.x; v[1] = f.y;
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = load_texel<FMT>(L.texels, e + c);
+    }
+}
+
+template <int FMT, int C, bool CUBIC>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(TexLevel L, const float* __restrict__ q, int32_t n,
+                                                            uint32_t key, float* __restrict__ out,
+                                                            int32_t* __restrict__ idx)
+{
+    int32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    float2 uv = reinterpret_cast<const float2*>(q)[i];
+    float x = uv.x * (float)L.w - 0.5f;
+    float y = uv.y * (float)L.h - 0.5f;
+    int cx, cy;
+    float tx, ty;
+    bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
+    float v[C];
+    int sx = BAD_INDEX, sy = BAD_INDEX;
+    if (ok) {
+        uint32_t b = pcg(key ^ (uint32_t)i);
+        float ux = axis_uniform(b, 0), uy = axis_uniform(b, 1);
+        if constexpr (CUBIC) {
+            sx = cx + choose_cubic(tx, ux);
+            sy = cy + choose_cubic(ty, uy);
+        } else {
+            sx = cx + choose_linear(tx, ux);
+            sy = cy + choose_linear(ty, uy);
+        }
+        sx = clampi(sx, L.w - 1);
+        sy = clampi(sy, L.h - 1);
+        load_rgba<FMT, C>(L, sx, sy, v);
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = __builtin_nanf("");
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[(int64_t)i * C + c] = v[c];
+    if (idx) {
+        idx[2 * (int64_t)i] = sx;
+        idx[2 * (int64_t)i + 1] = sy;
+    }
+}
+
+template <int FMT, int C, bool CUBIC>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(TexLevel L, const float* __restrict__ q, int32_t n,
+                                                               float* __restrict__ out)
+{
+    constexpr int NT = CUBIC ? 4 : 2;
+    int32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    float2 uv = reinterpret_cast<const float2*>(q)[i];
+    float x = uv.x * (float)L.w - 0.5f;
+    float y = uv.y * (float)L.h - 0.5f;
+    int cx, cy;
+    float tx, ty;
+    bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
+    float acc[C];
+    if (!ok) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[(int64_t)i * C + c] = __builtin_nanf("");
+        return;
+    }
+    float wx[NT], wy[NT];
+    if constexpr (CUBIC) {
+        Cubic6 a = cubic6(tx), b = cubic6(ty);
+        wx[0] = a.a0; wx[1] = a.a1; wx[2] = a.a2; wx[3] = a.a3;
+        wy[0] = b.a0; wy[1] = b.a1; wy[2] = b.a2; wy[3] = b.a3;
+        cx -= 1;
+        cy -= 1;
+    } else {
+        wx[0] = 1.0f - tx; wx[1] = tx;
+        wy[0] = 1.0f - ty; wy[1] = ty;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+        int yy = clampi(cy + b, L.h - 1);
+        float row[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) row[c] = 0.0f;
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            float v[C];
+            load_rgba<FMT, C>(L, clampi(cx + a, L.w - 1), yy, v);
+#pragma unroll
+            for (int c = 0; c < C; ++c) row[c] = __builtin_fmaf(wx[a], v[c], row[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = __builtin_fmaf(wy[b], row[c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[(int64_t)i * C + c] = CUBIC ? acc[c] / 36.0f : acc[c];
+}
+
+// channel-0 moments of the stochastic estimator over many seeds
+template <int FMT, int C, bool CUBIC>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_moments(TexLevel L, const float* __restrict__ q, int32_t n,
+                                                         uint64_t seed_base, int32_t n_seeds,
+                                                         double* __restrict__ sum, double* __restrict__ sumsq)
+{
+    __shared__ double s1[BLOCK], s2[BLOCK];
+    int32_t i = blockIdx.x;
+    float2 uv = reinterpret_cast<const float2*>(q)[i];
+    float x = uv.x * (float)L.w - 0.5f;
+    float y = uv.y * (float)L.h - 0.5f;
+    int cx, cy;
+    float tx, ty;
+    bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
+    double a1 = 0.0, a2 = 0.0;
+    if (ok) {
+        for (int32_t k = threadIdx.x; k < n_seeds; k += BLOCK) {
+            uint32_t b = pcg(seed_key(seed_base + (uint64_t)k) ^ (uint32_t)i);
+            float ux = axis_uniform(b, 0), uy = axis_uniform(b, 1);
+            int sx, sy;
+            if constexpr (CUBIC) {
+                sx = cx + choose_cubic(tx, ux); sy = cy + choose_cubic(ty, uy);
+            } else {
+                sx = cx + choose_linear(tx, ux); sy = cy + choose_linear(ty, uy);
+            }
+            float v[C];
+            load_rgba<FMT, C>(L, clampi(sx, L.w - 1), clampi(sy, L.h - 1), v);
+            double d = (double)v[0];
+            a1 += d;
+            a2 += d * d;
+        }
+    } else {
+        a1 = a2 = __builtin_nan("");
+    }
+    s1[threadIdx.x] = a1;
+    s2[threadIdx.x] = a2;
+    __syncthreads();
+    for (int stride = BLOCK / 2; stride > 0; stride >>= 1) {
+        if (threadIdx.x < stride) {
+            s1[threadIdx.x] += s1[threadIdx.x + stride];
+            s2[threadIdx.x] += s2[threadIdx.x + stride];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sum[i] = s1[0];
+        sumsq[i] = s2[0];
+    }
+}
+
+template <int FMT, int C>
+hipError_t launch2d_fc(const TexLevel& L, const float* q, int32_t n, int filter, int mode, uint32_t key, float* out,
+                       int32_t* idx, hipStream_t stream)
+{
+    dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
+    bool cubic = filter == STF_CUBIC_BSPLINE;
+    if (mode == STF_STOCHASTIC) {
+        if (cubic)
+            hipLaunchKernelGGL((k_tex2d_stochastic<FMT, C, true>), grid, block, 0, stream, L, q, n, key, out, idx);
+        else
+            hipLaunchKernelGGL((k_tex2d_stochastic<FMT, C, false>), grid, block, 0, stream, L, q, n, key, out, idx);
+    } else {
+        if (cubic)
+            hipLaunchKernelGGL((k_tex2d_deterministic<FMT, C, true>), grid, block, 0, stream, L, q, n, out);
+        else
+            hipLaunchKernelGGL((k_tex2d_deterministic<FMT, C, false>), grid, block, 0, stream, L, q, n, out);
+    }
+    return hipGetLastError();
+}
+
+template <int FMT, int C>
+hipError_t moments2d_fc(const TexLevel& L, const float* q, int32_t n, int filter, uint64_t seed_base,
+                        int32_t n_seeds, double* sum, double* sumsq, hipStream_t stream)
+{
+    dim3 grid(n), block(BLOCK);
+    if (filter == STF_CUBIC_BSPLINE)
+        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, true>), grid, block, 0, stream, L, q, n, seed_base, n_seeds, sum,
+                           sumsq);
+    else
+        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, false>), grid, block, 0, stream, L, q, n, seed_base, n_seeds, sum,
+                           sumsq);
+    return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t launch2d_f(const stf_texture* t, const float* q, int32_t n, int filter, int mode, uint32_t key,
+                      float* out, int32_t* idx, hipStream_t s)
+{
+    const TexLevel& L = t->level[0];
+    switch (t->channels) {
+    case 1: return launch2d_fc<FMT, 1>(L, q, n, filter, mode, key, out, idx, s);
+    case 2: return launch2d_fc<FMT, 2>(L, q, n, filter, mode, key, out, idx, s);
+    case 3: return launch2d_fc<FMT, 3>(L, q, n, filter, mode, key, out, idx, s);
+    case 4: return launch2d_fc<FMT, 4>(L, q, n, filter, mode, key, out, idx, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int FMT>
+hipError_t moments2d_f(const stf_texture* t, const float* q, int32_t n, int filter, uint64_t seed_base,
+                       int32_t n_seeds, double* sum, double* sumsq, hipStream_t s)
+{
+    const TexLevel& L = t->level[0];
+    switch (t->channels) {
+    case 1: return moments2d_fc<FMT, 1>(L, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    case 2: return moments2d_fc<FMT, 2>(L, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    case 3: return moments2d_fc<FMT, 3>(L, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    case 4: return moments2d_fc<FMT, 4>(L, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_filter2d(const stf_texture* t, const float* q, int32_t n, int filter, int mode, uint32_t key,
+                           float* out, int32_t* idx, hipStream_t s)
+{
+    switch (t->fmt) {
+    case F32: return launch2d_f<F32>(t, q, n, filter, mode, key, out, idx, s);
+    case F16: return launch2d_f<F16>(t, q, n, filter, mode, key, out, idx, s);
+    case BF16: return launch2d_f<BF16>(t, q, n, filter, mode, key, out, idx, s);
+    case FP8_E4M3: return launch2d_f<FP8_E4M3>(t, q, n, filter, mode, key, out, idx, s);
+    case U8: return launch2d_f<U8>(t, q, n, filter, mode, key, out, idx, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_moments2d(const stf_texture* t, const float* q, int32_t n, int filter, uint64_t seed_base,
+                            int32_t n_seeds, double* sum, double* sumsq, hipStream_t s)
+{
+    switch (t->fmt) {
+    case F32: return moments2d_f<F32>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    case F16: return moments2d_f<F16>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    case BF16: return moments2d_f<BF16>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    case FP8_E4M3: return moments2d_f<FP8_E4M3>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    case U8: return moments2d_f<U8>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    }
+    return hipErrorInvalidValue;
+}

@@ -1,0 +1,267 @@
+// filter3d.hip -- trilinear / tricubic B-spline filtering of sparse voxel
+// grids, deterministic (all 8 / 64 taps, Eq. filtered-texture) and stochastic
+// (one tap drawn with probability equal to its weight, Eq. stochastic-sum;
+// the per-axis draw of section "B-Spline and Anisotropic Filters").
+//
+// Grid walk: root slot (128^3 voxels) -> internal node child (8^3 voxels) ->
+// dense 8^3 leaf, x fastest.  Voxels outside the domain or in empty slots read
+// as the grid's background value.
+#include <math.h>
+
+#include "device_common.h"
+#include "stf_internal.h"
+
+using namespace stf;
+
+namespace {
+
+constexpr int BLOCK = 256;
+
+// Leaf id holding voxel (x, y, z), which must lie in the domain; -1 if none.
+__device__ __forceinline__ int32_t grid_leaf(const GridView& g, int x, int y, int z)
+{
+    int32_t node = g.root[((z >> 7) * g.ry + (y >> 7)) * g.rx + (x >> 7)];
+    if (node < 0) return -1;
+    return g.nodes[(int64_t)node * 4096 + (((z >> 3) & 15) * 16 + ((y >> 3) & 15)) * 16 + ((x >> 3) & 15)];
+}
+
+__device__ __forceinline__ bool in_domain(const GridView& g, int x, int y, int z)
+{
+    return (unsigned)x < (unsigned)g.dx && (unsigned)y < (unsigned)g.dy && (unsigned)z < (unsigned)g.dz;
+}
+
+template <int FMT>
+__device__ __forceinline__ float grid_voxel(const GridView& g, int x, int y, int z)
+{
+    if (!in_domain(g, x, y, z)) return g.background;
+    int32_t leaf = grid_leaf(g, x, y, z);
+    if (leaf < 0) return g.background;
+    return load_texel<FMT>(g.leaves, (int64_t)leaf * 512 + (((z & 7) * 8 + (y & 7)) * 8 + (x & 7)));
+}
+
+// ---------------------------------------------------------------------------
+// stochastic: one tap per query
+// ---------------------------------------------------------------------------
+template <int FMT, bool CUBIC>
+__global__ __launch_bounds__(BLOCK) void k_grid_stochastic(GridView g, const float* __restrict__ q, int32_t n,
+                                                           uint32_t key, float* __restrict__ out,
+                                                           int32_t* __restrict__ idx)
+{
+    int32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    float p0 = q[3 * (int64_t)i], p1 = q[3 * (int64_t)i + 1], p2 = q[3 * (int64_t)i + 2];
+    int c0, c1, c2;
+    float t0, t1, t2;
+    bool ok = cell_of(p0, c0, t0) & cell_of(p1, c1, t1) & cell_of(p2, c2, t2);
+    float v = __builtin_nanf("");
+    int v0 = BAD_INDEX, v1 = BAD_INDEX, v2 = BAD_INDEX;
+    if (ok) {
+        uint32_t b = pcg(key ^ (uint32_t)i);
+        float u0 = axis_uniform(b, 0), u1 = axis_uniform(b, 1), u2 = axis_uniform(b, 2);
+        if constexpr (CUBIC) {
+            v0 = c0 + choose_cubic(t0, u0);
+            v1 = c1 + choose_cubic(t1, u1);
+            v2 = c2 + choose_cubic(t2, u2);
+        } else {
+            v0 = c0 + choose_linear(t0, u0);
+            v1 = c1 + choose_linear(t1, u1);
+            v2 = c2 + choose_linear(t2, u2);
+        }
+        v = grid_voxel<FMT>(g, v0, v1, v2);
+    }
+    out[i] = v;
+    if (idx) {
+        idx[3 * (int64_t)i] = v0;
+        idx[3 * (int64_t)i + 1] = v1;
+        idx[3 * (int64_t)i + 2] = v2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic: all taps.  The taps of one axis span at most two leaves, so
+// the (up to) 2x2x2 leaves are resolved once and each tap picks its leaf by
+// the bit that says which side of the leaf boundary it lies on.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t pick8(const int32_t (&l)[8], bool kx, bool ky, bool kz)
+{
+    int32_t a = kx ? l[1] : l[0], b = kx ? l[3] : l[2], c = kx ? l[5] : l[4], d = kx ? l[7] : l[6];
+    int32_t e = ky ? b : a, f = ky ? d : c;
+    return kz ? f : e;
+}
+
+template <int FMT, bool CUBIC>
+__global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const float* __restrict__ q, int32_t n,
+                                                              float* __restrict__ out)
+{
+    constexpr int NT = CUBIC ? 4 : 2;
+    int32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    float p[3] = {q[3 * (int64_t)i], q[3 * (int64_t)i + 1], q[3 * (int64_t)i + 2]};
+    int c[3];
+    float t[3];
+    bool ok = cell_of(p[0], c[0], t[0]) & cell_of(p[1], c[1], t[1]) & cell_of(p[2], c[2], t[2]);
+    if (!ok) {
+        out[i] = __builtin_nanf("");
+        return;
+    }
+    float w[3][NT];
+    int base[3], lo[3];
+    for (int a = 0; a < 3; ++a) {
+        if constexpr (CUBIC) {
+            Cubic6 k = cubic6(t[a]);
+            w[a][0] = k.a0; w[a][1] = k.a1; w[a][2] = k.a2; w[a][3] = k.a3;
+            base[a] = c[a] - 1;
+        } else {
+            w[a][0] = 1.0f - t[a]; w[a][1] = t[a];
+            base[a] = c[a];
+        }
+        lo[a] = base[a] >> 3;   // leaf coordinate of the first tap (floor for negatives)
+    }
+    int32_t leaf[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int x = (lo[0] + (k & 1)) * 8, y = (lo[1] + ((k >> 1) & 1)) * 8, z = (lo[2] + (k >> 2)) * 8;
+        leaf[k] = in_domain(g, x, y, z) ? grid_leaf(g, x, y, z) : -1;
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int cz = 0; cz < NT; ++cz) {
+        int vz = base[2] + cz;
+        bool kz = (vz >> 3) != lo[2];
+        bool okz = (unsigned)vz < (unsigned)g.dz;
+        float plane = 0.0f;
+#pragma unroll
+        for (int cy = 0; cy < NT; ++cy) {
+            int vy = base[1] + cy;
+            bool ky = (vy >> 3) != lo[1];
+            bool oky = okz && (unsigned)vy < (unsigned)g.dy;
+            float row = 0.0f;
+#pragma unroll
+            for (int cx = 0; cx < NT; ++cx) {
+                int vx = base[0] + cx;
+                bool kx = (vx >> 3) != lo[0];
+                int32_t l = pick8(leaf, kx, ky, kz);
+                float v = g.background;
+                if (oky && (unsigned)vx < (unsigned)g.dx && l >= 0)
+                    v = load_texel<FMT>(g.leaves, (int64_t)l * 512 + (((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7)));
+                row = __builtin_fmaf(w[0][cx], v, row);
+            }
+            plane = __builtin_fmaf(w[1][cy], row, plane);
+        }
+        acc = __builtin_fmaf(w[2][cz], plane, acc);
+    }
+    if constexpr (CUBIC) acc = acc / 216.0f;   // the three per-axis factors of 1/6
+    out[i] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// moments of the stochastic estimator over many seeds (binary64 sums)
+// ---------------------------------------------------------------------------
+template <int FMT, bool CUBIC>
+__global__ __launch_bounds__(BLOCK) void k_grid_moments(GridView g, const float* __restrict__ q, int32_t n,
+                                                        uint64_t seed_base, int32_t n_seeds,
+                                                        double* __restrict__ sum, double* __restrict__ sumsq)
+{
+    // one block per query; the seeds are split over the block's lanes and the
+    // partial sums reduced in a fixed order (bitwise reproducible).
+    __shared__ double s1[BLOCK], s2[BLOCK];
+    int32_t i = blockIdx.x;
+    float p0 = q[3 * (int64_t)i], p1 = q[3 * (int64_t)i + 1], p2 = q[3 * (int64_t)i + 2];
+    int c0, c1, c2;
+    float t0, t1, t2;
+    bool ok = cell_of(p0, c0, t0) & cell_of(p1, c1, t1) & cell_of(p2, c2, t2);
+    double a1 = 0.0, a2 = 0.0;
+    if (ok) {
+        for (int32_t k = threadIdx.x; k < n_seeds; k += BLOCK) {
+            uint32_t b = pcg(seed_key(seed_base + (uint64_t)k) ^ (uint32_t)i);
+            float u0 = axis_uniform(b, 0), u1 = axis_uniform(b, 1), u2 = axis_uniform(b, 2);
+            int v0, v1, v2;
+            if constexpr (CUBIC) {
+                v0 = c0 + choose_cubic(t0, u0); v1 = c1 + choose_cubic(t1, u1); v2 = c2 + choose_cubic(t2, u2);
+            } else {
+                v0 = c0 + choose_linear(t0, u0); v1 = c1 + choose_linear(t1, u1); v2 = c2 + choose_linear(t2, u2);
+            }
+            double v = (double)grid_voxel<FMT>(g, v0, v1, v2);
+            a1 += v;
+            a2 += v * v;
+        }
+    } else {
+        a1 = a2 = __builtin_nan("");
+    }
+    s1[threadIdx.x] = a1;
+    s2[threadIdx.x] = a2;
+    __syncthreads();
+    for (int stride = BLOCK / 2; stride > 0; stride >>= 1) {
+        if (threadIdx.x < stride) {
+            s1[threadIdx.x] += s1[threadIdx.x + stride];
+            s2[threadIdx.x] += s2[threadIdx.x + stride];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sum[i] = s1[0];
+        sumsq[i] = s2[0];
+    }
+}
+
+template <int FMT>
+hipError_t launch3d_fmt(const GridView& g, const float* q, int32_t n, int filter, int mode, uint32_t key, float* out,
+                        int32_t* idx, hipStream_t stream)
+{
+    dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
+    bool cubic = filter == STF_CUBIC_BSPLINE;
+    if (mode == STF_STOCHASTIC) {
+        if (cubic)
+            hipLaunchKernelGGL((k_grid_stochastic<FMT, true>), grid, block, 0, stream, g, q, n, key, out, idx);
+        else
+            hipLaunchKernelGGL((k_grid_stochastic<FMT, false>), grid, block, 0, stream, g, q, n, key, out, idx);
+    } else {
+        if (cubic)
+            hipLaunchKernelGGL((k_grid_deterministic<FMT, true>), grid, block, 0, stream, g, q, n, out);
+        else
+            hipLaunchKernelGGL((k_grid_deterministic<FMT, false>), grid, block, 0, stream, g, q, n, out);
+    }
+    return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t moments3d_fmt(const GridView& g, const float* q, int32_t n, int filter, uint64_t seed_base,
+                         int32_t n_seeds, double* sum, double* sumsq, hipStream_t stream)
+{
+    dim3 grid(n), block(BLOCK);
+    if (filter == STF_CUBIC_BSPLINE)
+        hipLaunchKernelGGL((k_grid_moments<FMT, true>), grid, block, 0, stream, g, q, n, seed_base, n_seeds, sum, sumsq);
+    else
+        hipLaunchKernelGGL((k_grid_moments<FMT, false>), grid, block, 0, stream, g, q, n, seed_base, n_seeds, sum, sumsq);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_filter3d(const stf_texture* tex, const float* q, int32_t n, int filter, int mode, uint32_t key,
+                           float* out, int32_t* idx, hipStream_t stream)
+{
+    const GridView& g = tex->grid;
+    switch (tex->fmt) {
+    case F32: return launch3d_fmt<F32>(g, q, n, filter, mode, key, out, idx, stream);
+    case F16: return launch3d_fmt<F16>(g, q, n, filter, mode, key, out, idx, stream);
+    case BF16: return launch3d_fmt<BF16>(g, q, n, filter, mode, key, out, idx, stream);
+    case FP8_E4M3: return launch3d_fmt<FP8_E4M3>(g, q, n, filter, mode, key, out, idx, stream);
+    case U8: return launch3d_fmt<U8>(g, q, n, filter, mode, key, out, idx, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_moments3d(const stf_texture* tex, const float* q, int32_t n, int filter, uint64_t seed_base,
+                            int32_t n_seeds, double* sum, double* sumsq, hipStream_t stream)
+{
+    const GridView& g = tex->grid;
+    switch (tex->fmt) {
+    case F32: return moments3d_fmt<F32>(g, q, n, filter, seed_base, n_seeds, sum, sumsq, stream);
+    case F16: return moments3d_fmt<F16>(g, q, n, filter, seed_base, n_seeds, sum, sumsq, stream);
+    case BF16: return moments3d_fmt<BF16>(g, q, n, filter, seed_base, n_seeds, sum, sumsq, stream);
+    case FP8_E4M3: return moments3d_fmt<FP8_E4M3>(g, q, n, filter, seed_base, n_seeds, sum, sumsq, stream);
+    case U8: return moments3d_fmt<U8>(g, q, n, filter, seed_base, n_seeds, sum, sumsq, stream);
+    }
+    return hipErrorInvalidValue;
+}

@@ -1,0 +1,66 @@
+// stf_internal.h -- library-private declarations shared by the C ABI layer
+// and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/stf.h"
+
+enum stf_kind : int { STF_KIND_TEX2D = 1, STF_KIND_MATERIAL = 2, STF_KIND_GRID3D = 3 };
+
+constexpr int STF_MAX_LEVELS = 16;
+
+// Device view of one 2D level.
+struct TexLevel {
+    const void* texels;   // row-major, channels interleaved
+    int32_t w, h;
+};
+
+// Device view of a sparse grid: root table -> internal nodes of 16^3 children
+// -> dense 8^3 leaves.  A root slot covers 128^3 voxels, a node child slot
+// 8^3 voxels.  -1 marks an empty slot.
+struct GridView {
+    const int32_t* root;   // rx * ry * rz node ids
+    const int32_t* nodes;  // n_nodes * 4096 leaf ids, child (cx, cy, cz) at (cz*16 + cy)*16 + cx
+    const void* leaves;    // n_leaves * 512 values, x fastest
+    int32_t dx, dy, dz;    // domain
+    int32_t rx, ry;        // root extents in x and y
+    float background;
+};
+
+struct stf_texture {
+    int kind;
+    int fmt;
+    int channels;
+    int device;
+    int64_t bytes;
+    // 2D textures and materials
+    int levels;
+    TexLevel level[STF_MAX_LEVELS];
+    void* level_alloc[STF_MAX_LEVELS];
+    // 3D grids
+    GridView grid;
+    int32_t rz;
+    int64_t n_leaves;
+    int32_t n_nodes;
+    void* grid_alloc[3];
+};
+
+// Error reporting (thread-local message).
+stf_status stf_fail(stf_status code, const char* fmt, ...);
+void stf_clear_error();
+
+// Kernel launchers; each returns hipSuccess or the launch error.
+hipError_t launch_filter2d(const stf_texture* tex, const float* q, int32_t n, int filter, int mode,
+                           uint32_t skey, float* out, int32_t* idx, hipStream_t stream);
+hipError_t launch_filter3d(const stf_texture* tex, const float* q, int32_t n, int filter, int mode,
+                           uint32_t skey, float* out, int32_t* idx, hipStream_t stream);
+hipError_t launch_moments2d(const stf_texture* tex, const float* q, int32_t n, int filter,
+                            uint64_t seed_base, int32_t n_seeds, double* sum, double* sumsq,
+                            hipStream_t stream);
+hipError_t launch_moments3d(const stf_texture* tex, const float* q, int32_t n, int filter,
+                            uint64_t seed_base, int32_t n_seeds, double* sum, double* sumsq,
+                            hipStream_t stream);
+hipError_t launch_shade(const stf_texture* mat, const float* q, int32_t n, int filter, int mode,
+                        uint32_t skey, float* out, int32_t* idx, hipStream_t stream);
