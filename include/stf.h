@@ -32,15 +32,17 @@
  *        pcg(x): state = x*747796405 + 2891336453;
  *                word  = ((state >> ((state >> 28) + 4)) ^ state) * 277803737;
  *                return (word >> 22) ^ word          (all arithmetic mod 2^32)
- *        s = pcg(lo32(seed) ^ pcg(hi32(seed)));  b = pcg(s ^ q);
- *        u_a = (pcg(b + a) >> 8) * 2^-24             (a = 0, 1, 2 for x, y, z)
- *     so results do not depend on launch shape, ordering or other work.
+ *        s = pcg(lo32(seed) ^ pcg(hi32(seed)));  h0 = pcg(s ^ q);
+ *        h_a = pcg(h0 + a) for a >= 1;  u_a = (h_a >> 8) * 2^-24
+ *     (a = 0, 1, 2 for x, y, z), so results do not depend on launch shape,
+ *     ordering or other work.
  *   - Tap choice (stochastic mode), per axis, with i = floor(x), t = x - i in
  *     binary32:  linear: upper tap i+1 iff u < t, else i.  Cubic: with
- *     s = 1-t, a0 = (s*s)*s, a1 = 1 + (3*s)*(1 + s*t), a3 = (t*t)*t,
- *     K6 = 0x1.555556p-3f: c1 = a0*K6, c2 = (a0 + a1)*K6, c3 = 1 - a3*K6,
- *     tap = i - 1 + [u >= c1] + [u >= c2] + [u >= c3].  Every operation is a
- *     single binary32 rounding (no fused multiply-add), so the chosen tap is
+ *     s = 1-t, d = t - 0.5, K6 = 0x1.555556p-3f, K3 = 0x1.555556p-2f:
+ *     c1 = ((s*s)*s)*K6, c2 = fma(d, fma(d*d, K3, -0.75), 0.5),
+ *     c3 = fma(-((t*t)*t), K6, 1), tap = i - 1 + [u >= c1] + [u >= c2] +
+ *     [u >= c3] -- the cumulative B-spline weights.  Every operation is a
+ *     single binary32 rounding (each fma rounded once), so the chosen tap is
  *     reproducible bit for bit.  ("Sampling arrays", section "Sampling
  *     Techniques", applied per axis as in section "B-Spline and Anisotropic
  *     Filters".)

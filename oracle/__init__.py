@@ -52,6 +52,8 @@ def _declare(L):
     L.orc_axis_weights.argtypes, L.orc_axis_weights.restype = [i32, dbl, vp], None
     L.orc_select.argtypes, L.orc_select.restype = [i32, C.c_float, C.c_float], i32
     L.orc_max_threads.argtypes, L.orc_max_threads.restype = [], i32
+    L.orc_cubic_breakpoints.argtypes, L.orc_cubic_breakpoints.restype = [C.c_float, vp], None
+    L.orc_cubic_breakpoints_disorder.argtypes, L.orc_cubic_breakpoints_disorder.restype = [], i64
     L.orc_filter2d.argtypes = [vp, i32, i32, i32, i32, vp, i64, i32, i32, u64, vp, vp, i32]
     L.orc_filter2d.restype = i32
     L.orc_filter2d_brute.argtypes = [vp, i32, i32, i32, i32, vp, i64, i32, vp]
@@ -109,6 +111,16 @@ def axis_weights(filt: int, t: float) -> np.ndarray:
 
 def select(filt: int, t: float, u: float) -> int:
     return lib().orc_select(filt, float(np.float32(t)), float(np.float32(u)))
+
+
+def cubic_breakpoints(t: float) -> np.ndarray:
+    c = np.zeros(3, np.float32)
+    lib().orc_cubic_breakpoints(float(np.float32(t)), _p(c))
+    return c
+
+
+def cubic_breakpoints_disorder() -> int:
+    return lib().orc_cubic_breakpoints_disorder()
 
 
 def max_threads() -> int:

@@ -12,9 +12,10 @@
  *   - Every filtered *value* (weights, sums, variances) is computed in IEEE
  *     binary64 from the exact binary32 query coordinate.
  *   - Every sampling *decision* (which tap is taken) is computed in pinned
- *     binary32: each operation rounded to nearest-even, no fused multiply-add
- *     (this file is compiled with -ffp-contract=off), subnormals kept.  The
- *     decision therefore has one unique answer for a given query and seed.
+ *     binary32: each operation rounded to nearest-even, subnormals kept, and
+ *     no fused multiply-add except where fmaf() is written out (this file is
+ *     compiled with -ffp-contract=off).  The decision therefore has one unique
+ *     answer for a given query and seed.
  *   - Texels are decoded exactly from their storage format.
  *
  * Conventions where the paper leaves a choice (each is listed with its reason
@@ -57,7 +58,8 @@ enum { ORC_DET = 0, ORC_STOCH = 1, ORC_STOCH_REUSE = 2 };
 /* real-time section).  A counter-based generator makes the draw a pure       */
 /* function of (seed, query, axis): the one-round PCG hash "pcg" published by */
 /* Jarzynski and Olano (JCGT 9(3), 2020), chained as                          */
-/*   s = pcg(seed_lo ^ pcg(seed_hi)),  b = pcg(s ^ qid),  h_a = pcg(b + a),  */
+/*   s = pcg(seed_lo ^ pcg(seed_hi)),  h_0 = pcg(s ^ qid),                   */
+/*   h_a = pcg(h_0 + a) for a >= 1,                                           */
 /*   u_a = (h_a >> 8) * 2^-24  in [0, 1 - 2^-24].                             */
 /* ------------------------------------------------------------------------ */
 uint32_t orc_pcg(uint32_t x)
@@ -74,8 +76,8 @@ uint32_t orc_seed_key(uint64_t seed)
 
 float orc_uniform(uint64_t seed, uint32_t qid, uint32_t axis)
 {
-    uint32_t b = orc_pcg(orc_seed_key(seed) ^ qid);
-    uint32_t h = orc_pcg(b + axis);
+    uint32_t h = orc_pcg(orc_seed_key(seed) ^ qid);
+    if (axis > 0) h = orc_pcg(h + axis);
     return (float)(h >> 8) * 0x1p-24f;
 }
 
@@ -184,25 +186,51 @@ static int orc_cell(float x, int* i, float* t)
 /* u -- applied to the per-axis filter weights.                               */
 /*   Linear: the upper tap iff u < t (the strict comparison of the bilinear   */
 /*           listing; P(upper) = t, Eq. stochastic-lerp).                     */
-/*   Cubic:  breakpoints c1 = w0, c2 = w0 + w1, c3 = 1 - w3, with            */
-/*           6*w0 = s^3, 6*w1 = 1 + 3s(1 + st), 6*w3 = t^3 (s = 1 - t),      */
-/*           i.e. the B-spline weights of Eq. cubic-bspline in a form whose   */
-/*           terms are all non-negative; j = [u>=c1] + [u>=c2] + [u>=c3].     */
+/*   Cubic:  breakpoints at the cumulative B-spline weights of Eq.            */
+/*           cubic-bspline, c1 = w0 = s^3/6, c3 = 1 - w3 = 1 - t^3/6 and      */
+/*           c2 = w0 + w1 = 1/2 - (3/4) d + d^3/3 with s = 1 - t, d = t - 1/2  */
+/*           (the polynomial w0 + w1 expanded about t = 1/2), evaluated as     */
+/*             c1 = ((s*s)*s)*K6,  c3 = 1 - ((t*t)*t)*K6,                    */
+/*             c2 = fma(d, fma(d*d, K3, -0.75), 0.5),                          */
+/*           K6 = fl32(1/6), K3 = fl32(1/3), each fma rounded once;            */
+/*           j = [u>=c1] + [u>=c2] + [u>=c3].                                 */
 /* Returns the offset of the chosen tap from cell i (0/1 linear, -1..2 cubic).*/
+void orc_cubic_breakpoints(float t, float c[3])
+{
+    const float K6 = 0x1.555556p-3f;   /* (float)(1/6) */
+    const float K3 = 0x1.555556p-2f;   /* (float)(1/3) */
+    float s = 1.0f - t;
+    float d = t - 0.5f;
+    c[0] = ((s * s) * s) * K6;
+    c[1] = fmaf(d, fmaf(d * d, K3, -0.75f), 0.5f);
+    c[2] = 1.0f - ((t * t) * t) * K6;
+}
+
 int orc_select(int filter, float t, float u)
 {
     if (filter == ORC_LINEAR)
         return (u < t) ? 1 : 0;
-    const float K6 = 0x1.555556p-3f;   /* (float)(1/6) */
-    float s = 1.0f - t;
-    float a0 = (s * s) * s;
-    float a1 = 1.0f + (3.0f * s) * (1.0f + s * t);
-    float a3 = (t * t) * t;
-    float c1 = a0 * K6;
-    float c2 = (a0 + a1) * K6;
-    float c3 = 1.0f - a3 * K6;
-    int j = (u >= c1) + (u >= c2) + (u >= c3);
+    float c[3];
+    orc_cubic_breakpoints(t, c);
+    int j = (u >= c[0]) + (u >= c[1]) + (u >= c[2]);
     return j - 1;
+}
+
+/* Number of binary32 values t in [0, 1) whose breakpoints are out of order
+ * (c1 > c2 or c2 > c3); the cumulative-weight rule needs none. */
+int64_t orc_cubic_breakpoints_disorder(void)
+{
+    int64_t bad = 0;
+    const uint32_t end = 0x3f800000u;   /* bits of 1.0f */
+#pragma omp parallel for reduction(+ : bad) schedule(static)
+    for (int64_t b = 0; b < (int64_t)end; ++b) {
+        uint32_t w = (uint32_t)b;
+        float t, c[3];
+        memcpy(&t, &w, 4);
+        orc_cubic_breakpoints(t, c);
+        bad += (c[0] > c[1]) || (c[1] > c[2]);
+    }
+    return bad;
 }
 
 /* The paper's own sampler, for distribution tests only: the weights are     */

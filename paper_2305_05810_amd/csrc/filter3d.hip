@@ -16,6 +16,9 @@ using namespace stf;
 namespace {
 
 constexpr int BLOCK = 256;
+#ifndef STOCH_Q
+#define STOCH_Q 4   // queries per thread in the stochastic kernel
+#endif
 
 // Leaf id holding voxel (x, y, z), which must lie in the domain; -1 if none.
 __device__ __forceinline__ int32_t grid_leaf(const GridView& g, int x, int y, int z)
@@ -40,40 +43,121 @@ __device__ __forceinline__ float grid_voxel(const GridView& g, int x, int y, int
 }
 
 // ---------------------------------------------------------------------------
-// stochastic: one tap per query
+// stochastic: one tap per query.
+//
+// Each thread takes Q queries (block-strided, so every load and store
+// instruction of a wave covers one contiguous span) and walks their grid
+// paths in lock step: the Q root loads are issued together, then the Q node
+// loads, then the Q leaf loads, which keeps Q dependent-load chains in flight
+// per lane.  Lanes whose query is out of the domain or in an empty slot load
+// from offset 0 and discard the value, so the walk has no divergent branches;
+// a level is skipped only when no lane of the wave needs it.  Table offsets
+// are 32-bit (the library rejects grids whose tables exceed 4 GiB), so every
+// gather is a scalar-base + 32-bit vector-offset load.
 // ---------------------------------------------------------------------------
-template <int FMT, bool CUBIC>
+template <int FMT>
+__device__ __forceinline__ float leaf_value(const void* __restrict__ leaves, uint32_t elem)
+{
+    const char* p = reinterpret_cast<const char*>(leaves) + (size_t)(elem * (uint32_t)fmt_bytes(FMT));
+    if constexpr (FMT == F32) return *reinterpret_cast<const float*>(p);
+    if constexpr (FMT == F16) return dec_f16(*reinterpret_cast<const uint16_t*>(p));
+    if constexpr (FMT == BF16) return dec_bf16(*reinterpret_cast<const uint16_t*>(p));
+    if constexpr (FMT == FP8_E4M3) return dec_e4m3(*reinterpret_cast<const uint8_t*>(p));
+    if constexpr (FMT == U8) return dec_u8(*reinterpret_cast<const uint8_t*>(p));
+    return 0.0f;
+}
+
+__device__ __forceinline__ int32_t table_load(const int32_t* __restrict__ t, uint32_t elem)
+{
+    return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(t) + (size_t)(elem * 4u));
+}
+
+template <int FMT, bool CUBIC, int Q>
 __global__ __launch_bounds__(BLOCK) void k_grid_stochastic(GridView g, const float* __restrict__ q, int32_t n,
                                                            uint32_t key, float* __restrict__ out,
                                                            int32_t* __restrict__ idx)
 {
-    int32_t i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= n) return;
-    float p0 = q[3 * (int64_t)i], p1 = q[3 * (int64_t)i + 1], p2 = q[3 * (int64_t)i + 2];
-    int c0, c1, c2;
-    float t0, t1, t2;
-    bool ok = cell_of(p0, c0, t0) & cell_of(p1, c1, t1) & cell_of(p2, c2, t2);
-    float v = __builtin_nanf("");
-    int v0 = BAD_INDEX, v1 = BAD_INDEX, v2 = BAD_INDEX;
-    if (ok) {
-        uint32_t b = pcg(key ^ (uint32_t)i);
-        float u0 = axis_uniform(b, 0), u1 = axis_uniform(b, 1), u2 = axis_uniform(b, 2);
-        if constexpr (CUBIC) {
-            v0 = c0 + choose_cubic(t0, u0);
-            v1 = c1 + choose_cubic(t1, u1);
-            v2 = c2 + choose_cubic(t2, u2);
-        } else {
-            v0 = c0 + choose_linear(t0, u0);
-            v1 = c1 + choose_linear(t1, u1);
-            v2 = c2 + choose_linear(t2, u2);
-        }
-        v = grid_voxel<FMT>(g, v0, v1, v2);
+    const int32_t first = blockIdx.x * (BLOCK * Q) + threadIdx.x;
+    float p[Q][3];
+    bool live[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {   // all query loads first
+        int32_t i = first + k * BLOCK;
+        live[k] = i < n;
+        const float* e = q + 3 * (int64_t)(live[k] ? i : 0);
+        p[k][0] = __builtin_nontemporal_load(e);
+        p[k][1] = __builtin_nontemporal_load(e + 1);
+        p[k][2] = __builtin_nontemporal_load(e + 2);
     }
-    out[i] = v;
-    if (idx) {
-        idx[3 * (int64_t)i] = v0;
-        idx[3 * (int64_t)i + 1] = v1;
-        idx[3 * (int64_t)i + 2] = v2;
+    int vx[Q], vy[Q], vz[Q];
+    bool fin[Q], ok[Q];
+    uint32_t roff[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        int32_t i = first + k * BLOCK;
+        int c0 = 0, c1 = 0, c2 = 0;
+        float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f;
+        fin[k] = cell_of(p[k][0], c0, t0) & cell_of(p[k][1], c1, t1) & cell_of(p[k][2], c2, t2);
+        uint32_t h0 = pcg(key ^ (uint32_t)i), h1, h2;
+        pcg_next2(h0, h1, h2);
+        float m0 = hash_m(h0), m1 = hash_m(h1), m2 = hash_m(h2);
+        if constexpr (CUBIC) {
+            vx[k] = c0 + choose_cubic_m(t0, m0);
+            vy[k] = c1 + choose_cubic_m(t1, m1);
+            vz[k] = c2 + choose_cubic_m(t2, m2);
+        } else {
+            vx[k] = c0 + choose_linear_m(t0, m0);
+            vy[k] = c1 + choose_linear_m(t1, m1);
+            vz[k] = c2 + choose_linear_m(t2, m2);
+        }
+        ok[k] = live[k] && fin[k] && in_domain(g, vx[k], vy[k], vz[k]);
+        roff[k] = ok[k] ? (uint32_t)(((vz[k] >> 7) * g.ry + (vy[k] >> 7)) * g.rx + (vx[k] >> 7)) : 0u;
+    }
+    int32_t node[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) node[k] = table_load(g.root, roff[k]);
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        ok[k] = ok[k] && node[k] >= 0;
+        any |= ok[k];
+    }
+    float v[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) v[k] = g.background;
+    if (__any(any)) {
+        int32_t leaf[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            uint32_t child = ((((uint32_t)vz[k] >> 3) & 15u) * 16u + (((uint32_t)vy[k] >> 3) & 15u)) * 16u +
+                             (((uint32_t)vx[k] >> 3) & 15u);
+            leaf[k] = table_load(g.nodes, ok[k] ? (uint32_t)node[k] * 4096u + child : 0u);
+        }
+        any = false;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            ok[k] = ok[k] && leaf[k] >= 0;
+            any |= ok[k];
+        }
+        if (__any(any)) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                uint32_t vox = ((((uint32_t)vz[k] & 7u) * 8u + ((uint32_t)vy[k] & 7u)) * 8u) + ((uint32_t)vx[k] & 7u);
+                float t = leaf_value<FMT>(g.leaves, ok[k] ? (uint32_t)leaf[k] * 512u + vox : 0u);
+                v[k] = ok[k] ? t : g.background;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        int32_t i = first + k * BLOCK;
+        if (!live[k]) continue;
+        __builtin_nontemporal_store(fin[k] ? v[k] : __builtin_nanf(""), out + i);
+        if (idx) {
+            idx[3 * (int64_t)i] = fin[k] ? vx[k] : BAD_INDEX;
+            idx[3 * (int64_t)i + 1] = fin[k] ? vy[k] : BAD_INDEX;
+            idx[3 * (int64_t)i + 2] = fin[k] ? vz[k] : BAD_INDEX;
+        }
     }
 }
 
@@ -211,10 +295,12 @@ hipError_t launch3d_fmt(const GridView& g, const float* q, int32_t n, int filter
     dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
     bool cubic = filter == STF_CUBIC_BSPLINE;
     if (mode == STF_STOCHASTIC) {
+        constexpr int Q = STOCH_Q;
+        dim3 sgrid((unsigned)(((int64_t)n + BLOCK * Q - 1) / (BLOCK * Q)));
         if (cubic)
-            hipLaunchKernelGGL((k_grid_stochastic<FMT, true>), grid, block, 0, stream, g, q, n, key, out, idx);
+            hipLaunchKernelGGL((k_grid_stochastic<FMT, true, Q>), sgrid, block, 0, stream, g, q, n, key, out, idx);
         else
-            hipLaunchKernelGGL((k_grid_stochastic<FMT, false>), grid, block, 0, stream, g, q, n, key, out, idx);
+            hipLaunchKernelGGL((k_grid_stochastic<FMT, false, Q>), sgrid, block, 0, stream, g, q, n, key, out, idx);
     } else {
         if (cubic)
             hipLaunchKernelGGL((k_grid_deterministic<FMT, true>), grid, block, 0, stream, g, q, n, out);

@@ -221,6 +221,12 @@ stf_status stf_create_sparse_grid3d(int32_t dim_x, int32_t dim_y, int32_t dim_z,
         nodes[cs] = (int32_t)k;
     }
 
+    // the kernels address the node table and the leaf values with 32-bit byte offsets
+    if (nodes.size() * 4 >= ((size_t)1 << 32))
+        return stf_fail(STF_E_UNSUPPORTED, "grid needs %zu internal nodes; at most 262143 are supported",
+                        nodes.size() / 4096);
+    if ((size_t)n_leaves * 512 * stf::fmt_bytes(fmt) >= ((size_t)1 << 32))
+        return stf_fail(STF_E_UNSUPPORTED, "leaf values exceed 4 GiB (%lld leaves)", (long long)n_leaves);
     stf_texture* t = new (std::nothrow) stf_texture();
     if (!t) return stf_fail(STF_E_OOM, "host allocation failed");
     t->kind = STF_KIND_GRID3D;

@@ -92,3 +92,16 @@ def test_select_breakpoints_are_cumulative_weights():
             above = np.float32(c) + np.float32(4e-7)
             assert oracle.select(oracle.CUBIC, t, below) == k - 1
             assert oracle.select(oracle.CUBIC, t, above) == k
+
+
+def test_cubic_breakpoints_ordered_for_every_binary32_t():
+    # the chosen tap is the first whose cumulative weight exceeds u only if
+    # the breakpoints are ordered; checked for all 2^30 binary32 t in [0, 1)
+    assert oracle.cubic_breakpoints_disorder() == 0
+
+
+def test_cubic_breakpoints_close_to_exact_cumulative_weights():
+    for t in np.linspace(0.0, 1.0, 1001, endpoint=False).astype(np.float32):
+        w = oracle.axis_weights(oracle.CUBIC, float(t))
+        c = oracle.cubic_breakpoints(t).astype(np.float64)
+        assert np.allclose(c, np.cumsum(w)[:3], rtol=0, atol=2e-7)
