@@ -182,8 +182,11 @@ stf_status stf_filter_moments(const stf_texture* tex, const float* queries_dev, 
  *   F = 0.04 + 0.96 (1 - wi.h)^5,
  *   f^ = (albedo/pi + D G2 F / (4 (n.wo)(n.wi))) (n.wi), 0 if n.wo <= 0
  *   or n.wi <= 0.
- * out_rgb_dev: n x 3 binary32.  out_index_dev: NULL or, in stochastic mode,
- * n x 3 int32 (x, y, level). */
+ * Only levels 0..2 are reachable by the level rule; further levels are
+ * stored but unused.  out_rgb_dev: n x 3 binary32.  out_index_dev: NULL or,
+ * in stochastic mode, n x 3 int32 (x, y, level).  Results are binary32
+ * evaluations of the formulas above (no bit-exactness is promised for the
+ * shaded values; the sampled tap is exact). */
 stf_status stf_shade_filter(const stf_texture* material, const float* shade_queries_dev, int64_t n,
                             stf_filter_kind filter, stf_shade_mode mode, uint64_t seed,
                             float* out_rgb_dev, int32_t* out_index_dev, void* hip_stream);

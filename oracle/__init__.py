@@ -77,7 +77,19 @@ def _declare(L):
 
 
 def _declare_shade(L):
-    pass
+    vp, i32, i64, u64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_double
+    L.orc_shade.argtypes = [vp, vp, vp, i32, vp, i64, i32, i32, u64, vp, vp, i32]
+    L.orc_shade.restype = i32
+    L.orc_shade_at.argtypes = [vp, vp, vp, i32, vp, vp, i64, i32, i32, u64, vp, vp, i32]
+    L.orc_shade_at.restype = i32
+    L.orc_shade_moments.argtypes = [vp, vp, vp, i32, vp, i64, i32, vp, vp]
+    L.orc_shade_moments.restype = i32
+    L.orc_shade_eval.argtypes = [vp, vp, vp, vp]
+    L.orc_shade_eval.restype = None
+    L.orc_ggx_D.argtypes = [vp, vp, dbl]
+    L.orc_ggx_D.restype = dbl
+    L.orc_shade_level.argtypes = [C.c_float, i32]
+    L.orc_shade_level.restype = i32
 
 
 def _declare_neural(L):
@@ -229,3 +241,70 @@ class Grid:
         var = np.empty(n, np.float64)
         lib().orc_filter3d_moments(self._h, _p(p), n, filt, _p(mean), _p(var), nthreads)
         return mean, var
+
+
+# ----------------------------------------------------------------------------
+# filtering with shading (material textures)
+# ----------------------------------------------------------------------------
+SH_AFTER_FILTER, SH_FILTER_AFTER, SH_STOCH = 0, 1, 2
+
+
+class Material:
+    """Oracle view of a material: list of (H, W) structured or (H, W, 8) uint8
+    level arrays (8-byte texels)."""
+
+    def __init__(self, levels):
+        self.levels = [np.ascontiguousarray(lv).view(np.uint8).reshape(lv.shape[0], lv.shape[1], 8) for lv in levels]
+        self._ptrs = (C.c_void_p * len(self.levels))(*[lv.ctypes.data for lv in self.levels])
+        self._W = (C.c_int * len(self.levels))(*[lv.shape[1] for lv in self.levels])
+        self._H = (C.c_int * len(self.levels))(*[lv.shape[0] for lv in self.levels])
+
+    def shade(self, recs, filt: int, mode: int, seed: int = 0, want_index: bool = True, nthreads: int = 0):
+        recs = np.ascontiguousarray(recs, dtype=np.float32)
+        n = recs.shape[0]
+        out = np.empty((n, 3), np.float64)
+        idx = np.empty((n, 3), np.int32) if (want_index and mode == SH_STOCH) else None
+        rc = lib().orc_shade(self._ptrs, self._W, self._H, len(self.levels), _p(recs), n, filt, mode, seed,
+                             _p(out), _p(idx), nthreads)
+        if rc != 0:
+            raise ValueError("orc_shade failed")
+        return out, idx
+
+    def shade_at(self, recs, qids, filt: int, mode: int, seed: int = 0, nthreads: int = 0):
+        """Shade recs[qids] as members of the whole batch recs."""
+        recs = np.ascontiguousarray(recs, dtype=np.float32)
+        qids = np.ascontiguousarray(qids, dtype=np.int64)
+        m = qids.shape[0]
+        out = np.empty((m, 3), np.float64)
+        idx = np.empty((m, 3), np.int32) if mode == SH_STOCH else None
+        rc = lib().orc_shade_at(self._ptrs, self._W, self._H, len(self.levels), _p(recs), _p(qids), m, filt, mode,
+                                seed, _p(out), _p(idx), nthreads)
+        if rc != 0:
+            raise ValueError("orc_shade_at failed")
+        return out, idx
+
+    def moments(self, recs, filt: int):
+        recs = np.ascontiguousarray(recs, dtype=np.float32)
+        n = recs.shape[0]
+        mean = np.empty((n, 3), np.float64)
+        var = np.empty((n, 3), np.float64)
+        lib().orc_shade_moments(self._ptrs, self._W, self._H, len(self.levels), _p(recs), n, filt, _p(mean), _p(var))
+        return mean, var
+
+
+def shade_eval(mat6, wo, wi) -> np.ndarray:
+    """f^ for one decoded material (albedo r, g, b, roughness, nx, ny)."""
+    m = np.ascontiguousarray(mat6, np.float64)
+    a = np.ascontiguousarray(wo, np.float32)
+    b = np.ascontiguousarray(wi, np.float32)
+    out = np.zeros(3, np.float64)
+    lib().orc_shade_eval(_p(m), _p(a), _p(b), _p(out))
+    return out
+
+
+def ggx_D(n, h, alpha: float) -> float:
+    return lib().orc_ggx_D(_p(np.ascontiguousarray(n, np.float64)), _p(np.ascontiguousarray(h, np.float64)), alpha)
+
+
+def shade_level(s: float, levels: int) -> int:
+    return lib().orc_shade_level(float(np.float32(s)), levels)

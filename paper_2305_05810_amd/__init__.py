@@ -117,11 +117,25 @@ def _host(a: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(a)
 
 
+def _check_level_sizes(levels, width, height, texel_bytes):
+    """The C call reads w_l * h_l texels per level from host memory: make sure
+    the arrays hold that many bytes (positive sizes only; the library rejects
+    the rest)."""
+    if width <= 0 or height <= 0:
+        return
+    for l, a in enumerate(levels):
+        w, h = max(1, width >> l), max(1, height >> l)
+        if a.nbytes != w * h * texel_bytes:
+            raise ValueError(f"level {l} holds {a.nbytes} bytes, expected {w * h * texel_bytes}")
+
+
 def stf_create_texture2d(width: int, height: int, channels: int, fmt: int,
                          level_texels: Sequence[np.ndarray]) -> Texture:
     """level_texels[l]: raw texels of level l (any dtype whose bytes are the
     storage format), row-major, channels interleaved."""
     lv = [_host(a) for a in level_texels]
+    if fmt in FORMAT_BYTES and 1 <= channels <= 4:
+        _check_level_sizes(lv, width, height, channels * FORMAT_BYTES[fmt])
     arr = (C.c_void_p * len(lv))(*[a.ctypes.data for a in lv])
     h = C.c_void_p()
     _check(lib().stf_create_texture2d(width, height, channels, fmt, len(lv), arr, C.byref(h)))
@@ -130,6 +144,7 @@ def stf_create_texture2d(width: int, height: int, channels: int, fmt: int,
 
 def stf_create_material2d(width: int, height: int, level_texels: Sequence[np.ndarray]) -> Texture:
     lv = [_host(a) for a in level_texels]
+    _check_level_sizes(lv, width, height, 8)
     arr = (C.c_void_p * len(lv))(*[a.ctypes.data for a in lv])
     h = C.c_void_p()
     _check(lib().stf_create_material2d(width, height, len(lv), arr, C.byref(h)))

@@ -267,3 +267,81 @@ def uniform_box_queries(dims, n: int, seed: int = 5, margin: float = 2.0) -> np.
     lo = -margin
     hi = np.asarray(dims, np.float64) - 1.0 + margin
     return (lo + rng.random((n, 3)) * (hi - lo)).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# material texture for filtering with shading
+# ----------------------------------------------------------------------------
+MATERIAL_DTYPE = np.dtype([("albedo", np.uint8, 3), ("rough", np.uint8), ("nx", np.float16), ("ny", np.float16)])
+
+
+def _gauss_blur_fft(img: np.ndarray, sigma: float) -> np.ndarray:
+    """Periodic Gaussian blur of a 2D float64 image via the FFT."""
+    h, w = img.shape
+    fy = np.fft.fftfreq(h)[:, None]
+    fx = np.fft.rfftfreq(w)[None, :]
+    g = np.exp(-2.0 * (np.pi * sigma) ** 2 * (fx * fx + fy * fy))
+    return np.fft.irfft2(np.fft.rfft2(img) * g, s=img.shape)
+
+
+def material_levels(size: int = 4096, seed: int = 21, levels: int = 3):
+    """Material texels (H, W) of MATERIAL_DTYPE for levels 0..levels-1.
+
+    Level 0: albedo RGB uniform integers; roughness round(255 Beta(2, 5));
+    tangent normal from a height field of Gaussian bumps -- signed impulses at
+    uniform positions, blurred with radii 2..64 texels (log-spaced, density
+    falling with the radius squared, amplitude growing with the radius) plus a
+    small white perturbation -- by central differences, (nx, ny) rounded to
+    binary16.  Level l+1 is the 2x2 box average of level l: UNORM8 channels as
+    (a + b + c + d + 2) >> 2, normal components ((a + b) + c) + d in binary32,
+    divided by 4 and rounded to binary16, not renormalised."""
+    rng = np.random.default_rng(seed)
+    lv0 = np.zeros((size, size), MATERIAL_DTYPE)
+    lv0["albedo"] = rng.integers(0, 256, (size, size, 3), dtype=np.uint8)
+    lv0["rough"] = np.clip(np.rint(255.0 * rng.beta(2.0, 5.0, (size, size))), 0, 255).astype(np.uint8)
+    height = np.zeros((size, size), np.float64)
+    for r in (2.0, 4.0, 8.0, 16.0, 32.0, 64.0):
+        count = int(size * size / (r * r) * 0.05) + 1
+        imp = np.zeros((size, size), np.float64)
+        ys = rng.integers(0, size, count)
+        xs = rng.integers(0, size, count)
+        np.add.at(imp, (ys, xs), rng.normal(0.0, 1.0, count) * r * r * r * 2.0)
+        height += _gauss_blur_fft(imp, r)
+    height += rng.normal(0.0, 0.02, (size, size))
+    dhx = 0.5 * (np.roll(height, -1, axis=1) - np.roll(height, 1, axis=1))
+    dhy = 0.5 * (np.roll(height, -1, axis=0) - np.roll(height, 1, axis=0))
+    inv = 1.0 / np.sqrt(dhx * dhx + dhy * dhy + 1.0)
+    lv0["nx"] = (-dhx * inv).astype(np.float32).astype(np.float16)
+    lv0["ny"] = (-dhy * inv).astype(np.float32).astype(np.float16)
+    out = [lv0]
+    for _ in range(1, levels):
+        p = out[-1]
+        h2, w2 = p.shape[0] // 2, p.shape[1] // 2
+        q = np.zeros((h2, w2), MATERIAL_DTYPE)
+        a, b, c, d = p[0::2, 0::2], p[0::2, 1::2], p[1::2, 0::2], p[1::2, 1::2]
+        for f in ("albedo", "rough"):
+            s = a[f].astype(np.uint32) + b[f] + c[f] + d[f] + 2
+            q[f] = (s >> 2).astype(np.uint8)
+        for f in ("nx", "ny"):
+            s = ((a[f].astype(np.float32) + b[f].astype(np.float32)) + c[f].astype(np.float32)) + d[f].astype(np.float32)
+            q[f] = (s / np.float32(4.0)).astype(np.float16)
+        out.append(q)
+    return out
+
+
+def shade_queries(n: int = 1 << 23, seed: int = 22) -> np.ndarray:
+    """(n, 9) float32 shading records: uv uniform in [0,1)^2, footprint scale
+    s = 2^U(-2, 2) texels, then wo and wi uniform on the upper hemisphere
+    (z uniform in [0, 1), azimuth uniform)."""
+    rng = np.random.default_rng(seed)
+    rec = np.empty((n, 9), np.float32)
+    rec[:, 0:2] = rng.random((n, 2), dtype=np.float32)
+    rec[:, 2] = np.exp2(rng.random(n) * 4.0 - 2.0).astype(np.float32)
+    for k in (3, 6):
+        z = rng.random(n)
+        phi = rng.random(n) * 2.0 * np.pi
+        r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+        rec[:, k] = (r * np.cos(phi)).astype(np.float32)
+        rec[:, k + 1] = (r * np.sin(phi)).astype(np.float32)
+        rec[:, k + 2] = z.astype(np.float32)
+    return rec
