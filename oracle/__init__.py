@@ -93,7 +93,15 @@ def _declare_shade(L):
 
 
 def _declare_neural(L):
-    pass
+    vp, i32, i64, u64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_double
+    L.orc_ntex_nparams.argtypes, L.orc_ntex_nparams.restype = [], i32
+    L.orc_round_bf16.argtypes, L.orc_round_bf16.restype = [dbl], dbl
+    L.orc_ntex_decode.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, i32, vp]
+    L.orc_ntex_decode.restype = None
+    L.orc_ntex_filter.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, i64, i32, i32, u64, i32, vp, vp, i32]
+    L.orc_ntex_filter.restype = i32
+    L.orc_ntex_loss_grad.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, i64, vp, vp]
+    L.orc_ntex_loss_grad.restype = dbl
 
 
 # ----------------------------------------------------------------------------
@@ -308,3 +316,58 @@ def ggx_D(n, h, alpha: float) -> float:
 
 def shade_level(s: float, levels: int) -> int:
     return lib().orc_shade_level(float(np.float32(s)), levels)
+
+
+# ----------------------------------------------------------------------------
+# neural texture
+# ----------------------------------------------------------------------------
+NTEX_PARAMS = 5256
+
+
+def round_bf16(x: float) -> float:
+    return lib().orc_round_bf16(float(x))
+
+
+class NeuralTexture:
+    """Oracle view of a neural texture: latents (LH, LW, 8) and the MLP
+    parameter vector (5256) in binary64; decoded texture size W x H."""
+
+    def __init__(self, latents, mlp, width: int, height: int):
+        self.lat = np.ascontiguousarray(latents, np.float64)
+        self.mlp = np.ascontiguousarray(mlp, np.float64)
+        assert self.mlp.size == NTEX_PARAMS and self.lat.shape[2] == 8
+        self.LH, self.LW = self.lat.shape[:2]
+        self.W, self.H = width, height
+
+    def decode(self, i: int, j: int, emulate: bool = False) -> np.ndarray:
+        out = np.zeros(8, np.float64)
+        lib().orc_ntex_decode(_p(self.lat), self.LW, self.LH, self.W, self.H, _p(self.mlp), i, j, int(emulate),
+                              _p(out))
+        return out
+
+    def decode_all(self, emulate: bool = False) -> np.ndarray:
+        """(H, W, 8) decoded texels (texel-centre queries through the filter)."""
+        js, is_ = np.meshgrid(np.arange(self.H), np.arange(self.W), indexing="ij")
+        uv = np.stack([(is_ + 0.5) / self.W, (js + 0.5) / self.H], axis=-1).reshape(-1, 2).astype(np.float32)
+        out, _ = self.filter(uv, LINEAR, DET, emulate=emulate)
+        return out.reshape(self.H, self.W, 8)
+
+    def filter(self, uv, filt: int, mode: int, seed: int = 0, qids=None, emulate: bool = False, nthreads: int = 0):
+        uv = np.ascontiguousarray(uv, np.float32)
+        qids_a = None if qids is None else np.ascontiguousarray(qids, np.int64)
+        m = uv.shape[0] if qids_a is None else qids_a.shape[0]
+        out = np.empty((m, 8), np.float64)
+        idx = np.empty((m, 2), np.int32) if mode != DET else None
+        lib().orc_ntex_filter(_p(self.lat), self.LW, self.LH, self.W, self.H, _p(self.mlp), _p(uv), _p(qids_a), m,
+                              filt, mode, seed, int(emulate), _p(out), _p(idx), nthreads)
+        return out, idx
+
+    def loss_grad(self, target, pos, want_grad: bool = True):
+        """target (H, W, 8) float32; pos (B, 2) int32 texel (i, j)."""
+        target = np.ascontiguousarray(target, np.float32)
+        pos = np.ascontiguousarray(pos, np.int32)
+        gl = np.zeros_like(self.lat) if want_grad else None
+        gm = np.zeros(NTEX_PARAMS) if want_grad else None
+        loss = lib().orc_ntex_loss_grad(_p(self.lat), self.LW, self.LH, self.W, self.H, _p(self.mlp), _p(target),
+                                        _p(pos), pos.shape[0], _p(gl), _p(gm))
+        return loss, gl, gm

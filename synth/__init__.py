@@ -345,3 +345,67 @@ def shade_queries(n: int = 1 << 23, seed: int = 22) -> np.ndarray:
         rec[:, k + 1] = (r * np.sin(phi)).astype(np.float32)
         rec[:, k + 2] = z.astype(np.float32)
     return rec
+
+
+# ----------------------------------------------------------------------------
+# neural texture workload
+# ----------------------------------------------------------------------------
+def _smooth_field(size: int, rng, radii=(4.0, 8.0, 16.0, 32.0)) -> np.ndarray:
+    """Sum of periodically blurred white noise at several radii, normalised to
+    zero mean and unit standard deviation."""
+    f = np.zeros((size, size), np.float64)
+    for r in radii:
+        f += _gauss_blur_fft(rng.normal(0.0, 1.0, (size, size)), r) * r
+    f -= f.mean()
+    return f / (f.std() + 1e-30)
+
+
+def _fbm2d(size: int, rng, base_period: float = 64.0, octaves: int = 5) -> np.ndarray:
+    """2D value-noise fBm (lacunarity 2, gain 0.5), smoothstep-faded bilinear
+    interpolation of uniform [-1, 1) lattices."""
+    out = np.zeros((size, size), np.float64)
+    for o in range(octaves):
+        period = base_period / 2 ** o
+        cx, wx = _axis_interp(size, period, rng.random() * period)
+        cy, wy = _axis_interp(size, period, rng.random() * period)
+        lat = rng.random((int(cy[-1]) + 2, int(cx[-1]) + 2)) * 2.0 - 1.0
+        a = lat[:, cx] * (1 - wx) + lat[:, cx + 1] * wx
+        out += 0.5 ** o * (a[cy, :] * (1 - wy)[:, None] + a[cy + 1, :] * wy[:, None])
+    return out
+
+
+def neural_target(size: int = 4096, seed: int = 41) -> np.ndarray:
+    """(size, size, 8) float32 material for the neural texture: albedo RGB
+    and roughness as smooth fields squashed into [0, 1], a tangent normal
+    (x, y) from a Gaussian-bump height field, and two fBm detail channels."""
+    rng = np.random.default_rng(seed)
+    t = np.empty((size, size, 8), np.float32)
+    for c in range(3):
+        t[:, :, c] = 0.5 + 0.35 * np.tanh(_smooth_field(size, rng))
+    t[:, :, 3] = 0.35 + 0.25 * np.tanh(_smooth_field(size, rng, radii=(8.0, 32.0)))
+    height = _smooth_field(size, rng, radii=(2.0, 6.0, 18.0)) * 1.5
+    dhx = 0.5 * (np.roll(height, -1, axis=1) - np.roll(height, 1, axis=1))
+    dhy = 0.5 * (np.roll(height, -1, axis=0) - np.roll(height, 1, axis=0))
+    inv = 1.0 / np.sqrt(dhx * dhx + dhy * dhy + 1.0)
+    t[:, :, 4] = -dhx * inv
+    t[:, :, 5] = -dhy * inv
+    t[:, :, 6] = 0.5 + 0.5 * _fbm2d(size, rng)
+    t[:, :, 7] = 0.5 + 0.5 * _fbm2d(size, rng, base_period=32.0)
+    return t
+
+
+def neural_init(latent_size: int = 1024, seed: int = 42):
+    """Initial latents (latent_size, latent_size, 8) ~ N(0, 0.1^2) and MLP
+    parameters (5256,) with He-normal weights and zero biases, float32.
+    Layout: W1[64][8], b1[64], W2[64][64], b2[64], W3[8][64], b3[8]."""
+    rng = np.random.default_rng(seed)
+    lat = rng.normal(0.0, 0.1, (latent_size, latent_size, 8)).astype(np.float32)
+    w1 = rng.normal(0.0, np.sqrt(2.0 / 8), (64, 8))
+    w2 = rng.normal(0.0, np.sqrt(2.0 / 64), (64, 64))
+    w3 = rng.normal(0.0, np.sqrt(1.0 / 64), (8, 64))
+    mlp = np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3.ravel(), np.zeros(8)])
+    return lat, mlp.astype(np.float32)
+
+
+def neural_queries(n: int = 1 << 24, seed: int = 43) -> np.ndarray:
+    return uv_queries(n, seed)
