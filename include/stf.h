@@ -191,6 +191,69 @@ stf_status stf_shade_filter(const stf_texture* material, const float* shade_quer
                             stf_filter_kind filter, stf_shade_mode mode, uint64_t seed,
                             float* out_rgb_dev, int32_t* out_index_dev, void* hip_stream);
 
+/* ---------------------------------------------------------------------- */
+/* Neural texture                                                          */
+/* ---------------------------------------------------------------------- */
+/* A tex_w x tex_h texture of 8 channels represented by a lat_w x lat_h grid
+ * of 8-vectors and an MLP 8 -> 64 -> 64 -> 8 with ReLU after both hidden
+ * layers: texel (i, j) decodes to MLP(z), z the bilinear interpolation of
+ * the latent grid at X = (i + 1/2) lat_w/tex_w - 1/2 (likewise Y), corners
+ * clamped.  The paper's case for stochastic filtering of such encodings: a
+ * lookup decodes one texel instead of one per tap (sections Introduction
+ * and Background on neural and compressed representations).
+ *
+ * MLP parameter vector (stf_ntex_param_count() = 5256 binary32 values):
+ * W1[64][8], b1[64], W2[64][64], b2[64], W3[8][64], b3[8], row = output
+ * feature.  Latents: lat_h x lat_w x 8 binary32, channels interleaved. */
+typedef struct stf_neural stf_neural;   /* opaque, library-owned */
+
+int32_t stf_ntex_param_count(void);
+
+/* tex_w / lat_w and tex_h / lat_h must be powers of two (else
+ * STF_E_UNSUPPORTED).  Initial parameters are copied from host memory. */
+stf_status stf_ntex_create(int32_t tex_w, int32_t tex_h, int32_t lat_w, int32_t lat_h,
+                           const float* latents_host, const float* mlp_host, stf_neural** out);
+void stf_ntex_destroy(stf_neural* nt);
+
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on
+ * the mean squared error (1/(8B)) sum (decoded - target)^2 over batches of
+ * `batch` texel positions drawn from the counter hash of (seed, step).
+ * target_dev: tex_h x tex_w x 8 binary32 on the device (16-byte aligned).
+ * loss_dev: NULL or `steps` binary32, the loss of each step.  Training runs
+ * in binary32 with the library's own kernels; the latent gradient is
+ * accumulated with atomics, so it is not bitwise reproducible. */
+stf_status stf_ntex_train(stf_neural* nt, const float* target_dev, int32_t steps, int32_t batch,
+                          float lr_latent, float lr_mlp, uint64_t seed, float* loss_dev, void* hip_stream);
+
+/* The gradient of the same loss over an explicit batch: positions_dev is
+ * batch x 2 int32 texel coordinates (i, j).  Writes lat_h*lat_w*8 latent
+ * gradients, 5256 MLP gradients and the loss (nullable), all device memory.
+ * Positions outside the texture are clamped to it.
+ * The parameters are not changed. */
+stf_status stf_ntex_gradients(stf_neural* nt, const float* target_dev, const int32_t* positions_dev,
+                              int32_t batch, float* grad_latents_dev, float* grad_mlp_dev,
+                              float* loss_dev, void* hip_stream);
+
+/* Copies the current binary32 parameters to host memory (synchronises the
+ * device).  Either pointer may be NULL. */
+stf_status stf_ntex_get_params(const stf_neural* nt, float* latents_host, float* mlp_host);
+
+/* Freezes the current parameters for inference: latents rounded to binary16,
+ * weights to bfloat16 (round to nearest even), biases kept in binary32.
+ * Must be called after training and before stf_ntex_filter. */
+stf_status stf_ntex_prepare_inference(stf_neural* nt, void* hip_stream);
+
+/* Filters decoded texels at n uv queries (n x 2 binary32, raster rules of
+ * stf_create_texture2d, clamped taps), bilinear or bicubic B-spline;
+ * deterministic decodes every tap (4 or 16 decodes per query), stochastic
+ * decodes the one sampled tap.  Decoding runs on BF16 matrix cores with
+ * binary32 accumulation: the interpolated latent and each hidden activation
+ * (after ReLU) are rounded to bfloat16.  out_dev: n x 8 binary32 (16-byte
+ * aligned); out_index_dev: NULL or (stochastic) n x 2 int32 texel (x, y). */
+stf_status stf_ntex_filter(const stf_neural* nt, const float* queries_dev, int64_t n,
+                           stf_filter_kind filter, stf_mode mode, uint64_t seed, float* out_dev,
+                           int32_t* out_index_dev, void* hip_stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* stf_last_error(void);
 

@@ -228,3 +228,98 @@ def filter(tex: Texture, queries, filter: int, mode: int, seed: int = 0, want_in
         idx = torch.empty((n, tex.dims), dtype=torch.int32, device=queries.device)
     stf_filter(tex, queries, filter, mode, seed, out, idx, 0, stream)
     return out, idx
+
+
+# ----------------------------------------------------------------------------
+# neural texture
+# ----------------------------------------------------------------------------
+def _declare_ntex(L):
+    vp, i32, i64, u64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_float
+    L.stf_ntex_param_count.argtypes, L.stf_ntex_param_count.restype = [], i32
+    L.stf_ntex_create.argtypes = [i32, i32, i32, i32, vp, vp, C.POINTER(vp)]
+    L.stf_ntex_destroy.argtypes, L.stf_ntex_destroy.restype = [vp], None
+    L.stf_ntex_train.argtypes = [vp, vp, i32, i32, f32, f32, u64, vp, vp]
+    L.stf_ntex_gradients.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+    L.stf_ntex_get_params.argtypes = [vp, vp, vp]
+    L.stf_ntex_prepare_inference.argtypes = [vp, vp]
+    L.stf_ntex_filter.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, vp]
+    for name in ("stf_ntex_create", "stf_ntex_train", "stf_ntex_gradients", "stf_ntex_get_params",
+                 "stf_ntex_prepare_inference", "stf_ntex_filter"):
+        getattr(L, name).restype = i32
+
+
+class NeuralTexture:
+    """Owning handle of an stf_neural."""
+
+    def __init__(self, handle, tex_w, tex_h, lat_w, lat_h):
+        self.handle, self.W, self.H, self.LW, self.LH = handle, tex_w, tex_h, lat_w, lat_h
+
+    def destroy(self):
+        if self.handle:
+            lib().stf_ntex_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _ntex_lib():
+    L = lib()
+    if not getattr(L, "_ntex_declared", False):
+        _declare_ntex(L)
+        L._ntex_declared = True
+    return L
+
+
+def stf_ntex_param_count() -> int:
+    return _ntex_lib().stf_ntex_param_count()
+
+
+def stf_ntex_create(tex_w: int, tex_h: int, latents: np.ndarray, mlp: np.ndarray) -> NeuralTexture:
+    """latents: (lat_h, lat_w, 8) float32; mlp: (5256,) float32."""
+    lat = _host(np.asarray(latents, np.float32))
+    m = _host(np.asarray(mlp, np.float32))
+    if lat.ndim != 3 or lat.shape[2] != 8 or m.size != stf_ntex_param_count():
+        raise ValueError("latents must be (lat_h, lat_w, 8) and mlp must hold 5256 values")
+    h = C.c_void_p()
+    _check(_ntex_lib().stf_ntex_create(tex_w, tex_h, lat.shape[1], lat.shape[0], lat.ctypes.data, m.ctypes.data,
+                                       C.byref(h)))
+    return NeuralTexture(h.value, tex_w, tex_h, lat.shape[1], lat.shape[0])
+
+
+def stf_ntex_destroy(nt: NeuralTexture):
+    nt.destroy()
+
+
+def stf_ntex_train(nt: NeuralTexture, target, steps: int, batch: int, lr_latent: float, lr_mlp: float, seed: int,
+                   loss=None, stream=None):
+    """target: (tex_h, tex_w, 8) float32 GPU tensor; loss: None or (steps,) float32 GPU tensor."""
+    _check(_ntex_lib().stf_ntex_train(nt.handle, _dev_ptr(target, "target"), steps, batch, lr_latent, lr_mlp,
+                                      seed & (2 ** 64 - 1), _dev_ptr(loss, "loss"), _stream(stream)))
+
+
+def stf_ntex_gradients(nt: NeuralTexture, target, positions, grad_latents, grad_mlp, loss=None, stream=None):
+    _check(_ntex_lib().stf_ntex_gradients(nt.handle, _dev_ptr(target, "target"), _dev_ptr(positions, "positions"),
+                                          positions.shape[0], _dev_ptr(grad_latents, "grad_latents"),
+                                          _dev_ptr(grad_mlp, "grad_mlp"), _dev_ptr(loss, "loss"), _stream(stream)))
+
+
+def stf_ntex_get_params(nt: NeuralTexture):
+    lat = np.empty((nt.LH, nt.LW, 8), np.float32)
+    m = np.empty(stf_ntex_param_count(), np.float32)
+    _check(_ntex_lib().stf_ntex_get_params(nt.handle, lat.ctypes.data, m.ctypes.data))
+    return lat, m
+
+
+def stf_ntex_prepare_inference(nt: NeuralTexture, stream=None):
+    _check(_ntex_lib().stf_ntex_prepare_inference(nt.handle, _stream(stream)))
+
+
+def stf_ntex_filter(nt: NeuralTexture, queries, filter: int, mode: int, seed: int, out, out_index=None, stream=None):
+    """queries: (n, 2) float32 GPU tensor; out: (n, 8) float32 GPU tensor."""
+    _check(_ntex_lib().stf_ntex_filter(nt.handle, _dev_ptr(queries, "queries"), queries.shape[0], filter, mode,
+                                       seed & (2 ** 64 - 1), _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"),
+                                       _stream(stream)))

@@ -1,0 +1,821 @@
+// neural.hip -- a neural texture (latent grid + MLP) trained on the GPU and
+// filtered with BF16 MFMA inference.
+//
+// The paper argues that stochastic filtering makes expensive texel encodings
+// viable because a lookup decodes one texel instead of one per filter tap
+// (sections Introduction and Background, neural and compressed
+// representations).  Here a W x H x 8 texture is represented by an
+// LW x LH x 8 latent grid and an MLP 8 -> 64 -> 64 -> 8 (ReLU after the two
+// hidden layers): texel (i, j) decodes to MLP(bilerp of the latent grid at
+// X = (i + 1/2) LW/W - 1/2, clamped corners).  Filtering decodes every tap
+// (deterministic) or the one sampled tap (stochastic), with the tap rules of
+// the 2D filters.
+//
+// Training (binary32): per step a batch of texel positions, forward and
+// backward through the MLP and the bilinear interpolation, mean squared
+// error against the target texels, Adam.  One kernel processes tiles of 32
+// samples with the weights in LDS and accumulates weight gradients per block;
+// a second kernel reduces the blocks in a fixed order; latent gradients are
+// scattered with atomics.
+//
+// Inference: latents rounded to binary16, weights to bfloat16, biases kept in
+// binary32.  Each wave decodes 32 texels per MFMA batch with
+// v_mfma_f32_32x32x16_bf16 in the transposed form out^T = W in^T, so each
+// layer's accumulator registers are already the next layer's B operand once
+// the hidden units are stored in the order the accumulator layout produces.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "device_common.h"
+#include "stf_internal.h"
+
+using namespace stf;
+
+namespace {
+
+constexpr int NL = 8, NH = 64, NO = 8;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NL, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
+              OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NO * NH, NPARAM = OFF_B3 + NO;
+constexpr int PSTRIDE = NPARAM + 1;   // per-block partial gradients + loss
+constexpr int TS = 32;                 // samples per training tile
+constexpr int TBLOCK = 256;
+constexpr int OWN = (NPARAM + TBLOCK - 1) / TBLOCK;   // parameters owned per thread
+
+struct TrainArgs {
+    const float* lat;
+    const float* mlp;
+    const float* target;
+    const int32_t* pos;   // nullable: positions drawn from the counter hash
+    int32_t B, W, H, LW, LH;
+    float rx, ry;         // LW / W, LH / H (powers of two)
+    uint32_t kstep;
+    float dscale;         // 2 / (8 B)
+    float* g_lat;
+    float* partial;
+};
+
+__device__ __forceinline__ int clampi(int v, int hi)
+{
+    return v < 0 ? 0 : (v > hi ? hi : v);
+}
+
+__global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
+{
+    __shared__ float sW1[NH][NL + 1], sB1[NH], sW2[NH][NH + 1], sB2[NH], sW3[NO][NH + 1], sB3[NO];
+    __shared__ float sZ[TS][NL + 1], sT[TS][NO + 1], sH1[TS][NH + 1], sH2[TS][NH + 1], sDY[TS][NO + 1];
+    __shared__ float sD2[TS][NH + 1], sD1[TS][NH + 1];
+    __shared__ int32_t sCI[TS][4];
+    __shared__ float sCW[TS][4];
+    __shared__ int32_t sTex[TS];
+    __shared__ float sRed[TBLOCK];
+    const int t = threadIdx.x;
+    for (int p = t; p < NPARAM; p += TBLOCK) {
+        float v = a.mlp[p];
+        if (p < OFF_B1) sW1[p / NL][p % NL] = v;
+        else if (p < OFF_W2) sB1[p - OFF_B1] = v;
+        else if (p < OFF_B2) sW2[(p - OFF_W2) / NH][(p - OFF_W2) % NH] = v;
+        else if (p < OFF_W3) sB2[p - OFF_B2] = v;
+        else if (p < OFF_B3) sW3[(p - OFF_W3) / NH][(p - OFF_W3) % NH] = v;
+        else sB3[p - OFF_B3] = v;
+    }
+    float acc[OWN];
+#pragma unroll
+    for (int r = 0; r < OWN; ++r) acc[r] = 0.0f;
+    float lacc = 0.0f;
+    const int s = t / 8, k = t % 8;   // (sample, channel) for the gather/scatter phases
+    for (int tile = blockIdx.x; tile * TS < a.B; tile += gridDim.x) {
+        const int gs = tile * TS + s;
+        const bool live = gs < a.B;
+        __syncthreads();   // previous tile's LDS reads are done
+        if (k == 0) {
+            int i = 0, j = 0;
+            if (live) {
+                if (a.pos) {   // caller-supplied positions are clamped into the texture
+                    i = clampi(a.pos[2 * (int64_t)gs], a.W - 1);
+                    j = clampi(a.pos[2 * (int64_t)gs + 1], a.H - 1);
+                } else {
+                    uint32_t h = pcg(a.kstep ^ (uint32_t)gs);
+                    i = (int)(h % (uint32_t)a.W);
+                    j = (int)(pcg(h + 1u) % (uint32_t)a.H);
+                }
+            }
+            float X = ((float)i + 0.5f) * a.rx - 0.5f, Y = ((float)j + 0.5f) * a.ry - 0.5f;
+            float fx0 = floorf(X), fy0 = floorf(Y);
+            float fx = X - fx0, fy = Y - fy0;
+            int x0 = (int)fx0, y0 = (int)fy0;
+            int xa = clampi(x0, a.LW - 1), xb = clampi(x0 + 1, a.LW - 1);
+            int ya = clampi(y0, a.LH - 1), yb = clampi(y0 + 1, a.LH - 1);
+            sCI[s][0] = ya * a.LW + xa;
+            sCI[s][1] = ya * a.LW + xb;
+            sCI[s][2] = yb * a.LW + xa;
+            sCI[s][3] = yb * a.LW + xb;
+            sCW[s][0] = (1.0f - fx) * (1.0f - fy);
+            sCW[s][1] = fx * (1.0f - fy);
+            sCW[s][2] = (1.0f - fx) * fy;
+            sCW[s][3] = fx * fy;
+            sTex[s] = j * a.W + i;
+        }
+        __syncthreads();
+        {
+            float z = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) z = __builtin_fmaf(sCW[s][c], a.lat[(int64_t)sCI[s][c] * NL + k], z);
+            sZ[s][k] = live ? z : 0.0f;
+            sT[s][k] = live ? a.target[(int64_t)sTex[s] * NO + k] : 0.0f;
+        }
+        __syncthreads();
+        const int ha = t % NH, hs = t / NH;   // (hidden unit, first sample) for the 32 x 64 phases
+#pragma unroll
+        for (int r = 0; r < TS / 4; ++r) {
+            int s2 = hs + 4 * r;
+            float v = sB1[ha];
+#pragma unroll
+            for (int kk = 0; kk < NL; ++kk) v = __builtin_fmaf(sW1[ha][kk], sZ[s2][kk], v);
+            sH1[s2][ha] = fmaxf(v, 0.0f);
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int r = 0; r < TS / 4; ++r) {
+            int s2 = hs + 4 * r;
+            float v = sB2[ha];
+#pragma unroll 16
+            for (int b = 0; b < NH; ++b) v = __builtin_fmaf(sW2[ha][b], sH1[s2][b], v);
+            sH2[s2][ha] = fmaxf(v, 0.0f);
+        }
+        __syncthreads();
+        {
+            float y = sB3[k];
+#pragma unroll 16
+            for (int b = 0; b < NH; ++b) y = __builtin_fmaf(sW3[k][b], sH2[s][b], y);
+            float e = y - sT[s][k];
+            if (live) lacc = __builtin_fmaf(e, e, lacc);
+            sDY[s][k] = live ? e * a.dscale : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < TS / 4; ++r) {
+            int s2 = hs + 4 * r;
+            float v = 0.0f;
+#pragma unroll
+            for (int c = 0; c < NO; ++c) v = __builtin_fmaf(sW3[c][ha], sDY[s2][c], v);
+            sD2[s2][ha] = sH2[s2][ha] > 0.0f ? v : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int r = 0; r < TS / 4; ++r) {
+            int s2 = hs + 4 * r;
+            float v = 0.0f;
+#pragma unroll 16
+            for (int b = 0; b < NH; ++b) v = __builtin_fmaf(sW2[b][ha], sD2[s2][b], v);
+            sD1[s2][ha] = sH1[s2][ha] > 0.0f ? v : 0.0f;
+        }
+        __syncthreads();
+        {
+            float dz = 0.0f;
+#pragma unroll 16
+            for (int b = 0; b < NH; ++b) dz = __builtin_fmaf(sW1[b][k], sD1[s][b], dz);
+            if (live) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) atomicAdd(a.g_lat + (int64_t)sCI[s][c] * NL + k, sCW[s][c] * dz);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < OWN; ++r) {
+            int p = t + TBLOCK * r;
+            float g = 0.0f;
+            if (p < OFF_B1) {
+                int ua = p / NL, uk = p % NL;
+                for (int q = 0; q < TS; ++q) g = __builtin_fmaf(sD1[q][ua], sZ[q][uk], g);
+            } else if (p < OFF_W2) {
+                for (int q = 0; q < TS; ++q) g += sD1[q][p - OFF_B1];
+            } else if (p < OFF_B2) {
+                int ua = (p - OFF_W2) / NH, ub = (p - OFF_W2) % NH;
+                for (int q = 0; q < TS; ++q) g = __builtin_fmaf(sD2[q][ua], sH1[q][ub], g);
+            } else if (p < OFF_W3) {
+                for (int q = 0; q < TS; ++q) g += sD2[q][p - OFF_B2];
+            } else if (p < OFF_B3) {
+                int uc = (p - OFF_W3) / NH, ua = (p - OFF_W3) % NH;
+                for (int q = 0; q < TS; ++q) g = __builtin_fmaf(sDY[q][uc], sH2[q][ua], g);
+            } else if (p < NPARAM) {
+                for (int q = 0; q < TS; ++q) g += sDY[q][p - OFF_B3];
+            }
+            acc[r] += g;
+        }
+    }
+    float* out = a.partial + (int64_t)blockIdx.x * PSTRIDE;
+#pragma unroll
+    for (int r = 0; r < OWN; ++r) {
+        int p = t + TBLOCK * r;
+        if (p < NPARAM) out[p] = acc[r];
+    }
+    sRed[t] = lacc;
+    __syncthreads();
+    for (int st = TBLOCK / 2; st > 0; st >>= 1) {
+        if (t < st) sRed[t] += sRed[t + st];
+        __syncthreads();
+    }
+    if (t == 0) out[NPARAM] = sRed[0];
+}
+
+// Sum of the per-block partials in block order (reproducible).
+__global__ void k_ntex_reduce(const float* __restrict__ partial, int nblocks, float* __restrict__ g_mlp,
+                              float* __restrict__ loss, float loss_scale)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > NPARAM) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * PSTRIDE + p];
+    if (p < NPARAM) g_mlp[p] = s;
+    else if (loss) *loss = s * loss_scale;
+}
+
+// Adam (beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected); clears the
+// gradient it consumed.
+__global__ void k_adam(float* __restrict__ param, float* __restrict__ grad, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float c1, float c2)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float g = grad[e];
+    float mm = 0.9f * m[e] + 0.1f * g;
+    float vv = 0.999f * v[e] + 0.001f * g * g;
+    m[e] = mm;
+    v[e] = vv;
+    param[e] -= lr * (mm * c1) / (sqrtf(vv * c2) + 1e-8f);
+    grad[e] = 0.0f;
+}
+
+__global__ void k_fill(float* __restrict__ p, int64_t n, float v)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
+__global__ void k_to_f16(const float* __restrict__ src, uint16_t* __restrict__ dst, int64_t n)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) dst[e] = __builtin_bit_cast(uint16_t, (_Float16)src[e]);
+}
+
+// ---------------------------------------------------------------------------
+// inference
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Operand images, one 8-value (A) or 16-value (C) slot per lane, in the order
+// the kernel loads them.
+struct Packed {
+    bf16x8 a1[2][64];      // layer 1, M-blocks of 32 hidden units; K = 8 latent + 8 zero
+    bf16x8 a2[2][4][64];   // layer 2, M-blocks x K-blocks of 16
+    bf16x8 a3[4][64];      // layer 3, rows 0..7 real, 8..31 zero
+    float c1[2][64][16];   // biases laid out as accumulator images
+    float c2[2][64][16];
+    float c3[64][16];
+};
+
+// Hidden unit held by k-slot kappa = 16 kb + 8 h + j of the B operand when
+// the previous layer's accumulator registers are used in place.
+__host__ __device__ constexpr int hidden_of_slot(int kb, int h, int j)
+{
+    return 16 * kb + 8 * (j / 4) + 4 * h + (j % 4);
+}
+
+// Hidden/output unit held by accumulator register r of lane half h in M-block mb.
+__host__ __device__ constexpr int row_of_acc(int mb, int h, int r)
+{
+    return 32 * mb + 8 * (r / 4) + 4 * h + (r % 4);
+}
+
+struct InferArgs {
+    const Packed* pk;
+    const uint16_t* lat16;   // LH x LW x 8 binary16
+    const float* q;          // n x 2 uv
+    int32_t n, W, H, LW, LH;
+    float rx, ry;
+    uint32_t key;
+    float* out;              // n x 8
+    int32_t* idx;            // n x 2 (stochastic) or null
+};
+
+__device__ __forceinline__ bf16x8 relu_bf16(const f32x16& d, int base)
+{
+    bf16x8 r;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = (__bf16)fmaxf(d[base + j], 0.0f);
+    return r;
+}
+
+template <bool CUBIC, bool STOCH>
+__global__ __launch_bounds__(256) void k_ntex_infer(InferArgs a)
+{
+    constexpr int TAPS = STOCH ? 1 : (CUBIC ? 16 : 4);
+    constexpr int QPB = 32 / TAPS;   // queries per 32-decode batch
+    const int lane = threadIdx.x % 64, h = lane / 32, jd = lane % 32;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int nwaves = gridDim.x * blockDim.x / 64;
+    const Packed* pk = a.pk;
+    bf16x8 A1[2], A2[2][4], A3[4];
+    f32x16 C1[2], C2[2], C3;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+        A1[mb] = pk->a1[mb][lane];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) A2[mb][kb] = pk->a2[mb][kb][lane];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            C1[mb][r] = pk->c1[mb][lane][r];
+            C2[mb][r] = pk->c2[mb][lane][r];
+        }
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) A3[kb] = pk->a3[kb][lane];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) C3[r] = pk->c3[lane][r];
+
+    const int64_t nbatch = ((int64_t)a.n + QPB - 1) / QPB;
+    for (int64_t bt = wave; bt < nbatch; bt += nwaves) {
+        // ---- which query and tap this lane's decode serves
+        const int64_t qi = bt * QPB + jd / TAPS;
+        const int tap = jd % TAPS;
+        const bool live = qi < a.n;
+        float2 uv = live ? reinterpret_cast<const float2*>(a.q)[qi] : make_float2(0.5f, 0.5f);
+        float x = uv.x * (float)a.W - 0.5f, y = uv.y * (float)a.H - 0.5f;
+        int cx = 0, cy = 0;
+        float tx = 0.0f, ty = 0.0f;
+        const bool fin = cell_of(x, cx, tx) & cell_of(y, cy, ty);
+        int sx, sy;
+        float w = 1.0f;
+        if constexpr (STOCH) {
+            uint32_t h0 = pcg(a.key ^ (uint32_t)qi);
+            if constexpr (CUBIC) {
+                sx = cx + choose_cubic_m(tx, hash_m(h0));
+                sy = cy + choose_cubic_m(ty, hash_m(pcg(h0 + 1u)));
+            } else {
+                sx = cx + choose_linear_m(tx, hash_m(h0));
+                sy = cy + choose_linear_m(ty, hash_m(pcg(h0 + 1u)));
+            }
+        } else if constexpr (CUBIC) {
+            int ta = tap % 4, tb = tap / 4;
+            Cubic6 wa = cubic6(tx), wb = cubic6(ty);
+            float fa = ta == 0 ? wa.a0 : ta == 1 ? wa.a1 : ta == 2 ? wa.a2 : wa.a3;
+            float fb = tb == 0 ? wb.a0 : tb == 1 ? wb.a1 : tb == 2 ? wb.a2 : wb.a3;
+            w = (fa * K6) * (fb * K6);
+            sx = cx - 1 + ta;
+            sy = cy - 1 + tb;
+        } else {
+            int ta = tap % 2, tb = tap / 2;
+            w = (ta ? tx : 1.0f - tx) * (tb ? ty : 1.0f - ty);
+            sx = cx + ta;
+            sy = cy + tb;
+        }
+        sx = clampi(sx, a.W - 1);
+        sy = clampi(sy, a.H - 1);
+        // ---- latent interpolation (lanes 0..31 carry the 8 latent channels)
+        bf16x8 B1;
+        if (h == 0) {
+            float X = ((float)sx + 0.5f) * a.rx - 0.5f, Y = ((float)sy + 0.5f) * a.ry - 0.5f;
+            float fx0 = floorf(X), fy0 = floorf(Y);
+            float fx = X - fx0, fy = Y - fy0;
+            int x0 = (int)fx0, y0 = (int)fy0;
+            int xa = clampi(x0, a.LW - 1), xb = clampi(x0 + 1, a.LW - 1);
+            int ya = clampi(y0, a.LH - 1), yb = clampi(y0 + 1, a.LH - 1);
+            const uint4* L = reinterpret_cast<const uint4*>(a.lat16);
+            uint4 c00 = L[(int64_t)ya * a.LW + xa], c10 = L[(int64_t)ya * a.LW + xb];
+            uint4 c01 = L[(int64_t)yb * a.LW + xa], c11 = L[(int64_t)yb * a.LW + xb];
+            float w00 = (1.0f - fx) * (1.0f - fy), w10 = fx * (1.0f - fy), w01 = (1.0f - fx) * fy, w11 = fx * fy;
+            const uint32_t* p00 = reinterpret_cast<const uint32_t*>(&c00);
+            const uint32_t* p10 = reinterpret_cast<const uint32_t*>(&c10);
+            const uint32_t* p01 = reinterpret_cast<const uint32_t*>(&c01);
+            const uint32_t* p11 = reinterpret_cast<const uint32_t*>(&c11);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                int wsel = j / 2, sh = 16 * (j % 2);
+                float v = w00 * dec_f16((uint16_t)(p00[wsel] >> sh));
+                v = __builtin_fmaf(w10, dec_f16((uint16_t)(p10[wsel] >> sh)), v);
+                v = __builtin_fmaf(w01, dec_f16((uint16_t)(p01[wsel] >> sh)), v);
+                v = __builtin_fmaf(w11, dec_f16((uint16_t)(p11[wsel] >> sh)), v);
+                B1[j] = (__bf16)v;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) B1[j] = (__bf16)0.0f;
+        }
+        // ---- layer 1: 64 x 16 (K padded) by 16 x 32
+        f32x16 D1[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) D1[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[mb], B1, C1[mb], 0, 0, 0);
+        bf16x8 B2[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) B2[kb] = relu_bf16(D1[kb / 2], 8 * (kb % 2));
+        // ---- layer 2: 64 x 64 by 64 x 32
+        f32x16 D2[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            D2[mb] = C2[mb];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+                D2[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2[mb][kb], B2[kb], D2[mb], 0, 0, 0);
+        }
+        bf16x8 B3[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) B3[kb] = relu_bf16(D2[kb / 2], 8 * (kb % 2));
+        // ---- layer 3: 8 (of 32) x 64 by 64 x 32
+        f32x16 D3 = C3;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) D3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A3[kb], B3[kb], D3, 0, 0, 0);
+        // ---- registers 0..3 of this lane: channels 4h..4h+3 of decode jd
+        float o[4] = {D3[0] * w, D3[1] * w, D3[2] * w, D3[3] * w};
+#pragma unroll
+        for (int off = 1; off < TAPS; off <<= 1) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o[c] += __shfl_xor(o[c], off, 64);
+        }
+        if (live && tap == 0) {
+            float4 v = fin ? make_float4(o[0], o[1], o[2], o[3])
+                           : make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+            reinterpret_cast<float4*>(a.out)[qi * 2 + h] = v;
+            if (STOCH && a.idx && h == 0) {
+                a.idx[2 * qi] = fin ? sx : BAD_INDEX;
+                a.idx[2 * qi + 1] = fin ? sy : BAD_INDEX;
+            }
+        }
+    }
+}
+
+uint16_t f2bf16_host(float f)
+{
+    // round to nearest even (finite inputs)
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+void pack_weights(const float* mlp, Packed* pk)
+{
+    memset(pk, 0, sizeof(Packed));
+    auto put = [](bf16x8& dst, int j, float v) {
+        uint16_t u = f2bf16_host(v);
+        memcpy(reinterpret_cast<char*>(&dst) + 2 * j, &u, 2);
+    };
+    for (int lane = 0; lane < 64; ++lane) {
+        int h = lane / 32, m = lane % 32;
+        for (int mb = 0; mb < 2; ++mb) {
+            for (int j = 0; j < 8; ++j)
+                put(pk->a1[mb][lane], j, h == 0 ? mlp[OFF_W1 + (32 * mb + m) * NL + j] : 0.0f);
+            for (int kb = 0; kb < 4; ++kb)
+                for (int j = 0; j < 8; ++j)
+                    put(pk->a2[mb][kb][lane], j, mlp[OFF_W2 + (32 * mb + m) * NH + hidden_of_slot(kb, h, j)]);
+            for (int r = 0; r < 16; ++r) {
+                pk->c1[mb][lane][r] = mlp[OFF_B1 + row_of_acc(mb, h, r)];
+                pk->c2[mb][lane][r] = mlp[OFF_B2 + row_of_acc(mb, h, r)];
+            }
+        }
+        for (int kb = 0; kb < 4; ++kb)
+            for (int j = 0; j < 8; ++j)
+                put(pk->a3[kb][lane], j, m < NO ? mlp[OFF_W3 + m * NH + hidden_of_slot(kb, h, j)] : 0.0f);
+        for (int r = 0; r < 16; ++r) {
+            int c = row_of_acc(0, h, r);
+            pk->c3[lane][r] = c < NO ? mlp[OFF_B3 + c] : 0.0f;
+        }
+    }
+}
+
+bool pow2_ratio(int big, int small)
+{
+    if (small <= 0 || big < small || big % small) return false;
+    int r = big / small;
+    return (r & (r - 1)) == 0;
+}
+
+}  // namespace
+
+struct stf_neural {
+    int32_t W, H, LW, LH;
+    int device;
+    float* lat;
+    float* mlp;
+    float* m_lat;
+    float* v_lat;
+    float* m_mlp;
+    float* v_mlp;
+    float* g_lat;
+    float* g_mlp;
+    float* partial;
+    int32_t partial_blocks;
+    int64_t step;
+    uint16_t* lat16;
+    Packed* packed;
+    bool ready;
+};
+
+namespace {
+
+int64_t nlat(const stf_neural* nt)
+{
+    return (int64_t)nt->LW * nt->LH * NL;
+}
+
+void free_neural(stf_neural* nt)
+{
+    if (!nt) return;
+    void* ptrs[] = {nt->lat, nt->mlp, nt->m_lat, nt->v_lat, nt->m_mlp, nt->v_mlp,
+                    nt->g_lat, nt->g_mlp, nt->partial, nt->lat16, nt->packed};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete nt;
+}
+
+stf_status dalloc(void** p, size_t bytes, const char* what)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return stf_fail(STF_E_OOM, "hipMalloc of %zu bytes for %s failed", bytes, what);
+    }
+    return STF_OK;
+}
+
+hipError_t fill(float* p, int64_t n, float v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+constexpr int TRAIN_BLOCKS = 1024;
+
+stf_status ensure_partial(stf_neural* nt, int32_t blocks)
+{
+    if (nt->partial && nt->partial_blocks >= blocks) return STF_OK;
+    if (nt->partial) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(nt->partial);
+        nt->partial = nullptr;
+    }
+    stf_status s = dalloc((void**)&nt->partial, (size_t)blocks * PSTRIDE * 4, "gradient partials");
+    nt->partial_blocks = s == STF_OK ? blocks : 0;
+    return s;
+}
+
+// One forward/backward pass over a batch; leaves the MLP gradient in g_mlp,
+// the latent gradient accumulated in g_lat and the loss in *loss.
+hipError_t run_fwd_bwd(stf_neural* nt, const float* target, const int32_t* pos, int32_t B, uint32_t kstep,
+                       float* loss, hipStream_t s)
+{
+    int32_t blocks = (B + TS - 1) / TS;
+    if (blocks > nt->partial_blocks) blocks = nt->partial_blocks;
+    TrainArgs a;
+    a.lat = nt->lat;
+    a.mlp = nt->mlp;
+    a.target = target;
+    a.pos = pos;
+    a.B = B;
+    a.W = nt->W;
+    a.H = nt->H;
+    a.LW = nt->LW;
+    a.LH = nt->LH;
+    a.rx = (float)nt->LW / (float)nt->W;
+    a.ry = (float)nt->LH / (float)nt->H;
+    a.kstep = kstep;
+    a.dscale = 2.0f / (8.0f * (float)B);
+    a.g_lat = nt->g_lat;
+    a.partial = nt->partial;
+    hipLaunchKernelGGL(k_ntex_train, dim3(blocks), dim3(TBLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_ntex_reduce, dim3((PSTRIDE + 255) / 256), dim3(256), 0, s, nt->partial, blocks, nt->g_mlp,
+                       loss, 1.0f / (8.0f * (float)B));
+    return hipGetLastError();
+}
+
+stf_status check_neural(const stf_neural* nt)
+{
+    if (!nt) return stf_fail(STF_E_INVALID, "neural texture is NULL");
+    return STF_OK;
+}
+
+stf_status check_dev(const void* p, const char* what, size_t align)
+{
+    if (!p) return stf_fail(STF_E_INVALID, "%s is NULL", what);
+    if ((uintptr_t)p % align) return stf_fail(STF_E_INVALID, "%s is not %zu-byte aligned", what, align);
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return stf_fail(STF_E_INVALID, "%s is not a device pointer", what);
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return stf_fail(STF_E_INVALID, "%s is not device memory", what);
+    return STF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t stf_ntex_param_count(void)
+{
+    return NPARAM;
+}
+
+stf_status stf_ntex_create(int32_t tex_w, int32_t tex_h, int32_t lat_w, int32_t lat_h, const float* latents_host,
+                           const float* mlp_host, stf_neural** out)
+{
+    stf_clear_error();
+    if (!out) return stf_fail(STF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (tex_w < 1 || tex_h < 1 || tex_w > 65536 || tex_h > 65536 || lat_w < 1 || lat_h < 1)
+        return stf_fail(STF_E_INVALID, "sizes out of range");
+    if (!pow2_ratio(tex_w, lat_w) || !pow2_ratio(tex_h, lat_h))
+        return stf_fail(STF_E_UNSUPPORTED, "texture/latent size ratios must be powers of two");
+    if ((int64_t)lat_w * lat_h * NL * 2 >= ((int64_t)1 << 31))
+        return stf_fail(STF_E_UNSUPPORTED, "latent grid too large");
+    if (!latents_host || !mlp_host) return stf_fail(STF_E_INVALID, "initial parameters are NULL");
+    stf_neural* nt = new (std::nothrow) stf_neural();
+    if (!nt) return stf_fail(STF_E_OOM, "host allocation failed");
+    nt->W = tex_w;
+    nt->H = tex_h;
+    nt->LW = lat_w;
+    nt->LH = lat_h;
+    (void)hipGetDevice(&nt->device);
+    size_t lb = (size_t)nlat(nt) * 4;
+    stf_status s = STF_OK;
+    float** bufs[] = {&nt->lat, &nt->m_lat, &nt->v_lat, &nt->g_lat};
+    for (float** b : bufs)
+        if (s == STF_OK) s = dalloc((void**)b, lb, "latents");
+    float** mbufs[] = {&nt->mlp, &nt->m_mlp, &nt->v_mlp, &nt->g_mlp};
+    for (float** b : mbufs)
+        if (s == STF_OK) s = dalloc((void**)b, NPARAM * 4, "MLP parameters");
+    if (s == STF_OK) s = dalloc((void**)&nt->lat16, (size_t)nlat(nt) * 2, "binary16 latents");
+    if (s == STF_OK) s = dalloc((void**)&nt->packed, sizeof(Packed), "packed weights");
+    if (s == STF_OK) s = ensure_partial(nt, TRAIN_BLOCKS);
+    if (s == STF_OK) {
+        hipError_t e = hipMemcpy(nt->lat, latents_host, lb, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(nt->mlp, mlp_host, NPARAM * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = fill(nt->m_lat, nlat(nt), 0.0f, 0);
+        if (e == hipSuccess) e = fill(nt->v_lat, nlat(nt), 0.0f, 0);
+        if (e == hipSuccess) e = fill(nt->g_lat, nlat(nt), 0.0f, 0);
+        if (e == hipSuccess) e = fill(nt->m_mlp, NPARAM, 0.0f, 0);
+        if (e == hipSuccess) e = fill(nt->v_mlp, NPARAM, 0.0f, 0);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) s = stf_fail(STF_E_DEVICE, "initialising the neural texture failed: %s", hipGetErrorString(e));
+    }
+    if (s != STF_OK) {
+        free_neural(nt);
+        return s;
+    }
+    *out = nt;
+    return STF_OK;
+}
+
+void stf_ntex_destroy(stf_neural* nt)
+{
+    free_neural(nt);
+}
+
+stf_status stf_ntex_train(stf_neural* nt, const float* target_dev, int32_t steps, int32_t batch, float lr_latent,
+                          float lr_mlp, uint64_t seed, float* loss_dev, void* hip_stream)
+{
+    stf_clear_error();
+    stf_status s = check_neural(nt);
+    if (s != STF_OK) return s;
+    if (steps < 0 || batch < 1) return stf_fail(STF_E_INVALID, "steps = %d, batch = %d", steps, batch);
+    if (!(lr_latent >= 0.0f) || !(lr_mlp >= 0.0f)) return stf_fail(STF_E_INVALID, "learning rates must be >= 0");
+    if (steps == 0) return STF_OK;
+    s = check_dev(target_dev, "target_dev", 16);
+    if (s == STF_OK && loss_dev) s = check_dev(loss_dev, "loss_dev", 4);
+    if (s != STF_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    uint32_t key = seed_key(seed);
+    for (int32_t k = 0; k < steps; ++k) {
+        nt->step += 1;
+        double c1 = 1.0 / (1.0 - pow(0.9, (double)nt->step)), c2 = 1.0 / (1.0 - pow(0.999, (double)nt->step));
+        hipError_t e = run_fwd_bwd(nt, target_dev, nullptr, batch, pcg(key ^ (uint32_t)nt->step),
+                                   loss_dev ? loss_dev + k : nullptr, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, nt->mlp, nt->g_mlp, nt->m_mlp,
+                               nt->v_mlp, (int64_t)NPARAM, lr_mlp, (float)c1, (float)c2);
+            hipLaunchKernelGGL(k_adam, dim3((unsigned)((nlat(nt) + 255) / 256)), dim3(256), 0, st, nt->lat,
+                               nt->g_lat, nt->m_lat, nt->v_lat, nlat(nt), lr_latent, (float)c1, (float)c2);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "training launch failed: %s", hipGetErrorString(e));
+    }
+    nt->ready = false;
+    return STF_OK;
+}
+
+stf_status stf_ntex_gradients(stf_neural* nt, const float* target_dev, const int32_t* positions_dev, int32_t batch,
+                              float* grad_latents_dev, float* grad_mlp_dev, float* loss_dev, void* hip_stream)
+{
+    stf_clear_error();
+    stf_status s = check_neural(nt);
+    if (s != STF_OK) return s;
+    if (batch < 1) return stf_fail(STF_E_INVALID, "batch = %d", batch);
+    s = check_dev(target_dev, "target_dev", 16);
+    if (s == STF_OK) s = check_dev(positions_dev, "positions_dev", 4);
+    if (s == STF_OK) s = check_dev(grad_latents_dev, "grad_latents_dev", 4);
+    if (s == STF_OK) s = check_dev(grad_mlp_dev, "grad_mlp_dev", 4);
+    if (s == STF_OK && loss_dev) s = check_dev(loss_dev, "loss_dev", 4);
+    if (s != STF_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = fill(nt->g_lat, nlat(nt), 0.0f, st);
+    if (e == hipSuccess) e = run_fwd_bwd(nt, target_dev, positions_dev, batch, 0u, loss_dev, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(grad_latents_dev, nt->g_lat, (size_t)nlat(nt) * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(grad_mlp_dev, nt->g_mlp, NPARAM * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = fill(nt->g_lat, nlat(nt), 0.0f, st);
+    if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "gradient launch failed: %s", hipGetErrorString(e));
+    return STF_OK;
+}
+
+stf_status stf_ntex_get_params(const stf_neural* nt, float* latents_host, float* mlp_host)
+{
+    stf_clear_error();
+    stf_status s = check_neural(nt);
+    if (s != STF_OK) return s;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess && latents_host) e = hipMemcpy(latents_host, nt->lat, (size_t)nlat(nt) * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && mlp_host) e = hipMemcpy(mlp_host, nt->mlp, NPARAM * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "copying parameters failed: %s", hipGetErrorString(e));
+    return STF_OK;
+}
+
+stf_status stf_ntex_prepare_inference(stf_neural* nt, void* hip_stream)
+{
+    stf_clear_error();
+    stf_status s = check_neural(nt);
+    if (s != STF_OK) return s;
+    std::vector<float> mlp(NPARAM);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(mlp.data(), nt->mlp, NPARAM * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "reading the MLP failed: %s", hipGetErrorString(e));
+    Packed* pk = new (std::nothrow) Packed;
+    if (!pk) return stf_fail(STF_E_OOM, "host allocation failed");
+    pack_weights(mlp.data(), pk);
+    e = hipMemcpy(nt->packed, pk, sizeof(Packed), hipMemcpyHostToDevice);
+    delete pk;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_to_f16, dim3((unsigned)((nlat(nt) + 255) / 256)), dim3(256), 0, st, nt->lat, nt->lat16,
+                           nlat(nt));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "preparing inference failed: %s", hipGetErrorString(e));
+    nt->ready = true;
+    return STF_OK;
+}
+
+stf_status stf_ntex_filter(const stf_neural* nt, const float* queries_dev, int64_t n, stf_filter_kind filter,
+                           stf_mode mode, uint64_t seed, float* out_dev, int32_t* out_index_dev, void* hip_stream)
+{
+    stf_clear_error();
+    stf_status s = check_neural(nt);
+    if (s != STF_OK) return s;
+    if (!nt->ready) return stf_fail(STF_E_INVALID, "call stf_ntex_prepare_inference after training");
+    if (n < 0 || n > 0x7fffffff) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
+    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE) return stf_fail(STF_E_INVALID, "unknown filter");
+    if (mode != STF_DETERMINISTIC && mode != STF_STOCHASTIC) return stf_fail(STF_E_INVALID, "unknown mode");
+    if (mode == STF_DETERMINISTIC && out_index_dev)
+        return stf_fail(STF_E_INVALID, "out_index_dev must be NULL in deterministic mode");
+    if (n == 0) return STF_OK;
+    s = check_dev(queries_dev, "queries_dev", 8);
+    if (s == STF_OK) s = check_dev(out_dev, "out_dev", 16);
+    if (s == STF_OK && out_index_dev) s = check_dev(out_index_dev, "out_index_dev", 4);
+    if (s != STF_OK) return s;
+    InferArgs a;
+    a.pk = nt->packed;
+    a.lat16 = nt->lat16;
+    a.q = queries_dev;
+    a.n = (int32_t)n;
+    a.W = nt->W;
+    a.H = nt->H;
+    a.LW = nt->LW;
+    a.LH = nt->LH;
+    a.rx = (float)nt->LW / (float)nt->W;
+    a.ry = (float)nt->LH / (float)nt->H;
+    a.key = seed_key(seed);
+    a.out = out_dev;
+    a.idx = out_index_dev;
+    int taps = mode == STF_STOCHASTIC ? 1 : (filter == STF_CUBIC_BSPLINE ? 16 : 4);
+    int64_t batches = (n * taps + 31) / 32;
+    int64_t waves = batches < 2048 ? batches : 2048;   // persistent waves: the weights load once per wave
+    dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+    hipStream_t st = (hipStream_t)hip_stream;
+    bool cubic = filter == STF_CUBIC_BSPLINE;
+    if (mode == STF_STOCHASTIC) {
+        if (cubic) hipLaunchKernelGGL((k_ntex_infer<true, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_ntex_infer<false, true>), grid, block, 0, st, a);
+    } else {
+        if (cubic) hipLaunchKernelGGL((k_ntex_infer<true, false>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_ntex_infer<false, false>), grid, block, 0, st, a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return STF_OK;
+}
+
+}  // extern "C"
