@@ -254,6 +254,82 @@ stf_status stf_ntex_filter(const stf_neural* nt, const float* queries_dev, int64
                            stf_filter_kind filter, stf_mode mode, uint64_t seed, float* out_dev,
                            int32_t* out_index_dev, void* hip_stream);
 
+/* ---------------------------------------------------------------------- */
+/* Serving                                                                 */
+/* ---------------------------------------------------------------------- */
+/* A server batches stochastic lookup requests of any size against resident
+ * textures (2D textures and 3D grids) as they arrive.  A worker thread
+ * admits requests in arrival order while fewer than max_resident are
+ * resident and their device state fits in a memory_budget_bytes arena
+ * (staged queries unless STF_SERVE_QUERIES_ON_DEVICE, results, indices),
+ * serves the next chunk (<= chunk_queries) of every resident request in each
+ * round with one launch per (texture, filter), copies finished results to the
+ * caller's buffer, and records each request's latency from its arrival to
+ * the moment its results are in place.  Requests arriving while others run
+ * join the next round.  The random draw of a query depends only on (seed,
+ * index within the request), so each request's results are bit-identical to
+ * stf_filter(tex, queries, n, filter, STF_STOCHASTIC, seed, ...) alone.
+ * Buffers passed to a request must stay valid until it has completed. */
+typedef struct stf_server stf_server;   /* opaque, library-owned */
+
+typedef struct {
+    int64_t memory_budget_bytes;   /* device arena for request state (>= 4096) */
+    int32_t max_resident;          /* requests resident at once (1..65536) */
+    int32_t chunk_queries;         /* queries of one request per round (>= 1) */
+} stf_server_config;
+
+typedef struct {
+    int64_t completed, cancelled, queries, launches, rounds;
+    int64_t peak_resident, peak_arena_bytes, pending, resident;
+    double p50_ms, p99_ms, max_ms, mean_ms;   /* latency, arrival -> results in place */
+    double lookups_per_s;                     /* completed queries / (last completion - first arrival) */
+    double span_s;
+} stf_serve_stats;
+
+#define STF_SERVE_QUERIES_ON_DEVICE 1u   /* queries are device memory (else host) */
+#define STF_SERVE_RESULTS_ON_DEVICE 2u   /* out/out_index are device memory (else host) */
+
+stf_status stf_server_create(const stf_server_config* cfg, stf_server** out);
+/* Cancels pending requests, lets resident ones finish, frees everything. */
+void stf_server_destroy(stf_server* s);
+
+/* Queue a request of n queries (2 or 3 binary32 each, per the texture).
+ * out: n x channels binary32; out_index: NULL or n x dims int32.  flags:
+ * STF_SERVE_* bits.  A request whose state can never fit the arena is
+ * rejected with STF_E_OOM.  *ticket identifies it. */
+stf_status stf_server_submit(stf_server* s, const stf_texture* tex, const float* queries, int64_t n,
+                             stf_filter_kind filter, uint64_t seed, float* out, int32_t* out_index,
+                             uint32_t flags, uint64_t* ticket);
+/* *done = 1 once results are in place (STF_E_CANCELLED / STF_E_DEVICE if
+ * the request was cancelled / failed). */
+stf_status stf_server_poll(stf_server* s, uint64_t ticket, int32_t* done);
+/* Blocks until done or timeout (STF_E_BUSY on timeout). */
+stf_status stf_server_wait(stf_server* s, uint64_t ticket, double timeout_s);
+/* A pending request is dropped at once; a resident one gets no further
+ * chunks and is retired when its launches are done. */
+stf_status stf_server_cancel(stf_server* s, uint64_t ticket);
+/* Forget a finished request (its ticket becomes unknown). */
+stf_status stf_server_release(stf_server* s, uint64_t ticket);
+stf_status stf_server_stats(stf_server* s, stf_serve_stats* st);
+stf_status stf_server_reset_stats(stf_server* s);
+
+/* Open-loop replay: submits reqs[k] at arrival_s seconds after the call
+ * starts (arrivals non-decreasing), latency counted from that scheduled
+ * time, waits for all (at most timeout_s) and releases them. */
+typedef struct {
+    const stf_texture* tex;
+    const float* queries;
+    int64_t n;
+    stf_filter_kind filter;
+    uint64_t seed;
+    float* out;
+    int32_t* out_index;
+    double arrival_s;
+} stf_serve_request;
+
+stf_status stf_server_replay(stf_server* s, const stf_serve_request* reqs, int64_t count, uint32_t flags,
+                             double timeout_s);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* stf_last_error(void);
 

@@ -323,3 +323,150 @@ def stf_ntex_filter(nt: NeuralTexture, queries, filter: int, mode: int, seed: in
     _check(_ntex_lib().stf_ntex_filter(nt.handle, _dev_ptr(queries, "queries"), queries.shape[0], filter, mode,
                                        seed & (2 ** 64 - 1), _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"),
                                        _stream(stream)))
+
+
+# ----------------------------------------------------------------------------
+# serving
+# ----------------------------------------------------------------------------
+STF_SERVE_QUERIES_ON_DEVICE, STF_SERVE_RESULTS_ON_DEVICE = 1, 2
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("memory_budget_bytes", C.c_int64), ("max_resident", C.c_int32), ("chunk_queries", C.c_int32)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("completed", "cancelled", "queries", "launches", "rounds", "peak_resident",
+                                         "peak_arena_bytes", "pending", "resident")] + \
+               [(n, C.c_double) for n in ("p50_ms", "p99_ms", "max_ms", "mean_ms", "lookups_per_s", "span_s")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class ServeRequest(C.Structure):
+    _fields_ = [("tex", C.c_void_p), ("queries", C.c_void_p), ("n", C.c_int64), ("filter", C.c_int32),
+                ("seed", C.c_uint64), ("out", C.c_void_p), ("out_index", C.c_void_p), ("arrival_s", C.c_double)]
+
+
+def _declare_server(L):
+    vp, i32, i64, u32, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+    L.stf_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(vp)]
+    L.stf_server_destroy.argtypes, L.stf_server_destroy.restype = [vp], None
+    L.stf_server_submit.argtypes = [vp, vp, vp, i64, i32, u64, vp, vp, u32, C.POINTER(u64)]
+    L.stf_server_poll.argtypes = [vp, u64, C.POINTER(i32)]
+    L.stf_server_wait.argtypes = [vp, u64, dbl]
+    L.stf_server_cancel.argtypes = [vp, u64]
+    L.stf_server_release.argtypes = [vp, u64]
+    L.stf_server_stats.argtypes = [vp, C.POINTER(ServeStats)]
+    L.stf_server_reset_stats.argtypes = [vp]
+    L.stf_server_replay.argtypes = [vp, C.POINTER(ServeRequest), i64, u32, dbl]
+    for name in ("stf_server_create", "stf_server_submit", "stf_server_poll", "stf_server_wait", "stf_server_cancel",
+                 "stf_server_release", "stf_server_stats", "stf_server_reset_stats", "stf_server_replay"):
+        getattr(L, name).restype = i32
+
+
+def _srv_lib():
+    L = lib()
+    if not getattr(L, "_srv_declared", False):
+        _declare_server(L)
+        L._srv_declared = True
+    return L
+
+
+class Server:
+    """Owning handle of an stf_server; keeps host buffers of in-flight
+    requests alive until they are released."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self._keep = {}
+
+    def destroy(self):
+        if self.handle:
+            _srv_lib().stf_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def stf_server_create(memory_budget_bytes: int, max_resident: int, chunk_queries: int) -> Server:
+    cfg = ServerConfig(memory_budget_bytes, max_resident, chunk_queries)
+    h = C.c_void_p()
+    _check(_srv_lib().stf_server_create(C.byref(cfg), C.byref(h)))
+    return Server(h.value)
+
+
+def stf_server_destroy(s: Server):
+    s.destroy()
+
+
+def _buf(x, name):
+    """(pointer, on_device) of a torch tensor or numpy array."""
+    if x is None:
+        return None, None
+    if isinstance(x, np.ndarray):
+        if not x.flags.c_contiguous:
+            raise ValueError(f"{name} must be contiguous")
+        return x.ctypes.data, False
+    return _dev_ptr(x, name), True
+
+
+def stf_server_submit(s: Server, tex: Texture, queries, filter: int, seed: int, out, out_index=None) -> int:
+    """queries/out/out_index: numpy arrays (host) or GPU tensors (device);
+    queries and results may live on different sides."""
+    qp, qdev = _buf(queries, "queries")
+    op, odev = _buf(out, "out")
+    ip, idev = _buf(out_index, "out_index")
+    if ip is not None and idev != odev:
+        raise ValueError("out and out_index must be on the same side")
+    flags = (STF_SERVE_QUERIES_ON_DEVICE if qdev else 0) | (STF_SERVE_RESULTS_ON_DEVICE if odev else 0)
+    t = C.c_uint64()
+    _check(_srv_lib().stf_server_submit(s.handle, tex.handle, qp, queries.shape[0], filter, seed & (2 ** 64 - 1), op,
+                                        ip, flags, C.byref(t)))
+    s._keep[t.value] = (queries, out, out_index)
+    return t.value
+
+
+def stf_server_poll(s: Server, ticket: int) -> bool:
+    d = C.c_int32()
+    _check(_srv_lib().stf_server_poll(s.handle, ticket, C.byref(d)))
+    return bool(d.value)
+
+
+def stf_server_wait(s: Server, ticket: int, timeout_s: float = 60.0):
+    _check(_srv_lib().stf_server_wait(s.handle, ticket, timeout_s))
+
+
+def stf_server_cancel(s: Server, ticket: int):
+    _check(_srv_lib().stf_server_cancel(s.handle, ticket))
+
+
+def stf_server_release(s: Server, ticket: int):
+    _check(_srv_lib().stf_server_release(s.handle, ticket))
+    s._keep.pop(ticket, None)
+
+
+def stf_server_stats(s: Server) -> dict:
+    st = ServeStats()
+    _check(_srv_lib().stf_server_stats(s.handle, C.byref(st)))
+    return st.as_dict()
+
+
+def stf_server_reset_stats(s: Server):
+    _check(_srv_lib().stf_server_reset_stats(s.handle))
+
+
+def stf_server_replay(s: Server, requests, flags: int, timeout_s: float = 120.0):
+    """requests: sequence of (tex, queries_ptr, n, filter, seed, out_ptr,
+    out_index_ptr_or_None, arrival_s) with raw pointers (the caller keeps the
+    buffers alive); flags: STF_SERVE_* bits."""
+    arr = (ServeRequest * len(requests))()
+    for k, (tex, qp, n, f, seed, op, ip, t) in enumerate(requests):
+        arr[k] = ServeRequest(tex.handle, qp, n, f, seed & (2 ** 64 - 1), op, ip, t)
+    _check(_srv_lib().stf_server_replay(s.handle, arr, len(requests), flags, timeout_s))

@@ -17,7 +17,7 @@ ARCH = os.environ.get("STF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
+         "-Wall", "-Wno-unused-function", "-Wno-bitwise-instead-of-logical", "-I", os.path.join(HERE, "..", "include")]
 
 
 def sources():

@@ -39,12 +39,12 @@ __device__ __forceinline__ void load_rgba(const TexLevel& L, int x, int y, float
     }
 }
 
+// Query i of a batch of n, drawn with id qid0 + i.
 template <int FMT, int C, bool CUBIC>
-__global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(TexLevel L, const float* __restrict__ q, int32_t n,
-                                                            uint32_t key, float* __restrict__ out,
-                                                            int32_t* __restrict__ idx)
+__device__ __forceinline__ void tex2d_stochastic_one(const TexLevel& L, const float* __restrict__ q, int32_t n,
+                                                     int32_t i, uint32_t key, uint32_t qid0, float* __restrict__ out,
+                                                     int32_t* __restrict__ idx)
 {
-    int32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     float2 uv = reinterpret_cast<const float2*>(q)[i];
     float x = uv.x * (float)L.w - 0.5f;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(TexLevel L, const fl
     float v[C];
     int sx = BAD_INDEX, sy = BAD_INDEX;
     if (ok) {
-        uint32_t b = pcg(key ^ (uint32_t)i);
+        uint32_t b = pcg(key ^ (qid0 + (uint32_t)i));
         float ux = axis_uniform(b, 0), uy = axis_uniform(b, 1);
         if constexpr (CUBIC) {
             sx = cx + choose_cubic(tx, ux);
@@ -77,6 +77,30 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(TexLevel L, const fl
         idx[2 * (int64_t)i] = sx;
         idx[2 * (int64_t)i + 1] = sy;
     }
+}
+
+template <int FMT, int C, bool CUBIC>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(TexLevel L, const float* __restrict__ q, int32_t n,
+                                                            uint32_t key, float* __restrict__ out,
+                                                            int32_t* __restrict__ idx)
+{
+    tex2d_stochastic_one<FMT, C, CUBIC>(L, q, n, blockIdx.x * BLOCK + threadIdx.x, key, 0u, out, idx);
+}
+
+// Serving: block b serves chunk c with start[c] <= b < start[c + 1].
+template <int FMT, int C, bool CUBIC>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_serve(TexLevel L, const ServeChunk* __restrict__ chunks,
+                                                       int32_t nchunks)
+{
+    int lo = 0, hi = nchunks - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (chunks[mid].block0 <= (int32_t)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const ServeChunk c = chunks[lo];
+    tex2d_stochastic_one<FMT, C, CUBIC>(L, c.q, c.count, ((int32_t)blockIdx.x - c.block0) * BLOCK + threadIdx.x, c.key,
+                                        c.qid0, c.out, c.idx);
 }
 
 template <int FMT, int C, bool CUBIC>
@@ -202,6 +226,31 @@ hipError_t launch2d_fc(const TexLevel& L, const float* q, int32_t n, int filter,
 }
 
 template <int FMT, int C>
+hipError_t serve2d_fc(const TexLevel& L, int filter, const ServeChunk* chunks, int32_t nchunks, int32_t nblocks,
+                      hipStream_t s)
+{
+    if (filter == STF_CUBIC_BSPLINE)
+        hipLaunchKernelGGL((k_tex2d_serve<FMT, C, true>), dim3(nblocks), dim3(BLOCK), 0, s, L, chunks, nchunks);
+    else
+        hipLaunchKernelGGL((k_tex2d_serve<FMT, C, false>), dim3(nblocks), dim3(BLOCK), 0, s, L, chunks, nchunks);
+    return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t serve2d_f(const stf_texture* t, int filter, const ServeChunk* chunks, int32_t nchunks, int32_t nblocks,
+                     hipStream_t s)
+{
+    const TexLevel& L = t->level[0];
+    switch (t->channels) {
+    case 1: return serve2d_fc<FMT, 1>(L, filter, chunks, nchunks, nblocks, s);
+    case 2: return serve2d_fc<FMT, 2>(L, filter, chunks, nchunks, nblocks, s);
+    case 3: return serve2d_fc<FMT, 3>(L, filter, chunks, nchunks, nblocks, s);
+    case 4: return serve2d_fc<FMT, 4>(L, filter, chunks, nchunks, nblocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int FMT, int C>
 hipError_t moments2d_fc(const TexLevel& L, const float* q, int32_t n, int filter, uint64_t seed_base,
                         int32_t n_seeds, double* sum, double* sumsq, hipStream_t stream)
 {
@@ -267,6 +316,24 @@ hipError_t launch_moments2d(const stf_texture* t, const float* q, int32_t n, int
     case BF16: return moments2d_f<BF16>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
     case FP8_E4M3: return moments2d_f<FP8_E4M3>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
     case U8: return moments2d_f<U8>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+int32_t serve2d_queries_per_block()
+{
+    return BLOCK;
+}
+
+hipError_t launch_serve2d(const stf_texture* t, int filter, const ServeChunk* chunks, int32_t nchunks, int32_t nblocks,
+                          hipStream_t s)
+{
+    switch (t->fmt) {
+    case F32: return serve2d_f<F32>(t, filter, chunks, nchunks, nblocks, s);
+    case F16: return serve2d_f<F16>(t, filter, chunks, nchunks, nblocks, s);
+    case BF16: return serve2d_f<BF16>(t, filter, chunks, nchunks, nblocks, s);
+    case FP8_E4M3: return serve2d_f<FP8_E4M3>(t, filter, chunks, nchunks, nblocks, s);
+    case U8: return serve2d_f<U8>(t, filter, chunks, nchunks, nblocks, s);
     }
     return hipErrorInvalidValue;
 }

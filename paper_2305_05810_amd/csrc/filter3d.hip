@@ -72,12 +72,13 @@ __device__ __forceinline__ int32_t table_load(const int32_t* __restrict__ t, uin
     return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(t) + (size_t)(elem * 4u));
 }
 
+// One block's share: queries first + k*BLOCK (k < Q) of a batch of n, whose
+// random draw uses the id qid0 + index.
 template <int FMT, bool CUBIC, int Q>
-__global__ __launch_bounds__(BLOCK) void k_grid_stochastic(GridView g, const float* __restrict__ q, int32_t n,
-                                                           uint32_t key, float* __restrict__ out,
-                                                           int32_t* __restrict__ idx)
+__device__ __forceinline__ void grid_stochastic_block(const GridView& g, const float* __restrict__ q, int32_t n,
+                                                      int32_t first, uint32_t key, uint32_t qid0,
+                                                      float* __restrict__ out, int32_t* __restrict__ idx)
 {
-    const int32_t first = blockIdx.x * (BLOCK * Q) + threadIdx.x;
     float p[Q][3];
     bool live[Q];
 #pragma unroll
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(BLOCK) void k_grid_stochastic(GridView g, const flo
         int c0 = 0, c1 = 0, c2 = 0;
         float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f;
         fin[k] = cell_of(p[k][0], c0, t0) & cell_of(p[k][1], c1, t1) & cell_of(p[k][2], c2, t2);
-        uint32_t h0 = pcg(key ^ (uint32_t)i), h1, h2;
+        uint32_t h0 = pcg(key ^ (qid0 + (uint32_t)i)), h1, h2;
         pcg_next2(h0, h1, h2);
         float m0 = hash_m(h0), m1 = hash_m(h1), m2 = hash_m(h2);
         if constexpr (CUBIC) {
@@ -159,6 +160,30 @@ __global__ __launch_bounds__(BLOCK) void k_grid_stochastic(GridView g, const flo
             idx[3 * (int64_t)i + 2] = fin[k] ? vz[k] : BAD_INDEX;
         }
     }
+}
+
+template <int FMT, bool CUBIC, int Q>
+__global__ __launch_bounds__(BLOCK) void k_grid_stochastic(GridView g, const float* __restrict__ q, int32_t n,
+                                                           uint32_t key, float* __restrict__ out,
+                                                           int32_t* __restrict__ idx)
+{
+    grid_stochastic_block<FMT, CUBIC, Q>(g, q, n, blockIdx.x * (BLOCK * Q) + threadIdx.x, key, 0u, out, idx);
+}
+
+// Serving: one launch over many requests' chunks (same grid and filter).
+// Block b serves chunk c with start[c] <= b < start[c + 1].
+template <int FMT, bool CUBIC, int Q>
+__global__ __launch_bounds__(BLOCK) void k_grid_serve(GridView g, const ServeChunk* __restrict__ chunks, int32_t nchunks)
+{
+    int lo = 0, hi = nchunks - 1;
+    while (lo < hi) {   // last chunk whose first block is <= blockIdx.x
+        int mid = (lo + hi + 1) / 2;
+        if (chunks[mid].block0 <= (int32_t)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const ServeChunk c = chunks[lo];
+    grid_stochastic_block<FMT, CUBIC, Q>(g, c.q, c.count, ((int32_t)blockIdx.x - c.block0) * (BLOCK * Q) + threadIdx.x,
+                                         c.key, c.qid0, c.out, c.idx);
 }
 
 // ---------------------------------------------------------------------------
@@ -322,6 +347,17 @@ hipError_t moments3d_fmt(const GridView& g, const float* q, int32_t n, int filte
     return hipGetLastError();
 }
 
+template <int FMT>
+hipError_t serve3d_fmt(const GridView& g, int filter, const ServeChunk* chunks, int32_t nchunks, int32_t nblocks,
+                       hipStream_t s)
+{
+    if (filter == STF_CUBIC_BSPLINE)
+        hipLaunchKernelGGL((k_grid_serve<FMT, true, STOCH_Q>), dim3(nblocks), dim3(BLOCK), 0, s, g, chunks, nchunks);
+    else
+        hipLaunchKernelGGL((k_grid_serve<FMT, false, STOCH_Q>), dim3(nblocks), dim3(BLOCK), 0, s, g, chunks, nchunks);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_filter3d(const stf_texture* tex, const float* q, int32_t n, int filter, int mode, uint32_t key,
@@ -334,6 +370,25 @@ hipError_t launch_filter3d(const stf_texture* tex, const float* q, int32_t n, in
     case BF16: return launch3d_fmt<BF16>(g, q, n, filter, mode, key, out, idx, stream);
     case FP8_E4M3: return launch3d_fmt<FP8_E4M3>(g, q, n, filter, mode, key, out, idx, stream);
     case U8: return launch3d_fmt<U8>(g, q, n, filter, mode, key, out, idx, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+int32_t serve3d_queries_per_block()
+{
+    return BLOCK * STOCH_Q;
+}
+
+hipError_t launch_serve3d(const stf_texture* tex, int filter, const ServeChunk* chunks, int32_t nchunks,
+                          int32_t nblocks, hipStream_t s)
+{
+    const GridView& g = tex->grid;
+    switch (tex->fmt) {
+    case F32: return serve3d_fmt<F32>(g, filter, chunks, nchunks, nblocks, s);
+    case F16: return serve3d_fmt<F16>(g, filter, chunks, nchunks, nblocks, s);
+    case BF16: return serve3d_fmt<BF16>(g, filter, chunks, nchunks, nblocks, s);
+    case FP8_E4M3: return serve3d_fmt<FP8_E4M3>(g, filter, chunks, nchunks, nblocks, s);
+    case U8: return serve3d_fmt<U8>(g, filter, chunks, nchunks, nblocks, s);
     }
     return hipErrorInvalidValue;
 }

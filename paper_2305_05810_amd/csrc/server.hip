@@ -1,0 +1,607 @@
+// server.hip -- a serving loop for stochastic lookups: continuous batching of
+// uneven requests against resident textures, memory-based admission, and
+// per-request latency.
+//
+// A worker thread owns the device work.  Each round it
+//   1. admits pending requests in arrival order while a resident slot and
+//      room in the device arena (queries staged from host memory, results)
+//      are free;
+//   2. takes the next chunk (at most `chunk_queries`) of every resident
+//      request, groups the chunks by (texture, filter) and serves each group
+//      with one kernel launch over a chunk table;
+//   3. copies the results of requests whose last chunk was launched to the
+//      caller's buffer and records a completion event;
+//   4. retires requests whose completion event has fired: latency = fire time
+//      observed - arrival time, arena space freed.
+// Up to two rounds are in flight on the stream, so admission and the next
+// launch overlap the device work.  Requests arriving while others run join
+// the next round.  A query's random draw depends only on (request seed,
+// index within the request), so every result equals what stf_filter returns
+// for the same request alone.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "device_common.h"
+#include "stf_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double now_s()
+{
+    return std::chrono::duration<double>(Clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, size) in 256-byte units, coalescing on free.
+class Arena {
+public:
+    void init(size_t size)
+    {
+        free_.clear();
+        free_[0] = size;
+        used_ = peak_ = 0;
+    }
+    bool alloc(size_t bytes, size_t* off)
+    {
+        bytes = (bytes + 255) & ~(size_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                size_t rest = it->second - bytes, start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = (bytes + 255) & ~(size_t)255;
+        used_ -= bytes;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + bytes == next->first) {
+            bytes += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += bytes;
+                return;
+            }
+        }
+        free_[off] = bytes;
+    }
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+    void reset_peak() { peak_ = used_; }
+
+private:
+    std::map<size_t, size_t> free_;
+    size_t used_ = 0, peak_ = 0;
+};
+
+enum ReqState { PENDING, RESIDENT, FINISHING, DONE, CANCELLED, FAILED };
+
+struct Request {
+    uint64_t ticket;
+    const stf_texture* tex;
+    const float* q_user;
+    float* out_user;
+    int32_t* idx_user;
+    int64_t n;
+    int filter;
+    uint32_t key;
+    uint32_t flags;
+    double t_arrival;
+    int dims, channels;
+    size_t off = 0, bytes = 0;
+    const float* q_dev = nullptr;
+    float* out_dev = nullptr;
+    int32_t* idx_dev = nullptr;
+    int64_t next = 0;
+    bool cancel = false;
+    int state = PENDING;
+    hipEvent_t done_ev = nullptr;
+    int64_t round = -1;       // round whose launch carries the request's last chunk
+    int64_t last_round = -1;  // latest round that launched any chunk of the request
+};
+
+constexpr int RING = 4;
+
+}  // namespace
+
+struct stf_server {
+    stf_server_config cfg;
+    int device;
+    hipStream_t stream;
+    char* arena_dev = nullptr;
+    Arena arena;
+    ServeChunk* desc_host = nullptr;   // RING * max_resident, pinned
+    ServeChunk* desc_dev = nullptr;
+    hipEvent_t round_ev[RING];
+    int64_t round = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> pending;
+    std::vector<Request*> resident;
+    std::unordered_map<uint64_t, Request*> all;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+    // statistics since the last reset
+    std::vector<double> lat_ms;
+    int64_t completed = 0, cancelled = 0, queries = 0, launches = 0, peak_resident = 0;
+    double t_first = 0.0, t_last = 0.0;
+    int64_t n_rounds = 0;
+    std::string error;
+};
+
+namespace {
+
+void record_failure(stf_server* s, const char* what, hipError_t e)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    s->error = buf;
+}
+
+void retire(stf_server* s, Request* r, int state, double t)
+{
+    // caller holds s->mu
+    if (r->bytes) s->arena.release(r->off, r->bytes);
+    r->bytes = 0;
+    r->state = state;
+    if (state == DONE) {
+        s->completed += 1;
+        s->queries += r->n;
+        s->lat_ms.push_back((t - r->t_arrival) * 1e3);
+        if (s->t_first == 0.0 || r->t_arrival < s->t_first) s->t_first = r->t_arrival;
+        s->t_last = std::max(s->t_last, t);
+    } else if (state == CANCELLED) {
+        s->cancelled += 1;
+    }
+    s->cv_done.notify_all();
+}
+
+void worker_main(stf_server* s)
+{
+    (void)hipSetDevice(s->device);
+    const int qpb3 = serve3d_queries_per_block(), qpb2 = serve2d_queries_per_block();
+    std::vector<Request*> finishing;
+    for (;;) {
+        std::vector<Request*> admitted;
+        std::vector<Request*> round_reqs;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            // retire cancelled residents once no launch of theirs is in flight
+            // (the stream is in order: a later round's event implies earlier ones)
+            for (auto it = s->resident.begin(); it != s->resident.end();) {
+                Request* r = *it;
+                bool quiet = r->last_round < 0 || s->round - r->last_round >= RING ||
+                             hipEventQuery(s->round_ev[r->last_round % RING]) == hipSuccess;
+                if (r->cancel && r->state == RESIDENT && quiet) {
+                    retire(s, r, CANCELLED, now_s());
+                    it = s->resident.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            while (!s->pending.empty() && (int)s->resident.size() < s->cfg.max_resident) {
+                Request* r = s->pending.front();
+                size_t need = (size_t)r->n * ((r->flags & STF_SERVE_QUERIES_ON_DEVICE) ? 0 : 4 * r->dims) +
+                              (size_t)r->n * 4 * r->channels + 256 + (r->idx_user ? (size_t)r->n * 4 * r->dims + 256 : 0);
+                size_t off;
+                if (!s->arena.alloc(need, &off)) break;
+                s->pending.pop_front();
+                r->off = off;
+                r->bytes = need;
+                char* base = s->arena_dev + off;
+                size_t o = 0;
+                if (r->flags & STF_SERVE_QUERIES_ON_DEVICE) {
+                    r->q_dev = r->q_user;
+                } else {
+                    r->q_dev = (const float*)base;
+                    o += ((size_t)r->n * 4 * r->dims + 255) & ~(size_t)255;
+                }
+                r->out_dev = (float*)(base + o);
+                o += ((size_t)r->n * 4 * r->channels + 255) & ~(size_t)255;
+                r->idx_dev = r->idx_user ? (int32_t*)(base + o) : nullptr;
+                r->state = RESIDENT;
+                s->resident.push_back(r);
+                admitted.push_back(r);
+            }
+            s->peak_resident = std::max<int64_t>(s->peak_resident, (int64_t)s->resident.size());
+            for (Request* r : s->resident)
+                if (r->state == RESIDENT && !r->cancel && r->next < r->n) round_reqs.push_back(r);
+            if (round_reqs.empty() && finishing.empty() && admitted.empty()) {
+                if (s->stop && s->pending.empty()) break;
+                s->cv_work.wait_for(lk, std::chrono::microseconds(200));
+                continue;
+            }
+        }
+        hipError_t e = hipSuccess;
+        for (Request* r : admitted)
+            if (!(r->flags & STF_SERVE_QUERIES_ON_DEVICE) && e == hipSuccess)
+                e = hipMemcpyAsync((void*)r->q_dev, r->q_user, (size_t)r->n * 4 * r->dims, hipMemcpyHostToDevice,
+                                   s->stream);
+        if (!round_reqs.empty() && e == hipSuccess) {
+            // at most two rounds in flight; the descriptor slot of round - RING is free
+            int slot = (int)(s->round % RING);
+            if (s->round >= 2) e = hipEventSynchronize(s->round_ev[(s->round - 2) % RING]);
+            if (s->round >= RING && e == hipSuccess) e = hipEventSynchronize(s->round_ev[slot]);
+            ServeChunk* hd = s->desc_host + (size_t)slot * s->cfg.max_resident;
+            ServeChunk* dd = s->desc_dev + (size_t)slot * s->cfg.max_resident;
+            // group by (texture, filter); each group is contiguous in the table
+            std::stable_sort(round_reqs.begin(), round_reqs.end(), [](const Request* a, const Request* b) {
+                if (a->tex != b->tex) return a->tex < b->tex;
+                return a->filter < b->filter;
+            });
+            struct Group {
+                const stf_texture* tex;
+                int filter, first, count, blocks;
+            };
+            std::vector<Group> groups;
+            for (size_t k = 0; k < round_reqs.size(); ++k) {
+                Request* r = round_reqs[k];
+                bool is3d = r->tex->kind == STF_KIND_GRID3D;
+                int qpb = is3d ? qpb3 : qpb2;
+                if (groups.empty() || groups.back().tex != r->tex || groups.back().filter != r->filter)
+                    groups.push_back({r->tex, r->filter, (int)k, 0, 0});
+                Group& g = groups.back();
+                int64_t cnt = std::min<int64_t>(s->cfg.chunk_queries, r->n - r->next);
+                ServeChunk c;
+                c.q = r->q_dev + r->next * r->dims;
+                c.out = r->out_dev + r->next * r->channels;
+                c.idx = r->idx_dev ? r->idx_dev + r->next * r->dims : nullptr;
+                c.count = (int32_t)cnt;
+                c.qid0 = (uint32_t)r->next;
+                c.key = r->key;
+                c.block0 = g.blocks;
+                hd[k] = c;
+                g.count += 1;
+                g.blocks += (int)((cnt + qpb - 1) / qpb);
+                r->next += cnt;
+                r->last_round = s->round;
+                if (r->next == r->n) r->round = s->round;
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(dd, hd, round_reqs.size() * sizeof(ServeChunk), hipMemcpyHostToDevice, s->stream);
+            for (const Group& g : groups) {
+                if (e != hipSuccess) break;
+                e = g.tex->kind == STF_KIND_GRID3D
+                        ? launch_serve3d(g.tex, g.filter, dd + g.first, g.count, g.blocks, s->stream)
+                        : launch_serve2d(g.tex, g.filter, dd + g.first, g.count, g.blocks, s->stream);
+                s->launches += 1;
+            }
+            // results of requests finished in this round go to the caller's buffers
+            for (Request* r : round_reqs) {
+                if (r->next != r->n || e != hipSuccess) continue;
+                hipMemcpyKind kind = (r->flags & STF_SERVE_RESULTS_ON_DEVICE) ? hipMemcpyDeviceToDevice
+                                                                              : hipMemcpyDeviceToHost;
+                e = hipMemcpyAsync(r->out_user, r->out_dev, (size_t)r->n * 4 * r->channels, kind, s->stream);
+                if (e == hipSuccess && r->idx_user)
+                    e = hipMemcpyAsync(r->idx_user, r->idx_dev, (size_t)r->n * 4 * r->dims, kind, s->stream);
+                if (e == hipSuccess) e = hipEventRecord(r->done_ev, s->stream);
+                r->state = FINISHING;
+                finishing.push_back(r);
+            }
+            if (e == hipSuccess) e = hipEventRecord(s->round_ev[slot], s->stream);
+            s->round += 1;
+            s->n_rounds += 1;
+        }
+        if (e != hipSuccess) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            record_failure(s, "serving round failed", e);
+            for (Request* r : s->resident) retire(s, r, FAILED, now_s());
+            s->resident.clear();
+            finishing.clear();
+            continue;
+        }
+        // retire finished requests; block on the oldest one only when there is
+        // nothing else to do
+        bool idle = round_reqs.empty() && admitted.empty();
+        for (auto it = finishing.begin(); it != finishing.end();) {
+            Request* r = *it;
+            hipError_t q = idle && it == finishing.begin() ? hipEventSynchronize(r->done_ev) : hipEventQuery(r->done_ev);
+            if (q == hipErrorNotReady) {
+                ++it;
+                continue;
+            }
+            double t = now_s();
+            std::lock_guard<std::mutex> lk(s->mu);
+            auto pos = std::find(s->resident.begin(), s->resident.end(), r);
+            if (pos != s->resident.end()) s->resident.erase(pos);
+            retire(s, r, q == hipSuccess ? DONE : FAILED, t);
+            it = finishing.erase(it);
+        }
+    }
+}
+
+Request* find_req(stf_server* s, uint64_t ticket)
+{
+    auto it = s->all.find(ticket);
+    return it == s->all.end() ? nullptr : it->second;
+}
+
+stf_status submit_locked(stf_server* s, const stf_texture* tex, const float* queries, int64_t n,
+                         stf_filter_kind filter, uint64_t seed, float* out, int32_t* out_index, uint32_t flags,
+                         double t_arrival, uint64_t* ticket)
+{
+    Request* r = new (std::nothrow) Request();
+    if (!r) return stf_fail(STF_E_OOM, "host allocation failed");
+    if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) {
+        delete r;
+        return stf_fail(STF_E_DEVICE, "hipEventCreate failed");
+    }
+    r->ticket = s->next_ticket++;
+    r->tex = tex;
+    r->q_user = queries;
+    r->out_user = out;
+    r->idx_user = out_index;
+    r->n = n;
+    r->filter = filter;
+    r->key = stf::seed_key(seed);
+    r->flags = flags;
+    r->t_arrival = t_arrival;
+    r->dims = tex->kind == STF_KIND_GRID3D ? 3 : 2;
+    r->channels = tex->channels;
+    s->all[r->ticket] = r;
+    s->pending.push_back(r);
+    *ticket = r->ticket;
+    s->cv_work.notify_one();
+    return STF_OK;
+}
+
+stf_status validate_request(stf_server* s, const stf_texture* tex, const float* queries, int64_t n,
+                            stf_filter_kind filter, float* out, uint32_t flags)
+{
+    if (!tex || (tex->kind != STF_KIND_GRID3D && tex->kind != STF_KIND_TEX2D))
+        return stf_fail(STF_E_INVALID, "requests need a 3D grid or a 2D texture");
+    if (n < 1 || n > 0x7fffffff) return stf_fail(STF_E_INVALID, "n = %lld out of range (1..2^31-1)", (long long)n);
+    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE) return stf_fail(STF_E_INVALID, "unknown filter");
+    if (!queries || !out) return stf_fail(STF_E_INVALID, "queries and out are required");
+    if (flags & ~(uint32_t)(STF_SERVE_QUERIES_ON_DEVICE | STF_SERVE_RESULTS_ON_DEVICE))
+        return stf_fail(STF_E_INVALID, "unknown flags 0x%x", flags);
+    int dims = tex->kind == STF_KIND_GRID3D ? 3 : 2;
+    size_t need = (size_t)n * ((flags & STF_SERVE_QUERIES_ON_DEVICE) ? 0 : 4 * dims) + (size_t)n * 4 * tex->channels +
+                  (size_t)n * 4 * dims + 1024;
+    if (need > (size_t)s->cfg.memory_budget_bytes)
+        return stf_fail(STF_E_OOM, "request of %lld queries needs %zu bytes, more than the budget", (long long)n, need);
+    if ((uintptr_t)queries % ((flags & STF_SERVE_QUERIES_ON_DEVICE) && dims == 2 ? 8 : 4))
+        return stf_fail(STF_E_INVALID, "queries are misaligned");
+    return STF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stf_status stf_server_create(const stf_server_config* cfg, stf_server** out)
+{
+    stf_clear_error();
+    if (!cfg || !out) return stf_fail(STF_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (cfg->memory_budget_bytes < 4096 || cfg->max_resident < 1 || cfg->max_resident > 65536 ||
+        cfg->chunk_queries < 1)
+        return stf_fail(STF_E_INVALID, "bad server configuration");
+    stf_server* s = new (std::nothrow) stf_server();
+    if (!s) return stf_fail(STF_E_OOM, "host allocation failed");
+    s->cfg = *cfg;
+    (void)hipGetDevice(&s->device);
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->arena_dev, (size_t)cfg->memory_budget_bytes);
+    size_t dbytes = (size_t)RING * cfg->max_resident * sizeof(ServeChunk);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->desc_host, dbytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->desc_dev, dbytes);
+    for (int k = 0; k < RING && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->round_ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (s->arena_dev) (void)hipFree(s->arena_dev);
+        if (s->desc_host) (void)hipHostFree(s->desc_host);
+        if (s->desc_dev) (void)hipFree(s->desc_dev);
+        if (s->stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        return stf_fail(STF_E_OOM, "allocating the server's device state failed: %s", hipGetErrorString(e));
+    }
+    s->arena.init((size_t)cfg->memory_budget_bytes);
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return STF_OK;
+}
+
+void stf_server_destroy(stf_server* s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (Request* r : s->pending) {
+            r->state = CANCELLED;
+            s->cancelled += 1;
+        }
+        s->pending.clear();
+        for (Request* r : s->resident) r->cancel = true;
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    s->worker.join();
+    (void)hipStreamSynchronize(s->stream);
+    for (auto& kv : s->all) {
+        (void)hipEventDestroy(kv.second->done_ev);
+        delete kv.second;
+    }
+    for (int k = 0; k < RING; ++k) (void)hipEventDestroy(s->round_ev[k]);
+    (void)hipFree(s->arena_dev);
+    (void)hipHostFree(s->desc_host);
+    (void)hipFree(s->desc_dev);
+    (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+stf_status stf_server_submit(stf_server* s, const stf_texture* tex, const float* queries, int64_t n,
+                             stf_filter_kind filter, uint64_t seed, float* out, int32_t* out_index, uint32_t flags,
+                             uint64_t* ticket)
+{
+    stf_clear_error();
+    if (!s || !ticket) return stf_fail(STF_E_INVALID, "NULL argument");
+    stf_status st = validate_request(s, tex, queries, n, filter, out, flags);
+    if (st != STF_OK) return st;
+    std::lock_guard<std::mutex> lk(s->mu);
+    return submit_locked(s, tex, queries, n, filter, seed, out, out_index, flags, now_s(), ticket);
+}
+
+stf_status stf_server_poll(stf_server* s, uint64_t ticket, int32_t* done)
+{
+    stf_clear_error();
+    if (!s || !done) return stf_fail(STF_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Request* r = find_req(s, ticket);
+    if (!r) return stf_fail(STF_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    *done = r->state == DONE || r->state == CANCELLED || r->state == FAILED;
+    if (r->state == CANCELLED) return stf_fail(STF_E_CANCELLED, "request %llu was cancelled", (unsigned long long)ticket);
+    if (r->state == FAILED) return stf_fail(STF_E_DEVICE, "request failed: %s", s->error.c_str());
+    return STF_OK;
+}
+
+stf_status stf_server_wait(stf_server* s, uint64_t ticket, double timeout_s)
+{
+    stf_clear_error();
+    if (!s) return stf_fail(STF_E_INVALID, "NULL argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    Request* r = find_req(s, ticket);
+    if (!r) return stf_fail(STF_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    auto deadline = Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(timeout_s));
+    bool ok = s->cv_done.wait_until(lk, deadline, [&] { return r->state >= DONE; });
+    if (!ok) return stf_fail(STF_E_BUSY, "request %llu not finished after %.3f s", (unsigned long long)ticket, timeout_s);
+    if (r->state == CANCELLED) return stf_fail(STF_E_CANCELLED, "request %llu was cancelled", (unsigned long long)ticket);
+    if (r->state == FAILED) return stf_fail(STF_E_DEVICE, "request failed: %s", s->error.c_str());
+    return STF_OK;
+}
+
+stf_status stf_server_cancel(stf_server* s, uint64_t ticket)
+{
+    stf_clear_error();
+    if (!s) return stf_fail(STF_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Request* r = find_req(s, ticket);
+    if (!r) return stf_fail(STF_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    if (r->state == PENDING) {
+        s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
+        retire(s, r, CANCELLED, now_s());
+    } else if (r->state == RESIDENT) {
+        r->cancel = true;   // no further chunks; retired once its launches are done
+        s->cv_work.notify_one();
+    }
+    return STF_OK;
+}
+
+stf_status stf_server_release(stf_server* s, uint64_t ticket)
+{
+    stf_clear_error();
+    if (!s) return stf_fail(STF_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Request* r = find_req(s, ticket);
+    if (!r) return stf_fail(STF_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    if (r->state < DONE) return stf_fail(STF_E_BUSY, "request %llu is still in flight", (unsigned long long)ticket);
+    s->all.erase(ticket);
+    (void)hipEventDestroy(r->done_ev);
+    delete r;
+    return STF_OK;
+}
+
+stf_status stf_server_stats(stf_server* s, stf_serve_stats* st)
+{
+    stf_clear_error();
+    if (!s || !st) return stf_fail(STF_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    memset(st, 0, sizeof(*st));
+    st->completed = s->completed;
+    st->cancelled = s->cancelled;
+    st->queries = s->queries;
+    st->launches = s->launches;
+    st->rounds = s->n_rounds;
+    st->peak_resident = s->peak_resident;
+    st->peak_arena_bytes = (int64_t)s->arena.peak();
+    st->pending = (int64_t)s->pending.size();
+    st->resident = (int64_t)s->resident.size();
+    if (!s->lat_ms.empty()) {
+        std::vector<double> v = s->lat_ms;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) { return v[std::min(v.size() - 1, (size_t)(p * (v.size() - 1) + 0.5))]; };
+        double sum = 0.0;
+        for (double x : v) sum += x;
+        st->p50_ms = pct(0.50);
+        st->p99_ms = pct(0.99);
+        st->max_ms = v.back();
+        st->mean_ms = sum / v.size();
+        double span = s->t_last - s->t_first;
+        st->lookups_per_s = span > 0 ? s->queries / span : 0.0;
+        st->span_s = span;
+    }
+    return STF_OK;
+}
+
+stf_status stf_server_reset_stats(stf_server* s)
+{
+    stf_clear_error();
+    if (!s) return stf_fail(STF_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->lat_ms.clear();
+    s->completed = s->cancelled = s->queries = s->launches = s->n_rounds = 0;
+    s->peak_resident = (int64_t)s->resident.size();
+    s->t_first = s->t_last = 0.0;
+    s->arena.reset_peak();
+    return STF_OK;
+}
+
+stf_status stf_server_replay(stf_server* s, const stf_serve_request* reqs, int64_t count, uint32_t flags,
+                             double timeout_s)
+{
+    stf_clear_error();
+    if (!s || (!reqs && count)) return stf_fail(STF_E_INVALID, "NULL argument");
+    for (int64_t k = 0; k < count; ++k) {
+        stf_status st = validate_request(s, reqs[k].tex, reqs[k].queries, reqs[k].n, reqs[k].filter, reqs[k].out, flags);
+        if (st != STF_OK) return st;
+        if (k && reqs[k].arrival_s < reqs[k - 1].arrival_s) return stf_fail(STF_E_INVALID, "arrivals must not decrease");
+    }
+    std::vector<uint64_t> tickets((size_t)count);
+    double t0 = now_s();
+    for (int64_t k = 0; k < count; ++k) {
+        double due = t0 + reqs[k].arrival_s;
+        for (;;) {   // open loop: submit at the scheduled time; latency counts from it
+            double dt = due - now_s();
+            if (dt <= 0) break;
+            if (dt > 200e-6) std::this_thread::sleep_for(std::chrono::duration<double>(dt - 100e-6));
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        stf_status st = submit_locked(s, reqs[k].tex, reqs[k].queries, reqs[k].n, reqs[k].filter, reqs[k].seed,
+                                      reqs[k].out, reqs[k].out_index, flags, due, &tickets[k]);
+        if (st != STF_OK) return st;
+    }
+    double deadline = now_s() + timeout_s;
+    stf_status result = STF_OK;
+    for (int64_t k = 0; k < count; ++k) {
+        stf_status st = stf_server_wait(s, tickets[k], std::max(0.0, deadline - now_s()));
+        if (st != STF_OK && result == STF_OK) result = st;
+    }
+    for (int64_t k = 0; k < count; ++k) (void)stf_server_release(s, tickets[k]);
+    if (result != STF_OK) return stf_fail(result, "replay: not every request completed");
+    return STF_OK;
+}
+
+}  // extern "C"

@@ -47,6 +47,19 @@ struct stf_texture {
     void* grid_alloc[3];
 };
 
+// One serving chunk: queries [0, count) of a request's slice, drawn with ids
+// qid0 + index under the request's key, served by blocks [block0, next
+// chunk's block0).
+struct ServeChunk {
+    const float* q;
+    float* out;
+    int32_t* idx;
+    int32_t count;
+    uint32_t qid0;
+    uint32_t key;
+    int32_t block0;
+};
+
 // Error reporting (thread-local message).
 stf_status stf_fail(stf_status code, const char* fmt, ...);
 void stf_clear_error();
@@ -64,3 +77,10 @@ hipError_t launch_moments3d(const stf_texture* tex, const float* q, int32_t n, i
                             hipStream_t stream);
 hipError_t launch_shade(const stf_texture* mat, const float* q, int32_t n, int filter, int mode,
                         uint32_t skey, float* out, int32_t* idx, hipStream_t stream);
+
+int32_t serve3d_queries_per_block();
+int32_t serve2d_queries_per_block();
+hipError_t launch_serve3d(const stf_texture* tex, int filter, const ServeChunk* chunks, int32_t nchunks,
+                          int32_t nblocks, hipStream_t stream);
+hipError_t launch_serve2d(const stf_texture* tex, int filter, const ServeChunk* chunks, int32_t nchunks,
+                          int32_t nblocks, hipStream_t stream);
