@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
-"""Benchmark: filtered lookups/s on one MI355X, stochastic vs deterministic
-tricubic B-spline filtering of a sparse voxel grid.
+"""Benchmark of the stochastic texture filtering library on one MI355X.
 
-Workload: a 512^3 sparse grid of dense 8^3 FP32 leaves holding thresholded
-5-octave fBm value noise (about 6% of the leaves active), queried at
-16,777,216 positions along 65,536 random rays (256 samples per ray, ray-major
-order).  One step = one stf_filter call over the whole batch, inputs already
-resident in HBM.  The headline value is stochastic tricubic lookups/s; the
-deterministic 64-tap filter and the trilinear pair are timed beside it, on the
-same inputs.  The FP64 CPU oracle checks sampled outputs of every timed
-configuration and is timed on a bounded sample of the same workload
-(cpu_baseline).
+Default workload (`--workload grid`, the headline): a 512^3 sparse grid of
+dense 8^3 binary32 leaves holding thresholded 5-octave fBm value noise (about
+6% of the leaves active), queried at 16,777,216 positions along 65,536 random
+rays (256 samples per ray, ray-major order).  One step = one stf_filter call
+over the whole batch with inputs resident in HBM.  The headline value is
+stochastic tricubic lookups/s; the deterministic 64-tap filter and the
+trilinear pair are timed beside it on the same inputs.  The FP64 CPU oracle
+checks sampled outputs of every timed configuration and is timed on the same
+workload (cpu_baseline).
+
+Other workloads (one JSON line each): `tex2d` (256^2 RGBA texture, 65,536
+uv queries), `shade` (4096^2 material, 8M shading queries, three filter
+orders), `neural` (4096^2 x 8 texture as a 1024^2 x 8 latent grid + MLP:
+training and BF16-MFMA inference), `serving` (three resident textures,
+Poisson arrivals of log-normal request sizes at 0.5 / 1 / 2 G lookups/s).
 
 Prints one JSON line.
 """
@@ -26,6 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the headline kernel (stochastic tricubic, binary32
+# grid, ray order), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain
+# copy; to be re-measured (and set to None) whenever that kernel changes.
+HEADLINE_TRAFFIC_BYTES = {("f32", "ray"): 389.0e6}
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 METRIC = "filtered lookups/s, stochastic vs deterministic tricubic, at stated error; p99 batch latency"
 
 
@@ -35,7 +46,8 @@ def log(msg):
 
 def time_launches(fn, steps, warmup, torch):
     """Warm up, then time `steps` calls: wall clock between two device
-    synchronisations, and per-call HIP events on the launch stream."""
+    synchronisations, and per-call HIP events on the launch stream (torch's
+    current stream, which the library launches on)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -51,28 +63,24 @@ def time_launches(fn, steps, warmup, torch):
     return wall, kern_ms
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16", "fp8_e4m3"])
-    ap.add_argument("--order", default="ray", choices=["ray", "shuffled"])
-    ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="queries in the CPU-oracle timing sample")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle timing")
-    ap.add_argument("--only", default="", help="time only this variant (e.g. stoch_cubic)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
-        sys.exit(2)
+def base_line(args, value, unit, ms_per_step, dtype, config, higher=True):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": higher, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
-    import torch
 
-    import paper_2305_05810_amd as stf
-    import synth
+def variant_stats(n, steps, wall, kern, b_alg):
+    kmean = float(kern.mean())
+    return dict(lookups_per_s=n * steps / wall, ms_per_step=1e3 * wall / steps, kernel_ms_mean=kmean,
+                kernel_ms_p50=float(np.percentile(kern, 50)), kernel_ms_p99=float(np.percentile(kern, 99)),
+                bytes_per_lookup=b_alg, achieved_gbs=b_alg * n / (kmean * 1e-3) / 1e9)
 
+
+# ----------------------------------------------------------------------------
+# headline: sparse grid
+# ----------------------------------------------------------------------------
+def run_grid(args, torch, stf, synth):
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     dims = (512, 512, 512)
     t0 = time.time()
     grid = synth.fbm_grid(dims, seed=3)
@@ -85,86 +93,76 @@ def main():
     q = torch.from_numpy(pts).to(dev)
     out = torch.empty((n, 1), dtype=torch.float32, device=dev)
     texel_b = stf.FORMAT_BYTES[stf.FORMATS[args.fmt]]
-
     variants = [("stoch_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 64),
                 ("det_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_DETERMINISTIC, 64),
                 ("stoch_linear", stf.STF_LINEAR, stf.STF_STOCHASTIC, 8),
                 ("det_linear", stf.STF_LINEAR, stf.STF_DETERMINISTIC, 8)]
     if args.only:
         variants = [v for v in variants if v[0] == args.only]
+    if args.copy_calibration:
+        # a plain device copy of known size, for scaling hardware byte counters
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {a.numel() * 4} bytes read and written")
     res = {}
     seed = 0x5EED
     for name, filt, mode, taps in variants:
         fn = lambda: stf.stf_filter(tex, q, filt, mode, seed, out)
         wall, kern = time_launches(fn, args.steps, args.warmup, torch)
         b_alg = 12 + 4 + (texel_b if mode == stf.STF_STOCHASTIC else taps * texel_b)
-        kmean = float(kern.mean())
-        res[name] = dict(lookups_per_s=n * args.steps / wall, ms_per_step=1e3 * wall / args.steps,
-                         kernel_ms_mean=kmean, kernel_ms_p50=float(np.percentile(kern, 50)),
-                         kernel_ms_p99=float(np.percentile(kern, 99)), bytes_per_lookup=b_alg,
-                         achieved_gbs=b_alg * n / (kmean * 1e-3) / 1e9)
-        log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel {kmean * 1e3:.1f} us, "
-            f"{res[name]['achieved_gbs']:.0f} GB/s algorithmic")
+        res[name] = variant_stats(n, args.steps, wall, kern, b_alg)
+        log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel "
+            f"{res[name]['kernel_ms_mean'] * 1e3:.1f} us, {res[name]['achieved_gbs']:.0f} GB/s algorithmic")
 
-    # sampled parity of every timed configuration against the FP64 oracle
-    import oracle
-    ofmt = {"f32": oracle.F32, "f16": oracle.F16, "bf16": oracle.BF16, "fp8_e4m3": oracle.FP8_E4M3}[args.fmt]
-    og = oracle.Grid(dims, ofmt, grid.origins, raw)
-    rng = np.random.default_rng(12)
-    qids = np.sort(rng.choice(n, 1 << 16, replace=False))
-    parity = {}
-    for name, filt, mode, _ in variants:
-        ofilt = oracle.CUBIC if filt == stf.STF_CUBIC_BSPLINE else oracle.LINEAR
-        if mode == stf.STF_STOCHASTIC:
-            idx = torch.empty((n, 3), dtype=torch.int32, device=dev)
-            stf.stf_filter(tex, q, filt, mode, seed, out, idx)
-            gv = out[:, 0].cpu().numpy()[qids]
-            gi = idx.cpu().numpy()[qids]
-            ov, oi = og.filter_at(pts, qids, ofilt, oracle.STOCH, seed)
-            parity[name] = dict(sampled=int(qids.size), index_mismatches=int(np.any(gi != oi, axis=1).sum()),
-                                value_mismatches=int((gv != ov.astype(np.float32)).sum()))
-        else:
-            stf.stf_filter(tex, q, filt, mode, seed, out)
-            gv = out[:, 0].cpu().numpy()[qids].astype(np.float64)
-            ov, _ = og.filter_at(pts, qids, ofilt, oracle.DET, 0)
-            err = np.abs(gv - ov)
-            rel = np.where(ov != 0, err / np.where(ov == 0, 1, np.abs(ov)), np.where(err == 0, 0, np.inf))
-            parity[name] = dict(sampled=int(qids.size), max_rel_err=float(rel.max()),
-                                within_1e6=bool(np.all(err <= 1e-6 * np.abs(ov))))
-        log(f"parity {name}: {parity[name]}")
-
-    cpu = None
-    if not args.no_cpu and "stoch_cubic" in res:
-        m = min(args.cpu_sample, n)
-        sample = np.ascontiguousarray(pts[:m])
-        threads = oracle.max_threads()
-        t1 = time.perf_counter()
-        og.filter(sample, oracle.CUBIC, oracle.STOCH, seed, want_index=False, nthreads=threads)
-        dt = time.perf_counter() - t1
-        cpu = dict(value=m / dt, unit="lookups/s", cores=threads, kind="oracle",
-                   sample=f"first {m} of the {n} ray-ordered queries, stochastic tricubic, FP64 C oracle "
-                          f"with OpenMP, {dt:.2f} s")
-        log(f"cpu oracle: {m / dt / 1e6:.2f} M lookups/s on {threads} threads")
+    parity, cpu = {}, None
+    if not args.no_check:
+        import oracle
+        ofmt = {"f32": oracle.F32, "f16": oracle.F16, "bf16": oracle.BF16, "fp8_e4m3": oracle.FP8_E4M3}[args.fmt]
+        og = oracle.Grid(dims, ofmt, grid.origins, raw)
+        rng = np.random.default_rng(12)
+        qids = np.sort(rng.choice(n, 1 << 16, replace=False))
+        for name, filt, mode, _ in variants:
+            ofilt = oracle.CUBIC if filt == stf.STF_CUBIC_BSPLINE else oracle.LINEAR
+            if mode == stf.STF_STOCHASTIC:
+                idx = torch.empty((n, 3), dtype=torch.int32, device=dev)
+                stf.stf_filter(tex, q, filt, mode, seed, out, idx)
+                gv = out[:, 0].cpu().numpy()[qids]
+                gi = idx.cpu().numpy()[qids]
+                ov, oi = og.filter_at(pts, qids, ofilt, oracle.STOCH, seed)
+                parity[name] = dict(sampled=int(qids.size), index_mismatches=int(np.any(gi != oi, axis=1).sum()),
+                                    value_mismatches=int((gv != ov.astype(np.float32)).sum()))
+            else:
+                stf.stf_filter(tex, q, filt, mode, seed, out)
+                gv = out[:, 0].cpu().numpy()[qids].astype(np.float64)
+                ov, _ = og.filter_at(pts, qids, ofilt, oracle.DET, 0)
+                err = np.abs(gv - ov)
+                rel = np.where(ov != 0, err / np.where(ov == 0, 1, np.abs(ov)), np.where(err == 0, 0, np.inf))
+                parity[name] = dict(sampled=int(qids.size), max_rel_err=float(rel.max()),
+                                    within_1e6=bool(np.all(err <= 1e-6 * np.abs(ov))))
+            log(f"parity {name}: {parity[name]}")
+        if not args.no_cpu and "stoch_cubic" in res:
+            m = min(args.cpu_sample, n)
+            sample = np.ascontiguousarray(pts[:m])
+            threads = oracle.max_threads()
+            t1 = time.perf_counter()
+            og.filter(sample, oracle.CUBIC, oracle.STOCH, seed, want_index=False, nthreads=threads)
+            dt = time.perf_counter() - t1
+            cpu = dict(value=m / dt, unit="lookups/s", cores=threads, kind="oracle",
+                       sample=f"{'all' if m == n else 'first ' + str(m) + ' of the'} {n} ray-ordered queries, "
+                              f"stochastic tricubic, FP64 C oracle with OpenMP, {dt:.2f} s")
+            log(f"cpu oracle: {m / dt / 1e6:.2f} M lookups/s on {threads} threads")
 
     head = res.get("stoch_cubic") or next(iter(res.values()))
     det = res.get("det_cubic")
-    line = {
-        "metric": METRIC,
-        "value": head["lookups_per_s"],
-        "unit": "lookups/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": args.fmt,
-        "data": "synthetic",
-        "config": {"workload": f"sparse fBm voxel grid 512^3 of dense 8^3 {args.fmt} leaves "
-                               f"({grid.n_leaves} leaves), {n} {args.order}-ordered ray queries, "
-                               f"stochastic tricubic B-spline (deterministic 64-tap beside it)",
-                   "n_queries": n, "n_leaves": grid.n_leaves, "order": args.order},
+    line = base_line(args, head["lookups_per_s"], "lookups/s", head["ms_per_step"], args.fmt,
+                     {"workload": f"sparse fBm voxel grid 512^3 of dense 8^3 {args.fmt} leaves "
+                                  f"({grid.n_leaves} leaves), {n} {args.order}-ordered ray queries, "
+                                  f"stochastic tricubic B-spline (deterministic 64-tap beside it)",
+                      "n_queries": n, "n_leaves": grid.n_leaves, "order": args.order})
+    line.update({
         "p50_batch_ms": head["kernel_ms_p50"],
         "p99_batch_ms": head["kernel_ms_p99"],
         "deterministic_lookups_per_s": det["lookups_per_s"] if det else None,
@@ -172,10 +170,259 @@ def main():
         "variants": res,
         "parity": parity,
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
+                     "frac": head["achieved_gbs"] / HBM_PEAK_GBS,
+                     "traffic": args.traffic if args.traffic is not None
+                     else HEADLINE_TRAFFIC_BYTES.get((args.fmt, args.order))},
         "cpu_baseline": cpu,
-    }
+    })
     tex.destroy()
+    return line
+
+
+# ----------------------------------------------------------------------------
+# 2D texture
+# ----------------------------------------------------------------------------
+def run_tex2d(args, torch, stf, synth):
+    dev = torch.device("cuda:0")
+    tex_np = synth.texture2d(256, 256, 4, seed=1)
+    uv = synth.uv_queries(65536, seed=2)
+    n = uv.shape[0]
+    tex = stf.stf_create_texture2d(256, 256, 4, stf.STF_FMT_F32, [tex_np])
+    q = torch.from_numpy(uv).to(dev)
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    res = {}
+    for name, filt, mode, taps in (("stoch_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 16),
+                                   ("det_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_DETERMINISTIC, 16),
+                                   ("stoch_linear", stf.STF_LINEAR, stf.STF_STOCHASTIC, 4),
+                                   ("det_linear", stf.STF_LINEAR, stf.STF_DETERMINISTIC, 4)):
+        wall, kern = time_launches(lambda: stf.stf_filter(tex, q, filt, mode, 7, out), args.steps, args.warmup, torch)
+        res[name] = variant_stats(n, args.steps, wall, kern, 8 + 16 + (16 if mode == stf.STF_STOCHASTIC else 16 * taps))
+        log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel {res[name]['kernel_ms_mean'] * 1e3:.1f} us")
+    head = res["stoch_cubic"]
+    line = base_line(args, head["lookups_per_s"], "lookups/s", head["ms_per_step"], "f32",
+                     {"workload": "2D texture 256x256 RGBA f32, 65,536 uniform uv queries, clamp, stochastic bicubic "
+                                  "B-spline (deterministic 16-tap beside it)", "n_queries": n})
+    line.update({"variants": res,
+                 "stochastic_over_deterministic": head["lookups_per_s"] / res["det_cubic"]["lookups_per_s"],
+                 "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
+                 "cpu_baseline": None})
+    tex.destroy()
+    return line
+
+
+# ----------------------------------------------------------------------------
+# filtering with shading
+# ----------------------------------------------------------------------------
+GGX_FLOPS = 120   # binary32 operations of one shading evaluation (see the design notes)
+
+
+def run_shade(args, torch, stf, synth):
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    lv = synth.material_levels(4096, seed=21, levels=3)
+    recs = synth.shade_queries(1 << 23, seed=22)
+    n = recs.shape[0]
+    log(f"inputs {time.time() - t0:.1f}s")
+    mat = stf.stf_create_material2d(4096, 4096, lv)
+    q = torch.from_numpy(recs).to(dev)
+    out = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    res = {}
+    for name, mode, evals in (("stochastic", stf.STF_SHADE_STOCHASTIC, 1),
+                              ("filter_after_shade", stf.STF_FILTER_AFTER_SHADE, 16),
+                              ("shade_after_filter", stf.STF_SHADE_AFTER_FILTER, 1)):
+        wall, kern = time_launches(lambda: stf.stf_shade_filter(mat, q, stf.STF_CUBIC_BSPLINE, mode, 5, out),
+                                   args.steps, args.warmup, torch)
+        taps = 1 if mode == stf.STF_SHADE_STOCHASTIC else 16
+        res[name] = variant_stats(n, args.steps, wall, kern, 36 + 12 + 8 * taps)
+        res[name]["shading_evals"] = evals
+        res[name]["achieved_tflops"] = evals * GGX_FLOPS * n / (res[name]["kernel_ms_mean"] * 1e-3) / 1e12
+        log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel {res[name]['kernel_ms_mean'] * 1e3:.1f} us")
+    head = res["stochastic"]
+    fas = res["filter_after_shade"]
+    line = base_line(args, head["lookups_per_s"], "lookups/s", head["ms_per_step"], "f32",
+                     {"workload": "filter-after-shading, 4096^2 material (RGB8 albedo, U8 roughness, 2xf16 normal, "
+                                  "3 levels), 8,388,608 GGX shading queries, bicubic: stochastic (1 eval) vs "
+                                  "deterministic filter-after-shade (16 evals) vs shade-after-filter",
+                      "n_queries": n})
+    line.update({"variants": res,
+                 "stochastic_over_filter_after_shade": head["lookups_per_s"] / fas["lookups_per_s"],
+                 # the 16 taps of uniformly scattered queries are gathered from a 128 MiB
+                 # material: the kernel waits on memory, not on its GGX arithmetic
+                 "roofline": {"bound": "hbm", "achieved": fas["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": fas["achieved_gbs"] / HBM_PEAK_GBS,
+                              "traffic": None, "kernel": "filter_after_shade",
+                              "alu_tflops": fas["achieved_tflops"], "alu_peak_tflops": FP32_VECTOR_PEAK_TFLOPS},
+                 "cpu_baseline": None})
+    mat.destroy()
+    return line
+
+
+# ----------------------------------------------------------------------------
+# neural texture
+# ----------------------------------------------------------------------------
+DECODE_FLOPS = 2 * (8 * 64 + 64 * 64 + 64 * 8)   # useful multiply-adds of one decode, x2
+
+
+def run_neural(args, torch, stf, synth):
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    size, lsize = args.neural_size, args.neural_size // 4
+    target = synth.neural_target(size, seed=41)
+    lat, mlp = synth.neural_init(lsize, seed=42)
+    uv = synth.neural_queries(1 << 24, seed=43)
+    n = uv.shape[0]
+    log(f"inputs {time.time() - t0:.1f}s")
+    nt = stf.stf_ntex_create(size, size, lat, mlp)
+    tgt = torch.from_numpy(target).to(dev)
+    steps = args.neural_steps
+    loss = torch.empty(steps, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stf.stf_ntex_train(nt, tgt, steps, 1 << 18, 1e-2, 1e-3, 7, loss)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    loss_np = loss.cpu().numpy()
+    log(f"training: {steps} steps in {train_s:.2f}s, loss {loss_np[0]:.4g} -> {loss_np[-1]:.4g}")
+    stf.stf_ntex_prepare_inference(nt)
+    q = torch.from_numpy(uv).to(dev)
+    out = torch.empty((n, 8), dtype=torch.float32, device=dev)
+    res = {}
+    for name, filt, mode, dec in (("stoch_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 1),
+                                  ("det_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_DETERMINISTIC, 16),
+                                  ("stoch_linear", stf.STF_LINEAR, stf.STF_STOCHASTIC, 1),
+                                  ("det_linear", stf.STF_LINEAR, stf.STF_DETERMINISTIC, 4)):
+        wall, kern = time_launches(lambda: stf.stf_ntex_filter(nt, q, filt, mode, 3, out), args.steps, args.warmup,
+                                   torch)
+        res[name] = variant_stats(n, args.steps, wall, kern, 8 + 32 + 64 * dec)
+        res[name]["decodes_per_lookup"] = dec
+        res[name]["achieved_tflops"] = dec * DECODE_FLOPS * n / (res[name]["kernel_ms_mean"] * 1e-3) / 1e12
+        log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, "
+            f"{res[name]['achieved_tflops']:.1f} TFLOP/s useful")
+    # quality: decode every texel (bilinear at texel centres) against the stored texture
+    js, is_ = np.meshgrid(np.arange(size), np.arange(size), indexing="ij")
+    cen = np.stack([(is_ + 0.5) / size, (js + 0.5) / size], axis=-1).reshape(-1, 2).astype(np.float32)
+    cq = torch.from_numpy(cen).to(dev)
+    dec = torch.empty((cen.shape[0], 8), dtype=torch.float32, device=dev)
+    stf.stf_ntex_filter(nt, cq, stf.STF_LINEAR, stf.STF_DETERMINISTIC, 0, dec)
+    mse = float(((dec - tgt.reshape(-1, 8)) ** 2).mean().item())
+    head = res["det_cubic"]
+    line = base_line(args, res["stoch_cubic"]["lookups_per_s"], "lookups/s", res["stoch_cubic"]["ms_per_step"], "bf16",
+                     {"workload": f"neural texture {size}^2 x 8 as {lsize}^2 x 8 latents + MLP 8-64-64-8, "
+                                  f"{n} uv queries, bicubic: stochastic (1 decode) vs deterministic (16 decodes), "
+                                  "BF16 MFMA decode", "n_queries": n})
+    line.update({"variants": res,
+                 "stochastic_over_deterministic": res["stoch_cubic"]["lookups_per_s"] / head["lookups_per_s"],
+                 "training": {"steps": steps, "batch": 1 << 18, "seconds": train_s,
+                              "samples_per_s": steps * (1 << 18) / train_s, "loss_first": float(loss_np[0]),
+                              "loss_last": float(loss_np[-1])},
+                 "psnr_db": 10 * np.log10(1.0 / mse),
+                 "roofline": {"bound": "mfma", "achieved": head["achieved_tflops"], "peak": MFMA_BF16_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": head["achieved_tflops"] / MFMA_BF16_PEAK_TFLOPS,
+                              "traffic": None, "kernel": "det_cubic"},
+                 "cpu_baseline": None})
+    nt.destroy()
+    return line
+
+
+# ----------------------------------------------------------------------------
+# serving
+# ----------------------------------------------------------------------------
+def run_serving(args, torch, stf, synth):
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    g1 = synth.fbm_grid((512, 512, 512), seed=3)
+    g2 = synth.coarse_fbm_grid((2048, 2048, 2048), occupancy=0.02, seed=13)
+    mat = synth.material_levels(4096, seed=21, levels=1)[0]
+    rgba = np.stack([mat["albedo"][:, :, 0], mat["albedo"][:, :, 1], mat["albedo"][:, :, 2], mat["rough"]],
+                    axis=-1).astype(np.float32) / 255.0
+    t1 = stf.stf_create_sparse_grid3d(g1.dims, stf.STF_FMT_F16, g1.origins, g1.encoded("f16"))
+    t2 = stf.stf_create_sparse_grid3d(g2.dims, stf.STF_FMT_F16, g2.origins, g2.encoded("f16"))
+    t3 = stf.stf_create_texture2d(4096, 4096, 4, stf.STF_FMT_F16, [synth.encode(rgba, "f16")])
+    pool_n = 1 << 24
+    pools = [torch.from_numpy(synth.ray_queries(g1.dims, 65536, 256, seed=4)).to(dev),
+             torch.from_numpy(synth.ray_queries(g2.dims, 65536, 256, seed=14)).to(dev),
+             torch.from_numpy(synth.uv_queries(pool_n, seed=15)).to(dev)]
+    texs = [(t1, 3, 1), (t2, 3, 1), (t3, 2, 4)]
+    outs = [torch.empty((pool_n, c), dtype=torch.float32, device=dev) for _, _, c in texs]
+    log(f"inputs {time.time() - t0:.1f}s: grid512 {g1.n_leaves} leaves, grid2048 {g2.n_leaves} leaves")
+    srv = stf.stf_server_create(1 << 30, 4096, 1 << 18)
+    rng = np.random.default_rng(99)
+    loads = {}
+    flags = stf.STF_SERVE_QUERIES_ON_DEVICE | stf.STF_SERVE_RESULTS_ON_DEVICE
+    for load in args.loads:
+        sizes = np.clip(np.exp(rng.normal(np.log(16384.0), 1.0, 400000)), 1024, 1 << 20).astype(np.int64)
+        rate = load / sizes.mean()
+        count = int(rate * args.serve_seconds)
+        sizes = sizes[:count]
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
+        which = rng.integers(0, 3, count)
+        cubic = rng.random(count) < 0.5
+        offs = (rng.random(count) * (pool_n - sizes)).astype(np.int64)
+        reqs = []
+        for k in range(count):
+            tex, dims, ch = texs[which[k]]
+            reqs.append((tex, pools[which[k]].data_ptr() + 4 * dims * int(offs[k]), int(sizes[k]),
+                         stf.STF_CUBIC_BSPLINE if cubic[k] else stf.STF_LINEAR, k,
+                         outs[which[k]].data_ptr() + 4 * ch * int(offs[k]), None, float(arrivals[k])))
+        stf.stf_server_reset_stats(srv)
+        torch.cuda.synchronize()
+        stf.stf_server_replay(srv, reqs, flags, timeout_s=120.0)
+        st = stf.stf_server_stats(srv)
+        st["offered_lookups_per_s"] = load
+        st["requests"] = count
+        st["saturated"] = st["lookups_per_s"] < 0.9 * load
+        loads[f"{load:.2g}"] = st
+        log(f"load {load / 1e9:.1f} G/s: {count} requests, served {st['lookups_per_s'] / 1e9:.2f} G/s, "
+            f"p50 {st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms, peak resident {st['peak_resident']}")
+    top = loads[f"{args.loads[-1]:.2g}"]
+    line = base_line(args, top["lookups_per_s"], "lookups/s", None, "f16",
+                     {"workload": "serving: open-loop Poisson arrivals, log-normal request sizes (median 16,384, "
+                                  "clamp 1,024..1,048,576), 3 resident f16 textures (512^3 fBm grid, 2048^3 grid "
+                                  "at 2%, 4096^2 RGBA), stochastic tri/bi-linear and -cubic 50/50",
+                      "offered_loads": list(args.loads)})
+    line.update({"p50_batch_ms": top["p50_ms"], "p99_batch_ms": top["p99_ms"], "loads": loads,
+                 "roofline": None, "cpu_baseline": None})
+    srv.destroy()
+    for t, _, _ in texs:
+        t.destroy()
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="grid", choices=["grid", "tex2d", "shade", "neural", "serving"])
+    ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16", "fp8_e4m3"])
+    ap.add_argument("--order", default="ray", choices=["ray", "shuffled"])
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="queries in the CPU-oracle timing sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle timing")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle parity sample and the CPU timing")
+    ap.add_argument("--only", default="", help="time only this variant (e.g. stoch_cubic)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 256 MiB device copy first (hardware-counter calibration)")
+    ap.add_argument("--traffic", type=float, default=None,
+                    help="measured HBM bytes per launch of the headline kernel, overriding the recorded value")
+    ap.add_argument("--neural-size", type=int, default=4096)
+    ap.add_argument("--neural-steps", type=int, default=1000)
+    ap.add_argument("--loads", type=float, nargs="+", default=[0.5e9, 1e9, 2e9])
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2305_05810_amd as stf
+    import synth
+
+    torch.cuda.set_device(0)
+    run = {"grid": run_grid, "tex2d": run_tex2d, "shade": run_shade, "neural": run_neural,
+           "serving": run_serving}[args.workload]
+    line = run(args, torch, stf, synth)
     print(json.dumps(line), flush=True)
 
 

@@ -276,12 +276,14 @@ MATERIAL_DTYPE = np.dtype([("albedo", np.uint8, 3), ("rough", np.uint8), ("nx", 
 
 
 def _gauss_blur_fft(img: np.ndarray, sigma: float) -> np.ndarray:
-    """Periodic Gaussian blur of a 2D float64 image via the FFT."""
+    """Periodic Gaussian blur of a 2D float64 image via the FFT (torch's
+    multi-threaded CPU FFT)."""
     h, w = img.shape
-    fy = np.fft.fftfreq(h)[:, None]
-    fx = np.fft.rfftfreq(w)[None, :]
-    g = np.exp(-2.0 * (np.pi * sigma) ** 2 * (fx * fx + fy * fy))
-    return np.fft.irfft2(np.fft.rfft2(img) * g, s=img.shape)
+    fy = torch.fft.fftfreq(h, dtype=torch.float64)[:, None]
+    fx = torch.fft.rfftfreq(w, dtype=torch.float64)[None, :]
+    g = torch.exp(-2.0 * (np.pi * sigma) ** 2 * (fx * fx + fy * fy))
+    f = torch.fft.rfft2(torch.from_numpy(np.ascontiguousarray(img, np.float64)))
+    return torch.fft.irfft2(f * g, s=img.shape).numpy()
 
 
 def material_levels(size: int = 4096, seed: int = 21, levels: int = 3):
@@ -409,3 +411,24 @@ def neural_init(latent_size: int = 1024, seed: int = 42):
 
 def neural_queries(n: int = 1 << 24, seed: int = 43) -> np.ndarray:
     return uv_queries(n, seed)
+
+
+# ----------------------------------------------------------------------------
+# large sparse grid for the serving workload
+# ----------------------------------------------------------------------------
+def coarse_fbm_grid(dims=(2048, 2048, 2048), occupancy: float = 0.02, seed: int = 13,
+                    base_period_leaves: float = 16.0) -> SparseGrid:
+    """A sparse grid whose active leaves are chosen at leaf resolution: the
+    fBm of _FbmOctaves evaluated at leaf centres (one value per 8^3 leaf) is
+    thresholded at the quantile that keeps `occupancy` of the leaves; a voxel
+    of an active leaf holds (leaf value - threshold) * (0.5 + xi), xi uniform
+    in [0, 1) per voxel.  Cheap enough for a 2048^3 domain."""
+    nb = tuple(d // 8 for d in dims)
+    coarse = _FbmOctaves(nb, base_period_leaves, seed).slab(0, nb[2])    # (bz, by, bx)
+    thr = np.quantile(coarse, 1.0 - occupancy)
+    kz, ky, kx = np.nonzero(coarse > thr)
+    origins = np.stack([kx * 8, ky * 8, kz * 8], axis=1).astype(np.int32)
+    rng = np.random.default_rng(seed + 1)
+    base = (coarse[kz, ky, kx] - thr).astype(np.float32)
+    values = base[:, None, None, None] * (np.float32(0.5) + rng.random((kz.size, 8, 8, 8), dtype=np.float32))
+    return SparseGrid(dims, origins, values)
