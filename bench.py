@@ -92,6 +92,19 @@ def run_grid(args, torch, stf, synth):
     tex = stf.stf_create_sparse_grid3d(dims, stf.FORMATS[args.fmt], grid.origins, raw)
     q = torch.from_numpy(pts).to(dev)
     out = torch.empty((n, 1), dtype=torch.float32, device=dev)
+    sort_info = None
+    call = lambda filt, mode, seed_, o, idx=None: stf.stf_filter(tex, q, filt, mode, seed_, o, idx)
+    if args.order == "morton":
+        # the library's Morton sort of the ray-ordered batch, timed on its own;
+        # filtering then runs on the sorted stream (results in sorted order)
+        sq = torch.empty_like(q)
+        order = torch.empty(n, dtype=torch.int32, device=dev)
+        ws = torch.empty(stf.stf_sort_workspace_bytes(n), dtype=torch.uint8, device=dev)
+        wall, kern = time_launches(lambda: stf.stf_sort_queries(tex, q, sq, order, ws), args.steps, args.warmup,
+                                   torch)
+        sort_info = {"sort_ms": 1e3 * wall / args.steps}
+        log(f"morton sort of {n} queries: {sort_info['sort_ms']:.3f} ms")
+        call = lambda filt, mode, seed_, o, idx=None: stf.stf_filter_ordered(tex, sq, order, filt, mode, seed_, o, idx)
     texel_b = stf.FORMAT_BYTES[stf.FORMATS[args.fmt]]
     variants = [("stoch_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 64),
                 ("det_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_DETERMINISTIC, 64),
@@ -110,7 +123,7 @@ def run_grid(args, torch, stf, synth):
     res = {}
     seed = 0x5EED
     for name, filt, mode, taps in variants:
-        fn = lambda: stf.stf_filter(tex, q, filt, mode, seed, out)
+        fn = lambda: call(filt, mode, seed, out)
         wall, kern = time_launches(fn, args.steps, args.warmup, torch)
         b_alg = 12 + 4 + (texel_b if mode == stf.STF_STOCHASTIC else taps * texel_b)
         res[name] = variant_stats(n, args.steps, wall, kern, b_alg)
@@ -128,15 +141,25 @@ def run_grid(args, torch, stf, synth):
             ofilt = oracle.CUBIC if filt == stf.STF_CUBIC_BSPLINE else oracle.LINEAR
             if mode == stf.STF_STOCHASTIC:
                 idx = torch.empty((n, 3), dtype=torch.int32, device=dev)
-                stf.stf_filter(tex, q, filt, mode, seed, out, idx)
-                gv = out[:, 0].cpu().numpy()[qids]
-                gi = idx.cpu().numpy()[qids]
+                call(filt, mode, seed, out, idx)
+                gv = out[:, 0].cpu().numpy()
+                gi = idx.cpu().numpy()
+                if args.order == "morton":   # back to the caller's order
+                    inv = np.empty(n, np.int64)
+                    inv[order.cpu().numpy()] = np.arange(n)
+                    gv, gi = gv[inv], gi[inv]
+                gv, gi = gv[qids], gi[qids]
                 ov, oi = og.filter_at(pts, qids, ofilt, oracle.STOCH, seed)
                 parity[name] = dict(sampled=int(qids.size), index_mismatches=int(np.any(gi != oi, axis=1).sum()),
                                     value_mismatches=int((gv != ov.astype(np.float32)).sum()))
             else:
-                stf.stf_filter(tex, q, filt, mode, seed, out)
-                gv = out[:, 0].cpu().numpy()[qids].astype(np.float64)
+                call(filt, mode, seed, out)
+                gv = out[:, 0].cpu().numpy()
+                if args.order == "morton":
+                    inv = np.empty(n, np.int64)
+                    inv[order.cpu().numpy()] = np.arange(n)
+                    gv = gv[inv]
+                gv = gv[qids].astype(np.float64)
                 ov, _ = og.filter_at(pts, qids, ofilt, oracle.DET, 0)
                 err = np.abs(gv - ov)
                 rel = np.where(ov != 0, err / np.where(ov == 0, 1, np.abs(ov)), np.where(err == 0, 0, np.inf))
@@ -168,6 +191,7 @@ def run_grid(args, torch, stf, synth):
         "deterministic_lookups_per_s": det["lookups_per_s"] if det else None,
         "stochastic_over_deterministic": head["lookups_per_s"] / det["lookups_per_s"] if det else None,
         "variants": res,
+        "sort": sort_info,
         "parity": parity,
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["achieved_gbs"] / HBM_PEAK_GBS,
@@ -396,7 +420,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grid", choices=["grid", "tex2d", "shade", "neural", "serving"])
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16", "fp8_e4m3"])
-    ap.add_argument("--order", default="ray", choices=["ray", "shuffled"])
+    ap.add_argument("--order", default="ray", choices=["ray", "shuffled", "morton"])
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="queries in the CPU-oracle timing sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle timing")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle parity sample and the CPU timing")

@@ -157,6 +157,36 @@ stf_status stf_filter(const stf_texture* tex, const float* queries_dev, int64_t 
                       stf_filter_kind filter, stf_mode mode, uint64_t seed,
                       float* out_dev, int32_t* out_index_dev, uint32_t flags, void* hip_stream);
 
+/* ---------------------------------------------------------------------- */
+/* Morton-ordered query streams                                            */
+/* ---------------------------------------------------------------------- */
+/* Device workspace (bytes) that stf_sort_queries needs for n queries. */
+stf_status stf_sort_workspace_bytes(int64_t n, size_t* bytes);
+
+/* Orders n queries of `tex` by the Morton code of their 8^3 leaf (3D grids)
+ * or 4x4 texel tile (2D textures, level 0), so that queries touching the
+ * same region run next to each other.  Writes order_dev[k] = the index in
+ * queries_dev of the k-th query in that order (a permutation; ties keep
+ * their input order; non-finite queries go last) and sorted_queries_dev[k]
+ * = queries_dev[order_dev[k]].  workspace_dev: at least
+ * stf_sort_workspace_bytes(n) bytes of device memory, 256-byte aligned,
+ * used only during the call's stream work. */
+stf_status stf_sort_queries(const stf_texture* tex, const float* queries_dev, int64_t n,
+                            float* sorted_queries_dev, int32_t* order_dev, void* workspace_dev,
+                            size_t workspace_bytes, void* hip_stream);
+
+#define STF_ORDER_SCATTER 1u   /* results at out[order[k]] (the caller's order) */
+
+/* stf_filter on a sorted stream: query k of sorted_queries_dev is query
+ * order_dev[k] of the caller's batch and draws its random numbers as that
+ * query.  Results go to out[k] (sorted order), or to out[order_dev[k]] with
+ * STF_ORDER_SCATTER, where they equal stf_filter's on the unsorted batch
+ * bit for bit. */
+stf_status stf_filter_ordered(const stf_texture* tex, const float* sorted_queries_dev,
+                              const int32_t* order_dev, int64_t n, stf_filter_kind filter,
+                              stf_mode mode, uint64_t seed, float* out_dev, int32_t* out_index_dev,
+                              uint32_t flags, void* hip_stream);
+
 /* Per-query first and second moments of the stochastic estimator over
  * n_seeds draws (seeds seed_base .. seed_base + n_seeds - 1), accumulated in
  * binary64 on the device: sum_dev[q] = sum_k v_k, sumsq_dev[q] = sum_k v_k^2,

@@ -470,3 +470,55 @@ def stf_server_replay(s: Server, requests, flags: int, timeout_s: float = 120.0)
     for k, (tex, qp, n, f, seed, op, ip, t) in enumerate(requests):
         arr[k] = ServeRequest(tex.handle, qp, n, f, seed & (2 ** 64 - 1), op, ip, t)
     _check(_srv_lib().stf_server_replay(s.handle, arr, len(requests), flags, timeout_s))
+
+
+# ----------------------------------------------------------------------------
+# Morton-ordered query streams
+# ----------------------------------------------------------------------------
+STF_ORDER_SCATTER = 1
+
+
+def _sort_lib():
+    L = lib()
+    if not getattr(L, "_sort_declared", False):
+        vp, i32, i64, u32, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
+        L.stf_sort_workspace_bytes.argtypes = [i64, C.POINTER(C.c_size_t)]
+        L.stf_sort_queries.argtypes = [vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
+        L.stf_filter_ordered.argtypes = [vp, vp, vp, i64, i32, i32, u64, vp, vp, u32, vp]
+        for name in ("stf_sort_workspace_bytes", "stf_sort_queries", "stf_filter_ordered"):
+            getattr(L, name).restype = i32
+        L._sort_declared = True
+    return L
+
+
+def stf_sort_workspace_bytes(n: int) -> int:
+    b = C.c_size_t()
+    _check(_sort_lib().stf_sort_workspace_bytes(n, C.byref(b)))
+    return b.value
+
+
+def stf_sort_queries(tex: Texture, queries, sorted_out, order_out, workspace, stream=None):
+    """workspace: a uint8 GPU tensor of at least stf_sort_workspace_bytes(n)."""
+    _check(_sort_lib().stf_sort_queries(tex.handle, _dev_ptr(queries, "queries"), queries.shape[0],
+                                        _dev_ptr(sorted_out, "sorted_out"), _dev_ptr(order_out, "order_out"),
+                                        _dev_ptr(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+                                        _stream(stream)))
+
+
+def stf_filter_ordered(tex: Texture, sorted_queries, order, filter: int, mode: int, seed: int, out, out_index=None,
+                       flags: int = 0, stream=None):
+    _check(_sort_lib().stf_filter_ordered(tex.handle, _dev_ptr(sorted_queries, "sorted_queries"),
+                                          _dev_ptr(order, "order"), sorted_queries.shape[0], filter, mode,
+                                          seed & (2 ** 64 - 1), _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"),
+                                          flags, _stream(stream)))
+
+
+def sort_queries(tex: Texture, queries, stream=None):
+    """Convenience: allocate outputs and workspace, return (sorted, order)."""
+    import torch
+    n = queries.shape[0]
+    sorted_q = torch.empty_like(queries)
+    order = torch.empty(n, dtype=torch.int32, device=queries.device)
+    ws = torch.empty(max(1, stf_sort_workspace_bytes(n)), dtype=torch.uint8, device=queries.device)
+    stf_sort_queries(tex, queries, sorted_q, order, ws, stream)
+    return sorted_q, order

@@ -43,9 +43,12 @@ __device__ __forceinline__ void load_rgba(const TexLevel& L, int x, int y, float
 template <int FMT, int C, bool CUBIC>
 __device__ __forceinline__ void tex2d_stochastic_one(const TexLevel& L, const float* __restrict__ q, int32_t n,
                                                      int32_t i, uint32_t key, uint32_t qid0, float* __restrict__ out,
-                                                     int32_t* __restrict__ idx)
+                                                     int32_t* __restrict__ idx, const int32_t* __restrict__ order,
+                                                     int scatter)
 {
     if (i >= n) return;
+    const int32_t id = order ? order[i] : (int32_t)(qid0 + (uint32_t)i);
+    const int64_t oi = (order && scatter) ? (int64_t)id : (int64_t)i;
     float2 uv = reinterpret_cast<const float2*>(q)[i];
     float x = uv.x * (float)L.w - 0.5f;
     float y = uv.y * (float)L.h - 0.5f;
@@ -55,7 +58,7 @@ __device__ __forceinline__ void tex2d_stochastic_one(const TexLevel& L, const fl
     float v[C];
     int sx = BAD_INDEX, sy = BAD_INDEX;
     if (ok) {
-        uint32_t b = pcg(key ^ (qid0 + (uint32_t)i));
+        uint32_t b = pcg(key ^ (uint32_t)id);
         float ux = axis_uniform(b, 0), uy = axis_uniform(b, 1);
         if constexpr (CUBIC) {
             sx = cx + choose_cubic(tx, ux);
@@ -72,19 +75,20 @@ __device__ __forceinline__ void tex2d_stochastic_one(const TexLevel& L, const fl
         for (int c = 0; c < C; ++c) v[c] = __builtin_nanf("");
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) out[(int64_t)i * C + c] = v[c];
+    for (int c = 0; c < C; ++c) out[oi * C + c] = v[c];
     if (idx) {
-        idx[2 * (int64_t)i] = sx;
-        idx[2 * (int64_t)i + 1] = sy;
+        idx[2 * oi] = sx;
+        idx[2 * oi + 1] = sy;
     }
 }
 
 template <int FMT, int C, bool CUBIC>
 __global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(TexLevel L, const float* __restrict__ q, int32_t n,
                                                             uint32_t key, float* __restrict__ out,
-                                                            int32_t* __restrict__ idx)
+                                                            int32_t* __restrict__ idx, const int32_t* __restrict__ order,
+                                                            int scatter)
 {
-    tex2d_stochastic_one<FMT, C, CUBIC>(L, q, n, blockIdx.x * BLOCK + threadIdx.x, key, 0u, out, idx);
+    tex2d_stochastic_one<FMT, C, CUBIC>(L, q, n, blockIdx.x * BLOCK + threadIdx.x, key, 0u, out, idx, order, scatter);
 }
 
 // Serving: block b serves chunk c with start[c] <= b < start[c + 1].
@@ -100,16 +104,18 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_serve(TexLevel L, const ServeCh
     }
     const ServeChunk c = chunks[lo];
     tex2d_stochastic_one<FMT, C, CUBIC>(L, c.q, c.count, ((int32_t)blockIdx.x - c.block0) * BLOCK + threadIdx.x, c.key,
-                                        c.qid0, c.out, c.idx);
+                                        c.qid0, c.out, c.idx, nullptr, 0);
 }
 
 template <int FMT, int C, bool CUBIC>
 __global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(TexLevel L, const float* __restrict__ q, int32_t n,
-                                                               float* __restrict__ out)
+                                                               float* __restrict__ out, const int32_t* __restrict__ order,
+                                                               int scatter)
 {
     constexpr int NT = CUBIC ? 4 : 2;
     int32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
+    const int64_t oi = (order && scatter) ? (int64_t)order[i] : (int64_t)i;
     float2 uv = reinterpret_cast<const float2*>(q)[i];
     float x = uv.x * (float)L.w - 0.5f;
     float y = uv.y * (float)L.h - 0.5f;
@@ -119,7 +125,7 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(TexLevel L, const
     float acc[C];
     if (!ok) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) out[(int64_t)i * C + c] = __builtin_nanf("");
+        for (int c = 0; c < C; ++c) out[oi * C + c] = __builtin_nanf("");
         return;
     }
     float wx[NT], wy[NT];
@@ -152,7 +158,7 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(TexLevel L, const
         for (int c = 0; c < C; ++c) acc[c] = __builtin_fmaf(wy[b], row[c], acc[c]);
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) out[(int64_t)i * C + c] = CUBIC ? acc[c] / 36.0f : acc[c];
+    for (int c = 0; c < C; ++c) out[oi * C + c] = CUBIC ? acc[c] / 36.0f : acc[c];
 }
 
 // channel-0 moments of the stochastic estimator over many seeds
@@ -207,20 +213,22 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_moments(TexLevel L, const float
 
 template <int FMT, int C>
 hipError_t launch2d_fc(const TexLevel& L, const float* q, int32_t n, int filter, int mode, uint32_t key, float* out,
-                       int32_t* idx, hipStream_t stream)
+                       int32_t* idx, const int32_t* order, int scatter, hipStream_t stream)
 {
     dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
     bool cubic = filter == STF_CUBIC_BSPLINE;
     if (mode == STF_STOCHASTIC) {
         if (cubic)
-            hipLaunchKernelGGL((k_tex2d_stochastic<FMT, C, true>), grid, block, 0, stream, L, q, n, key, out, idx);
+            hipLaunchKernelGGL((k_tex2d_stochastic<FMT, C, true>), grid, block, 0, stream, L, q, n, key, out, idx, order,
+                               scatter);
         else
-            hipLaunchKernelGGL((k_tex2d_stochastic<FMT, C, false>), grid, block, 0, stream, L, q, n, key, out, idx);
+            hipLaunchKernelGGL((k_tex2d_stochastic<FMT, C, false>), grid, block, 0, stream, L, q, n, key, out, idx, order,
+                               scatter);
     } else {
         if (cubic)
-            hipLaunchKernelGGL((k_tex2d_deterministic<FMT, C, true>), grid, block, 0, stream, L, q, n, out);
+            hipLaunchKernelGGL((k_tex2d_deterministic<FMT, C, true>), grid, block, 0, stream, L, q, n, out, order, scatter);
         else
-            hipLaunchKernelGGL((k_tex2d_deterministic<FMT, C, false>), grid, block, 0, stream, L, q, n, out);
+            hipLaunchKernelGGL((k_tex2d_deterministic<FMT, C, false>), grid, block, 0, stream, L, q, n, out, order, scatter);
     }
     return hipGetLastError();
 }
@@ -266,14 +274,14 @@ hipError_t moments2d_fc(const TexLevel& L, const float* q, int32_t n, int filter
 
 template <int FMT>
 hipError_t launch2d_f(const stf_texture* t, const float* q, int32_t n, int filter, int mode, uint32_t key,
-                      float* out, int32_t* idx, hipStream_t s)
+                      float* out, int32_t* idx, const int32_t* order, int scatter, hipStream_t s)
 {
     const TexLevel& L = t->level[0];
     switch (t->channels) {
-    case 1: return launch2d_fc<FMT, 1>(L, q, n, filter, mode, key, out, idx, s);
-    case 2: return launch2d_fc<FMT, 2>(L, q, n, filter, mode, key, out, idx, s);
-    case 3: return launch2d_fc<FMT, 3>(L, q, n, filter, mode, key, out, idx, s);
-    case 4: return launch2d_fc<FMT, 4>(L, q, n, filter, mode, key, out, idx, s);
+    case 1: return launch2d_fc<FMT, 1>(L, q, n, filter, mode, key, out, idx, order, scatter, s);
+    case 2: return launch2d_fc<FMT, 2>(L, q, n, filter, mode, key, out, idx, order, scatter, s);
+    case 3: return launch2d_fc<FMT, 3>(L, q, n, filter, mode, key, out, idx, order, scatter, s);
+    case 4: return launch2d_fc<FMT, 4>(L, q, n, filter, mode, key, out, idx, order, scatter, s);
     }
     return hipErrorInvalidValue;
 }
@@ -295,14 +303,14 @@ hipError_t moments2d_f(const stf_texture* t, const float* q, int32_t n, int filt
 }  // namespace
 
 hipError_t launch_filter2d(const stf_texture* t, const float* q, int32_t n, int filter, int mode, uint32_t key,
-                           float* out, int32_t* idx, hipStream_t s)
+                           float* out, int32_t* idx, const int32_t* order, int scatter, hipStream_t s)
 {
     switch (t->fmt) {
-    case F32: return launch2d_f<F32>(t, q, n, filter, mode, key, out, idx, s);
-    case F16: return launch2d_f<F16>(t, q, n, filter, mode, key, out, idx, s);
-    case BF16: return launch2d_f<BF16>(t, q, n, filter, mode, key, out, idx, s);
-    case FP8_E4M3: return launch2d_f<FP8_E4M3>(t, q, n, filter, mode, key, out, idx, s);
-    case U8: return launch2d_f<U8>(t, q, n, filter, mode, key, out, idx, s);
+    case F32: return launch2d_f<F32>(t, q, n, filter, mode, key, out, idx, order, scatter, s);
+    case F16: return launch2d_f<F16>(t, q, n, filter, mode, key, out, idx, order, scatter, s);
+    case BF16: return launch2d_f<BF16>(t, q, n, filter, mode, key, out, idx, order, scatter, s);
+    case FP8_E4M3: return launch2d_f<FP8_E4M3>(t, q, n, filter, mode, key, out, idx, order, scatter, s);
+    case U8: return launch2d_f<U8>(t, q, n, filter, mode, key, out, idx, order, scatter, s);
     }
     return hipErrorInvalidValue;
 }

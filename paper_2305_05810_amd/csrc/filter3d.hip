@@ -77,15 +77,22 @@ __device__ __forceinline__ int32_t table_load(const int32_t* __restrict__ t, uin
 template <int FMT, bool CUBIC, int Q>
 __device__ __forceinline__ void grid_stochastic_block(const GridView& g, const float* __restrict__ q, int32_t n,
                                                       int32_t first, uint32_t key, uint32_t qid0,
-                                                      float* __restrict__ out, int32_t* __restrict__ idx)
+                                                      float* __restrict__ out, int32_t* __restrict__ idx,
+                                                      const int32_t* __restrict__ order, int scatter)
 {
     float p[Q][3];
     bool live[Q];
+    uint32_t qid[Q];   // id of the draw: the query's place in the caller's batch
+    int64_t oi[Q];     // where its result goes
 #pragma unroll
     for (int k = 0; k < Q; ++k) {   // all query loads first
         int32_t i = first + k * BLOCK;
         live[k] = i < n;
-        const float* e = q + 3 * (int64_t)(live[k] ? i : 0);
+        int32_t src = live[k] ? i : 0;
+        int32_t id = order ? order[src] : (int32_t)(qid0 + (uint32_t)i);
+        qid[k] = (uint32_t)id;
+        oi[k] = (order && scatter) ? (int64_t)id : (int64_t)i;
+        const float* e = q + 3 * (int64_t)src;
         p[k][0] = __builtin_nontemporal_load(e);
         p[k][1] = __builtin_nontemporal_load(e + 1);
         p[k][2] = __builtin_nontemporal_load(e + 2);
@@ -99,7 +106,7 @@ __device__ __forceinline__ void grid_stochastic_block(const GridView& g, const f
         int c0 = 0, c1 = 0, c2 = 0;
         float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f;
         fin[k] = cell_of(p[k][0], c0, t0) & cell_of(p[k][1], c1, t1) & cell_of(p[k][2], c2, t2);
-        uint32_t h0 = pcg(key ^ (qid0 + (uint32_t)i)), h1, h2;
+        uint32_t h0 = pcg(key ^ qid[k]), h1, h2;
         pcg_next2(h0, h1, h2);
         float m0 = hash_m(h0), m1 = hash_m(h1), m2 = hash_m(h2);
         if constexpr (CUBIC) {
@@ -153,11 +160,11 @@ __device__ __forceinline__ void grid_stochastic_block(const GridView& g, const f
     for (int k = 0; k < Q; ++k) {
         int32_t i = first + k * BLOCK;
         if (!live[k]) continue;
-        __builtin_nontemporal_store(fin[k] ? v[k] : __builtin_nanf(""), out + i);
+        __builtin_nontemporal_store(fin[k] ? v[k] : __builtin_nanf(""), out + oi[k]);
         if (idx) {
-            idx[3 * (int64_t)i] = fin[k] ? vx[k] : BAD_INDEX;
-            idx[3 * (int64_t)i + 1] = fin[k] ? vy[k] : BAD_INDEX;
-            idx[3 * (int64_t)i + 2] = fin[k] ? vz[k] : BAD_INDEX;
+            idx[3 * oi[k]] = fin[k] ? vx[k] : BAD_INDEX;
+            idx[3 * oi[k] + 1] = fin[k] ? vy[k] : BAD_INDEX;
+            idx[3 * oi[k] + 2] = fin[k] ? vz[k] : BAD_INDEX;
         }
     }
 }
@@ -165,9 +172,11 @@ __device__ __forceinline__ void grid_stochastic_block(const GridView& g, const f
 template <int FMT, bool CUBIC, int Q>
 __global__ __launch_bounds__(BLOCK) void k_grid_stochastic(GridView g, const float* __restrict__ q, int32_t n,
                                                            uint32_t key, float* __restrict__ out,
-                                                           int32_t* __restrict__ idx)
+                                                           int32_t* __restrict__ idx, const int32_t* __restrict__ order,
+                                                           int scatter)
 {
-    grid_stochastic_block<FMT, CUBIC, Q>(g, q, n, blockIdx.x * (BLOCK * Q) + threadIdx.x, key, 0u, out, idx);
+    grid_stochastic_block<FMT, CUBIC, Q>(g, q, n, blockIdx.x * (BLOCK * Q) + threadIdx.x, key, 0u, out, idx, order,
+                                         scatter);
 }
 
 // Serving: one launch over many requests' chunks (same grid and filter).
@@ -183,7 +192,7 @@ __global__ __launch_bounds__(BLOCK) void k_grid_serve(GridView g, const ServeChu
     }
     const ServeChunk c = chunks[lo];
     grid_stochastic_block<FMT, CUBIC, Q>(g, c.q, c.count, ((int32_t)blockIdx.x - c.block0) * (BLOCK * Q) + threadIdx.x,
-                                         c.key, c.qid0, c.out, c.idx);
+                                         c.key, c.qid0, c.out, c.idx, nullptr, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -200,7 +209,8 @@ __device__ __forceinline__ int32_t pick8(const int32_t (&l)[8], bool kx, bool ky
 
 template <int FMT, bool CUBIC>
 __global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const float* __restrict__ q, int32_t n,
-                                                              float* __restrict__ out)
+                                                              float* __restrict__ out, const int32_t* __restrict__ order,
+                                                              int scatter)
 {
     constexpr int NT = CUBIC ? 4 : 2;
     int32_t i = blockIdx.x * BLOCK + threadIdx.x;
@@ -210,7 +220,7 @@ __global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const 
     float t[3];
     bool ok = cell_of(p[0], c[0], t[0]) & cell_of(p[1], c[1], t[1]) & cell_of(p[2], c[2], t[2]);
     if (!ok) {
-        out[i] = __builtin_nanf("");
+        out[(order && scatter) ? order[i] : i] = __builtin_nanf("");
         return;
     }
     float w[3][NT];
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const 
         acc = __builtin_fmaf(w[2][cz], plane, acc);
     }
     if constexpr (CUBIC) acc = acc / 216.0f;   // the three per-axis factors of 1/6
-    out[i] = acc;
+    out[(order && scatter) ? order[i] : i] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -315,7 +325,7 @@ __global__ __launch_bounds__(BLOCK) void k_grid_moments(GridView g, const float*
 
 template <int FMT>
 hipError_t launch3d_fmt(const GridView& g, const float* q, int32_t n, int filter, int mode, uint32_t key, float* out,
-                        int32_t* idx, hipStream_t stream)
+                        int32_t* idx, const int32_t* order, int scatter, hipStream_t stream)
 {
     dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
     bool cubic = filter == STF_CUBIC_BSPLINE;
@@ -323,14 +333,16 @@ hipError_t launch3d_fmt(const GridView& g, const float* q, int32_t n, int filter
         constexpr int Q = STOCH_Q;
         dim3 sgrid((unsigned)(((int64_t)n + BLOCK * Q - 1) / (BLOCK * Q)));
         if (cubic)
-            hipLaunchKernelGGL((k_grid_stochastic<FMT, true, Q>), sgrid, block, 0, stream, g, q, n, key, out, idx);
+            hipLaunchKernelGGL((k_grid_stochastic<FMT, true, Q>), sgrid, block, 0, stream, g, q, n, key, out, idx, order,
+                               scatter);
         else
-            hipLaunchKernelGGL((k_grid_stochastic<FMT, false, Q>), sgrid, block, 0, stream, g, q, n, key, out, idx);
+            hipLaunchKernelGGL((k_grid_stochastic<FMT, false, Q>), sgrid, block, 0, stream, g, q, n, key, out, idx, order,
+                               scatter);
     } else {
         if (cubic)
-            hipLaunchKernelGGL((k_grid_deterministic<FMT, true>), grid, block, 0, stream, g, q, n, out);
+            hipLaunchKernelGGL((k_grid_deterministic<FMT, true>), grid, block, 0, stream, g, q, n, out, order, scatter);
         else
-            hipLaunchKernelGGL((k_grid_deterministic<FMT, false>), grid, block, 0, stream, g, q, n, out);
+            hipLaunchKernelGGL((k_grid_deterministic<FMT, false>), grid, block, 0, stream, g, q, n, out, order, scatter);
     }
     return hipGetLastError();
 }
@@ -361,15 +373,15 @@ hipError_t serve3d_fmt(const GridView& g, int filter, const ServeChunk* chunks, 
 }  // namespace
 
 hipError_t launch_filter3d(const stf_texture* tex, const float* q, int32_t n, int filter, int mode, uint32_t key,
-                           float* out, int32_t* idx, hipStream_t stream)
+                           float* out, int32_t* idx, const int32_t* order, int scatter, hipStream_t stream)
 {
     const GridView& g = tex->grid;
     switch (tex->fmt) {
-    case F32: return launch3d_fmt<F32>(g, q, n, filter, mode, key, out, idx, stream);
-    case F16: return launch3d_fmt<F16>(g, q, n, filter, mode, key, out, idx, stream);
-    case BF16: return launch3d_fmt<BF16>(g, q, n, filter, mode, key, out, idx, stream);
-    case FP8_E4M3: return launch3d_fmt<FP8_E4M3>(g, q, n, filter, mode, key, out, idx, stream);
-    case U8: return launch3d_fmt<U8>(g, q, n, filter, mode, key, out, idx, stream);
+    case F32: return launch3d_fmt<F32>(g, q, n, filter, mode, key, out, idx, order, scatter, stream);
+    case F16: return launch3d_fmt<F16>(g, q, n, filter, mode, key, out, idx, order, scatter, stream);
+    case BF16: return launch3d_fmt<BF16>(g, q, n, filter, mode, key, out, idx, order, scatter, stream);
+    case FP8_E4M3: return launch3d_fmt<FP8_E4M3>(g, q, n, filter, mode, key, out, idx, order, scatter, stream);
+    case U8: return launch3d_fmt<U8>(g, q, n, filter, mode, key, out, idx, order, scatter, stream);
     }
     return hipErrorInvalidValue;
 }

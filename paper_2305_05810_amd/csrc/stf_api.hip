@@ -293,8 +293,10 @@ stf_status stf_filter(const stf_texture* tex, const float* queries_dev, int64_t 
     if (s != STF_OK) return s;
     uint32_t key = stf::seed_key(seed);
     hipStream_t st = (hipStream_t)hip_stream;
-    hipError_t e = is2d ? launch_filter2d(tex, queries_dev, (int32_t)n, filter, mode, key, out_dev, out_index_dev, st)
-                        : launch_filter3d(tex, queries_dev, (int32_t)n, filter, mode, key, out_dev, out_index_dev, st);
+    hipError_t e = is2d ? launch_filter2d(tex, queries_dev, (int32_t)n, filter, mode, key, out_dev, out_index_dev,
+                                          nullptr, 0, st)
+                        : launch_filter3d(tex, queries_dev, (int32_t)n, filter, mode, key, out_dev, out_index_dev,
+                                          nullptr, 0, st);
     if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return STF_OK;
 }

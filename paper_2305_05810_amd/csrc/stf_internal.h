@@ -65,10 +65,14 @@ stf_status stf_fail(stf_status code, const char* fmt, ...);
 void stf_clear_error();
 
 // Kernel launchers; each returns hipSuccess or the launch error.
+// order: NULL, or the caller-batch index of each (sorted) query, which keys
+// its random draw; scatter: results go to out[order[i]] instead of out[i].
 hipError_t launch_filter2d(const stf_texture* tex, const float* q, int32_t n, int filter, int mode,
-                           uint32_t skey, float* out, int32_t* idx, hipStream_t stream);
+                           uint32_t skey, float* out, int32_t* idx, const int32_t* order, int scatter,
+                           hipStream_t stream);
 hipError_t launch_filter3d(const stf_texture* tex, const float* q, int32_t n, int filter, int mode,
-                           uint32_t skey, float* out, int32_t* idx, hipStream_t stream);
+                           uint32_t skey, float* out, int32_t* idx, const int32_t* order, int scatter,
+                           hipStream_t stream);
 hipError_t launch_moments2d(const stf_texture* tex, const float* q, int32_t n, int filter,
                             uint64_t seed_base, int32_t n_seeds, double* sum, double* sumsq,
                             hipStream_t stream);

@@ -1,0 +1,105 @@
+"""Morton-ordered query streams: the sort returns a permutation whose keys
+(interleaved leaf / tile coordinates, recomputed here) do not decrease, and
+filtering the sorted stream reproduces stf_filter on the unsorted batch bit
+for bit (results scattered back) or in sorted order."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2305_05810_amd as stf
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _spread(v, bits, step):
+    out = np.zeros_like(v, dtype=np.uint64)
+    for b in range(bits):
+        out |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(step * b)
+    return out
+
+
+def _keys3d(p):
+    fin = np.all(np.isfinite(p), axis=1)
+    c = np.floor(np.clip(np.nan_to_num(p, nan=0.0), -1.0, 16777215.0)).astype(np.int64) >> 3
+    c = np.clip(c, 0, 1023).astype(np.uint64)
+    k = _spread(c[:, 0], 10, 3) | (_spread(c[:, 1], 10, 3) << np.uint64(1)) | (_spread(c[:, 2], 10, 3) << np.uint64(2))
+    return np.where(fin, k, np.uint64(0xFFFFFFFF))
+
+
+def _keys2d(uv, w, h):
+    fin = np.all(np.isfinite(uv), axis=1)
+    x = (uv[:, 0] * np.float32(w) - np.float32(0.5)).astype(np.float32)
+    y = (uv[:, 1] * np.float32(h) - np.float32(0.5)).astype(np.float32)
+    cx = np.clip(np.floor(np.clip(np.nan_to_num(x), -1, 16777215)).astype(np.int64) >> 2, 0, 32767).astype(np.uint64)
+    cy = np.clip(np.floor(np.clip(np.nan_to_num(y), -1, 16777215)).astype(np.int64) >> 2, 0, 32767).astype(np.uint64)
+    k = _spread(cx, 15, 2) | (_spread(cy, 15, 2) << np.uint64(1))
+    return np.where(fin, k, np.uint64(0xFFFFFFFF))
+
+
+@pytest.fixture(scope="module")
+def grid_case():
+    g = synth.fbm_grid((64, 64, 64), base_period=16.0, seed=7)
+    p = synth.uniform_box_queries(g.dims, 70001, seed=3, margin=3.0)
+    p[5] = [np.nan, 1, 1]
+    return g, p
+
+
+def _check_order(keys, order, n):
+    assert np.array_equal(np.sort(order), np.arange(n))
+    assert np.all(np.diff(keys[order].astype(np.int64)) >= 0)
+
+
+def test_grid_sort_and_ordered_filter(dev, grid_case):
+    g, p = grid_case
+    tex = stf.stf_create_sparse_grid3d(g.dims, stf.STF_FMT_F32, g.origins, g.values)
+    q = torch.from_numpy(p).to(dev)
+    sq, order = stf.sort_queries(tex, q)
+    o = order.cpu().numpy()
+    _check_order(_keys3d(p), o, p.shape[0])
+    assert np.array_equal(np.nan_to_num(sq.cpu().numpy(), nan=-9), np.nan_to_num(p[o], nan=-9))
+    for filt in (stf.STF_LINEAR, stf.STF_CUBIC_BSPLINE):
+        ref, ridx = stf.filter(tex, q, filt, stf.STF_STOCHASTIC, 11, want_index=True)
+        out = torch.empty_like(ref)
+        idx = torch.empty_like(ridx)
+        stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_STOCHASTIC, 11, out, idx, stf.STF_ORDER_SCATTER)
+        assert torch.equal(idx, ridx) and torch.equal(out.nan_to_num(-7), ref.nan_to_num(-7))
+        stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_STOCHASTIC, 11, out, idx, 0)
+        assert torch.equal(out.nan_to_num(-7), ref[order.long()].nan_to_num(-7))
+        dref, _ = stf.filter(tex, q, filt, stf.STF_DETERMINISTIC, 0)
+        stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_DETERMINISTIC, 0, out, None, stf.STF_ORDER_SCATTER)
+        assert torch.equal(out.nan_to_num(-7), dref.nan_to_num(-7))
+    tex.destroy()
+
+
+def test_tex2d_sort_and_ordered_filter(dev):
+    t = synth.texture2d(300, 200, 4, seed=4)
+    tex = stf.stf_create_texture2d(300, 200, 4, stf.STF_FMT_F32, [t])
+    uv = synth.uv_queries(50000, seed=5) * np.float32(1.2) - np.float32(0.1)
+    q = torch.from_numpy(uv).to(dev)
+    sq, order = stf.sort_queries(tex, q)
+    o = order.cpu().numpy()
+    _check_order(_keys2d(uv, 300, 200), o, uv.shape[0])
+    for filt in (stf.STF_LINEAR, stf.STF_CUBIC_BSPLINE):
+        ref, ridx = stf.filter(tex, q, filt, stf.STF_STOCHASTIC, 3, want_index=True)
+        out = torch.empty_like(ref)
+        idx = torch.empty_like(ridx)
+        stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_STOCHASTIC, 3, out, idx, stf.STF_ORDER_SCATTER)
+        assert torch.equal(idx, ridx) and torch.equal(out, ref)
+        dref, _ = stf.filter(tex, q, filt, stf.STF_DETERMINISTIC, 0)
+        stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_DETERMINISTIC, 0, out, None, stf.STF_ORDER_SCATTER)
+        assert torch.equal(out, dref)
+    tex.destroy()
+
+
+def test_sort_argument_errors(dev, grid_case):
+    g, p = grid_case
+    tex = stf.stf_create_sparse_grid3d(g.dims, stf.STF_FMT_F32, g.origins, g.values)
+    q = torch.from_numpy(p[:1000]).to(dev)
+    small = torch.empty(16, dtype=torch.uint8, device=dev)
+    with pytest.raises(stf.STFError):
+        stf.stf_sort_queries(tex, q, torch.empty_like(q), torch.empty(1000, dtype=torch.int32, device=dev), small)
+    with pytest.raises(stf.STFError):   # the sorted copy may not alias the input
+        ws = torch.empty(stf.stf_sort_workspace_bytes(1000), dtype=torch.uint8, device=dev)
+        stf.stf_sort_queries(tex, q, q, torch.empty(1000, dtype=torch.int32, device=dev), ws)
+    tex.destroy()
