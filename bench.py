@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the headline kernel (stochastic tricubic, binary32
 # grid, ray order), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain
 # copy; to be re-measured (and set to None) whenever that kernel changes.
-HEADLINE_TRAFFIC_BYTES = {("f32", "ray"): 389.0e6}
+HEADLINE_TRAFFIC_BYTES = {("f32", "ray"): 389.1e6}
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 METRIC = "filtered lookups/s, stochastic vs deterministic tricubic, at stated error; p99 batch latency"

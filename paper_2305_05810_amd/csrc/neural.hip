@@ -41,7 +41,18 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NL, OFF_W2 = OFF_B1 + NH, OFF_B
 constexpr int PSTRIDE = NPARAM + 1;   // per-block partial gradients + loss
 constexpr int TS = 32;                 // samples per training tile
 constexpr int TBLOCK = 256;
-constexpr int OWN = (NPARAM + TBLOCK - 1) / TBLOCK;   // parameters owned per thread
+// Weight-gradient ownership: thread t accumulates W2 entries t + 256 r
+// (r < 16) and entries t + 256 r (r < 5) of the remaining 1160 parameters
+// (W1, b1, b2, W3, b3), each in a register across all tiles of its block.
+constexpr int OWN2 = NH * NH / TBLOCK;                        // 16
+constexpr int NREST = NPARAM - NH * NH;                       // 1160
+constexpr int OWNR = (NREST + TBLOCK - 1) / TBLOCK;           // 5
+
+// flat parameter index of entry r of the non-W2 list
+__host__ __device__ constexpr int rest_param(int r)
+{
+    return r < OFF_W2 ? r : r + NH * NH;   // W1, b1 precede W2; b2, W3, b3 follow
+}
 
 struct TrainArgs {
     const float* lat;
@@ -80,9 +91,11 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
         else if (p < OFF_B3) sW3[(p - OFF_W3) / NH][(p - OFF_W3) % NH] = v;
         else sB3[p - OFF_B3] = v;
     }
-    float acc[OWN];
+    float acc2[OWN2], accr[OWNR];
 #pragma unroll
-    for (int r = 0; r < OWN; ++r) acc[r] = 0.0f;
+    for (int r = 0; r < OWN2; ++r) acc2[r] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < OWNR; ++r) accr[r] = 0.0f;
     float lacc = 0.0f;
     const int s = t / 8, k = t % 8;   // (sample, channel) for the gather/scatter phases
     for (int tile = blockIdx.x; tile * TS < a.B; tile += gridDim.x) {
@@ -181,34 +194,44 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
                 for (int c = 0; c < 4; ++c) atomicAdd(a.g_lat + (int64_t)sCI[s][c] * NL + k, sCW[s][c] * dz);
             }
         }
+        // W2 gradient: dW2[ua][ub] = sum_q dh2[q][ua] h1[q][ub]; ua = t/64 + 4r, ub = t%64
 #pragma unroll
-        for (int r = 0; r < OWN; ++r) {
-            int p = t + TBLOCK * r;
+        for (int r = 0; r < OWN2; ++r) {
+            const int ua = t / NH + (TBLOCK / NH) * r, ub = t % NH;
+            float g = 0.0f;
+#pragma unroll 8
+            for (int q = 0; q < TS; ++q) g = __builtin_fmaf(sD2[q][ua], sH1[q][ub], g);
+            acc2[r] += g;
+        }
+#pragma unroll
+        for (int r = 0; r < OWNR; ++r) {
+            const int e = t + TBLOCK * r;
+            if (e >= NREST) break;
+            const int p = rest_param(e);
             float g = 0.0f;
             if (p < OFF_B1) {
                 int ua = p / NL, uk = p % NL;
                 for (int q = 0; q < TS; ++q) g = __builtin_fmaf(sD1[q][ua], sZ[q][uk], g);
             } else if (p < OFF_W2) {
                 for (int q = 0; q < TS; ++q) g += sD1[q][p - OFF_B1];
-            } else if (p < OFF_B2) {
-                int ua = (p - OFF_W2) / NH, ub = (p - OFF_W2) % NH;
-                for (int q = 0; q < TS; ++q) g = __builtin_fmaf(sD2[q][ua], sH1[q][ub], g);
             } else if (p < OFF_W3) {
                 for (int q = 0; q < TS; ++q) g += sD2[q][p - OFF_B2];
             } else if (p < OFF_B3) {
                 int uc = (p - OFF_W3) / NH, ua = (p - OFF_W3) % NH;
                 for (int q = 0; q < TS; ++q) g = __builtin_fmaf(sDY[q][uc], sH2[q][ua], g);
-            } else if (p < NPARAM) {
+            } else {
                 for (int q = 0; q < TS; ++q) g += sDY[q][p - OFF_B3];
             }
-            acc[r] += g;
+            accr[r] += g;
         }
     }
     float* out = a.partial + (int64_t)blockIdx.x * PSTRIDE;
 #pragma unroll
-    for (int r = 0; r < OWN; ++r) {
-        int p = t + TBLOCK * r;
-        if (p < NPARAM) out[p] = acc[r];
+    for (int r = 0; r < OWN2; ++r) out[OFF_W2 + (t / NH + (TBLOCK / NH) * r) * NH + t % NH] = acc2[r];
+#pragma unroll
+    for (int r = 0; r < OWNR; ++r) {
+        const int e = t + TBLOCK * r;
+        if (e < NREST) out[rest_param(e)] = accr[r];
     }
     sRed[t] = lacc;
     __syncthreads();
@@ -219,14 +242,28 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
     if (t == 0) out[NPARAM] = sRed[0];
 }
 
-// Sum of the per-block partials in block order (reproducible).
-__global__ void k_ntex_reduce(const float* __restrict__ partial, int nblocks, float* __restrict__ g_mlp,
-                              float* __restrict__ loss, float loss_scale)
+// Sum of the per-block partials in a fixed order (reproducible): stage 1
+// sums consecutive groups of RGROUP blocks, stage 2 sums the group totals.
+constexpr int RGROUP = 32;
+
+__global__ void k_ntex_reduce1(const float* __restrict__ partial, int nblocks, float* __restrict__ group_sums)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > NPARAM) return;
+    int g = blockIdx.y;
+    if (p >= PSTRIDE) return;
     float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * PSTRIDE + p];
+    int b1 = min(nblocks, (g + 1) * RGROUP);
+    for (int b = g * RGROUP; b < b1; ++b) s += partial[(int64_t)b * PSTRIDE + p];
+    group_sums[(int64_t)g * PSTRIDE + p] = s;
+}
+
+__global__ void k_ntex_reduce2(const float* __restrict__ group_sums, int ngroups, float* __restrict__ g_mlp,
+                               float* __restrict__ loss, float loss_scale)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= PSTRIDE) return;
+    float s = 0.0f;
+    for (int g = 0; g < ngroups; ++g) s += group_sums[(int64_t)g * PSTRIDE + p];
     if (p < NPARAM) g_mlp[p] = s;
     else if (loss) *loss = s * loss_scale;
 }
@@ -265,15 +302,17 @@ __global__ void k_to_f16(const float* __restrict__ src, uint16_t* __restrict__ d
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Operand images, one 8-value (A) or 16-value (C) slot per lane, in the order
-// the kernel loads them.
+// Operand images: one 8-value A slot per lane for every MFMA.  Biases enter
+// the products themselves: every bias is split exactly into three bf16 terms
+// held in k-slots 8..10 of an A operand, which meet ones in the same slots of
+// the B operand.  Layer 1 uses its padding slots for this; layers 2 and 3
+// start their accumulation with one bias-only MFMA.
 struct Packed {
-    bf16x8 a1[2][64];      // layer 1, M-blocks of 32 hidden units; K = 8 latent + 8 zero
+    bf16x8 a1[2][64];      // layer 1, M-blocks of 32 hidden units; k 0..7 latent, 8..10 bias terms
     bf16x8 a2[2][4][64];   // layer 2, M-blocks x K-blocks of 16
     bf16x8 a3[4][64];      // layer 3, rows 0..7 real, 8..31 zero
-    float c1[2][64][16];   // biases laid out as accumulator images
-    float c2[2][64][16];
-    float c3[64][16];
+    bf16x8 ab2[2][64];     // layer 2 bias terms per M-block
+    bf16x8 ab3[64];        // layer 3 bias terms
 };
 
 // Hidden unit held by k-slot kappa = 16 kb + 8 h + j of the B operand when
@@ -288,6 +327,8 @@ __host__ __device__ constexpr int row_of_acc(int mb, int h, int r)
 {
     return 32 * mb + 8 * (r / 4) + 4 * h + (r % 4);
 }
+static_assert(row_of_acc(0, 0, 0) == 0 && row_of_acc(0, 1, 3) == 7,
+              "registers 0..3 of lane half h hold output channels 4h..4h+3");
 
 struct InferArgs {
     const Packed* pk;
@@ -300,121 +341,182 @@ struct InferArgs {
     int32_t* idx;            // n x 2 (stochastic) or null
 };
 
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU after rounding to bf16, done on the bit patterns: a bf16 whose sign
+// bit is set reads as a negative int16, so a signed 16-bit max with zero maps
+// it (and -0) to +0 and leaves every other value as it is.  Rounding keeps
+// the sign, so this equals rounding the ReLU of the fp32 value.
 __device__ __forceinline__ bf16x8 relu_bf16(const f32x16& d, int base)
 {
-    bf16x8 r;
+    i16x8 v;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) r[j] = (__bf16)fmaxf(d[base + j], 0.0f);
-    return r;
+    for (int j = 0; j < 8; j += 2) {
+        i16x2 p = __builtin_bit_cast(i16x2, __builtin_convertvector((f32x2){d[base + j], d[base + j + 1]}, bf16x2));
+        p = __builtin_elementwise_max(p, (i16x2)0);
+        v[j] = p[0];
+        v[j + 1] = p[1];
+    }
+    return __builtin_bit_cast(bf16x8, v);
 }
 
+// One lane's decode within a 32-decode batch: the query it serves, the tap,
+// the tap's filter weight and the texel it decodes.
+struct Decode {
+    int64_t qi;
+    int tap, sx, sy;
+    float w;
+    bool live, fin;
+};
+
 template <bool CUBIC, bool STOCH>
-__global__ __launch_bounds__(256) void k_ntex_infer(InferArgs a)
+__device__ __forceinline__ Decode locate(const InferArgs& a, int64_t qi, int tap, float2 uv)
+{
+    Decode d;
+    d.qi = qi;
+    d.tap = tap;
+    d.live = qi < a.n;
+    float x = uv.x * (float)a.W - 0.5f, y = uv.y * (float)a.H - 0.5f;
+    int cx = 0, cy = 0;
+    float tx = 0.0f, ty = 0.0f;
+    d.fin = cell_of(x, cx, tx) & cell_of(y, cy, ty);
+    d.w = 1.0f;
+    if constexpr (STOCH) {
+        uint32_t h0 = pcg(a.key ^ (uint32_t)qi);
+        if constexpr (CUBIC) {
+            d.sx = cx + choose_cubic_m(tx, hash_m(h0));
+            d.sy = cy + choose_cubic_m(ty, hash_m(pcg(h0 + 1u)));
+        } else {
+            d.sx = cx + choose_linear_m(tx, hash_m(h0));
+            d.sy = cy + choose_linear_m(ty, hash_m(pcg(h0 + 1u)));
+        }
+    } else if constexpr (CUBIC) {
+        int ta = tap % 4, tb = tap / 4;
+        Cubic6 wa = cubic6(tx), wb = cubic6(ty);
+        float fa = ta == 0 ? wa.a0 : ta == 1 ? wa.a1 : ta == 2 ? wa.a2 : wa.a3;
+        float fb = tb == 0 ? wb.a0 : tb == 1 ? wb.a1 : tb == 2 ? wb.a2 : wb.a3;
+        d.w = (fa * K6) * (fb * K6);
+        d.sx = cx - 1 + ta;
+        d.sy = cy - 1 + tb;
+    } else {
+        int ta = tap % 2, tb = tap / 2;
+        d.w = (ta ? tx : 1.0f - tx) * (tb ? ty : 1.0f - ty);
+        d.sx = cx + ta;
+        d.sy = cy + tb;
+    }
+    d.sx = clampi(d.sx, a.W - 1);
+    d.sy = clampi(d.sy, a.H - 1);
+    return d;
+}
+
+// The four latent corners of a decode's texel and their bilinear weights.
+__device__ __forceinline__ void latent_corners(const InferArgs& a, const Decode& d, uint32_t (&c)[4], float (&w)[4])
+{
+    float X = ((float)d.sx + 0.5f) * a.rx - 0.5f, Y = ((float)d.sy + 0.5f) * a.ry - 0.5f;
+    float fx0 = floorf(X), fy0 = floorf(Y);
+    float fx = X - fx0, fy = Y - fy0;
+    int x0 = (int)fx0, y0 = (int)fy0;
+    int xa = clampi(x0, a.LW - 1), xb = clampi(x0 + 1, a.LW - 1);
+    int ya = clampi(y0, a.LH - 1), yb = clampi(y0 + 1, a.LH - 1);
+    c[0] = (uint32_t)(ya * a.LW + xa);   // the latent table is below 2 GiB
+    c[1] = (uint32_t)(ya * a.LW + xb);
+    c[2] = (uint32_t)(yb * a.LW + xa);
+    c[3] = (uint32_t)(yb * a.LW + xb);
+    w[0] = (1.0f - fx) * (1.0f - fy);
+    w[1] = fx * (1.0f - fy);
+    w[2] = (1.0f - fx) * fy;
+    w[3] = fx * fy;
+}
+
+// Persistent waves; each handles batches wave, wave + nwaves, ...  The loop is
+// software-pipelined: while batch i runs its MFMAs, the latents of batch
+// i + 1 and the queries of batch i + 2 are in flight.
+template <bool CUBIC, bool STOCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_ntex_infer(InferArgs a)
 {
     constexpr int TAPS = STOCH ? 1 : (CUBIC ? 16 : 4);
     constexpr int QPB = 32 / TAPS;   // queries per 32-decode batch
     const int lane = threadIdx.x % 64, h = lane / 32, jd = lane % 32;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int nwaves = gridDim.x * blockDim.x / 64;
-    const Packed* pk = a.pk;
-    bf16x8 A1[2], A2[2][4], A3[4];
-    f32x16 C1[2], C2[2], C3;
+    const Packed* __restrict__ pk = a.pk;
+    bf16x8 A1[2], A2[2][4], A3[4], AB2[2], AB3, ONES;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
         A1[mb] = pk->a1[mb][lane];
+        AB2[mb] = pk->ab2[mb][lane];
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) A2[mb][kb] = pk->a2[mb][kb][lane];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            C1[mb][r] = pk->c1[mb][lane][r];
-            C2[mb][r] = pk->c2[mb][lane][r];
-        }
     }
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) A3[kb] = pk->a3[kb][lane];
+    AB3 = pk->ab3[lane];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) C3[r] = pk->c3[lane][r];
+    for (int j = 0; j < 8; ++j) ONES[j] = (__bf16)((h == 1 && j < 3) ? 1.0f : 0.0f);   // k-slots 8..10
 
     const int64_t nbatch = ((int64_t)a.n + QPB - 1) / QPB;
-    for (int64_t bt = wave; bt < nbatch; bt += nwaves) {
-        // ---- which query and tap this lane's decode serves
-        const int64_t qi = bt * QPB + jd / TAPS;
-        const int tap = jd % TAPS;
-        const bool live = qi < a.n;
-        float2 uv = live ? reinterpret_cast<const float2*>(a.q)[qi] : make_float2(0.5f, 0.5f);
-        float x = uv.x * (float)a.W - 0.5f, y = uv.y * (float)a.H - 0.5f;
-        int cx = 0, cy = 0;
-        float tx = 0.0f, ty = 0.0f;
-        const bool fin = cell_of(x, cx, tx) & cell_of(y, cy, ty);
-        int sx, sy;
-        float w = 1.0f;
-        if constexpr (STOCH) {
-            uint32_t h0 = pcg(a.key ^ (uint32_t)qi);
-            if constexpr (CUBIC) {
-                sx = cx + choose_cubic_m(tx, hash_m(h0));
-                sy = cy + choose_cubic_m(ty, hash_m(pcg(h0 + 1u)));
-            } else {
-                sx = cx + choose_linear_m(tx, hash_m(h0));
-                sy = cy + choose_linear_m(ty, hash_m(pcg(h0 + 1u)));
-            }
-        } else if constexpr (CUBIC) {
-            int ta = tap % 4, tb = tap / 4;
-            Cubic6 wa = cubic6(tx), wb = cubic6(ty);
-            float fa = ta == 0 ? wa.a0 : ta == 1 ? wa.a1 : ta == 2 ? wa.a2 : wa.a3;
-            float fb = tb == 0 ? wb.a0 : tb == 1 ? wb.a1 : tb == 2 ? wb.a2 : wb.a3;
-            w = (fa * K6) * (fb * K6);
-            sx = cx - 1 + ta;
-            sy = cy - 1 + tb;
-        } else {
-            int ta = tap % 2, tb = tap / 2;
-            w = (ta ? tx : 1.0f - tx) * (tb ? ty : 1.0f - ty);
-            sx = cx + ta;
-            sy = cy + tb;
-        }
-        sx = clampi(sx, a.W - 1);
-        sy = clampi(sy, a.H - 1);
-        // ---- latent interpolation (lanes 0..31 carry the 8 latent channels)
-        bf16x8 B1;
+    const int tap = jd % TAPS;
+    const uint4* L = reinterpret_cast<const uint4*>(a.lat16);
+    auto load_uv = [&](int64_t bt) {
+        int64_t qi = bt * QPB + jd / TAPS;
+        return (bt < nbatch && qi < a.n) ? reinterpret_cast<const float2*>(a.q)[qi] : make_float2(0.5f, 0.5f);
+    };
+    // Every lane loads: the corners are clamped into the table for any query
+    // (padding lanes carry uv = (0.5, 0.5)), and the two lane halves of a
+    // decode read the same addresses, which the wave's request coalesces.
+    auto load_lat = [&](const Decode& d, uint4 (&v)[4], float (&w)[4]) {
+        uint32_t c[4];
+        latent_corners(a, d, c, w);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = L[c[k]];
+    };
+
+    int64_t bt = wave;
+    float2 uv_next = load_uv(bt + nwaves);
+    Decode cur = locate<CUBIC, STOCH>(a, bt * QPB + jd / TAPS, tap, load_uv(bt));
+    uint4 lat_cur[4];
+    float wl_cur[4];
+    load_lat(cur, lat_cur, wl_cur);
+    for (; bt < nbatch; bt += nwaves) {
+        // ---- stage the next two batches
+        const float2 uv_after = load_uv(bt + 2 * (int64_t)nwaves);
+        const Decode nxt = locate<CUBIC, STOCH>(a, (bt + nwaves) * QPB + jd / TAPS, tap, uv_next);
+        uint4 lat_nxt[4];
+        float wl_nxt[4];
+        load_lat(nxt, lat_nxt, wl_nxt);
+        // ---- latent interpolation of this batch (lanes 0..31 carry the 8 channels)
+        bf16x8 B1 = ONES;
         if (h == 0) {
-            float X = ((float)sx + 0.5f) * a.rx - 0.5f, Y = ((float)sy + 0.5f) * a.ry - 0.5f;
-            float fx0 = floorf(X), fy0 = floorf(Y);
-            float fx = X - fx0, fy = Y - fy0;
-            int x0 = (int)fx0, y0 = (int)fy0;
-            int xa = clampi(x0, a.LW - 1), xb = clampi(x0 + 1, a.LW - 1);
-            int ya = clampi(y0, a.LH - 1), yb = clampi(y0 + 1, a.LH - 1);
-            const uint4* L = reinterpret_cast<const uint4*>(a.lat16);
-            uint4 c00 = L[(int64_t)ya * a.LW + xa], c10 = L[(int64_t)ya * a.LW + xb];
-            uint4 c01 = L[(int64_t)yb * a.LW + xa], c11 = L[(int64_t)yb * a.LW + xb];
-            float w00 = (1.0f - fx) * (1.0f - fy), w10 = fx * (1.0f - fy), w01 = (1.0f - fx) * fy, w11 = fx * fy;
-            const uint32_t* p00 = reinterpret_cast<const uint32_t*>(&c00);
-            const uint32_t* p10 = reinterpret_cast<const uint32_t*>(&c10);
-            const uint32_t* p01 = reinterpret_cast<const uint32_t*>(&c01);
-            const uint32_t* p11 = reinterpret_cast<const uint32_t*>(&c11);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 int wsel = j / 2, sh = 16 * (j % 2);
-                float v = w00 * dec_f16((uint16_t)(p00[wsel] >> sh));
-                v = __builtin_fmaf(w10, dec_f16((uint16_t)(p10[wsel] >> sh)), v);
-                v = __builtin_fmaf(w01, dec_f16((uint16_t)(p01[wsel] >> sh)), v);
-                v = __builtin_fmaf(w11, dec_f16((uint16_t)(p11[wsel] >> sh)), v);
+                const uint32_t* p0 = reinterpret_cast<const uint32_t*>(&lat_cur[0]);
+                const uint32_t* p1 = reinterpret_cast<const uint32_t*>(&lat_cur[1]);
+                const uint32_t* p2 = reinterpret_cast<const uint32_t*>(&lat_cur[2]);
+                const uint32_t* p3 = reinterpret_cast<const uint32_t*>(&lat_cur[3]);
+                float v = wl_cur[0] * dec_f16((uint16_t)(p0[wsel] >> sh));
+                v = __builtin_fmaf(wl_cur[1], dec_f16((uint16_t)(p1[wsel] >> sh)), v);
+                v = __builtin_fmaf(wl_cur[2], dec_f16((uint16_t)(p2[wsel] >> sh)), v);
+                v = __builtin_fmaf(wl_cur[3], dec_f16((uint16_t)(p3[wsel] >> sh)), v);
                 B1[j] = (__bf16)v;
             }
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) B1[j] = (__bf16)0.0f;
         }
-        // ---- layer 1: 64 x 16 (K padded) by 16 x 32
+        const f32x16 Z = {};
+        // ---- layer 1: 64 x 16 by 16 x 32 (k 0..7 latents, 8..10 bias terms)
         f32x16 D1[2];
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) D1[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[mb], B1, C1[mb], 0, 0, 0);
+        for (int mb = 0; mb < 2; ++mb) D1[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[mb], B1, Z, 0, 0, 0);
         bf16x8 B2[4];
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) B2[kb] = relu_bf16(D1[kb / 2], 8 * (kb % 2));
-        // ---- layer 2: 64 x 64 by 64 x 32
+        // ---- layer 2: bias, then 64 x 64 by 64 x 32
         f32x16 D2[2];
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
-            D2[mb] = C2[mb];
+            D2[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AB2[mb], ONES, Z, 0, 0, 0);
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb)
                 D2[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2[mb][kb], B2[kb], D2[mb], 0, 0, 0);
@@ -422,25 +524,33 @@ __global__ __launch_bounds__(256) void k_ntex_infer(InferArgs a)
         bf16x8 B3[4];
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) B3[kb] = relu_bf16(D2[kb / 2], 8 * (kb % 2));
-        // ---- layer 3: 8 (of 32) x 64 by 64 x 32
-        f32x16 D3 = C3;
+        // ---- layer 3: bias, then 8 (of 32) x 64 by 64 x 32
+        f32x16 D3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AB3, ONES, Z, 0, 0, 0);
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) D3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A3[kb], B3[kb], D3, 0, 0, 0);
         // ---- registers 0..3 of this lane: channels 4h..4h+3 of decode jd
-        float o[4] = {D3[0] * w, D3[1] * w, D3[2] * w, D3[3] * w};
+        float o[4] = {D3[0] * cur.w, D3[1] * cur.w, D3[2] * cur.w, D3[3] * cur.w};
 #pragma unroll
         for (int off = 1; off < TAPS; off <<= 1) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) o[c] += __shfl_xor(o[c], off, 64);
         }
-        if (live && tap == 0) {
-            float4 v = fin ? make_float4(o[0], o[1], o[2], o[3])
-                           : make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
-            reinterpret_cast<float4*>(a.out)[qi * 2 + h] = v;
+        if (cur.live && tap == 0) {
+            float4 v = cur.fin ? make_float4(o[0], o[1], o[2], o[3])
+                               : make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""),
+                                             __builtin_nanf(""));
+            reinterpret_cast<float4*>(a.out)[cur.qi * 2 + h] = v;
             if (STOCH && a.idx && h == 0) {
-                a.idx[2 * qi] = fin ? sx : BAD_INDEX;
-                a.idx[2 * qi + 1] = fin ? sy : BAD_INDEX;
+                a.idx[2 * cur.qi] = cur.fin ? cur.sx : BAD_INDEX;
+                a.idx[2 * cur.qi + 1] = cur.fin ? cur.sy : BAD_INDEX;
             }
+        }
+        cur = nxt;
+        uv_next = uv_after;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lat_cur[k] = lat_nxt[k];
+            wl_cur[k] = wl_nxt[k];
         }
     }
 }
@@ -454,6 +564,21 @@ uint16_t f2bf16_host(float f)
     return (uint16_t)(b >> 16);
 }
 
+// Exact split of an fp32 value into three bf16 terms: each term takes the
+// leading 8 significant bits of what the previous ones left, and 24 bits of
+// significand are used up after three.
+void split3_bf16(float v, uint16_t (&t)[3])
+{
+    float rest = v;
+    for (int i = 0; i < 3; ++i) {
+        t[i] = f2bf16_host(rest);
+        uint32_t b = (uint32_t)t[i] << 16;
+        float f;
+        memcpy(&f, &b, 4);
+        rest -= f;
+    }
+}
+
 void pack_weights(const float* mlp, Packed* pk)
 {
     memset(pk, 0, sizeof(Packed));
@@ -461,26 +586,28 @@ void pack_weights(const float* mlp, Packed* pk)
         uint16_t u = f2bf16_host(v);
         memcpy(reinterpret_cast<char*>(&dst) + 2 * j, &u, 2);
     };
+    auto put_bias = [](bf16x8& dst, float v) {   // k-slots 8..10: lanes 32..63, j = 0..2
+        uint16_t t[3];
+        split3_bf16(v, t);
+        memcpy(&dst, t, sizeof t);
+    };
     for (int lane = 0; lane < 64; ++lane) {
         int h = lane / 32, m = lane % 32;
         for (int mb = 0; mb < 2; ++mb) {
-            for (int j = 0; j < 8; ++j)
-                put(pk->a1[mb][lane], j, h == 0 ? mlp[OFF_W1 + (32 * mb + m) * NL + j] : 0.0f);
+            if (h == 0)
+                for (int j = 0; j < 8; ++j) put(pk->a1[mb][lane], j, mlp[OFF_W1 + (32 * mb + m) * NL + j]);
+            else {
+                put_bias(pk->a1[mb][lane], mlp[OFF_B1 + 32 * mb + m]);
+                put_bias(pk->ab2[mb][lane], mlp[OFF_B2 + 32 * mb + m]);
+            }
             for (int kb = 0; kb < 4; ++kb)
                 for (int j = 0; j < 8; ++j)
                     put(pk->a2[mb][kb][lane], j, mlp[OFF_W2 + (32 * mb + m) * NH + hidden_of_slot(kb, h, j)]);
-            for (int r = 0; r < 16; ++r) {
-                pk->c1[mb][lane][r] = mlp[OFF_B1 + row_of_acc(mb, h, r)];
-                pk->c2[mb][lane][r] = mlp[OFF_B2 + row_of_acc(mb, h, r)];
-            }
         }
         for (int kb = 0; kb < 4; ++kb)
             for (int j = 0; j < 8; ++j)
                 put(pk->a3[kb][lane], j, m < NO ? mlp[OFF_W3 + m * NH + hidden_of_slot(kb, h, j)] : 0.0f);
-        for (int r = 0; r < 16; ++r) {
-            int c = row_of_acc(0, h, r);
-            pk->c3[lane][r] = c < NO ? mlp[OFF_B3 + c] : 0.0f;
-        }
+        if (h == 1 && m < NO) put_bias(pk->ab3[lane], mlp[OFF_B3 + m]);
     }
 }
 
@@ -556,7 +683,8 @@ stf_status ensure_partial(stf_neural* nt, int32_t blocks)
         (void)hipFree(nt->partial);
         nt->partial = nullptr;
     }
-    stf_status s = dalloc((void**)&nt->partial, (size_t)blocks * PSTRIDE * 4, "gradient partials");
+    size_t groups = ((size_t)blocks + RGROUP - 1) / RGROUP;
+    stf_status s = dalloc((void**)&nt->partial, ((size_t)blocks + groups) * PSTRIDE * 4, "gradient partials");
     nt->partial_blocks = s == STF_OK ? blocks : 0;
     return s;
 }
@@ -585,7 +713,11 @@ hipError_t run_fwd_bwd(stf_neural* nt, const float* target, const int32_t* pos, 
     a.g_lat = nt->g_lat;
     a.partial = nt->partial;
     hipLaunchKernelGGL(k_ntex_train, dim3(blocks), dim3(TBLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_ntex_reduce, dim3((PSTRIDE + 255) / 256), dim3(256), 0, s, nt->partial, blocks, nt->g_mlp,
+    int ngroups = (blocks + RGROUP - 1) / RGROUP;
+    float* group_sums = nt->partial + (int64_t)nt->partial_blocks * PSTRIDE;
+    hipLaunchKernelGGL(k_ntex_reduce1, dim3((PSTRIDE + 255) / 256, ngroups), dim3(256), 0, s, nt->partial, blocks,
+                       group_sums);
+    hipLaunchKernelGGL(k_ntex_reduce2, dim3((PSTRIDE + 255) / 256), dim3(256), 0, s, group_sums, ngroups, nt->g_mlp,
                        loss, 1.0f / (8.0f * (float)B));
     return hipGetLastError();
 }
@@ -802,7 +934,9 @@ stf_status stf_ntex_filter(const stf_neural* nt, const float* queries_dev, int64
     a.idx = out_index_dev;
     int taps = mode == STF_STOCHASTIC ? 1 : (filter == STF_CUBIC_BSPLINE ? 16 : 4);
     int64_t batches = (n * taps + 31) / 32;
-    int64_t waves = batches < 2048 ? batches : 2048;   // persistent waves: the weights load once per wave
+    // Persistent waves, one resident set (3 per SIMD on 256 CUs): the weights
+    // load once per wave.
+    int64_t waves = batches < 3072 ? batches : 3072;
     dim3 grid((unsigned)((waves + 3) / 4)), block(256);
     hipStream_t st = (hipStream_t)hip_stream;
     bool cubic = filter == STF_CUBIC_BSPLINE;
