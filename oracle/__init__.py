@@ -20,7 +20,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 # storage formats / filters / modes (the oracle's own numbering)
 F32, F16, BF16, FP8_E4M3, U8 = 0, 1, 2, 3, 4
-LINEAR, CUBIC = 0, 1
+LINEAR, CUBIC, KEYS, MITCHELL = 0, 1, 2, 3
+POSITIVIZED = (KEYS, MITCHELL)
 DET, STOCH, STOCH_REUSE = 0, 1, 2
 BAD_INDEX = -(2 ** 31)
 
@@ -50,6 +51,18 @@ def _declare(L):
     L.orc_kernel_tent.argtypes, L.orc_kernel_tent.restype = [dbl], dbl
     L.orc_kernel_bspline.argtypes, L.orc_kernel_bspline.restype = [dbl], dbl
     L.orc_axis_weights.argtypes, L.orc_axis_weights.restype = [i32, dbl, vp], None
+    L.orc_kernel_keys.argtypes, L.orc_kernel_keys.restype = [dbl], dbl
+    L.orc_kernel_mitchell.argtypes, L.orc_kernel_mitchell.restype = [dbl], dbl
+    L.orc_kernel.argtypes, L.orc_kernel.restype = [i32, dbl], dbl
+    L.orc_interp_weights32.argtypes, L.orc_interp_weights32.restype = [i32, C.c_float, vp], None
+    L.orc_cumulative_choice.argtypes, L.orc_cumulative_choice.restype = [vp, i32, C.c_float], i32
+    L.orc_positivized_taps.argtypes = [i32, i32, vp, u64, u32, vp, vp]
+    L.orc_positivized_taps.restype = i32
+    L.orc_positivized_masses.argtypes, L.orc_positivized_masses.restype = [i32, i32, vp, vp, vp], None
+    L.orc_positivized_wrs2d.argtypes = [i32, dbl, dbl, dbl, vp, vp]
+    L.orc_positivized_wrs2d.restype = i32
+    L.orc_filter2d_moments.argtypes = [vp, i32, i32, i32, i32, vp, i64, i32, vp, vp, i32]
+    L.orc_filter2d_moments.restype = i32
     L.orc_select.argtypes, L.orc_select.restype = [i32, C.c_float, C.c_float], i32
     L.orc_max_threads.argtypes, L.orc_max_threads.restype = [], i32
     L.orc_cubic_breakpoints.argtypes, L.orc_cubic_breakpoints.restype = [C.c_float, vp], None
@@ -123,6 +136,54 @@ def kernel_bspline(d: float) -> float:
     return lib().orc_kernel_bspline(d)
 
 
+def kernel(filt: int, d: float) -> float:
+    return lib().orc_kernel(filt, d)
+
+
+def interp_weights32(filt: int, t: float) -> np.ndarray:
+    """Pinned binary32 per-axis weights of an interpolating cubic, scaled
+    (Keys by 2, Mitchell by 18)."""
+    w = np.zeros(4, np.float32)
+    lib().orc_interp_weights32(filt, float(np.float32(t)), _p(w))
+    return w
+
+
+def cumulative_choice(masses, u: float) -> int:
+    m = np.ascontiguousarray(masses, np.float32)
+    return lib().orc_cumulative_choice(_p(m), m.size, float(np.float32(u)))
+
+
+def positivized_taps(filt: int, t, seed: int, qid: int):
+    """Tap offsets (-1..2 per axis) of the positive and negative draws and
+    whether a negative tap exists."""
+    t = np.ascontiguousarray(t, np.float32)
+    D = t.size
+    op = np.zeros(D, np.int32)
+    on = np.zeros(D, np.int32)
+    neg = lib().orc_positivized_taps(filt, D, _p(t), seed, qid & 0xFFFFFFFF, _p(op), _p(on))
+    return op, on, bool(neg)
+
+
+def positivized_masses(filt: int, t):
+    t = np.ascontiguousarray(t, np.float64)
+    sp, sn = C.c_double(), C.c_double()
+    lib().orc_positivized_masses(filt, t.size, _p(t), C.byref(sp), C.byref(sn))
+    return sp.value, sn.value
+
+
+def positivized_wrs2d(filt: int, tx: float, ty: float, u: float):
+    op = np.zeros(2, np.int32)
+    on = np.zeros(2, np.int32)
+    neg = lib().orc_positivized_wrs2d(filt, float(tx), float(ty), float(u), _p(op), _p(on))
+    return op, on, bool(neg)
+
+
+def index_width(filt: int, dims: int) -> int:
+    """Index entries per stochastic query: the tap, or for positivized filters
+    the positive tap followed by the negative tap."""
+    return 2 * dims if filt in POSITIVIZED else dims
+
+
 def axis_weights(filt: int, t: float) -> np.ndarray:
     w = np.zeros(4, np.float64)
     lib().orc_axis_weights(filt, float(t), _p(w))
@@ -168,11 +229,24 @@ def filter2d(tex: np.ndarray, fmt: int, uv: np.ndarray, filt: int, mode: int, se
     uv = np.ascontiguousarray(uv, dtype=np.float32)
     n = uv.shape[0]
     out = np.empty((n, Ch), np.float64)
-    idx = np.empty((n, 2), np.int32) if (want_index and mode != DET) else None
+    idx = np.empty((n, index_width(filt, 2)), np.int32) if (want_index and mode != DET) else None
     rc = lib().orc_filter2d(_p(tex), W, H, Ch, fmt, _p(uv), n, filt, mode, seed, _p(out), _p(idx), nthreads)
     if rc != 0:
         raise ValueError("orc_filter2d rejected its arguments")
     return out, idx
+
+
+def moments2d(tex: np.ndarray, fmt: int, uv: np.ndarray, filt: int, nthreads: int = 0):
+    """Exact mean and variance (n, C) of the stochastic estimator."""
+    tex = np.ascontiguousarray(tex)
+    H, W, Ch = tex.shape
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    n = uv.shape[0]
+    mean = np.empty((n, Ch), np.float64)
+    var = np.empty((n, Ch), np.float64)
+    if lib().orc_filter2d_moments(_p(tex), W, H, Ch, fmt, _p(uv), n, filt, _p(mean), _p(var), nthreads) != 0:
+        raise ValueError("orc_filter2d_moments rejected its arguments")
+    return mean, var
 
 
 def filter2d_brute(tex: np.ndarray, fmt: int, uv: np.ndarray, filt: int) -> np.ndarray:
@@ -216,7 +290,7 @@ class Grid:
         p = np.ascontiguousarray(p, dtype=np.float32)
         n = p.shape[0]
         out = np.empty(n, np.float64)
-        idx = np.empty((n, 3), np.int32) if (want_index and mode != DET) else None
+        idx = np.empty((n, index_width(filt, 3)), np.int32) if (want_index and mode != DET) else None
         rc = lib().orc_filter3d(self._h, _p(p), n, filt, mode, seed, _p(out), _p(idx), nthreads)
         if rc != 0:
             raise ValueError("orc_filter3d failed")
@@ -230,7 +304,7 @@ class Grid:
         qids = np.ascontiguousarray(qids, dtype=np.int64)
         m = qids.shape[0]
         out = np.empty(m, np.float64)
-        idx = np.empty((m, 3), np.int32) if mode != DET else None
+        idx = np.empty((m, index_width(filt, 3)), np.int32) if mode != DET else None
         rc = lib().orc_filter3d_at(self._h, _p(p), _p(qids), m, filt, mode, seed, _p(out), _p(idx), nthreads)
         if rc != 0:
             raise ValueError("orc_filter3d_at failed")
@@ -247,7 +321,8 @@ class Grid:
         n = p.shape[0]
         mean = np.empty(n, np.float64)
         var = np.empty(n, np.float64)
-        lib().orc_filter3d_moments(self._h, _p(p), n, filt, _p(mean), _p(var), nthreads)
+        if lib().orc_filter3d_moments(self._h, _p(p), n, filt, _p(mean), _p(var), nthreads) != 0:
+            raise ValueError("orc_filter3d_moments rejected its arguments")
         return mean, var
 
 

@@ -35,6 +35,10 @@
  *     tests only).
  *   - 2D addressing clamps each tap to the texture; 3D addressing returns the
  *     grid's background value outside the domain and in inactive leaves.
+ *   - The interpolating cubics (negative lobes) are the paper's cubic
+ *     polynomial kernel K_3 with a = -1/2 ("Keys") and the Mitchell-Netravali
+ *     cubic with B = C = 1/3; both are estimated by positivization with one
+ *     tap drawn from the positive and one from the negative weights.
  */
 #include <math.h>
 #include <stdint.h>
@@ -47,7 +51,7 @@
 /* storage formats */
 enum { ORC_F32 = 0, ORC_F16 = 1, ORC_BF16 = 2, ORC_FP8_E4M3 = 3, ORC_U8 = 4 };
 /* filters and modes */
-enum { ORC_LINEAR = 0, ORC_CUBIC = 1 };
+enum { ORC_LINEAR = 0, ORC_CUBIC = 1, ORC_KEYS = 2, ORC_MITCHELL = 3 };
 enum { ORC_DET = 0, ORC_STOCH = 1, ORC_STOCH_REUSE = 2 };
 
 #define ORC_BAD_INDEX ((int32_t)0x80000000)
@@ -149,15 +153,57 @@ double orc_kernel_bspline(double d)   /* K_bs, Eq. cubic-bspline */
     return 0.0;
 }
 
+/* The cubic polynomial kernel K_3 of the supplement ("Filter Kernels") with
+ * the free parameter a = -1/2 that the paper recommends: the interpolating
+ * (negative lobe) cubic of its real-time results. */
+double orc_kernel_keys(double d)
+{
+    const double a = -0.5;
+    d = fabs(d);
+    if (d < 1.0) return (a + 2.0) * d * d * d - (a + 3.0) * d * d + 1.0;
+    if (d < 2.0) return a * d * d * d - 5.0 * a * d * d + 8.0 * a * d - 4.0 * a;
+    return 0.0;
+}
+
+/* Mitchell and Netravali's cubic (SIGGRAPH 1988) with B = C = 1/3, the other
+ * filter the name "Mitchell" can mean; it also has negative lobes. */
+double orc_kernel_mitchell(double d)
+{
+    const double B = 1.0 / 3.0, C = 1.0 / 3.0;
+    d = fabs(d);
+    if (d < 1.0) return ((12.0 - 9.0 * B - 6.0 * C) * d * d * d + (-18.0 + 12.0 * B + 6.0 * C) * d * d + (6.0 - 2.0 * B)) / 6.0;
+    if (d < 2.0)
+        return ((-B - 6.0 * C) * d * d * d + (6.0 * B + 30.0 * C) * d * d + (-12.0 * B - 48.0 * C) * d + (8.0 * B + 24.0 * C)) / 6.0;
+    return 0.0;
+}
+
+/* The kernel of a filter, evaluated at a signed distance (brute-force paths). */
+double orc_kernel(int filter, double d)
+{
+    switch (filter) {
+    case ORC_LINEAR: return orc_kernel_tent(d);
+    case ORC_CUBIC: return orc_kernel_bspline(d);
+    case ORC_KEYS: return orc_kernel_keys(d);
+    case ORC_MITCHELL: return orc_kernel_mitchell(d);
+    }
+    return NAN;
+}
+
 /* Per-axis weights of the taps of cell i for the fractional offset t.
  * Linear: taps i, i+1 with (1-t, t) -- the lerp of section "Linear Filters".
  * Cubic:  taps i-1..i+2 with the B-spline weights of the bicubic listing,
  * i.e. K_bs(t+1), K_bs(t), K_bs(1-t), K_bs(2-t); the first is written as
- * (1-t)^3/6 rather than the listing's expanded polynomial (same value). */
+ * (1-t)^3/6 rather than the listing's expanded polynomial (same value).
+ * Keys / Mitchell: taps i-1..i+2 with the kernel at the same four distances. */
 void orc_axis_weights(int filter, double t, double w[4])
 {
     if (filter == ORC_LINEAR) {
         w[0] = 1.0 - t; w[1] = t; w[2] = 0.0; w[3] = 0.0;
+    } else if (filter == ORC_KEYS || filter == ORC_MITCHELL) {
+        w[0] = orc_kernel(filter, t + 1.0);
+        w[1] = orc_kernel(filter, t);
+        w[2] = orc_kernel(filter, 1.0 - t);
+        w[3] = orc_kernel(filter, 2.0 - t);
     } else {
         double t2 = t * t, t3 = t2 * t, s = 1.0 - t;
         w[0] = s * s * s / 6.0;
@@ -271,6 +317,173 @@ static int orc_select_reuse(int filter, float t, float* u)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Positivization (section "Sampling Techniques", paragraph on               */
+/* positivization; supplement, "The interpolating (negative lobe) bicubic    */
+/* filter").  The tensor-product weights w of an interpolating cubic are     */
+/* split into the positive weights w+ and the magnitudes w- of the negative  */
+/* ones, with masses S+ = sum w+ and S- = sum w-.  One tap j+ is drawn with  */
+/* probability w+_j / S+ and, independently, one tap j- with probability     */
+/* w-_j / S-; the estimate is                                                */
+/*     <F> = S+ t(j+) - S- t(j-),                                            */
+/* whose mean is sum w t (the estimator of the positivization paragraph with */
+/* both sums weighted, as the paper prescribes for a normalised filter).     */
+/* When S- = 0 there is no negative tap.                                     */
+/*                                                                           */
+/* Drawing (pinned binary32, decisions only).  Per axis the four weights are */
+/* split into positive parts p_k and negative parts n_k with masses P and N. */
+/* A tap of the tensor product is positive exactly when an even number of    */
+/* its axis factors is negative, so w+ is the sum over the sign patterns     */
+/* with an even number of N axes of the products of the chosen per-axis      */
+/* parts, and w- the same over the odd patterns.  A draw from w+ picks a     */
+/* pattern in proportion to the product of its per-axis masses and then, on  */
+/* each axis, a tap in proportion to that axis's chosen part.                */
+/*   - Patterns are numbered by their bits (bit a set = axis a takes its      */
+/*     negative part) and visited in increasing order; a pattern's mass is   */
+/*     the product of the axis masses from axis 0 up.                        */
+/*   - Every choice among masses m_0..m_{k-1} uses one uniform u and the      */
+/*     cumulative rule: T = u * M with M = ((m_0 + m_1) + ...) + m_{k-1};     */
+/*     the choice is the number of partial sums m_0 + ... + m_i (i < k-1)     */
+/*     that are <= T, lowered to the last nonzero mass if it lands past it.   */
+/*   - Uniforms: the positive draw takes axes 0..D-1 and 4 (pattern), the     */
+/*     negative draw axes 5..5+D-1 and 8 (pattern).                          */
+/* Per-axis weights in binary32 (scaled: Keys by 2, Mitchell by 18), in      */
+/* factored forms whose relative error stays small near their zeros, with    */
+/* s = 1 - t and every operation rounded once:                               */
+/*   Keys:      2w0 = -((t*s)*s)              2w3 = -((t*t)*s)                */
+/*              2w1 = s*(2 + t*(2 - 3*t))     2w2 = t*(2 + s*(2 - 3*s))       */
+/*   Mitchell: 18w0 = (s*s)*fma(-7, t, 1)    18w3 = (t*t)*fma(-7, s, 1)       */
+/*             18w1 = 1 + s*(9 + s*(27 - 21*s))                              */
+/*             18w2 = 1 + t*(9 + t*(27 - 21*t))                              */
+/* (These are the kernels at distances t+1, t, 1-t, 2-t, factored.)          */
+/* ------------------------------------------------------------------------ */
+void orc_interp_weights32(int filter, float t, float w[4])
+{
+    float s = 1.0f - t;
+    if (filter == ORC_KEYS) {
+        w[0] = -((t * s) * s);
+        w[1] = s * (2.0f + t * (2.0f - 3.0f * t));
+        w[2] = t * (2.0f + s * (2.0f - 3.0f * s));
+        w[3] = -((t * t) * s);
+    } else {
+        w[0] = (s * s) * fmaf(-7.0f, t, 1.0f);
+        w[1] = 1.0f + s * (9.0f + s * (27.0f - 21.0f * s));
+        w[2] = 1.0f + t * (9.0f + t * (27.0f - 21.0f * t));
+        w[3] = (t * t) * fmaf(-7.0f, s, 1.0f);
+    }
+}
+
+/* The cumulative rule over k masses (see above). */
+int orc_cumulative_choice(const float* m, int k, float u)
+{
+    float total = 0.0f;
+    int last = 0;
+    for (int i = 0; i < k; ++i) {
+        total += m[i];
+        if (m[i] > 0.0f) last = i;
+    }
+    float T = u * total, c = 0.0f;
+    int j = 0;
+    for (int i = 0; i < k - 1; ++i) {
+        c += m[i];
+        j += (T >= c);
+    }
+    return j > last ? last : j;
+}
+
+/* Tap offsets (relative to the cell, -1..2 per axis) of the positive draw
+ * and, when the negative weights have mass, the negative draw; returns
+ * whether a negative tap was drawn. */
+int orc_positivized_taps(int filter, int D, const float* t, uint64_t seed, uint32_t qid, int* off_pos, int* off_neg)
+{
+    float part[2][3][4], mass[2][3];   /* [positive/negative][axis][tap] */
+    for (int a = 0; a < D; ++a) {
+        float w[4];
+        orc_interp_weights32(filter, t[a], w);
+        mass[0][a] = mass[1][a] = 0.0f;
+        for (int k = 0; k < 4; ++k) {
+            part[0][a][k] = w[k] > 0.0f ? w[k] : 0.0f;
+            part[1][a][k] = w[k] < 0.0f ? -w[k] : 0.0f;
+            mass[0][a] += part[0][a][k];
+            mass[1][a] += part[1][a][k];
+        }
+    }
+    int has_neg = 0;
+    for (int set = 0; set < 2; ++set) {   /* 0: positive (even patterns), 1: negative (odd) */
+        int pat[4], np = 0;
+        float pm[4];
+        for (int b = 0; b < (1 << D); ++b) {
+            int odd = __builtin_popcount((unsigned)b) & 1;
+            if (odd != set) continue;
+            float m = mass[b & 1][0];
+            for (int a = 1; a < D; ++a) m = m * mass[(b >> a) & 1][a];
+            pat[np] = b;
+            pm[np++] = m;
+        }
+        float total = 0.0f;
+        for (int i = 0; i < np; ++i) total += pm[i];
+        if (set == 1 && !(total > 0.0f)) break;
+        uint32_t ubase = set == 0 ? 0u : 5u, ucomp = set == 0 ? 4u : 8u;
+        int b = pat[orc_cumulative_choice(pm, np, orc_uniform(seed, qid, ucomp))];
+        int* off = set == 0 ? off_pos : off_neg;
+        for (int a = 0; a < D; ++a)
+            off[a] = orc_cumulative_choice(part[(b >> a) & 1][a], 4, orc_uniform(seed, qid, ubase + (uint32_t)a)) - 1;
+        if (set == 1) has_neg = 1;
+    }
+    return has_neg;
+}
+
+/* Exact masses S+ and S- of the tensor-product weights (binary64, from the
+ * exact fractional offsets). */
+void orc_positivized_masses(int filter, int D, const double* t, double* Sp, double* Sn)
+{
+    double w[3][4];
+    for (int a = 0; a < D; ++a) orc_axis_weights(filter, t[a], w[a]);
+    *Sp = *Sn = 0.0;
+    int ntap = 1;
+    for (int a = 0; a < D; ++a) ntap *= 4;
+    for (int k = 0; k < ntap; ++k) {
+        double wt = 1.0;
+        for (int a = 0, r = k; a < D; ++a, r /= 4) wt *= w[a][r % 4];
+        if (wt > 0.0) *Sp += wt;
+        else *Sn -= wt;
+    }
+}
+
+/* The paper's own sampler for the interpolating bicubic, for distribution
+ * tests only: the 16 weights are visited row by row (y outer, x inner) and
+ * fed to two weighted reservoirs, one per sign, that share one uniform
+ * re-used by the warping of Eq. uniform-sample-reuse.  Zero weights are not
+ * offered to either reservoir (the first one would divide zero by zero).
+ * Binary64 throughout.  Returns whether a negative tap was chosen. */
+int orc_positivized_wrs2d(int filter, double tx, double ty, double u, int* off_pos, int* off_neg)
+{
+    double wx[4], wy[4], sum[2] = {0.0, 0.0};
+    int chosen[2][2] = {{0, 0}, {0, 0}}, any[2] = {0, 0};
+    orc_axis_weights(filter, tx, wx);
+    orc_axis_weights(filter, ty, wy);
+    for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 4; ++a) {
+            double w = wx[a] * wy[b];
+            if (w == 0.0) continue;
+            int r = w < 0.0;
+            sum[r] += fabs(w);
+            double p = fabs(w) / sum[r];
+            if (u < p) {
+                chosen[r][0] = a - 1;
+                chosen[r][1] = b - 1;
+                any[r] = 1;
+                u = u / p;
+            } else {
+                u = (u - p) / (1.0 - p);
+            }
+            if (!(u < 1.0)) u = 0x1.fffffffffffffp-1;
+        }
+    off_pos[0] = chosen[0][0]; off_pos[1] = chosen[0][1];
+    off_neg[0] = chosen[1][0]; off_neg[1] = chosen[1][1];
+    return any[1];
+}
+
+/* ------------------------------------------------------------------------ */
 /* 2D textures: row-major texels, channels interleaved; tap indices clamped. */
 /* ------------------------------------------------------------------------ */
 static int orc_clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -295,18 +508,28 @@ static void orc_nan_out(double* out, int C, int32_t* idx, int dims)
     if (idx) for (int a = 0; a < dims; ++a) idx[a] = ORC_BAD_INDEX;
 }
 
+static int orc_positivized(int filter) { return filter == ORC_KEYS || filter == ORC_MITCHELL; }
+
+/* Index entries per query: the chosen tap, or for positivized filters the
+ * positive tap followed by the negative one. */
+static int orc_index_width(int filter, int dims) { return orc_positivized(filter) ? 2 * dims : dims; }
+
 /* One 2D query.  mode: ORC_DET (separable weighted sum, Eq. filtered-texture
  * with the tensor-product weights), ORC_STOCH (one tap per Eq.
- * stochastic-sum), ORC_STOCH_REUSE (paper listing sampler). */
+ * stochastic-sum, or the two taps of positivization), ORC_STOCH_REUSE (the
+ * paper's listing samplers). */
 static void orc_query2d(const void* tex, int W, int H, int C, int fmt, const float* uv,
                         int filter, int mode, uint64_t seed, uint32_t qid, double* out, int32_t* idx)
 {
     float x, y, tx, ty;
     int ix, iy;
     orc_raster2d(uv, W, H, &x, &y);
-    if (!orc_cell(x, &ix, &tx) || !orc_cell(y, &iy, &ty)) { orc_nan_out(out, C, idx, 2); return; }
-    int base = (filter == ORC_CUBIC) ? -1 : 0;
-    int ntap = (filter == ORC_CUBIC) ? 4 : 2;
+    if (!orc_cell(x, &ix, &tx) || !orc_cell(y, &iy, &ty)) {
+        orc_nan_out(out, C, idx, orc_index_width(filter, 2));
+        return;
+    }
+    int base = (filter == ORC_LINEAR) ? 0 : -1;
+    int ntap = (filter == ORC_LINEAR) ? 2 : 4;
     if (mode == ORC_DET) {
         double wx[4], wy[4];
         orc_axis_weights(filter, (double)x - floor((double)x), wx);
@@ -320,6 +543,29 @@ static void orc_query2d(const void* tex, int W, int H, int C, int fmt, const flo
                 acc += wy[b] * row;
             }
             out[c] = acc;
+        }
+        return;
+    }
+    if (orc_positivized(filter)) {
+        int op[2], on[2], neg;
+        float t2[2] = {tx, ty};
+        if (mode == ORC_STOCH)
+            neg = orc_positivized_taps(filter, 2, t2, seed, qid, op, on);
+        else
+            neg = orc_positivized_wrs2d(filter, (double)tx, (double)ty, (double)orc_uniform(seed, qid, 0), op, on);
+        double tt[2] = {(double)tx, (double)ty}, Sp, Sn;
+        orc_positivized_masses(filter, 2, tt, &Sp, &Sn);
+        int px = orc_clampi(ix + op[0], 0, W - 1), py = orc_clampi(iy + op[1], 0, H - 1);
+        int nx = orc_clampi(ix + on[0], 0, W - 1), ny = orc_clampi(iy + on[1], 0, H - 1);
+        for (int c = 0; c < C; ++c) {
+            double v = Sp * orc_texel2d(tex, W, H, C, fmt, px, py, c);
+            if (neg) v -= Sn * orc_texel2d(tex, W, H, C, fmt, nx, ny, c);
+            out[c] = v;
+        }
+        if (idx) {
+            idx[0] = px; idx[1] = py;
+            idx[2] = neg ? nx : ORC_BAD_INDEX;
+            idx[3] = neg ? ny : ORC_BAD_INDEX;
         }
         return;
     }
@@ -352,13 +598,13 @@ int orc_max_threads(void) { return orc_threads(0); }
 int orc_filter2d(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n,
                  int filter, int mode, uint64_t seed, double* out, int32_t* idx, int nthreads)
 {
-    if (W <= 0 || H <= 0 || C <= 0 || C > 4 || n < 0) return -1;
-    int nt = orc_threads(nthreads);
+    if (W <= 0 || H <= 0 || C <= 0 || C > 4 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
+    int nt = orc_threads(nthreads), iw = orc_index_width(filter, 2);
     (void)nt;
 #pragma omp parallel for schedule(static) num_threads(nt)
     for (int64_t q = 0; q < n; ++q)
         orc_query2d(tex, W, H, C, fmt, uv + 2 * q, filter, mode, seed, (uint32_t)q,
-                    out + q * C, idx ? idx + 2 * q : NULL);
+                    out + q * C, idx ? idx + iw * q : NULL);
     return 0;
 }
 
@@ -379,9 +625,7 @@ int orc_filter2d_brute(const void* tex, int W, int H, int C, int fmt, const floa
             double acc = 0.0;
             for (int b = iy - 2; b <= iy + 3; ++b)
                 for (int a = ix - 2; a <= ix + 3; ++a) {
-                    double w = (filter == ORC_CUBIC)
-                        ? orc_kernel_bspline((double)x - a) * orc_kernel_bspline((double)y - b)
-                        : orc_kernel_tent((double)x - a) * orc_kernel_tent((double)y - b);
+                    double w = orc_kernel(filter, (double)x - a) * orc_kernel(filter, (double)y - b);
                     if (w != 0.0) acc += w * orc_texel2d(tex, W, H, C, fmt, a, b, c);
                 }
             o[c] = acc;
@@ -455,9 +699,9 @@ static void orc_query3d(const orc_grid* g, const float* p, int filter, int mode,
     int i[3];
     float t[3];
     for (int a = 0; a < 3; ++a)
-        if (!orc_cell(p[a], &i[a], &t[a])) { orc_nan_out(out, 1, idx, 3); return; }
-    int base = (filter == ORC_CUBIC) ? -1 : 0;
-    int ntap = (filter == ORC_CUBIC) ? 4 : 2;
+        if (!orc_cell(p[a], &i[a], &t[a])) { orc_nan_out(out, 1, idx, orc_index_width(filter, 3)); return; }
+    int base = (filter == ORC_LINEAR) ? 0 : -1;
+    int ntap = (filter == ORC_LINEAR) ? 2 : 4;
     if (mode == ORC_DET) {
         double w[3][4];
         for (int a = 0; a < 3; ++a) orc_axis_weights(filter, (double)p[a] - floor((double)p[a]), w[a]);
@@ -475,6 +719,21 @@ static void orc_query3d(const orc_grid* g, const float* p, int filter, int mode,
         out[0] = acc;
         return;
     }
+    if (orc_positivized(filter)) {
+        int op[3], on[3];
+        int neg = orc_positivized_taps(filter, 3, t, seed, qid, op, on);
+        double tt[3] = {(double)t[0], (double)t[1], (double)t[2]}, Sp, Sn;
+        orc_positivized_masses(filter, 3, tt, &Sp, &Sn);
+        double v = Sp * orc_grid_texel(g, i[0] + op[0], i[1] + op[1], i[2] + op[2]);
+        if (neg) v -= Sn * orc_grid_texel(g, i[0] + on[0], i[1] + on[1], i[2] + on[2]);
+        out[0] = v;
+        if (idx)
+            for (int a = 0; a < 3; ++a) {
+                idx[a] = i[a] + op[a];
+                idx[3 + a] = neg ? i[a] + on[a] : ORC_BAD_INDEX;
+            }
+        return;
+    }
     int v[3];
     if (mode == ORC_STOCH) {
         for (int a = 0; a < 3; ++a) v[a] = i[a] + orc_select(filter, t[a], orc_uniform(seed, qid, (uint32_t)a));
@@ -486,15 +745,21 @@ static void orc_query3d(const orc_grid* g, const float* p, int filter, int mode,
     if (idx) { idx[0] = v[0]; idx[1] = v[1]; idx[2] = v[2]; }
 }
 
+static int orc_filter3d_args_ok(const orc_grid* g, int64_t n, int filter, int mode)
+{
+    if (!g || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return 0;
+    return !(orc_positivized(filter) && mode == ORC_STOCH_REUSE);   /* the paper's listing is 2D */
+}
+
 int orc_filter3d(const orc_grid* g, const float* p, int64_t n, int filter, int mode, uint64_t seed,
                  double* out, int32_t* idx, int nthreads)
 {
-    if (!g || n < 0) return -1;
-    int nt = orc_threads(nthreads);
+    if (!orc_filter3d_args_ok(g, n, filter, mode)) return -1;
+    int nt = orc_threads(nthreads), iw = orc_index_width(filter, 3);
     (void)nt;
 #pragma omp parallel for schedule(static) num_threads(nt)
     for (int64_t q = 0; q < n; ++q)
-        orc_query3d(g, p + 3 * q, filter, mode, seed, (uint32_t)q, out + q, idx ? idx + 3 * q : NULL);
+        orc_query3d(g, p + 3 * q, filter, mode, seed, (uint32_t)q, out + q, idx ? idx + iw * q : NULL);
     return 0;
 }
 
@@ -504,13 +769,13 @@ int orc_filter3d(const orc_grid* g, const float* p, int64_t n, int filter, int m
 int orc_filter3d_at(const orc_grid* g, const float* p, const int64_t* qids, int64_t m, int filter,
                     int mode, uint64_t seed, double* out, int32_t* idx, int nthreads)
 {
-    if (!g || m < 0) return -1;
-    int nt = orc_threads(nthreads);
+    if (!orc_filter3d_args_ok(g, m, filter, mode)) return -1;
+    int nt = orc_threads(nthreads), iw = orc_index_width(filter, 3);
     (void)nt;
 #pragma omp parallel for schedule(static) num_threads(nt)
     for (int64_t k = 0; k < m; ++k)
         orc_query3d(g, p + 3 * qids[k], filter, mode, seed, (uint32_t)qids[k], out + k,
-                    idx ? idx + 3 * k : NULL);
+                    idx ? idx + iw * k : NULL);
     return 0;
 }
 
@@ -528,11 +793,8 @@ int orc_filter3d_brute(const orc_grid* g, const float* p, int64_t n, int filter,
         for (int z = i2 - 2; z <= i2 + 3; ++z)
             for (int y = i1 - 2; y <= i1 + 3; ++y)
                 for (int x = i0 - 2; x <= i0 + 3; ++x) {
-                    double w = (filter == ORC_CUBIC)
-                        ? orc_kernel_bspline((double)pq[0] - x) * orc_kernel_bspline((double)pq[1] - y) *
-                          orc_kernel_bspline((double)pq[2] - z)
-                        : orc_kernel_tent((double)pq[0] - x) * orc_kernel_tent((double)pq[1] - y) *
-                          orc_kernel_tent((double)pq[2] - z);
+                    double w = orc_kernel(filter, (double)pq[0] - x) * orc_kernel(filter, (double)pq[1] - y) *
+                               orc_kernel(filter, (double)pq[2] - z);
                     if (w != 0.0) acc += w * orc_grid_texel(g, x, y, z);
                 }
         out[q] = acc;
@@ -540,14 +802,35 @@ int orc_filter3d_brute(const orc_grid* g, const float* p, int64_t n, int filter,
     return 0;
 }
 
-/* Exact mean and variance of the single-tap estimator for each query:       */
-/* E = sum w t  (the deterministic value), Var = sum w t^2 - E^2, with the    */
-/* tensor-product tap probabilities equal to the normalised weights          */
-/* (Eqs. filtered-texture and stochastic-sum).                               */
+/* Exact mean and variance of the stochastic estimator of one query from its
+ * taps (weights w, texels v):
+ *   single tap (Eqs. filtered-texture and stochastic-sum; the tap
+ *   probabilities are the normalised weights): E = sum w v,
+ *   Var = sum w v^2 - E^2;
+ *   positivized (two independent draws, see above): with A = sum_{w>0} w v,
+ *   B = sum_{w<0} |w| v, E = A - B and
+ *   Var = S+ sum_{w>0} w v^2 + S- sum_{w<0} |w| v^2 - A^2 - B^2. */
+typedef struct orc_moment_acc { double A, B, A2, B2, Sp, Sn; } orc_moment_acc;
+
+static void orc_moment_add(orc_moment_acc* m, double w, double v)
+{
+    if (w > 0.0) { m->A += w * v; m->A2 += w * v * v; m->Sp += w; }
+    else if (w < 0.0) { m->B -= w * v; m->B2 -= w * v * v; m->Sn -= w; }
+}
+
+static void orc_moment_finish(const orc_moment_acc* m, int filter, double* mean, double* var)
+{
+    *mean = m->A - m->B;
+    if (orc_positivized(filter))
+        *var = m->Sp * m->A2 + m->Sn * m->B2 - m->A * m->A - m->B * m->B;
+    else
+        *var = m->A2 - m->A * m->A;   /* weights are non-negative */
+}
+
 int orc_filter3d_moments(const orc_grid* g, const float* p, int64_t n, int filter,
                          double* mean, double* var, int nthreads)
 {
-    if (!g || n < 0) return -1;
+    if (!orc_filter3d_args_ok(g, n, filter, ORC_STOCH)) return -1;
     int nt = orc_threads(nthreads);
     (void)nt;
 #pragma omp parallel for schedule(static) num_threads(nt)
@@ -560,18 +843,45 @@ int orc_filter3d_moments(const orc_grid* g, const float* p, int64_t n, int filte
         if (!ok) { mean[q] = NAN; var[q] = NAN; continue; }
         double w[3][4];
         for (int a = 0; a < 3; ++a) orc_axis_weights(filter, (double)pq[a] - floor((double)pq[a]), w[a]);
-        int base = (filter == ORC_CUBIC) ? -1 : 0, ntap = (filter == ORC_CUBIC) ? 4 : 2;
-        double m1 = 0.0, m2 = 0.0;
+        int base = (filter == ORC_LINEAR) ? 0 : -1, ntap = (filter == ORC_LINEAR) ? 2 : 4;
+        orc_moment_acc m = {0, 0, 0, 0, 0, 0};
         for (int cz = 0; cz < ntap; ++cz)
             for (int cy = 0; cy < ntap; ++cy)
-                for (int cx = 0; cx < ntap; ++cx) {
-                    double wt = w[0][cx] * w[1][cy] * w[2][cz];
-                    double v = orc_grid_texel(g, i[0] + base + cx, i[1] + base + cy, i[2] + base + cz);
-                    m1 += wt * v;
-                    m2 += wt * v * v;
-                }
-        mean[q] = m1;
-        var[q] = m2 - m1 * m1;
+                for (int cx = 0; cx < ntap; ++cx)
+                    orc_moment_add(&m, w[0][cx] * w[1][cy] * w[2][cz],
+                                   orc_grid_texel(g, i[0] + base + cx, i[1] + base + cy, i[2] + base + cz));
+        orc_moment_finish(&m, filter, &mean[q], &var[q]);
+    }
+    return 0;
+}
+
+/* The same for 2D textures, per channel (n x C outputs). */
+int orc_filter2d_moments(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n, int filter,
+                         double* mean, double* var, int nthreads)
+{
+    if (W <= 0 || H <= 0 || C <= 0 || C > 4 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
+    int nt = orc_threads(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t q = 0; q < n; ++q) {
+        float x, y, tx, ty;
+        int ix, iy;
+        orc_raster2d(uv + 2 * q, W, H, &x, &y);
+        if (!orc_cell(x, &ix, &tx) || !orc_cell(y, &iy, &ty)) {
+            for (int c = 0; c < C; ++c) mean[q * C + c] = var[q * C + c] = NAN;
+            continue;
+        }
+        double wx[4], wy[4];
+        orc_axis_weights(filter, (double)tx, wx);
+        orc_axis_weights(filter, (double)ty, wy);
+        int base = (filter == ORC_LINEAR) ? 0 : -1, ntap = (filter == ORC_LINEAR) ? 2 : 4;
+        for (int c = 0; c < C; ++c) {
+            orc_moment_acc m = {0, 0, 0, 0, 0, 0};
+            for (int b = 0; b < ntap; ++b)
+                for (int a = 0; a < ntap; ++a)
+                    orc_moment_add(&m, wx[a] * wy[b], orc_texel2d(tex, W, H, C, fmt, ix + base + a, iy + base + b, c));
+            orc_moment_finish(&m, filter, &mean[q * C + c], &var[q * C + c]);
+        }
     }
     return 0;
 }
