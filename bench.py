@@ -109,7 +109,11 @@ def run_grid(args, torch, stf, synth):
     variants = [("stoch_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 64),
                 ("det_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_DETERMINISTIC, 64),
                 ("stoch_linear", stf.STF_LINEAR, stf.STF_STOCHASTIC, 8),
-                ("det_linear", stf.STF_LINEAR, stf.STF_DETERMINISTIC, 8)]
+                ("det_linear", stf.STF_LINEAR, stf.STF_DETERMINISTIC, 8),
+                ("stoch_keys", stf.STF_CUBIC_KEYS, stf.STF_STOCHASTIC, 64),
+                ("det_keys", stf.STF_CUBIC_KEYS, stf.STF_DETERMINISTIC, 64),
+                ("stoch_mitchell", stf.STF_CUBIC_MITCHELL, stf.STF_STOCHASTIC, 64),
+                ("det_mitchell", stf.STF_CUBIC_MITCHELL, stf.STF_DETERMINISTIC, 64)]
     if args.only:
         variants = [v for v in variants if v[0] == args.only]
     if args.copy_calibration:
@@ -125,7 +129,9 @@ def run_grid(args, torch, stf, synth):
     for name, filt, mode, taps in variants:
         fn = lambda: call(filt, mode, seed, out)
         wall, kern = time_launches(fn, args.steps, args.warmup, torch)
-        b_alg = 12 + 4 + (texel_b if mode == stf.STF_STOCHASTIC else taps * texel_b)
+        # stochastic: one texel, two for the positivized interpolating cubics
+        drawn = 2 if filt in stf.POSITIVIZED_FILTERS else 1
+        b_alg = 12 + 4 + (drawn * texel_b if mode == stf.STF_STOCHASTIC else taps * texel_b)
         res[name] = variant_stats(n, args.steps, wall, kern, b_alg)
         log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel "
             f"{res[name]['kernel_ms_mean'] * 1e3:.1f} us, {res[name]['achieved_gbs']:.0f} GB/s algorithmic")
@@ -137,9 +143,28 @@ def run_grid(args, torch, stf, synth):
         og = oracle.Grid(dims, ofmt, grid.origins, raw)
         rng = np.random.default_rng(12)
         qids = np.sort(rng.choice(n, 1 << 16, replace=False))
+        ofilts = {stf.STF_LINEAR: oracle.LINEAR, stf.STF_CUBIC_BSPLINE: oracle.CUBIC, stf.STF_CUBIC_KEYS: oracle.KEYS,
+                  stf.STF_CUBIC_MITCHELL: oracle.MITCHELL}
         for name, filt, mode, _ in variants:
-            ofilt = oracle.CUBIC if filt == stf.STF_CUBIC_BSPLINE else oracle.LINEAR
-            if mode == stf.STF_STOCHASTIC:
+            ofilt = ofilts[filt]
+            if mode == stf.STF_STOCHASTIC and filt in stf.POSITIVIZED_FILTERS:
+                idx = torch.empty((n, 6), dtype=torch.int32, device=dev)
+                call(filt, mode, seed, out, idx)
+                gv = out[:, 0].cpu().numpy()
+                gi = idx.cpu().numpy()
+                if args.order == "morton":
+                    inv = np.empty(n, np.int64)
+                    inv[order.cpu().numpy()] = np.arange(n)
+                    gv, gi = gv[inv], gi[inv]
+                gv, gi = gv[qids].astype(np.float64), gi[qids]
+                ov, oi = og.filter_at(pts, qids, ofilt, oracle.STOCH, seed)
+                scale = positivized_scale(oracle, og, pts[qids], oi, ofilt)
+                err = np.abs(gv - ov)
+                parity[name] = dict(sampled=int(qids.size), index_mismatches=int(np.any(gi != oi, axis=1).sum()),
+                                    max_rel_err=float(np.max(np.where(scale > 0, err / np.where(scale > 0, scale, 1),
+                                                                      np.where(err == 0, 0, np.inf)))),
+                                    within_1e6=bool(np.all(err <= 1e-6 * scale)))
+            elif mode == stf.STF_STOCHASTIC:
                 idx = torch.empty((n, 3), dtype=torch.int32, device=dev)
                 call(filt, mode, seed, out, idx)
                 gv = out[:, 0].cpu().numpy()
@@ -161,10 +186,11 @@ def run_grid(args, torch, stf, synth):
                     gv = gv[inv]
                 gv = gv[qids].astype(np.float64)
                 ov, _ = og.filter_at(pts, qids, ofilt, oracle.DET, 0)
+                scale, _ = og.filter_at(pts, qids, ofilt, oracle.DET_ABS, 0)   # sum |w_k t_k|
                 err = np.abs(gv - ov)
-                rel = np.where(ov != 0, err / np.where(ov == 0, 1, np.abs(ov)), np.where(err == 0, 0, np.inf))
+                rel = np.where(scale != 0, err / np.where(scale == 0, 1, scale), np.where(err == 0, 0, np.inf))
                 parity[name] = dict(sampled=int(qids.size), max_rel_err=float(rel.max()),
-                                    within_1e6=bool(np.all(err <= 1e-6 * np.abs(ov))))
+                                    within_1e6=bool(np.all(err <= 1e-6 * scale)))
             log(f"parity {name}: {parity[name]}")
         if not args.no_cpu and "stoch_cubic" in res:
             m = min(args.cpu_sample, n)
@@ -190,6 +216,9 @@ def run_grid(args, torch, stf, synth):
         "p99_batch_ms": head["kernel_ms_p99"],
         "deterministic_lookups_per_s": det["lookups_per_s"] if det else None,
         "stochastic_over_deterministic": head["lookups_per_s"] / det["lookups_per_s"] if det else None,
+        "interpolating_stochastic_over_deterministic": {
+            k: res[f"stoch_{k}"]["lookups_per_s"] / res[f"det_{k}"]["lookups_per_s"]
+            for k in ("keys", "mitchell") if f"stoch_{k}" in res and f"det_{k}" in res},
         "variants": res,
         "sort": sort_info,
         "parity": parity,
@@ -201,6 +230,21 @@ def run_grid(args, torch, stf, synth):
     })
     tex.destroy()
     return line
+
+
+def positivized_scale(oracle, og, pts, oi, ofilt):
+    """S+|t(j+)| + S-|t(j-)| per query: the scale of the positivized tolerance."""
+    out = np.zeros(pts.shape[0])
+    for k in range(pts.shape[0]):
+        if not np.all(np.isfinite(pts[k])) or np.any(np.abs(pts[k]) >= 2 ** 24):
+            continue
+        t = (pts[k] - np.floor(pts[k])).astype(np.float64)
+        sp, sn = oracle.positivized_masses(ofilt, t)
+        s = sp * abs(og.texel(*(int(v) for v in oi[k, :3])))
+        if oi[k, 3] != oracle.BAD_INDEX:
+            s += sn * abs(og.texel(*(int(v) for v in oi[k, 3:])))
+        out[k] = s
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -83,9 +83,20 @@ typedef enum {
     STF_FMT_U8 = 4         /* UNORM8 */
 } stf_format;
 
+/* Filters.  The B-spline and linear filters have non-negative weights and
+ * their stochastic mode reads one tap.  The interpolating cubics have
+ * negative lobes; their stochastic mode is positivization (section
+ * "Sampling Techniques", positivization; supplement, "The interpolating
+ * (negative lobe) bicubic filter"): one tap j+ drawn in proportion to the
+ * positive weights and one tap j- in proportion to the magnitudes of the
+ * negative ones, result S+ t(j+) - S- t(j-) with S+/S- the two weight
+ * masses (the second term only when S- > 0).  Taps i-1..i+2 of cell i. */
 typedef enum {
     STF_LINEAR = 0,          /* bilinear (2D, 4 taps) / trilinear (3D, 8 taps) */
-    STF_CUBIC_BSPLINE = 1    /* bicubic (16 taps) / tricubic (64 taps) B-spline */
+    STF_CUBIC_BSPLINE = 1,   /* bicubic (16 taps) / tricubic (64 taps) B-spline */
+    STF_CUBIC_KEYS = 2,      /* the cubic polynomial kernel K_3 with a = -1/2 (supplement, "Filter
+                                Kernels"; Catmull-Rom, interpolating); stochastic: 2 taps */
+    STF_CUBIC_MITCHELL = 3   /* Mitchell-Netravali cubic, B = C = 1/3; stochastic: 2 taps */
 } stf_filter_kind;
 
 typedef enum {
@@ -150,6 +161,9 @@ stf_status stf_texture_bytes(const stf_texture* tex, int64_t* bytes);
  *   out_index_dev: NULL, or (stochastic mode only) n x dims int32: the texel
  *                  that was read -- clamped (x, y) for 2D, (x, y, z) for 3D
  *                  (may lie outside the domain, which reads as background).
+ *                  For STF_CUBIC_KEYS / STF_CUBIC_MITCHELL: n x 2*dims, the
+ *                  positive tap then the negative tap (INT32_MIN entries
+ *                  when there is no negative weight).
  *   flags:         0.
  * Deterministic results carry binary32 weight and accumulation error only;
  * stochastic results are the decoded texel exactly. */
@@ -192,7 +206,8 @@ stf_status stf_filter_ordered(const stf_texture* tex, const float* sorted_querie
  * binary64 on the device: sum_dev[q] = sum_k v_k, sumsq_dev[q] = sum_k v_k^2,
  * where v_k is exactly what stf_filter(..., STF_STOCHASTIC, seed_base + k)
  * returns for query q (channel 0 of 2D textures).  This is the statistic of
- * the unbiasedness claim of Eq. stochastic-sum. */
+ * the unbiasedness claim of Eq. stochastic-sum (and, for the interpolating
+ * cubics, of the positivized estimate). */
 stf_status stf_filter_moments(const stf_texture* tex, const float* queries_dev, int64_t n,
                               stf_filter_kind filter, uint64_t seed_base, int32_t n_seeds,
                               double* sum_dev, double* sumsq_dev, void* hip_stream);
@@ -203,7 +218,8 @@ stf_status stf_filter_moments(const stf_texture* tex, const float* queries_dev, 
  * unit vectors in the tangent frame (z = geometric normal).  The level is
  * l = [s >= 1.41421354f] + [s >= 2.82842708f], capped at levels-1.  The
  * filter is the B-spline (`filter` = STF_CUBIC_BSPLINE) or linear one on
- * that level.  Shading f^ = BSDF * cos is a GGX microfacet model:
+ * that level (the interpolating cubics give STF_E_UNSUPPORTED).  Shading
+ * f^ = BSDF * cos is a GGX microfacet model:
  *   albedo = rgb/255, alpha = max(r^2, 1e-3) with r = roughness/255,
  *   n = normalize-free (x, y, sqrt(max(0, 1 - x^2 - y^2))),
  *   h = normalize(wo + wi), D = alpha^2 / (pi (c^2 alpha^2 + |n x h|^2)^2)
@@ -279,7 +295,8 @@ stf_status stf_ntex_prepare_inference(stf_neural* nt, void* hip_stream);
  * decodes the one sampled tap.  Decoding runs on BF16 matrix cores with
  * binary32 accumulation: the interpolated latent and each hidden activation
  * (after ReLU) are rounded to bfloat16.  out_dev: n x 8 binary32 (16-byte
- * aligned); out_index_dev: NULL or (stochastic) n x 2 int32 texel (x, y). */
+ * aligned); out_index_dev: NULL or (stochastic) n x 2 int32 texel (x, y).
+ * The interpolating cubics give STF_E_UNSUPPORTED. */
 stf_status stf_ntex_filter(const stf_neural* nt, const float* queries_dev, int64_t n,
                            stf_filter_kind filter, stf_mode mode, uint64_t seed, float* out_dev,
                            int32_t* out_index_dev, void* hip_stream);
@@ -326,7 +343,8 @@ void stf_server_destroy(stf_server* s);
 /* Queue a request of n queries (2 or 3 binary32 each, per the texture).
  * out: n x channels binary32; out_index: NULL or n x dims int32.  flags:
  * STF_SERVE_* bits.  A request whose state can never fit the arena is
- * rejected with STF_E_OOM.  *ticket identifies it. */
+ * rejected with STF_E_OOM; the interpolating cubics give
+ * STF_E_UNSUPPORTED.  *ticket identifies it. */
 stf_status stf_server_submit(stf_server* s, const stf_texture* tex, const float* queries, int64_t n,
                              stf_filter_kind filter, uint64_t seed, float* out, int32_t* out_index,
                              uint32_t flags, uint64_t* ticket);

@@ -22,7 +22,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 F32, F16, BF16, FP8_E4M3, U8 = 0, 1, 2, 3, 4
 LINEAR, CUBIC, KEYS, MITCHELL = 0, 1, 2, 3
 POSITIVIZED = (KEYS, MITCHELL)
-DET, STOCH, STOCH_REUSE = 0, 1, 2
+DET, STOCH, STOCH_REUSE, DET_ABS = 0, 1, 2, 3   # DET_ABS: sum |w_k| |t_k| (tolerance scale)
 BAD_INDEX = -(2 ** 31)
 
 _lib = None
@@ -229,7 +229,7 @@ def filter2d(tex: np.ndarray, fmt: int, uv: np.ndarray, filt: int, mode: int, se
     uv = np.ascontiguousarray(uv, dtype=np.float32)
     n = uv.shape[0]
     out = np.empty((n, Ch), np.float64)
-    idx = np.empty((n, index_width(filt, 2)), np.int32) if (want_index and mode != DET) else None
+    idx = np.empty((n, index_width(filt, 2)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE)) else None
     rc = lib().orc_filter2d(_p(tex), W, H, Ch, fmt, _p(uv), n, filt, mode, seed, _p(out), _p(idx), nthreads)
     if rc != 0:
         raise ValueError("orc_filter2d rejected its arguments")
@@ -290,7 +290,7 @@ class Grid:
         p = np.ascontiguousarray(p, dtype=np.float32)
         n = p.shape[0]
         out = np.empty(n, np.float64)
-        idx = np.empty((n, index_width(filt, 3)), np.int32) if (want_index and mode != DET) else None
+        idx = np.empty((n, index_width(filt, 3)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE)) else None
         rc = lib().orc_filter3d(self._h, _p(p), n, filt, mode, seed, _p(out), _p(idx), nthreads)
         if rc != 0:
             raise ValueError("orc_filter3d failed")
@@ -304,7 +304,7 @@ class Grid:
         qids = np.ascontiguousarray(qids, dtype=np.int64)
         m = qids.shape[0]
         out = np.empty(m, np.float64)
-        idx = np.empty((m, index_width(filt, 3)), np.int32) if mode != DET else None
+        idx = np.empty((m, index_width(filt, 3)), np.int32) if mode in (STOCH, STOCH_REUSE) else None
         rc = lib().orc_filter3d_at(self._h, _p(p), _p(qids), m, filt, mode, seed, _p(out), _p(idx), nthreads)
         if rc != 0:
             raise ValueError("orc_filter3d_at failed")

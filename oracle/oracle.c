@@ -52,7 +52,8 @@
 enum { ORC_F32 = 0, ORC_F16 = 1, ORC_BF16 = 2, ORC_FP8_E4M3 = 3, ORC_U8 = 4 };
 /* filters and modes */
 enum { ORC_LINEAR = 0, ORC_CUBIC = 1, ORC_KEYS = 2, ORC_MITCHELL = 3 };
-enum { ORC_DET = 0, ORC_STOCH = 1, ORC_STOCH_REUSE = 2 };
+enum { ORC_DET = 0, ORC_STOCH = 1, ORC_STOCH_REUSE = 2, ORC_DET_ABS = 3 };
+/* ORC_DET_ABS: sum_k |w_k| |t_k|, the scale of the deterministic tolerance. */
 
 #define ORC_BAD_INDEX ((int32_t)0x80000000)
 
@@ -530,17 +531,20 @@ static void orc_query2d(const void* tex, int W, int H, int C, int fmt, const flo
     }
     int base = (filter == ORC_LINEAR) ? 0 : -1;
     int ntap = (filter == ORC_LINEAR) ? 2 : 4;
-    if (mode == ORC_DET) {
+    if (mode == ORC_DET || mode == ORC_DET_ABS) {
         double wx[4], wy[4];
         orc_axis_weights(filter, (double)x - floor((double)x), wx);
         orc_axis_weights(filter, (double)y - floor((double)y), wy);
+        int ab = mode == ORC_DET_ABS;
         for (int c = 0; c < C; ++c) {
             double acc = 0.0;
             for (int b = 0; b < ntap; ++b) {
                 double row = 0.0;
-                for (int a = 0; a < ntap; ++a)
-                    row += wx[a] * orc_texel2d(tex, W, H, C, fmt, ix + base + a, iy + base + b, c);
-                acc += wy[b] * row;
+                for (int a = 0; a < ntap; ++a) {
+                    double v = orc_texel2d(tex, W, H, C, fmt, ix + base + a, iy + base + b, c);
+                    row += ab ? fabs(wx[a]) * fabs(v) : wx[a] * v;
+                }
+                acc += (ab ? fabs(wy[b]) : wy[b]) * row;
             }
             out[c] = acc;
         }
@@ -702,16 +706,21 @@ static void orc_query3d(const orc_grid* g, const float* p, int filter, int mode,
         if (!orc_cell(p[a], &i[a], &t[a])) { orc_nan_out(out, 1, idx, orc_index_width(filter, 3)); return; }
     int base = (filter == ORC_LINEAR) ? 0 : -1;
     int ntap = (filter == ORC_LINEAR) ? 2 : 4;
-    if (mode == ORC_DET) {
+    if (mode == ORC_DET || mode == ORC_DET_ABS) {
         double w[3][4];
         for (int a = 0; a < 3; ++a) orc_axis_weights(filter, (double)p[a] - floor((double)p[a]), w[a]);
+        if (mode == ORC_DET_ABS)
+            for (int a = 0; a < 3; ++a)
+                for (int k = 0; k < 4; ++k) w[a][k] = fabs(w[a][k]);
         double acc = 0.0;
         for (int cz = 0; cz < ntap; ++cz) {
             double plane = 0.0;
             for (int cy = 0; cy < ntap; ++cy) {
                 double row = 0.0;
-                for (int cx = 0; cx < ntap; ++cx)
-                    row += w[0][cx] * orc_grid_texel(g, i[0] + base + cx, i[1] + base + cy, i[2] + base + cz);
+                for (int cx = 0; cx < ntap; ++cx) {
+                    double v = orc_grid_texel(g, i[0] + base + cx, i[1] + base + cy, i[2] + base + cz);
+                    row += w[0][cx] * (mode == ORC_DET_ABS ? fabs(v) : v);
+                }
                 plane += w[1][cy] * row;
             }
             acc += w[2][cz] * plane;

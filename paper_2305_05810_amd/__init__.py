@@ -19,7 +19,14 @@ LIB_PATH = os.path.join(_HERE, "libstf.so")
 # enums of include/stf.h
 STF_OK, STF_E_INVALID, STF_E_OOM, STF_E_UNSUPPORTED, STF_E_DEVICE, STF_E_BUSY, STF_E_CANCELLED = 0, -1, -2, -3, -4, -5, -6
 STF_FMT_F32, STF_FMT_F16, STF_FMT_BF16, STF_FMT_FP8_E4M3, STF_FMT_U8 = 0, 1, 2, 3, 4
-STF_LINEAR, STF_CUBIC_BSPLINE = 0, 1
+STF_LINEAR, STF_CUBIC_BSPLINE, STF_CUBIC_KEYS, STF_CUBIC_MITCHELL = 0, 1, 2, 3
+POSITIVIZED_FILTERS = (STF_CUBIC_KEYS, STF_CUBIC_MITCHELL)
+
+
+def index_width(filter: int, dims: int) -> int:
+    """int32 index entries per query in stochastic mode: the tap, or for the
+    interpolating cubics the positive tap followed by the negative tap."""
+    return 2 * dims if filter in POSITIVIZED_FILTERS else dims
 STF_DETERMINISTIC, STF_STOCHASTIC = 0, 1
 STF_SHADE_AFTER_FILTER, STF_FILTER_AFTER_SHADE, STF_SHADE_STOCHASTIC = 0, 1, 2
 
@@ -192,11 +199,22 @@ def _stream(stream):
     return s.cuda_stream
 
 
+def _check_outputs(tex: Texture, n: int, filter: int, out, out_index):
+    """The library writes n x channels results and n x index_width indices
+    through raw pointers; refuse buffers that are too small."""
+    if out is not None and out.numel() < n * tex.channels:
+        raise ValueError(f"out holds {out.numel()} values, {n * tex.channels} needed")
+    if out_index is not None and out_index.numel() < n * index_width(filter, tex.dims):
+        raise ValueError(f"out_index holds {out_index.numel()} entries, {n * index_width(filter, tex.dims)} needed")
+
+
 def stf_filter(tex: Texture, queries, filter: int, mode: int, seed: int, out, out_index=None, flags: int = 0,
                stream=None):
     """queries: (n, 2|3) float32 GPU tensor; out: (n, channels) float32 GPU
-    tensor; out_index: None or (n, dims) int32 GPU tensor (stochastic)."""
+    tensor; out_index: None or (n, index_width(filter, dims)) int32 GPU
+    tensor (stochastic)."""
     n = queries.shape[0]
+    _check_outputs(tex, n, filter, out, out_index)
     _check(lib().stf_filter(tex.handle, _dev_ptr(queries, "queries"), n, filter, mode, seed & (2 ** 64 - 1),
                             _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"), flags, _stream(stream)))
 
@@ -204,6 +222,8 @@ def stf_filter(tex: Texture, queries, filter: int, mode: int, seed: int, out, ou
 def stf_filter_moments(tex: Texture, queries, filter: int, seed_base: int, n_seeds: int, sum_out, sumsq_out,
                        stream=None):
     n = queries.shape[0]
+    if sum_out.numel() < n or sumsq_out.numel() < n:
+        raise ValueError("sum/sumsq hold fewer than n values")
     _check(lib().stf_filter_moments(tex.handle, _dev_ptr(queries, "queries"), n, filter, seed_base, n_seeds,
                                     _dev_ptr(sum_out, "sum"), _dev_ptr(sumsq_out, "sumsq"), _stream(stream)))
 
@@ -225,7 +245,7 @@ def filter(tex: Texture, queries, filter: int, mode: int, seed: int = 0, want_in
     out = torch.empty((n, tex.channels), dtype=torch.float32, device=queries.device)
     idx = None
     if want_index and mode == STF_STOCHASTIC:
-        idx = torch.empty((n, tex.dims), dtype=torch.int32, device=queries.device)
+        idx = torch.empty((n, index_width(filter, tex.dims)), dtype=torch.int32, device=queries.device)
     stf_filter(tex, queries, filter, mode, seed, out, idx, 0, stream)
     return out, idx
 
@@ -507,6 +527,9 @@ def stf_sort_queries(tex: Texture, queries, sorted_out, order_out, workspace, st
 
 def stf_filter_ordered(tex: Texture, sorted_queries, order, filter: int, mode: int, seed: int, out, out_index=None,
                        flags: int = 0, stream=None):
+    _check_outputs(tex, sorted_queries.shape[0], filter, out, out_index)
+    if order.numel() < sorted_queries.shape[0]:
+        raise ValueError("order is shorter than the query stream")
     _check(_sort_lib().stf_filter_ordered(tex.handle, _dev_ptr(sorted_queries, "sorted_queries"),
                                           _dev_ptr(order, "order"), sorted_queries.shape[0], filter, mode,
                                           seed & (2 ** 64 - 1), _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"),

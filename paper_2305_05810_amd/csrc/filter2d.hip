@@ -4,11 +4,16 @@
 // per-axis draw of Eq. stochastic-bilerp / the bicubic sampling of section
 // "B-Spline and Anisotropic Filters").
 //
+// The interpolating cubics (Keys, Mitchell) filter deterministically with
+// their 16 weights and stochastically by positivization: one tap from the
+// positive and one from the negative weights (interp.h).
+//
 // Raster position: x = uv.x * W - 0.5 (texel centres at half-integers of
 // uv * W); taps are clamped to the texture.
 #include <math.h>
 
 #include "device_common.h"
+#include "interp.h"
 #include "stf_internal.h"
 
 using namespace stf;
@@ -91,6 +96,54 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(TexLevel L, const fl
     tex2d_stochastic_one<FMT, C, CUBIC>(L, q, n, blockIdx.x * BLOCK + threadIdx.x, key, 0u, out, idx, order, scatter);
 }
 
+// Positivized estimate of an interpolating cubic for query i: two clamped
+// taps, value (S+ t(j+) - S- t(j-)) / scale^2; index (x+, y+, x-, y-), the
+// negative tap INT32_MIN when S- = 0.
+template <int FMT, int C, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_positivized(TexLevel L, const float* __restrict__ q, int32_t n,
+                                                             uint32_t key, float* __restrict__ out,
+                                                             int32_t* __restrict__ idx,
+                                                             const int32_t* __restrict__ order, int scatter)
+{
+    const int32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int32_t id = order ? order[i] : i;
+    const int64_t oi = (order && scatter) ? (int64_t)id : (int64_t)i;
+    float2 uv = reinterpret_cast<const float2*>(q)[i];
+    float x = uv.x * (float)L.w - 0.5f;
+    float y = uv.y * (float)L.h - 0.5f;
+    int cx, cy;
+    float tx, ty;
+    bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
+    float v[C];
+    int ix[4] = {BAD_INDEX, BAD_INDEX, BAD_INDEX, BAD_INDEX};
+    if (ok) {
+        const float t[2] = {tx, ty};
+        const PosDraw<2> d = positivized_draw<2, KIND>(t, pcg(key ^ (uint32_t)id));
+        ix[0] = clampi(cx + d.op[0], L.w - 1);
+        ix[1] = clampi(cy + d.op[1], L.h - 1);
+        float vp[C], vn[C];
+        load_rgba<FMT, C>(L, ix[0], ix[1], vp);
+        if (d.neg) {
+            ix[2] = clampi(cx + d.on[0], L.w - 1);
+            ix[3] = clampi(cy + d.on[1], L.h - 1);
+            load_rgba<FMT, C>(L, ix[2], ix[3], vn);
+        }
+        constexpr float inv = inv_scale<2, KIND>();
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = (d.neg ? d.sp * vp[c] - d.sn * vn[c] : d.sp * vp[c]) * inv;
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = __builtin_nanf("");
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[oi * C + c] = v[c];
+    if (idx) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) idx[4 * oi + k] = ix[k];
+    }
+}
+
 // Serving: block b serves chunk c with start[c] <= b < start[c + 1].
 template <int FMT, int C, bool CUBIC>
 __global__ __launch_bounds__(BLOCK) void k_tex2d_serve(TexLevel L, const ServeChunk* __restrict__ chunks,
@@ -107,12 +160,12 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_serve(TexLevel L, const ServeCh
                                         c.qid0, c.out, c.idx, nullptr, 0);
 }
 
-template <int FMT, int C, bool CUBIC>
+template <int FMT, int C, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(TexLevel L, const float* __restrict__ q, int32_t n,
                                                                float* __restrict__ out, const int32_t* __restrict__ order,
                                                                int scatter)
 {
-    constexpr int NT = CUBIC ? 4 : 2;
+    constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
     int32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int64_t oi = (order && scatter) ? (int64_t)order[i] : (int64_t)i;
@@ -128,17 +181,9 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(TexLevel L, const
         for (int c = 0; c < C; ++c) out[oi * C + c] = __builtin_nanf("");
         return;
     }
-    float wx[NT], wy[NT];
-    if constexpr (CUBIC) {
-        Cubic6 a = cubic6(tx), b = cubic6(ty);
-        wx[0] = a.a0; wx[1] = a.a1; wx[2] = a.a2; wx[3] = a.a3;
-        wy[0] = b.a0; wy[1] = b.a1; wy[2] = b.a2; wy[3] = b.a3;
-        cx -= 1;
-        cy -= 1;
-    } else {
-        wx[0] = 1.0f - tx; wx[1] = tx;
-        wy[0] = 1.0f - ty; wy[1] = ty;
-    }
+    float wx[4], wy[4];
+    cx += axis_weights_scaled<KIND>(tx, wx);
+    cy += axis_weights_scaled<KIND>(ty, wy);
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0f;
 #pragma unroll
@@ -157,12 +202,13 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(TexLevel L, const
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = __builtin_fmaf(wy[b], row[c], acc[c]);
     }
+    constexpr float S2 = axis_scale<KIND>() * axis_scale<KIND>();   // 36 (B-spline), 4 (Keys), 324 (Mitchell)
 #pragma unroll
-    for (int c = 0; c < C; ++c) out[oi * C + c] = CUBIC ? acc[c] / 36.0f : acc[c];
+    for (int c = 0; c < C; ++c) out[oi * C + c] = KIND == KIND_LINEAR ? acc[c] : acc[c] / S2;
 }
 
 // channel-0 moments of the stochastic estimator over many seeds
-template <int FMT, int C, bool CUBIC>
+template <int FMT, int C, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_tex2d_moments(TexLevel L, const float* __restrict__ q, int32_t n,
                                                          uint64_t seed_base, int32_t n_seeds,
                                                          double* __restrict__ sum, double* __restrict__ sumsq)
@@ -179,16 +225,31 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_moments(TexLevel L, const float
     if (ok) {
         for (int32_t k = threadIdx.x; k < n_seeds; k += BLOCK) {
             uint32_t b = pcg(seed_key(seed_base + (uint64_t)k) ^ (uint32_t)i);
-            float ux = axis_uniform(b, 0), uy = axis_uniform(b, 1);
-            int sx, sy;
-            if constexpr (CUBIC) {
-                sx = cx + choose_cubic(tx, ux); sy = cy + choose_cubic(ty, uy);
+            float e;
+            if constexpr (KIND == KIND_KEYS || KIND == KIND_MITCHELL) {
+                const float t[2] = {tx, ty};
+                const PosDraw<2> d = positivized_draw<2, KIND>(t, b);
+                float vp[C], vn[C];
+                load_rgba<FMT, C>(L, clampi(cx + d.op[0], L.w - 1), clampi(cy + d.op[1], L.h - 1), vp);
+                e = d.sp * vp[0];
+                if (d.neg) {
+                    load_rgba<FMT, C>(L, clampi(cx + d.on[0], L.w - 1), clampi(cy + d.on[1], L.h - 1), vn);
+                    e = e - d.sn * vn[0];
+                }
+                e = e * inv_scale<2, KIND>();
             } else {
-                sx = cx + choose_linear(tx, ux); sy = cy + choose_linear(ty, uy);
+                float ux = axis_uniform(b, 0), uy = axis_uniform(b, 1);
+                int sx, sy;
+                if constexpr (KIND == KIND_BSPLINE) {
+                    sx = cx + choose_cubic(tx, ux); sy = cy + choose_cubic(ty, uy);
+                } else {
+                    sx = cx + choose_linear(tx, ux); sy = cy + choose_linear(ty, uy);
+                }
+                float v[C];
+                load_rgba<FMT, C>(L, clampi(sx, L.w - 1), clampi(sy, L.h - 1), v);
+                e = v[0];
             }
-            float v[C];
-            load_rgba<FMT, C>(L, clampi(sx, L.w - 1), clampi(sy, L.h - 1), v);
-            double d = (double)v[0];
+            double d = (double)e;
             a1 += d;
             a2 += d * d;
         }
@@ -211,24 +272,33 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_moments(TexLevel L, const float
     }
 }
 
+template <int FMT, int C, int KIND>
+void launch2d_kind(const TexLevel& L, const float* q, int32_t n, int mode, uint32_t key, float* out, int32_t* idx,
+                   const int32_t* order, int scatter, hipStream_t stream)
+{
+    dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
+    if (mode == STF_STOCHASTIC) {
+        if constexpr (KIND == KIND_KEYS || KIND == KIND_MITCHELL)
+            hipLaunchKernelGGL((k_tex2d_positivized<FMT, C, KIND>), grid, block, 0, stream, L, q, n, key, out, idx,
+                               order, scatter);
+        else
+            hipLaunchKernelGGL((k_tex2d_stochastic<FMT, C, KIND == KIND_BSPLINE>), grid, block, 0, stream, L, q, n, key,
+                               out, idx, order, scatter);
+    } else {
+        hipLaunchKernelGGL((k_tex2d_deterministic<FMT, C, KIND>), grid, block, 0, stream, L, q, n, out, order, scatter);
+    }
+}
+
 template <int FMT, int C>
 hipError_t launch2d_fc(const TexLevel& L, const float* q, int32_t n, int filter, int mode, uint32_t key, float* out,
                        int32_t* idx, const int32_t* order, int scatter, hipStream_t stream)
 {
-    dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
-    bool cubic = filter == STF_CUBIC_BSPLINE;
-    if (mode == STF_STOCHASTIC) {
-        if (cubic)
-            hipLaunchKernelGGL((k_tex2d_stochastic<FMT, C, true>), grid, block, 0, stream, L, q, n, key, out, idx, order,
-                               scatter);
-        else
-            hipLaunchKernelGGL((k_tex2d_stochastic<FMT, C, false>), grid, block, 0, stream, L, q, n, key, out, idx, order,
-                               scatter);
-    } else {
-        if (cubic)
-            hipLaunchKernelGGL((k_tex2d_deterministic<FMT, C, true>), grid, block, 0, stream, L, q, n, out, order, scatter);
-        else
-            hipLaunchKernelGGL((k_tex2d_deterministic<FMT, C, false>), grid, block, 0, stream, L, q, n, out, order, scatter);
+    switch (filter) {
+    case KIND_LINEAR: launch2d_kind<FMT, C, KIND_LINEAR>(L, q, n, mode, key, out, idx, order, scatter, stream); break;
+    case KIND_BSPLINE: launch2d_kind<FMT, C, KIND_BSPLINE>(L, q, n, mode, key, out, idx, order, scatter, stream); break;
+    case KIND_KEYS: launch2d_kind<FMT, C, KIND_KEYS>(L, q, n, mode, key, out, idx, order, scatter, stream); break;
+    case KIND_MITCHELL: launch2d_kind<FMT, C, KIND_MITCHELL>(L, q, n, mode, key, out, idx, order, scatter, stream); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -263,12 +333,25 @@ hipError_t moments2d_fc(const TexLevel& L, const float* q, int32_t n, int filter
                         int32_t n_seeds, double* sum, double* sumsq, hipStream_t stream)
 {
     dim3 grid(n), block(BLOCK);
-    if (filter == STF_CUBIC_BSPLINE)
-        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, true>), grid, block, 0, stream, L, q, n, seed_base, n_seeds, sum,
-                           sumsq);
-    else
-        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, false>), grid, block, 0, stream, L, q, n, seed_base, n_seeds, sum,
-                           sumsq);
+    switch (filter) {
+    case KIND_LINEAR:
+        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, KIND_LINEAR>), grid, block, 0, stream, L, q, n, seed_base, n_seeds,
+                           sum, sumsq);
+        break;
+    case KIND_BSPLINE:
+        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, KIND_BSPLINE>), grid, block, 0, stream, L, q, n, seed_base, n_seeds,
+                           sum, sumsq);
+        break;
+    case KIND_KEYS:
+        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, KIND_KEYS>), grid, block, 0, stream, L, q, n, seed_base, n_seeds,
+                           sum, sumsq);
+        break;
+    case KIND_MITCHELL:
+        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, KIND_MITCHELL>), grid, block, 0, stream, L, q, n, seed_base,
+                           n_seeds, sum, sumsq);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

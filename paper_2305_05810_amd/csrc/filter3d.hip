@@ -3,12 +3,17 @@
 // (one tap drawn with probability equal to its weight, Eq. stochastic-sum;
 // the per-axis draw of section "B-Spline and Anisotropic Filters").
 //
+// The interpolating cubics (Keys, Mitchell) filter deterministically with
+// their 64 weights and stochastically by positivization: one tap from the
+// positive and one from the negative weights (interp.h).
+//
 // Grid walk: root slot (128^3 voxels) -> internal node child (8^3 voxels) ->
 // dense 8^3 leaf, x fastest.  Voxels outside the domain or in empty slots read
 // as the grid's background value.
 #include <math.h>
 
 #include "device_common.h"
+#include "interp.h"
 #include "stf_internal.h"
 
 using namespace stf;
@@ -179,6 +184,125 @@ __global__ __launch_bounds__(BLOCK) void k_grid_stochastic(GridView g, const flo
                                          scatter);
 }
 
+// ---------------------------------------------------------------------------
+// positivized interpolating cubics: two taps per query.
+//
+// Each thread takes Q queries (block-strided like the single-tap kernel) and
+// walks the 2Q voxel paths of their positive and negative taps in lock step.
+// ---------------------------------------------------------------------------
+// Values of T voxels, walked in lock step: root loads, then node loads, then
+// leaf loads; a voxel with ok[k] false (or outside the domain, or in an empty
+// slot) reads as background and loads from offset 0.
+template <int FMT, int T>
+__device__ __forceinline__ void grid_fetch(const GridView& g, const int (&vx)[T], const int (&vy)[T],
+                                           const int (&vz)[T], bool (&ok)[T], float (&v)[T])
+{
+    uint32_t roff[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        ok[k] = ok[k] && in_domain(g, vx[k], vy[k], vz[k]);
+        roff[k] = ok[k] ? (uint32_t)(((vz[k] >> 7) * g.ry + (vy[k] >> 7)) * g.rx + (vx[k] >> 7)) : 0u;
+        v[k] = g.background;
+    }
+    int32_t node[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) node[k] = table_load(g.root, roff[k]);
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        ok[k] = ok[k] && node[k] >= 0;
+        any |= ok[k];
+    }
+    if (!__any(any)) return;
+    int32_t leaf[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        uint32_t child = ((((uint32_t)vz[k] >> 3) & 15u) * 16u + (((uint32_t)vy[k] >> 3) & 15u)) * 16u +
+                         (((uint32_t)vx[k] >> 3) & 15u);
+        leaf[k] = table_load(g.nodes, ok[k] ? (uint32_t)node[k] * 4096u + child : 0u);
+    }
+    any = false;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        ok[k] = ok[k] && leaf[k] >= 0;
+        any |= ok[k];
+    }
+    if (!__any(any)) return;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        uint32_t vox = ((((uint32_t)vz[k] & 7u) * 8u + ((uint32_t)vy[k] & 7u)) * 8u) + ((uint32_t)vx[k] & 7u);
+        float t = leaf_value<FMT>(g.leaves, ok[k] ? (uint32_t)leaf[k] * 512u + vox : 0u);
+        v[k] = ok[k] ? t : g.background;
+    }
+}
+
+// Value (S+ t(j+) - S- t(j-)) / scale^3; index (x+, y+, z+, x-, y-, z-), the
+// negative tap INT32_MIN when S- = 0.
+template <int FMT, int KIND, int Q>
+__global__ __launch_bounds__(BLOCK) void k_grid_positivized(GridView g, const float* __restrict__ q, int32_t n,
+                                                            uint32_t key, float* __restrict__ out,
+                                                            int32_t* __restrict__ idx,
+                                                            const int32_t* __restrict__ order, int scatter)
+{
+    const int32_t first = blockIdx.x * (BLOCK * Q) + threadIdx.x;
+    float p[Q][3];
+    bool live[Q];
+    int64_t oi[Q];
+    uint32_t qid[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        int32_t i = first + k * BLOCK;
+        live[k] = i < n;
+        int32_t src = live[k] ? i : 0;
+        int32_t id = order ? order[src] : i;
+        qid[k] = (uint32_t)id;
+        oi[k] = (order && scatter) ? (int64_t)id : (int64_t)i;
+        const float* e = q + 3 * (int64_t)src;
+        p[k][0] = __builtin_nontemporal_load(e);
+        p[k][1] = __builtin_nontemporal_load(e + 1);
+        p[k][2] = __builtin_nontemporal_load(e + 2);
+    }
+    int vx[2 * Q], vy[2 * Q], vz[2 * Q];
+    bool ok[2 * Q], fin[Q], neg[Q];
+    float sp[Q], sn[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        int c[3] = {0, 0, 0};
+        float t[3] = {0.0f, 0.0f, 0.0f};
+        fin[k] = cell_of(p[k][0], c[0], t[0]) & cell_of(p[k][1], c[1], t[1]) & cell_of(p[k][2], c[2], t[2]);
+        const PosDraw<3> d = positivized_draw<3, KIND>(t, pcg(key ^ qid[k]));
+        vx[2 * k] = c[0] + d.op[0];
+        vy[2 * k] = c[1] + d.op[1];
+        vz[2 * k] = c[2] + d.op[2];
+        vx[2 * k + 1] = c[0] + d.on[0];
+        vy[2 * k + 1] = c[1] + d.on[1];
+        vz[2 * k + 1] = c[2] + d.on[2];
+        neg[k] = d.neg;
+        sp[k] = d.sp;
+        sn[k] = d.sn;
+        ok[2 * k] = live[k] && fin[k];
+        ok[2 * k + 1] = live[k] && fin[k] && d.neg;
+    }
+    float v[2 * Q];
+    grid_fetch<FMT, 2 * Q>(g, vx, vy, vz, ok, v);
+    constexpr float inv = inv_scale<3, KIND>();
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        if (!live[k]) continue;
+        float r = (neg[k] ? sp[k] * v[2 * k] - sn[k] * v[2 * k + 1] : sp[k] * v[2 * k]) * inv;
+        __builtin_nontemporal_store(fin[k] ? r : __builtin_nanf(""), out + oi[k]);
+        if (idx) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int pv = a == 0 ? vx[2 * k] : (a == 1 ? vy[2 * k] : vz[2 * k]);
+                const int nv = a == 0 ? vx[2 * k + 1] : (a == 1 ? vy[2 * k + 1] : vz[2 * k + 1]);
+                idx[6 * oi[k] + a] = fin[k] ? pv : BAD_INDEX;
+                idx[6 * oi[k] + 3 + a] = (fin[k] && neg[k]) ? nv : BAD_INDEX;
+            }
+        }
+    }
+}
+
 // Serving: one launch over many requests' chunks (same grid and filter).
 // Block b serves chunk c with start[c] <= b < start[c + 1].
 template <int FMT, bool CUBIC, int Q>
@@ -207,12 +331,12 @@ __device__ __forceinline__ int32_t pick8(const int32_t (&l)[8], bool kx, bool ky
     return kz ? f : e;
 }
 
-template <int FMT, bool CUBIC>
+template <int FMT, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const float* __restrict__ q, int32_t n,
                                                               float* __restrict__ out, const int32_t* __restrict__ order,
                                                               int scatter)
 {
-    constexpr int NT = CUBIC ? 4 : 2;
+    constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
     int32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     float p[3] = {q[3 * (int64_t)i], q[3 * (int64_t)i + 1], q[3 * (int64_t)i + 2]};
@@ -223,17 +347,10 @@ __global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const 
         out[(order && scatter) ? order[i] : i] = __builtin_nanf("");
         return;
     }
-    float w[3][NT];
+    float w[3][4];
     int base[3], lo[3];
     for (int a = 0; a < 3; ++a) {
-        if constexpr (CUBIC) {
-            Cubic6 k = cubic6(t[a]);
-            w[a][0] = k.a0; w[a][1] = k.a1; w[a][2] = k.a2; w[a][3] = k.a3;
-            base[a] = c[a] - 1;
-        } else {
-            w[a][0] = 1.0f - t[a]; w[a][1] = t[a];
-            base[a] = c[a];
-        }
+        base[a] = c[a] + axis_weights_scaled<KIND>(t[a], w[a]);
         lo[a] = base[a] >> 3;   // leaf coordinate of the first tap (floor for negatives)
     }
     int32_t leaf[8];
@@ -269,14 +386,15 @@ __global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const 
         }
         acc = __builtin_fmaf(w[2][cz], plane, acc);
     }
-    if constexpr (CUBIC) acc = acc / 216.0f;   // the three per-axis factors of 1/6
+    constexpr float S3 = axis_scale<KIND>() * axis_scale<KIND>() * axis_scale<KIND>();   // 216, 8 or 5832
+    if constexpr (KIND != KIND_LINEAR) acc = acc / S3;   // the three per-axis scale factors
     out[(order && scatter) ? order[i] : i] = acc;
 }
 
 // ---------------------------------------------------------------------------
 // moments of the stochastic estimator over many seeds (binary64 sums)
 // ---------------------------------------------------------------------------
-template <int FMT, bool CUBIC>
+template <int FMT, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_grid_moments(GridView g, const float* __restrict__ q, int32_t n,
                                                         uint64_t seed_base, int32_t n_seeds,
                                                         double* __restrict__ sum, double* __restrict__ sumsq)
@@ -293,14 +411,24 @@ __global__ __launch_bounds__(BLOCK) void k_grid_moments(GridView g, const float*
     if (ok) {
         for (int32_t k = threadIdx.x; k < n_seeds; k += BLOCK) {
             uint32_t b = pcg(seed_key(seed_base + (uint64_t)k) ^ (uint32_t)i);
-            float u0 = axis_uniform(b, 0), u1 = axis_uniform(b, 1), u2 = axis_uniform(b, 2);
-            int v0, v1, v2;
-            if constexpr (CUBIC) {
-                v0 = c0 + choose_cubic(t0, u0); v1 = c1 + choose_cubic(t1, u1); v2 = c2 + choose_cubic(t2, u2);
+            float e;
+            if constexpr (KIND == KIND_KEYS || KIND == KIND_MITCHELL) {
+                const float t[3] = {t0, t1, t2};
+                const PosDraw<3> d = positivized_draw<3, KIND>(t, b);
+                e = d.sp * grid_voxel<FMT>(g, c0 + d.op[0], c1 + d.op[1], c2 + d.op[2]);
+                if (d.neg) e = e - d.sn * grid_voxel<FMT>(g, c0 + d.on[0], c1 + d.on[1], c2 + d.on[2]);
+                e = e * inv_scale<3, KIND>();
             } else {
-                v0 = c0 + choose_linear(t0, u0); v1 = c1 + choose_linear(t1, u1); v2 = c2 + choose_linear(t2, u2);
+                float u0 = axis_uniform(b, 0), u1 = axis_uniform(b, 1), u2 = axis_uniform(b, 2);
+                int v0, v1, v2;
+                if constexpr (KIND == KIND_BSPLINE) {
+                    v0 = c0 + choose_cubic(t0, u0); v1 = c1 + choose_cubic(t1, u1); v2 = c2 + choose_cubic(t2, u2);
+                } else {
+                    v0 = c0 + choose_linear(t0, u0); v1 = c1 + choose_linear(t1, u1); v2 = c2 + choose_linear(t2, u2);
+                }
+                e = grid_voxel<FMT>(g, v0, v1, v2);
             }
-            double v = (double)grid_voxel<FMT>(g, v0, v1, v2);
+            double v = (double)e;
             a1 += v;
             a2 += v * v;
         }
@@ -323,26 +451,39 @@ __global__ __launch_bounds__(BLOCK) void k_grid_moments(GridView g, const float*
     }
 }
 
+template <int FMT, int KIND>
+void launch3d_kind(const GridView& g, const float* q, int32_t n, int mode, uint32_t key, float* out, int32_t* idx,
+                   const int32_t* order, int scatter, hipStream_t stream)
+{
+    dim3 block(BLOCK);
+    if (mode == STF_STOCHASTIC) {
+        if constexpr (KIND == KIND_KEYS || KIND == KIND_MITCHELL) {
+            constexpr int Q = 2;   // two taps per query: 2Q = 4 walks in lock step
+            dim3 pgrid((unsigned)(((int64_t)n + BLOCK * Q - 1) / (BLOCK * Q)));
+            hipLaunchKernelGGL((k_grid_positivized<FMT, KIND, Q>), pgrid, block, 0, stream, g, q, n, key, out, idx,
+                               order, scatter);
+        } else {
+            constexpr int Q = STOCH_Q;
+            dim3 sgrid((unsigned)(((int64_t)n + BLOCK * Q - 1) / (BLOCK * Q)));
+            hipLaunchKernelGGL((k_grid_stochastic<FMT, KIND == KIND_BSPLINE, Q>), sgrid, block, 0, stream, g, q, n, key,
+                               out, idx, order, scatter);
+        }
+    } else {
+        dim3 grid((n + BLOCK - 1) / BLOCK);
+        hipLaunchKernelGGL((k_grid_deterministic<FMT, KIND>), grid, block, 0, stream, g, q, n, out, order, scatter);
+    }
+}
+
 template <int FMT>
 hipError_t launch3d_fmt(const GridView& g, const float* q, int32_t n, int filter, int mode, uint32_t key, float* out,
                         int32_t* idx, const int32_t* order, int scatter, hipStream_t stream)
 {
-    dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
-    bool cubic = filter == STF_CUBIC_BSPLINE;
-    if (mode == STF_STOCHASTIC) {
-        constexpr int Q = STOCH_Q;
-        dim3 sgrid((unsigned)(((int64_t)n + BLOCK * Q - 1) / (BLOCK * Q)));
-        if (cubic)
-            hipLaunchKernelGGL((k_grid_stochastic<FMT, true, Q>), sgrid, block, 0, stream, g, q, n, key, out, idx, order,
-                               scatter);
-        else
-            hipLaunchKernelGGL((k_grid_stochastic<FMT, false, Q>), sgrid, block, 0, stream, g, q, n, key, out, idx, order,
-                               scatter);
-    } else {
-        if (cubic)
-            hipLaunchKernelGGL((k_grid_deterministic<FMT, true>), grid, block, 0, stream, g, q, n, out, order, scatter);
-        else
-            hipLaunchKernelGGL((k_grid_deterministic<FMT, false>), grid, block, 0, stream, g, q, n, out, order, scatter);
+    switch (filter) {
+    case KIND_LINEAR: launch3d_kind<FMT, KIND_LINEAR>(g, q, n, mode, key, out, idx, order, scatter, stream); break;
+    case KIND_BSPLINE: launch3d_kind<FMT, KIND_BSPLINE>(g, q, n, mode, key, out, idx, order, scatter, stream); break;
+    case KIND_KEYS: launch3d_kind<FMT, KIND_KEYS>(g, q, n, mode, key, out, idx, order, scatter, stream); break;
+    case KIND_MITCHELL: launch3d_kind<FMT, KIND_MITCHELL>(g, q, n, mode, key, out, idx, order, scatter, stream); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -352,10 +493,25 @@ hipError_t moments3d_fmt(const GridView& g, const float* q, int32_t n, int filte
                          int32_t n_seeds, double* sum, double* sumsq, hipStream_t stream)
 {
     dim3 grid(n), block(BLOCK);
-    if (filter == STF_CUBIC_BSPLINE)
-        hipLaunchKernelGGL((k_grid_moments<FMT, true>), grid, block, 0, stream, g, q, n, seed_base, n_seeds, sum, sumsq);
-    else
-        hipLaunchKernelGGL((k_grid_moments<FMT, false>), grid, block, 0, stream, g, q, n, seed_base, n_seeds, sum, sumsq);
+    switch (filter) {
+    case KIND_LINEAR:
+        hipLaunchKernelGGL((k_grid_moments<FMT, KIND_LINEAR>), grid, block, 0, stream, g, q, n, seed_base, n_seeds, sum,
+                           sumsq);
+        break;
+    case KIND_BSPLINE:
+        hipLaunchKernelGGL((k_grid_moments<FMT, KIND_BSPLINE>), grid, block, 0, stream, g, q, n, seed_base, n_seeds,
+                           sum, sumsq);
+        break;
+    case KIND_KEYS:
+        hipLaunchKernelGGL((k_grid_moments<FMT, KIND_KEYS>), grid, block, 0, stream, g, q, n, seed_base, n_seeds, sum,
+                           sumsq);
+        break;
+    case KIND_MITCHELL:
+        hipLaunchKernelGGL((k_grid_moments<FMT, KIND_MITCHELL>), grid, block, 0, stream, g, q, n, seed_base, n_seeds,
+                           sum, sumsq);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -909,7 +909,9 @@ stf_status stf_ntex_filter(const stf_neural* nt, const float* queries_dev, int64
     if (s != STF_OK) return s;
     if (!nt->ready) return stf_fail(STF_E_INVALID, "call stf_ntex_prepare_inference after training");
     if (n < 0 || n > 0x7fffffff) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
-    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE) return stf_fail(STF_E_INVALID, "unknown filter");
+    if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter");
+    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE)
+        return stf_fail(STF_E_UNSUPPORTED, "neural textures support the linear and B-spline filters only");
     if (mode != STF_DETERMINISTIC && mode != STF_STOCHASTIC) return stf_fail(STF_E_INVALID, "unknown mode");
     if (mode == STF_DETERMINISTIC && out_index_dev)
         return stf_fail(STF_E_INVALID, "out_index_dev must be NULL in deterministic mode");

@@ -374,7 +374,9 @@ stf_status validate_request(stf_server* s, const stf_texture* tex, const float* 
     if (!tex || (tex->kind != STF_KIND_GRID3D && tex->kind != STF_KIND_TEX2D))
         return stf_fail(STF_E_INVALID, "requests need a 3D grid or a 2D texture");
     if (n < 1 || n > 0x7fffffff) return stf_fail(STF_E_INVALID, "n = %lld out of range (1..2^31-1)", (long long)n);
-    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE) return stf_fail(STF_E_INVALID, "unknown filter");
+    if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter");
+    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE)
+        return stf_fail(STF_E_UNSUPPORTED, "serving supports the linear and B-spline filters only");
     if (!queries || !out) return stf_fail(STF_E_INVALID, "queries and out are required");
     if (flags & ~(uint32_t)(STF_SERVE_QUERIES_ON_DEVICE | STF_SERVE_RESULTS_ON_DEVICE))
         return stf_fail(STF_E_INVALID, "unknown flags 0x%x", flags);

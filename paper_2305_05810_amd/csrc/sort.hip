@@ -181,7 +181,7 @@ stf_status stf_filter_ordered(const stf_texture* tex, const float* sorted_querie
     if (tex->kind != STF_KIND_TEX2D && tex->kind != STF_KIND_GRID3D)
         return stf_fail(STF_E_INVALID, "stf_filter_ordered needs a 2D texture or a 3D grid");
     if (n < 0 || n > 0x7fffffff) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
-    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
+    if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
     if (mode != STF_DETERMINISTIC && mode != STF_STOCHASTIC) return stf_fail(STF_E_INVALID, "unknown mode %d", (int)mode);
     if (flags & ~(uint32_t)STF_ORDER_SCATTER) return stf_fail(STF_E_INVALID, "unknown flags 0x%x", flags);
     if (mode == STF_DETERMINISTIC && out_index_dev)

@@ -280,7 +280,7 @@ stf_status stf_filter(const stf_texture* tex, const float* queries_dev, int64_t 
     if (tex->kind != STF_KIND_TEX2D && tex->kind != STF_KIND_GRID3D)
         return stf_fail(STF_E_INVALID, "stf_filter needs a 2D texture or a 3D grid");
     if (n < 0 || n > MAX_QUERIES) return stf_fail(STF_E_INVALID, "n = %lld out of range (0..2^31-1)", (long long)n);
-    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
+    if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
     if (mode != STF_DETERMINISTIC && mode != STF_STOCHASTIC) return stf_fail(STF_E_INVALID, "unknown mode %d", (int)mode);
     if (flags != 0) return stf_fail(STF_E_INVALID, "unknown flags 0x%x", flags);
     if (mode == STF_DETERMINISTIC && out_index_dev)
@@ -311,7 +311,7 @@ stf_status stf_filter_moments(const stf_texture* tex, const float* queries_dev, 
         return stf_fail(STF_E_INVALID, "stf_filter_moments needs a 2D texture or a 3D grid");
     if (n < 0 || n > MAX_QUERIES) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
     if (n_seeds < 1) return stf_fail(STF_E_INVALID, "n_seeds = %d must be >= 1", n_seeds);
-    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
+    if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
     if (n == 0) return STF_OK;
     bool is2d = tex->kind == STF_KIND_TEX2D;
     stf_status s = check_device_ptr(queries_dev, "queries_dev", is2d ? 8 : 4);
@@ -333,7 +333,9 @@ stf_status stf_shade_filter(const stf_texture* material, const float* shade_quer
     if (!material || material->kind != STF_KIND_MATERIAL)
         return stf_fail(STF_E_INVALID, "stf_shade_filter needs a material texture");
     if (n < 0 || n > MAX_QUERIES) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
-    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
+    if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
+    if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE)
+        return stf_fail(STF_E_UNSUPPORTED, "shading supports the linear and B-spline filters only");
     if (mode != STF_SHADE_AFTER_FILTER && mode != STF_FILTER_AFTER_SHADE && mode != STF_SHADE_STOCHASTIC)
         return stf_fail(STF_E_INVALID, "unknown shade mode %d", (int)mode);
     if (mode != STF_SHADE_STOCHASTIC && out_index_dev)

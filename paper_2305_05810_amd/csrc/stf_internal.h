@@ -62,6 +62,12 @@ struct ServeChunk {
 
 // Error reporting (thread-local message).
 stf_status stf_fail(stf_status code, const char* fmt, ...);
+
+// Filters of stf_filter / stf_filter_ordered / stf_filter_moments.
+inline bool valid_filter(int f)
+{
+    return f == STF_LINEAR || f == STF_CUBIC_BSPLINE || f == STF_CUBIC_KEYS || f == STF_CUBIC_MITCHELL;
+}
 void stf_clear_error();
 
 // Kernel launchers; each returns hipSuccess or the launch error.

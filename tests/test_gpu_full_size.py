@@ -58,3 +58,46 @@ def test_full_size_parity(dev, workload, fmt):
             err = np.abs(d[qids] - od)
             assert np.all(err <= 1e-6 * np.abs(od)), err.max()
     tex.destroy()
+
+
+@pytest.mark.parametrize("gf,of", [(stf.STF_CUBIC_KEYS, oracle.KEYS), (stf.STF_CUBIC_MITCHELL, oracle.MITCHELL)])
+def test_full_size_interpolating_cubics(dev, workload, gf, of):
+    """Positivized stochastic (two taps) and 64-tap deterministic filtering
+    with the interpolating cubics on the whole batch, checked at the sampled
+    queries: indices exact, values within 1e-6 of S+|t+| + S-|t-| (stochastic)
+    and of sum |w t| (deterministic)."""
+    grid, pts, qids = workload
+    tex = stf.stf_create_sparse_grid3d(DIMS, stf.STF_FMT_F32, grid.origins, grid.values)
+    og = oracle.Grid(DIMS, oracle.F32, grid.origins, grid.values)
+    n = pts.shape[0]
+    q = torch.from_numpy(pts).to(dev)
+    out = torch.empty((n, 1), dtype=torch.float32, device=dev)
+    idx = torch.empty((n, 6), dtype=torch.int32, device=dev)
+    seed = 0xC0FFEE
+    sub = qids[:8192]
+    stf.stf_filter(tex, q, gf, stf.STF_STOCHASTIC, seed, out, idx)
+    v = out[:, 0].cpu().numpy().astype(np.float64)
+    ix = idx.cpu().numpy()
+    ov, oi = og.filter_at(pts, sub, of, oracle.STOCH, seed)
+    assert np.array_equal(ix[sub], oi)
+    scale = np.zeros(sub.size)
+    for k, qi in enumerate(sub):
+        t = (pts[qi] - np.floor(pts[qi])).astype(np.float64)
+        sp, sn = oracle.positivized_masses(of, t)
+        scale[k] = sp * abs(og.texel(*(int(c) for c in oi[k, :3])))
+        if oi[k, 3] != oracle.BAD_INDEX:
+            scale[k] += sn * abs(og.texel(*(int(c) for c in oi[k, 3:])))
+    assert np.all(np.abs(v[sub] - ov) <= 1e-6 * scale)
+    # whole batch: both taps lie in the 4^3 support of their query
+    lo = np.floor(pts).astype(np.int64)
+    off = ix[:, :3].astype(np.int64) - lo
+    assert off.min() >= -1 and off.max() <= 2
+    has = ix[:, 3] != oracle.BAD_INDEX
+    offn = ix[has, 3:].astype(np.int64) - lo[has]
+    assert offn.min() >= -1 and offn.max() <= 2
+    stf.stf_filter(tex, q, gf, stf.STF_DETERMINISTIC, 0, out)
+    d = out[:, 0].cpu().numpy().astype(np.float64)
+    od, _ = og.filter_at(pts, qids, of, oracle.DET, 0)
+    sc, _ = og.filter_at(pts, qids, of, oracle.DET_ABS, 0)
+    assert np.all(np.abs(d[qids] - od) <= 1e-6 * sc)
+    tex.destroy()

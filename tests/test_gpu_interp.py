@@ -1,0 +1,317 @@
+"""GPU parity of the interpolating cubics (K_3 with a = -1/2 and
+Mitchell-Netravali) through the C ABI against the FP64 oracle.
+
+Bar: stochastic (positivized) mode -- both drawn taps equal the oracle's for
+every query, and the value S+ t(j+) - S- t(j-) is within POS_REL of the
+oracle's relative to S+|t(j+)| + S-|t(j-)| (binary32 masses: per-axis weights
+within ~6 ulps, products of up to three masses, three more roundings);
+deterministic mode -- within 1e-6 of the oracle relative to sum_k |w_k t_k|,
+the same bar as the B-spline."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2305_05810_amd as stf
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FILTERS = [("keys", stf.STF_CUBIC_KEYS, oracle.KEYS), ("mitchell", stf.STF_CUBIC_MITCHELL, oracle.MITCHELL)]
+REL = 1e-6
+POS_REL = 1e-6
+
+
+def _decode(raw, fmt):
+    """Exact binary64 values of stored texels (tolerance scales only)."""
+    if fmt == "f32":
+        return raw.astype(np.float64)
+    if fmt == "f16":
+        return raw.view(np.float16).astype(np.float64)
+    if fmt == "bf16":
+        return (raw.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    if fmt == "u8":
+        return raw.astype(np.float64) / 255.0
+    raise ValueError(fmt)
+
+
+def _frac32(x):
+    x = np.asarray(x, np.float32)
+    return (x - np.floor(x)).astype(np.float64)
+
+
+def _axis_w(of, t):
+    return np.array([oracle.axis_weights(of, float(v)) for v in t])
+
+
+def check_positivized(gv, gi, ov, oi, scale, label):
+    gv = gv.reshape(ov.shape).astype(np.float64)
+    assert np.array_equal(gi, oi), f"{label}: {np.sum(np.any(gi != oi, axis=1))} index mismatches"
+    both_nan = np.isnan(gv) & np.isnan(ov)
+    err = np.abs(gv - ov)
+    ok = both_nan | (err <= POS_REL * scale)
+    worst = np.nanmax(np.where(scale > 0, err / np.where(scale > 0, scale, 1), 0))
+    assert ok.all(), f"{label}: {np.sum(~ok)} outside {POS_REL} (worst {worst:.3g})"
+    return worst
+
+
+def check_det(gd, od, scale, label):
+    gd = gd.reshape(od.shape).astype(np.float64)
+    both_nan = np.isnan(gd) & np.isnan(od)
+    err = np.abs(gd - od)
+    ok = both_nan | (err <= REL * scale)
+    worst = np.nanmax(np.where(scale > 0, err / np.where(scale > 0, scale, 1), 0))
+    assert ok.all(), f"{label}: {np.sum(~ok)} outside 1e-6 (worst {worst:.3g})"
+    return worst
+
+
+# ----------------------------------------------------------------------------
+# 2D
+# ----------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def tex2d_inputs():
+    tex = synth.texture2d(96, 80, 4, seed=11)
+    uv = synth.uv_queries(30000, seed=12) * np.float32(1.1) - np.float32(0.05)
+    uv[:64] = np.round(uv[:64] * 96 - 0.5) / 96 + np.float32(0.5 / 96)   # texel centres in x
+    uv[64:96] = (np.round(uv[64:96] * [96, 80] - 0.5) + 0.5) / np.array([96, 80], np.float32)   # both axes
+    uv[96:100] = [[np.nan, 0.5], [0.5, np.inf], [1e30, 0.5], [-0.7, 1.4]]
+    return tex, uv.astype(np.float32)
+
+
+def _scales2d(raw, fmt, uv, of, oi, W, H):
+    """Per query: sum_k |w_k t_k| (deterministic) and S+|t+| + S-|t-|
+    (stochastic), channel by channel."""
+    val = _decode(raw, fmt)                       # (H, W, C)
+    x = uv[:, 0] * np.float32(W) - np.float32(0.5)
+    y = uv[:, 1] * np.float32(H) - np.float32(0.5)
+    fin = np.isfinite(x) & np.isfinite(y) & (np.abs(x) < 2 ** 24) & (np.abs(y) < 2 ** 24)
+    n, C = uv.shape[0], raw.shape[2]
+    det = np.zeros((n, C))
+    pos = np.zeros((n, C))
+    for q in np.nonzero(fin)[0]:
+        ix, iy = math.floor(x[q]), math.floor(y[q])
+        tx, ty = float(x[q]) - ix, float(y[q]) - iy
+        wx, wy = oracle.axis_weights(of, tx), oracle.axis_weights(of, ty)
+        xs = np.clip(np.arange(ix - 1, ix + 3), 0, W - 1)
+        ys = np.clip(np.arange(iy - 1, iy + 3), 0, H - 1)
+        blk = val[ys][:, xs]                        # (4, 4, C)
+        det[q] = np.einsum("b,a,bac->c", np.abs(wy), np.abs(wx), np.abs(blk))
+        sp, sn = oracle.positivized_masses(of, [tx, ty])
+        s = sp * np.abs(val[oi[q, 1], oi[q, 0]])
+        if oi[q, 2] != oracle.BAD_INDEX:
+            s = s + sn * np.abs(val[oi[q, 3], oi[q, 2]])
+        pos[q] = s
+    return det, pos
+
+
+@pytest.mark.parametrize("fmt", ["f32", "f16", "u8"])
+@pytest.mark.parametrize("fname,gf,of", FILTERS)
+def test_2d_parity(dev, tex2d_inputs, fmt, fname, gf, of):
+    tex, uv = tex2d_inputs
+    raw = synth.encode(tex, fmt)
+    H, W, Cc = tex.shape
+    orc_fmt = {"f32": oracle.F32, "f16": oracle.F16, "u8": oracle.U8}[fmt]
+    t = stf.stf_create_texture2d(W, H, Cc, stf.FORMATS[fmt], [raw])
+    q = torch.from_numpy(uv).to(dev)
+    seed = 0xFEED_0042
+    gv, gi = stf.filter(t, q, gf, stf.STF_STOCHASTIC, seed, want_index=True)
+    ov, oi = oracle.filter2d(raw, orc_fmt, uv, of, oracle.STOCH, seed)
+    det_scale, pos_scale = _scales2d(raw, fmt, uv, of, oi, W, H)
+    w1 = check_positivized(gv.cpu().numpy(), gi.cpu().numpy(), ov, oi, pos_scale, f"2d {fmt} {fname} stoch")
+    gd, _ = stf.filter(t, q, gf, stf.STF_DETERMINISTIC, 0)
+    od, _ = oracle.filter2d(raw, orc_fmt, uv, of, oracle.DET)
+    w2 = check_det(gd.cpu().numpy(), od, det_scale, f"2d {fmt} {fname} det")
+    print(f"2d {fmt} {fname}: worst rel stoch {w1:.3g} det {w2:.3g}")
+    # texel centres on both axes (t = 0 exactly in binary32): Keys has no
+    # negative weight there and returns the texel; the negative index is
+    # INT32_MIN
+    with np.errstate(invalid="ignore"):
+        x = uv[:, 0] * np.float32(W) - np.float32(0.5)
+        y = uv[:, 1] * np.float32(H) - np.float32(0.5)
+        centre = (x == np.floor(x)) & (y == np.floor(y))
+    assert centre.sum() >= 10
+    if gf == stf.STF_CUBIC_KEYS:
+        assert np.all(gi.cpu().numpy()[centre][:, 2:] == oracle.BAD_INDEX)
+        assert np.array_equal(gv.cpu().numpy()[centre], gd.cpu().numpy()[centre])
+    t.destroy()
+
+
+# ----------------------------------------------------------------------------
+# 3D
+# ----------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def grid_inputs():
+    g = synth.fbm_grid((64, 64, 64), base_period=16.0, seed=7)
+    p = synth.uniform_box_queries(g.dims, 20000, seed=18, margin=3.0)
+    p[:300] = np.round(p[:300])
+    p[300:306] = [[np.nan, 1, 1], [1, np.inf, 1], [1e9, 1, 1], [0, 0, 0], [63, 63, 63], [-0.5, -0.5, -0.5]]
+    return g, p
+
+
+def _scales3d(g, fmt, p, of, oi):
+    raw = g.encoded(fmt)
+    nb = [(d + 7) // 8 for d in g.dims]
+    dense = np.zeros((nb[2] * 8 + 16, nb[1] * 8 + 16, nb[0] * 8 + 16))   # 8-voxel zero border
+    vals = _decode(raw, fmt)
+    for (ox, oy, oz), v in zip(g.origins, vals):
+        dense[oz + 8:oz + 16, oy + 8:oy + 16, ox + 8:ox + 16] = v
+    dx, dy, dz = g.dims
+    dense[8 + dz:, :, :] = 0
+    dense[:, 8 + dy:, :] = 0
+    dense[:, :, 8 + dx:] = 0
+
+    def at(x, y, z):
+        inside = (0 <= x < dx) and (0 <= y < dy) and (0 <= z < dz)
+        return dense[z + 8, y + 8, x + 8] if inside else 0.0
+
+    n = p.shape[0]
+    det = np.zeros(n)
+    pos = np.zeros(n)
+    for q in range(n):
+        if not np.all(np.isfinite(p[q])) or np.any(np.abs(p[q]) >= 2 ** 24):
+            continue
+        c = np.floor(p[q]).astype(np.int64)
+        t = _frac32(p[q])
+        w = [np.abs(oracle.axis_weights(of, float(v))) for v in t]
+        lo = c - 1
+        if np.all(lo >= -8) and np.all(lo + 4 <= np.array([dx, dy, dz]) + 8):
+            blk = np.abs(dense[lo[2] + 8:lo[2] + 12, lo[1] + 8:lo[1] + 12, lo[0] + 8:lo[0] + 12])
+            det[q] = np.einsum("c,b,a,cba->", w[2], w[1], w[0], blk)
+        sp, sn = oracle.positivized_masses(of, list(t))
+        s = sp * abs(at(*oi[q, :3]))
+        if oi[q, 3] != oracle.BAD_INDEX:
+            s += sn * abs(at(*oi[q, 3:]))
+        pos[q] = s
+    return det, pos
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+@pytest.mark.parametrize("fname,gf,of", FILTERS)
+def test_3d_parity(dev, grid_inputs, fmt, fname, gf, of):
+    g, p = grid_inputs
+    raw = g.encoded(fmt)
+    orc_fmt = {"f32": oracle.F32, "bf16": oracle.BF16}[fmt]
+    t = stf.stf_create_sparse_grid3d(g.dims, stf.FORMATS[fmt], g.origins, raw)
+    og = oracle.Grid(g.dims, orc_fmt, g.origins, raw)
+    q = torch.from_numpy(p).to(dev)
+    seed = 1234567
+    gv, gi = stf.filter(t, q, gf, stf.STF_STOCHASTIC, seed, want_index=True)
+    ov, oi = og.filter(p, of, oracle.STOCH, seed)
+    det_scale, pos_scale = _scales3d(g, fmt, p, of, oi)
+    w1 = check_positivized(gv.cpu().numpy(), gi.cpu().numpy(), ov, oi, pos_scale, f"3d {fmt} {fname} stoch")
+    gd, _ = stf.filter(t, q, gf, stf.STF_DETERMINISTIC, 0)
+    od, _ = og.filter(p, of, oracle.DET)
+    w2 = check_det(gd.cpu().numpy(), od, det_scale, f"3d {fmt} {fname} det")
+    print(f"3d {fmt} {fname}: worst rel stoch {w1:.3g} det {w2:.3g}")
+    t.destroy()
+
+
+def test_3d_ragged_and_background(dev):
+    rng = np.random.default_rng(15)
+    from tests._util import leaves_from_dense
+    field = rng.random((16, 24, 24)).astype(np.float32) - np.float32(0.3)   # signed texels
+    keep = rng.random((2, 3, 3)) < 0.7
+    o, v = leaves_from_dense(field, keep)
+    dims = (21, 19, 13)
+    inside = (o[:, 0] < dims[0]) & (o[:, 1] < dims[1]) & (o[:, 2] < dims[2])
+    o, v = o[inside], v[inside]
+    t = stf.stf_create_sparse_grid3d(dims, stf.STF_FMT_F32, o, v, background=0.5)
+    og = oracle.Grid(dims, oracle.F32, o, v, background=0.5)
+    p = synth.uniform_box_queries(dims, 8000, seed=16, margin=3.0)
+    q = torch.from_numpy(p).to(dev)
+    for fname, gf, of in FILTERS:
+        gv, gi = stf.filter(t, q, gf, stf.STF_STOCHASTIC, 21, want_index=True)
+        ov, oi = og.filter(p, of, oracle.STOCH, 21)
+        assert np.array_equal(gi.cpu().numpy(), oi), fname
+        # |texel| <= 1 here, so S+ + S- bounds the scale
+        sp_sn = np.array([sum(oracle.positivized_masses(of, list(_frac32(r)))) if np.all(np.isfinite(r)) else 1.0
+                          for r in p])
+        err = np.abs(gv.cpu().numpy()[:, 0].astype(np.float64) - ov)
+        assert np.all(err <= POS_REL * sp_sn), (fname, err.max())
+        gd, _ = stf.filter(t, q, gf, stf.STF_DETERMINISTIC, 0)
+        od, _ = og.filter(p, of, oracle.DET)
+        err = np.abs(gd.cpu().numpy()[:, 0].astype(np.float64) - od)
+        assert np.all(err <= REL * sp_sn), (fname, err.max())
+    t.destroy()
+
+
+# ----------------------------------------------------------------------------
+# unbiasedness and the ordered path
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("fname,gf,of", FILTERS)
+def test_moments_unbiased_5_sigma(dev, fname, gf, of):
+    g = synth.fbm_grid((64, 64, 64), base_period=16.0, seed=7)
+    t = stf.stf_create_sparse_grid3d(g.dims, stf.STF_FMT_F32, g.origins, g.values)
+    og = oracle.Grid(g.dims, oracle.F32, g.origins, g.values)
+    rng = np.random.default_rng(23)
+    leaf, vz, vy, vx = np.nonzero(g.values > 0)
+    pick = rng.integers(0, leaf.size, 1024)
+    vox = g.origins[leaf[pick]] + np.stack([vx[pick], vy[pick], vz[pick]], axis=1)
+    p = (vox + rng.random((1024, 3)) * 2.0 - 1.0).astype(np.float32)
+    q = torch.from_numpy(p).to(dev)
+    K = 16384
+    s1 = torch.empty(1024, dtype=torch.float64, device=dev)
+    s2 = torch.empty_like(s1)
+    stf.stf_filter_moments(t, q, gf, 500, K, s1, s2)
+    s1, s2 = s1.cpu().numpy(), s2.cpu().numpy()
+    mean, var = og.moments(p, of)
+    live = var > 1e-12
+    assert live.sum() > 900
+    z = (s1 / K - mean)[live] / np.sqrt(var[live] / K)
+    assert np.all(np.abs(z) < 5.0), np.abs(z).max()
+    v_hat = s2 / K - (s1 / K) ** 2
+    assert 0.95 < v_hat[live].sum() / var[live].sum() < 1.05
+    t.destroy()
+
+
+@pytest.mark.parametrize("fname,gf,of", FILTERS)
+def test_moments_2d_unbiased_5_sigma(dev, fname, gf, of):
+    tex = synth.texture2d(32, 32, 4, seed=31)
+    uv = synth.uv_queries(512, seed=32)
+    t = stf.stf_create_texture2d(32, 32, 4, stf.STF_FMT_F32, [tex])
+    q = torch.from_numpy(uv).to(dev)
+    K = 8192
+    s1 = torch.empty(512, dtype=torch.float64, device=dev)
+    s2 = torch.empty_like(s1)
+    stf.stf_filter_moments(t, q, gf, 77, K, s1, s2)
+    mean, var = oracle.moments2d(tex, oracle.F32, uv, of)
+    mean, var = mean[:, 0], var[:, 0]
+    live = var > 1e-12
+    z = (s1.cpu().numpy() / K - mean)[live] / np.sqrt(var[live] / K)
+    assert live.sum() > 400 and np.all(np.abs(z) < 5.0), np.abs(z).max()
+    t.destroy()
+
+
+@pytest.mark.parametrize("fname,gf,of", FILTERS)
+def test_ordered_stream_equals_unsorted(dev, grid_inputs, fname, gf, of):
+    g, p = grid_inputs
+    t = stf.stf_create_sparse_grid3d(g.dims, stf.STF_FMT_F32, g.origins, g.values)
+    q = torch.from_numpy(p).to(dev)
+    a, ia = stf.filter(t, q, gf, stf.STF_STOCHASTIC, 9, want_index=True)
+    sq, order = stf.sort_queries(t, q)
+    out = torch.empty_like(a)
+    idx = torch.empty_like(ia)
+    stf.stf_filter_ordered(t, sq, order, gf, stf.STF_STOCHASTIC, 9, out, idx, stf.STF_ORDER_SCATTER)
+    assert torch.equal(idx, ia) and torch.equal(out.nan_to_num(3.5), a.nan_to_num(3.5))
+    t.destroy()
+
+
+def test_unsupported_paths_and_small_index_buffer(dev):
+    g = synth.fbm_grid((32, 32, 32), base_period=8.0, seed=2)
+    t = stf.stf_create_sparse_grid3d(g.dims, stf.STF_FMT_F32, g.origins, g.values)
+    q = torch.zeros((8, 3), dtype=torch.float32, device=dev)
+    out = torch.empty((8, 1), dtype=torch.float32, device=dev)
+    with pytest.raises(ValueError):   # the binding refuses an (n, 3) index buffer for a two-tap filter
+        stf.stf_filter(t, q, stf.STF_CUBIC_KEYS, stf.STF_STOCHASTIC, 0, out,
+                       torch.empty((8, 3), dtype=torch.int32, device=dev))
+    L = stf.lib()
+    lv = synth.material_levels(64, seed=3, levels=1)
+    m = stf.stf_create_material2d(64, 64, lv)
+    sq = torch.zeros((8, 9), dtype=torch.float32, device=dev)
+    rgb = torch.empty((8, 3), dtype=torch.float32, device=dev)
+    rc = L.stf_shade_filter(m.handle, sq.data_ptr(), 8, stf.STF_CUBIC_KEYS, 0, 0, rgb.data_ptr(), None, None)
+    assert rc == stf.STF_E_UNSUPPORTED
+    m.destroy()
+    t.destroy()

@@ -309,3 +309,18 @@ def test_reuse_sampler_is_2d_only():
     g = oracle.Grid((8, 8, 8), oracle.F32, np.zeros((1, 3), np.int32), np.zeros((1, 8, 8, 8), np.float32))
     with pytest.raises(ValueError):
         g.filter(np.zeros((1, 3), np.float32), oracle.KEYS, oracle.STOCH_REUSE)
+
+
+@pytest.mark.parametrize("f", FILTERS + [pytest.param(oracle.CUBIC, id="bspline")])
+def test_abs_scale_bounds_the_value(f):
+    """DET_ABS = sum |w||t| >= |F|, with equality for non-negative weights
+    and texels."""
+    rng = np.random.default_rng(10)
+    tex = (rng.random((12, 12, 2)) - 0.3).astype(np.float32)
+    uv = rng.random((300, 2)).astype(np.float32)
+    d, _ = oracle.filter2d(tex, oracle.F32, uv, f, oracle.DET)
+    a, _ = oracle.filter2d(tex, oracle.F32, uv, f, oracle.DET_ABS)
+    assert np.all(a >= np.abs(d) - 1e-15)
+    pos, _ = oracle.filter2d(np.abs(tex), oracle.F32, uv, oracle.CUBIC, oracle.DET)
+    apos, _ = oracle.filter2d(np.abs(tex), oracle.F32, uv, oracle.CUBIC, oracle.DET_ABS)
+    assert np.allclose(pos, apos, rtol=1e-14)
