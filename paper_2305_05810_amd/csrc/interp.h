@@ -115,57 +115,108 @@ struct PosDraw {
     float sp, sn;  // binary32 masses S+ and S-, scaled by axis_scale^D
 };
 
+// Sign patterns of each set in increasing order (bit a set: axis a takes
+// its negative part): even patterns for w+, odd ones for w-.
+template <int D>
+__device__ __forceinline__ int pattern_bits(int set, int j)
+{
+    if constexpr (D == 2) return set == 0 ? (j == 0 ? 0 : 3) : (j == 0 ? 1 : 2);
+    else
+        return set == 0 ? (j == 0 ? 0 : (j == 1 ? 3 : (j == 2 ? 5 : 6)))
+                        : (j == 0 ? 1 : (j == 1 ? 2 : (j == 2 ? 4 : 7)));
+}
+
+// Mass of pattern b: the per-axis masses multiplied from axis 0 up.
+template <int D>
+__device__ __forceinline__ float pattern_mass(const float (&P)[D], const float (&N)[D], int b)
+{
+    float m = (b & 1) ? N[0] : P[0];
+#pragma unroll
+    for (int a = 1; a < D; ++a) m = m * (((b >> a) & 1) ? N[a] : P[a]);
+    return m;
+}
+
+// Per-axis draws from the positive and the negative part of the weights w
+// (scaled), each the cumulative rule over the four taps, returning the tap
+// offset -1..2.  Both kernels have positive inner weights (taps i, i+1), so
+// the negative part lives on the outer taps only; with its zero middle
+// masses the four-tap rule reduces exactly to a two-way choice between
+// offsets -1 and +2 (the partial sums n0, n0 + 0, n0 + 0 coincide).  For
+// KEYS the outer weights are never positive, and the positive part likewise
+// reduces to a two-way choice between offsets 0 and +1.
+template <int KIND>
+__device__ __forceinline__ int pick_positive(const float (&w)[4], float P, float u)
+{
+    if constexpr (KIND == KIND_KEYS) {
+        const float T = u * P;
+        const int j = (T >= w[1]) ? 1 : 0;
+        return (w[2] > 0.0f) ? j : 0;
+    } else {
+        float m[4] = {w[0] > 0.0f ? w[0] : 0.0f, w[1], w[2], w[3] > 0.0f ? w[3] : 0.0f};
+        return cumulative_pick<4>(m, u) - 1;
+    }
+}
+
+__device__ __forceinline__ int pick_negative(float n0, float n3, float N, float u)
+{
+    const float T = u * N;
+    const bool upper = (T >= n0) && (n3 > 0.0f);
+    return upper ? 2 : -1;
+}
+
+// The uniform of hash index a >= 1 of a query: pcg(h0 + a) with the first
+// multiply-add shared, (h0 + a) M + C = (h0 M + C) + a M (mod 2^32), where
+// base = h0 M + C.
+__device__ __forceinline__ float uniform_from_base(uint32_t base, uint32_t a)
+{
+    const uint32_t state = base + a * 747796405u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return hash_uniform((word >> 22u) ^ word);
+}
+
 // Both draws of one query; h0 = pcg(key ^ qid) is the query's first hash.
+// All array indices are compile-time constants after unrolling; the pattern
+// picked at run time only steers selects.
 template <int D, int KIND>
 __device__ __forceinline__ PosDraw<D> positivized_draw(const float (&t)[D], uint32_t h0)
 {
     constexpr int NP = 1 << (D - 1);   // patterns per sign set
-    float part[2][D][4], mass[2][D];
+    float w[D][4], n0[D], n3[D], P[D], N[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        float w[4];
-        interp_weights<KIND>(t[a], w);
-        mass[0][a] = 0.0f;
-        mass[1][a] = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            part[0][a][k] = w[k] > 0.0f ? w[k] : 0.0f;
-            part[1][a][k] = w[k] < 0.0f ? -w[k] : 0.0f;
-            mass[0][a] += part[0][a][k];
-            mass[1][a] += part[1][a][k];
+        interp_weights<KIND>(t[a], w[a]);
+        n0[a] = w[a][0] < 0.0f ? -w[a][0] : 0.0f;
+        n3[a] = w[a][3] < 0.0f ? -w[a][3] : 0.0f;
+        // masses in tap order, zero terms included where they can be nonzero
+        if constexpr (KIND == KIND_KEYS) {
+            P[a] = w[a][1] + w[a][2];
+        } else {
+            P[a] = (((w[a][0] > 0.0f ? w[a][0] : 0.0f) + w[a][1]) + w[a][2]) + (w[a][3] > 0.0f ? w[a][3] : 0.0f);
         }
+        N[a] = n0[a] + n3[a];
     }
+    const uint32_t base = h0 * 747796405u + 2891336453u;
     PosDraw<D> r;
 #pragma unroll
     for (int set = 0; set < 2; ++set) {
-        int pat[NP];
         float pm[NP];
-        int np = 0;
 #pragma unroll
-        for (int b = 0; b < (1 << D); ++b) {
-            if ((__builtin_popcount((unsigned)b) & 1) != set) continue;
-            float m = mass[b & 1][0];
-#pragma unroll
-            for (int a = 1; a < D; ++a) m = m * mass[(b >> a) & 1][a];
-            pat[np] = b;
-            pm[np] = m;
-            ++np;
-        }
+        for (int j = 0; j < NP; ++j) pm[j] = pattern_mass<D>(P, N, pattern_bits<D>(set, j));
         float total = pm[0];
 #pragma unroll
-        for (int i = 1; i < NP; ++i) total += pm[i];
+        for (int j = 1; j < NP; ++j) total += pm[j];
         const uint32_t ubase = set == 0 ? 0u : 5u, ucomp = set == 0 ? 4u : 8u;
-        const int b = pat[cumulative_pick<NP>(pm, axis_uniform(h0, ucomp))];
+        const int b = pattern_bits<D>(set, cumulative_pick<NP>(pm, uniform_from_base(base, ucomp)));
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const int sel = (b >> a) & 1;
-            float pa[4] = {part[sel][a][0], part[sel][a][1], part[sel][a][2], part[sel][a][3]};
-            const int o = cumulative_pick<4>(pa, axis_uniform(h0, ubase + (uint32_t)a)) - 1;
+            const float u = ubase + a == 0 ? hash_uniform(h0) : uniform_from_base(base, ubase + (uint32_t)a);
+            const int o = ((b >> a) & 1) ? pick_negative(n0[a], n3[a], N[a], u) : pick_positive<KIND>(w[a], P[a], u);
             if (set == 0) r.op[a] = o;
             else r.on[a] = o;
         }
-        if (set == 0) r.sp = total;
-        else {
+        if (set == 0) {
+            r.sp = total;
+        } else {
             r.sn = total;
             r.neg = total > 0.0f;
         }
