@@ -238,7 +238,7 @@ def positivized_scale(oracle, og, pts, oi, ofilt):
     for k in range(pts.shape[0]):
         if not np.all(np.isfinite(pts[k])) or np.any(np.abs(pts[k]) >= 2 ** 24):
             continue
-        t = (pts[k] - np.floor(pts[k])).astype(np.float64)
+        t = pts[k].astype(np.float64) - np.floor(pts[k].astype(np.float64))
         sp, sn = oracle.positivized_masses(ofilt, t)
         s = sp * abs(og.texel(*(int(v) for v in oi[k, :3])))
         if oi[k, 3] != oracle.BAD_INDEX:

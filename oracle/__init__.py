@@ -83,6 +83,14 @@ def _declare(L):
     L.orc_filter3d_brute.restype = i32
     L.orc_filter3d_moments.argtypes = [vp, vp, i64, i32, vp, vp, i32]
     L.orc_filter3d_moments.restype = i32
+    L.orc_dct_coefficient.argtypes, L.orc_dct_coefficient.restype = [vp, i32, i32], dbl
+    L.orc_dct_dequant.argtypes, L.orc_dct_dequant.restype = [u32, i32], dbl
+    L.orc_dct_encode.argtypes, L.orc_dct_encode.restype = [vp, i32, i32, i32, vp], i32
+    L.orc_dct_texel.argtypes, L.orc_dct_texel.restype = [vp, i32, i32, i32, i32, i32], dbl
+    L.orc_dct_filter2d.argtypes = [vp, i32, i32, i32, vp, i64, i32, i32, u64, vp, vp, i32]
+    L.orc_dct_filter2d.restype = i32
+    L.orc_dct_moments2d.argtypes = [vp, i32, i32, i32, vp, i64, i32, vp, vp, i32]
+    L.orc_dct_moments2d.restype = i32
     if hasattr(L, "orc_shade"):
         _declare_shade(L)
     if hasattr(L, "orc_ntex_decode"):
@@ -256,6 +264,72 @@ def filter2d_brute(tex: np.ndarray, fmt: int, uv: np.ndarray, filt: int) -> np.n
     out = np.empty((uv.shape[0], Ch), np.float64)
     lib().orc_filter2d_brute(_p(tex), W, H, Ch, fmt, _p(uv), uv.shape[0], filt, _p(out))
     return out
+
+
+# ----------------------------------------------------------------------------
+# DCT-compressed textures
+# ----------------------------------------------------------------------------
+def dct_coefficient(block: np.ndarray, u: int, v: int) -> float:
+    """Orthonormal DCT-II coefficient F(u, v) of an 8x8 block f[y][x]."""
+    b = np.ascontiguousarray(block, np.float64)
+    assert b.shape == (8, 8)
+    return lib().orc_dct_coefficient(_p(b), u, v)
+
+
+def dct_dequant(word: int, k: int) -> float:
+    return lib().orc_dct_dequant(word & 0xFFFFFFFF, k)
+
+
+def dct_encode(texels: np.ndarray) -> np.ndarray:
+    """(H, W, C) uint8 texels -> (H/8, W/8, C) uint32 words."""
+    t = np.ascontiguousarray(texels, np.uint8)
+    H, W, Ch = t.shape
+    out = np.zeros((H // 8, W // 8, Ch), np.uint32)
+    if lib().orc_dct_encode(_p(t), W, H, Ch, _p(out)) != 0:
+        raise ValueError("orc_dct_encode rejected its arguments")
+    return out
+
+
+def dct_texel(blocks: np.ndarray, x: int, y: int, c: int) -> float:
+    b = np.ascontiguousarray(blocks, np.uint32)
+    return lib().orc_dct_texel(_p(b), b.shape[1] * 8, b.shape[2], x, y, c)
+
+
+def dct_decode_all(blocks: np.ndarray) -> np.ndarray:
+    b = np.ascontiguousarray(blocks, np.uint32)
+    H, W, Ch = b.shape[0] * 8, b.shape[1] * 8, b.shape[2]
+    L = lib()
+    out = np.empty((H, W, Ch))
+    for y in range(H):
+        for x in range(W):
+            for c in range(Ch):
+                out[y, x, c] = L.orc_dct_texel(_p(b), W, Ch, x, y, c)
+    return out
+
+
+def dct_filter2d(blocks: np.ndarray, uv: np.ndarray, filt: int, mode: int, seed: int = 0, want_index: bool = True,
+                 nthreads: int = 0):
+    b = np.ascontiguousarray(blocks, np.uint32)
+    H, W, Ch = b.shape[0] * 8, b.shape[1] * 8, b.shape[2]
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    n = uv.shape[0]
+    out = np.empty((n, Ch), np.float64)
+    idx = np.empty((n, index_width(filt, 2)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE)) else None
+    if lib().orc_dct_filter2d(_p(b), W, H, Ch, _p(uv), n, filt, mode, seed, _p(out), _p(idx), nthreads) != 0:
+        raise ValueError("orc_dct_filter2d rejected its arguments")
+    return out, idx
+
+
+def dct_moments2d(blocks: np.ndarray, uv: np.ndarray, filt: int, nthreads: int = 0):
+    b = np.ascontiguousarray(blocks, np.uint32)
+    H, W, Ch = b.shape[0] * 8, b.shape[1] * 8, b.shape[2]
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    n = uv.shape[0]
+    mean = np.empty((n, Ch))
+    var = np.empty((n, Ch))
+    if lib().orc_dct_moments2d(_p(b), W, H, Ch, _p(uv), n, filt, _p(mean), _p(var), nthreads) != 0:
+        raise ValueError("orc_dct_moments2d rejected its arguments")
+    return mean, var
 
 
 # ----------------------------------------------------------------------------

@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oracle.c", "shade.c", "neural.c"]
+SOURCES = ["oracle.c", "shade.c", "neural.c", "dct.c"]
 TARGET = os.path.join(HERE, "liboracle.so")
 
 

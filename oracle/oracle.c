@@ -489,11 +489,28 @@ int orc_positivized_wrs2d(int filter, double tx, double ty, double u, int* off_p
 /* ------------------------------------------------------------------------ */
 static int orc_clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+/* A 2D texel source: stored texels of a format, or DCT-compressed blocks
+ * (dct.c).  Taps are clamped to the texture before they are read. */
+typedef struct orc_src2d {
+    const void* tex;
+    int W, H, C, fmt;   /* fmt: a storage format, or ORC_FMT_DCT */
+} orc_src2d;
+
+#define ORC_FMT_DCT 100
+double orc_dct_texel(const uint32_t* blocks, int W, int C, int x, int y, int c);
+
+static double orc_src_texel(const orc_src2d* s, int x, int y, int c)
+{
+    x = orc_clampi(x, 0, s->W - 1);
+    y = orc_clampi(y, 0, s->H - 1);
+    if (s->fmt == ORC_FMT_DCT) return orc_dct_texel((const uint32_t*)s->tex, s->W, s->C, x, y, c);
+    return orc_decode(s->fmt, s->tex, ((int64_t)y * s->W + x) * s->C + c);
+}
+
 static double orc_texel2d(const void* tex, int W, int H, int C, int fmt, int x, int y, int c)
 {
-    x = orc_clampi(x, 0, W - 1);
-    y = orc_clampi(y, 0, H - 1);
-    return orc_decode(fmt, tex, ((int64_t)y * W + x) * C + c);
+    orc_src2d s = {tex, W, H, C, fmt};
+    return orc_src_texel(&s, x, y, c);
 }
 
 static int orc_raster2d(const float* uv, int W, int H, float* x, float* y)
@@ -519,9 +536,10 @@ static int orc_index_width(int filter, int dims) { return orc_positivized(filter
  * with the tensor-product weights), ORC_STOCH (one tap per Eq.
  * stochastic-sum, or the two taps of positivization), ORC_STOCH_REUSE (the
  * paper's listing samplers). */
-static void orc_query2d(const void* tex, int W, int H, int C, int fmt, const float* uv,
-                        int filter, int mode, uint64_t seed, uint32_t qid, double* out, int32_t* idx)
+static void orc_query2d(const orc_src2d* src, const float* uv, int filter, int mode, uint64_t seed, uint32_t qid,
+                        double* out, int32_t* idx)
 {
+    const int W = src->W, H = src->H, C = src->C;
     float x, y, tx, ty;
     int ix, iy;
     orc_raster2d(uv, W, H, &x, &y);
@@ -541,7 +559,7 @@ static void orc_query2d(const void* tex, int W, int H, int C, int fmt, const flo
             for (int b = 0; b < ntap; ++b) {
                 double row = 0.0;
                 for (int a = 0; a < ntap; ++a) {
-                    double v = orc_texel2d(tex, W, H, C, fmt, ix + base + a, iy + base + b, c);
+                    double v = orc_src_texel(src, ix + base + a, iy + base + b, c);
                     row += ab ? fabs(wx[a]) * fabs(v) : wx[a] * v;
                 }
                 acc += (ab ? fabs(wy[b]) : wy[b]) * row;
@@ -557,13 +575,13 @@ static void orc_query2d(const void* tex, int W, int H, int C, int fmt, const flo
             neg = orc_positivized_taps(filter, 2, t2, seed, qid, op, on);
         else
             neg = orc_positivized_wrs2d(filter, (double)tx, (double)ty, (double)orc_uniform(seed, qid, 0), op, on);
-        double tt[2] = {(double)tx, (double)ty}, Sp, Sn;
+        double tt[2] = {(double)x - floor((double)x), (double)y - floor((double)y)}, Sp, Sn;   /* exact offsets */
         orc_positivized_masses(filter, 2, tt, &Sp, &Sn);
         int px = orc_clampi(ix + op[0], 0, W - 1), py = orc_clampi(iy + op[1], 0, H - 1);
         int nx = orc_clampi(ix + on[0], 0, W - 1), ny = orc_clampi(iy + on[1], 0, H - 1);
         for (int c = 0; c < C; ++c) {
-            double v = Sp * orc_texel2d(tex, W, H, C, fmt, px, py, c);
-            if (neg) v -= Sn * orc_texel2d(tex, W, H, C, fmt, nx, ny, c);
+            double v = Sp * orc_src_texel(src, px, py, c);
+            if (neg) v -= Sn * orc_src_texel(src, nx, ny, c);
             out[c] = v;
         }
         if (idx) {
@@ -583,7 +601,7 @@ static void orc_query2d(const void* tex, int W, int H, int C, int fmt, const flo
         jy = orc_select_reuse(filter, ty, &u);
     }
     int sx = orc_clampi(ix + jx, 0, W - 1), sy = orc_clampi(iy + jy, 0, H - 1);
-    for (int c = 0; c < C; ++c) out[c] = orc_texel2d(tex, W, H, C, fmt, sx, sy, c);
+    for (int c = 0; c < C; ++c) out[c] = orc_src_texel(src, sx, sy, c);
     if (idx) { idx[0] = sx; idx[1] = sy; }
 }
 
@@ -599,17 +617,33 @@ static int orc_threads(int nthreads)
 
 int orc_max_threads(void) { return orc_threads(0); }
 
+static int orc_filter_src2d(const orc_src2d* src, const float* uv, int64_t n, int filter, int mode, uint64_t seed,
+                            double* out, int32_t* idx, int nthreads)
+{
+    int nt = orc_threads(nthreads), iw = orc_index_width(filter, 2), C = src->C;
+    (void)nt;
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t q = 0; q < n; ++q)
+        orc_query2d(src, uv + 2 * q, filter, mode, seed, (uint32_t)q, out + q * C, idx ? idx + iw * q : NULL);
+    return 0;
+}
+
+/* DCT-compressed textures (blocks as written by orc_dct_encode). */
+int orc_dct_filter2d(const uint32_t* blocks, int W, int H, int C, const float* uv, int64_t n, int filter, int mode,
+                     uint64_t seed, double* out, int32_t* idx, int nthreads)
+{
+    if (W <= 0 || H <= 0 || W % 8 || H % 8 || C <= 0 || C > 16 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL)
+        return -1;
+    orc_src2d src = {blocks, W, H, C, ORC_FMT_DCT};
+    return orc_filter_src2d(&src, uv, n, filter, mode, seed, out, idx, nthreads);
+}
+
 int orc_filter2d(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n,
                  int filter, int mode, uint64_t seed, double* out, int32_t* idx, int nthreads)
 {
     if (W <= 0 || H <= 0 || C <= 0 || C > 4 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
-    int nt = orc_threads(nthreads), iw = orc_index_width(filter, 2);
-    (void)nt;
-#pragma omp parallel for schedule(static) num_threads(nt)
-    for (int64_t q = 0; q < n; ++q)
-        orc_query2d(tex, W, H, C, fmt, uv + 2 * q, filter, mode, seed, (uint32_t)q,
-                    out + q * C, idx ? idx + iw * q : NULL);
-    return 0;
+    orc_src2d src = {tex, W, H, C, fmt};
+    return orc_filter_src2d(&src, uv, n, filter, mode, seed, out, idx, nthreads);
 }
 
 /* Brute-force deterministic 2D filter: every texel of a 6x6 window around the
@@ -731,7 +765,8 @@ static void orc_query3d(const orc_grid* g, const float* p, int filter, int mode,
     if (orc_positivized(filter)) {
         int op[3], on[3];
         int neg = orc_positivized_taps(filter, 3, t, seed, qid, op, on);
-        double tt[3] = {(double)t[0], (double)t[1], (double)t[2]}, Sp, Sn;
+        double tt[3], Sp, Sn;   /* exact offsets */
+        for (int a = 0; a < 3; ++a) tt[a] = (double)p[a] - floor((double)p[a]);
         orc_positivized_masses(filter, 3, tt, &Sp, &Sn);
         double v = Sp * orc_grid_texel(g, i[0] + op[0], i[1] + op[1], i[2] + op[2]);
         if (neg) v -= Sn * orc_grid_texel(g, i[0] + on[0], i[1] + on[1], i[2] + on[2]);
@@ -865,10 +900,10 @@ int orc_filter3d_moments(const orc_grid* g, const float* p, int64_t n, int filte
 }
 
 /* The same for 2D textures, per channel (n x C outputs). */
-int orc_filter2d_moments(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n, int filter,
-                         double* mean, double* var, int nthreads)
+static int orc_moments_src2d(const orc_src2d* src, const float* uv, int64_t n, int filter, double* mean, double* var,
+                             int nthreads)
 {
-    if (W <= 0 || H <= 0 || C <= 0 || C > 4 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
+    const int W = src->W, H = src->H, C = src->C;
     int nt = orc_threads(nthreads);
     (void)nt;
 #pragma omp parallel for schedule(static) num_threads(nt)
@@ -881,16 +916,33 @@ int orc_filter2d_moments(const void* tex, int W, int H, int C, int fmt, const fl
             continue;
         }
         double wx[4], wy[4];
-        orc_axis_weights(filter, (double)tx, wx);
-        orc_axis_weights(filter, (double)ty, wy);
+        orc_axis_weights(filter, (double)x - floor((double)x), wx);   /* exact offsets */
+        orc_axis_weights(filter, (double)y - floor((double)y), wy);
         int base = (filter == ORC_LINEAR) ? 0 : -1, ntap = (filter == ORC_LINEAR) ? 2 : 4;
         for (int c = 0; c < C; ++c) {
             orc_moment_acc m = {0, 0, 0, 0, 0, 0};
             for (int b = 0; b < ntap; ++b)
                 for (int a = 0; a < ntap; ++a)
-                    orc_moment_add(&m, wx[a] * wy[b], orc_texel2d(tex, W, H, C, fmt, ix + base + a, iy + base + b, c));
+                    orc_moment_add(&m, wx[a] * wy[b], orc_src_texel(src, ix + base + a, iy + base + b, c));
             orc_moment_finish(&m, filter, &mean[q * C + c], &var[q * C + c]);
         }
     }
     return 0;
+}
+
+int orc_filter2d_moments(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n, int filter,
+                         double* mean, double* var, int nthreads)
+{
+    if (W <= 0 || H <= 0 || C <= 0 || C > 4 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
+    orc_src2d src = {tex, W, H, C, fmt};
+    return orc_moments_src2d(&src, uv, n, filter, mean, var, nthreads);
+}
+
+int orc_dct_moments2d(const uint32_t* blocks, int W, int H, int C, const float* uv, int64_t n, int filter,
+                      double* mean, double* var, int nthreads)
+{
+    if (W <= 0 || H <= 0 || W % 8 || H % 8 || C <= 0 || C > 16 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL)
+        return -1;
+    orc_src2d src = {blocks, W, H, C, ORC_FMT_DCT};
+    return orc_moments_src2d(&src, uv, n, filter, mean, var, nthreads);
 }

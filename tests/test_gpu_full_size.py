@@ -82,7 +82,7 @@ def test_full_size_interpolating_cubics(dev, workload, gf, of):
     assert np.array_equal(ix[sub], oi)
     scale = np.zeros(sub.size)
     for k, qi in enumerate(sub):
-        t = (pts[qi] - np.floor(pts[qi])).astype(np.float64)
+        t = pts[qi].astype(np.float64) - np.floor(pts[qi].astype(np.float64))
         sp, sn = oracle.positivized_masses(of, t)
         scale[k] = sp * abs(og.texel(*(int(c) for c in oi[k, :3])))
         if oi[k, 3] != oracle.BAD_INDEX:

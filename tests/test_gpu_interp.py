@@ -38,8 +38,9 @@ def _decode(raw, fmt):
 
 
 def _frac32(x):
-    x = np.asarray(x, np.float32)
-    return (x - np.floor(x)).astype(np.float64)
+    """Exact fractional offsets of binary32 coordinates."""
+    x = np.asarray(x, np.float32).astype(np.float64)
+    return x - np.floor(x)
 
 
 def _axis_w(of, t):
