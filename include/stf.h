@@ -172,6 +172,38 @@ stf_status stf_filter(const stf_texture* tex, const float* queries_dev, int64_t 
                       float* out_dev, int32_t* out_index_dev, uint32_t flags, void* hip_stream);
 
 /* ---------------------------------------------------------------------- */
+/* DCT-compressed textures                                                 */
+/* ---------------------------------------------------------------------- */
+/* A texture of 8x8 texel blocks, each channel of a block stored as one
+ * 32-bit word: the six lowest-frequency coefficients of its orthonormal 2D
+ * DCT (section "Results", texture compression), 16x smaller than 8-bit
+ * texels.  A lookup decodes single texels, so stochastic filtering decodes
+ * one texel per lookup where deterministic bilinear / bicubic decode 4 / 16.
+ *
+ * Word layout: bits 0..6 DC code d (value d * 8/127), then five 5-bit AC
+ * codes (bits 7..11, 12..16, 17..21, 22..26, 27..31) for the coefficients
+ * (v, u) = (0,1), (1,0), (2,0), (1,1), (0,2) (v vertical, u horizontal
+ * frequency), each q + 16 with q in -15..15 (value q * 2/15).  A decoded
+ * texel is the inverse DCT of these six coefficients (not clamped); the
+ * device decodes in binary32. */
+
+/* Encodes width x height x channels 8-bit texels (row-major, channels
+ * interleaved, value v/255) into (height/8)(width/8) channels words (blocks
+ * row-major, channel words consecutive) on the host: DCT in binary64, codes
+ * rounded to nearest (halves away from zero) and saturated.  width and
+ * height: multiples of 8 up to 65536; channels 1..16. */
+stf_status stf_dct_encode(int32_t width, int32_t height, int32_t channels, const uint8_t* texels_host,
+                          uint32_t* blocks_host);
+
+/* Creates a DCT texture from words laid out as stf_dct_encode writes them
+ * (copied; may be freed on return).  Filter it with stf_filter /
+ * stf_filter_ordered / stf_filter_moments and uv queries (raster rules and
+ * clamping of stf_create_texture2d); results are channels binary32 per
+ * query.  Not usable with shading, neural or serving calls. */
+stf_status stf_create_dct_texture2d(int32_t width, int32_t height, int32_t channels, const uint32_t* blocks_host,
+                                    stf_texture** out);
+
+/* ---------------------------------------------------------------------- */
 /* Morton-ordered query streams                                            */
 /* ---------------------------------------------------------------------- */
 /* Device workspace (bytes) that stf_sort_queries needs for n queries. */

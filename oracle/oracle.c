@@ -641,7 +641,7 @@ int orc_dct_filter2d(const uint32_t* blocks, int W, int H, int C, const float* u
 int orc_filter2d(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n,
                  int filter, int mode, uint64_t seed, double* out, int32_t* idx, int nthreads)
 {
-    if (W <= 0 || H <= 0 || C <= 0 || C > 4 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
+    if (W <= 0 || H <= 0 || C <= 0 || C > 16 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
     orc_src2d src = {tex, W, H, C, fmt};
     return orc_filter_src2d(&src, uv, n, filter, mode, seed, out, idx, nthreads);
 }
@@ -933,7 +933,7 @@ static int orc_moments_src2d(const orc_src2d* src, const float* uv, int64_t n, i
 int orc_filter2d_moments(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n, int filter,
                          double* mean, double* var, int nthreads)
 {
-    if (W <= 0 || H <= 0 || C <= 0 || C > 4 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
+    if (W <= 0 || H <= 0 || C <= 0 || C > 16 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
     orc_src2d src = {tex, W, H, C, fmt};
     return orc_moments_src2d(&src, uv, n, filter, mean, var, nthreads);
 }

@@ -75,8 +75,11 @@ def _declare(L):
     L.stf_filter.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, u32, vp]
     L.stf_filter_moments.argtypes = [vp, vp, i64, i32, u64, i32, vp, vp, vp]
     L.stf_shade_filter.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, vp]
+    L.stf_dct_encode.argtypes = [i32, i32, i32, vp, vp]
+    L.stf_create_dct_texture2d.argtypes = [i32, i32, i32, vp, C.POINTER(vp)]
     for name in ("stf_create_texture2d", "stf_create_material2d", "stf_create_sparse_grid3d",
-                 "stf_texture_bytes", "stf_filter", "stf_filter_moments", "stf_shade_filter"):
+                 "stf_texture_bytes", "stf_filter", "stf_filter_moments", "stf_shade_filter", "stf_dct_encode",
+                 "stf_create_dct_texture2d"):
         getattr(L, name).restype = i32
 
 
@@ -147,6 +150,28 @@ def stf_create_texture2d(width: int, height: int, channels: int, fmt: int,
     h = C.c_void_p()
     _check(lib().stf_create_texture2d(width, height, channels, fmt, len(lv), arr, C.byref(h)))
     return Texture(h.value, "tex2d", channels, 2)
+
+
+def stf_dct_encode(texels: np.ndarray) -> np.ndarray:
+    """(H, W, C) uint8 texels (H, W multiples of 8, C <= 16) -> (H/8, W/8, C)
+    uint32 DCT block words, encoded by the library on the host."""
+    t = _host(np.ascontiguousarray(texels, np.uint8))
+    if t.ndim != 3:
+        raise ValueError("texels must be (H, W, C)")
+    H, W, Ch = t.shape
+    out = np.zeros((max(H // 8, 0), max(W // 8, 0), Ch), np.uint32)
+    _check(lib().stf_dct_encode(W, H, Ch, t.ctypes.data, out.ctypes.data))
+    return out
+
+
+def stf_create_dct_texture2d(width: int, height: int, channels: int, blocks: np.ndarray) -> Texture:
+    """blocks: (height/8, width/8, channels) uint32 DCT words."""
+    b = _host(np.ascontiguousarray(blocks, np.uint32))
+    if b.size != (width // 8) * (height // 8) * channels:
+        raise ValueError(f"blocks hold {b.size} words, {(width // 8) * (height // 8) * channels} needed")
+    h = C.c_void_p()
+    _check(lib().stf_create_dct_texture2d(width, height, channels, b.ctypes.data, C.byref(h)))
+    return Texture(h.value, "dct2d", channels, 2)
 
 
 def stf_create_material2d(width: int, height: int, level_texels: Sequence[np.ndarray]) -> Texture:

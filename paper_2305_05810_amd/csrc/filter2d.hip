@@ -1,17 +1,22 @@
-// filter2d.hip -- bilinear / bicubic B-spline filtering of dense 2D textures,
+// filter2d.hip -- filtering of 2D textures: bilinear / bicubic B-spline,
 // deterministic (all 4 / 16 taps, Eq. filtered-texture with tensor-product
 // weights) and stochastic (one tap per query, Eq. stochastic-sum with the
 // per-axis draw of Eq. stochastic-bilerp / the bicubic sampling of section
-// "B-Spline and Anisotropic Filters").
+// "B-Spline and Anisotropic Filters").  The interpolating cubics (Keys,
+// Mitchell) filter deterministically with their 16 weights and
+// stochastically by positivization: one tap from the positive and one from
+// the negative weights (interp.h).
 //
-// The interpolating cubics (Keys, Mitchell) filter deterministically with
-// their 16 weights and stochastically by positivization: one tap from the
-// positive and one from the negative weights (interp.h).
+// Every kernel is generic over its texel source: stored texels of a format
+// (DenseSrc), or DCT-compressed blocks decoded one texel at a time
+// (DctSrc; the stochastic filters decode one texel per lookup instead of
+// 4 or 16, the case the paper makes for compressed formats).
 //
 // Raster position: x = uv.x * W - 0.5 (texel centres at half-integers of
 // uv * W); taps are clamped to the texture.
 #include <math.h>
 
+#include "dct_decode.h"
 #include "device_common.h"
 #include "interp.h"
 #include "stf_internal.h"
@@ -44,10 +49,54 @@ __device__ __forceinline__ void load_rgba(const TexLevel& L, int x, int y, float
     }
 }
 
+// Stored texels: C channels of format FMT.
+template <int FMT, int C>
+struct DenseSrc {
+    static constexpr int CAP = C;
+    TexLevel L;
+    __device__ int w() const { return L.w; }
+    __device__ int h() const { return L.h; }
+    __device__ int channels() const { return C; }
+    __device__ void load(int x, int y, float (&v)[CAP]) const { load_rgba<FMT, C>(L, x, y, v); }
+};
+
+// DCT blocks: CAP words per block (a multiple of 4), C <= CAP channels used.
+template <int CAP_>
+struct DctSrc {
+    static constexpr int CAP = CAP_;
+    const uint32_t* blocks;
+    int32_t W, H, BW, C;
+    __device__ int w() const { return W; }
+    __device__ int h() const { return H; }
+    __device__ int channels() const { return C; }
+    __device__ void load(int x, int y, float (&v)[CAP]) const
+    {
+        const uint4* b = reinterpret_cast<const uint4*>(blocks + ((int64_t)(y >> 3) * BW + (x >> 3)) * CAP);
+        const DctBasis B = dct_basis(x & 7, y & 7);
+#pragma unroll
+        for (int g = 0; g < CAP / 4; ++g) {
+            const uint4 q = b[g];
+            v[4 * g] = dct_decode_word(q.x, B);
+            v[4 * g + 1] = dct_decode_word(q.y, B);
+            v[4 * g + 2] = dct_decode_word(q.z, B);
+            v[4 * g + 3] = dct_decode_word(q.w, B);
+        }
+    }
+};
+
+template <class Src>
+__device__ __forceinline__ void store_channels(const Src& S, float* __restrict__ out, int64_t oi, const float* v)
+{
+    const int C = S.channels();
+#pragma unroll
+    for (int c = 0; c < Src::CAP; ++c)
+        if (c < C) out[oi * C + c] = v[c];
+}
+
 // Query i of a batch of n, drawn with id qid0 + i.
-template <int FMT, int C, bool CUBIC>
-__device__ __forceinline__ void tex2d_stochastic_one(const TexLevel& L, const float* __restrict__ q, int32_t n,
-                                                     int32_t i, uint32_t key, uint32_t qid0, float* __restrict__ out,
+template <class Src, bool CUBIC>
+__device__ __forceinline__ void tex2d_stochastic_one(const Src& S, const float* __restrict__ q, int32_t n, int32_t i,
+                                                     uint32_t key, uint32_t qid0, float* __restrict__ out,
                                                      int32_t* __restrict__ idx, const int32_t* __restrict__ order,
                                                      int scatter)
 {
@@ -55,12 +104,12 @@ __device__ __forceinline__ void tex2d_stochastic_one(const TexLevel& L, const fl
     const int32_t id = order ? order[i] : (int32_t)(qid0 + (uint32_t)i);
     const int64_t oi = (order && scatter) ? (int64_t)id : (int64_t)i;
     float2 uv = reinterpret_cast<const float2*>(q)[i];
-    float x = uv.x * (float)L.w - 0.5f;
-    float y = uv.y * (float)L.h - 0.5f;
+    float x = uv.x * (float)S.w() - 0.5f;
+    float y = uv.y * (float)S.h() - 0.5f;
     int cx, cy;
     float tx, ty;
     bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
-    float v[C];
+    float v[Src::CAP];
     int sx = BAD_INDEX, sy = BAD_INDEX;
     if (ok) {
         uint32_t b = pcg(key ^ (uint32_t)id);
@@ -72,72 +121,71 @@ __device__ __forceinline__ void tex2d_stochastic_one(const TexLevel& L, const fl
             sx = cx + choose_linear(tx, ux);
             sy = cy + choose_linear(ty, uy);
         }
-        sx = clampi(sx, L.w - 1);
-        sy = clampi(sy, L.h - 1);
-        load_rgba<FMT, C>(L, sx, sy, v);
+        sx = clampi(sx, S.w() - 1);
+        sy = clampi(sy, S.h() - 1);
+        S.load(sx, sy, v);
     } else {
 #pragma unroll
-        for (int c = 0; c < C; ++c) v[c] = __builtin_nanf("");
+        for (int c = 0; c < Src::CAP; ++c) v[c] = __builtin_nanf("");
     }
-#pragma unroll
-    for (int c = 0; c < C; ++c) out[oi * C + c] = v[c];
+    store_channels(S, out, oi, v);
     if (idx) {
         idx[2 * oi] = sx;
         idx[2 * oi + 1] = sy;
     }
 }
 
-template <int FMT, int C, bool CUBIC>
-__global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(TexLevel L, const float* __restrict__ q, int32_t n,
+template <class Src, bool CUBIC>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(Src S, const float* __restrict__ q, int32_t n,
                                                             uint32_t key, float* __restrict__ out,
                                                             int32_t* __restrict__ idx, const int32_t* __restrict__ order,
                                                             int scatter)
 {
-    tex2d_stochastic_one<FMT, C, CUBIC>(L, q, n, blockIdx.x * BLOCK + threadIdx.x, key, 0u, out, idx, order, scatter);
+    tex2d_stochastic_one<Src, CUBIC>(S, q, n, blockIdx.x * BLOCK + threadIdx.x, key, 0u, out, idx, order, scatter);
 }
 
 // Positivized estimate of an interpolating cubic for query i: two clamped
 // taps, value (S+ t(j+) - S- t(j-)) / scale^2; index (x+, y+, x-, y-), the
 // negative tap INT32_MIN when S- = 0.
-template <int FMT, int C, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_tex2d_positivized(TexLevel L, const float* __restrict__ q, int32_t n,
+template <class Src, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_positivized(Src S, const float* __restrict__ q, int32_t n,
                                                              uint32_t key, float* __restrict__ out,
                                                              int32_t* __restrict__ idx,
                                                              const int32_t* __restrict__ order, int scatter)
 {
+    constexpr int CAP = Src::CAP;
     const int32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int32_t id = order ? order[i] : i;
     const int64_t oi = (order && scatter) ? (int64_t)id : (int64_t)i;
     float2 uv = reinterpret_cast<const float2*>(q)[i];
-    float x = uv.x * (float)L.w - 0.5f;
-    float y = uv.y * (float)L.h - 0.5f;
+    float x = uv.x * (float)S.w() - 0.5f;
+    float y = uv.y * (float)S.h() - 0.5f;
     int cx, cy;
     float tx, ty;
     bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
-    float v[C];
+    float v[CAP];
     int ix[4] = {BAD_INDEX, BAD_INDEX, BAD_INDEX, BAD_INDEX};
     if (ok) {
         const float t[2] = {tx, ty};
         const PosDraw<2> d = positivized_draw<2, KIND>(t, pcg(key ^ (uint32_t)id));
-        ix[0] = clampi(cx + d.op[0], L.w - 1);
-        ix[1] = clampi(cy + d.op[1], L.h - 1);
-        float vp[C], vn[C];
-        load_rgba<FMT, C>(L, ix[0], ix[1], vp);
+        ix[0] = clampi(cx + d.op[0], S.w() - 1);
+        ix[1] = clampi(cy + d.op[1], S.h() - 1);
+        float vp[CAP], vn[CAP];
+        S.load(ix[0], ix[1], vp);
         if (d.neg) {
-            ix[2] = clampi(cx + d.on[0], L.w - 1);
-            ix[3] = clampi(cy + d.on[1], L.h - 1);
-            load_rgba<FMT, C>(L, ix[2], ix[3], vn);
+            ix[2] = clampi(cx + d.on[0], S.w() - 1);
+            ix[3] = clampi(cy + d.on[1], S.h() - 1);
+            S.load(ix[2], ix[3], vn);
         }
         constexpr float inv = inv_scale<2, KIND>();
 #pragma unroll
-        for (int c = 0; c < C; ++c) v[c] = (d.neg ? d.sp * vp[c] - d.sn * vn[c] : d.sp * vp[c]) * inv;
+        for (int c = 0; c < CAP; ++c) v[c] = (d.neg ? d.sp * vp[c] - d.sn * vn[c] : d.sp * vp[c]) * inv;
     } else {
 #pragma unroll
-        for (int c = 0; c < C; ++c) v[c] = __builtin_nanf("");
+        for (int c = 0; c < CAP; ++c) v[c] = __builtin_nanf("");
     }
-#pragma unroll
-    for (int c = 0; c < C; ++c) out[oi * C + c] = v[c];
+    store_channels(S, out, oi, v);
     if (idx) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) idx[4 * oi + k] = ix[k];
@@ -145,9 +193,8 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_positivized(TexLevel L, const f
 }
 
 // Serving: block b serves chunk c with start[c] <= b < start[c + 1].
-template <int FMT, int C, bool CUBIC>
-__global__ __launch_bounds__(BLOCK) void k_tex2d_serve(TexLevel L, const ServeChunk* __restrict__ chunks,
-                                                       int32_t nchunks)
+template <class Src, bool CUBIC>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_serve(Src S, const ServeChunk* __restrict__ chunks, int32_t nchunks)
 {
     int lo = 0, hi = nchunks - 1;
     while (lo < hi) {
@@ -156,68 +203,72 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_serve(TexLevel L, const ServeCh
         else hi = mid - 1;
     }
     const ServeChunk c = chunks[lo];
-    tex2d_stochastic_one<FMT, C, CUBIC>(L, c.q, c.count, ((int32_t)blockIdx.x - c.block0) * BLOCK + threadIdx.x, c.key,
-                                        c.qid0, c.out, c.idx, nullptr, 0);
+    tex2d_stochastic_one<Src, CUBIC>(S, c.q, c.count, ((int32_t)blockIdx.x - c.block0) * BLOCK + threadIdx.x, c.key,
+                                     c.qid0, c.out, c.idx, nullptr, 0);
 }
 
-template <int FMT, int C, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(TexLevel L, const float* __restrict__ q, int32_t n,
+template <class Src, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(Src S, const float* __restrict__ q, int32_t n,
                                                                float* __restrict__ out, const int32_t* __restrict__ order,
                                                                int scatter)
 {
     constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
+    constexpr int CAP = Src::CAP;
     int32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int64_t oi = (order && scatter) ? (int64_t)order[i] : (int64_t)i;
     float2 uv = reinterpret_cast<const float2*>(q)[i];
-    float x = uv.x * (float)L.w - 0.5f;
-    float y = uv.y * (float)L.h - 0.5f;
+    float x = uv.x * (float)S.w() - 0.5f;
+    float y = uv.y * (float)S.h() - 0.5f;
     int cx, cy;
     float tx, ty;
     bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
-    float acc[C];
+    float acc[CAP];
     if (!ok) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) out[oi * C + c] = __builtin_nanf("");
+        for (int c = 0; c < CAP; ++c) acc[c] = __builtin_nanf("");
+        store_channels(S, out, oi, acc);
         return;
     }
     float wx[4], wy[4];
     cx += axis_weights_scaled<KIND>(tx, wx);
     cy += axis_weights_scaled<KIND>(ty, wy);
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+    for (int c = 0; c < CAP; ++c) acc[c] = 0.0f;
 #pragma unroll
     for (int b = 0; b < NT; ++b) {
-        int yy = clampi(cy + b, L.h - 1);
-        float row[C];
+        int yy = clampi(cy + b, S.h() - 1);
+        float row[CAP];
 #pragma unroll
-        for (int c = 0; c < C; ++c) row[c] = 0.0f;
+        for (int c = 0; c < CAP; ++c) row[c] = 0.0f;
 #pragma unroll
         for (int a = 0; a < NT; ++a) {
-            float v[C];
-            load_rgba<FMT, C>(L, clampi(cx + a, L.w - 1), yy, v);
+            float v[CAP];
+            S.load(clampi(cx + a, S.w() - 1), yy, v);
 #pragma unroll
-            for (int c = 0; c < C; ++c) row[c] = __builtin_fmaf(wx[a], v[c], row[c]);
+            for (int c = 0; c < CAP; ++c) row[c] = __builtin_fmaf(wx[a], v[c], row[c]);
         }
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] = __builtin_fmaf(wy[b], row[c], acc[c]);
+        for (int c = 0; c < CAP; ++c) acc[c] = __builtin_fmaf(wy[b], row[c], acc[c]);
     }
     constexpr float S2 = axis_scale<KIND>() * axis_scale<KIND>();   // 36 (B-spline), 4 (Keys), 324 (Mitchell)
 #pragma unroll
-    for (int c = 0; c < C; ++c) out[oi * C + c] = KIND == KIND_LINEAR ? acc[c] : acc[c] / S2;
+    for (int c = 0; c < CAP; ++c) acc[c] = KIND == KIND_LINEAR ? acc[c] : acc[c] / S2;
+    store_channels(S, out, oi, acc);
 }
 
 // channel-0 moments of the stochastic estimator over many seeds
-template <int FMT, int C, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_tex2d_moments(TexLevel L, const float* __restrict__ q, int32_t n,
+template <class Src, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_moments(Src S, const float* __restrict__ q, int32_t n,
                                                          uint64_t seed_base, int32_t n_seeds,
                                                          double* __restrict__ sum, double* __restrict__ sumsq)
 {
+    constexpr int CAP = Src::CAP;
     __shared__ double s1[BLOCK], s2[BLOCK];
     int32_t i = blockIdx.x;
     float2 uv = reinterpret_cast<const float2*>(q)[i];
-    float x = uv.x * (float)L.w - 0.5f;
-    float y = uv.y * (float)L.h - 0.5f;
+    float x = uv.x * (float)S.w() - 0.5f;
+    float y = uv.y * (float)S.h() - 0.5f;
     int cx, cy;
     float tx, ty;
     bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
@@ -229,11 +280,11 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_moments(TexLevel L, const float
             if constexpr (KIND == KIND_KEYS || KIND == KIND_MITCHELL) {
                 const float t[2] = {tx, ty};
                 const PosDraw<2> d = positivized_draw<2, KIND>(t, b);
-                float vp[C], vn[C];
-                load_rgba<FMT, C>(L, clampi(cx + d.op[0], L.w - 1), clampi(cy + d.op[1], L.h - 1), vp);
+                float vp[CAP], vn[CAP];
+                S.load(clampi(cx + d.op[0], S.w() - 1), clampi(cy + d.op[1], S.h() - 1), vp);
                 e = d.sp * vp[0];
                 if (d.neg) {
-                    load_rgba<FMT, C>(L, clampi(cx + d.on[0], L.w - 1), clampi(cy + d.on[1], L.h - 1), vn);
+                    S.load(clampi(cx + d.on[0], S.w() - 1), clampi(cy + d.on[1], S.h() - 1), vn);
                     e = e - d.sn * vn[0];
                 }
                 e = e * inv_scale<2, KIND>();
@@ -245,8 +296,8 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_moments(TexLevel L, const float
                 } else {
                     sx = cx + choose_linear(tx, ux); sy = cy + choose_linear(ty, uy);
                 }
-                float v[C];
-                load_rgba<FMT, C>(L, clampi(sx, L.w - 1), clampi(sy, L.h - 1), v);
+                float v[CAP];
+                S.load(clampi(sx, S.w() - 1), clampi(sy, S.h() - 1), v);
                 e = v[0];
             }
             double d = (double)e;
@@ -272,113 +323,102 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_moments(TexLevel L, const float
     }
 }
 
-template <int FMT, int C, int KIND>
-void launch2d_kind(const TexLevel& L, const float* q, int32_t n, int mode, uint32_t key, float* out, int32_t* idx,
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <class Src, int KIND>
+void launch2d_kind(const Src& S, const float* q, int32_t n, int mode, uint32_t key, float* out, int32_t* idx,
                    const int32_t* order, int scatter, hipStream_t stream)
 {
     dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
     if (mode == STF_STOCHASTIC) {
         if constexpr (KIND == KIND_KEYS || KIND == KIND_MITCHELL)
-            hipLaunchKernelGGL((k_tex2d_positivized<FMT, C, KIND>), grid, block, 0, stream, L, q, n, key, out, idx,
-                               order, scatter);
+            hipLaunchKernelGGL((k_tex2d_positivized<Src, KIND>), grid, block, 0, stream, S, q, n, key, out, idx, order,
+                               scatter);
         else
-            hipLaunchKernelGGL((k_tex2d_stochastic<FMT, C, KIND == KIND_BSPLINE>), grid, block, 0, stream, L, q, n, key,
+            hipLaunchKernelGGL((k_tex2d_stochastic<Src, KIND == KIND_BSPLINE>), grid, block, 0, stream, S, q, n, key,
                                out, idx, order, scatter);
     } else {
-        hipLaunchKernelGGL((k_tex2d_deterministic<FMT, C, KIND>), grid, block, 0, stream, L, q, n, out, order, scatter);
+        hipLaunchKernelGGL((k_tex2d_deterministic<Src, KIND>), grid, block, 0, stream, S, q, n, out, order, scatter);
     }
 }
 
-template <int FMT, int C>
-hipError_t launch2d_fc(const TexLevel& L, const float* q, int32_t n, int filter, int mode, uint32_t key, float* out,
-                       int32_t* idx, const int32_t* order, int scatter, hipStream_t stream)
+template <class Src>
+hipError_t launch2d_src(const Src& S, const float* q, int32_t n, int filter, int mode, uint32_t key, float* out,
+                        int32_t* idx, const int32_t* order, int scatter, hipStream_t stream)
 {
     switch (filter) {
-    case KIND_LINEAR: launch2d_kind<FMT, C, KIND_LINEAR>(L, q, n, mode, key, out, idx, order, scatter, stream); break;
-    case KIND_BSPLINE: launch2d_kind<FMT, C, KIND_BSPLINE>(L, q, n, mode, key, out, idx, order, scatter, stream); break;
-    case KIND_KEYS: launch2d_kind<FMT, C, KIND_KEYS>(L, q, n, mode, key, out, idx, order, scatter, stream); break;
-    case KIND_MITCHELL: launch2d_kind<FMT, C, KIND_MITCHELL>(L, q, n, mode, key, out, idx, order, scatter, stream); break;
+    case KIND_LINEAR: launch2d_kind<Src, KIND_LINEAR>(S, q, n, mode, key, out, idx, order, scatter, stream); break;
+    case KIND_BSPLINE: launch2d_kind<Src, KIND_BSPLINE>(S, q, n, mode, key, out, idx, order, scatter, stream); break;
+    case KIND_KEYS: launch2d_kind<Src, KIND_KEYS>(S, q, n, mode, key, out, idx, order, scatter, stream); break;
+    case KIND_MITCHELL: launch2d_kind<Src, KIND_MITCHELL>(S, q, n, mode, key, out, idx, order, scatter, stream); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int FMT, int C>
-hipError_t serve2d_fc(const TexLevel& L, int filter, const ServeChunk* chunks, int32_t nchunks, int32_t nblocks,
-                      hipStream_t s)
-{
-    if (filter == STF_CUBIC_BSPLINE)
-        hipLaunchKernelGGL((k_tex2d_serve<FMT, C, true>), dim3(nblocks), dim3(BLOCK), 0, s, L, chunks, nchunks);
-    else
-        hipLaunchKernelGGL((k_tex2d_serve<FMT, C, false>), dim3(nblocks), dim3(BLOCK), 0, s, L, chunks, nchunks);
-    return hipGetLastError();
-}
-
-template <int FMT>
-hipError_t serve2d_f(const stf_texture* t, int filter, const ServeChunk* chunks, int32_t nchunks, int32_t nblocks,
-                     hipStream_t s)
-{
-    const TexLevel& L = t->level[0];
-    switch (t->channels) {
-    case 1: return serve2d_fc<FMT, 1>(L, filter, chunks, nchunks, nblocks, s);
-    case 2: return serve2d_fc<FMT, 2>(L, filter, chunks, nchunks, nblocks, s);
-    case 3: return serve2d_fc<FMT, 3>(L, filter, chunks, nchunks, nblocks, s);
-    case 4: return serve2d_fc<FMT, 4>(L, filter, chunks, nchunks, nblocks, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <int FMT, int C>
-hipError_t moments2d_fc(const TexLevel& L, const float* q, int32_t n, int filter, uint64_t seed_base,
-                        int32_t n_seeds, double* sum, double* sumsq, hipStream_t stream)
+template <class Src>
+hipError_t moments2d_src(const Src& S, const float* q, int32_t n, int filter, uint64_t seed_base, int32_t n_seeds,
+                         double* sum, double* sumsq, hipStream_t stream)
 {
     dim3 grid(n), block(BLOCK);
     switch (filter) {
     case KIND_LINEAR:
-        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, KIND_LINEAR>), grid, block, 0, stream, L, q, n, seed_base, n_seeds,
-                           sum, sumsq);
+        hipLaunchKernelGGL((k_tex2d_moments<Src, KIND_LINEAR>), grid, block, 0, stream, S, q, n, seed_base, n_seeds, sum,
+                           sumsq);
         break;
     case KIND_BSPLINE:
-        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, KIND_BSPLINE>), grid, block, 0, stream, L, q, n, seed_base, n_seeds,
+        hipLaunchKernelGGL((k_tex2d_moments<Src, KIND_BSPLINE>), grid, block, 0, stream, S, q, n, seed_base, n_seeds,
                            sum, sumsq);
         break;
     case KIND_KEYS:
-        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, KIND_KEYS>), grid, block, 0, stream, L, q, n, seed_base, n_seeds,
-                           sum, sumsq);
+        hipLaunchKernelGGL((k_tex2d_moments<Src, KIND_KEYS>), grid, block, 0, stream, S, q, n, seed_base, n_seeds, sum,
+                           sumsq);
         break;
     case KIND_MITCHELL:
-        hipLaunchKernelGGL((k_tex2d_moments<FMT, C, KIND_MITCHELL>), grid, block, 0, stream, L, q, n, seed_base,
-                           n_seeds, sum, sumsq);
+        hipLaunchKernelGGL((k_tex2d_moments<Src, KIND_MITCHELL>), grid, block, 0, stream, S, q, n, seed_base, n_seeds,
+                           sum, sumsq);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int FMT>
-hipError_t launch2d_f(const stf_texture* t, const float* q, int32_t n, int filter, int mode, uint32_t key,
-                      float* out, int32_t* idx, const int32_t* order, int scatter, hipStream_t s)
+template <int FMT, class F>
+hipError_t with_dense(const stf_texture* t, F&& f)
 {
     const TexLevel& L = t->level[0];
     switch (t->channels) {
-    case 1: return launch2d_fc<FMT, 1>(L, q, n, filter, mode, key, out, idx, order, scatter, s);
-    case 2: return launch2d_fc<FMT, 2>(L, q, n, filter, mode, key, out, idx, order, scatter, s);
-    case 3: return launch2d_fc<FMT, 3>(L, q, n, filter, mode, key, out, idx, order, scatter, s);
-    case 4: return launch2d_fc<FMT, 4>(L, q, n, filter, mode, key, out, idx, order, scatter, s);
+    case 1: return f(DenseSrc<FMT, 1>{L});
+    case 2: return f(DenseSrc<FMT, 2>{L});
+    case 3: return f(DenseSrc<FMT, 3>{L});
+    case 4: return f(DenseSrc<FMT, 4>{L});
     }
     return hipErrorInvalidValue;
 }
 
-template <int FMT>
-hipError_t moments2d_f(const stf_texture* t, const float* q, int32_t n, int filter, uint64_t seed_base,
-                       int32_t n_seeds, double* sum, double* sumsq, hipStream_t s)
+// Calls f with the texel source of a 2D texture: a dense format and channel
+// count, or DCT blocks and their padded word count.
+template <class F>
+hipError_t with_src(const stf_texture* t, F&& f)
 {
-    const TexLevel& L = t->level[0];
-    switch (t->channels) {
-    case 1: return moments2d_fc<FMT, 1>(L, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
-    case 2: return moments2d_fc<FMT, 2>(L, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
-    case 3: return moments2d_fc<FMT, 3>(L, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
-    case 4: return moments2d_fc<FMT, 4>(L, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
+    if (t->kind == STF_KIND_DCT2D) {
+        const TexLevel& L = t->level[0];
+        const uint32_t* b = static_cast<const uint32_t*>(L.texels);
+        switch (t->dct_wpb) {
+        case 4: return f(DctSrc<4>{b, L.w, L.h, L.w / 8, t->channels});
+        case 8: return f(DctSrc<8>{b, L.w, L.h, L.w / 8, t->channels});
+        case 12: return f(DctSrc<12>{b, L.w, L.h, L.w / 8, t->channels});
+        case 16: return f(DctSrc<16>{b, L.w, L.h, L.w / 8, t->channels});
+        }
+        return hipErrorInvalidValue;
+    }
+    switch (t->fmt) {
+    case F32: return with_dense<F32>(t, f);
+    case F16: return with_dense<F16>(t, f);
+    case BF16: return with_dense<BF16>(t, f);
+    case FP8_E4M3: return with_dense<FP8_E4M3>(t, f);
+    case U8: return with_dense<U8>(t, f);
     }
     return hipErrorInvalidValue;
 }
@@ -388,27 +428,13 @@ hipError_t moments2d_f(const stf_texture* t, const float* q, int32_t n, int filt
 hipError_t launch_filter2d(const stf_texture* t, const float* q, int32_t n, int filter, int mode, uint32_t key,
                            float* out, int32_t* idx, const int32_t* order, int scatter, hipStream_t s)
 {
-    switch (t->fmt) {
-    case F32: return launch2d_f<F32>(t, q, n, filter, mode, key, out, idx, order, scatter, s);
-    case F16: return launch2d_f<F16>(t, q, n, filter, mode, key, out, idx, order, scatter, s);
-    case BF16: return launch2d_f<BF16>(t, q, n, filter, mode, key, out, idx, order, scatter, s);
-    case FP8_E4M3: return launch2d_f<FP8_E4M3>(t, q, n, filter, mode, key, out, idx, order, scatter, s);
-    case U8: return launch2d_f<U8>(t, q, n, filter, mode, key, out, idx, order, scatter, s);
-    }
-    return hipErrorInvalidValue;
+    return with_src(t, [&](auto S) { return launch2d_src(S, q, n, filter, mode, key, out, idx, order, scatter, s); });
 }
 
 hipError_t launch_moments2d(const stf_texture* t, const float* q, int32_t n, int filter, uint64_t seed_base,
                             int32_t n_seeds, double* sum, double* sumsq, hipStream_t s)
 {
-    switch (t->fmt) {
-    case F32: return moments2d_f<F32>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
-    case F16: return moments2d_f<F16>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
-    case BF16: return moments2d_f<BF16>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
-    case FP8_E4M3: return moments2d_f<FP8_E4M3>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
-    case U8: return moments2d_f<U8>(t, q, n, filter, seed_base, n_seeds, sum, sumsq, s);
-    }
-    return hipErrorInvalidValue;
+    return with_src(t, [&](auto S) { return moments2d_src(S, q, n, filter, seed_base, n_seeds, sum, sumsq, s); });
 }
 
 int32_t serve2d_queries_per_block()
@@ -419,12 +445,13 @@ int32_t serve2d_queries_per_block()
 hipError_t launch_serve2d(const stf_texture* t, int filter, const ServeChunk* chunks, int32_t nchunks, int32_t nblocks,
                           hipStream_t s)
 {
-    switch (t->fmt) {
-    case F32: return serve2d_f<F32>(t, filter, chunks, nchunks, nblocks, s);
-    case F16: return serve2d_f<F16>(t, filter, chunks, nchunks, nblocks, s);
-    case BF16: return serve2d_f<BF16>(t, filter, chunks, nchunks, nblocks, s);
-    case FP8_E4M3: return serve2d_f<FP8_E4M3>(t, filter, chunks, nchunks, nblocks, s);
-    case U8: return serve2d_f<U8>(t, filter, chunks, nchunks, nblocks, s);
-    }
-    return hipErrorInvalidValue;
+    if (t->kind != STF_KIND_TEX2D) return hipErrorInvalidValue;
+    return with_src(t, [&](auto S) {
+        using Src = decltype(S);
+        if (filter == STF_CUBIC_BSPLINE)
+            hipLaunchKernelGGL((k_tex2d_serve<Src, true>), dim3(nblocks), dim3(BLOCK), 0, s, S, chunks, nchunks);
+        else
+            hipLaunchKernelGGL((k_tex2d_serve<Src, false>), dim3(nblocks), dim3(BLOCK), 0, s, S, chunks, nchunks);
+        return hipGetLastError();
+    });
 }

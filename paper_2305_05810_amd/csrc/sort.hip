@@ -178,7 +178,7 @@ stf_status stf_filter_ordered(const stf_texture* tex, const float* sorted_querie
 {
     stf_clear_error();
     if (!tex) return stf_fail(STF_E_INVALID, "texture is NULL");
-    if (tex->kind != STF_KIND_TEX2D && tex->kind != STF_KIND_GRID3D)
+    if (!is_2d_filterable(tex) && tex->kind != STF_KIND_GRID3D)
         return stf_fail(STF_E_INVALID, "stf_filter_ordered needs a 2D texture or a 3D grid");
     if (n < 0 || n > 0x7fffffff) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
     if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
@@ -187,7 +187,7 @@ stf_status stf_filter_ordered(const stf_texture* tex, const float* sorted_querie
     if (mode == STF_DETERMINISTIC && out_index_dev)
         return stf_fail(STF_E_INVALID, "out_index_dev must be NULL in deterministic mode");
     if (n == 0) return STF_OK;
-    bool is2d = tex->kind == STF_KIND_TEX2D;
+    bool is2d = is_2d_filterable(tex);
     stf_status s = check_ptr(sorted_queries_dev, "sorted_queries_dev", is2d ? 8 : 4);
     if (s == STF_OK) s = check_ptr(order_dev, "order_dev", 4);
     if (s == STF_OK) s = check_ptr(out_dev, "out_dev", 4);

@@ -277,7 +277,7 @@ stf_status stf_filter(const stf_texture* tex, const float* queries_dev, int64_t 
 {
     stf_clear_error();
     if (!tex) return stf_fail(STF_E_INVALID, "texture is NULL");
-    if (tex->kind != STF_KIND_TEX2D && tex->kind != STF_KIND_GRID3D)
+    if (!is_2d_filterable(tex) && tex->kind != STF_KIND_GRID3D)
         return stf_fail(STF_E_INVALID, "stf_filter needs a 2D texture or a 3D grid");
     if (n < 0 || n > MAX_QUERIES) return stf_fail(STF_E_INVALID, "n = %lld out of range (0..2^31-1)", (long long)n);
     if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
@@ -286,7 +286,7 @@ stf_status stf_filter(const stf_texture* tex, const float* queries_dev, int64_t 
     if (mode == STF_DETERMINISTIC && out_index_dev)
         return stf_fail(STF_E_INVALID, "out_index_dev must be NULL in deterministic mode");
     if (n == 0) return STF_OK;
-    bool is2d = tex->kind == STF_KIND_TEX2D;
+    bool is2d = is_2d_filterable(tex);
     stf_status s = check_device_ptr(queries_dev, "queries_dev", is2d ? 8 : 4);
     if (s == STF_OK) s = check_device_ptr(out_dev, "out_dev", 4);
     if (s == STF_OK && out_index_dev) s = check_device_ptr(out_index_dev, "out_index_dev", 4);
@@ -307,13 +307,13 @@ stf_status stf_filter_moments(const stf_texture* tex, const float* queries_dev, 
 {
     stf_clear_error();
     if (!tex) return stf_fail(STF_E_INVALID, "texture is NULL");
-    if (tex->kind != STF_KIND_TEX2D && tex->kind != STF_KIND_GRID3D)
+    if (!is_2d_filterable(tex) && tex->kind != STF_KIND_GRID3D)
         return stf_fail(STF_E_INVALID, "stf_filter_moments needs a 2D texture or a 3D grid");
     if (n < 0 || n > MAX_QUERIES) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
     if (n_seeds < 1) return stf_fail(STF_E_INVALID, "n_seeds = %d must be >= 1", n_seeds);
     if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
     if (n == 0) return STF_OK;
-    bool is2d = tex->kind == STF_KIND_TEX2D;
+    bool is2d = is_2d_filterable(tex);
     stf_status s = check_device_ptr(queries_dev, "queries_dev", is2d ? 8 : 4);
     if (s == STF_OK) s = check_device_ptr(sum_dev, "sum_dev", 8);
     if (s == STF_OK) s = check_device_ptr(sumsq_dev, "sumsq_dev", 8);

@@ -7,7 +7,7 @@
 
 #include "../../include/stf.h"
 
-enum stf_kind : int { STF_KIND_TEX2D = 1, STF_KIND_MATERIAL = 2, STF_KIND_GRID3D = 3 };
+enum stf_kind : int { STF_KIND_TEX2D = 1, STF_KIND_MATERIAL = 2, STF_KIND_GRID3D = 3, STF_KIND_DCT2D = 4 };
 
 constexpr int STF_MAX_LEVELS = 16;
 
@@ -35,10 +35,11 @@ struct stf_texture {
     int channels;
     int device;
     int64_t bytes;
-    // 2D textures and materials
+    // 2D textures and materials (DCT textures: level 0 holds the blocks)
     int levels;
     TexLevel level[STF_MAX_LEVELS];
     void* level_alloc[STF_MAX_LEVELS];
+    int32_t dct_wpb;   // DCT textures: words per block on the device (channels padded to a multiple of 4)
     // 3D grids
     GridView grid;
     int32_t rz;
@@ -62,6 +63,12 @@ struct ServeChunk {
 
 // Error reporting (thread-local message).
 stf_status stf_fail(stf_status code, const char* fmt, ...);
+
+// Textures that stf_filter reads with 2D (uv) queries.
+inline bool is_2d_filterable(const stf_texture* t)
+{
+    return t->kind == STF_KIND_TEX2D || t->kind == STF_KIND_DCT2D;
+}
 
 // Filters of stf_filter / stf_filter_ordered / stf_filter_moments.
 inline bool valid_filter(int f)
