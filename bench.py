@@ -15,7 +15,10 @@ Other workloads (one JSON line each): `tex2d` (256^2 RGBA texture, 65,536
 uv queries), `shade` (4096^2 material, 8M shading queries, three filter
 orders), `neural` (4096^2 x 8 texture as a 1024^2 x 8 latent grid + MLP:
 training and BF16-MFMA inference), `serving` (three resident textures,
-Poisson arrivals of log-normal request sizes at 0.5 / 1 / 2 G lookups/s).
+Poisson arrivals of log-normal request sizes at 0.5 / 1 / 2 G lookups/s),
+`dct` (4096^2 x 9 DCT-compressed texture set, 16M uv queries, one decode per
+stochastic lookup).  The grid workload also times the interpolating cubics
+(Keys, Mitchell-Netravali; positivized two-tap stochastic vs 64-tap).
 
 Prints one JSON line.
 """
@@ -280,6 +283,66 @@ def run_tex2d(args, torch, stf, synth):
 
 
 # ----------------------------------------------------------------------------
+# DCT-compressed texture set
+# ----------------------------------------------------------------------------
+def run_dct(args, torch, stf, synth):
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    size, C = 4096, 9
+    tex_np = synth.texture_set_u8(size, seed=51)
+    words = stf.stf_dct_encode(tex_np)
+    tex = stf.stf_create_dct_texture2d(size, size, C, words)
+    uv = synth.screen_uv_queries(3840, 2160, seed=53)   # a 4K frame of the textured ground plane
+    uv_rand = synth.uv_queries(uv.shape[0], seed=52)     # the same count, uniform and unordered
+    n = uv.shape[0]
+    log(f"inputs and host encoding {time.time() - t0:.1f}s, {stf.stf_texture_bytes(tex) / 1e6:.1f} MB of blocks")
+    q = torch.from_numpy(uv).to(dev)
+    q_rand = torch.from_numpy(uv_rand).to(dev)
+    out = torch.empty((n, C), dtype=torch.float32, device=dev)
+    block_b = 4 * ((C + 3) // 4 * 4)   # one decode reads its block's channel words
+    res = {}
+    for name, filt, mode, taps, qq in (("stoch_linear", stf.STF_LINEAR, stf.STF_STOCHASTIC, 4, q),
+                                       ("det_linear", stf.STF_LINEAR, stf.STF_DETERMINISTIC, 4, q),
+                                       ("stoch_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 16, q),
+                                       ("det_cubic", stf.STF_CUBIC_BSPLINE, stf.STF_DETERMINISTIC, 16, q),
+                                       ("stoch_keys", stf.STF_CUBIC_KEYS, stf.STF_STOCHASTIC, 16, q),
+                                       ("det_keys", stf.STF_CUBIC_KEYS, stf.STF_DETERMINISTIC, 16, q),
+                                       ("stoch_linear_random_uv", stf.STF_LINEAR, stf.STF_STOCHASTIC, 4, q_rand),
+                                       ("det_linear_random_uv", stf.STF_LINEAR, stf.STF_DETERMINISTIC, 4, q_rand)):
+        decodes = (2 if filt in stf.POSITIVIZED_FILTERS else 1) if mode == stf.STF_STOCHASTIC else taps
+        wall, kern = time_launches(lambda: stf.stf_filter(tex, qq, filt, mode, 11, out), args.steps, args.warmup,
+                                   torch)
+        res[name] = variant_stats(n, args.steps, wall, kern, 8 + 4 * C + decodes * block_b)
+        res[name]["decodes_per_lookup"] = decodes
+        log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel "
+            f"{res[name]['kernel_ms_mean'] * 1e3:.1f} us")
+    # quality of the compression: bilinear at texel centres returns decoded texels
+    js, is_ = np.meshgrid(np.arange(size), np.arange(size), indexing="ij")
+    cen = np.stack([(is_ + 0.5) / size, (js + 0.5) / size], axis=-1).reshape(-1, 2).astype(np.float32)
+    dec = torch.empty((cen.shape[0], C), dtype=torch.float32, device=dev)
+    stf.stf_filter(tex, torch.from_numpy(cen).to(dev), stf.STF_LINEAR, stf.STF_DETERMINISTIC, 0, dec)
+    ref = torch.from_numpy(tex_np.reshape(-1, C)).to(dev).float() / 255.0
+    mse = float(((dec - ref) ** 2).mean().item())
+    head = res["stoch_linear"]
+    line = base_line(args, head["lookups_per_s"], "lookups/s", head["ms_per_step"], "f32",
+                     {"workload": f"DCT-compressed {size}^2 x {C} texture set (8x8 blocks, 6 coefficients per channel "
+                                  f"in 32 bits), {n} uv queries of a 3840x2160 frame of a textured ground plane "
+                                  "(pixel order), stochastic bilinear (1 decode) vs deterministic (4 decodes); "
+                                  "bicubic, Keys and uniformly random uv beside it", "n_queries": n})
+    line.update({"variants": res,
+                 "stochastic_over_deterministic": head["lookups_per_s"] / res["det_linear"]["lookups_per_s"],
+                 "bicubic_stochastic_over_deterministic":
+                     res["stoch_cubic"]["lookups_per_s"] / res["det_cubic"]["lookups_per_s"],
+                 "compression": {"block_bytes": stf.stf_texture_bytes(tex), "u8_bytes": int(tex_np.nbytes),
+                                 "psnr_db": 10 * np.log10(1.0 / mse)},
+                 "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
+                 "cpu_baseline": None})
+    tex.destroy()
+    return line
+
+
+# ----------------------------------------------------------------------------
 # filtering with shading
 # ----------------------------------------------------------------------------
 GGX_FLOPS = 120   # binary32 operations of one shading evaluation (see the design notes)
@@ -462,7 +525,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="grid", choices=["grid", "tex2d", "shade", "neural", "serving"])
+    ap.add_argument("--workload", default="grid", choices=["grid", "tex2d", "shade", "neural", "serving", "dct"])
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16", "fp8_e4m3"])
     ap.add_argument("--order", default="ray", choices=["ray", "shuffled", "morton"])
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="queries in the CPU-oracle timing sample")
@@ -488,7 +551,7 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
-    run = {"grid": run_grid, "tex2d": run_tex2d, "shade": run_shade, "neural": run_neural,
+    run = {"grid": run_grid, "tex2d": run_tex2d, "shade": run_shade, "neural": run_neural, "dct": run_dct,
            "serving": run_serving}[args.workload]
     line = run(args, torch, stf, synth)
     print(json.dumps(line), flush=True)

@@ -93,24 +93,58 @@ __device__ __forceinline__ void store_channels(const Src& S, float* __restrict__
         if (c < C) out[oi * C + c] = v[c];
 }
 
-// Query i of a batch of n, drawn with id qid0 + i.
-template <class Src, bool CUBIC>
-__device__ __forceinline__ void tex2d_stochastic_one(const Src& S, const float* __restrict__ q, int32_t n, int32_t i,
-                                                     uint32_t key, uint32_t qid0, float* __restrict__ out,
-                                                     int32_t* __restrict__ idx, const int32_t* __restrict__ order,
-                                                     int scatter)
+// Stores the C results of every live query of the block.  In batch order the
+// block's results are one contiguous span of cnt * C floats: each thread
+// stages its values in LDS and the block writes the span with consecutive
+// 16-byte stores (4-byte ones if the span is not 16-byte aligned), instead of
+// C strided 4-byte stores per lane.  Scattered results (an ordered stream
+// with STF_ORDER_SCATTER) are stored directly.  Every thread of the block
+// must call this (it synchronises the block).
+template <class Src>
+__device__ __forceinline__ void block_store(const Src& S, float* __restrict__ out, int32_t n, bool live, int64_t oi,
+                                            const float (&v)[Src::CAP], bool scattered)
 {
-    if (i >= n) return;
+    const int C = S.channels();
+    if (scattered) {
+        if (live) store_channels(S, out, oi, v);
+        return;
+    }
+    __shared__ __align__(16) float stage[BLOCK * Src::CAP];
+#pragma unroll
+    for (int c = 0; c < Src::CAP; ++c)
+        if (c < C) stage[threadIdx.x * C + c] = v[c];
+    __syncthreads();
+    const int64_t first = (int64_t)blockIdx.x * BLOCK;
+    const int cnt = (int)((int64_t)n - first < BLOCK ? (int64_t)n - first : BLOCK);
+    const int total = cnt * C;
+    float* dst = out + first * C;
+    int k0 = 0;
+    if ((reinterpret_cast<uintptr_t>(dst) & 15u) == 0) {
+        const int n4 = total >> 2;
+        for (int k = threadIdx.x; k < n4; k += BLOCK)
+            reinterpret_cast<float4*>(dst)[k] = reinterpret_cast<const float4*>(stage)[k];
+        k0 = n4 << 2;
+    }
+    for (int k = k0 + threadIdx.x; k < total; k += BLOCK) dst[k] = stage[k];
+}
+
+// Query i of a batch (i valid), drawn with id qid0 + i (or order[i]): its
+// values, its tap (INT32_MIN for a non-finite query) and where its results go.
+template <class Src, bool CUBIC>
+__device__ __forceinline__ void tex2d_stochastic_eval(const Src& S, const float* __restrict__ q, int32_t i, uint32_t key,
+                                                      uint32_t qid0, const int32_t* __restrict__ order, int scatter,
+                                                      float (&v)[Src::CAP], int& sx, int& sy, int64_t& oi)
+{
     const int32_t id = order ? order[i] : (int32_t)(qid0 + (uint32_t)i);
-    const int64_t oi = (order && scatter) ? (int64_t)id : (int64_t)i;
+    oi = (order && scatter) ? (int64_t)id : (int64_t)i;
     float2 uv = reinterpret_cast<const float2*>(q)[i];
     float x = uv.x * (float)S.w() - 0.5f;
     float y = uv.y * (float)S.h() - 0.5f;
     int cx, cy;
     float tx, ty;
     bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
-    float v[Src::CAP];
-    int sx = BAD_INDEX, sy = BAD_INDEX;
+    sx = BAD_INDEX;
+    sy = BAD_INDEX;
     if (ok) {
         uint32_t b = pcg(key ^ (uint32_t)id);
         float ux = axis_uniform(b, 0), uy = axis_uniform(b, 1);
@@ -128,11 +162,6 @@ __device__ __forceinline__ void tex2d_stochastic_one(const Src& S, const float* 
 #pragma unroll
         for (int c = 0; c < Src::CAP; ++c) v[c] = __builtin_nanf("");
     }
-    store_channels(S, out, oi, v);
-    if (idx) {
-        idx[2 * oi] = sx;
-        idx[2 * oi + 1] = sy;
-    }
 }
 
 template <class Src, bool CUBIC>
@@ -141,7 +170,17 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(Src S, const float* 
                                                             int32_t* __restrict__ idx, const int32_t* __restrict__ order,
                                                             int scatter)
 {
-    tex2d_stochastic_one<Src, CUBIC>(S, q, n, blockIdx.x * BLOCK + threadIdx.x, key, 0u, out, idx, order, scatter);
+    const int32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    const bool live = i < n;
+    float v[Src::CAP];
+    int sx, sy;
+    int64_t oi;
+    tex2d_stochastic_eval<Src, CUBIC>(S, q, live ? i : 0, key, 0u, order, scatter, v, sx, sy, oi);
+    block_store(S, out, n, live, oi, v, order && scatter);
+    if (live && idx) {
+        idx[2 * oi] = sx;
+        idx[2 * oi + 1] = sy;
+    }
 }
 
 // Positivized estimate of an interpolating cubic for query i: two clamped
@@ -154,8 +193,9 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_positivized(Src S, const float*
                                                              const int32_t* __restrict__ order, int scatter)
 {
     constexpr int CAP = Src::CAP;
-    const int32_t i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= n) return;
+    const int32_t i0 = blockIdx.x * BLOCK + threadIdx.x;
+    const bool live = i0 < n;
+    const int32_t i = live ? i0 : 0;
     const int32_t id = order ? order[i] : i;
     const int64_t oi = (order && scatter) ? (int64_t)id : (int64_t)i;
     float2 uv = reinterpret_cast<const float2*>(q)[i];
@@ -185,8 +225,8 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_positivized(Src S, const float*
 #pragma unroll
         for (int c = 0; c < CAP; ++c) v[c] = __builtin_nanf("");
     }
-    store_channels(S, out, oi, v);
-    if (idx) {
+    block_store(S, out, n, live, oi, v, order && scatter);
+    if (live && idx) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) idx[4 * oi + k] = ix[k];
     }
@@ -203,8 +243,17 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_serve(Src S, const ServeChunk* 
         else hi = mid - 1;
     }
     const ServeChunk c = chunks[lo];
-    tex2d_stochastic_one<Src, CUBIC>(S, c.q, c.count, ((int32_t)blockIdx.x - c.block0) * BLOCK + threadIdx.x, c.key,
-                                     c.qid0, c.out, c.idx, nullptr, 0);
+    const int32_t i = ((int32_t)blockIdx.x - c.block0) * BLOCK + threadIdx.x;
+    if (i >= c.count) return;
+    float v[Src::CAP];
+    int sx, sy;
+    int64_t oi;
+    tex2d_stochastic_eval<Src, CUBIC>(S, c.q, i, c.key, c.qid0, nullptr, 0, v, sx, sy, oi);
+    store_channels(S, c.out, oi, v);
+    if (c.idx) {
+        c.idx[2 * oi] = sx;
+        c.idx[2 * oi + 1] = sy;
+    }
 }
 
 template <class Src, int KIND>
@@ -214,28 +263,26 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(Src S, const floa
 {
     constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
     constexpr int CAP = Src::CAP;
-    int32_t i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= n) return;
+    const int32_t i0 = blockIdx.x * BLOCK + threadIdx.x;
+    const bool live = i0 < n;
+    const int32_t i = live ? i0 : 0;
     const int64_t oi = (order && scatter) ? (int64_t)order[i] : (int64_t)i;
     float2 uv = reinterpret_cast<const float2*>(q)[i];
     float x = uv.x * (float)S.w() - 0.5f;
     float y = uv.y * (float)S.h() - 0.5f;
-    int cx, cy;
-    float tx, ty;
-    bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
+    int cx = 0, cy = 0;
+    float tx = 0.0f, ty = 0.0f;
+    const bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
     float acc[CAP];
-    if (!ok) {
-#pragma unroll
-        for (int c = 0; c < CAP; ++c) acc[c] = __builtin_nanf("");
-        store_channels(S, out, oi, acc);
-        return;
-    }
     float wx[4], wy[4];
     cx += axis_weights_scaled<KIND>(tx, wx);
     cy += axis_weights_scaled<KIND>(ty, wy);
 #pragma unroll
     for (int c = 0; c < CAP; ++c) acc[c] = 0.0f;
-#pragma unroll
+    // Wide sources (DCT blocks of 8+ channels) keep one row of taps in
+    // flight: unrolling all rows would hold every tap's words at once.
+    constexpr int ROWS_UNROLLED = CAP > 4 ? 1 : NT;
+#pragma unroll ROWS_UNROLLED
     for (int b = 0; b < NT; ++b) {
         int yy = clampi(cy + b, S.h() - 1);
         float row[CAP];
@@ -253,8 +300,8 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(Src S, const floa
     }
     constexpr float S2 = axis_scale<KIND>() * axis_scale<KIND>();   // 36 (B-spline), 4 (Keys), 324 (Mitchell)
 #pragma unroll
-    for (int c = 0; c < CAP; ++c) acc[c] = KIND == KIND_LINEAR ? acc[c] : acc[c] / S2;
-    store_channels(S, out, oi, acc);
+    for (int c = 0; c < CAP; ++c) acc[c] = !ok ? __builtin_nanf("") : (KIND == KIND_LINEAR ? acc[c] : acc[c] / S2);
+    block_store(S, out, n, live, oi, acc, order && scatter);
 }
 
 // channel-0 moments of the stochastic estimator over many seeds

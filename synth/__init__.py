@@ -105,6 +105,37 @@ def uv_queries(n: int = 65536, seed: int = 2) -> np.ndarray:
     return rng.random((n, 2), dtype=np.float32)
 
 
+def screen_uv_queries(width: int = 3840, height: int = 2160, seed: int = 53) -> np.ndarray:
+    """(width * height, 2) float32 texture coordinates of a frame, pixel-major
+    (row by row): a pinhole camera (60-degree horizontal field of view) 2
+    units above a ground plane, looking 25 degrees down; the plane carries the
+    texture tiled every 8 units (so the texel density runs from magnified in
+    the foreground to minified towards the horizon).  Pixels whose ray misses
+    the plane (above the horizon) look at the sky and are given a random uv
+    (a query stream has no holes).  A per-frame jitter of the pixel centres
+    comes from the seed."""
+    rng = np.random.default_rng(seed)
+    jx, jy = rng.random(2)
+    px = (np.arange(width) + jx) / width * 2.0 - 1.0
+    py = 1.0 - (np.arange(height) + jy) / height * 2.0
+    tan_h = np.tan(np.radians(30.0))
+    X, Y = np.meshgrid(px * tan_h, py * tan_h * height / width)
+    pitch = np.radians(25.0)
+    # camera frame: forward f, right r, up u (world z up)
+    f = np.array([0.0, np.cos(pitch), -np.sin(pitch)])
+    u = np.array([0.0, np.sin(pitch), np.cos(pitch)])
+    d = f[None, None, :] + X[:, :, None] * np.array([1.0, 0.0, 0.0]) + Y[:, :, None] * u[None, None, :]
+    hit = d[:, :, 2] < -1e-6
+    t = np.where(hit, 2.0 / np.maximum(-d[:, :, 2], 1e-6), 0.0)
+    wx = d[:, :, 0] * t
+    wy = d[:, :, 1] * t
+    uv = np.stack([wx / 8.0, wy / 8.0], axis=-1)
+    uv = uv - np.floor(uv)
+    sky = ~hit
+    uv[sky] = rng.random((int(sky.sum()), 2))
+    return np.ascontiguousarray(uv.reshape(-1, 2).astype(np.float32))
+
+
 # ----------------------------------------------------------------------------
 # fBm value noise and the sparse grid built from it
 # ----------------------------------------------------------------------------
@@ -394,6 +425,24 @@ def neural_target(size: int = 4096, seed: int = 41) -> np.ndarray:
     t[:, :, 6] = 0.5 + 0.5 * _fbm2d(size, rng)
     t[:, :, 7] = 0.5 + 0.5 * _fbm2d(size, rng, base_period=32.0)
     return t
+
+
+def texture_set_u8(size: int = 4096, seed: int = 51) -> np.ndarray:
+    """(size, size, 9) uint8 texture set: the eight channels of the neural
+    target (albedo RGB, roughness, tangent normal x and y mapped from [-1, 1]
+    to [0, 1], two fBm detail channels) plus a third fBm detail channel,
+    quantised as round(255 v) after clamping to [0, 1]."""
+    t = neural_target(size, seed)
+    rng = np.random.default_rng(seed + 1)
+    out = np.empty((size, size, 9), np.uint8)
+    for c in range(8):
+        v = t[:, :, c].astype(np.float64)
+        if c in (4, 5):
+            v = 0.5 * (v + 1.0)
+        out[:, :, c] = np.round(np.clip(v, 0.0, 1.0) * 255.0).astype(np.uint8)
+    extra = 0.5 + 0.5 * _fbm2d(size, rng, base_period=16.0)
+    out[:, :, 8] = np.round(np.clip(extra, 0.0, 1.0) * 255.0).astype(np.uint8)
+    return out
 
 
 def neural_init(latent_size: int = 1024, seed: int = 42):
