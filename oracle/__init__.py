@@ -22,7 +22,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 F32, F16, BF16, FP8_E4M3, U8 = 0, 1, 2, 3, 4
 LINEAR, CUBIC, KEYS, MITCHELL = 0, 1, 2, 3
 POSITIVIZED = (KEYS, MITCHELL)
-DET, STOCH, STOCH_REUSE, DET_ABS = 0, 1, 2, 3   # DET_ABS: sum |w_k| |t_k| (tolerance scale)
+DET, STOCH, STOCH_REUSE, DET_ABS, STOCH_FIS = 0, 1, 2, 3, 4   # DET_ABS: sum |w_k| |t_k| (tolerance scale)
+G_FIS, G_FIS_MEAN, G_DISCRETE, G_DISCRETE_MEAN = 0, 1, 2, 3
 BAD_INDEX = -(2 ** 31)
 
 _lib = None
@@ -91,6 +92,14 @@ def _declare(L):
     L.orc_dct_filter2d.restype = i32
     L.orc_dct_moments2d.argtypes = [vp, i32, i32, i32, vp, i64, i32, vp, vp, i32]
     L.orc_dct_moments2d.restype = i32
+    L.orc_fis_tap.argtypes, L.orc_fis_tap.restype = [i32, dbl, u64, u32, i32], i32
+    L.orc_gauss_radius.argtypes, L.orc_gauss_radius.restype = [dbl], i32
+    L.orc_gauss_filter2d.argtypes = [vp, i32, i32, i32, i32, vp, i64, dbl, i32, u64, vp, vp, i32]
+    L.orc_gauss_filter2d.restype = i32
+    L.orc_dct_gauss_filter2d.argtypes = [vp, i32, i32, i32, vp, i64, dbl, i32, u64, vp, vp, i32]
+    L.orc_dct_gauss_filter2d.restype = i32
+    L.orc_gauss_fis_positions.argtypes = [i32, i32, vp, i64, dbl, u64, vp]
+    L.orc_gauss_fis_positions.restype = i32
     if hasattr(L, "orc_shade"):
         _declare_shade(L)
     if hasattr(L, "orc_ntex_decode"):
@@ -237,7 +246,8 @@ def filter2d(tex: np.ndarray, fmt: int, uv: np.ndarray, filt: int, mode: int, se
     uv = np.ascontiguousarray(uv, dtype=np.float32)
     n = uv.shape[0]
     out = np.empty((n, Ch), np.float64)
-    idx = np.empty((n, index_width(filt, 2)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE)) else None
+    idx = np.empty((n, index_width(filt, 2)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE, STOCH_FIS)) \
+        else None
     rc = lib().orc_filter2d(_p(tex), W, H, Ch, fmt, _p(uv), n, filt, mode, seed, _p(out), _p(idx), nthreads)
     if rc != 0:
         raise ValueError("orc_filter2d rejected its arguments")
@@ -264,6 +274,52 @@ def filter2d_brute(tex: np.ndarray, fmt: int, uv: np.ndarray, filt: int) -> np.n
     out = np.empty((uv.shape[0], Ch), np.float64)
     lib().orc_filter2d_brute(_p(tex), W, H, Ch, fmt, _p(uv), uv.shape[0], filt, _p(out))
     return out
+
+
+# ----------------------------------------------------------------------------
+# filter importance sampling and Gaussian filters
+# ----------------------------------------------------------------------------
+def fis_tap(filt: int, x: float, seed: int, qid: int, axis: int) -> int:
+    return lib().orc_fis_tap(filt, float(x), seed, qid & 0xFFFFFFFF, axis)
+
+
+def gauss_radius(sigma: float) -> int:
+    return lib().orc_gauss_radius(float(sigma))
+
+
+def gauss_filter2d(tex: np.ndarray, fmt: int, uv: np.ndarray, sigma: float, gmode: int, seed: int = 0,
+                   want_index: bool = True, nthreads: int = 0):
+    tex = np.ascontiguousarray(tex)
+    H, W, Ch = tex.shape
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    n = uv.shape[0]
+    out = np.empty((n, Ch), np.float64)
+    idx = np.empty((n, 2), np.int32) if (want_index and gmode in (G_FIS, G_DISCRETE)) else None
+    if lib().orc_gauss_filter2d(_p(tex), W, H, Ch, fmt, _p(uv), n, float(sigma), gmode, seed, _p(out), _p(idx),
+                                nthreads) != 0:
+        raise ValueError("orc_gauss_filter2d rejected its arguments")
+    return out, idx
+
+
+def dct_gauss_filter2d(blocks: np.ndarray, uv: np.ndarray, sigma: float, gmode: int, seed: int = 0,
+                       want_index: bool = True, nthreads: int = 0):
+    b = np.ascontiguousarray(blocks, np.uint32)
+    H, W, Ch = b.shape[0] * 8, b.shape[1] * 8, b.shape[2]
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    n = uv.shape[0]
+    out = np.empty((n, Ch), np.float64)
+    idx = np.empty((n, 2), np.int32) if (want_index and gmode in (G_FIS, G_DISCRETE)) else None
+    if lib().orc_dct_gauss_filter2d(_p(b), W, H, Ch, _p(uv), n, float(sigma), gmode, seed, _p(out), _p(idx),
+                                    nthreads) != 0:
+        raise ValueError("orc_dct_gauss_filter2d rejected its arguments")
+    return out, idx
+
+
+def gauss_fis_positions(W: int, H: int, uv: np.ndarray, sigma: float, seed: int) -> np.ndarray:
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    pos = np.empty((uv.shape[0], 2), np.float64)
+    lib().orc_gauss_fis_positions(W, H, _p(uv), uv.shape[0], float(sigma), seed, _p(pos))
+    return pos
 
 
 # ----------------------------------------------------------------------------
@@ -314,7 +370,8 @@ def dct_filter2d(blocks: np.ndarray, uv: np.ndarray, filt: int, mode: int, seed:
     uv = np.ascontiguousarray(uv, dtype=np.float32)
     n = uv.shape[0]
     out = np.empty((n, Ch), np.float64)
-    idx = np.empty((n, index_width(filt, 2)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE)) else None
+    idx = np.empty((n, index_width(filt, 2)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE, STOCH_FIS)) \
+        else None
     if lib().orc_dct_filter2d(_p(b), W, H, Ch, _p(uv), n, filt, mode, seed, _p(out), _p(idx), nthreads) != 0:
         raise ValueError("orc_dct_filter2d rejected its arguments")
     return out, idx
@@ -364,7 +421,8 @@ class Grid:
         p = np.ascontiguousarray(p, dtype=np.float32)
         n = p.shape[0]
         out = np.empty(n, np.float64)
-        idx = np.empty((n, index_width(filt, 3)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE)) else None
+        idx = np.empty((n, index_width(filt, 3)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE, STOCH_FIS)) \
+            else None
         rc = lib().orc_filter3d(self._h, _p(p), n, filt, mode, seed, _p(out), _p(idx), nthreads)
         if rc != 0:
             raise ValueError("orc_filter3d failed")
@@ -378,7 +436,7 @@ class Grid:
         qids = np.ascontiguousarray(qids, dtype=np.int64)
         m = qids.shape[0]
         out = np.empty(m, np.float64)
-        idx = np.empty((m, index_width(filt, 3)), np.int32) if mode in (STOCH, STOCH_REUSE) else None
+        idx = np.empty((m, index_width(filt, 3)), np.int32) if mode in (STOCH, STOCH_REUSE, STOCH_FIS) else None
         rc = lib().orc_filter3d_at(self._h, _p(p), _p(qids), m, filt, mode, seed, _p(out), _p(idx), nthreads)
         if rc != 0:
             raise ValueError("orc_filter3d_at failed")

@@ -52,7 +52,7 @@
 enum { ORC_F32 = 0, ORC_F16 = 1, ORC_BF16 = 2, ORC_FP8_E4M3 = 3, ORC_U8 = 4 };
 /* filters and modes */
 enum { ORC_LINEAR = 0, ORC_CUBIC = 1, ORC_KEYS = 2, ORC_MITCHELL = 3 };
-enum { ORC_DET = 0, ORC_STOCH = 1, ORC_STOCH_REUSE = 2, ORC_DET_ABS = 3 };
+enum { ORC_DET = 0, ORC_STOCH = 1, ORC_STOCH_REUSE = 2, ORC_DET_ABS = 3, ORC_STOCH_FIS = 4 };
 /* ORC_DET_ABS: sum_k |w_k| |t_k|, the scale of the deterministic tolerance. */
 
 #define ORC_BAD_INDEX ((int32_t)0x80000000)
@@ -485,6 +485,27 @@ int orc_positivized_wrs2d(int filter, double tx, double ty, double u, int* off_p
 }
 
 /* ------------------------------------------------------------------------ */
+/* Filter importance sampling of the tent and cubic B-spline filters        */
+/* (section "Filter Importance Sampling"): a B-spline of degree n is the     */
+/* box-convolution of one of degree n - 1, so the position is jittered by a  */
+/* draw of the degree n - 1 spline -- a box (one uniform minus 1/2) for the  */
+/* tent, a quadratic B-spline (three uniforms minus 3/2, the Cox-de Boor     */
+/* sum) for the cubic -- and the nearest texel floor(x' + 1/2) is read.      */
+/* Binary64, exact: x is binary32 and the uniforms lie on the 2^-24 grid.    */
+/* Uniforms of axis a: hash index a (tent); a, 4 + a, 8 + a (cubic).         */
+/* ------------------------------------------------------------------------ */
+int orc_fis_tap(int filter, double x, uint64_t seed, uint32_t qid, int a)
+{
+    double s;
+    if (filter == ORC_LINEAR)
+        s = (double)orc_uniform(seed, qid, (uint32_t)a) - 0.5;
+    else
+        s = ((double)orc_uniform(seed, qid, (uint32_t)a) + (double)orc_uniform(seed, qid, 4u + (uint32_t)a)) +
+            (double)orc_uniform(seed, qid, 8u + (uint32_t)a) - 1.5;
+    return (int)floor(x + s + 0.5);
+}
+
+/* ------------------------------------------------------------------------ */
 /* 2D textures: row-major texels, channels interleaved; tap indices clamped. */
 /* ------------------------------------------------------------------------ */
 static int orc_clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -592,7 +613,10 @@ static void orc_query2d(const orc_src2d* src, const float* uv, int filter, int m
         return;
     }
     int jx, jy;
-    if (mode == ORC_STOCH) {
+    if (mode == ORC_STOCH_FIS) {
+        jx = orc_fis_tap(filter, (double)x, seed, qid, 0) - ix;
+        jy = orc_fis_tap(filter, (double)y, seed, qid, 1) - iy;
+    } else if (mode == ORC_STOCH) {
         jx = orc_select(filter, tx, orc_uniform(seed, qid, 0));
         jy = orc_select(filter, ty, orc_uniform(seed, qid, 1));
     } else {
@@ -620,6 +644,7 @@ int orc_max_threads(void) { return orc_threads(0); }
 static int orc_filter_src2d(const orc_src2d* src, const float* uv, int64_t n, int filter, int mode, uint64_t seed,
                             double* out, int32_t* idx, int nthreads)
 {
+    if (mode < ORC_DET || mode > ORC_STOCH_FIS || (orc_positivized(filter) && mode == ORC_STOCH_FIS)) return -1;
     int nt = orc_threads(nthreads), iw = orc_index_width(filter, 2), C = src->C;
     (void)nt;
 #pragma omp parallel for schedule(static) num_threads(nt)
@@ -779,7 +804,9 @@ static void orc_query3d(const orc_grid* g, const float* p, int filter, int mode,
         return;
     }
     int v[3];
-    if (mode == ORC_STOCH) {
+    if (mode == ORC_STOCH_FIS) {
+        for (int a = 0; a < 3; ++a) v[a] = orc_fis_tap(filter, (double)p[a], seed, qid, a);
+    } else if (mode == ORC_STOCH) {
         for (int a = 0; a < 3; ++a) v[a] = i[a] + orc_select(filter, t[a], orc_uniform(seed, qid, (uint32_t)a));
     } else {
         float u = orc_uniform(seed, qid, 0);
@@ -791,7 +818,8 @@ static void orc_query3d(const orc_grid* g, const float* p, int filter, int mode,
 
 static int orc_filter3d_args_ok(const orc_grid* g, int64_t n, int filter, int mode)
 {
-    if (!g || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return 0;
+    if (!g || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL || mode < ORC_DET || mode > ORC_STOCH_FIS) return 0;
+    if (orc_positivized(filter) && mode == ORC_STOCH_FIS) return 0;    /* FIS covers the B-spline family */
     return !(orc_positivized(filter) && mode == ORC_STOCH_REUSE);   /* the paper's listing is 2D */
 }
 
@@ -945,4 +973,168 @@ int orc_dct_moments2d(const uint32_t* blocks, int W, int H, int C, const float* 
         return -1;
     orc_src2d src = {blocks, W, H, C, ORC_FMT_DCT};
     return orc_moments_src2d(&src, uv, n, filter, mean, var, nthreads);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gaussian texture filtering (sections "Filter Importance Sampling" and     */
+/* "Results", magnification; supplement, "Real-time discrete and filter      */
+/* importance sampling").  Four modes, 2D, standard deviation sigma texels:  */
+/*   ORC_G_FIS: the position is offset by sigma times a standard normal pair */
+/*     from the Box-Muller transform of two uniforms (hash indices 0 and 1:  */
+/*     r = sqrt(-2 ln(1 - u0)), angle 2 pi u1, x offset r cos, y offset      */
+/*     r sin) and the nearest texel floor(x' + 1/2) is read (clamped);       */
+/*   ORC_G_FIS_MEAN: what FIS estimates -- the Gaussian convolved with the   */
+/*     nearest-texel box: tap k has weight Phi((k + 1/2 - x)/sigma) -        */
+/*     Phi((k - 1/2 - x)/sigma) per axis, over |k - floor(x)| <= R with      */
+/*     R = ceil(6 sigma) + 1 (the mass outside is below 2e-9);               */
+/*   ORC_G_DISCRETE: one tap of the 4x4 window i-1..i+2 drawn with           */
+/*     probability proportional to exp(-|d - t|^2 / (2 sigma^2)) (separable: */
+/*     per axis, hash index a, cumulative rule on the four weights);         */
+/*   ORC_G_DISCRETE_MEAN: the normalised weighted sum over that window.      */
+/* Binary64 throughout (the decisions of ORC_G_FIS and ORC_G_DISCRETE go     */
+/* through transcendental functions, so a device evaluating them with other  */
+/* rounding can differ only where a sample lies within rounding distance of  */
+/* a decision boundary).                                                     */
+/* ------------------------------------------------------------------------ */
+enum { ORC_G_FIS = 0, ORC_G_FIS_MEAN = 1, ORC_G_DISCRETE = 2, ORC_G_DISCRETE_MEAN = 3 };
+#define ORC_GAUSS_PI 3.14159265358979323846
+
+static double orc_phi(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
+int orc_gauss_radius(double sigma) { return (int)ceil(6.0 * sigma) + 1; }
+
+/* The FIS sample position of query qid (binary64). */
+void orc_gauss_fis_position(double x, double y, double sigma, uint64_t seed, uint32_t qid, double* xs, double* ys)
+{
+    double u0 = (double)orc_uniform(seed, qid, 0), u1 = (double)orc_uniform(seed, qid, 1);
+    double r = sqrt(-2.0 * log(1.0 - u0));
+    *xs = x + sigma * (r * cos(2.0 * ORC_GAUSS_PI * u1));
+    *ys = y + sigma * (r * sin(2.0 * ORC_GAUSS_PI * u1));
+}
+
+/* Discrete per-axis weights exp(-(d - t)^2 / (2 sigma^2)), d = -1..2. */
+static void orc_gauss_discrete_weights(double t, double sigma, double w[4])
+{
+    for (int k = 0; k < 4; ++k) {
+        double d = (double)(k - 1) - t;
+        w[k] = exp(-d * d / (2.0 * sigma * sigma));
+    }
+}
+
+static int orc_choice64(const double* m, int k, double u)
+{
+    double total = 0.0, c = 0.0;
+    int last = 0, j = 0;
+    for (int i = 0; i < k; ++i) {
+        total += m[i];
+        if (m[i] > 0.0) last = i;
+    }
+    double T = u * total;
+    for (int i = 0; i < k - 1; ++i) {
+        c += m[i];
+        j += (T >= c);
+    }
+    return j > last ? last : j;
+}
+
+static void orc_gauss_query(const orc_src2d* src, const float* uv, double sigma, int gmode, uint64_t seed,
+                            uint32_t qid, double* out, int32_t* idx)
+{
+    const int W = src->W, H = src->H, C = src->C;
+    float x, y, tx, ty;
+    int ix, iy;
+    orc_raster2d(uv, W, H, &x, &y);
+    if (!orc_cell(x, &ix, &tx) || !orc_cell(y, &iy, &ty)) { orc_nan_out(out, C, idx, 2); return; }
+    double xe = (double)x, ye = (double)y;
+    double fx = xe - floor(xe), fy = ye - floor(ye);   /* exact offsets */
+    if (gmode == ORC_G_FIS) {
+        double xs, ys;
+        orc_gauss_fis_position(xe, ye, sigma, seed, qid, &xs, &ys);
+        int sx = orc_clampi((int)fmax(fmin(floor(xs + 0.5), 2e9), -2e9), 0, W - 1);
+        int sy = orc_clampi((int)fmax(fmin(floor(ys + 0.5), 2e9), -2e9), 0, H - 1);
+        for (int c = 0; c < C; ++c) out[c] = orc_src_texel(src, sx, sy, c);
+        if (idx) { idx[0] = sx; idx[1] = sy; }
+        return;
+    }
+    if (gmode == ORC_G_DISCRETE) {
+        double wx[4], wy[4];
+        orc_gauss_discrete_weights(fx, sigma, wx);
+        orc_gauss_discrete_weights(fy, sigma, wy);
+        int sx = orc_clampi(ix - 1 + orc_choice64(wx, 4, (double)orc_uniform(seed, qid, 0)), 0, W - 1);
+        int sy = orc_clampi(iy - 1 + orc_choice64(wy, 4, (double)orc_uniform(seed, qid, 1)), 0, H - 1);
+        for (int c = 0; c < C; ++c) out[c] = orc_src_texel(src, sx, sy, c);
+        if (idx) { idx[0] = sx; idx[1] = sy; }
+        return;
+    }
+    if (gmode == ORC_G_DISCRETE_MEAN) {
+        double wx[4], wy[4], sx = 0.0, sy = 0.0;
+        orc_gauss_discrete_weights(fx, sigma, wx);
+        orc_gauss_discrete_weights(fy, sigma, wy);
+        for (int k = 0; k < 4; ++k) { sx += wx[k]; sy += wy[k]; }
+        for (int c = 0; c < C; ++c) {
+            double acc = 0.0;
+            for (int b = 0; b < 4; ++b)
+                for (int a = 0; a < 4; ++a) acc += wx[a] * wy[b] * orc_src_texel(src, ix - 1 + a, iy - 1 + b, c);
+            out[c] = acc / (sx * sy);
+        }
+        return;
+    }
+    /* ORC_G_FIS_MEAN */
+    int R = orc_gauss_radius(sigma), nt = 2 * R + 2;
+    double* wx = (double*)malloc(sizeof(double) * (size_t)nt * 2);
+    double* wy = wx + nt;
+    for (int k = 0; k < nt; ++k) {
+        double dx = (double)(ix - R + k) - xe, dy = (double)(iy - R + k) - ye;
+        wx[k] = orc_phi((dx + 0.5) / sigma) - orc_phi((dx - 0.5) / sigma);
+        wy[k] = orc_phi((dy + 0.5) / sigma) - orc_phi((dy - 0.5) / sigma);
+    }
+    for (int c = 0; c < C; ++c) {
+        double acc = 0.0;
+        for (int b = 0; b < nt; ++b) {
+            double row = 0.0;
+            for (int a = 0; a < nt; ++a) row += wx[a] * orc_src_texel(src, ix - R + a, iy - R + b, c);
+            acc += wy[b] * row;
+        }
+        out[c] = acc;
+    }
+    free(wx);
+}
+
+static int orc_gauss_src2d(const orc_src2d* src, const float* uv, int64_t n, double sigma, int gmode, uint64_t seed,
+                           double* out, int32_t* idx, int nthreads)
+{
+    if (!(sigma > 0.0 && sigma <= 16.0) || gmode < ORC_G_FIS || gmode > ORC_G_DISCRETE_MEAN || n < 0) return -1;
+    int nt = orc_threads(nthreads), C = src->C;
+    (void)nt;
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t q = 0; q < n; ++q)
+        orc_gauss_query(src, uv + 2 * q, sigma, gmode, seed, (uint32_t)q, out + q * C, idx ? idx + 2 * q : NULL);
+    return 0;
+}
+
+int orc_gauss_filter2d(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n, double sigma,
+                       int gmode, uint64_t seed, double* out, int32_t* idx, int nthreads)
+{
+    if (W <= 0 || H <= 0 || C <= 0 || C > 16) return -1;
+    orc_src2d src = {tex, W, H, C, fmt};
+    return orc_gauss_src2d(&src, uv, n, sigma, gmode, seed, out, idx, nthreads);
+}
+
+int orc_dct_gauss_filter2d(const uint32_t* blocks, int W, int H, int C, const float* uv, int64_t n, double sigma,
+                           int gmode, uint64_t seed, double* out, int32_t* idx, int nthreads)
+{
+    if (W <= 0 || H <= 0 || W % 8 || H % 8 || C <= 0 || C > 16) return -1;
+    orc_src2d src = {blocks, W, H, C, ORC_FMT_DCT};
+    return orc_gauss_src2d(&src, uv, n, sigma, gmode, seed, out, idx, nthreads);
+}
+
+/* FIS sample positions (binary64) of a batch, for boundary-distance checks. */
+int orc_gauss_fis_positions(int W, int H, const float* uv, int64_t n, double sigma, uint64_t seed, double* pos)
+{
+    for (int64_t q = 0; q < n; ++q) {
+        float x, y;
+        orc_raster2d(uv + 2 * q, W, H, &x, &y);
+        orc_gauss_fis_position((double)x, (double)y, sigma, seed, (uint32_t)q, &pos[2 * q], &pos[2 * q + 1]);
+    }
+    return 0;
 }
