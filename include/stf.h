@@ -101,7 +101,13 @@ typedef enum {
 
 typedef enum {
     STF_DETERMINISTIC = 0,   /* weighted sum over all taps (Eq. filtered-texture) */
-    STF_STOCHASTIC = 1       /* one tap drawn with probability = weight (Eq. stochastic-sum) */
+    STF_STOCHASTIC = 1,      /* one tap drawn with probability = weight (Eq. stochastic-sum) */
+    STF_STOCHASTIC_FIS = 2   /* linear / B-spline only: filter importance sampling (section "Filter
+                                Importance Sampling") -- the position jittered by a draw of the
+                                B-spline one degree lower (u - 1/2 for the tent; u_a + u_b + u_c - 3/2,
+                                a quadratic B-spline, for the cubic) and the nearest texel
+                                floor(x' + 1/2) read; the same tap distribution as STF_STOCHASTIC,
+                                no weights evaluated.  Decided in binary64 (exact). */
 } stf_mode;
 
 typedef enum {
@@ -170,6 +176,37 @@ stf_status stf_texture_bytes(const stf_texture* tex, int64_t* bytes);
 stf_status stf_filter(const stf_texture* tex, const float* queries_dev, int64_t n,
                       stf_filter_kind filter, stf_mode mode, uint64_t seed,
                       float* out_dev, int32_t* out_index_dev, uint32_t flags, void* hip_stream);
+
+/* ---------------------------------------------------------------------- */
+/* Gaussian filters                                                        */
+/* ---------------------------------------------------------------------- */
+/* Gaussian filtering of 2D (and DCT) textures with standard deviation sigma
+ * texels (sections "Filter Importance Sampling" and "Results",
+ * magnification; supplement, "Real-time discrete and filter importance
+ * sampling"):
+ *   STF_GAUSS_FIS: the position offset by sigma * (r cos 2 pi u1,
+ *     r sin 2 pi u1), r = sqrt(-2 ln(1 - u0)) (Box-Muller), and the nearest
+ *     texel floor(x' + 1/2) read -- an infinite-support filter, one texel;
+ *   STF_GAUSS_FIS_MEAN: what FIS estimates, the Gaussian convolved with the
+ *     nearest-texel box: per-axis weights Phi((k + 1/2 - x)/sigma) -
+ *     Phi((k - 1/2 - x)/sigma) over |k - floor(x)| <= ceil(6 sigma) + 1
+ *     (sigma <= 4 for this mode);
+ *   STF_GAUSS_DISCRETE: one tap of the 4x4 window i-1..i+2 with probability
+ *     proportional to exp(-|d - t|^2 / (2 sigma^2));
+ *   STF_GAUSS_DISCRETE_MEAN: the normalised weighted sum over that window.
+ * 0 < sigma <= 16.  Weights and decisions in binary64 (transcendental
+ * functions), accumulation in binary32.  out_index_dev: NULL or, for the two
+ * stochastic modes, n x 2 int32 (clamped texel). */
+typedef enum {
+    STF_GAUSS_FIS = 0,
+    STF_GAUSS_FIS_MEAN = 1,
+    STF_GAUSS_DISCRETE = 2,
+    STF_GAUSS_DISCRETE_MEAN = 3
+} stf_gauss_mode;
+
+stf_status stf_filter_gaussian(const stf_texture* tex, const float* queries_dev, int64_t n, float sigma,
+                               stf_gauss_mode mode, uint64_t seed, float* out_dev, int32_t* out_index_dev,
+                               void* hip_stream);
 
 /* ---------------------------------------------------------------------- */
 /* DCT-compressed textures                                                 */

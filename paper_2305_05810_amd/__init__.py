@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libstf.so")
 STF_OK, STF_E_INVALID, STF_E_OOM, STF_E_UNSUPPORTED, STF_E_DEVICE, STF_E_BUSY, STF_E_CANCELLED = 0, -1, -2, -3, -4, -5, -6
 STF_FMT_F32, STF_FMT_F16, STF_FMT_BF16, STF_FMT_FP8_E4M3, STF_FMT_U8 = 0, 1, 2, 3, 4
 STF_LINEAR, STF_CUBIC_BSPLINE, STF_CUBIC_KEYS, STF_CUBIC_MITCHELL = 0, 1, 2, 3
+STF_GAUSS_FIS, STF_GAUSS_FIS_MEAN, STF_GAUSS_DISCRETE, STF_GAUSS_DISCRETE_MEAN = 0, 1, 2, 3
 POSITIVIZED_FILTERS = (STF_CUBIC_KEYS, STF_CUBIC_MITCHELL)
 
 
@@ -27,7 +28,7 @@ def index_width(filter: int, dims: int) -> int:
     """int32 index entries per query in stochastic mode: the tap, or for the
     interpolating cubics the positive tap followed by the negative tap."""
     return 2 * dims if filter in POSITIVIZED_FILTERS else dims
-STF_DETERMINISTIC, STF_STOCHASTIC = 0, 1
+STF_DETERMINISTIC, STF_STOCHASTIC, STF_STOCHASTIC_FIS = 0, 1, 2
 STF_SHADE_AFTER_FILTER, STF_FILTER_AFTER_SHADE, STF_SHADE_STOCHASTIC = 0, 1, 2
 
 FORMATS = {"f32": STF_FMT_F32, "f16": STF_FMT_F16, "bf16": STF_FMT_BF16, "fp8_e4m3": STF_FMT_FP8_E4M3,
@@ -76,10 +77,11 @@ def _declare(L):
     L.stf_filter_moments.argtypes = [vp, vp, i64, i32, u64, i32, vp, vp, vp]
     L.stf_shade_filter.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, vp]
     L.stf_dct_encode.argtypes = [i32, i32, i32, vp, vp]
+    L.stf_filter_gaussian.argtypes = [vp, vp, i64, f32, i32, u64, vp, vp, vp]
     L.stf_create_dct_texture2d.argtypes = [i32, i32, i32, vp, C.POINTER(vp)]
     for name in ("stf_create_texture2d", "stf_create_material2d", "stf_create_sparse_grid3d",
                  "stf_texture_bytes", "stf_filter", "stf_filter_moments", "stf_shade_filter", "stf_dct_encode",
-                 "stf_create_dct_texture2d"):
+                 "stf_create_dct_texture2d", "stf_filter_gaussian"):
         getattr(L, name).restype = i32
 
 
@@ -244,6 +246,19 @@ def stf_filter(tex: Texture, queries, filter: int, mode: int, seed: int, out, ou
                             _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"), flags, _stream(stream)))
 
 
+def stf_filter_gaussian(tex: Texture, queries, sigma: float, mode: int, seed: int, out, out_index=None, stream=None):
+    """Gaussian filtering of a 2D texture (STF_GAUSS_* modes); out: (n,
+    channels) float32; out_index: None or (n, 2) int32 (stochastic modes)."""
+    n = queries.shape[0]
+    if out.numel() < n * tex.channels:
+        raise ValueError("out is too small")
+    if out_index is not None and out_index.numel() < 2 * n:
+        raise ValueError("out_index is too small")
+    _check(lib().stf_filter_gaussian(
+        tex.handle, _dev_ptr(queries, "queries"), n, float(sigma), mode, seed & (2 ** 64 - 1), _dev_ptr(out, "out"),
+        _dev_ptr(out_index, "out_index"), _stream(stream)))
+
+
 def stf_filter_moments(tex: Texture, queries, filter: int, seed_base: int, n_seeds: int, sum_out, sumsq_out,
                        stream=None):
     n = queries.shape[0]
@@ -269,7 +284,7 @@ def filter(tex: Texture, queries, filter: int, mode: int, seed: int = 0, want_in
     n = queries.shape[0]
     out = torch.empty((n, tex.channels), dtype=torch.float32, device=queries.device)
     idx = None
-    if want_index and mode == STF_STOCHASTIC:
+    if want_index and mode in (STF_STOCHASTIC, STF_STOCHASTIC_FIS):
         idx = torch.empty((n, index_width(filter, tex.dims)), dtype=torch.int32, device=queries.device)
     stf_filter(tex, queries, filter, mode, seed, out, idx, 0, stream)
     return out, idx

@@ -130,7 +130,7 @@ __device__ __forceinline__ void block_store(const Src& S, float* __restrict__ ou
 
 // Query i of a batch (i valid), drawn with id qid0 + i (or order[i]): its
 // values, its tap (INT32_MIN for a non-finite query) and where its results go.
-template <class Src, bool CUBIC>
+template <class Src, bool CUBIC, bool FIS = false>
 __device__ __forceinline__ void tex2d_stochastic_eval(const Src& S, const float* __restrict__ q, int32_t i, uint32_t key,
                                                       uint32_t qid0, const int32_t* __restrict__ order, int scatter,
                                                       float (&v)[Src::CAP], int& sx, int& sy, int64_t& oi)
@@ -147,13 +147,18 @@ __device__ __forceinline__ void tex2d_stochastic_eval(const Src& S, const float*
     sy = BAD_INDEX;
     if (ok) {
         uint32_t b = pcg(key ^ (uint32_t)id);
-        float ux = axis_uniform(b, 0), uy = axis_uniform(b, 1);
-        if constexpr (CUBIC) {
-            sx = cx + choose_cubic(tx, ux);
-            sy = cy + choose_cubic(ty, uy);
+        if constexpr (FIS) {
+            sx = fis_tap<CUBIC>(x, b, 0);
+            sy = fis_tap<CUBIC>(y, b, 1);
         } else {
-            sx = cx + choose_linear(tx, ux);
-            sy = cy + choose_linear(ty, uy);
+            float ux = axis_uniform(b, 0), uy = axis_uniform(b, 1);
+            if constexpr (CUBIC) {
+                sx = cx + choose_cubic(tx, ux);
+                sy = cy + choose_cubic(ty, uy);
+            } else {
+                sx = cx + choose_linear(tx, ux);
+                sy = cy + choose_linear(ty, uy);
+            }
         }
         sx = clampi(sx, S.w() - 1);
         sy = clampi(sy, S.h() - 1);
@@ -164,7 +169,7 @@ __device__ __forceinline__ void tex2d_stochastic_eval(const Src& S, const float*
     }
 }
 
-template <class Src, bool CUBIC>
+template <class Src, bool CUBIC, bool FIS>
 __global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(Src S, const float* __restrict__ q, int32_t n,
                                                             uint32_t key, float* __restrict__ out,
                                                             int32_t* __restrict__ idx, const int32_t* __restrict__ order,
@@ -175,7 +180,7 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_stochastic(Src S, const float* 
     float v[Src::CAP];
     int sx, sy;
     int64_t oi;
-    tex2d_stochastic_eval<Src, CUBIC>(S, q, live ? i : 0, key, 0u, order, scatter, v, sx, sy, oi);
+    tex2d_stochastic_eval<Src, CUBIC, FIS>(S, q, live ? i : 0, key, 0u, order, scatter, v, sx, sy, oi);
     block_store(S, out, n, live, oi, v, order && scatter);
     if (live && idx) {
         idx[2 * oi] = sx;
@@ -371,6 +376,159 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_moments(Src S, const float* __r
 }
 
 // ---------------------------------------------------------------------------
+// Gaussian filters (sections "Filter Importance Sampling" and "Results",
+// magnification).  Decisions and weights in binary64; sigma in texels.
+//   GAUSS_FIS: offset sigma (r cos 2 pi u1, r sin 2 pi u1), r = sqrt(-2 ln(1 -
+//     u0)) (Box-Muller of hash indices 0, 1), nearest texel floor(x' + 1/2).
+//   GAUSS_FIS_MEAN: the Gaussian convolved with the nearest-texel box (what
+//     GAUSS_FIS estimates): per-axis weights Phi((k + 1/2 - x)/sigma) -
+//     Phi((k - 1/2 - x)/sigma) over |k - floor(x)| <= R = ceil(6 sigma) + 1.
+//   GAUSS_DISCRETE: window i-1..i+2, per-axis weights exp(-(d - t)^2 /
+//     (2 sigma^2)), one tap per axis by the cumulative rule (hash index a).
+//   GAUSS_DISCRETE_MEAN: the normalised sum over that window.
+// ---------------------------------------------------------------------------
+enum GaussMode { GAUSS_FIS = 0, GAUSS_FIS_MEAN = 1, GAUSS_DISCRETE = 2, GAUSS_DISCRETE_MEAN = 3 };
+constexpr int GAUSS_MAX_TAPS = 52;   // 2 R + 2 for sigma <= 4 (GAUSS_FIS_MEAN)
+
+__device__ __forceinline__ double gauss_phi(double z)
+{
+    return 0.5 * erfc(-z * 0.70710678118654752440);
+}
+
+__device__ __forceinline__ void gauss_discrete_weights(double t, double inv2s2, double (&w)[4])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double d = (double)(k - 1) - t;
+        w[k] = exp(-(d * d) * inv2s2);
+    }
+}
+
+__device__ __forceinline__ int gauss_pick(const double (&m)[4], double u)
+{
+    const double total = ((m[0] + m[1]) + m[2]) + m[3];
+    const int last = m[3] > 0.0 ? 3 : (m[2] > 0.0 ? 2 : (m[1] > 0.0 ? 1 : 0));
+    const double T = u * total;
+    int j = (T >= m[0]) + (T >= m[0] + m[1]) + (T >= (m[0] + m[1]) + m[2]);
+    return j > last ? last : j;
+}
+
+template <class Src, int GMODE>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __restrict__ q, int32_t n, float sigma,
+                                                       int32_t radius, uint32_t key, float* __restrict__ out,
+                                                       int32_t* __restrict__ idx)
+{
+    constexpr int CAP = Src::CAP;
+    const int32_t i0 = blockIdx.x * BLOCK + threadIdx.x;
+    const bool live = i0 < n;
+    const int32_t i = live ? i0 : 0;
+    float2 uv = reinterpret_cast<const float2*>(q)[i];
+    const float x = uv.x * (float)S.w() - 0.5f;
+    const float y = uv.y * (float)S.h() - 0.5f;
+    int cx = 0, cy = 0;
+    float tx = 0.0f, ty = 0.0f;
+    const bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
+    const double xe = (double)x, ye = (double)y, sg = (double)sigma;
+    float v[CAP];
+    int sx = BAD_INDEX, sy = BAD_INDEX;
+    if constexpr (GMODE == GAUSS_FIS || GMODE == GAUSS_DISCRETE) {
+        if (ok) {
+            const uint32_t h0 = pcg(key ^ (uint32_t)i);
+            const double u0 = (double)hash_uniform(h0), u1 = (double)axis_uniform(h0, 1);
+            if constexpr (GMODE == GAUSS_FIS) {
+                const double r = sqrt(-2.0 * log(1.0 - u0));
+                const double a = 6.28318530717958647692 * u1;
+                const double xs = xe + sg * (r * cos(a)), ys = ye + sg * (r * sin(a));
+                sx = (int)fmin(fmax(floor(xs + 0.5), -1.0), (double)S.w());
+                sy = (int)fmin(fmax(floor(ys + 0.5), -1.0), (double)S.h());
+            } else {
+                const double inv2s2 = 1.0 / (2.0 * sg * sg);
+                double wx[4], wy[4];
+                gauss_discrete_weights(xe - floor(xe), inv2s2, wx);
+                gauss_discrete_weights(ye - floor(ye), inv2s2, wy);
+                sx = cx - 1 + gauss_pick(wx, u0);
+                sy = cy - 1 + gauss_pick(wy, u1);
+            }
+            sx = clampi(sx, S.w() - 1);
+            sy = clampi(sy, S.h() - 1);
+            S.load(sx, sy, v);
+        } else {
+#pragma unroll
+            for (int c = 0; c < CAP; ++c) v[c] = __builtin_nanf("");
+        }
+    } else if constexpr (GMODE == GAUSS_DISCRETE_MEAN) {
+        const double inv2s2 = 1.0 / (2.0 * sg * sg);
+        double dx[4], dy[4];
+        gauss_discrete_weights(xe - floor(xe), inv2s2, dx);
+        gauss_discrete_weights(ye - floor(ye), inv2s2, dy);
+        const double nx = ((dx[0] + dx[1]) + dx[2]) + dx[3], ny = ((dy[0] + dy[1]) + dy[2]) + dy[3];
+        float wx[4], wy[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            wx[k] = (float)(dx[k] / nx);
+            wy[k] = (float)(dy[k] / ny);
+        }
+        float acc[CAP];
+#pragma unroll
+        for (int c = 0; c < CAP; ++c) acc[c] = 0.0f;
+        for (int b = 0; b < 4; ++b) {
+            const int yy = clampi(cy - 1 + b, S.h() - 1);
+            float row[CAP];
+#pragma unroll
+            for (int c = 0; c < CAP; ++c) row[c] = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                float t[CAP];
+                S.load(clampi(cx - 1 + a, S.w() - 1), yy, t);
+#pragma unroll
+                for (int c = 0; c < CAP; ++c) row[c] = __builtin_fmaf(wx[a], t[c], row[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < CAP; ++c) acc[c] = __builtin_fmaf(wy[b], row[c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < CAP; ++c) v[c] = ok ? acc[c] : __builtin_nanf("");
+    } else {   // GAUSS_FIS_MEAN
+        const int nt = 2 * radius + 2;
+        float wx[GAUSS_MAX_TAPS], wy[GAUSS_MAX_TAPS];
+        double px = gauss_phi(((double)(cx - radius) - xe - 0.5) / sg);
+        double py = gauss_phi(((double)(cy - radius) - ye - 0.5) / sg);
+        for (int k = 0; k < nt; ++k) {
+            const double qx = gauss_phi(((double)(cx - radius + k) - xe + 0.5) / sg);
+            const double qy = gauss_phi(((double)(cy - radius + k) - ye + 0.5) / sg);
+            wx[k] = (float)(qx - px);
+            wy[k] = (float)(qy - py);
+            px = qx;
+            py = qy;
+        }
+        float acc[CAP];
+#pragma unroll
+        for (int c = 0; c < CAP; ++c) acc[c] = 0.0f;
+        for (int b = 0; b < nt; ++b) {
+            const int yy = clampi(cy - radius + b, S.h() - 1);
+            float row[CAP];
+#pragma unroll
+            for (int c = 0; c < CAP; ++c) row[c] = 0.0f;
+            for (int a = 0; a < nt; ++a) {
+                float t[CAP];
+                S.load(clampi(cx - radius + a, S.w() - 1), yy, t);
+#pragma unroll
+                for (int c = 0; c < CAP; ++c) row[c] = __builtin_fmaf(wx[a], t[c], row[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < CAP; ++c) acc[c] = __builtin_fmaf(wy[b], row[c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < CAP; ++c) v[c] = ok ? acc[c] : __builtin_nanf("");
+    }
+    block_store(S, out, n, live, (int64_t)i, v, false);
+    if (live && idx && (GMODE == GAUSS_FIS || GMODE == GAUSS_DISCRETE)) {
+        idx[2 * (int64_t)i] = sx;
+        idx[2 * (int64_t)i + 1] = sy;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 template <class Src, int KIND>
@@ -383,8 +541,12 @@ void launch2d_kind(const Src& S, const float* q, int32_t n, int mode, uint32_t k
             hipLaunchKernelGGL((k_tex2d_positivized<Src, KIND>), grid, block, 0, stream, S, q, n, key, out, idx, order,
                                scatter);
         else
-            hipLaunchKernelGGL((k_tex2d_stochastic<Src, KIND == KIND_BSPLINE>), grid, block, 0, stream, S, q, n, key,
-                               out, idx, order, scatter);
+            hipLaunchKernelGGL((k_tex2d_stochastic<Src, KIND == KIND_BSPLINE, false>), grid, block, 0, stream, S, q, n,
+                               key, out, idx, order, scatter);
+    } else if (mode == STF_STOCHASTIC_FIS) {
+        if constexpr (KIND == KIND_LINEAR || KIND == KIND_BSPLINE)
+            hipLaunchKernelGGL((k_tex2d_stochastic<Src, KIND == KIND_BSPLINE, true>), grid, block, 0, stream, S, q, n,
+                               key, out, idx, order, scatter);
     } else {
         hipLaunchKernelGGL((k_tex2d_deterministic<Src, KIND>), grid, block, 0, stream, S, q, n, out, order, scatter);
     }
@@ -470,7 +632,42 @@ hipError_t with_src(const stf_texture* t, F&& f)
     return hipErrorInvalidValue;
 }
 
+template <class Src>
+hipError_t gauss2d_src(const Src& S, const float* q, int32_t n, float sigma, int gmode, uint32_t key, float* out,
+                       int32_t* idx, hipStream_t stream)
+{
+    dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
+    const int32_t radius = (int32_t)ceilf(6.0f * sigma) + 1;
+    switch (gmode) {
+    case GAUSS_FIS:
+        hipLaunchKernelGGL((k_tex2d_gauss<Src, GAUSS_FIS>), grid, block, 0, stream, S, q, n, sigma, radius, key, out,
+                           idx);
+        break;
+    case GAUSS_FIS_MEAN:
+        if (2 * radius + 2 > GAUSS_MAX_TAPS) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_tex2d_gauss<Src, GAUSS_FIS_MEAN>), grid, block, 0, stream, S, q, n, sigma, radius, key,
+                           out, idx);
+        break;
+    case GAUSS_DISCRETE:
+        hipLaunchKernelGGL((k_tex2d_gauss<Src, GAUSS_DISCRETE>), grid, block, 0, stream, S, q, n, sigma, radius, key,
+                           out, idx);
+        break;
+    case GAUSS_DISCRETE_MEAN:
+        hipLaunchKernelGGL((k_tex2d_gauss<Src, GAUSS_DISCRETE_MEAN>), grid, block, 0, stream, S, q, n, sigma, radius,
+                           key, out, idx);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_gauss2d(const stf_texture* t, const float* q, int32_t n, float sigma, int gmode, uint32_t key,
+                          float* out, int32_t* idx, hipStream_t s)
+{
+    return with_src(t, [&](auto S) { return gauss2d_src(S, q, n, sigma, gmode, key, out, idx, s); });
+}
 
 hipError_t launch_filter2d(const stf_texture* t, const float* q, int32_t n, int filter, int mode, uint32_t key,
                            float* out, int32_t* idx, const int32_t* order, int scatter, hipStream_t s)

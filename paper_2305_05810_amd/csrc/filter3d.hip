@@ -79,7 +79,7 @@ __device__ __forceinline__ int32_t table_load(const int32_t* __restrict__ t, uin
 
 // One block's share: queries first + k*BLOCK (k < Q) of a batch of n, whose
 // random draw uses the id qid0 + index.
-template <int FMT, bool CUBIC, int Q>
+template <int FMT, bool CUBIC, int Q, bool FIS = false>
 __device__ __forceinline__ void grid_stochastic_block(const GridView& g, const float* __restrict__ q, int32_t n,
                                                       int32_t first, uint32_t key, uint32_t qid0,
                                                       float* __restrict__ out, int32_t* __restrict__ idx,
@@ -114,7 +114,11 @@ __device__ __forceinline__ void grid_stochastic_block(const GridView& g, const f
         uint32_t h0 = pcg(key ^ qid[k]), h1, h2;
         pcg_next2(h0, h1, h2);
         float m0 = hash_m(h0), m1 = hash_m(h1), m2 = hash_m(h2);
-        if constexpr (CUBIC) {
+        if constexpr (FIS) {
+            vx[k] = fis_tap<CUBIC>(p[k][0], h0, 0);
+            vy[k] = fis_tap<CUBIC>(p[k][1], h0, 1);
+            vz[k] = fis_tap<CUBIC>(p[k][2], h0, 2);
+        } else if constexpr (CUBIC) {
             vx[k] = c0 + choose_cubic_m(t0, m0);
             vy[k] = c1 + choose_cubic_m(t1, m1);
             vz[k] = c2 + choose_cubic_m(t2, m2);
@@ -303,6 +307,17 @@ __global__ __launch_bounds__(BLOCK) void k_grid_positivized(GridView g, const fl
     }
 }
 
+// Filter importance sampling of the same filters: jittered position, nearest
+// voxel (fis_tap); otherwise the single-tap kernel.
+template <int FMT, bool CUBIC, int Q>
+__global__ __launch_bounds__(BLOCK) void k_grid_fis(GridView g, const float* __restrict__ q, int32_t n, uint32_t key,
+                                                    float* __restrict__ out, int32_t* __restrict__ idx,
+                                                    const int32_t* __restrict__ order, int scatter)
+{
+    grid_stochastic_block<FMT, CUBIC, Q, true>(g, q, n, blockIdx.x * (BLOCK * Q) + threadIdx.x, key, 0u, out, idx,
+                                               order, scatter);
+}
+
 // Serving: one launch over many requests' chunks (same grid and filter).
 // Block b serves chunk c with start[c] <= b < start[c + 1].
 template <int FMT, bool CUBIC, int Q>
@@ -467,6 +482,13 @@ void launch3d_kind(const GridView& g, const float* q, int32_t n, int mode, uint3
             dim3 sgrid((unsigned)(((int64_t)n + BLOCK * Q - 1) / (BLOCK * Q)));
             hipLaunchKernelGGL((k_grid_stochastic<FMT, KIND == KIND_BSPLINE, Q>), sgrid, block, 0, stream, g, q, n, key,
                                out, idx, order, scatter);
+        }
+    } else if (mode == STF_STOCHASTIC_FIS) {
+        if constexpr (KIND == KIND_LINEAR || KIND == KIND_BSPLINE) {
+            constexpr int Q = STOCH_Q;
+            dim3 sgrid((unsigned)(((int64_t)n + BLOCK * Q - 1) / (BLOCK * Q)));
+            hipLaunchKernelGGL((k_grid_fis<FMT, KIND == KIND_BSPLINE, Q>), sgrid, block, 0, stream, g, q, n, key, out,
+                               idx, order, scatter);
         }
     } else {
         dim3 grid((n + BLOCK - 1) / BLOCK);

@@ -224,6 +224,26 @@ __device__ __forceinline__ PosDraw<D> positivized_draw(const float (&t)[D], uint
     return r;
 }
 
+// Filter importance sampling of the tent / cubic B-spline (section "Filter
+// Importance Sampling"): jitter the position by a draw of the B-spline one
+// degree lower -- a box (u - 1/2) for the tent, a quadratic B-spline (the sum
+// of three uniforms minus 3/2) for the cubic -- and read the nearest texel
+// floor(x' + 1/2).  Binary64 is exact here (binary32 x, uniforms on the 2^-24
+// grid), so the tap is a pure function of (x, seed, query).  Uniforms of axis
+// a: hash index a (tent); a, 4 + a, 8 + a (cubic).
+template <bool CUBIC>
+__device__ __forceinline__ int fis_tap(float x, uint32_t h0, int a)
+{
+    const uint32_t base = h0 * 747796405u + 2891336453u;
+    auto u = [&](uint32_t k) { return (double)(k == 0 ? hash_uniform(h0) : uniform_from_base(base, k)); };
+    double s;
+    if constexpr (CUBIC)
+        s = ((u((uint32_t)a) + u(4u + (uint32_t)a)) + u(8u + (uint32_t)a)) - 1.5;
+    else
+        s = u((uint32_t)a) - 0.5;
+    return (int)__builtin_floor((double)x + s + 0.5);
+}
+
 // 1 / axis_scale^D as a binary32 constant.
 template <int D, int KIND>
 constexpr float inv_scale()

@@ -182,7 +182,7 @@ stf_status stf_filter_ordered(const stf_texture* tex, const float* sorted_querie
         return stf_fail(STF_E_INVALID, "stf_filter_ordered needs a 2D texture or a 3D grid");
     if (n < 0 || n > 0x7fffffff) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
     if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
-    if (mode != STF_DETERMINISTIC && mode != STF_STOCHASTIC) return stf_fail(STF_E_INVALID, "unknown mode %d", (int)mode);
+    if (!valid_mode(filter, mode)) return stf_fail(STF_E_INVALID, "mode %d is not available for filter %d", (int)mode, (int)filter);
     if (flags & ~(uint32_t)STF_ORDER_SCATTER) return stf_fail(STF_E_INVALID, "unknown flags 0x%x", flags);
     if (mode == STF_DETERMINISTIC && out_index_dev)
         return stf_fail(STF_E_INVALID, "out_index_dev must be NULL in deterministic mode");

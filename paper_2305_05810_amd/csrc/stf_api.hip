@@ -281,7 +281,7 @@ stf_status stf_filter(const stf_texture* tex, const float* queries_dev, int64_t 
         return stf_fail(STF_E_INVALID, "stf_filter needs a 2D texture or a 3D grid");
     if (n < 0 || n > MAX_QUERIES) return stf_fail(STF_E_INVALID, "n = %lld out of range (0..2^31-1)", (long long)n);
     if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter %d", (int)filter);
-    if (mode != STF_DETERMINISTIC && mode != STF_STOCHASTIC) return stf_fail(STF_E_INVALID, "unknown mode %d", (int)mode);
+    if (!valid_mode(filter, mode)) return stf_fail(STF_E_INVALID, "mode %d is not available for filter %d", (int)mode, (int)filter);
     if (flags != 0) return stf_fail(STF_E_INVALID, "unknown flags 0x%x", flags);
     if (mode == STF_DETERMINISTIC && out_index_dev)
         return stf_fail(STF_E_INVALID, "out_index_dev must be NULL in deterministic mode");
@@ -297,6 +297,31 @@ stf_status stf_filter(const stf_texture* tex, const float* queries_dev, int64_t 
                                           nullptr, 0, st)
                         : launch_filter3d(tex, queries_dev, (int32_t)n, filter, mode, key, out_dev, out_index_dev,
                                           nullptr, 0, st);
+    if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return STF_OK;
+}
+
+stf_status stf_filter_gaussian(const stf_texture* tex, const float* queries_dev, int64_t n, float sigma,
+                               stf_gauss_mode mode, uint64_t seed, float* out_dev, int32_t* out_index_dev,
+                               void* hip_stream)
+{
+    stf_clear_error();
+    if (!tex) return stf_fail(STF_E_INVALID, "texture is NULL");
+    if (!is_2d_filterable(tex)) return stf_fail(STF_E_INVALID, "stf_filter_gaussian needs a 2D texture");
+    if (n < 0 || n > MAX_QUERIES) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
+    if (!(sigma > 0.0f && sigma <= 16.0f)) return stf_fail(STF_E_INVALID, "sigma = %g out of range (0, 16]", (double)sigma);
+    if (mode < STF_GAUSS_FIS || mode > STF_GAUSS_DISCRETE_MEAN) return stf_fail(STF_E_INVALID, "unknown mode %d", (int)mode);
+    if (mode == STF_GAUSS_FIS_MEAN && sigma > 4.0f)
+        return stf_fail(STF_E_UNSUPPORTED, "STF_GAUSS_FIS_MEAN supports sigma <= 4 (window of 52 taps per axis)");
+    if (out_index_dev && (mode == STF_GAUSS_FIS_MEAN || mode == STF_GAUSS_DISCRETE_MEAN))
+        return stf_fail(STF_E_INVALID, "out_index_dev must be NULL in the deterministic modes");
+    if (n == 0) return STF_OK;
+    stf_status s = check_device_ptr(queries_dev, "queries_dev", 8);
+    if (s == STF_OK) s = check_device_ptr(out_dev, "out_dev", 4);
+    if (s == STF_OK && out_index_dev) s = check_device_ptr(out_index_dev, "out_index_dev", 4);
+    if (s != STF_OK) return s;
+    hipError_t e = launch_gauss2d(tex, queries_dev, (int32_t)n, sigma, (int)mode, stf::seed_key(seed), out_dev,
+                                  out_index_dev, (hipStream_t)hip_stream);
     if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return STF_OK;
 }

@@ -70,6 +70,14 @@ inline bool is_2d_filterable(const stf_texture* t)
     return t->kind == STF_KIND_TEX2D || t->kind == STF_KIND_DCT2D;
 }
 
+// Modes of stf_filter for a filter (filter importance sampling covers the
+// B-spline family only).
+inline bool valid_mode(int filter, int mode)
+{
+    if (mode == STF_DETERMINISTIC || mode == STF_STOCHASTIC) return true;
+    return mode == STF_STOCHASTIC_FIS && (filter == STF_LINEAR || filter == STF_CUBIC_BSPLINE);
+}
+
 // Filters of stf_filter / stf_filter_ordered / stf_filter_moments.
 inline bool valid_filter(int f)
 {
@@ -86,6 +94,8 @@ hipError_t launch_filter2d(const stf_texture* tex, const float* q, int32_t n, in
 hipError_t launch_filter3d(const stf_texture* tex, const float* q, int32_t n, int filter, int mode,
                            uint32_t skey, float* out, int32_t* idx, const int32_t* order, int scatter,
                            hipStream_t stream);
+hipError_t launch_gauss2d(const stf_texture* t, const float* q, int32_t n, float sigma, int gmode, uint32_t key,
+                          float* out, int32_t* idx, hipStream_t s);
 hipError_t launch_moments2d(const stf_texture* tex, const float* q, int32_t n, int filter,
                             uint64_t seed_base, int32_t n_seeds, double* sum, double* sumsq,
                             hipStream_t stream);
