@@ -16,8 +16,9 @@ uv queries), `shade` (4096^2 material, 8M shading queries, three filter
 orders), `neural` (4096^2 x 8 texture as a 1024^2 x 8 latent grid + MLP:
 training and BF16-MFMA inference), `serving` (three resident textures,
 Poisson arrivals of log-normal request sizes at 0.5 / 1 / 2 G lookups/s),
-`dct` (4096^2 x 9 DCT-compressed texture set, 16M uv queries, one decode per
-stochastic lookup).  The grid workload also times the interpolating cubics
+`dct` (4096^2 x 9 DCT-compressed texture set, a 4K frame of uv queries, one
+decode per stochastic lookup), `gauss` (Gaussian FIS vs discrete 4x4 at sigma
+0.3 / 0.5 / 0.8 on the same set and frame).  The grid workload also times the interpolating cubics
 (Keys, Mitchell-Netravali; positivized two-tap stochastic vs 64-tap).
 
 Prints one JSON line.
@@ -343,6 +344,54 @@ def run_dct(args, torch, stf, synth):
 
 
 # ----------------------------------------------------------------------------
+# Gaussian filters and filter importance sampling
+# ----------------------------------------------------------------------------
+def run_gauss(args, torch, stf, synth):
+    """The sigma in {0.3, 0.5, 0.8} comparison of FIS and discrete 4x4
+    sampling on the DCT texture set over a 4K frame: throughput of each mode
+    and, per sigma, how far the discrete 4x4 filter's mean lies from the
+    box-convolved Gaussian that FIS estimates (RMS over the frame)."""
+    dev = torch.device("cuda:0")
+    size, C = 4096, 9
+    tex_np = synth.texture_set_u8(size, seed=51)
+    tex = stf.stf_create_dct_texture2d(size, size, C, stf.stf_dct_encode(tex_np))
+    uv = synth.screen_uv_queries(3840, 2160, seed=53)
+    n = uv.shape[0]
+    q = torch.from_numpy(uv).to(dev)
+    out = torch.empty((n, C), dtype=torch.float32, device=dev)
+    ref = torch.empty_like(out)
+    res, quality = {}, {}
+    block_b = 4 * ((C + 3) // 4 * 4)
+    for sigma in (0.3, 0.5, 0.8):
+        for name, mode in (("fis", stf.STF_GAUSS_FIS), ("discrete", stf.STF_GAUSS_DISCRETE),
+                           ("fis_mean", stf.STF_GAUSS_FIS_MEAN), ("discrete_mean", stf.STF_GAUSS_DISCRETE_MEAN)):
+            taps = {"fis": 1, "discrete": 1, "discrete_mean": 16,
+                    "fis_mean": (2 * (int(np.ceil(6 * sigma)) + 1) + 2) ** 2}[name]
+            wall, kern = time_launches(lambda: stf.stf_filter_gaussian(tex, q, sigma, mode, 5, out), args.steps,
+                                       args.warmup, torch)
+            key = f"{name}_sigma{sigma}"
+            res[key] = variant_stats(n, args.steps, wall, kern, 8 + 4 * C + taps * block_b)
+            res[key]["decodes_per_lookup"] = taps
+            log(f"{key}: {res[key]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel {res[key]['kernel_ms_mean'] * 1e3:.1f} us")
+        stf.stf_filter_gaussian(tex, q, sigma, stf.STF_GAUSS_FIS_MEAN, 0, ref)
+        stf.stf_filter_gaussian(tex, q, sigma, stf.STF_GAUSS_DISCRETE_MEAN, 0, out)
+        quality[f"sigma{sigma}"] = {"rms_discrete_mean_minus_fis_mean": float(torch.sqrt(((out - ref) ** 2).mean()).item())}
+        log(f"sigma {sigma}: {quality[f'sigma{sigma}']}")
+    head = res["fis_sigma0.5"]
+    line = base_line(args, head["lookups_per_s"], "lookups/s", head["ms_per_step"], "f32",
+                     {"workload": f"Gaussian filtering (sigma 0.3 / 0.5 / 0.8 texels) of the DCT-compressed {size}^2 x "
+                                  f"{C} texture set over a 3840x2160 frame ({n} uv): FIS (Box-Muller + nearest, 1 "
+                                  "decode) and discrete 4x4 sampling vs their deterministic means", "n_queries": n})
+    line.update({"variants": res, "quality": quality,
+                 "fis_over_fis_mean_sigma0.5": head["lookups_per_s"] / res["fis_mean_sigma0.5"]["lookups_per_s"],
+                 "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
+                 "cpu_baseline": None})
+    tex.destroy()
+    return line
+
+
+# ----------------------------------------------------------------------------
 # filtering with shading
 # ----------------------------------------------------------------------------
 GGX_FLOPS = 120   # binary32 operations of one shading evaluation (see the design notes)
@@ -525,7 +574,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="grid", choices=["grid", "tex2d", "shade", "neural", "serving", "dct"])
+    ap.add_argument("--workload", default="grid", choices=["grid", "tex2d", "shade", "neural", "serving", "dct", "gauss"])
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16", "fp8_e4m3"])
     ap.add_argument("--order", default="ray", choices=["ray", "shuffled", "morton"])
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="queries in the CPU-oracle timing sample")
@@ -551,7 +600,7 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
-    run = {"grid": run_grid, "tex2d": run_tex2d, "shade": run_shade, "neural": run_neural, "dct": run_dct,
+    run = {"grid": run_grid, "tex2d": run_tex2d, "shade": run_shade, "neural": run_neural, "dct": run_dct, "gauss": run_gauss,
            "serving": run_serving}[args.workload]
     line = run(args, torch, stf, synth)
     print(json.dumps(line), flush=True)
