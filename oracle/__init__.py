@@ -93,6 +93,10 @@ def _declare(L):
     L.orc_dct_moments2d.argtypes = [vp, i32, i32, i32, vp, i64, i32, vp, vp, i32]
     L.orc_dct_moments2d.restype = i32
     L.orc_fis_tap.argtypes, L.orc_fis_tap.restype = [i32, dbl, u64, u32, i32], i32
+    L.orc_ewa_lut_value.argtypes, L.orc_ewa_lut_value.restype = [i32], C.c_float
+    L.orc_ewa_lods.argtypes, L.orc_ewa_lods.restype = [vp, i64, i32, C.c_float, vp], i32
+    L.orc_ewa_filter2d.argtypes = [vp, vp, vp, i32, i32, i32, vp, i64, C.c_float, i32, u64, vp, vp, i32]
+    L.orc_ewa_filter2d.restype = i32
     L.orc_gauss_radius.argtypes, L.orc_gauss_radius.restype = [dbl], i32
     L.orc_gauss_filter2d.argtypes = [vp, i32, i32, i32, i32, vp, i64, dbl, i32, u64, vp, vp, i32]
     L.orc_gauss_filter2d.restype = i32
@@ -320,6 +324,40 @@ def gauss_fis_positions(W: int, H: int, uv: np.ndarray, sigma: float, seed: int)
     pos = np.empty((uv.shape[0], 2), np.float64)
     lib().orc_gauss_fis_positions(W, H, _p(uv), uv.shape[0], float(sigma), seed, _p(pos))
     return pos
+
+
+# ----------------------------------------------------------------------------
+# elliptically weighted average (EWA) filtering over a MIP pyramid
+# ----------------------------------------------------------------------------
+def ewa_lut(i: int) -> float:
+    return lib().orc_ewa_lut_value(i)
+
+
+def ewa_lods(q: np.ndarray, levels: int, max_aniso: float) -> np.ndarray:
+    q = np.ascontiguousarray(q, np.float32)
+    out = np.empty(q.shape[0])
+    lib().orc_ewa_lods(_p(q), q.shape[0], levels, float(max_aniso), _p(out))
+    return out
+
+
+def ewa_filter2d(levels, fmt: int, q: np.ndarray, max_aniso: float, mode: int, seed: int = 0,
+                 want_index: bool = True, nthreads: int = 0):
+    """levels: list of (H_l, W_l, C) raw texel arrays; q: (n, 6) float32
+    (s, t, ds/dx, dt/dx, ds/dy, dt/dy).  Returns values (n, C) and, in
+    stochastic mode, indices (n, 3) = (x, y, level)."""
+    lv = [np.ascontiguousarray(a) for a in levels]
+    ptrs = (C.c_void_p * len(lv))(*[a.ctypes.data for a in lv])
+    Ws = (C.c_int * len(lv))(*[a.shape[1] for a in lv])
+    Hs = (C.c_int * len(lv))(*[a.shape[0] for a in lv])
+    Ch = lv[0].shape[2]
+    q = np.ascontiguousarray(q, np.float32)
+    n = q.shape[0]
+    out = np.empty((n, Ch))
+    idx = np.empty((n, 3), np.int32) if (want_index and mode == STOCH) else None
+    if lib().orc_ewa_filter2d(ptrs, Ws, Hs, len(lv), Ch, fmt, _p(q), n, float(max_aniso), mode, seed, _p(out),
+                              _p(idx), nthreads) != 0:
+        raise ValueError("orc_ewa_filter2d rejected its arguments")
+    return out, idx
 
 
 # ----------------------------------------------------------------------------

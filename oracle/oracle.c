@@ -1138,3 +1138,224 @@ int orc_gauss_fis_positions(int W, int H, const float* uv, int64_t n, double sig
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Elliptically weighted average filtering, deterministic and stochastic     */
+/* (section "B-Spline and Anisotropic Filters": after a stochastic choice of */
+/* MIP level from the ellipse's extent, one tap is drawn in proportion to    */
+/* the EWA weights; supplement, "Stochastic sampling of the EWA kernel",     */
+/* which follows pbrt's EWA lookup).                                         */
+/* A query is (s, t, ds/dx, dt/dx, ds/dy, dt/dy) in [0,1] texture units.     */
+/*   Axes: the longer of the two derivative vectors is the major axis; if    */
+/*   shorter * max_aniso < longer (and shorter > 0) the shorter vector is    */
+/*   scaled by longer / (shorter * max_aniso).  Binary32, each operation      */
+/*   rounded once (lengths sqrt(x*x + y*y)).  shorter == 0: bilinear on      */
+/*   level 0 (stochastic: the pinned linear draw with hash indices 2, 3).    */
+/*   Level of detail lod = max(0, (levels - 1) + log2(shorter)) in binary64; */
+/*   deterministic: lerp(lod - floor(lod), EWA(floor), EWA(floor + 1));       */
+/*   stochastic: level floor(lod) + [u0 < lod - floor(lod)] (hash index 0).  */
+/*   Levels past the last read the last level.                              */
+/*   EWA on level l (resolution W x H, binary32 as pbrt): st = (s W - 0.5,    */
+/*   t H - 0.5), d0 = dst0 (W, H), d1 = dst1 (W, H);                          */
+/*     A = (d0y^2 + d1y^2) + 1, B = -2 (d0x d0y + d1x d1y), C = (d0x^2 + d1x^2) + 1, */
+/*     invF = 1 / (A C - B^2 * 0.25), A, B, C scaled by invF,                */
+/*     det = -B^2 + 4 A C, invDet = 1/det, us = sqrt(det C), vs = sqrt(A det), */
+/*     s0 = ceil(st.x - 2 invDet us), s1 = floor(st.x + 2 invDet us), same   */
+/*     for t with vs; over t0..t1 (outer) and s0..s1 (inner): ss = s - st.x, */
+/*     tt = t - st.y, r2 = ((A (ss ss)) + ((B ss) tt)) + (C (tt tt)); taps   */
+/*     with r2 < 1 get weight LUT[min((int)(r2 * 128), 127)], LUT[i] =        */
+/*     fl32(exp(-2 i/127) - exp(-2)) (a truncated Gaussian), taps clamped.   */
+/*   Deterministic: sum w t / sum w.  Stochastic: T = u1 * sum w (hash index  */
+/*   1), the first tap in scan order whose running sum exceeds T (the last   */
+/*   tap with weight if none does); the value is that texel.                 */
+/* Values in binary64; the weights are the binary32 LUT values.              */
+/* ------------------------------------------------------------------------ */
+static float orc_ewa_lut[128];
+static int orc_ewa_lut_ready = 0;
+
+static void orc_ewa_init(void)
+{
+    if (orc_ewa_lut_ready) return;
+    for (int i = 0; i < 128; ++i) orc_ewa_lut[i] = (float)(exp(-2.0 * i / 127.0) - exp(-2.0));
+    orc_ewa_lut_ready = 1;
+}
+
+float orc_ewa_lut_value(int i)
+{
+    orc_ewa_init();
+    return (i >= 0 && i < 128) ? orc_ewa_lut[i] : NAN;
+}
+
+typedef struct orc_ewa_tex {
+    const void* const* lv;
+    const int* W;
+    const int* H;
+    int levels, C, fmt;
+} orc_ewa_tex;
+
+static double orc_ewa_texel(const orc_ewa_tex* T, int l, int x, int y, int c)
+{
+    orc_src2d s = {T->lv[l], T->W[l], T->H[l], T->C, T->fmt};
+    return orc_src_texel(&s, x, y, c);
+}
+
+/* EWA on one level: the deterministic value (per channel) and/or the drawn
+ * tap. */
+static void orc_ewa_level(const orc_ewa_tex* T, int l, float s, float t, const float d0in[2], const float d1in[2],
+                          int stochastic, float u, double* out, int* tx, int* ty)
+{
+    const int W = T->W[l], H = T->H[l];
+    float stx = s * (float)W - 0.5f, sty = t * (float)H - 0.5f;
+    float d0x = d0in[0] * (float)W, d0y = d0in[1] * (float)H;
+    float d1x = d1in[0] * (float)W, d1y = d1in[1] * (float)H;
+    float A = (d0y * d0y + d1y * d1y) + 1.0f;
+    float B = -2.0f * (d0x * d0y + d1x * d1y);
+    float Cc = (d0x * d0x + d1x * d1x) + 1.0f;
+    float invF = 1.0f / (A * Cc - (B * B) * 0.25f);
+    A *= invF;
+    B *= invF;
+    Cc *= invF;
+    float det = -(B * B) + 4.0f * A * Cc;
+    float invDet = 1.0f / det;
+    float us = sqrtf(fmaxf(det * Cc, 0.0f)), vs = sqrtf(fmaxf(A * det, 0.0f));
+    int s0 = (int)ceilf(stx - 2.0f * invDet * us), s1 = (int)floorf(stx + 2.0f * invDet * us);
+    int t0 = (int)ceilf(sty - 2.0f * invDet * vs), t1 = (int)floorf(sty + 2.0f * invDet * vs);
+    float total = 0.0f;
+    double acc[16] = {0};
+    double wsum = 0.0;
+    int lastx = s0, lasty = t0;
+    for (int it = t0; it <= t1; ++it) {
+        float tt = (float)it - sty;
+        for (int is = s0; is <= s1; ++is) {
+            float ss = (float)is - stx;
+            float r2 = (A * (ss * ss) + (B * ss) * tt) + Cc * (tt * tt);
+            if (!(r2 < 1.0f)) continue;
+            int idx = (int)(r2 * 128.0f);
+            if (idx > 127) idx = 127;
+            float w = orc_ewa_lut[idx];
+            if (!(w > 0.0f)) continue;
+            total += w;
+            lastx = is;
+            lasty = it;
+            if (!stochastic) {
+                wsum += (double)w;
+                for (int c = 0; c < T->C; ++c) acc[c] += (double)w * orc_ewa_texel(T, l, is, it, c);
+            }
+        }
+    }
+    if (!stochastic) {
+        for (int c = 0; c < T->C; ++c) out[c] = acc[c] / wsum;
+        return;
+    }
+    float Tq = u * total, run = 0.0f;
+    *tx = lastx;
+    *ty = lasty;
+    for (int it = t0; it <= t1; ++it) {
+        float tt = (float)it - sty;
+        for (int is = s0; is <= s1; ++is) {
+            float ss = (float)is - stx;
+            float r2 = (A * (ss * ss) + (B * ss) * tt) + Cc * (tt * tt);
+            if (!(r2 < 1.0f)) continue;
+            int idx = (int)(r2 * 128.0f);
+            if (idx > 127) idx = 127;
+            float w = orc_ewa_lut[idx];
+            if (!(w > 0.0f)) continue;
+            run += w;
+            if (Tq < run) { *tx = is; *ty = it; return; }
+        }
+    }
+}
+
+/* Level of detail and the two axes (binary32, then log2 in binary64). */
+static double orc_ewa_axes(const float q[6], int levels, float max_aniso, float d0[2], float d1[2], float* shorter)
+{
+    d0[0] = q[2]; d0[1] = q[3];
+    d1[0] = q[4]; d1[1] = q[5];
+    if (d0[0] * d0[0] + d0[1] * d0[1] < d1[0] * d1[0] + d1[1] * d1[1]) {
+        float a = d0[0], b = d0[1];
+        d0[0] = d1[0]; d0[1] = d1[1];
+        d1[0] = a; d1[1] = b;
+    }
+    float longer = sqrtf(d0[0] * d0[0] + d0[1] * d0[1]);
+    float sh = sqrtf(d1[0] * d1[0] + d1[1] * d1[1]);
+    if (sh * max_aniso < longer && sh > 0.0f) {
+        float scale = longer / (sh * max_aniso);
+        d1[0] *= scale;
+        d1[1] *= scale;
+        sh *= scale;
+    }
+    *shorter = sh;
+    if (!(sh > 0.0f)) return 0.0;
+    double lod = (double)(levels - 1) + log2((double)sh);
+    return lod < 0.0 ? 0.0 : lod;
+}
+
+/* The binary64 level of detail of each query (for boundary checks). */
+int orc_ewa_lods(const float* q, int64_t n, int levels, float max_aniso, double* lod)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        float d0[2], d1[2], sh;
+        lod[k] = orc_ewa_axes(q + 6 * k, levels, max_aniso, d0, d1, &sh);
+    }
+    return 0;
+}
+
+int orc_ewa_filter2d(const void* const* level_texels, const int* W, const int* H, int levels, int C, int fmt,
+                     const float* q, int64_t n, float max_aniso, int mode, uint64_t seed, double* out, int32_t* idx,
+                     int nthreads)
+{
+    if (!level_texels || levels < 1 || C < 1 || C > 16 || n < 0 || !(max_aniso >= 1.0f) ||
+        (mode != ORC_DET && mode != ORC_STOCH))
+        return -1;
+    orc_ewa_init();
+    orc_ewa_tex T = {level_texels, W, H, levels, C, fmt};
+    int nt = orc_threads(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(dynamic, 256) num_threads(nt)
+    for (int64_t k = 0; k < n; ++k) {
+        const float* qk = q + 6 * k;
+        double* o = out + k * C;
+        int32_t* ix = idx ? idx + 3 * k : NULL;
+        int ok = 1;
+        for (int j = 0; j < 6; ++j) ok &= isfinite(qk[j]) && fabsf(qk[j]) < 65536.0f;
+        if (!ok) { orc_nan_out(o, C, ix, 3); continue; }
+        float d0[2], d1[2], sh;
+        double lod = orc_ewa_axes(qk, levels, max_aniso, d0, d1, &sh);
+        uint32_t qid = (uint32_t)k;
+        if (!(sh > 0.0f)) {   /* degenerate footprint: bilinear on level 0 */
+            orc_src2d s0 = {level_texels[0], W[0], H[0], C, fmt};
+            float uv[2] = {qk[0], qk[1]};
+            if (mode == ORC_DET) {
+                orc_query2d(&s0, uv, ORC_LINEAR, ORC_DET, seed, qid, o, NULL);
+            } else {
+                float x, y, tx, ty;
+                int cx, cy;
+                orc_raster2d(uv, W[0], H[0], &x, &y);
+                if (!orc_cell(x, &cx, &tx) || !orc_cell(y, &cy, &ty)) { orc_nan_out(o, C, ix, 3); continue; }
+                int sx = orc_clampi(cx + orc_select(ORC_LINEAR, tx, orc_uniform(seed, qid, 2)), 0, W[0] - 1);
+                int sy = orc_clampi(cy + orc_select(ORC_LINEAR, ty, orc_uniform(seed, qid, 3)), 0, H[0] - 1);
+                for (int c = 0; c < C; ++c) o[c] = orc_src_texel(&s0, sx, sy, c);
+                if (ix) { ix[0] = sx; ix[1] = sy; ix[2] = 0; }
+            }
+            continue;
+        }
+        int il = (int)floor(lod);
+        double frac = lod - (double)il;
+        if (mode == ORC_DET) {
+            double a[16], b[16];
+            int l0 = il < levels ? il : levels - 1, l1 = il + 1 < levels ? il + 1 : levels - 1;
+            orc_ewa_level(&T, l0, qk[0], qk[1], d0, d1, 0, 0.0f, a, NULL, NULL);
+            orc_ewa_level(&T, l1, qk[0], qk[1], d0, d1, 0, 0.0f, b, NULL, NULL);
+            for (int c = 0; c < C; ++c) o[c] = (1.0 - frac) * a[c] + frac * b[c];
+        } else {
+            int l = il + ((double)orc_uniform(seed, qid, 0) < frac ? 1 : 0);
+            if (l > levels - 1) l = levels - 1;
+            int tx, ty;
+            orc_ewa_level(&T, l, qk[0], qk[1], d0, d1, 1, orc_uniform(seed, qid, 1), NULL, &tx, &ty);
+            int sx = orc_clampi(tx, 0, W[l] - 1), sy = orc_clampi(ty, 0, H[l] - 1);
+            for (int c = 0; c < C; ++c) o[c] = orc_ewa_texel(&T, l, sx, sy, c);
+            if (ix) { ix[0] = sx; ix[1] = sy; ix[2] = l; }
+        }
+    }
+    return 0;
+}

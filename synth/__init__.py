@@ -136,6 +136,55 @@ def screen_uv_queries(width: int = 3840, height: int = 2160, seed: int = 53) -> 
     return np.ascontiguousarray(uv.reshape(-1, 2).astype(np.float32))
 
 
+def mip_levels(tex: np.ndarray, min_size: int = 1) -> list:
+    """MIP pyramid of an (H, W, C) texture: each level the 2x2 box average of
+    the previous one in binary64, stored in the input's dtype (round to
+    nearest for integer types), down to min_size texels on the shorter side."""
+    levels = [np.ascontiguousarray(tex)]
+    cur = tex.astype(np.float64)
+    while min(cur.shape[0], cur.shape[1]) // 2 >= min_size and min(cur.shape[0], cur.shape[1]) >= 2:
+        cur = 0.25 * (cur[0::2, 0::2] + cur[1::2, 0::2] + cur[0::2, 1::2] + cur[1::2, 1::2])
+        if np.issubdtype(tex.dtype, np.integer):
+            levels.append(np.ascontiguousarray(np.rint(cur).astype(tex.dtype)))
+        else:
+            levels.append(np.ascontiguousarray(cur.astype(tex.dtype)))
+    return levels
+
+
+def screen_ewa_queries(width: int = 3840, height: int = 2160, seed: int = 53, tile: float = 2.0) -> np.ndarray:
+    """(width * height, 6) float32 EWA queries of the camera and ground plane
+    of screen_uv_queries, the texture tiled every `tile` units (2 by default:
+    mostly minified, strongly anisotropic towards the horizon): (s, t) and
+    the texture-space derivatives along the
+    pixel x and y axes (forward differences of the untiled coordinates, the
+    last column / row repeated); sky pixels get a random (s, t) and a
+    one-texel footprint of a 4096^2 texture."""
+    rng = np.random.default_rng(seed)
+    jx, jy = rng.random(2)
+    px = (np.arange(width) + jx) / width * 2.0 - 1.0
+    py = 1.0 - (np.arange(height) + jy) / height * 2.0
+    tan_h = np.tan(np.radians(30.0))
+    X, Y = np.meshgrid(px * tan_h, py * tan_h * height / width)
+    pitch = np.radians(25.0)
+    f = np.array([0.0, np.cos(pitch), -np.sin(pitch)])
+    u = np.array([0.0, np.sin(pitch), np.cos(pitch)])
+    d = f[None, None, :] + X[:, :, None] * np.array([1.0, 0.0, 0.0]) + Y[:, :, None] * u[None, None, :]
+    hit = d[:, :, 2] < -1e-6
+    t = np.where(hit, 2.0 / np.maximum(-d[:, :, 2], 1e-6), 0.0)
+    su = d[:, :, 0] * t / tile
+    sv = d[:, :, 1] * t / tile
+    dsx = np.diff(su, axis=1, append=su[:, -1:] + (su[:, -1:] - su[:, -2:-1]))
+    dtx = np.diff(sv, axis=1, append=sv[:, -1:] + (sv[:, -1:] - sv[:, -2:-1]))
+    dsy = np.diff(su, axis=0, append=su[-1:, :] + (su[-1:, :] - su[-2:-1, :]))
+    dty = np.diff(sv, axis=0, append=sv[-1:, :] + (sv[-1:, :] - sv[-2:-1, :]))
+    q = np.stack([su - np.floor(su), sv - np.floor(sv), dsx, dtx, dsy, dty], axis=-1)
+    sky = ~hit | ~np.all(np.isfinite(q), axis=-1) | (np.abs(q[..., 2:]) > 1.0).any(axis=-1)
+    m = int(sky.sum())
+    q[sky, 0:2] = rng.random((m, 2))
+    q[sky, 2:6] = np.array([1.0 / 4096, 0.0, 0.0, 1.0 / 4096])
+    return np.ascontiguousarray(q.reshape(-1, 6).astype(np.float32))
+
+
 # ----------------------------------------------------------------------------
 # fBm value noise and the sparse grid built from it
 # ----------------------------------------------------------------------------
