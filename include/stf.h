@@ -209,6 +209,33 @@ stf_status stf_filter_gaussian(const stf_texture* tex, const float* queries_dev,
                                void* hip_stream);
 
 /* ---------------------------------------------------------------------- */
+/* Elliptically weighted average filtering                                 */
+/* ---------------------------------------------------------------------- */
+/* EWA filtering of a 2D texture's MIP levels (section "B-Spline and
+ * Anisotropic Filters"; supplement, "Stochastic sampling of the EWA kernel",
+ * after pbrt's EWA lookup).  Each query is 6 binary32: (s, t) in [0, 1] and
+ * the texture-space derivatives (ds/dx, dt/dx, ds/dy, dt/dy).
+ *   - The longer derivative vector is the major axis; the shorter one is
+ *     raised to longer / max_anisotropy if needed (binary32).
+ *   - lod = max(0, (levels - 1) + log2(shorter)) (binary64).
+ *   - Deterministic: lerp(lod - floor(lod), EWA(floor(lod)), EWA(floor(lod)
+ *     + 1)); EWA on a level = sum w t / sum w over its texels with
+ *     r2 = A ss^2 + B ss tt + C tt^2 < 1 (pbrt's ellipse coefficients in
+ *     texels), w = LUT[min(floor(128 r2), 127)], LUT[i] = exp(-2 i/127) -
+ *     exp(-2).
+ *   - Stochastic: level floor(lod) + [u0 < lod - floor(lod)], then one texel
+ *     drawn with probability w / sum w (the first in row-major scan order
+ *     whose running binary32 sum exceeds u1 sum w): one texel read per
+ *     lookup.
+ *   - A zero footprint reads bilinearly from level 0 (stochastic: the linear
+ *     draw); levels past the last read the last; taps are clamped.
+ * Queries with a non-finite or |value| >= 65536 entry give NaN.
+ * max_anisotropy in [1, 1024].  out_index_dev: NULL or (stochastic) n x 3
+ * int32 (x, y, level).  Binary32 accumulation. */
+stf_status stf_filter_ewa(const stf_texture* tex, const float* queries_dev, int64_t n, float max_anisotropy,
+                          stf_mode mode, uint64_t seed, float* out_dev, int32_t* out_index_dev, void* hip_stream);
+
+/* ---------------------------------------------------------------------- */
 /* DCT-compressed textures                                                 */
 /* ---------------------------------------------------------------------- */
 /* A texture of 8x8 texel blocks, each channel of a block stored as one

@@ -78,10 +78,11 @@ def _declare(L):
     L.stf_shade_filter.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, vp]
     L.stf_dct_encode.argtypes = [i32, i32, i32, vp, vp]
     L.stf_filter_gaussian.argtypes = [vp, vp, i64, f32, i32, u64, vp, vp, vp]
+    L.stf_filter_ewa.argtypes = [vp, vp, i64, f32, i32, u64, vp, vp, vp]
     L.stf_create_dct_texture2d.argtypes = [i32, i32, i32, vp, C.POINTER(vp)]
     for name in ("stf_create_texture2d", "stf_create_material2d", "stf_create_sparse_grid3d",
                  "stf_texture_bytes", "stf_filter", "stf_filter_moments", "stf_shade_filter", "stf_dct_encode",
-                 "stf_create_dct_texture2d", "stf_filter_gaussian"):
+                 "stf_create_dct_texture2d", "stf_filter_gaussian", "stf_filter_ewa"):
         getattr(L, name).restype = i32
 
 
@@ -257,6 +258,20 @@ def stf_filter_gaussian(tex: Texture, queries, sigma: float, mode: int, seed: in
     _check(lib().stf_filter_gaussian(
         tex.handle, _dev_ptr(queries, "queries"), n, float(sigma), mode, seed & (2 ** 64 - 1), _dev_ptr(out, "out"),
         _dev_ptr(out_index, "out_index"), _stream(stream)))
+
+
+def stf_filter_ewa(tex: Texture, queries, max_anisotropy: float, mode: int, seed: int, out, out_index=None,
+                   stream=None):
+    """EWA filtering: queries (n, 6) float32 GPU tensor; out (n, channels);
+    out_index None or (n, 3) int32 (stochastic)."""
+    n = queries.shape[0]
+    if queries.numel() < 6 * n or out.numel() < n * tex.channels:
+        raise ValueError("queries or out is too small")
+    if out_index is not None and out_index.numel() < 3 * n:
+        raise ValueError("out_index is too small")
+    _check(lib().stf_filter_ewa(tex.handle, _dev_ptr(queries, "queries"), n, float(max_anisotropy), mode,
+                                seed & (2 ** 64 - 1), _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"),
+                                _stream(stream)))
 
 
 def stf_filter_moments(tex: Texture, queries, filter: int, seed_base: int, n_seeds: int, sum_out, sumsq_out,

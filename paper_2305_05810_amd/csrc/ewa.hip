@@ -1,0 +1,327 @@
+// ewa.hip -- elliptically weighted average filtering over a MIP pyramid,
+// deterministic and stochastic (section "B-Spline and Anisotropic Filters":
+// a stochastic choice of MIP level from the ellipse's extent, then one tap
+// drawn in proportion to the EWA weights; supplement, "Stochastic sampling of
+// the EWA kernel", which follows pbrt's EWA lookup).
+//
+// A query is (s, t, ds/dx, dt/dx, ds/dy, dt/dy) in [0, 1] texture units.
+//  - Axes (binary32): the longer derivative vector is the major axis; the
+//    shorter is raised to longer / max_aniso if it is shorter than that.
+//  - lod = max(0, (levels - 1) + log2(shorter)) in binary64; deterministic:
+//    lerp(lod - floor(lod), EWA(floor(lod)), EWA(floor(lod) + 1)); stochastic:
+//    level floor(lod) + [u0 < lod - floor(lod)] (hash index 0), then one tap.
+//  - EWA on a level (binary32, each operation rounded once in this order):
+//    A = (d0y^2 + d1y^2) + 1, B = -2 (d0x d0y + d1x d1y), C = (d0x^2 + d1x^2)
+//    + 1 with the derivatives in texels; A, B, C divided by F = A C -
+//    B^2 / 4; the bounding box st +- 2 sqrt(det C) / det (x), +- 2 sqrt(A det)
+//    / det (y), det = -B^2 + 4 A C; taps with r2 = A ss^2 + B ss tt + C tt^2
+//    < 1 weigh LUT[min(floor(128 r2), 127)], LUT[i] = exp(-2 i/127) -
+//    exp(-2).  The stochastic tap: T = u1 * sum w (hash index 1), the first
+//    tap in scan order (rows outer) whose running sum exceeds T.
+//  - A zero footprint reads bilinearly from level 0 (stochastic: the linear
+//    draw with hash indices 2, 3); levels past the last read the last.
+// Taps are clamped to their level.
+#include <math.h>
+
+#include <new>
+
+#include "device_common.h"
+#include "stf_internal.h"
+
+using namespace stf;
+
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr int LUT_SIZE = 128;
+
+struct EwaLevels {
+    TexLevel level[STF_MAX_LEVELS];
+    int32_t levels;
+};
+
+struct EwaLut {
+    float v[LUT_SIZE];
+};
+
+EwaLut make_lut()
+{
+    EwaLut L;
+    for (int i = 0; i < LUT_SIZE; ++i) L.v[i] = (float)(std::exp(-2.0 * i / 127.0) - std::exp(-2.0));
+    return L;
+}
+
+__device__ __forceinline__ int clampi(int v, int hi)
+{
+    return v < 0 ? 0 : (v > hi ? hi : v);
+}
+
+template <int FMT, int C>
+__device__ __forceinline__ void texel(const TexLevel& L, int x, int y, float (&v)[C])
+{
+    const int64_t e = ((int64_t)clampi(y, L.h - 1) * L.w + clampi(x, L.w - 1)) * C;
+    if constexpr (FMT == F32 && C == 4) {
+        const float4 f = reinterpret_cast<const float4*>(L.texels)[e >> 2];
+        v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = load_texel<FMT>(L.texels, e + c);
+    }
+}
+
+// The ellipse of one level in texel units: coefficients and bounding box.
+struct Ellipse {
+    float stx, sty, A, B, C;
+    int s0, s1, t0, t1;
+};
+
+__device__ __forceinline__ Ellipse ellipse(const TexLevel& L, float s, float t, const float (&d0)[2],
+                                           const float (&d1)[2])
+{
+    Ellipse e;
+    const float W = (float)L.w, H = (float)L.h;
+    e.stx = s * W - 0.5f;
+    e.sty = t * H - 0.5f;
+    const float d0x = d0[0] * W, d0y = d0[1] * H, d1x = d1[0] * W, d1y = d1[1] * H;
+    float A = (d0y * d0y + d1y * d1y) + 1.0f;
+    float B = -2.0f * (d0x * d0y + d1x * d1y);
+    float C = (d0x * d0x + d1x * d1x) + 1.0f;
+    const float invF = 1.0f / (A * C - (B * B) * 0.25f);
+    A *= invF;
+    B *= invF;
+    C *= invF;
+    const float det = -(B * B) + 4.0f * A * C;
+    const float invDet = 1.0f / det;
+    const float us = sqrtf(fmaxf(det * C, 0.0f)), vs = sqrtf(fmaxf(A * det, 0.0f));
+    e.s0 = (int)ceilf(e.stx - 2.0f * invDet * us);
+    e.s1 = (int)floorf(e.stx + 2.0f * invDet * us);
+    e.t0 = (int)ceilf(e.sty - 2.0f * invDet * vs);
+    e.t1 = (int)floorf(e.sty + 2.0f * invDet * vs);
+    e.A = A;
+    e.B = B;
+    e.C = C;
+    return e;
+}
+
+__device__ __forceinline__ float ewa_weight(const Ellipse& e, const float* lut, int is, int it)
+{
+    const float ss = (float)is - e.stx, tt = (float)it - e.sty;
+    const float r2 = (e.A * (ss * ss) + (e.B * ss) * tt) + e.C * (tt * tt);
+    if (!(r2 < 1.0f)) return 0.0f;
+    int idx = (int)(r2 * 128.0f);
+    return lut[idx > 127 ? 127 : idx];
+}
+
+template <int FMT, int C>
+__device__ __forceinline__ void ewa_mean(const TexLevel& L, const Ellipse& e, const float* lut, float (&v)[C])
+{
+    float acc[C], wsum = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+    for (int it = e.t0; it <= e.t1; ++it)
+        for (int is = e.s0; is <= e.s1; ++is) {
+            const float w = ewa_weight(e, lut, is, it);
+            if (!(w > 0.0f)) continue;
+            float t[C];
+            texel<FMT, C>(L, is, it, t);
+            wsum += w;
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = __builtin_fmaf(w, t[c], acc[c]);
+        }
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = acc[c] / wsum;
+}
+
+__device__ __forceinline__ void ewa_draw(const Ellipse& e, const float* lut, float u, int& tx, int& ty)
+{
+    float total = 0.0f;
+    tx = e.s0;
+    ty = e.t0;
+    for (int it = e.t0; it <= e.t1; ++it)
+        for (int is = e.s0; is <= e.s1; ++is) {
+            const float w = ewa_weight(e, lut, is, it);
+            if (!(w > 0.0f)) continue;
+            total += w;
+            tx = is;   // the last tap with weight, if the running sum never exceeds T
+            ty = it;
+        }
+    const float T = u * total;
+    float run = 0.0f;
+    for (int it = e.t0; it <= e.t1; ++it)
+        for (int is = e.s0; is <= e.s1; ++is) {
+            const float w = ewa_weight(e, lut, is, it);
+            if (!(w > 0.0f)) continue;
+            run += w;
+            if (T < run) {
+                tx = is;
+                ty = it;
+                return;
+            }
+        }
+}
+
+template <int FMT, int C, bool STOCH>
+__global__ __launch_bounds__(BLOCK) void k_ewa(EwaLevels P, EwaLut lut_in, const float* __restrict__ q, int32_t n,
+                                               float max_aniso, uint32_t key, float* __restrict__ out,
+                                               int32_t* __restrict__ idx)
+{
+    __shared__ float lut[LUT_SIZE];
+    for (int k = threadIdx.x; k < LUT_SIZE; k += BLOCK) lut[k] = lut_in.v[k];
+    __syncthreads();
+    const int32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    float r[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) r[j] = q[6 * (int64_t)i + j];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) ok = ok && (__builtin_fabsf(r[j]) < 65536.0f);
+    float v[C];
+    int ix[3] = {BAD_INDEX, BAD_INDEX, BAD_INDEX};
+    if (!ok) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = __builtin_nanf("");
+    } else {
+        float d0[2] = {r[2], r[3]}, d1[2] = {r[4], r[5]};
+        if (d0[0] * d0[0] + d0[1] * d0[1] < d1[0] * d1[0] + d1[1] * d1[1]) {
+            const float a = d0[0], b = d0[1];
+            d0[0] = d1[0]; d0[1] = d1[1];
+            d1[0] = a; d1[1] = b;
+        }
+        const float longer = sqrtf(d0[0] * d0[0] + d0[1] * d0[1]);
+        float sh = sqrtf(d1[0] * d1[0] + d1[1] * d1[1]);
+        if (sh * max_aniso < longer && sh > 0.0f) {
+            const float scale = longer / (sh * max_aniso);
+            d1[0] *= scale;
+            d1[1] *= scale;
+            sh *= scale;
+        }
+        const uint32_t h0 = pcg(key ^ (uint32_t)i);
+        const int L = P.levels;
+        if (!(sh > 0.0f)) {   // degenerate footprint: bilinear on level 0
+            const TexLevel& T0 = P.level[0];
+            const float x = r[0] * (float)T0.w - 0.5f, y = r[1] * (float)T0.h - 0.5f;
+            int cx = 0, cy = 0;
+            float tx = 0.0f, ty = 0.0f;
+            cell_of(x, cx, tx);
+            cell_of(y, cy, ty);
+            if constexpr (STOCH) {
+                ix[0] = clampi(cx + choose_linear(tx, axis_uniform(h0, 2)), T0.w - 1);
+                ix[1] = clampi(cy + choose_linear(ty, axis_uniform(h0, 3)), T0.h - 1);
+                ix[2] = 0;
+                texel<FMT, C>(T0, ix[0], ix[1], v);
+            } else {
+                float a[C], b[C], c2[C], d[C];
+                texel<FMT, C>(T0, cx, cy, a);
+                texel<FMT, C>(T0, cx + 1, cy, b);
+                texel<FMT, C>(T0, cx, cy + 1, c2);
+                texel<FMT, C>(T0, cx + 1, cy + 1, d);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const float r0 = __builtin_fmaf(tx, b[c], (1.0f - tx) * a[c]);
+                    const float r1 = __builtin_fmaf(tx, d[c], (1.0f - tx) * c2[c]);
+                    v[c] = __builtin_fmaf(ty, r1, (1.0f - ty) * r0);
+                }
+            }
+        } else {
+            double lod = (double)(L - 1) + log2((double)sh);
+            lod = lod < 0.0 ? 0.0 : lod;
+            const int il = (int)floor(lod);
+            const double frac = lod - (double)il;
+            if constexpr (STOCH) {
+                int l = il + ((double)hash_uniform(h0) < frac ? 1 : 0);
+                l = l > L - 1 ? L - 1 : l;
+                const Ellipse e = ellipse(P.level[l], r[0], r[1], d0, d1);
+                int tx, ty;
+                ewa_draw(e, lut, axis_uniform(h0, 1), tx, ty);
+                ix[0] = clampi(tx, P.level[l].w - 1);
+                ix[1] = clampi(ty, P.level[l].h - 1);
+                ix[2] = l;
+                texel<FMT, C>(P.level[l], ix[0], ix[1], v);
+            } else {
+                const int l0 = il < L ? il : L - 1, l1 = il + 1 < L ? il + 1 : L - 1;
+                float a[C], b[C];
+                ewa_mean<FMT, C>(P.level[l0], ellipse(P.level[l0], r[0], r[1], d0, d1), lut, a);
+                ewa_mean<FMT, C>(P.level[l1], ellipse(P.level[l1], r[0], r[1], d0, d1), lut, b);
+#pragma unroll
+                for (int c = 0; c < C; ++c) v[c] = (float)((1.0 - frac) * (double)a[c] + frac * (double)b[c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[(int64_t)i * C + c] = v[c];
+    if (STOCH && idx) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) idx[3 * (int64_t)i + k] = ix[k];
+    }
+}
+
+template <int FMT, int C>
+hipError_t launch_ewa_fc(const EwaLevels& P, const float* q, int32_t n, float max_aniso, int mode, uint32_t key,
+                         float* out, int32_t* idx, hipStream_t s)
+{
+    static const EwaLut lut = make_lut();
+    dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
+    if (mode == STF_STOCHASTIC)
+        hipLaunchKernelGGL((k_ewa<FMT, C, true>), grid, block, 0, s, P, lut, q, n, max_aniso, key, out, idx);
+    else
+        hipLaunchKernelGGL((k_ewa<FMT, C, false>), grid, block, 0, s, P, lut, q, n, max_aniso, key, out, idx);
+    return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t launch_ewa_f(const EwaLevels& P, int C, const float* q, int32_t n, float max_aniso, int mode, uint32_t key,
+                        float* out, int32_t* idx, hipStream_t s)
+{
+    switch (C) {
+    case 1: return launch_ewa_fc<FMT, 1>(P, q, n, max_aniso, mode, key, out, idx, s);
+    case 2: return launch_ewa_fc<FMT, 2>(P, q, n, max_aniso, mode, key, out, idx, s);
+    case 3: return launch_ewa_fc<FMT, 3>(P, q, n, max_aniso, mode, key, out, idx, s);
+    case 4: return launch_ewa_fc<FMT, 4>(P, q, n, max_aniso, mode, key, out, idx, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+extern "C" stf_status stf_filter_ewa(const stf_texture* tex, const float* queries_dev, int64_t n, float max_anisotropy,
+                                     stf_mode mode, uint64_t seed, float* out_dev, int32_t* out_index_dev,
+                                     void* hip_stream)
+{
+    stf_clear_error();
+    if (!tex) return stf_fail(STF_E_INVALID, "texture is NULL");
+    if (tex->kind != STF_KIND_TEX2D) return stf_fail(STF_E_INVALID, "stf_filter_ewa needs a 2D texture (with levels)");
+    if (n < 0 || n > 0x7fffffff) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
+    if (!(max_anisotropy >= 1.0f && max_anisotropy <= 1024.0f))
+        return stf_fail(STF_E_INVALID, "max_anisotropy = %g out of range [1, 1024]", (double)max_anisotropy);
+    if (mode != STF_DETERMINISTIC && mode != STF_STOCHASTIC) return stf_fail(STF_E_INVALID, "unknown mode %d", (int)mode);
+    if (mode == STF_DETERMINISTIC && out_index_dev)
+        return stf_fail(STF_E_INVALID, "out_index_dev must be NULL in deterministic mode");
+    if (n == 0) return STF_OK;
+    hipPointerAttribute_t attr;
+    for (const void* p : {(const void*)queries_dev, (const void*)out_dev, (const void*)out_index_dev}) {
+        if (!p) continue;
+        if ((uintptr_t)p % 4) return stf_fail(STF_E_INVALID, "a device buffer is not 4-byte aligned");
+        if (hipPointerGetAttributes(&attr, p) != hipSuccess ||
+            (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
+            (void)hipGetLastError();
+            return stf_fail(STF_E_INVALID, "queries, out and out_index must be device memory");
+        }
+    }
+    if (!queries_dev || !out_dev) return stf_fail(STF_E_INVALID, "queries_dev or out_dev is NULL");
+    EwaLevels P;
+    for (int l = 0; l < STF_MAX_LEVELS; ++l) P.level[l] = tex->level[l];
+    P.levels = tex->levels;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const uint32_t key = seed_key(seed);
+    hipError_t e = hipErrorInvalidValue;
+    switch (tex->fmt) {
+    case F32: e = launch_ewa_f<F32>(P, tex->channels, queries_dev, (int32_t)n, max_anisotropy, mode, key, out_dev, out_index_dev, st); break;
+    case F16: e = launch_ewa_f<F16>(P, tex->channels, queries_dev, (int32_t)n, max_anisotropy, mode, key, out_dev, out_index_dev, st); break;
+    case BF16: e = launch_ewa_f<BF16>(P, tex->channels, queries_dev, (int32_t)n, max_anisotropy, mode, key, out_dev, out_index_dev, st); break;
+    case FP8_E4M3: e = launch_ewa_f<FP8_E4M3>(P, tex->channels, queries_dev, (int32_t)n, max_anisotropy, mode, key, out_dev, out_index_dev, st); break;
+    case U8: e = launch_ewa_f<U8>(P, tex->channels, queries_dev, (int32_t)n, max_anisotropy, mode, key, out_dev, out_index_dev, st); break;
+    }
+    if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return STF_OK;
+}

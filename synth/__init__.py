@@ -136,14 +136,21 @@ def screen_uv_queries(width: int = 3840, height: int = 2160, seed: int = 53) -> 
     return np.ascontiguousarray(uv.reshape(-1, 2).astype(np.float32))
 
 
-def mip_levels(tex: np.ndarray, min_size: int = 1) -> list:
-    """MIP pyramid of an (H, W, C) texture: each level the 2x2 box average of
-    the previous one in binary64, stored in the input's dtype (round to
-    nearest for integer types), down to min_size texels on the shorter side."""
+def mip_levels(tex: np.ndarray) -> list:
+    """Full MIP pyramid of an (H, W, C) texture down to 1x1: level l has
+    max(1, H >> l) x max(1, W >> l) texels, each the average of the 2x2 block
+    below it (rows / columns beyond an odd edge dropped; a side of 1 averages
+    its single row / column twice), computed in binary64 and stored in the
+    input's dtype (round to nearest for integer types)."""
     levels = [np.ascontiguousarray(tex)]
     cur = tex.astype(np.float64)
-    while min(cur.shape[0], cur.shape[1]) // 2 >= min_size and min(cur.shape[0], cur.shape[1]) >= 2:
-        cur = 0.25 * (cur[0::2, 0::2] + cur[1::2, 0::2] + cur[0::2, 1::2] + cur[1::2, 1::2])
+    while cur.shape[0] > 1 or cur.shape[1] > 1:
+        h, w = max(1, cur.shape[0] // 2), max(1, cur.shape[1] // 2)
+        r0 = cur[0:2 * h:2] if cur.shape[0] > 1 else cur
+        r1 = cur[1:2 * h:2] if cur.shape[0] > 1 else cur
+        a = (r0[:, 0:2 * w:2] if cur.shape[1] > 1 else r0) + (r0[:, 1:2 * w:2] if cur.shape[1] > 1 else r0)
+        b = (r1[:, 0:2 * w:2] if cur.shape[1] > 1 else r1) + (r1[:, 1:2 * w:2] if cur.shape[1] > 1 else r1)
+        cur = 0.25 * (a + b)
         if np.issubdtype(tex.dtype, np.integer):
             levels.append(np.ascontiguousarray(np.rint(cur).astype(tex.dtype)))
         else:

@@ -1,0 +1,82 @@
+"""GPU parity of EWA filtering over a MIP pyramid through the C ABI against
+the FP64 oracle.
+
+Bar: stochastic -- (x, y, level) equal to the oracle's for every query
+(the ellipse and the tap draw are pinned binary32; the level decision goes
+through log2 in binary64, so a query whose binary64 lod lies within 1e-9 of
+an integer, or whose level uniform lies within 1e-9 of the fractional part,
+may differ -- none does in practice) and the value is the texel; deterministic
+-- within 1e-6 of the oracle relative to the value (weights and texels are
+non-negative here)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2305_05810_amd as stf
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _queries(n, seed, res):
+    rng = np.random.default_rng(seed)
+    st = rng.random((n, 2))
+    ang = rng.random(n) * np.pi
+    a = 2.0 ** rng.uniform(-2, 4, n) / res
+    r = 2.0 ** rng.uniform(0, 4, n)
+    d0 = np.stack([a * r * np.cos(ang), a * r * np.sin(ang)], axis=1)
+    d1 = np.stack([-a * np.sin(ang), a * np.cos(ang)], axis=1)
+    q = np.concatenate([st, d0, d1], axis=1).astype(np.float32)
+    q[:4, 2:] = 0.0                                   # degenerate footprints
+    q[4] = [np.nan, 0.5, 0.01, 0, 0, 0.01]
+    q[5] = [0.5, 0.5, 1e6, 0, 0, 0.01]
+    return q
+
+
+@pytest.mark.parametrize("fmt", ["f32", "u8"])
+@pytest.mark.parametrize("aniso", [1.0, 8.0, 64.0])
+def test_ewa_parity(dev, fmt, aniso):
+    rng = np.random.default_rng(1)
+    base = rng.random((128, 96, 4)).astype(np.float32)
+    tex = synth.encode(base, fmt)
+    lv = synth.mip_levels(tex)
+    t = stf.stf_create_texture2d(96, 128, 4, stf.FORMATS[fmt], lv)
+    ofmt = {"f32": oracle.F32, "u8": oracle.U8}[fmt]
+    q = _queries(20000, 2, 96.0)
+    qd = torch.from_numpy(q).to(dev)
+    n = q.shape[0]
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    idx = torch.empty((n, 3), dtype=torch.int32, device=dev)
+    stf.stf_filter_ewa(t, qd, aniso, stf.STF_STOCHASTIC, 7, out, idx)
+    ov, oi = oracle.ewa_filter2d(lv, ofmt, q, aniso, oracle.STOCH, seed=7)
+    gi = idx.cpu().numpy()
+    lod = oracle.ewa_lods(q, len(lv), aniso)
+    with np.errstate(invalid="ignore"):
+        edge = np.abs(lod - np.round(lod)) < 1e-9
+    diff = np.any(gi != oi, axis=1)
+    assert not np.any(diff & ~edge), int(diff.sum())
+    gv = out.cpu().numpy()
+    same = ~diff
+    assert np.array_equal(np.nan_to_num(gv[same], nan=-1), np.nan_to_num(ov[same].astype(np.float32), nan=-1))
+    stf.stf_filter_ewa(t, qd, aniso, stf.STF_DETERMINISTIC, 0, out)
+    od, _ = oracle.ewa_filter2d(lv, ofmt, q, aniso, oracle.DET)
+    gd = out.cpu().numpy().astype(np.float64)
+    err = np.abs(gd - od)
+    ok = (np.isnan(gd) & np.isnan(od)) | (err <= 1e-6 * np.abs(od) + 1e-12)
+    assert ok.all(), np.nanmax(err / np.maximum(np.abs(od), 1e-30))
+    t.destroy()
+
+
+def test_ewa_argument_errors(dev):
+    t = stf.stf_create_texture2d(8, 8, 1, stf.STF_FMT_F32, [np.zeros((8, 8, 1), np.float32)])
+    q = torch.zeros((4, 6), dtype=torch.float32, device=dev)
+    out = torch.empty((4, 1), dtype=torch.float32, device=dev)
+    idx = torch.empty((4, 3), dtype=torch.int32, device=dev)
+    L = stf.lib()
+    assert L.stf_filter_ewa(t.handle, q.data_ptr(), 4, 0.5, 0, 0, out.data_ptr(), None, None) == stf.STF_E_INVALID
+    assert L.stf_filter_ewa(t.handle, q.data_ptr(), 4, 8.0, 0, 0, out.data_ptr(), idx.data_ptr(), None) == stf.STF_E_INVALID
+    assert L.stf_filter_ewa(t.handle, q.data_ptr(), 4, 8.0, 5, 0, out.data_ptr(), None, None) == stf.STF_E_INVALID
+    host = np.zeros((4, 6), np.float32)
+    assert L.stf_filter_ewa(t.handle, host.ctypes.data, 4, 8.0, 0, 0, out.data_ptr(), None, None) == stf.STF_E_INVALID
+    t.destroy()
