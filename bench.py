@@ -18,7 +18,8 @@ training and BF16-MFMA inference), `serving` (three resident textures,
 Poisson arrivals of log-normal request sizes at 0.5 / 1 / 2 G lookups/s),
 `dct` (4096^2 x 9 DCT-compressed texture set, a 4K frame of uv queries, one
 decode per stochastic lookup), `gauss` (Gaussian FIS vs discrete 4x4 at sigma
-0.3 / 0.5 / 0.8 on the same set and frame).  The grid workload also times the interpolating cubics
+0.3 / 0.5 / 0.8 on the same set and frame), `ewa` (EWA over a 4096^2 RGBA8
+MIP pyramid for a frame of queries with derivatives).  The grid workload also times the interpolating cubics
 (Keys, Mitchell-Netravali; positivized two-tap stochastic vs 64-tap).
 
 Prints one JSON line.
@@ -392,6 +393,48 @@ def run_gauss(args, torch, stf, synth):
 
 
 # ----------------------------------------------------------------------------
+# elliptically weighted average filtering
+# ----------------------------------------------------------------------------
+def run_ewa(args, torch, stf, synth):
+    """EWA over the full MIP pyramid of a 4096^2 RGBA8 texture (the albedo and
+    roughness of the texture set) for the EWA queries of a 3840x2160 frame of
+    the ground plane (texture tiled every 2 units: minified, anisotropic
+    towards the horizon): one texel per stochastic lookup vs the full
+    two-level EWA."""
+    dev = torch.device("cuda:0")
+    size = 4096
+    rgba = np.ascontiguousarray(synth.texture_set_u8(size, seed=51)[:, :, :4])
+    lv = synth.mip_levels(rgba)
+    tex = stf.stf_create_texture2d(size, size, 4, stf.STF_FMT_U8, lv)
+    qn = synth.screen_ewa_queries(3840, 2160, seed=53)
+    n = qn.shape[0]
+    q = torch.from_numpy(qn).to(dev)
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    res = {}
+    for aniso in (8.0, 64.0):
+        for name, mode in (("stoch", stf.STF_STOCHASTIC), ("det", stf.STF_DETERMINISTIC)):
+            wall, kern = time_launches(lambda: stf.stf_filter_ewa(tex, q, aniso, mode, 9, out), args.steps,
+                                       args.warmup, torch)
+            key = f"{name}_aniso{int(aniso)}"
+            res[key] = variant_stats(n, args.steps, wall, kern, 24 + 16 + 4)
+            log(f"{key}: {res[key]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel {res[key]['kernel_ms_mean'] * 1e3:.1f} us")
+    head = res["stoch_aniso8"]
+    line = base_line(args, head["lookups_per_s"], "lookups/s", head["ms_per_step"], "f32",
+                     {"workload": f"EWA over the MIP pyramid of a {size}^2 RGBA8 texture, {n} queries of a 3840x2160 "
+                                  "frame (uv + derivatives), max anisotropy 8 and 64: stochastic (level draw + one "
+                                  "texel) vs deterministic two-level EWA", "n_queries": n})
+    line.update({"variants": res,
+                 "stochastic_over_deterministic": head["lookups_per_s"] / res["det_aniso8"]["lookups_per_s"],
+                 "stochastic_over_deterministic_aniso64":
+                     res["stoch_aniso64"]["lookups_per_s"] / res["det_aniso64"]["lookups_per_s"],
+                 "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
+                 "cpu_baseline": None})
+    tex.destroy()
+    return line
+
+
+# ----------------------------------------------------------------------------
 # filtering with shading
 # ----------------------------------------------------------------------------
 GGX_FLOPS = 120   # binary32 operations of one shading evaluation (see the design notes)
@@ -574,7 +617,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="grid", choices=["grid", "tex2d", "shade", "neural", "serving", "dct", "gauss"])
+    ap.add_argument("--workload", default="grid", choices=["grid", "tex2d", "shade", "neural", "serving", "dct", "gauss", "ewa"])
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16", "fp8_e4m3"])
     ap.add_argument("--order", default="ray", choices=["ray", "shuffled", "morton"])
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="queries in the CPU-oracle timing sample")
@@ -600,7 +643,7 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
-    run = {"grid": run_grid, "tex2d": run_tex2d, "shade": run_shade, "neural": run_neural, "dct": run_dct, "gauss": run_gauss,
+    run = {"grid": run_grid, "tex2d": run_tex2d, "shade": run_shade, "neural": run_neural, "dct": run_dct, "gauss": run_gauss, "ewa": run_ewa,
            "serving": run_serving}[args.workload]
     line = run(args, torch, stf, synth)
     print(json.dumps(line), flush=True)
