@@ -1165,9 +1165,12 @@ int orc_gauss_fis_positions(int W, int H, const float* uv, int64_t n, double sig
 /*     tt = t - st.y, r2 = ((A (ss ss)) + ((B ss) tt)) + (C (tt tt)); taps   */
 /*     with r2 < 1 get weight LUT[min((int)(r2 * 128), 127)], LUT[i] =        */
 /*     fl32(exp(-2 i/127) - exp(-2)) (a truncated Gaussian), taps clamped.   */
-/*   Deterministic: sum w t / sum w.  Stochastic: T = u1 * sum w (hash index  */
-/*   1), the first tap in scan order whose running sum exceeds T (the last   */
-/*   tap with weight if none does); the value is that texel.                 */
+/*   Deterministic: sum w t / sum w.  Stochastic: a row of the box by        */
+/*   weighted reservoir sampling over the row sums R_k (binary32 sums in     */
+/*   scan order; row k replaces the choice iff u_(16+k) * S < R_k with S the */
+/*   running sum of R), then a tap of that row: T = u1 R, the first tap whose */
+/*   running sum exceeds T (the last tap with weight if none does).  One     */
+/*   pass over the box and one over a row; the value is that texel.          */
 /* Values in binary64; the weights are the binary32 LUT values.              */
 /* ------------------------------------------------------------------------ */
 static float orc_ewa_lut[128];
@@ -1202,7 +1205,7 @@ static double orc_ewa_texel(const orc_ewa_tex* T, int l, int x, int y, int c)
 /* EWA on one level: the deterministic value (per channel) and/or the drawn
  * tap. */
 static void orc_ewa_level(const orc_ewa_tex* T, int l, float s, float t, const float d0in[2], const float d1in[2],
-                          int stochastic, float u, double* out, int* tx, int* ty)
+                          int stochastic, float u, uint64_t seed, uint32_t qid, double* out, int* tx, int* ty)
 {
     const int W = T->W[l], H = T->H[l];
     float stx = s * (float)W - 0.5f, sty = t * (float)H - 0.5f;
@@ -1220,38 +1223,34 @@ static void orc_ewa_level(const orc_ewa_tex* T, int l, float s, float t, const f
     float us = sqrtf(fmaxf(det * Cc, 0.0f)), vs = sqrtf(fmaxf(A * det, 0.0f));
     int s0 = (int)ceilf(stx - 2.0f * invDet * us), s1 = (int)floorf(stx + 2.0f * invDet * us);
     int t0 = (int)ceilf(sty - 2.0f * invDet * vs), t1 = (int)floorf(sty + 2.0f * invDet * vs);
-    float total = 0.0f;
-    double acc[16] = {0};
-    double wsum = 0.0;
-    int lastx = s0, lasty = t0;
-    for (int it = t0; it <= t1; ++it) {
-        float tt = (float)it - sty;
-        for (int is = s0; is <= s1; ++is) {
-            float ss = (float)is - stx;
-            float r2 = (A * (ss * ss) + (B * ss) * tt) + Cc * (tt * tt);
-            if (!(r2 < 1.0f)) continue;
-            int idx = (int)(r2 * 128.0f);
-            if (idx > 127) idx = 127;
-            float w = orc_ewa_lut[idx];
-            if (!(w > 0.0f)) continue;
-            total += w;
-            lastx = is;
-            lasty = it;
-            if (!stochastic) {
+    if (!stochastic) {
+        double acc[16] = {0};
+        double wsum = 0.0;
+        for (int it = t0; it <= t1; ++it) {
+            float tt = (float)it - sty;
+            for (int is = s0; is <= s1; ++is) {
+                float ss = (float)is - stx;
+                float r2 = (A * (ss * ss) + (B * ss) * tt) + Cc * (tt * tt);
+                if (!(r2 < 1.0f)) continue;
+                int idx = (int)(r2 * 128.0f);
+                if (idx > 127) idx = 127;
+                float w = orc_ewa_lut[idx];
+                if (!(w > 0.0f)) continue;
                 wsum += (double)w;
                 for (int c = 0; c < T->C; ++c) acc[c] += (double)w * orc_ewa_texel(T, l, is, it, c);
             }
         }
-    }
-    if (!stochastic) {
         for (int c = 0; c < T->C; ++c) out[c] = acc[c] / wsum;
         return;
     }
-    float Tq = u * total, run = 0.0f;
-    *tx = lastx;
-    *ty = lasty;
+    /* stochastic: a row by weighted reservoir sampling over the row sums
+     * (row k of the box replaces the choice iff u_(16+k) * S < R_k, S the
+     * running sum of row sums), then a tap of that row by the cumulative rule
+     * (T = u1 * R, the first tap whose running sum exceeds T) */
+    float S = 0.0f, Rsel = 0.0f;
+    int rsel = t0, found = 0;
     for (int it = t0; it <= t1; ++it) {
-        float tt = (float)it - sty;
+        float tt = (float)it - sty, R = 0.0f;
         for (int is = s0; is <= s1; ++is) {
             float ss = (float)is - stx;
             float r2 = (A * (ss * ss) + (B * ss) * tt) + Cc * (tt * tt);
@@ -1259,10 +1258,27 @@ static void orc_ewa_level(const orc_ewa_tex* T, int l, float s, float t, const f
             int idx = (int)(r2 * 128.0f);
             if (idx > 127) idx = 127;
             float w = orc_ewa_lut[idx];
-            if (!(w > 0.0f)) continue;
-            run += w;
-            if (Tq < run) { *tx = is; *ty = it; return; }
+            if (w > 0.0f) R += w;
         }
+        if (!(R > 0.0f)) continue;
+        S += R;
+        if (orc_uniform(seed, qid, 16u + (uint32_t)(it - t0)) * S < R) { rsel = it; Rsel = R; found = 1; }
+    }
+    *tx = s0;
+    *ty = rsel;
+    if (!found) return;
+    float tt = (float)rsel - sty, Tq = u * Rsel, run = 0.0f;
+    for (int is = s0; is <= s1; ++is) {
+        float ss = (float)is - stx;
+        float r2 = (A * (ss * ss) + (B * ss) * tt) + Cc * (tt * tt);
+        if (!(r2 < 1.0f)) continue;
+        int idx = (int)(r2 * 128.0f);
+        if (idx > 127) idx = 127;
+        float w = orc_ewa_lut[idx];
+        if (!(w > 0.0f)) continue;
+        run += w;
+        *tx = is;   /* the last tap with weight, if the running sum never exceeds T */
+        if (Tq < run) return;
     }
 }
 
@@ -1344,14 +1360,14 @@ int orc_ewa_filter2d(const void* const* level_texels, const int* W, const int* H
         if (mode == ORC_DET) {
             double a[16], b[16];
             int l0 = il < levels ? il : levels - 1, l1 = il + 1 < levels ? il + 1 : levels - 1;
-            orc_ewa_level(&T, l0, qk[0], qk[1], d0, d1, 0, 0.0f, a, NULL, NULL);
-            orc_ewa_level(&T, l1, qk[0], qk[1], d0, d1, 0, 0.0f, b, NULL, NULL);
+            orc_ewa_level(&T, l0, qk[0], qk[1], d0, d1, 0, 0.0f, seed, qid, a, NULL, NULL);
+            orc_ewa_level(&T, l1, qk[0], qk[1], d0, d1, 0, 0.0f, seed, qid, b, NULL, NULL);
             for (int c = 0; c < C; ++c) o[c] = (1.0 - frac) * a[c] + frac * b[c];
         } else {
             int l = il + ((double)orc_uniform(seed, qid, 0) < frac ? 1 : 0);
             if (l > levels - 1) l = levels - 1;
             int tx, ty;
-            orc_ewa_level(&T, l, qk[0], qk[1], d0, d1, 1, orc_uniform(seed, qid, 1), NULL, &tx, &ty);
+            orc_ewa_level(&T, l, qk[0], qk[1], d0, d1, 1, orc_uniform(seed, qid, 1), seed, qid, NULL, &tx, &ty);
             int sx = orc_clampi(tx, 0, W[l] - 1), sy = orc_clampi(ty, 0, H[l] - 1);
             for (int c = 0; c < C; ++c) o[c] = orc_ewa_texel(&T, l, sx, sy, c);
             if (ix) { ix[0] = sx; ix[1] = sy; ix[2] = l; }

@@ -16,8 +16,8 @@
 //    B^2 / 4; the bounding box st +- 2 sqrt(det C) / det (x), +- 2 sqrt(A det)
 //    / det (y), det = -B^2 + 4 A C; taps with r2 = A ss^2 + B ss tt + C tt^2
 //    < 1 weigh LUT[min(floor(128 r2), 127)], LUT[i] = exp(-2 i/127) -
-//    exp(-2).  The stochastic tap: T = u1 * sum w (hash index 1), the first
-//    tap in scan order (rows outer) whose running sum exceeds T.
+//    exp(-2).  The stochastic tap: a row by weighted reservoir sampling over
+//    the row sums, then a tap of the row by the cumulative rule (ewa_draw).
 //  - A zero footprint reads bilinearly from level 0 (stochastic: the linear
 //    draw with hash indices 2, 3); levels past the last read the last.
 // Taps are clamped to their level.
@@ -26,6 +26,7 @@
 #include <new>
 
 #include "device_common.h"
+#include "interp.h"
 #include "stf_internal.h"
 
 using namespace stf;
@@ -132,32 +133,43 @@ __device__ __forceinline__ void ewa_mean(const TexLevel& L, const Ellipse& e, co
     for (int c = 0; c < C; ++c) v[c] = acc[c] / wsum;
 }
 
-__device__ __forceinline__ void ewa_draw(const Ellipse& e, const float* lut, float u, int& tx, int& ty)
+// The stochastic tap: a row of the box by weighted reservoir sampling over
+// the row sums R_k (binary32, scan order; row k replaces the choice iff
+// u_(16+k) * S < R_k, S the running sum of row sums), then a tap of that row
+// by the cumulative rule (T = u1 R, the first tap whose running sum exceeds
+// T).  One pass over the box and one over a single row.
+__device__ __forceinline__ void ewa_draw(const Ellipse& e, const float* lut, uint32_t h0, float u1, int& tx, int& ty)
 {
-    float total = 0.0f;
+    const uint32_t base = h0 * 747796405u + 2891336453u;
+    float S = 0.0f, Rsel = 0.0f;
+    int rsel = e.t0;
+    bool found = false;
+    for (int it = e.t0; it <= e.t1; ++it) {
+        float R = 0.0f;
+        for (int is = e.s0; is <= e.s1; ++is) {
+            const float w = ewa_weight(e, lut, is, it);
+            if (w > 0.0f) R += w;
+        }
+        if (!(R > 0.0f)) continue;
+        S += R;
+        if (uniform_from_base(base, 16u + (uint32_t)(it - e.t0)) * S < R) {
+            rsel = it;
+            Rsel = R;
+            found = true;
+        }
+    }
     tx = e.s0;
-    ty = e.t0;
-    for (int it = e.t0; it <= e.t1; ++it)
-        for (int is = e.s0; is <= e.s1; ++is) {
-            const float w = ewa_weight(e, lut, is, it);
-            if (!(w > 0.0f)) continue;
-            total += w;
-            tx = is;   // the last tap with weight, if the running sum never exceeds T
-            ty = it;
-        }
-    const float T = u * total;
+    ty = rsel;
+    if (!found) return;
+    const float T = u1 * Rsel;
     float run = 0.0f;
-    for (int it = e.t0; it <= e.t1; ++it)
-        for (int is = e.s0; is <= e.s1; ++is) {
-            const float w = ewa_weight(e, lut, is, it);
-            if (!(w > 0.0f)) continue;
-            run += w;
-            if (T < run) {
-                tx = is;
-                ty = it;
-                return;
-            }
-        }
+    for (int is = e.s0; is <= e.s1; ++is) {
+        const float w = ewa_weight(e, lut, is, rsel);
+        if (!(w > 0.0f)) continue;
+        run += w;
+        tx = is;   // the last tap with weight, if the running sum never exceeds T
+        if (T < run) return;
+    }
 }
 
 template <int FMT, int C, bool STOCH>
@@ -233,7 +245,7 @@ __global__ __launch_bounds__(BLOCK) void k_ewa(EwaLevels P, EwaLut lut_in, const
                 l = l > L - 1 ? L - 1 : l;
                 const Ellipse e = ellipse(P.level[l], r[0], r[1], d0, d1);
                 int tx, ty;
-                ewa_draw(e, lut, axis_uniform(h0, 1), tx, ty);
+                ewa_draw(e, lut, h0, axis_uniform(h0, 1), tx, ty);
                 ix[0] = clampi(tx, P.level[l].w - 1);
                 ix[1] = clampi(ty, P.level[l].h - 1);
                 ix[2] = l;
