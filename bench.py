@@ -209,6 +209,14 @@ def run_grid(args, torch, stf, synth):
                               f"stochastic tricubic, FP64 C oracle with OpenMP, {dt:.2f} s")
             log(f"cpu oracle: {m / dt / 1e6:.2f} M lookups/s on {threads} threads")
 
+    # context for the roofline: a plain 1 GiB device-to-device copy (read +
+    # write) timed the same way -- the practically reachable HBM rate
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    cw, ck = time_launches(lambda: dst.copy_(src), 5, 2, torch)
+    copy_gbs = 2 * src.numel() * 4 / (float(np.mean(ck)) * 1e-3) / 1e9
+    del src, dst
+    log(f"device copy: {copy_gbs:.0f} GB/s")
     head = res.get("stoch_cubic") or next(iter(res.values()))
     det = res.get("det_cubic")
     line = base_line(args, head["lookups_per_s"], "lookups/s", head["ms_per_step"], args.fmt,
@@ -227,6 +235,7 @@ def run_grid(args, torch, stf, synth):
         "variants": res,
         "sort": sort_info,
         "parity": parity,
+        "hbm_copy_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": args.traffic if args.traffic is not None
