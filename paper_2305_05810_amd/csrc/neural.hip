@@ -363,22 +363,18 @@ __device__ __forceinline__ bf16x8 relu_bf16(const f32x16& d, int base)
     return __builtin_bit_cast(bf16x8, v);
 }
 
-// One lane's decode within a 32-decode batch: the query it serves, the tap,
-// the tap's filter weight and the texel it decodes.
+// One lane's decode: the tap it stands for, the texel it decodes and the
+// tap's filter weight.
 struct Decode {
-    int64_t qi;
-    int tap, sx, sy;
+    int sx, sy;
     float w;
-    bool live, fin;
+    bool fin;
 };
 
 template <bool CUBIC, bool STOCH>
 __device__ __forceinline__ Decode locate(const InferArgs& a, int64_t qi, int tap, float2 uv)
 {
     Decode d;
-    d.qi = qi;
-    d.tap = tap;
-    d.live = qi < a.n;
     float x = uv.x * (float)a.W - 0.5f, y = uv.y * (float)a.H - 0.5f;
     int cx = 0, cy = 0;
     float tx = 0.0f, ty = 0.0f;
@@ -431,14 +427,68 @@ __device__ __forceinline__ void latent_corners(const InferArgs& a, const Decode&
     w[3] = fx * fy;
 }
 
-// Persistent waves; each handles batches wave, wave + nwaves, ...  The loop is
-// software-pipelined: while batch i runs its MFMAs, the latents of batch
-// i + 1 and the queries of batch i + 2 are in flight.
+// The decoder MLP on one 32-decode batch: B1 holds the bf16 latents of the
+// batch's decodes in k-slots 0..7 (lanes 0..31) and ones in the bias slots
+// 8..10 (lanes 32..63).  Returns layer 3's accumulator.
+__device__ __forceinline__ f32x16 mlp_batch(const bf16x8& B1, const bf16x8 (&A1)[2], const bf16x8 (&A2)[2][4],
+                                            const bf16x8 (&A3)[4], const bf16x8 (&AB2)[2], const bf16x8& AB3,
+                                            const bf16x8& ONES)
+{
+    const f32x16 Z = {};
+    // layer 1: 64 x 16 by 16 x 32 (k 0..7 latents, 8..10 bias terms)
+    f32x16 D1[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) D1[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[mb], B1, Z, 0, 0, 0);
+    bf16x8 B2[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) B2[kb] = relu_bf16(D1[kb / 2], 8 * (kb % 2));
+    // layer 2: bias, then 64 x 64 by 64 x 32
+    f32x16 D2[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+        D2[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AB2[mb], ONES, Z, 0, 0, 0);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+            D2[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2[mb][kb], B2[kb], D2[mb], 0, 0, 0);
+    }
+    bf16x8 B3[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) B3[kb] = relu_bf16(D2[kb / 2], 8 * (kb % 2));
+    // layer 3: bias, then 8 (of 32) x 64 by 64 x 32
+    f32x16 D3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AB3, ONES, Z, 0, 0, 0);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) D3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A3[kb], B3[kb], D3, 0, 0, 0);
+    return D3;
+}
+
+// Registers 0..3 of layer 3's accumulator hold channels 4h..4h+3 of decode
+// jd; weight them, sum the taps of each query and store.  A non-finite query
+// carries a NaN weight, so every channel it stores is NaN.
+template <int TAPS>
+__device__ __forceinline__ void emit(const InferArgs& a, const f32x16& D3, float w, int64_t qi, int tap, int h)
+{
+    float o[4] = {D3[0] * w, D3[1] * w, D3[2] * w, D3[3] * w};
+#pragma unroll
+    for (int off = 1; off < TAPS; off <<= 1) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o[c] += __shfl_xor(o[c], off, 64);
+    }
+    if (qi < a.n && tap == 0) reinterpret_cast<float4*>(a.out)[qi * 2 + h] = make_float4(o[0], o[1], o[2], o[3]);
+}
+
+// Persistent waves; each handles pairs of 32-decode batches p = wave,
+// wave + nwaves, ...  Lane l does the per-decode work (tap choice, latent
+// gather and interpolation) for decode l of the pair, so no lane repeats
+// another's; one cross-half swap then lays the two batches' latents out as
+// MFMA B operands, each with the bias ones in its upper half.  The loop is
+// software-pipelined: while pair i runs its MFMAs, the latents of pair i + 1
+// and the queries of pair i + 2 are in flight.
 template <bool CUBIC, bool STOCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_ntex_infer(InferArgs a)
 {
     constexpr int TAPS = STOCH ? 1 : (CUBIC ? 16 : 4);
     constexpr int QPB = 32 / TAPS;   // queries per 32-decode batch
+    constexpr int QPP = 2 * QPB;     // queries per pair of batches
     const int lane = threadIdx.x % 64, h = lane / 32, jd = lane % 32;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int nwaves = gridDim.x * blockDim.x / 64;
@@ -456,17 +506,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     AB3 = pk->ab3[lane];
 #pragma unroll
     for (int j = 0; j < 8; ++j) ONES[j] = (__bf16)((h == 1 && j < 3) ? 1.0f : 0.0f);   // k-slots 8..10
+    // The bias ones as every lane's slots j = 0..2 hold them in the upper
+    // half: (1, 1, 1, 0, 0, 0, 0, 0) in bf16, as four 32-bit words.
+    const uint32_t ONE_WORDS[4] = {0x3F803F80u, 0x00003F80u, 0u, 0u};
 
-    const int64_t nbatch = ((int64_t)a.n + QPB - 1) / QPB;
-    const int tap = jd % TAPS;
+    const int64_t npair = ((int64_t)a.n + QPP - 1) / QPP;
+    const int tap = lane % TAPS;
     const uint4* L = reinterpret_cast<const uint4*>(a.lat16);
-    auto load_uv = [&](int64_t bt) {
-        int64_t qi = bt * QPB + jd / TAPS;
-        return (bt < nbatch && qi < a.n) ? reinterpret_cast<const float2*>(a.q)[qi] : make_float2(0.5f, 0.5f);
+    auto load_uv = [&](int64_t p) {
+        int64_t qi = p * QPP + lane / TAPS;
+        return (p < npair && qi < a.n) ? reinterpret_cast<const float2*>(a.q)[qi] : make_float2(0.5f, 0.5f);
     };
     // Every lane loads: the corners are clamped into the table for any query
-    // (padding lanes carry uv = (0.5, 0.5)), and the two lane halves of a
-    // decode read the same addresses, which the wave's request coalesces.
+    // (padding lanes carry uv = (0.5, 0.5)).
     auto load_lat = [&](const Decode& d, uint4 (&v)[4], float (&w)[4]) {
         uint32_t c[4];
         latent_corners(a, d, c, w);
@@ -474,75 +526,66 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int k = 0; k < 4; ++k) v[k] = L[c[k]];
     };
 
-    int64_t bt = wave;
-    float2 uv_next = load_uv(bt + nwaves);
-    Decode cur = locate<CUBIC, STOCH>(a, bt * QPB + jd / TAPS, tap, load_uv(bt));
+    int64_t p = wave;
+    float2 uv_next = load_uv(p + nwaves);
+    Decode cur = locate<CUBIC, STOCH>(a, p * QPP + lane / TAPS, tap, load_uv(p));
     uint4 lat_cur[4];
     float wl_cur[4];
     load_lat(cur, lat_cur, wl_cur);
-    for (; bt < nbatch; bt += nwaves) {
-        // ---- stage the next two batches
-        const float2 uv_after = load_uv(bt + 2 * (int64_t)nwaves);
-        const Decode nxt = locate<CUBIC, STOCH>(a, (bt + nwaves) * QPB + jd / TAPS, tap, uv_next);
+    for (; p < npair; p += nwaves) {
+        // ---- stage the next two pairs
+        const float2 uv_after = load_uv(p + 2 * (int64_t)nwaves);
+        const Decode nxt = locate<CUBIC, STOCH>(a, (p + nwaves) * QPP + lane / TAPS, tap, uv_next);
         uint4 lat_nxt[4];
         float wl_nxt[4];
         load_lat(nxt, lat_nxt, wl_nxt);
-        // ---- latent interpolation of this batch (lanes 0..31 carry the 8 channels)
-        bf16x8 B1 = ONES;
-        if (h == 0) {
+        // ---- latent interpolation of this lane's decode, rounded to bf16
+        uint32_t X[4];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                int wsel = j / 2, sh = 16 * (j % 2);
+        for (int wsel = 0; wsel < 4; ++wsel) {
+            float v[2];
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const int sh = 16 * half;
                 const uint32_t* p0 = reinterpret_cast<const uint32_t*>(&lat_cur[0]);
                 const uint32_t* p1 = reinterpret_cast<const uint32_t*>(&lat_cur[1]);
                 const uint32_t* p2 = reinterpret_cast<const uint32_t*>(&lat_cur[2]);
                 const uint32_t* p3 = reinterpret_cast<const uint32_t*>(&lat_cur[3]);
-                float v = wl_cur[0] * dec_f16((uint16_t)(p0[wsel] >> sh));
-                v = __builtin_fmaf(wl_cur[1], dec_f16((uint16_t)(p1[wsel] >> sh)), v);
-                v = __builtin_fmaf(wl_cur[2], dec_f16((uint16_t)(p2[wsel] >> sh)), v);
-                v = __builtin_fmaf(wl_cur[3], dec_f16((uint16_t)(p3[wsel] >> sh)), v);
-                B1[j] = (__bf16)v;
+                float s = wl_cur[0] * dec_f16((uint16_t)(p0[wsel] >> sh));
+                s = __builtin_fmaf(wl_cur[1], dec_f16((uint16_t)(p1[wsel] >> sh)), s);
+                s = __builtin_fmaf(wl_cur[2], dec_f16((uint16_t)(p2[wsel] >> sh)), s);
+                s = __builtin_fmaf(wl_cur[3], dec_f16((uint16_t)(p3[wsel] >> sh)), s);
+                v[half] = s;
             }
+            X[wsel] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){v[0], v[1]}, bf16x2));
         }
-        const f32x16 Z = {};
-        // ---- layer 1: 64 x 16 by 16 x 32 (k 0..7 latents, 8..10 bias terms)
-        f32x16 D1[2];
+        // ---- batch 0 = decodes 0..31, batch 1 = decodes 32..63.  Swapping
+        // the upper half of X with the lower half of the ones gives batch 0's
+        // B operand in the first result and batch 1's in the second.
+        uint32_t B1w[2][4];
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) D1[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[mb], B1, Z, 0, 0, 0);
-        bf16x8 B2[4];
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) B2[kb] = relu_bf16(D1[kb / 2], 8 * (kb % 2));
-        // ---- layer 2: bias, then 64 x 64 by 64 x 32
-        f32x16 D2[2];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-            D2[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AB2[mb], ONES, Z, 0, 0, 0);
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
-                D2[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2[mb][kb], B2[kb], D2[mb], 0, 0, 0);
+        for (int k = 0; k < 4; ++k) {
+            auto r = __builtin_amdgcn_permlane32_swap(X[k], ONE_WORDS[k], false, false);
+            B1w[0][k] = r[0];
+            B1w[1][k] = r[1];
         }
-        bf16x8 B3[4];
+        // decode weights in the same way: lane l of batch b needs decode 32 b + l % 32's
+        const float wd = cur.fin ? cur.w : __builtin_nanf("");
+        const uint32_t wb = __builtin_bit_cast(uint32_t, wd);
+        const auto rw = __builtin_amdgcn_permlane32_swap(wb, wb, false, false);
+        const int64_t q0 = p * QPP + jd / TAPS;
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) B3[kb] = relu_bf16(D2[kb / 2], 8 * (kb % 2));
-        // ---- layer 3: bias, then 8 (of 32) x 64 by 64 x 32
-        f32x16 D3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AB3, ONES, Z, 0, 0, 0);
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) D3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A3[kb], B3[kb], D3, 0, 0, 0);
-        // ---- registers 0..3 of this lane: channels 4h..4h+3 of decode jd
-        float o[4] = {D3[0] * cur.w, D3[1] * cur.w, D3[2] * cur.w, D3[3] * cur.w};
-#pragma unroll
-        for (int off = 1; off < TAPS; off <<= 1) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) o[c] += __shfl_xor(o[c], off, 64);
+        for (int b = 0; b < 2; ++b) {
+            const bf16x8 B1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(B1w[b]));
+            const f32x16 D3 = mlp_batch(B1, A1, A2, A3, AB2, AB3, ONES);
+            emit<TAPS>(a, D3, __builtin_bit_cast(float, (uint32_t)rw[b]), q0 + b * QPB, tap, h);
         }
-        if (cur.live && tap == 0) {
-            float4 v = cur.fin ? make_float4(o[0], o[1], o[2], o[3])
-                               : make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""),
-                                             __builtin_nanf(""));
-            reinterpret_cast<float4*>(a.out)[cur.qi * 2 + h] = v;
-            if (STOCH && a.idx && h == 0) {
-                a.idx[2 * cur.qi] = cur.fin ? cur.sx : BAD_INDEX;
-                a.idx[2 * cur.qi + 1] = cur.fin ? cur.sy : BAD_INDEX;
+        // selected texel of this lane's own decode (stochastic: one decode per query)
+        if (STOCH && a.idx) {
+            const int64_t qi = p * QPP + lane;
+            if (qi < a.n) {
+                a.idx[2 * qi] = cur.fin ? cur.sx : BAD_INDEX;
+                a.idx[2 * qi + 1] = cur.fin ? cur.sy : BAD_INDEX;
             }
         }
         cur = nxt;
@@ -935,10 +978,10 @@ stf_status stf_ntex_filter(const stf_neural* nt, const float* queries_dev, int64
     a.out = out_dev;
     a.idx = out_index_dev;
     int taps = mode == STF_STOCHASTIC ? 1 : (filter == STF_CUBIC_BSPLINE ? 16 : 4);
-    int64_t batches = (n * taps + 31) / 32;
+    int64_t pairs = (n * taps + 63) / 64;   // pairs of 32-decode batches
     // Persistent waves, one resident set (3 per SIMD on 256 CUs): the weights
     // load once per wave.
-    int64_t waves = batches < 3072 ? batches : 3072;
+    int64_t waves = pairs < 3072 ? pairs : 3072;
     dim3 grid((unsigned)((waves + 3) / 4)), block(256);
     hipStream_t st = (hipStream_t)hip_stream;
     bool cubic = filter == STF_CUBIC_BSPLINE;
