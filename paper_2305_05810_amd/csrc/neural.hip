@@ -461,6 +461,34 @@ __device__ __forceinline__ f32x16 mlp_batch(const bf16x8& B1, const bf16x8 (&A1)
     return D3;
 }
 
+// Sum of v over each group of TAPS consecutive lanes (TAPS = 1, 4 or 16),
+// left in every lane of the group, by data-parallel-primitive moves within a
+// row of 16 lanes: swapping neighbours, then pairs, gives each quad its sum;
+// mirroring within 8 lanes adds the neighbouring quad, mirroring within 16
+// lanes the other half-row.
+template <int TAPS>
+__device__ __forceinline__ float tap_sum(float v)
+{
+    static_assert(TAPS == 1 || TAPS == 4 || TAPS == 16, "taps per query");
+    auto dpp = [](float x, int ctrl) {
+        switch (ctrl) {   // the control word must be a constant
+        case 0:  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, true));
+        case 1:  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, true));
+        case 2:  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x141, 0xF, 0xF, true));
+        default: return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x140, 0xF, 0xF, true));
+        }
+    };
+    if constexpr (TAPS >= 4) {
+        v += dpp(v, 0);   // quad_perm [1,0,3,2]
+        v += dpp(v, 1);   // quad_perm [2,3,0,1]
+    }
+    if constexpr (TAPS >= 16) {
+        v += dpp(v, 2);   // row_half_mirror
+        v += dpp(v, 3);   // row_mirror
+    }
+    return v;
+}
+
 // Registers 0..3 of layer 3's accumulator hold channels 4h..4h+3 of decode
 // jd; weight them, sum the taps of each query and store.  A non-finite query
 // carries a NaN weight, so every channel it stores is NaN.
@@ -469,10 +497,7 @@ __device__ __forceinline__ void emit(const InferArgs& a, const f32x16& D3, float
 {
     float o[4] = {D3[0] * w, D3[1] * w, D3[2] * w, D3[3] * w};
 #pragma unroll
-    for (int off = 1; off < TAPS; off <<= 1) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) o[c] += __shfl_xor(o[c], off, 64);
-    }
+    for (int c = 0; c < 4; ++c) o[c] = tap_sum<TAPS>(o[c]);
     if (qi < a.n && tap == 0) reinterpret_cast<float4*>(a.out)[qi * 2 + h] = make_float4(o[0], o[1], o[2], o[3]);
 }
 
