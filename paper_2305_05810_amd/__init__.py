@@ -211,6 +211,15 @@ def stf_texture_bytes(tex: Texture) -> int:
     return b.value
 
 
+# Element type of every buffer the library reads or writes, by argument name
+# (the library sees raw pointers, so a wrong type would be read or written
+# past its end).
+_DTYPES = {"queries": "float32", "sorted_queries": "float32", "sorted_out": "float32", "out": "float32",
+           "out_rgb": "float32", "target": "float32", "grad_latents": "float32", "grad_mlp": "float32",
+           "loss": "float32", "out_index": "int32", "order": "int32", "order_out": "int32",
+           "positions": "int32", "sum": "float64", "sumsq": "float64", "workspace": "uint8"}
+
+
 def _dev_ptr(t, name):
     if t is None:
         return None
@@ -218,6 +227,9 @@ def _dev_ptr(t, name):
         raise ValueError(f"{name} must be a GPU tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    want = _DTYPES[name]
+    if str(t.dtype) != "torch." + want:
+        raise ValueError(f"{name} must be {want}, not {t.dtype}")
     return t.data_ptr()
 
 
@@ -225,6 +237,12 @@ def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return s.cuda_stream
+
+
+def _check_queries(tex: Texture, queries, n: int):
+    """The library reads n x dims binary32 coordinates through a raw pointer."""
+    if queries.numel() < n * tex.dims:
+        raise ValueError(f"queries hold {queries.numel()} values, {n * tex.dims} needed ({tex.dims} per query)")
 
 
 def _check_outputs(tex: Texture, n: int, filter: int, out, out_index):
@@ -242,6 +260,7 @@ def stf_filter(tex: Texture, queries, filter: int, mode: int, seed: int, out, ou
     tensor; out_index: None or (n, index_width(filter, dims)) int32 GPU
     tensor (stochastic)."""
     n = queries.shape[0]
+    _check_queries(tex, queries, n)
     _check_outputs(tex, n, filter, out, out_index)
     _check(lib().stf_filter(tex.handle, _dev_ptr(queries, "queries"), n, filter, mode, seed & (2 ** 64 - 1),
                             _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"), flags, _stream(stream)))
@@ -251,6 +270,7 @@ def stf_filter_gaussian(tex: Texture, queries, sigma: float, mode: int, seed: in
     """Gaussian filtering of a 2D texture (STF_GAUSS_* modes); out: (n,
     channels) float32; out_index: None or (n, 2) int32 (stochastic modes)."""
     n = queries.shape[0]
+    _check_queries(tex, queries, n)
     if out.numel() < n * tex.channels:
         raise ValueError("out is too small")
     if out_index is not None and out_index.numel() < 2 * n:
@@ -277,6 +297,7 @@ def stf_filter_ewa(tex: Texture, queries, max_anisotropy: float, mode: int, seed
 def stf_filter_moments(tex: Texture, queries, filter: int, seed_base: int, n_seeds: int, sum_out, sumsq_out,
                        stream=None):
     n = queries.shape[0]
+    _check_queries(tex, queries, n)
     if sum_out.numel() < n or sumsq_out.numel() < n:
         raise ValueError("sum/sumsq hold fewer than n values")
     _check(lib().stf_filter_moments(tex.handle, _dev_ptr(queries, "queries"), n, filter, seed_base, n_seeds,
@@ -285,7 +306,13 @@ def stf_filter_moments(tex: Texture, queries, filter: int, seed_base: int, n_see
 
 def stf_shade_filter(material: Texture, queries, filter: int, mode: int, seed: int, out_rgb, out_index=None,
                      stream=None):
+    """queries: (n, 9) float32 shading records; out_rgb: (n, 3) float32;
+    out_index: None or (n, 3) int32 (x, y, level; stochastic mode)."""
     n = queries.shape[0]
+    if queries.numel() < 9 * n or out_rgb.numel() < 3 * n:
+        raise ValueError("queries or out_rgb is too small")
+    if out_index is not None and out_index.numel() < 3 * n:
+        raise ValueError("out_index is too small")
     _check(lib().stf_shade_filter(material.handle, _dev_ptr(queries, "queries"), n, filter, mode,
                                   seed & (2 ** 64 - 1), _dev_ptr(out_rgb, "out_rgb"),
                                   _dev_ptr(out_index, "out_index"), _stream(stream)))
@@ -394,8 +421,14 @@ def stf_ntex_prepare_inference(nt: NeuralTexture, stream=None):
 
 
 def stf_ntex_filter(nt: NeuralTexture, queries, filter: int, mode: int, seed: int, out, out_index=None, stream=None):
-    """queries: (n, 2) float32 GPU tensor; out: (n, 8) float32 GPU tensor."""
-    _check(_ntex_lib().stf_ntex_filter(nt.handle, _dev_ptr(queries, "queries"), queries.shape[0], filter, mode,
+    """queries: (n, 2) float32 GPU tensor; out: (n, 8) float32 GPU tensor;
+    out_index: None or (n, 2) int32 (stochastic mode)."""
+    n = queries.shape[0]
+    if queries.numel() < 2 * n or out.numel() < 8 * n:
+        raise ValueError("queries or out is too small")
+    if out_index is not None and out_index.numel() < 2 * n:
+        raise ValueError("out_index is too small")
+    _check(_ntex_lib().stf_ntex_filter(nt.handle, _dev_ptr(queries, "queries"), n, filter, mode,
                                        seed & (2 ** 64 - 1), _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"),
                                        _stream(stream)))
 
@@ -488,6 +521,8 @@ def _buf(x, name):
     if isinstance(x, np.ndarray):
         if not x.flags.c_contiguous:
             raise ValueError(f"{name} must be contiguous")
+        if x.dtype != np.dtype(_DTYPES[name]):
+            raise ValueError(f"{name} must be {_DTYPES[name]}, not {x.dtype}")
         return x.ctypes.data, False
     return _dev_ptr(x, name), True
 
@@ -573,8 +608,13 @@ def stf_sort_workspace_bytes(n: int) -> int:
 
 
 def stf_sort_queries(tex: Texture, queries, sorted_out, order_out, workspace, stream=None):
-    """workspace: a uint8 GPU tensor of at least stf_sort_workspace_bytes(n)."""
-    _check(_sort_lib().stf_sort_queries(tex.handle, _dev_ptr(queries, "queries"), queries.shape[0],
+    """workspace: a uint8 GPU tensor of at least stf_sort_workspace_bytes(n);
+    sorted_out: like queries; order_out: n int32."""
+    n = queries.shape[0]
+    _check_queries(tex, queries, n)
+    if sorted_out.numel() < n * tex.dims or order_out.numel() < n:
+        raise ValueError("sorted_out or order_out is too small")
+    _check(_sort_lib().stf_sort_queries(tex.handle, _dev_ptr(queries, "queries"), n,
                                         _dev_ptr(sorted_out, "sorted_out"), _dev_ptr(order_out, "order_out"),
                                         _dev_ptr(workspace, "workspace"), workspace.numel() * workspace.element_size(),
                                         _stream(stream)))
@@ -582,6 +622,7 @@ def stf_sort_queries(tex: Texture, queries, sorted_out, order_out, workspace, st
 
 def stf_filter_ordered(tex: Texture, sorted_queries, order, filter: int, mode: int, seed: int, out, out_index=None,
                        flags: int = 0, stream=None):
+    _check_queries(tex, sorted_queries, sorted_queries.shape[0])
     _check_outputs(tex, sorted_queries.shape[0], filter, out, out_index)
     if order.numel() < sorted_queries.shape[0]:
         raise ValueError("order is shorter than the query stream")
