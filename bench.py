@@ -89,7 +89,10 @@ def run_grid(args, torch, stf, synth):
     dims = (512, 512, 512)
     t0 = time.time()
     grid = synth.fbm_grid(dims, seed=3)
-    pts = synth.ray_queries(dims, n_rays=65536, samples_per_ray=256, seed=4, shuffle=args.order == "shuffled")
+    if args.order == "medium":   # ray samples whose taps meet a stored leaf
+        pts = synth.medium_ray_queries(grid, 1 << 24, seed=4)
+    else:
+        pts = synth.ray_queries(dims, n_rays=65536, samples_per_ray=256, seed=4, shuffle=args.order == "shuffled")
     n = pts.shape[0]
     log(f"inputs: {grid.n_leaves} leaves ({100 * grid.occupancy():.2f}% of slots), {n} queries, "
         f"{time.time() - t0:.1f}s")
@@ -211,9 +214,13 @@ def run_grid(args, torch, stf, synth):
                     break
             cpu = dict(value=passes * m / dt, unit="lookups/s", cores=threads, kind="oracle",
                        sample=f"{passes} pass(es) over {'all' if m == n else 'the first ' + str(m) + ' of the'} "
-                              f"{n} ray-ordered queries, stochastic tricubic, FP64 C oracle with OpenMP, "
+                              f"{n} queries of the batch, stochastic tricubic, FP64 C oracle with OpenMP, "
                               f"{dt:.2f} s in all")
             log(f"cpu oracle: {passes * m / dt / 1e6:.2f} M lookups/s on {threads} threads ({passes} passes, {dt:.1f} s)")
+
+    medium = None
+    if args.order == "ray" and not args.only and not args.no_medium:
+        medium = run_grid_medium(args, torch, stf, synth, grid, tex, raw, out, seed, texel_b)
 
     # context for the roofline: a plain 1 GiB device-to-device copy (read +
     # write) timed the same way -- the practically reachable HBM rate
@@ -227,7 +234,8 @@ def run_grid(args, torch, stf, synth):
     det = res.get("det_cubic")
     line = base_line(args, head["lookups_per_s"], "lookups/s", head["ms_per_step"], args.fmt,
                      {"workload": f"sparse fBm voxel grid 512^3 of dense 8^3 {args.fmt} leaves "
-                                  f"({grid.n_leaves} leaves), {n} {args.order}-ordered ray queries, "
+                                  f"({grid.n_leaves} leaves), {n} "
+                                  f"{'ray samples inside the medium' if args.order == 'medium' else args.order + '-ordered ray queries'}, "
                                   f"stochastic tricubic B-spline (deterministic 64-tap beside it)",
                       "n_queries": n, "n_leaves": grid.n_leaves, "order": args.order})
     line.update({
@@ -239,6 +247,7 @@ def run_grid(args, torch, stf, synth):
             k: res[f"stoch_{k}"]["lookups_per_s"] / res[f"det_{k}"]["lookups_per_s"]
             for k in ("keys", "mitchell") if f"stoch_{k}" in res and f"det_{k}" in res},
         "variants": res,
+        "in_medium": medium,
         "sort": sort_info,
         "parity": parity,
         "hbm_copy_gbs": copy_gbs,
@@ -250,6 +259,47 @@ def run_grid(args, torch, stf, synth):
     })
     tex.destroy()
     return line
+
+
+def run_grid_medium(args, torch, stf, synth, grid, tex, raw, out, seed, texel_b):
+    """Stochastic vs deterministic tricubic on the ray samples whose taps meet
+    a stored leaf (the lookups a renderer makes inside the medium, empty space
+    skipped), same grid, same count; with an oracle parity sample."""
+    dev = out.device
+    n = out.shape[0]
+    t1 = time.time()
+    mp = synth.medium_ray_queries(grid, n, seed=4)
+    qm = torch.from_numpy(mp).to(dev)
+    log(f"in-medium stream: {n} ray samples whose taps meet a leaf, {time.time() - t1:.1f}s")
+    res = {}
+    for name, mode in (("stoch_cubic", stf.STF_STOCHASTIC), ("det_cubic", stf.STF_DETERMINISTIC)):
+        wall, kern = time_launches(lambda: stf.stf_filter(tex, qm, stf.STF_CUBIC_BSPLINE, mode, seed, out),
+                                   args.steps, args.warmup, torch)
+        res[name] = variant_stats(n, args.steps, wall, kern, 12 + 4 + (1 if mode == stf.STF_STOCHASTIC else 64) * texel_b)
+        log(f"in-medium {name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel "
+            f"{res[name]['kernel_ms_mean'] * 1e3:.1f} us")
+    res["stochastic_over_deterministic"] = res["stoch_cubic"]["lookups_per_s"] / res["det_cubic"]["lookups_per_s"]
+    if not args.no_check:
+        import oracle
+        ofmt = {"f32": oracle.F32, "f16": oracle.F16, "bf16": oracle.BF16, "fp8_e4m3": oracle.FP8_E4M3}[args.fmt]
+        og = oracle.Grid(grid.dims, ofmt, grid.origins, raw)
+        qids = np.sort(np.random.default_rng(13).choice(n, 1 << 14, replace=False))
+        idx = torch.empty((n, 3), dtype=torch.int32, device=dev)
+        stf.stf_filter(tex, qm, stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, seed, out, idx)
+        gv, gi = out[:, 0].cpu().numpy()[qids], idx.cpu().numpy()[qids]
+        ov, oi = og.filter_at(mp, qids, oracle.CUBIC, oracle.STOCH, seed)
+        par = {"sampled": int(qids.size), "index_mismatches": int(np.any(gi != oi, axis=1).sum()),
+               "value_mismatches": int((gv != ov.astype(np.float32)).sum())}
+        del idx
+        stf.stf_filter(tex, qm, stf.STF_CUBIC_BSPLINE, stf.STF_DETERMINISTIC, 0, out)
+        gd = out[:, 0].cpu().numpy()[qids].astype(np.float64)
+        od, _ = og.filter_at(mp, qids, oracle.CUBIC, oracle.DET, 0)
+        scale, _ = og.filter_at(mp, qids, oracle.CUBIC, oracle.DET_ABS, 0)
+        par["det_within_1e6"] = bool(np.all(np.abs(gd - od) <= 1e-6 * scale))
+        res["parity"] = par
+        log(f"in-medium parity: {par}")
+    del qm
+    return res
 
 
 def positivized_scale(oracle, og, pts, oi, ofilt):
@@ -634,11 +684,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grid", choices=["grid", "tex2d", "shade", "neural", "serving", "dct", "gauss", "ewa"])
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16", "fp8_e4m3"])
-    ap.add_argument("--order", default="ray", choices=["ray", "shuffled", "morton"])
+    ap.add_argument("--order", default="ray", choices=["ray", "shuffled", "morton", "medium"],
+                    help="grid query stream: ray samples in ray order, shuffled, Morton-sorted, or only the ray "
+                         "samples whose taps meet a stored leaf (inside the medium)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="queries in the CPU-oracle timing sample")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the CPU-oracle timing over the sample for at least this long")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle timing")
+    ap.add_argument("--no-medium", action="store_true",
+                    help="skip the in-medium stream beside the ray stream (grid workload)")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle parity sample and the CPU timing")
     ap.add_argument("--only", default="", help="time only this variant (e.g. stoch_cubic)")
     ap.add_argument("--copy-calibration", action="store_true",

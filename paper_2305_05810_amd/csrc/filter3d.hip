@@ -374,32 +374,49 @@ __global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const 
         int x = (lo[0] + (k & 1)) * 8, y = (lo[1] + ((k >> 1) & 1)) * 8, z = (lo[2] + (k >> 2)) * 8;
         leaf[k] = in_domain(g, x, y, z) ? grid_leaf(g, x, y, z) : -1;
     }
+    bool live = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) live = live || leaf[k] >= 0;
     float acc = 0.0f;
+    if (!live) {
+        // Empty space: every tap reads the background, so the nested sums
+        // below reduce to one row, one plane and one volume sum of it (the
+        // same operations in the same order, so the same binary32 result),
+        // and a wave whose queries are all in empty space skips the taps.
+        float row = 0.0f, plane = 0.0f;
 #pragma unroll
-    for (int cz = 0; cz < NT; ++cz) {
-        int vz = base[2] + cz;
-        bool kz = (vz >> 3) != lo[2];
-        bool okz = (unsigned)vz < (unsigned)g.dz;
-        float plane = 0.0f;
+        for (int cx = 0; cx < NT; ++cx) row = __builtin_fmaf(w[0][cx], g.background, row);
 #pragma unroll
-        for (int cy = 0; cy < NT; ++cy) {
-            int vy = base[1] + cy;
-            bool ky = (vy >> 3) != lo[1];
-            bool oky = okz && (unsigned)vy < (unsigned)g.dy;
-            float row = 0.0f;
+        for (int cy = 0; cy < NT; ++cy) plane = __builtin_fmaf(w[1][cy], row, plane);
 #pragma unroll
-            for (int cx = 0; cx < NT; ++cx) {
-                int vx = base[0] + cx;
-                bool kx = (vx >> 3) != lo[0];
-                int32_t l = pick8(leaf, kx, ky, kz);
-                float v = g.background;
-                if (oky && (unsigned)vx < (unsigned)g.dx && l >= 0)
-                    v = load_texel<FMT>(g.leaves, (int64_t)l * 512 + (((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7)));
-                row = __builtin_fmaf(w[0][cx], v, row);
+        for (int cz = 0; cz < NT; ++cz) acc = __builtin_fmaf(w[2][cz], plane, acc);
+    } else {
+#pragma unroll
+        for (int cz = 0; cz < NT; ++cz) {
+            int vz = base[2] + cz;
+            bool kz = (vz >> 3) != lo[2];
+            bool okz = (unsigned)vz < (unsigned)g.dz;
+            float plane = 0.0f;
+#pragma unroll
+            for (int cy = 0; cy < NT; ++cy) {
+                int vy = base[1] + cy;
+                bool ky = (vy >> 3) != lo[1];
+                bool oky = okz && (unsigned)vy < (unsigned)g.dy;
+                float row = 0.0f;
+#pragma unroll
+                for (int cx = 0; cx < NT; ++cx) {
+                    int vx = base[0] + cx;
+                    bool kx = (vx >> 3) != lo[0];
+                    int32_t l = pick8(leaf, kx, ky, kz);
+                    float v = g.background;
+                    if (oky && (unsigned)vx < (unsigned)g.dx && l >= 0)
+                        v = load_texel<FMT>(g.leaves, (int64_t)l * 512 + (((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7)));
+                    row = __builtin_fmaf(w[0][cx], v, row);
+                }
+                plane = __builtin_fmaf(w[1][cy], row, plane);
             }
-            plane = __builtin_fmaf(w[1][cy], row, plane);
+            acc = __builtin_fmaf(w[2][cz], plane, acc);
         }
-        acc = __builtin_fmaf(w[2][cz], plane, acc);
     }
     constexpr float S3 = axis_scale<KIND>() * axis_scale<KIND>() * axis_scale<KIND>();   // 216, 8 or 5832
     if constexpr (KIND != KIND_LINEAR) acc = acc / S3;   // the three per-axis scale factors

@@ -347,6 +347,34 @@ def ray_queries(dims=(512, 512, 512), n_rays: int = 65536, samples_per_ray: int 
     return np.ascontiguousarray(out)
 
 
+def medium_ray_queries(grid: "SparseGrid", n: int = 1 << 24, seed: int = 4,
+                       samples_per_ray: int = 256) -> np.ndarray:
+    """(n, 3) float32 ray samples as ray_queries makes them (ray-major), kept
+    only where the 4^3 voxel block around the sample (voxels floor(p) - 1 ..
+    floor(p) + 2 per axis) meets a stored leaf: the lookups a renderer makes
+    inside the medium once empty space is skipped.  Rays come in batches of
+    65,536 (seeds seed, seed + 1, ...) until n samples are kept."""
+    nb = [(d + 7) // 8 for d in grid.dims]
+    occ = np.zeros((nb[0] + 2, nb[1] + 2, nb[2] + 2), bool)   # leaf (x, y, z) at [x + 1, y + 1, z + 1]
+    o = grid.origins.astype(np.int64) // 8
+    occ[o[:, 0] + 1, o[:, 1] + 1, o[:, 2] + 1] = True
+    kept, total, k = [], 0, 0
+    while total < n:
+        pts = ray_queries(grid.dims, 65536, samples_per_ray, seed + k)
+        c = np.floor(pts).astype(np.int64) - 1
+        lo = np.clip(c >> 3, -1, np.asarray(nb)) + 1
+        hi = np.clip((c + 3) >> 3, -1, np.asarray(nb)) + 1
+        hit = np.zeros(pts.shape[0], bool)
+        for sx in (lo[:, 0], hi[:, 0]):
+            for sy in (lo[:, 1], hi[:, 1]):
+                for sz in (lo[:, 2], hi[:, 2]):
+                    hit |= occ[sx, sy, sz]
+        kept.append(pts[hit])
+        total += int(hit.sum())
+        k += 1
+    return np.ascontiguousarray(np.concatenate(kept)[:n])
+
+
 def uniform_box_queries(dims, n: int, seed: int = 5, margin: float = 2.0) -> np.ndarray:
     """(n, 3) float32 positions uniform in [-margin, dim - 1 + margin] per
     axis, covering the boundary and the background outside the domain."""
