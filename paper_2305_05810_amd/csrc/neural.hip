@@ -23,6 +23,9 @@
 // v_mfma_f32_32x32x16_bf16 in the transposed form out^T = W in^T, so each
 // layer's accumulator registers are already the next layer's B operand once
 // the hidden units are stored in the order the accumulator layout produces.
+// A wave runs two batches at a time: each of its 64 lanes does the tap
+// choice, latent gather and interpolation of one of the 64 decodes, and a
+// lane-half swap forms both batches' first B operands.
 #include <math.h>
 #include <string.h>
 

@@ -281,3 +281,30 @@ def test_binding_refuses_wrong_buffers(dev, grid):
                                torch.empty(64, dtype=torch.float64, device=dev))
     with pytest.raises(ValueError, match="contiguous"):
         stf.stf_filter(t, q, stf.STF_LINEAR, stf.STF_STOCHASTIC, 0, torch.empty((64, 2), device=dev)[:, :1])
+
+
+# ----------------------------------------------------------------------------
+# neural texture: batches that fill part of a 64-decode pair of MFMA batches
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 3, 31, 33, 65, 1027])
+def test_neural_ragged_batches(dev, n):
+    lat, mlp = synth.neural_init(16, seed=71)
+    nt = stf.stf_ntex_create(64, 64, lat, mlp)
+    stf.stf_ntex_prepare_inference(nt)
+    on = oracle.NeuralTexture(np.asarray(lat, np.float32).astype(np.float16).astype(np.float64), mlp, 64, 64)
+    uv = np.ascontiguousarray(synth.uv_queries(n, seed=72))
+    q = torch.from_numpy(uv).to(dev)
+    for gf, of in ((stf.STF_LINEAR, oracle.LINEAR), (stf.STF_CUBIC_BSPLINE, oracle.CUBIC)):
+        ob, out = _padded(n, 8, torch.float32, dev, FILL)
+        ib, idx = _padded(n, 2, torch.int32, dev, -99)
+        stf.stf_ntex_filter(nt, q, gf, stf.STF_STOCHASTIC, 3, out, idx)
+        ov, oi = on.filter(uv, of, oracle.STOCH, seed=3, emulate=True)
+        assert np.array_equal(idx.cpu().numpy(), oi)
+        assert np.abs(out.cpu().numpy() - ov).max() < 1e-2   # the bf16 inference bar of the neural parity test
+        assert _tail_ok(ob, n, FILL) and _tail_ok(ib, n, -99)
+        ob, out = _padded(n, 8, torch.float32, dev, FILL)
+        stf.stf_ntex_filter(nt, q, gf, stf.STF_DETERMINISTIC, 0, out)
+        od, _ = on.filter(uv, of, oracle.DET, emulate=True)
+        assert np.abs(out.cpu().numpy() - od).max() < 1e-2
+        assert _tail_ok(ob, n, FILL)
+    nt.destroy()
