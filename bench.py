@@ -218,6 +218,19 @@ def run_grid(args, torch, stf, synth):
                               f"{dt:.2f} s in all")
             log(f"cpu oracle: {passes * m / dt / 1e6:.2f} M lookups/s on {threads} threads ({passes} passes, {dt:.1f} s)")
 
+    # the same query stream against an empty grid of the same domain (every
+    # walk ends at the root): the stream-only floor of the stochastic kernel
+    stream_only = None
+    if not args.only and args.order != "morton":
+        empty = stf.stf_create_sparse_grid3d(dims, stf.FORMATS[args.fmt], np.zeros((0, 3), np.int32),
+                                             np.zeros(0, raw.dtype))
+        wall, kern = time_launches(lambda: stf.stf_filter(empty, q, stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, seed, out),
+                                   args.steps, args.warmup, torch)
+        stream_only = variant_stats(n, args.steps, wall, kern, 12 + 4)
+        empty.destroy()
+        log(f"stream only (empty grid): {stream_only['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel "
+            f"{stream_only['kernel_ms_mean'] * 1e3:.1f} us, {stream_only['achieved_gbs']:.0f} GB/s of query + result")
+
     medium = None
     if args.order == "ray" and not args.only and not args.no_medium:
         medium = run_grid_medium(args, torch, stf, synth, grid, tex, raw, out, seed, texel_b)
@@ -248,6 +261,7 @@ def run_grid(args, torch, stf, synth):
             for k in ("keys", "mitchell") if f"stoch_{k}" in res and f"det_{k}" in res},
         "variants": res,
         "in_medium": medium,
+        "stream_only_empty_grid": stream_only,
         "sort": sort_info,
         "parity": parity,
         "hbm_copy_gbs": copy_gbs,

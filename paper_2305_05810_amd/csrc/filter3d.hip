@@ -391,27 +391,49 @@ __global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const 
 #pragma unroll
         for (int cz = 0; cz < NT; ++cz) acc = __builtin_fmaf(w[2][cz], plane, acc);
     } else {
+        // Per axis and tap: which of the two leaves along the axis holds it,
+        // whether it is inside the domain, and its offset within the leaf.
+        bool kx[NT], ky[NT], kz[NT], inx[NT], iny[NT], inz[NT];
+        uint32_t ox[NT], oy[NT], oz[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            const int vx = base[0] + k, vy = base[1] + k, vz = base[2] + k;
+            kx[k] = (vx >> 3) != lo[0];
+            ky[k] = (vy >> 3) != lo[1];
+            kz[k] = (vz >> 3) != lo[2];
+            inx[k] = (unsigned)vx < (unsigned)g.dx;
+            iny[k] = (unsigned)vy < (unsigned)g.dy;
+            inz[k] = (unsigned)vz < (unsigned)g.dz;
+            ox[k] = (uint32_t)(vx & 7);
+            oy[k] = (uint32_t)(vy & 7) * 8u;
+            oz[k] = (uint32_t)(vz & 7) * 64u;
+        }
+        // Every tap loads without a branch: a tap with no stored texel
+        // (empty slot, outside the domain) loads from leaf 0 -- some leaf
+        // exists here -- and takes the background instead.
+        const char* __restrict__ leaves = reinterpret_cast<const char*>(g.leaves);
+        constexpr uint32_t TB = FMT == F32 ? 4u : (FMT == F16 || FMT == BF16 ? 2u : 1u);
 #pragma unroll
         for (int cz = 0; cz < NT; ++cz) {
-            int vz = base[2] + cz;
-            bool kz = (vz >> 3) != lo[2];
-            bool okz = (unsigned)vz < (unsigned)g.dz;
             float plane = 0.0f;
 #pragma unroll
             for (int cy = 0; cy < NT; ++cy) {
-                int vy = base[1] + cy;
-                bool ky = (vy >> 3) != lo[1];
-                bool oky = okz && (unsigned)vy < (unsigned)g.dy;
+                // the row's two leaves (low and high side along x): first
+                // element of the row in each, and whether it holds texels
+                const int32_t la = kz[cz] ? (ky[cy] ? leaf[6] : leaf[4]) : (ky[cy] ? leaf[2] : leaf[0]);
+                const int32_t lb = kz[cz] ? (ky[cy] ? leaf[7] : leaf[5]) : (ky[cy] ? leaf[3] : leaf[1]);
+                const bool ryz = iny[cy] && inz[cz];
+                const bool oka = ryz && la >= 0, okb = ryz && lb >= 0;
+                const uint32_t roff = oz[cz] + oy[cy];
+                const uint32_t ea = oka ? (uint32_t)la * 512u + roff : 0u;
+                const uint32_t eb = okb ? (uint32_t)lb * 512u + roff : 0u;
                 float row = 0.0f;
 #pragma unroll
                 for (int cx = 0; cx < NT; ++cx) {
-                    int vx = base[0] + cx;
-                    bool kx = (vx >> 3) != lo[0];
-                    int32_t l = pick8(leaf, kx, ky, kz);
-                    float v = g.background;
-                    if (oky && (unsigned)vx < (unsigned)g.dx && l >= 0)
-                        v = load_texel<FMT>(g.leaves, (int64_t)l * 512 + (((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7)));
-                    row = __builtin_fmaf(w[0][cx], v, row);
+                    const uint32_t e = (kx[cx] ? eb : ea) + ox[cx];
+                    const bool tap = (kx[cx] ? okb : oka) && inx[cx];
+                    const float v = load_texel<FMT>(leaves + (size_t)(e * TB), 0);
+                    row = __builtin_fmaf(w[0][cx], tap ? v : g.background, row);
                 }
                 plane = __builtin_fmaf(w[1][cy], row, plane);
             }
