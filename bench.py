@@ -221,7 +221,7 @@ def run_grid(args, torch, stf, synth):
     # the same query stream against an empty grid of the same domain (every
     # walk ends at the root): the stream-only floor of the stochastic kernel
     stream_only = None
-    if not args.only and args.order != "morton":
+    if not args.only and args.order != "morton" and not args.no_stream_floor:
         empty = stf.stf_create_sparse_grid3d(dims, stf.FORMATS[args.fmt], np.zeros((0, 3), np.int32),
                                              np.zeros(0, raw.dtype))
         wall, kern = time_launches(lambda: stf.stf_filter(empty, q, stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, seed, out),
@@ -705,6 +705,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the CPU-oracle timing over the sample for at least this long")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle timing")
+    ap.add_argument("--no-stream-floor", action="store_true",
+                    help="skip the stream-only run against an empty grid (grid workload)")
     ap.add_argument("--no-medium", action="store_true",
                     help="skip the in-medium stream beside the ray stream (grid workload)")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle parity sample and the CPU timing")
