@@ -84,12 +84,18 @@ def variant_stats(n, steps, wall, kern, b_alg):
 # ----------------------------------------------------------------------------
 # headline: sparse grid
 # ----------------------------------------------------------------------------
+STREAMS = {"ray": "ray-ordered ray queries", "shuffled": "shuffled ray queries",
+           "morton": "ray queries Morton-sorted by the library (sort timed apart)",
+           "medium": "ray samples inside the medium (taps meet a stored leaf)",
+           "medium-morton": "ray samples inside the medium, Morton-sorted by the library (sort timed apart)"}
+
+
 def run_grid(args, torch, stf, synth):
     dev = torch.device("cuda:0")
     dims = (512, 512, 512)
     t0 = time.time()
     grid = synth.fbm_grid(dims, seed=3)
-    if args.order == "medium":   # ray samples whose taps meet a stored leaf
+    if args.order.startswith("medium"):   # ray samples whose taps meet a stored leaf
         pts = synth.medium_ray_queries(grid, 1 << 24, seed=4)
     else:
         pts = synth.ray_queries(dims, n_rays=65536, samples_per_ray=256, seed=4, shuffle=args.order == "shuffled")
@@ -102,8 +108,8 @@ def run_grid(args, torch, stf, synth):
     out = torch.empty((n, 1), dtype=torch.float32, device=dev)
     sort_info = None
     call = lambda filt, mode, seed_, o, idx=None: stf.stf_filter(tex, q, filt, mode, seed_, o, idx)
-    if args.order == "morton":
-        # the library's Morton sort of the ray-ordered batch, timed on its own;
+    if args.order.endswith("morton"):
+        # the library's Morton sort of the batch, timed on its own;
         # filtering then runs on the sorted stream (results in sorted order)
         sq = torch.empty_like(q)
         order = torch.empty(n, dtype=torch.int32, device=dev)
@@ -160,7 +166,7 @@ def run_grid(args, torch, stf, synth):
                 call(filt, mode, seed, out, idx)
                 gv = out[:, 0].cpu().numpy()
                 gi = idx.cpu().numpy()
-                if args.order == "morton":
+                if args.order.endswith("morton"):
                     inv = np.empty(n, np.int64)
                     inv[order.cpu().numpy()] = np.arange(n)
                     gv, gi = gv[inv], gi[inv]
@@ -177,7 +183,7 @@ def run_grid(args, torch, stf, synth):
                 call(filt, mode, seed, out, idx)
                 gv = out[:, 0].cpu().numpy()
                 gi = idx.cpu().numpy()
-                if args.order == "morton":   # back to the caller's order
+                if args.order.endswith("morton"):   # back to the caller's order
                     inv = np.empty(n, np.int64)
                     inv[order.cpu().numpy()] = np.arange(n)
                     gv, gi = gv[inv], gi[inv]
@@ -188,7 +194,7 @@ def run_grid(args, torch, stf, synth):
             else:
                 call(filt, mode, seed, out)
                 gv = out[:, 0].cpu().numpy()
-                if args.order == "morton":
+                if args.order.endswith("morton"):
                     inv = np.empty(n, np.int64)
                     inv[order.cpu().numpy()] = np.arange(n)
                     gv = gv[inv]
@@ -221,7 +227,7 @@ def run_grid(args, torch, stf, synth):
     # the same query stream against an empty grid of the same domain (every
     # walk ends at the root): the stream-only floor of the stochastic kernel
     stream_only = None
-    if not args.only and args.order != "morton" and not args.no_stream_floor:
+    if not args.only and not args.order.endswith("morton") and not args.no_stream_floor:
         empty = stf.stf_create_sparse_grid3d(dims, stf.FORMATS[args.fmt], np.zeros((0, 3), np.int32),
                                              np.zeros(0, raw.dtype))
         wall, kern = time_launches(lambda: stf.stf_filter(empty, q, stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, seed, out),
@@ -248,7 +254,7 @@ def run_grid(args, torch, stf, synth):
     line = base_line(args, head["lookups_per_s"], "lookups/s", head["ms_per_step"], args.fmt,
                      {"workload": f"sparse fBm voxel grid 512^3 of dense 8^3 {args.fmt} leaves "
                                   f"({grid.n_leaves} leaves), {n} "
-                                  f"{'ray samples inside the medium' if args.order == 'medium' else args.order + '-ordered ray queries'}, "
+                                  f"{STREAMS[args.order]}, "
                                   f"stochastic tricubic B-spline (deterministic 64-tap beside it)",
                       "n_queries": n, "n_leaves": grid.n_leaves, "order": args.order})
     line.update({
@@ -397,6 +403,24 @@ def run_dct(args, torch, stf, synth):
         res[name]["decodes_per_lookup"] = decodes
         log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel "
             f"{res[name]['kernel_ms_mean'] * 1e3:.1f} us")
+    # the frame Morton-sorted by the library (sort timed apart): deterministic
+    # bicubic blocks then decode each texel of their taps once into LDS
+    sq = torch.empty_like(q)
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = torch.empty(stf.stf_sort_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    wall, _ = time_launches(lambda: stf.stf_sort_queries(tex, q, sq, order, ws), args.steps, args.warmup, torch)
+    sort_ms = 1e3 * wall / args.steps
+    log(f"morton sort of the frame: {sort_ms:.3f} ms")
+    for name, filt, mode, taps in (("stoch_cubic_sorted", stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 16),
+                                   ("det_cubic_sorted", stf.STF_CUBIC_BSPLINE, stf.STF_DETERMINISTIC, 16)):
+        decodes = 1 if mode == stf.STF_STOCHASTIC else taps
+        wall, kern = time_launches(lambda: stf.stf_filter_ordered(tex, sq, order, filt, mode, 11, out),
+                                   args.steps, args.warmup, torch)
+        res[name] = variant_stats(n, args.steps, wall, kern, 8 + 4 * C + decodes * block_b)
+        res[name]["decodes_per_lookup"] = decodes
+        log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel "
+            f"{res[name]['kernel_ms_mean'] * 1e3:.1f} us")
+    del sq, order, ws
     # quality of the compression: bilinear at texel centres returns decoded texels
     js, is_ = np.meshgrid(np.arange(size), np.arange(size), indexing="ij")
     cen = np.stack([(is_ + 0.5) / size, (js + 0.5) / size], axis=-1).reshape(-1, 2).astype(np.float32)
@@ -414,6 +438,9 @@ def run_dct(args, torch, stf, synth):
                  "stochastic_over_deterministic": head["lookups_per_s"] / res["det_linear"]["lookups_per_s"],
                  "bicubic_stochastic_over_deterministic":
                      res["stoch_cubic"]["lookups_per_s"] / res["det_cubic"]["lookups_per_s"],
+                 "sorted_bicubic_stochastic_over_deterministic":
+                     res["stoch_cubic_sorted"]["lookups_per_s"] / res["det_cubic_sorted"]["lookups_per_s"],
+                 "sort_ms": sort_ms,
                  "compression": {"block_bytes": stf.stf_texture_bytes(tex), "u8_bytes": int(tex_np.nbytes),
                                  "psnr_db": 10 * np.log10(1.0 / mse)},
                  "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -698,9 +725,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grid", choices=["grid", "tex2d", "shade", "neural", "serving", "dct", "gauss", "ewa"])
     ap.add_argument("--fmt", default="f32", choices=["f32", "f16", "bf16", "fp8_e4m3"])
-    ap.add_argument("--order", default="ray", choices=["ray", "shuffled", "morton", "medium"],
-                    help="grid query stream: ray samples in ray order, shuffled, Morton-sorted, or only the ray "
-                         "samples whose taps meet a stored leaf (inside the medium)")
+    ap.add_argument("--order", default="ray", choices=list(STREAMS),
+                    help="grid query stream: ray samples in ray order, shuffled or Morton-sorted by the library, "
+                         "or only the ray samples whose taps meet a stored leaf (inside the medium), as they come "
+                         "or Morton-sorted")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="queries in the CPU-oracle timing sample")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the CPU-oracle timing over the sample for at least this long")

@@ -291,7 +291,9 @@ stf_status stf_sort_queries(const stf_texture* tex, const float* queries_dev, in
  * order_dev[k] of the caller's batch and draws its random numbers as that
  * query.  Results go to out[k] (sorted order), or to out[order_dev[k]] with
  * STF_ORDER_SCATTER, where they equal stf_filter's on the unsorted batch
- * bit for bit. */
+ * bit for bit.  Deterministic bicubic / tricubic filtering of a sorted
+ * stream of a 3D grid or a DCT texture reads the texels its neighbouring
+ * queries share once per block (staged in LDS) where that pays. */
 stf_status stf_filter_ordered(const stf_texture* tex, const float* sorted_queries_dev,
                               const int32_t* order_dev, int64_t n, stf_filter_kind filter,
                               stf_mode mode, uint64_t seed, float* out_dev, int32_t* out_index_dev,

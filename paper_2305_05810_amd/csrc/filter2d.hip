@@ -14,6 +14,7 @@
 //
 // Raster position: x = uv.x * W - 0.5 (texel centres at half-integers of
 // uv * W); taps are clamped to the texture.
+#include <limits.h>
 #include <math.h>
 
 #include "dct_decode.h"
@@ -53,6 +54,7 @@ __device__ __forceinline__ void load_rgba(const TexLevel& L, int x, int y, float
 template <int FMT, int C>
 struct DenseSrc {
     static constexpr int CAP = C;
+    static constexpr bool DECODES = false;   // a texel is a plain load
     TexLevel L;
     __device__ int w() const { return L.w; }
     __device__ int h() const { return L.h; }
@@ -64,6 +66,7 @@ struct DenseSrc {
 template <int CAP_>
 struct DctSrc {
     static constexpr int CAP = CAP_;
+    static constexpr bool DECODES = true;   // a texel costs an inverse DCT per channel
     const uint32_t* blocks;
     int32_t W, H, BW, C;
     __device__ int w() const { return W; }
@@ -101,15 +104,14 @@ __device__ __forceinline__ void store_channels(const Src& S, float* __restrict__
 // with STF_ORDER_SCATTER) are stored directly.  Every thread of the block
 // must call this (it synchronises the block).
 template <class Src>
-__device__ __forceinline__ void block_store(const Src& S, float* __restrict__ out, int32_t n, bool live, int64_t oi,
-                                            const float (&v)[Src::CAP], bool scattered)
+__device__ __forceinline__ void block_store_via(const Src& S, float* __restrict__ out, int32_t n, bool live, int64_t oi,
+                                                const float (&v)[Src::CAP], bool scattered, float* stage)
 {
     const int C = S.channels();
     if (scattered) {
         if (live) store_channels(S, out, oi, v);
         return;
     }
-    __shared__ __align__(16) float stage[BLOCK * Src::CAP];
 #pragma unroll
     for (int c = 0; c < Src::CAP; ++c)
         if (c < C) stage[threadIdx.x * C + c] = v[c];
@@ -126,6 +128,15 @@ __device__ __forceinline__ void block_store(const Src& S, float* __restrict__ ou
         k0 = n4 << 2;
     }
     for (int k = k0 + threadIdx.x; k < total; k += BLOCK) dst[k] = stage[k];
+}
+
+// block_store_via with LDS of its own (BLOCK * CAP floats, 16-byte aligned).
+template <class Src>
+__device__ __forceinline__ void block_store(const Src& S, float* __restrict__ out, int32_t n, bool live, int64_t oi,
+                                            const float (&v)[Src::CAP], bool scattered)
+{
+    __shared__ __align__(16) float stage[BLOCK * Src::CAP];
+    block_store_via(S, out, n, live, oi, v, scattered, stage);
 }
 
 // Query i of a batch (i valid), drawn with id qid0 + i (or order[i]): its
@@ -307,6 +318,122 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_deterministic(Src S, const floa
 #pragma unroll
     for (int c = 0; c < CAP; ++c) acc[c] = !ok ? __builtin_nanf("") : (KIND == KIND_LINEAR ? acc[c] : acc[c] / S2);
     block_store(S, out, n, live, oi, acc, order && scatter);
+}
+
+// Deterministic bicubic filtering of a Morton-sorted stream (neighbouring
+// queries close in the texture) of a source whose texels cost a decode.  The block decodes every texel of the bounding
+// box of its queries' clamped taps once into LDS and filters each query from
+// there; a block whose box exceeds STAGE_FLOATS values, or whose queries
+// would read fewer than STAGE_REUSE taps per decoded texel, decodes per tap
+// like k_tex2d_deterministic.  Both paths see the same decoded values and sum
+// them in the same order, so the results are the same.
+constexpr int STAGE_FLOATS = 8192;   // 32 KiB per block
+constexpr int STAGE_REUSE = 4;
+
+__device__ __forceinline__ int block_reduce_min(int v, int* red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = v;
+    __syncthreads();
+    int r = red[0];
+#pragma unroll
+    for (int k = 1; k < BLOCK / 64; ++k) r = min(r, red[k]);
+    __syncthreads();
+    return r;
+}
+
+template <class Src, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_tex2d_det_staged(Src S, const float* __restrict__ q, int32_t n,
+                                                            float* __restrict__ out, const int32_t* __restrict__ order,
+                                                            int scatter)
+{
+    constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
+    constexpr int CAP = Src::CAP;
+    static_assert(BLOCK * CAP <= STAGE_FLOATS, "the tile also stages the block's results");
+    __shared__ __align__(16) float tile[STAGE_FLOATS];
+    __shared__ int red[BLOCK / 64];
+    const int32_t i0 = blockIdx.x * BLOCK + threadIdx.x;
+    const bool live = i0 < n;
+    const int32_t i = live ? i0 : 0;
+    const int64_t oi = (order && scatter) ? (int64_t)order[i] : (int64_t)i;
+    float2 uv = reinterpret_cast<const float2*>(q)[i];
+    float x = uv.x * (float)S.w() - 0.5f;
+    float y = uv.y * (float)S.h() - 0.5f;
+    int cx = 0, cy = 0;
+    float tx = 0.0f, ty = 0.0f;
+    const bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
+    float wx[4], wy[4];
+    cx += axis_weights_scaled<KIND>(tx, wx);
+    cy += axis_weights_scaled<KIND>(ty, wy);
+    // box of the clamped taps of the block's queries (clamping is monotone)
+    const bool in = live && ok;
+    const int W1 = S.w() - 1, H1 = S.h() - 1;
+    const int x0 = block_reduce_min(in ? clampi(cx, W1) : INT_MAX, red);
+    const int x1 = -block_reduce_min(in ? -clampi(cx + NT - 1, W1) : INT_MAX, red);
+    const int y0 = block_reduce_min(in ? clampi(cy, H1) : INT_MAX, red);
+    const int y1 = -block_reduce_min(in ? -clampi(cy + NT - 1, H1) : INT_MAX, red);
+    const int nin = __syncthreads_count(in);
+    const int C = S.channels();
+    const int ew = nin ? x1 - x0 + 1 : 0, eh = nin ? y1 - y0 + 1 : 0;   // both within the texture
+    const int64_t ntex = (int64_t)ew * eh;
+    float acc[CAP];
+#pragma unroll
+    for (int c = 0; c < CAP; ++c) acc[c] = 0.0f;
+    if (nin && ntex * C <= STAGE_FLOATS && ntex * STAGE_REUSE <= (int64_t)nin * NT * NT) {
+        for (int t = threadIdx.x; t < (int)ntex; t += BLOCK) {
+            float v[CAP];
+            S.load(x0 + t % ew, y0 + t / ew, v);
+#pragma unroll
+            for (int c = 0; c < CAP; ++c)
+                if (c < C) tile[t * C + c] = v[c];
+        }
+        __syncthreads();
+        // tap offsets in the box (a query without a cell reads texel 0)
+        int ix[NT];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) ix[a] = in ? (clampi(cx + a, W1) - x0) * C : 0;
+        // wide sources keep one row of taps in registers at a time
+        constexpr int ROWS = CAP > 4 ? 1 : NT;
+#pragma unroll ROWS
+        for (int b = 0; b < NT; ++b) {
+            const int iy = in ? (clampi(cy + b, H1) - y0) * ew * C : 0;
+            float row[CAP];
+#pragma unroll
+            for (int c = 0; c < CAP; ++c) row[c] = 0.0f;
+#pragma unroll
+            for (int a = 0; a < NT; ++a) {
+                const float* e = tile + iy + ix[a];
+#pragma unroll
+                for (int c = 0; c < CAP; ++c) row[c] = __builtin_fmaf(wx[a], c < C ? e[c] : 0.0f, row[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < CAP; ++c) acc[c] = __builtin_fmaf(wy[b], row[c], acc[c]);
+        }
+    } else {
+        constexpr int ROWS_UNROLLED = CAP > 4 ? 1 : NT;
+#pragma unroll ROWS_UNROLLED
+        for (int b = 0; b < NT; ++b) {
+            int yy = clampi(cy + b, H1);
+            float row[CAP];
+#pragma unroll
+            for (int c = 0; c < CAP; ++c) row[c] = 0.0f;
+#pragma unroll
+            for (int a = 0; a < NT; ++a) {
+                float v[CAP];
+                S.load(clampi(cx + a, W1), yy, v);
+#pragma unroll
+                for (int c = 0; c < CAP; ++c) row[c] = __builtin_fmaf(wx[a], v[c], row[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < CAP; ++c) acc[c] = __builtin_fmaf(wy[b], row[c], acc[c]);
+        }
+    }
+    constexpr float S2 = axis_scale<KIND>() * axis_scale<KIND>();
+#pragma unroll
+    for (int c = 0; c < CAP; ++c) acc[c] = !ok ? __builtin_nanf("") : (KIND == KIND_LINEAR ? acc[c] : acc[c] / S2);
+    __syncthreads();   // every thread is done with the tile: it now stages the results
+    block_store_via(S, out, n, live, oi, acc, order && scatter, tile);
 }
 
 // channel-0 moments of the stochastic estimator over many seeds
@@ -548,6 +675,13 @@ void launch2d_kind(const Src& S, const float* q, int32_t n, int mode, uint32_t k
             hipLaunchKernelGGL((k_tex2d_stochastic<Src, KIND == KIND_BSPLINE, true>), grid, block, 0, stream, S, q, n,
                                key, out, idx, order, scatter);
     } else {
+        if constexpr (Src::DECODES && KIND != KIND_LINEAR) {
+            if (order) {   // a sorted stream of a decoded source: the 16 taps of neighbours share decodes
+                hipLaunchKernelGGL((k_tex2d_det_staged<Src, KIND>), grid, block, 0, stream, S, q, n, out, order,
+                                   scatter);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_tex2d_deterministic<Src, KIND>), grid, block, 0, stream, S, q, n, out, order, scatter);
     }
 }

@@ -10,6 +10,7 @@
 // Grid walk: root slot (128^3 voxels) -> internal node child (8^3 voxels) ->
 // dense 8^3 leaf, x fastest.  Voxels outside the domain or in empty slots read
 // as the grid's background value.
+#include <limits.h>
 #include <math.h>
 
 #include "device_common.h"
@@ -346,28 +347,15 @@ __device__ __forceinline__ int32_t pick8(const int32_t (&l)[8], bool kx, bool ky
     return kz ? f : e;
 }
 
+// The unscaled sum over the NT^3 taps starting at voxel base, from global
+// memory (weights scaled by axis_scale per axis).
 template <int FMT, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const float* __restrict__ q, int32_t n,
-                                                              float* __restrict__ out, const int32_t* __restrict__ order,
-                                                              int scatter)
+__device__ __forceinline__ float det_sum_global(const GridView& g, const int (&base)[3], const float (&w)[3][4])
 {
     constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
-    int32_t i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= n) return;
-    float p[3] = {q[3 * (int64_t)i], q[3 * (int64_t)i + 1], q[3 * (int64_t)i + 2]};
-    int c[3];
-    float t[3];
-    bool ok = cell_of(p[0], c[0], t[0]) & cell_of(p[1], c[1], t[1]) & cell_of(p[2], c[2], t[2]);
-    if (!ok) {
-        out[(order && scatter) ? order[i] : i] = __builtin_nanf("");
-        return;
-    }
-    float w[3][4];
-    int base[3], lo[3];
-    for (int a = 0; a < 3; ++a) {
-        base[a] = c[a] + axis_weights_scaled<KIND>(t[a], w[a]);
-        lo[a] = base[a] >> 3;   // leaf coordinate of the first tap (floor for negatives)
-    }
+    int lo[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lo[a] = base[a] >> 3;   // leaf coordinate of the first tap (floor for negatives)
     int32_t leaf[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -440,9 +428,208 @@ __global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const 
             acc = __builtin_fmaf(w[2][cz], plane, acc);
         }
     }
-    constexpr float S3 = axis_scale<KIND>() * axis_scale<KIND>() * axis_scale<KIND>();   // 216, 8 or 5832
-    if constexpr (KIND != KIND_LINEAR) acc = acc / S3;   // the three per-axis scale factors
-    out[(order && scatter) ? order[i] : i] = acc;
+    return acc;
+}
+
+// Cell, first tap and scaled per-axis weights of a query; false if the
+// position has no cell (R10: non-finite or too large).
+template <int KIND>
+__device__ __forceinline__ bool det_setup(const float (&p)[3], int (&base)[3], float (&w)[3][4])
+{
+    int c[3];
+    float t[3];
+    const bool ok = cell_of(p[0], c[0], t[0]) & cell_of(p[1], c[1], t[1]) & cell_of(p[2], c[2], t[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) base[a] = c[a] + axis_weights_scaled<KIND>(t[a], w[a]);
+    return ok;
+}
+
+// The three per-axis scale factors (216, 8 or 5832) divided out.
+template <int KIND>
+__device__ __forceinline__ float det_unscale(float acc)
+{
+    constexpr float S3 = axis_scale<KIND>() * axis_scale<KIND>() * axis_scale<KIND>();
+    if constexpr (KIND != KIND_LINEAR) acc = acc / S3;
+    return acc;
+}
+
+template <int FMT, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const float* __restrict__ q, int32_t n,
+                                                              float* __restrict__ out, const int32_t* __restrict__ order,
+                                                              int scatter)
+{
+    int32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const float p[3] = {q[3 * (int64_t)i], q[3 * (int64_t)i + 1], q[3 * (int64_t)i + 2]};
+    int base[3];
+    float w[3][4];
+    const bool ok = det_setup<KIND>(p, base, w);
+    out[(order && scatter) ? order[i] : i] = ok ? det_unscale<KIND>(det_sum_global<FMT, KIND>(g, base, w))
+                                                : __builtin_nanf("");
+}
+
+// ---------------------------------------------------------------------------
+// deterministic filtering of a sorted stream with the block's taps staged in
+// LDS.  Queries that are neighbours in Morton order share most of their tap
+// blocks, so a block reads every voxel of the bounding box of its queries'
+// tap blocks once and then filters each query from LDS: the box's leaf slots
+// are resolved first (one walk per slot), then each voxel is one load.  A
+// block stages only when that pays: the box holds at most STAGE_VOXELS
+// voxels in at most STAGE_SLOTS leaf slots, its queries read at least
+// STAGE_REUSE taps per staged voxel, and some slot holds a leaf; otherwise it
+// filters from global memory (where all-empty tap blocks cost no loads).
+// Both paths read the same texel values and sum them in the same order, so
+// the results are the same.
+// ---------------------------------------------------------------------------
+constexpr int STAGE_VOXELS = 4096;   // 16 KiB of binary32 per block
+constexpr int STAGE_SLOTS = 64;
+constexpr int STAGE_REUSE = 4;
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <int FMT, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_grid_det_staged(GridView g, const float* __restrict__ q, int32_t n,
+                                                           float* __restrict__ out, const int32_t* __restrict__ order,
+                                                           int scatter)
+{
+    constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
+    __shared__ float tile[STAGE_VOXELS];
+    __shared__ int32_t slot_leaf[STAGE_SLOTS];
+    __shared__ int box[6][BLOCK / 64];
+    const int32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    const bool live = i < n;
+    float p[3] = {0.0f, 0.0f, 0.0f};
+    if (live) {
+        p[0] = q[3 * (int64_t)i];
+        p[1] = q[3 * (int64_t)i + 1];
+        p[2] = q[3 * (int64_t)i + 2];
+    }
+    int base[3];
+    float w[3][4];
+    const bool ok = live && det_setup<KIND>(p, base, w);
+    // bounding box of the block's tap blocks (queries with a cell only)
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int mn = wave_min(ok ? base[a] : INT_MAX), mx = wave_max(ok ? base[a] + NT - 1 : INT_MIN);
+        if (lane == 0) {
+            box[a][wave] = mn;
+            box[3 + a][wave] = mx;
+        }
+    }
+    const int nok = __syncthreads_count(ok);
+    int lo[3], ext[3], l0[3], nl[3];
+    bool fits = nok > 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int mn = box[a][0], mx = box[3 + a][0];
+#pragma unroll
+        for (int k = 1; k < BLOCK / 64; ++k) {
+            mn = min(mn, box[a][k]);
+            mx = max(mx, box[3 + a][k]);
+        }
+        lo[a] = mn;
+        ext[a] = fits ? mx - mn + 1 : 0;   // at most 2^25 + 4: coordinates with a cell are below 2^24
+        l0[a] = mn >> 3;
+        nl[a] = fits ? (mx >> 3) - l0[a] + 1 : 0;
+        fits = fits && ext[a] <= STAGE_VOXELS && nl[a] <= STAGE_SLOTS;
+    }
+    const int64_t vol = (int64_t)ext[0] * ext[1] * ext[2];
+    const int nslot = nl[0] * nl[1] * nl[2];
+    // the same decision in every thread of the block
+    bool stage = fits && vol <= STAGE_VOXELS && nslot <= STAGE_SLOTS &&
+                 vol * STAGE_REUSE <= (int64_t)nok * NT * NT * NT;
+    bool taps = false;   // this query's tap block meets a stored leaf
+    if (stage) {
+        if ((int)threadIdx.x < nslot) {
+            const int sx = l0[0] + (int)threadIdx.x % nl[0], sy = l0[1] + ((int)threadIdx.x / nl[0]) % nl[1],
+                      sz = l0[2] + (int)threadIdx.x / (nl[0] * nl[1]);
+            slot_leaf[threadIdx.x] = in_domain(g, sx * 8, sy * 8, sz * 8) ? grid_leaf(g, sx * 8, sy * 8, sz * 8) : -1;
+        }
+        __syncthreads();
+        if (ok) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int sx = ((base[0] + ((k & 1) ? NT - 1 : 0)) >> 3) - l0[0];
+                const int sy = ((base[1] + ((k & 2) ? NT - 1 : 0)) >> 3) - l0[1];
+                const int sz = ((base[2] + ((k & 4) ? NT - 1 : 0)) >> 3) - l0[2];
+                taps = taps || slot_leaf[(sz * nl[1] + sy) * nl[0] + sx] >= 0;
+            }
+        }
+        // staging pays only for the queries that read texels; the others
+        // (empty space) sum the background either way
+        stage = (int64_t)__syncthreads_count(taps) * NT * NT * NT >= vol * STAGE_REUSE;
+    }
+    if (stage) {
+        // voxel v = threadIdx.x + k BLOCK of the box, x fastest; its
+        // coordinates advance by those of BLOCK (one carry per axis at most)
+        const int e01 = ext[0] * ext[1];
+        const int sx = BLOCK % ext[0], sy = (BLOCK / ext[0]) % ext[1], sz = BLOCK / e01;
+        int x = (int)threadIdx.x % ext[0], y = ((int)threadIdx.x / ext[0]) % ext[1], z = (int)threadIdx.x / e01;
+        for (int v = threadIdx.x; v < (int)vol; v += BLOCK) {
+            const int vx = lo[0] + x, vy = lo[1] + y, vz = lo[2] + z;
+            const int32_t lf = slot_leaf[((vz >> 3) - l0[2]) * nl[1] * nl[0] + ((vy >> 3) - l0[1]) * nl[0] +
+                                         (vx >> 3) - l0[0]];
+            tile[v] = (lf >= 0 && in_domain(g, vx, vy, vz))
+                          ? load_texel<FMT>(g.leaves, (int64_t)lf * 512 + (((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7)))
+                          : g.background;
+            x += sx;
+            y += sy;
+            z += sz;
+            if (x >= ext[0]) {
+                x -= ext[0];
+                ++y;
+            }
+            if (y >= ext[1]) {
+                y -= ext[1];
+                ++z;
+            }
+        }
+        __syncthreads();
+        if (!live) return;
+        float acc = 0.0f;
+        if (ok && !taps) {   // empty space: the background sums of det_sum_global
+            float row = 0.0f, plane = 0.0f;
+#pragma unroll
+            for (int cx = 0; cx < NT; ++cx) row = __builtin_fmaf(w[0][cx], g.background, row);
+#pragma unroll
+            for (int cy = 0; cy < NT; ++cy) plane = __builtin_fmaf(w[1][cy], row, plane);
+#pragma unroll
+            for (int cz = 0; cz < NT; ++cz) acc = __builtin_fmaf(w[2][cz], plane, acc);
+        } else if (ok) {
+#pragma unroll
+            for (int cz = 0; cz < NT; ++cz) {
+                float plane = 0.0f;
+#pragma unroll
+                for (int cy = 0; cy < NT; ++cy) {
+                    const float* r = tile + ((base[2] + cz - lo[2]) * ext[1] + (base[1] + cy - lo[1])) * ext[0] +
+                                     (base[0] - lo[0]);
+                    float row = 0.0f;
+#pragma unroll
+                    for (int cx = 0; cx < NT; ++cx) row = __builtin_fmaf(w[0][cx], r[cx], row);
+                    plane = __builtin_fmaf(w[1][cy], row, plane);
+                }
+                acc = __builtin_fmaf(w[2][cz], plane, acc);
+            }
+        }
+        out[(order && scatter) ? order[i] : i] = ok ? det_unscale<KIND>(acc) : __builtin_nanf("");
+    } else {
+        if (!live) return;
+        out[(order && scatter) ? order[i] : i] = ok ? det_unscale<KIND>(det_sum_global<FMT, KIND>(g, base, w))
+                                                    : __builtin_nanf("");
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -531,7 +718,10 @@ void launch3d_kind(const GridView& g, const float* q, int32_t n, int mode, uint3
         }
     } else {
         dim3 grid((n + BLOCK - 1) / BLOCK);
-        hipLaunchKernelGGL((k_grid_deterministic<FMT, KIND>), grid, block, 0, stream, g, q, n, out, order, scatter);
+        if (order && KIND != KIND_LINEAR)   // a sorted stream: neighbouring queries share their 64 taps
+            hipLaunchKernelGGL((k_grid_det_staged<FMT, KIND>), grid, block, 0, stream, g, q, n, out, order, scatter);
+        else
+            hipLaunchKernelGGL((k_grid_deterministic<FMT, KIND>), grid, block, 0, stream, g, q, n, out, order, scatter);
     }
 }
 

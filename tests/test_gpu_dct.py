@@ -137,3 +137,28 @@ def test_dct_ordered_stream_and_errors(dev):
     rgb = torch.empty((4, 3), dtype=torch.float32, device=dev)
     assert L.stf_shade_filter(t.handle, sq9.data_ptr(), 4, 1, 0, 0, rgb.data_ptr(), None, None) == stf.STF_E_INVALID
     t.destroy()
+
+
+@pytest.mark.parametrize("fname,gf,of", FILTERS)
+@pytest.mark.parametrize("W,H,C", [(96, 80, 9), (64, 48, 16)])
+def test_dct_sorted_stream_staged_decode(dev, fname, gf, of, W, H, C):
+    """A Morton-sorted stream: deterministic bicubic blocks decode the texels
+    of their taps once into LDS (blocks whose taps span too many texels decode
+    per tap).  Values within the bar of the oracle, and bit for bit those of
+    the unsorted call (which decodes per tap)."""
+    tex = _texture(H, W, C, seed=W + 7)
+    words = stf.stf_dct_encode(tex)
+    t = stf.stf_create_dct_texture2d(W, H, C, words)
+    uv = synth.uv_queries(30000, seed=W) * np.float32(1.1) - np.float32(0.05)
+    q = torch.from_numpy(uv).to(dev)
+    ref, _ = stf.filter(t, q, gf, stf.STF_DETERMINISTIC, 0)
+    sq, order = stf.sort_queries(t, q)
+    out = torch.empty_like(ref)
+    stf.stf_filter_ordered(t, sq, order, gf, stf.STF_DETERMINISTIC, 0, out, None, stf.STF_ORDER_SCATTER)
+    assert torch.equal(out.nan_to_num(-7), ref.nan_to_num(-7)), fname
+    gd = out.cpu().numpy().astype(np.float64)
+    od, _ = oracle.dct_filter2d(words, uv, of, oracle.DET)
+    A = _abs_terms(words).astype(np.float32)
+    dscale, _ = oracle.filter2d(A, oracle.F32, uv, of, oracle.DET_ABS)
+    assert np.all((np.isnan(gd) & np.isnan(od)) | (np.abs(gd - od) <= REL * dscale)), fname
+    t.destroy()

@@ -58,7 +58,7 @@ def test_grid_sort_and_ordered_filter(dev, grid_case):
     o = order.cpu().numpy()
     _check_order(_keys3d(p), o, p.shape[0])
     assert np.array_equal(np.nan_to_num(sq.cpu().numpy(), nan=-9), np.nan_to_num(p[o], nan=-9))
-    for filt in (stf.STF_LINEAR, stf.STF_CUBIC_BSPLINE):
+    for filt in (stf.STF_LINEAR, stf.STF_CUBIC_BSPLINE, stf.STF_CUBIC_KEYS):
         ref, ridx = stf.filter(tex, q, filt, stf.STF_STOCHASTIC, 11, want_index=True)
         out = torch.empty_like(ref)
         idx = torch.empty_like(ridx)
@@ -66,7 +66,30 @@ def test_grid_sort_and_ordered_filter(dev, grid_case):
         assert torch.equal(idx, ridx) and torch.equal(out.nan_to_num(-7), ref.nan_to_num(-7))
         stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_STOCHASTIC, 11, out, idx, 0)
         assert torch.equal(out.nan_to_num(-7), ref[order.long()].nan_to_num(-7))
+        # deterministic: sorted blocks are filtered from their taps staged in
+        # LDS (blocks whose taps span too wide a box read global memory);
+        # both give the unsorted call's values bit for bit
         dref, _ = stf.filter(tex, q, filt, stf.STF_DETERMINISTIC, 0)
+        stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_DETERMINISTIC, 0, out, None, stf.STF_ORDER_SCATTER)
+        assert torch.equal(out.nan_to_num(-7), dref.nan_to_num(-7))
+        stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_DETERMINISTIC, 0, out, None, 0)
+        assert torch.equal(out.nan_to_num(-7), dref[order.long()].nan_to_num(-7))
+    tex.destroy()
+
+
+@pytest.mark.parametrize("fmt", ["f16", "fp8_e4m3"])
+def test_grid_staged_deterministic_formats_and_background(dev, fmt):
+    # a domain that is not a multiple of 8, leaves sticking out of it and a
+    # non-zero background: staged taps outside the domain read the background
+    g = synth.fbm_grid((40, 48, 56), base_period=12.0, seed=9)
+    raw = g.encoded(fmt)
+    tex = stf.stf_create_sparse_grid3d((37, 45, 51), stf.FORMATS[fmt], g.origins, raw, background=0.25)
+    p = synth.uniform_box_queries((37, 45, 51), 30000, seed=10, margin=2.5)
+    q = torch.from_numpy(p).to(dev)
+    sq, order = stf.sort_queries(tex, q)
+    for filt in (stf.STF_LINEAR, stf.STF_CUBIC_BSPLINE, stf.STF_CUBIC_MITCHELL):
+        dref, _ = stf.filter(tex, q, filt, stf.STF_DETERMINISTIC, 0)
+        out = torch.empty_like(dref)
         stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_DETERMINISTIC, 0, out, None, stf.STF_ORDER_SCATTER)
         assert torch.equal(out.nan_to_num(-7), dref.nan_to_num(-7))
     tex.destroy()
