@@ -40,6 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # grid, ray order), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain
 # copy; to be re-measured (and set to None) whenever that kernel changes.
 HEADLINE_TRAFFIC_BYTES = {("f32", "ray"): 389.1e6}
+# the same for the DCT workload's stochastic bilinear kernel over the 4K frame
+# (uv in, 9 results out; the 12.6 MB of blocks mostly cache-resident)
+DCT_STOCH_LINEAR_TRAFFIC_BYTES = 412.7e6
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 METRIC = "filtered lookups/s, stochastic vs deterministic tricubic, at stated error; p99 batch latency"
@@ -444,7 +447,7 @@ def run_dct(args, torch, stf, synth):
                  "compression": {"block_bytes": stf.stf_texture_bytes(tex), "u8_bytes": int(tex_np.nbytes),
                                  "psnr_db": 10 * np.log10(1.0 / mse)},
                  "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
+                              "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": DCT_STOCH_LINEAR_TRAFFIC_BYTES},
                  "cpu_baseline": None})
     tex.destroy()
     return line
