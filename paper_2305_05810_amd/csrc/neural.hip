@@ -293,10 +293,25 @@ __global__ void k_fill(float* __restrict__ p, int64_t n, float v)
     if (e < n) p[e] = v;
 }
 
-__global__ void k_to_f16(const float* __restrict__ src, uint16_t* __restrict__ dst, int64_t n)
+// Corner quads for inference: entry (y0 + 1, x0 + 1) for every cell
+// x0 = -1 .. LW - 1, y0 = -1 .. LH - 1 holds the binary16 latents of its
+// clamped corners (x0, y0), (x0 + 1, y0), (x0, y0 + 1), (x0 + 1, y0 + 1), so a
+// decode reads one 64-byte quad instead of two rows of the grid.
+__global__ void k_to_quads(const float* __restrict__ lat, uint16_t* __restrict__ quad, int32_t LW, int32_t LH)
 {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) dst[e] = __builtin_bit_cast(uint16_t, (_Float16)src[e]);
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)(LW + 1) * (LH + 1)) return;
+    const int x0 = (int)(e % (LW + 1)) - 1, y0 = (int)(e / (LW + 1)) - 1;
+    const int xs[2] = {clampi(x0, LW - 1), clampi(x0 + 1, LW - 1)};
+    const int ys[2] = {clampi(y0, LH - 1), clampi(y0 + 1, LH - 1)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float* src = lat + ((int64_t)ys[k / 2] * LW + xs[k % 2]) * NL;
+        uint16_t h[NL];
+#pragma unroll
+        for (int c = 0; c < NL; ++c) h[c] = __builtin_bit_cast(uint16_t, (_Float16)src[c]);
+        reinterpret_cast<uint4*>(quad)[4 * e + k] = __builtin_bit_cast(uint4, h);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -335,7 +350,7 @@ static_assert(row_of_acc(0, 0, 0) == 0 && row_of_acc(0, 1, 3) == 7,
 
 struct InferArgs {
     const Packed* pk;
-    const uint16_t* lat16;   // LH x LW x 8 binary16
+    const uint16_t* quad16;   // (LH + 1) x (LW + 1) corner quads, 4 x 8 binary16 each
     const float* q;          // n x 2 uv
     int32_t n, W, H, LW, LH;
     float rx, ry;
@@ -411,23 +426,20 @@ __device__ __forceinline__ Decode locate(const InferArgs& a, int64_t qi, int tap
     return d;
 }
 
-// The four latent corners of a decode's texel and their bilinear weights.
-__device__ __forceinline__ void latent_corners(const InferArgs& a, const Decode& d, uint32_t (&c)[4], float (&w)[4])
+// The corner quad of a decode's texel (its four clamped latent corners,
+// 64 contiguous bytes: one cache line) and their bilinear weights.  With
+// LW <= W the cell x0 = floor(X) lies in -1 .. LW - 1 (likewise y0).
+__device__ __forceinline__ uint32_t latent_quad(const InferArgs& a, const Decode& d, float (&w)[4])
 {
     float X = ((float)d.sx + 0.5f) * a.rx - 0.5f, Y = ((float)d.sy + 0.5f) * a.ry - 0.5f;
     float fx0 = floorf(X), fy0 = floorf(Y);
     float fx = X - fx0, fy = Y - fy0;
-    int x0 = (int)fx0, y0 = (int)fy0;
-    int xa = clampi(x0, a.LW - 1), xb = clampi(x0 + 1, a.LW - 1);
-    int ya = clampi(y0, a.LH - 1), yb = clampi(y0 + 1, a.LH - 1);
-    c[0] = (uint32_t)(ya * a.LW + xa);   // the latent table is below 2 GiB
-    c[1] = (uint32_t)(ya * a.LW + xb);
-    c[2] = (uint32_t)(yb * a.LW + xa);
-    c[3] = (uint32_t)(yb * a.LW + xb);
+    const int x0 = min(max((int)fx0, -1), a.LW - 1), y0 = min(max((int)fy0, -1), a.LH - 1);
     w[0] = (1.0f - fx) * (1.0f - fy);
     w[1] = fx * (1.0f - fy);
     w[2] = (1.0f - fx) * fy;
     w[3] = fx * fy;
+    return (uint32_t)((y0 + 1) * (a.LW + 1) + (x0 + 1));   // below 2^27 quads
 }
 
 // The decoder MLP on one 32-decode batch: B1 holds the bf16 latents of the
@@ -540,18 +552,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
     const int64_t npair = ((int64_t)a.n + QPP - 1) / QPP;
     const int tap = lane % TAPS;
-    const uint4* L = reinterpret_cast<const uint4*>(a.lat16);
+    const uint4* L = reinterpret_cast<const uint4*>(a.quad16);
     auto load_uv = [&](int64_t p) {
         int64_t qi = p * QPP + lane / TAPS;
         return (p < npair && qi < a.n) ? reinterpret_cast<const float2*>(a.q)[qi] : make_float2(0.5f, 0.5f);
     };
-    // Every lane loads: the corners are clamped into the table for any query
+    // Every lane loads: the quad index is in the table for any query
     // (padding lanes carry uv = (0.5, 0.5)).
     auto load_lat = [&](const Decode& d, uint4 (&v)[4], float (&w)[4]) {
-        uint32_t c[4];
-        latent_corners(a, d, c, w);
+        const uint32_t e = latent_quad(a, d, w);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = L[c[k]];
+        for (int k = 0; k < 4; ++k) v[k] = L[4 * (size_t)e + k];
     };
 
     int64_t p = wave;
@@ -705,7 +716,7 @@ struct stf_neural {
     float* partial;
     int32_t partial_blocks;
     int64_t step;
-    uint16_t* lat16;
+    uint16_t* quad16;
     Packed* packed;
     bool ready;
 };
@@ -721,7 +732,7 @@ void free_neural(stf_neural* nt)
 {
     if (!nt) return;
     void* ptrs[] = {nt->lat, nt->mlp, nt->m_lat, nt->v_lat, nt->m_mlp, nt->v_mlp,
-                    nt->g_lat, nt->g_mlp, nt->partial, nt->lat16, nt->packed};
+                    nt->g_lat, nt->g_mlp, nt->partial, nt->quad16, nt->packed};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete nt;
@@ -851,7 +862,8 @@ stf_status stf_ntex_create(int32_t tex_w, int32_t tex_h, int32_t lat_w, int32_t 
     float** mbufs[] = {&nt->mlp, &nt->m_mlp, &nt->v_mlp, &nt->g_mlp};
     for (float** b : mbufs)
         if (s == STF_OK) s = dalloc((void**)b, NPARAM * 4, "MLP parameters");
-    if (s == STF_OK) s = dalloc((void**)&nt->lat16, (size_t)nlat(nt) * 2, "binary16 latents");
+    if (s == STF_OK)
+        s = dalloc((void**)&nt->quad16, (size_t)(lat_w + 1) * (lat_h + 1) * 4 * NL * 2, "binary16 corner quads");
     if (s == STF_OK) s = dalloc((void**)&nt->packed, sizeof(Packed), "packed weights");
     if (s == STF_OK) s = ensure_partial(nt, TRAIN_BLOCKS);
     if (s == STF_OK) {
@@ -962,8 +974,9 @@ stf_status stf_ntex_prepare_inference(stf_neural* nt, void* hip_stream)
     delete pk;
     hipStream_t st = (hipStream_t)hip_stream;
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_to_f16, dim3((unsigned)((nlat(nt) + 255) / 256)), dim3(256), 0, st, nt->lat, nt->lat16,
-                           nlat(nt));
+        const int64_t nq = (int64_t)(nt->LW + 1) * (nt->LH + 1);
+        hipLaunchKernelGGL(k_to_quads, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, nt->lat, nt->quad16, nt->LW,
+                           nt->LH);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -993,7 +1006,7 @@ stf_status stf_ntex_filter(const stf_neural* nt, const float* queries_dev, int64
     if (s != STF_OK) return s;
     InferArgs a;
     a.pk = nt->packed;
-    a.lat16 = nt->lat16;
+    a.quad16 = nt->quad16;
     a.q = queries_dev;
     a.n = (int32_t)n;
     a.W = nt->W;
