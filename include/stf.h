@@ -384,7 +384,9 @@ stf_status stf_ntex_get_params(const stf_neural* nt, float* latents_host, float*
 
 /* Freezes the current parameters for inference: latents rounded to binary16,
  * weights to bfloat16 (round to nearest even), biases kept in binary32.
- * Must be called after training and before stf_ntex_filter. */
+ * Must be called after training and before stf_ntex_filter.  The inference
+ * copy of the latents holds, per latent cell, the four corners a bilinear
+ * lookup reads (64 (lat_w + 1)(lat_h + 1) bytes, allocated at creation). */
 stf_status stf_ntex_prepare_inference(stf_neural* nt, void* hip_stream);
 
 /* Filters decoded texels at n uv queries (n x 2 binary32, raster rules of
