@@ -44,9 +44,10 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NL, OFF_W2 = OFF_B1 + NH, OFF_B
 constexpr int PSTRIDE = NPARAM + 1;   // per-block partial gradients + loss
 constexpr int TS = 32;                 // samples per training tile
 constexpr int TBLOCK = 256;
-// Weight-gradient ownership: thread t accumulates W2 entries t + 256 r
-// (r < 16) and entries t + 256 r (r < 5) of the remaining 1160 parameters
-// (W1, b1, b2, W3, b3), each in a register across all tiles of its block.
+// Weight-gradient ownership: thread t accumulates the W2 entries of rows
+// 16 (t / 64) + r (r < 16), column t % 64, and entries t + 256 r (r < 5) of
+// the remaining 1160 parameters (W1, b1, b2, W3, b3), each in a register
+// across all tiles of its block.
 constexpr int OWN2 = NH * NH / TBLOCK;                        // 16
 constexpr int NREST = NPARAM - NH * NH;                       // 1160
 constexpr int OWNR = (NREST + TBLOCK - 1) / TBLOCK;           // 5
@@ -77,9 +78,14 @@ __device__ __forceinline__ int clampi(int v, int hi)
 
 __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
 {
-    __shared__ float sW1[NH][NL + 1], sB1[NH], sW2[NH][NH + 1], sB2[NH], sW3[NO][NH + 1], sB3[NO];
-    __shared__ float sZ[TS][NL + 1], sT[TS][NO + 1], sH1[TS][NH + 1], sH2[TS][NH + 1], sDY[TS][NO + 1];
-    __shared__ float sD2[TS][NH + 1], sD1[TS][NH + 1];
+    // W2, its transpose, H1 and D2 feed the 64 x 64 products four values at
+    // a time (16-byte reads): rows of NH + 4 floats stay 16-byte aligned and
+    // spread the 16 lanes of a read phase over all banks.
+    constexpr int R4 = NH + 4;
+    __shared__ __align__(16) float sW2[NH][R4], sW2T[NH][R4], sH1[TS][R4], sD2[TS][R4];
+    __shared__ float sW1[NH][NL + 1], sB1[NH], sB2[NH], sW3[NO][NH + 1], sB3[NO];
+    __shared__ float sZ[TS][NL + 1], sT[TS][NO + 1], sH2[TS][NH + 1], sDY[TS][NO + 1];
+    __shared__ float sD1[TS][NH + 1];
     __shared__ int32_t sCI[TS][4];
     __shared__ float sCW[TS][4];
     __shared__ int32_t sTex[TS];
@@ -89,7 +95,10 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
         float v = a.mlp[p];
         if (p < OFF_B1) sW1[p / NL][p % NL] = v;
         else if (p < OFF_W2) sB1[p - OFF_B1] = v;
-        else if (p < OFF_B2) sW2[(p - OFF_W2) / NH][(p - OFF_W2) % NH] = v;
+        else if (p < OFF_B2) {
+            sW2[(p - OFF_W2) / NH][(p - OFF_W2) % NH] = v;
+            sW2T[(p - OFF_W2) % NH][(p - OFF_W2) / NH] = v;
+        }
         else if (p < OFF_W3) sB2[p - OFF_B2] = v;
         else if (p < OFF_B3) sW3[(p - OFF_W3) / NH][(p - OFF_W3) % NH] = v;
         else sB3[p - OFF_B3] = v;
@@ -152,13 +161,25 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
             sH1[s2][ha] = fmaxf(v, 0.0f);
         }
         __syncthreads();
-#pragma unroll 2
-        for (int r = 0; r < TS / 4; ++r) {
-            int s2 = hs + 4 * r;
-            float v = sB2[ha];
-#pragma unroll 16
-            for (int b = 0; b < NH; ++b) v = __builtin_fmaf(sW2[ha][b], sH1[s2][b], v);
-            sH2[s2][ha] = fmaxf(v, 0.0f);
+        {
+            // each W2 row read serves the thread's 8 samples (same sums, same order)
+            float v[TS / 4];
+#pragma unroll
+            for (int r = 0; r < TS / 4; ++r) v[r] = sB2[ha];
+#pragma unroll 4
+            for (int b = 0; b < NH; b += 4) {
+                const float4 w = *reinterpret_cast<const float4*>(&sW2[ha][b]);
+#pragma unroll
+                for (int r = 0; r < TS / 4; ++r) {
+                    const float4 x = *reinterpret_cast<const float4*>(&sH1[hs + 4 * r][b]);
+                    v[r] = __builtin_fmaf(w.x, x.x, v[r]);
+                    v[r] = __builtin_fmaf(w.y, x.y, v[r]);
+                    v[r] = __builtin_fmaf(w.z, x.z, v[r]);
+                    v[r] = __builtin_fmaf(w.w, x.w, v[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < TS / 4; ++r) sH2[hs + 4 * r][ha] = fmaxf(v[r], 0.0f);
         }
         __syncthreads();
         {
@@ -179,13 +200,24 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
             sD2[s2][ha] = sH2[s2][ha] > 0.0f ? v : 0.0f;
         }
         __syncthreads();
-#pragma unroll 2
-        for (int r = 0; r < TS / 4; ++r) {
-            int s2 = hs + 4 * r;
-            float v = 0.0f;
-#pragma unroll 16
-            for (int b = 0; b < NH; ++b) v = __builtin_fmaf(sW2[b][ha], sD2[s2][b], v);
-            sD1[s2][ha] = sH1[s2][ha] > 0.0f ? v : 0.0f;
+        {
+            float v[TS / 4];
+#pragma unroll
+            for (int r = 0; r < TS / 4; ++r) v[r] = 0.0f;
+#pragma unroll 4
+            for (int b = 0; b < NH; b += 4) {
+                const float4 w = *reinterpret_cast<const float4*>(&sW2T[ha][b]);   // W2[b..b+3][ha]
+#pragma unroll
+                for (int r = 0; r < TS / 4; ++r) {
+                    const float4 d = *reinterpret_cast<const float4*>(&sD2[hs + 4 * r][b]);
+                    v[r] = __builtin_fmaf(w.x, d.x, v[r]);
+                    v[r] = __builtin_fmaf(w.y, d.y, v[r]);
+                    v[r] = __builtin_fmaf(w.z, d.z, v[r]);
+                    v[r] = __builtin_fmaf(w.w, d.w, v[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < TS / 4; ++r) sD1[hs + 4 * r][ha] = sH1[hs + 4 * r][ha] > 0.0f ? v[r] : 0.0f;
         }
         __syncthreads();
         {
@@ -197,14 +229,28 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
                 for (int c = 0; c < 4; ++c) atomicAdd(a.g_lat + (int64_t)sCI[s][c] * NL + k, sCW[s][c] * dz);
             }
         }
-        // W2 gradient: dW2[ua][ub] = sum_q dh2[q][ua] h1[q][ub]; ua = t/64 + 4r, ub = t%64
+        // W2 gradient: dW2[ua][ub] = sum_q dh2[q][ua] h1[q][ub] with
+        // ua = 16 (t/64) + r, ub = t%64: per sample one H1 value and four
+        // 16-byte reads of D2 serve the thread's 16 entries
+        {
+            float g[OWN2];
 #pragma unroll
-        for (int r = 0; r < OWN2; ++r) {
-            const int ua = t / NH + (TBLOCK / NH) * r, ub = t % NH;
-            float g = 0.0f;
-#pragma unroll 8
-            for (int q = 0; q < TS; ++q) g = __builtin_fmaf(sD2[q][ua], sH1[q][ub], g);
-            acc2[r] += g;
+            for (int r = 0; r < OWN2; ++r) g[r] = 0.0f;
+            const int u0 = OWN2 * (t / NH), ub = t % NH;
+#pragma unroll 4
+            for (int q = 0; q < TS; ++q) {
+                const float h = sH1[q][ub];
+#pragma unroll
+                for (int r4 = 0; r4 < OWN2; r4 += 4) {
+                    const float4 d = *reinterpret_cast<const float4*>(&sD2[q][u0 + r4]);
+                    g[r4] = __builtin_fmaf(d.x, h, g[r4]);
+                    g[r4 + 1] = __builtin_fmaf(d.y, h, g[r4 + 1]);
+                    g[r4 + 2] = __builtin_fmaf(d.z, h, g[r4 + 2]);
+                    g[r4 + 3] = __builtin_fmaf(d.w, h, g[r4 + 3]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < OWN2; ++r) acc2[r] += g[r];
         }
 #pragma unroll
         for (int r = 0; r < OWNR; ++r) {
@@ -230,7 +276,7 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
     }
     float* out = a.partial + (int64_t)blockIdx.x * PSTRIDE;
 #pragma unroll
-    for (int r = 0; r < OWN2; ++r) out[OFF_W2 + (t / NH + (TBLOCK / NH) * r) * NH + t % NH] = acc2[r];
+    for (int r = 0; r < OWN2; ++r) out[OFF_W2 + (OWN2 * (t / NH) + r) * NH + t % NH] = acc2[r];
 #pragma unroll
     for (int r = 0; r < OWNR; ++r) {
         const int e = t + TBLOCK * r;
