@@ -44,19 +44,12 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NL, OFF_W2 = OFF_B1 + NH, OFF_B
 constexpr int PSTRIDE = NPARAM + 1;   // per-block partial gradients + loss
 constexpr int TS = 32;                 // samples per training tile
 constexpr int TBLOCK = 256;
-// Weight-gradient ownership: thread t accumulates the W2 entries of rows
-// 16 (t / 64) + r (r < 16), column t % 64, and entries t + 256 r (r < 5) of
-// the remaining 1160 parameters (W1, b1, b2, W3, b3), each in a register
-// across all tiles of its block.
+// Weight-gradient ownership (each in registers across all tiles of a
+// block): thread t holds the W2 entries of rows 16 (t / 64) + r (r < 16),
+// column t % 64; threads 0..63 also hold row t of W1 and b1[t], threads
+// 64..127 column t - 64 of W3 and b2[t - 64], threads 128..135 b3[t - 128].
 constexpr int OWN2 = NH * NH / TBLOCK;                        // 16
-constexpr int NREST = NPARAM - NH * NH;                       // 1160
-constexpr int OWNR = (NREST + TBLOCK - 1) / TBLOCK;           // 5
-
-// flat parameter index of entry r of the non-W2 list
-__host__ __device__ constexpr int rest_param(int r)
-{
-    return r < OFF_W2 ? r : r + NH * NH;   // W1, b1 precede W2; b2, W3, b3 follow
-}
+static_assert(NL == 8 && NO == 8 && NH == 64 && TBLOCK == 256, "the ownership above");
 
 struct TrainArgs {
     const float* lat;
@@ -78,22 +71,23 @@ __device__ __forceinline__ int clampi(int v, int hi)
 
 __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
 {
-    // W2, its transpose, H1 and D2 feed the 64 x 64 products four values at
-    // a time (16-byte reads): rows of NH + 4 floats stay 16-byte aligned and
-    // spread the 16 lanes of a read phase over all banks.
+    // Operands of the products are read four values at a time (16-byte LDS
+    // reads), each read serving several FMAs; every sum keeps its order.
+    // Rows of NH + 4 floats stay 16-byte aligned and spread the 16 lanes of a
+    // read phase over all banks.  80 KiB per block: two blocks per CU.
     constexpr int R4 = NH + 4;
-    __shared__ __align__(16) float sW2[NH][R4], sW2T[NH][R4], sH1[TS][R4], sD2[TS][R4];
-    __shared__ float sW1[NH][NL + 1], sB1[NH], sB2[NH], sW3[NO][NH + 1], sB3[NO];
-    __shared__ float sZ[TS][NL + 1], sT[TS][NO + 1], sH2[TS][NH + 1], sDY[TS][NO + 1];
-    __shared__ float sD1[TS][NH + 1];
+    __shared__ __align__(16) float sW2[NH][R4], sW2T[NH][R4], sW3[NO][R4], sW1T[NL][R4];
+    __shared__ __align__(16) float sH1[TS][R4], sH2[TS][R4], sD2[TS][R4], sD1[TS][R4];
+    __shared__ __align__(16) float sZ[TS][NL], sDY[TS][NO];
+    __shared__ float sB1[NH], sB2[NH], sB3[NO], sT[TS][NO + 1];
     __shared__ int32_t sCI[TS][4];
     __shared__ float sCW[TS][4];
     __shared__ int32_t sTex[TS];
-    __shared__ float sRed[TBLOCK];
+    static_assert(TS * (NO + 1) >= TBLOCK, "the loss reduction reuses sT");
     const int t = threadIdx.x;
     for (int p = t; p < NPARAM; p += TBLOCK) {
         float v = a.mlp[p];
-        if (p < OFF_B1) sW1[p / NL][p % NL] = v;
+        if (p < OFF_B1) sW1T[p % NL][p / NL] = v;
         else if (p < OFF_W2) sB1[p - OFF_B1] = v;
         else if (p < OFF_B2) {
             sW2[(p - OFF_W2) / NH][(p - OFF_W2) % NH] = v;
@@ -103,13 +97,15 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
         else if (p < OFF_B3) sW3[(p - OFF_W3) / NH][(p - OFF_W3) % NH] = v;
         else sB3[p - OFF_B3] = v;
     }
-    float acc2[OWN2], accr[OWNR];
+    // gradients owned by this thread (see the ownership note above)
+    float acc2[OWN2], accw[NL], accb = 0.0f;
 #pragma unroll
     for (int r = 0; r < OWN2; ++r) acc2[r] = 0.0f;
 #pragma unroll
-    for (int r = 0; r < OWNR; ++r) accr[r] = 0.0f;
+    for (int r = 0; r < NL; ++r) accw[r] = 0.0f;
     float lacc = 0.0f;
-    const int s = t / 8, k = t % 8;   // (sample, channel) for the gather/scatter phases
+    const int s = t / 8, k = t % 8;       // (sample, channel) for the gather/scatter and output phases
+    const int ha = t % NH, hs = t / NH;   // (hidden unit, first sample) for the 32 x 64 phases
     for (int tile = blockIdx.x; tile * TS < a.B; tile += gridDim.x) {
         const int gs = tile * TS + s;
         const bool live = gs < a.B;
@@ -151,18 +147,29 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
             sT[s][k] = live ? a.target[(int64_t)sTex[s] * NO + k] : 0.0f;
         }
         __syncthreads();
-        const int ha = t % NH, hs = t / NH;   // (hidden unit, first sample) for the 32 x 64 phases
+        {   // H1 = relu(W1 Z + b1): the thread's W1 row once, two reads per sample
+            float w[NL];
 #pragma unroll
-        for (int r = 0; r < TS / 4; ++r) {
-            int s2 = hs + 4 * r;
-            float v = sB1[ha];
+            for (int kk = 0; kk < NL; ++kk) w[kk] = sW1T[kk][ha];
 #pragma unroll
-            for (int kk = 0; kk < NL; ++kk) v = __builtin_fmaf(sW1[ha][kk], sZ[s2][kk], v);
-            sH1[s2][ha] = fmaxf(v, 0.0f);
+            for (int r = 0; r < TS / 4; ++r) {
+                const int s2 = hs + 4 * r;
+                const float4 z0 = *reinterpret_cast<const float4*>(&sZ[s2][0]);
+                const float4 z1 = *reinterpret_cast<const float4*>(&sZ[s2][4]);
+                float v = sB1[ha];
+                v = __builtin_fmaf(w[0], z0.x, v);
+                v = __builtin_fmaf(w[1], z0.y, v);
+                v = __builtin_fmaf(w[2], z0.z, v);
+                v = __builtin_fmaf(w[3], z0.w, v);
+                v = __builtin_fmaf(w[4], z1.x, v);
+                v = __builtin_fmaf(w[5], z1.y, v);
+                v = __builtin_fmaf(w[6], z1.z, v);
+                v = __builtin_fmaf(w[7], z1.w, v);
+                sH1[s2][ha] = fmaxf(v, 0.0f);
+            }
         }
         __syncthreads();
-        {
-            // each W2 row read serves the thread's 8 samples (same sums, same order)
+        {   // H2 = relu(W2 H1 + b2): each W2 row read serves the thread's 8 samples
             float v[TS / 4];
 #pragma unroll
             for (int r = 0; r < TS / 4; ++r) v[r] = sB2[ha];
@@ -182,25 +189,45 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
             for (int r = 0; r < TS / 4; ++r) sH2[hs + 4 * r][ha] = fmaxf(v[r], 0.0f);
         }
         __syncthreads();
-        {
+        {   // Y = W3 H2 + b3 and the loss: thread (s, k)
             float y = sB3[k];
-#pragma unroll 16
-            for (int b = 0; b < NH; ++b) y = __builtin_fmaf(sW3[k][b], sH2[s][b], y);
+#pragma unroll 4
+            for (int b = 0; b < NH; b += 4) {
+                const float4 w = *reinterpret_cast<const float4*>(&sW3[k][b]);
+                const float4 x = *reinterpret_cast<const float4*>(&sH2[s][b]);
+                y = __builtin_fmaf(w.x, x.x, y);
+                y = __builtin_fmaf(w.y, x.y, y);
+                y = __builtin_fmaf(w.z, x.z, y);
+                y = __builtin_fmaf(w.w, x.w, y);
+            }
             float e = y - sT[s][k];
             if (live) lacc = __builtin_fmaf(e, e, lacc);
             sDY[s][k] = live ? e * a.dscale : 0.0f;
         }
         __syncthreads();
+        {   // D2 = (W3^T dY) * [H2 > 0]: the thread's W3 column once
+            float w[NO];
 #pragma unroll
-        for (int r = 0; r < TS / 4; ++r) {
-            int s2 = hs + 4 * r;
-            float v = 0.0f;
+            for (int c = 0; c < NO; ++c) w[c] = sW3[c][ha];
 #pragma unroll
-            for (int c = 0; c < NO; ++c) v = __builtin_fmaf(sW3[c][ha], sDY[s2][c], v);
-            sD2[s2][ha] = sH2[s2][ha] > 0.0f ? v : 0.0f;
+            for (int r = 0; r < TS / 4; ++r) {
+                const int s2 = hs + 4 * r;
+                const float4 d0 = *reinterpret_cast<const float4*>(&sDY[s2][0]);
+                const float4 d1 = *reinterpret_cast<const float4*>(&sDY[s2][4]);
+                float v = 0.0f;
+                v = __builtin_fmaf(w[0], d0.x, v);
+                v = __builtin_fmaf(w[1], d0.y, v);
+                v = __builtin_fmaf(w[2], d0.z, v);
+                v = __builtin_fmaf(w[3], d0.w, v);
+                v = __builtin_fmaf(w[4], d1.x, v);
+                v = __builtin_fmaf(w[5], d1.y, v);
+                v = __builtin_fmaf(w[6], d1.z, v);
+                v = __builtin_fmaf(w[7], d1.w, v);
+                sD2[s2][ha] = sH2[s2][ha] > 0.0f ? v : 0.0f;
+            }
         }
         __syncthreads();
-        {
+        {   // D1 = (W2^T D2) * [H1 > 0]
             float v[TS / 4];
 #pragma unroll
             for (int r = 0; r < TS / 4; ++r) v[r] = 0.0f;
@@ -220,19 +247,24 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
             for (int r = 0; r < TS / 4; ++r) sD1[hs + 4 * r][ha] = sH1[hs + 4 * r][ha] > 0.0f ? v[r] : 0.0f;
         }
         __syncthreads();
-        {
+        {   // dZ = W1^T D1, scattered to the four latent corners
             float dz = 0.0f;
-#pragma unroll 16
-            for (int b = 0; b < NH; ++b) dz = __builtin_fmaf(sW1[b][k], sD1[s][b], dz);
+#pragma unroll 4
+            for (int b = 0; b < NH; b += 4) {
+                const float4 w = *reinterpret_cast<const float4*>(&sW1T[k][b]);   // W1[b..b+3][k]
+                const float4 d = *reinterpret_cast<const float4*>(&sD1[s][b]);
+                dz = __builtin_fmaf(w.x, d.x, dz);
+                dz = __builtin_fmaf(w.y, d.y, dz);
+                dz = __builtin_fmaf(w.z, d.z, dz);
+                dz = __builtin_fmaf(w.w, d.w, dz);
+            }
             if (live) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) atomicAdd(a.g_lat + (int64_t)sCI[s][c] * NL + k, sCW[s][c] * dz);
             }
         }
-        // W2 gradient: dW2[ua][ub] = sum_q dh2[q][ua] h1[q][ub] with
-        // ua = 16 (t/64) + r, ub = t%64: per sample one H1 value and four
-        // 16-byte reads of D2 serve the thread's 16 entries
-        {
+        {   // dW2[ua][ub] = sum_q D2[q][ua] H1[q][ub], ua = 16 (t/64) + r, ub = t%64:
+            // per sample one H1 value and four 16-byte reads of D2
             float g[OWN2];
 #pragma unroll
             for (int r = 0; r < OWN2; ++r) g[r] = 0.0f;
@@ -252,36 +284,55 @@ __global__ __launch_bounds__(TBLOCK) void k_ntex_train(TrainArgs a)
 #pragma unroll
             for (int r = 0; r < OWN2; ++r) acc2[r] += g[r];
         }
+        if (t < 2 * NH) {   // dW1 row t and b1[t] / dW3 column t - 64 and b2[t - 64]
+            const int ua = t % NH;
+            const bool first = t < NH;
+            const float(*D)[R4] = first ? sD1 : sD2;
+            const float(*X)[NL] = first ? sZ : sDY;
+            const float(*Hq)[R4] = first ? sD1 : sH2;
+            float g[NL], gb = 0.0f;
 #pragma unroll
-        for (int r = 0; r < OWNR; ++r) {
-            const int e = t + TBLOCK * r;
-            if (e >= NREST) break;
-            const int p = rest_param(e);
-            float g = 0.0f;
-            if (p < OFF_B1) {
-                int ua = p / NL, uk = p % NL;
-                for (int q = 0; q < TS; ++q) g = __builtin_fmaf(sD1[q][ua], sZ[q][uk], g);
-            } else if (p < OFF_W2) {
-                for (int q = 0; q < TS; ++q) g += sD1[q][p - OFF_B1];
-            } else if (p < OFF_W3) {
-                for (int q = 0; q < TS; ++q) g += sD2[q][p - OFF_B2];
-            } else if (p < OFF_B3) {
-                int uc = (p - OFF_W3) / NH, ua = (p - OFF_W3) % NH;
-                for (int q = 0; q < TS; ++q) g = __builtin_fmaf(sDY[q][uc], sH2[q][ua], g);
-            } else {
-                for (int q = 0; q < TS; ++q) g += sDY[q][p - OFF_B3];
+            for (int r = 0; r < NL; ++r) g[r] = 0.0f;
+#pragma unroll 4
+            for (int q = 0; q < TS; ++q) {
+                const float hq = Hq[q][ua];   // D1[q][ua] (dW1) or H2[q][ua] (dW3)
+                const float4 x0 = *reinterpret_cast<const float4*>(&X[q][0]);   // Z[q][.] or dY[q][.]
+                const float4 x1 = *reinterpret_cast<const float4*>(&X[q][4]);
+                g[0] = __builtin_fmaf(first ? hq : x0.x, first ? x0.x : hq, g[0]);
+                g[1] = __builtin_fmaf(first ? hq : x0.y, first ? x0.y : hq, g[1]);
+                g[2] = __builtin_fmaf(first ? hq : x0.z, first ? x0.z : hq, g[2]);
+                g[3] = __builtin_fmaf(first ? hq : x0.w, first ? x0.w : hq, g[3]);
+                g[4] = __builtin_fmaf(first ? hq : x1.x, first ? x1.x : hq, g[4]);
+                g[5] = __builtin_fmaf(first ? hq : x1.y, first ? x1.y : hq, g[5]);
+                g[6] = __builtin_fmaf(first ? hq : x1.z, first ? x1.z : hq, g[6]);
+                g[7] = __builtin_fmaf(first ? hq : x1.w, first ? x1.w : hq, g[7]);
+                gb += D[q][ua];   // b1 from D1, b2 from D2
             }
-            accr[r] += g;
+#pragma unroll
+            for (int r = 0; r < NL; ++r) accw[r] += g[r];
+            accb += gb;
+        } else if (t < 2 * NH + NO) {   // b3
+            float gb = 0.0f;
+            for (int q = 0; q < TS; ++q) gb += sDY[q][t - 2 * NH];
+            accb += gb;
         }
     }
     float* out = a.partial + (int64_t)blockIdx.x * PSTRIDE;
 #pragma unroll
     for (int r = 0; r < OWN2; ++r) out[OFF_W2 + (OWN2 * (t / NH) + r) * NH + t % NH] = acc2[r];
+    if (t < NH) {
 #pragma unroll
-    for (int r = 0; r < OWNR; ++r) {
-        const int e = t + TBLOCK * r;
-        if (e < NREST) out[rest_param(e)] = accr[r];
+        for (int r = 0; r < NL; ++r) out[OFF_W1 + t * NL + r] = accw[r];
+        out[OFF_B1 + t] = accb;
+    } else if (t < 2 * NH) {
+#pragma unroll
+        for (int r = 0; r < NO; ++r) out[OFF_W3 + r * NH + (t - NH)] = accw[r];
+        out[OFF_B2 + t - NH] = accb;
+    } else if (t < 2 * NH + NO) {
+        out[OFF_B3 + t - 2 * NH] = accb;
     }
+    float* sRed = &sT[0][0];
+    __syncthreads();   // the last tile's reads of sT are done
     sRed[t] = lacc;
     __syncthreads();
     for (int st = TBLOCK / 2; st > 0; st >>= 1) {
