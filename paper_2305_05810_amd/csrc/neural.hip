@@ -852,7 +852,7 @@ hipError_t fill(float* p, int64_t n, float v, hipStream_t s)
     return hipGetLastError();
 }
 
-constexpr int TRAIN_BLOCKS = 1024;
+constexpr int TRAIN_BLOCKS = 512;   // one resident set: two 80 KiB blocks per CU
 
 stf_status ensure_partial(stf_neural* nt, int32_t blocks)
 {
