@@ -148,13 +148,21 @@ __global__ __launch_bounds__(BLOCK) void k_shade(Levels L, const float* __restri
                 wx[0] = 1.0f - tx; wx[1] = tx;
                 wy[0] = 1.0f - ty; wy[1] = ty;
             }
+            // all taps' texels first: their loads are then in flight together
+            // instead of one latency per tap between shading evaluations
+            uint2 texel[NT][NT];
+#pragma unroll
+            for (int b = 0; b < NT; ++b) {
+                const int64_t row = (int64_t)clampi(cy + b, T.h - 1) * T.w;
+#pragma unroll
+                for (int a = 0; a < NT; ++a) texel[b][a] = tex[row + clampi(cx + a, T.w - 1)];
+            }
             float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int b = 0; b < NT; ++b) {
-                int yy = clampi(cy + b, T.h - 1);
 #pragma unroll
                 for (int a = 0; a < NT; ++a) {
-                    Material m = decode_material(tex[(int64_t)yy * T.w + clampi(cx + a, T.w - 1)]);
+                    Material m = decode_material(texel[b][a]);
                     float w = wx[a] * wy[b];
                     if constexpr (MODE == STF_SHADE_AFTER_FILTER) {
                         acc[0] = __builtin_fmaf(w, m.albedo[0], acc[0]);
