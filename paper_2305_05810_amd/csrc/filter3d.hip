@@ -13,6 +13,8 @@
 #include <limits.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "interp.h"
 #include "stf_internal.h"
@@ -349,86 +351,213 @@ __device__ __forceinline__ int32_t pick8(const int32_t (&l)[8], bool kx, bool ky
 
 // The unscaled sum over the NT^3 taps starting at voxel base, from global
 // memory (weights scaled by axis_scale per axis).
-template <int FMT, int KIND>
-__device__ __forceinline__ float det_sum_global(const GridView& g, const int (&base)[3], const float (&w)[3][4])
+// The value itself, opaque to the optimizer (an empty asm statement, no
+// instruction): a byte offset selected against 0 otherwise becomes a select
+// of 64-bit addresses, and the loads lose the uniform-base-plus-32-bit-offset
+// form (two VGPRs of address per load in flight instead of one).
+__device__ __forceinline__ uint32_t vgpr_u32(uint32_t v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// As vgpr_u32, and ordered after `dep` is known: loads addressed by the
+// result wait for the value (a partial sum) that `dep` carries.
+__device__ __forceinline__ uint32_t vgpr_u32_after(uint32_t v, float dep)
+{
+    asm volatile("" : "+v"(v) : "v"(dep));
+    return v;
+}
+
+// The NT taps of a row from its two-chunk window (uint4 chunks: 4 binary32
+// or 8 16-bit values; uint2 chunks: 8 8-bit values), starting at voxel p of
+// the window.  Selection is branch-free on the bits of p, then each tap is
+// decoded exactly as a single-texel load would.
+template <int FMT, int NT>
+__device__ __forceinline__ void window_taps(const uint4& c0, const uint4& c1, int p, float (&t)[NT])
+{
+    // (named registers, not an indexed array: the selection stays in VGPRs)
+    if constexpr (FMT == F32) {
+        // p in 0..3: tap j is dword p + j of the window
+        const bool b0 = p & 1, b1 = p & 2;
+        const uint32_t s0 = b0 ? c0.y : c0.x, s1 = b0 ? c0.z : c0.y, s2 = b0 ? c0.w : c0.z,
+                       s3 = b0 ? c1.x : c0.w;
+        t[0] = __builtin_bit_cast(float, b1 ? s2 : s0);
+        t[1] = __builtin_bit_cast(float, b1 ? s3 : s1);
+        if constexpr (NT == 4) {
+            const uint32_t s4 = b0 ? c1.y : c1.x, s5 = b0 ? c1.z : c1.y;
+            t[2] = __builtin_bit_cast(float, b1 ? s4 : s2);
+            t[3] = __builtin_bit_cast(float, b1 ? s5 : s3);
+        }
+    } else {
+        // p in 0..7: tap j is half p + j; the taps' dwords start at p >> 1
+        const bool b1 = p & 2, b2 = p & 4;
+        const uint32_t s0 = b1 ? c0.y : c0.x, s1 = b1 ? c0.z : c0.y, s2 = b1 ? c0.w : c0.z,
+                       s3 = b1 ? c1.x : c0.w;
+        const uint32_t e0 = b2 ? s2 : s0, e1 = b2 ? s3 : s1;
+        const uint32_t sh = (uint32_t)(p & 1) * 16u;
+        uint32_t wd[NT / 2];
+        wd[0] = __builtin_amdgcn_alignbit(e1, e0, sh);
+        if constexpr (NT == 4) {
+            const uint32_t s4 = b1 ? c1.y : c1.x;
+            const uint32_t e2 = b2 ? s4 : s2;
+            wd[1] = __builtin_amdgcn_alignbit(e2, e1, sh);
+        }
+#pragma unroll
+        for (int k = 0; k < NT / 2; ++k) {
+            if constexpr (FMT == F16) {
+                t[2 * k] = dec_f16((uint16_t)wd[k]);
+                t[2 * k + 1] = dec_f16((uint16_t)(wd[k] >> 16));
+            } else {
+                t[2 * k] = dec_bf16((uint16_t)wd[k]);
+                t[2 * k + 1] = dec_bf16((uint16_t)(wd[k] >> 16));
+            }
+        }
+    }
+}
+
+template <int FMT, int NT>
+__device__ __forceinline__ void window_taps(const uint2& c0, const uint2& c1, int p, float (&t)[NT])
+{
+    // p in 0..7: tap j is byte p + j of the 16-byte window
+    const uint32_t lo = (p & 4) ? c0.y : c0.x, hi = (p & 4) ? c1.x : c0.y;
+    const uint32_t wd = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(p & 3) * 8u);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const uint32_t b = (wd >> (8 * j)) & 0xffu;
+        t[j] = FMT == FP8_E4M3 ? dec_e4m3(b) : dec_u8(b);
+    }
+}
+
+// The at most 2x2x2 leaves that a query's tap block (NT^3 voxels from base)
+// meets, low/high side per axis in bits 0/1/2 of k; -1 where no stored leaf
+// is (empty slot, outside the domain) or where no tap lies.  True if any
+// holds texels.
+template <int KIND>
+__device__ __forceinline__ bool det_leaves(const GridView& g, const int (&base)[3], int32_t (&leaf)[8])
 {
     constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
     int lo[3];
+    bool nb[3];   // the second leaf along an axis is resolved only when a tap lies in it
 #pragma unroll
-    for (int a = 0; a < 3; ++a) lo[a] = base[a] >> 3;   // leaf coordinate of the first tap (floor for negatives)
-    int32_t leaf[8];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = base[a] >> 3;   // leaf coordinate of the first tap (floor for negatives)
+        nb[a] = ((base[a] + NT - 1) >> 3) != lo[a];
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
+        const bool used = (!(k & 1) || nb[0]) && (!(k & 2) || nb[1]) && (!(k & 4) || nb[2]);
         int x = (lo[0] + (k & 1)) * 8, y = (lo[1] + ((k >> 1) & 1)) * 8, z = (lo[2] + (k >> 2)) * 8;
-        leaf[k] = in_domain(g, x, y, z) ? grid_leaf(g, x, y, z) : -1;
+        leaf[k] = used && in_domain(g, x, y, z) ? grid_leaf(g, x, y, z) : -1;
     }
     bool live = false;
 #pragma unroll
     for (int k = 0; k < 8; ++k) live = live || leaf[k] >= 0;
+    return live;
+}
+
+// Empty space: every tap reads the background, so the nested sums of
+// det_taps reduce to one row, one plane and one volume sum of it (the same
+// operations in the same order, so the same binary32 result).
+template <int KIND>
+__device__ __forceinline__ float det_background(const GridView& g, const float (&w)[3][4])
+{
+    constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
+    float row = 0.0f, plane = 0.0f, acc = 0.0f;
+#pragma unroll
+    for (int cx = 0; cx < NT; ++cx) row = __builtin_fmaf(w[0][cx], g.background, row);
+#pragma unroll
+    for (int cy = 0; cy < NT; ++cy) plane = __builtin_fmaf(w[1][cy], row, plane);
+#pragma unroll
+    for (int cz = 0; cz < NT; ++cz) acc = __builtin_fmaf(w[2][cz], plane, acc);
+    return acc;
+}
+
+// The separable tap sum (x innermost, then y, then z) over the query's leaves.
+template <int FMT, int KIND>
+__device__ __forceinline__ float det_taps(const GridView& g, const int (&base)[3], const int32_t (&leaf)[8],
+                                          const float (&w)[3][4])
+{
+    constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
+    int lo[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lo[a] = base[a] >> 3;
     float acc = 0.0f;
-    if (!live) {
-        // Empty space: every tap reads the background, so the nested sums
-        // below reduce to one row, one plane and one volume sum of it (the
-        // same operations in the same order, so the same binary32 result),
-        // and a wave whose queries are all in empty space skips the taps.
-        float row = 0.0f, plane = 0.0f;
+    // Per axis and tap: whether the tap lies in the second leaf along
+    // the axis and inside the domain; row offsets within a leaf.
+    bool ky[NT], kz[NT], inx[NT], iny[NT], inz[NT];
+    uint32_t oy[NT], oz[NT];
 #pragma unroll
-        for (int cx = 0; cx < NT; ++cx) row = __builtin_fmaf(w[0][cx], g.background, row);
+    for (int k = 0; k < NT; ++k) {
+        const int vx = base[0] + k, vy = base[1] + k, vz = base[2] + k;
+        ky[k] = (vy >> 3) != lo[1];
+        kz[k] = (vz >> 3) != lo[2];
+        inx[k] = (unsigned)vx < (unsigned)g.dx;
+        iny[k] = (unsigned)vy < (unsigned)g.dy;
+        inz[k] = (unsigned)vz < (unsigned)g.dz;
+        oy[k] = (uint32_t)(vy & 7) * 8u;
+        oz[k] = (uint32_t)(vz & 7) * 64u;
+    }
+    // A row's taps are read as one window of two aligned chunks along x
+    // (16 bytes each: half a leaf row of binary32, a whole row of 16-bit
+    // values; 8 bytes, a whole row, of 8-bit values), one vector load per
+    // chunk instead of one load per tap.  The taps start at voxel p of the
+    // window; the second chunk is loaded only when a tap reaches it, and
+    // lies in the x-neighbour leaf when the first ends a leaf row.
+    constexpr uint32_t TB = FMT == F32 ? 4u : (FMT == F16 || FMT == BF16 ? 2u : 1u);
+    constexpr int CV = FMT == F32 ? 4 : 8;
+    using Chunk = typename std::conditional<TB == 1u, uint2, uint4>::type;
+    const int p = base[0] & (CV - 1);
+    const uint32_t xo0 = (uint32_t)(base[0] & 7 & ~(CV - 1));   // first chunk's offset in its leaf row
+    const bool c1b = xo0 + CV == 8;                             // second chunk in the x-neighbour leaf
+    const uint32_t xo1 = c1b ? 0u : xo0 + CV;
+    const bool two = p + NT > CV;
+    const char* __restrict__ leaves = reinterpret_cast<const char*>(g.leaves);
+    // the leaves as values, so that selecting a row's pair stays a register
+    // select rather than becoming an indexed read of a local array
+    const int32_t L0 = leaf[0], L1 = leaf[1], L2 = leaf[2], L3 = leaf[3], L4 = leaf[4], L5 = leaf[5],
+                  L6 = leaf[6], L7 = leaf[7];
 #pragma unroll
-        for (int cy = 0; cy < NT; ++cy) plane = __builtin_fmaf(w[1][cy], row, plane);
+    for (int cz = 0; cz < NT; ++cz) {
+        float plane = 0.0f;
 #pragma unroll
-        for (int cz = 0; cz < NT; ++cz) acc = __builtin_fmaf(w[2][cz], plane, acc);
-    } else {
-        // Per axis and tap: which of the two leaves along the axis holds it,
-        // whether it is inside the domain, and its offset within the leaf.
-        bool kx[NT], ky[NT], kz[NT], inx[NT], iny[NT], inz[NT];
-        uint32_t ox[NT], oy[NT], oz[NT];
+        for (int cy = 0; cy < NT; ++cy) {
+            // the row's leaves on the low and high side along x, and
+            // whether each chunk holds texels; a chunk with none (or not
+            // needed) loads from offset 0, shared by all such lanes
+            const int32_t la = kz[cz] ? (ky[cy] ? L6 : L4) : (ky[cy] ? L2 : L0);
+            const int32_t lb = kz[cz] ? (ky[cy] ? L7 : L5) : (ky[cy] ? L3 : L1);
+            const int32_t l1 = c1b ? lb : la;
+            const bool ryz = iny[cy] && inz[cz];
+            const bool ok0 = ryz && la >= 0, ok1 = ryz && l1 >= 0;
+            const uint32_t roff = oz[cz] + oy[cy];
+            // the second half of the rows is addressed after the first half
+            // is summed: half the loads in flight, half the registers
+            const float gate = 2 * cz < NT ? 0.0f : acc;
+            const uint32_t a0 = vgpr_u32_after(ok0 ? ((uint32_t)la * 512u + roff + xo0) * TB : 0u, gate);
+            const uint32_t a1 = vgpr_u32_after((ok1 && two) ? ((uint32_t)l1 * 512u + roff + xo1) * TB : 0u, gate);
+            const Chunk v0 = *reinterpret_cast<const Chunk*>(leaves + a0);
+            const Chunk v1 = *reinterpret_cast<const Chunk*>(leaves + a1);
+            float t[NT];
+            window_taps<FMT>(v0, v1, p, t);
+            float row = 0.0f;
 #pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            const int vx = base[0] + k, vy = base[1] + k, vz = base[2] + k;
-            kx[k] = (vx >> 3) != lo[0];
-            ky[k] = (vy >> 3) != lo[1];
-            kz[k] = (vz >> 3) != lo[2];
-            inx[k] = (unsigned)vx < (unsigned)g.dx;
-            iny[k] = (unsigned)vy < (unsigned)g.dy;
-            inz[k] = (unsigned)vz < (unsigned)g.dz;
-            ox[k] = (uint32_t)(vx & 7);
-            oy[k] = (uint32_t)(vy & 7) * 8u;
-            oz[k] = (uint32_t)(vz & 7) * 64u;
-        }
-        // Every tap loads without a branch: a tap with no stored texel
-        // (empty slot, outside the domain) loads from leaf 0 -- some leaf
-        // exists here -- and takes the background instead.
-        const char* __restrict__ leaves = reinterpret_cast<const char*>(g.leaves);
-        constexpr uint32_t TB = FMT == F32 ? 4u : (FMT == F16 || FMT == BF16 ? 2u : 1u);
-#pragma unroll
-        for (int cz = 0; cz < NT; ++cz) {
-            float plane = 0.0f;
-#pragma unroll
-            for (int cy = 0; cy < NT; ++cy) {
-                // the row's two leaves (low and high side along x): first
-                // element of the row in each, and whether it holds texels
-                const int32_t la = kz[cz] ? (ky[cy] ? leaf[6] : leaf[4]) : (ky[cy] ? leaf[2] : leaf[0]);
-                const int32_t lb = kz[cz] ? (ky[cy] ? leaf[7] : leaf[5]) : (ky[cy] ? leaf[3] : leaf[1]);
-                const bool ryz = iny[cy] && inz[cz];
-                const bool oka = ryz && la >= 0, okb = ryz && lb >= 0;
-                const uint32_t roff = oz[cz] + oy[cy];
-                const uint32_t ea = oka ? (uint32_t)la * 512u + roff : 0u;
-                const uint32_t eb = okb ? (uint32_t)lb * 512u + roff : 0u;
-                float row = 0.0f;
-#pragma unroll
-                for (int cx = 0; cx < NT; ++cx) {
-                    const uint32_t e = (kx[cx] ? eb : ea) + ox[cx];
-                    const bool tap = (kx[cx] ? okb : oka) && inx[cx];
-                    const float v = load_texel<FMT>(leaves + (size_t)(e * TB), 0);
-                    row = __builtin_fmaf(w[0][cx], tap ? v : g.background, row);
-                }
-                plane = __builtin_fmaf(w[1][cy], row, plane);
+            for (int cx = 0; cx < NT; ++cx) {
+                const bool tap = (p + cx >= CV ? ok1 : ok0) && inx[cx];
+                row = __builtin_fmaf(w[0][cx], tap ? t[cx] : g.background, row);
             }
-            acc = __builtin_fmaf(w[2][cz], plane, acc);
+            plane = __builtin_fmaf(w[1][cy], row, plane);
         }
+        acc = __builtin_fmaf(w[2][cz], plane, acc);
     }
     return acc;
+}
+
+template <int FMT, int KIND>
+__device__ __forceinline__ float det_sum_global(const GridView& g, const int (&base)[3], const float (&w)[3][4])
+{
+    int32_t leaf[8];
+    return det_leaves<KIND>(g, base, leaf) ? det_taps<FMT, KIND>(g, base, leaf, w) : det_background<KIND>(g, w);
 }
 
 // Cell, first tap and scaled per-axis weights of a query; false if the
@@ -453,10 +582,14 @@ __device__ __forceinline__ float det_unscale(float acc)
     return acc;
 }
 
+// Deterministic filtering from global memory, one query per thread, at 8
+// waves per SIMD (64 VGPRs): the dependent leaf walks of empty-space queries
+// need the waves to hide their latency, and the tap rows of a query are
+// loaded in two halves to fit.  (FP8 decoding needs more registers: 4 waves.)
 template <int FMT, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_grid_deterministic(GridView g, const float* __restrict__ q, int32_t n,
-                                                              float* __restrict__ out, const int32_t* __restrict__ order,
-                                                              int scatter)
+__global__ __launch_bounds__(BLOCK, FMT == FP8_E4M3 ? 4 : 8) void k_grid_deterministic(GridView g, const float* __restrict__ q, int32_t n,
+                                                                 float* __restrict__ out,
+                                                                 const int32_t* __restrict__ order, int scatter)
 {
     int32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
@@ -600,14 +733,8 @@ __global__ __launch_bounds__(BLOCK) void k_grid_det_staged(GridView g, const flo
         __syncthreads();
         if (!live) return;
         float acc = 0.0f;
-        if (ok && !taps) {   // empty space: the background sums of det_sum_global
-            float row = 0.0f, plane = 0.0f;
-#pragma unroll
-            for (int cx = 0; cx < NT; ++cx) row = __builtin_fmaf(w[0][cx], g.background, row);
-#pragma unroll
-            for (int cy = 0; cy < NT; ++cy) plane = __builtin_fmaf(w[1][cy], row, plane);
-#pragma unroll
-            for (int cz = 0; cz < NT; ++cz) acc = __builtin_fmaf(w[2][cz], plane, acc);
+        if (ok && !taps) {   // empty space
+            acc = det_background<KIND>(g, w);
         } else if (ok) {
 #pragma unroll
             for (int cz = 0; cz < NT; ++cz) {

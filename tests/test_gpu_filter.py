@@ -147,6 +147,35 @@ def test_3d_ragged_domain_and_background(dev):
     t.destroy()
 
 
+@pytest.mark.parametrize("fmt", FMTS)
+def test_3d_every_row_window_offset(dev, fmt):
+    # The deterministic filter reads each row of taps as aligned chunks along
+    # x; sweep the first tap over every offset within a leaf and across leaf
+    # boundaries, next to missing leaves and a domain edge inside a leaf
+    # (x = 29 of the 32 voxels the last leaves hold), with a background that
+    # differs from every texel.
+    rng = np.random.default_rng(11)
+    field = rng.random((16, 16, 32)).astype(np.float32)   # (z, y, x)
+    keep = rng.random((2, 2, 4)) < 0.75
+    keep[0, 0, :] = True
+    o, v = leaves_from_dense(field, keep)
+    dims = (29, 16, 13)
+    inside = (o[:, 0] < dims[0]) & (o[:, 1] < dims[1]) & (o[:, 2] < dims[2])
+    o, v = o[inside], v[inside]
+    raw = synth.encode(v, fmt)
+    t = stf.stf_create_sparse_grid3d(dims, stf.FORMATS[fmt], o, raw, background=0.75)
+    og = oracle.Grid(dims, ORC_FMT[fmt], o, raw, background=0.75)
+    xs = np.arange(-3.0, 33.0, 0.125, dtype=np.float32)   # every cell offset, several t per cell
+    yz = rng.random((xs.size * 8, 2)).astype(np.float32) * np.array([19.0, 16.0], np.float32) - 2.0
+    p = np.stack([np.repeat(xs, 8), yz[:, 0], yz[:, 1]], axis=1).astype(np.float32)
+    q = torch.from_numpy(p).to(dev)
+    for fname, gf, of in FILTERS:
+        gd, _ = stf.filter(t, q, gf, stf.STF_DETERMINISTIC, 0)
+        od, _ = og.filter(p, of, oracle.DET)
+        check_deterministic(gd.cpu().numpy(), od, f"row windows {fmt} {fname}")
+    t.destroy()
+
+
 def test_3d_empty_grid_reads_background(dev):
     t = stf.stf_create_sparse_grid3d((32, 32, 32), stf.STF_FMT_F32, np.zeros((0, 3), np.int32),
                                      np.zeros(0, np.float32), background=0.25)
