@@ -547,6 +547,11 @@ __device__ __forceinline__ f32x16 mlp_batch(const bf16x8& B1, const bf16x8 (&A1)
                                             const bf16x8& ONES)
 {
     const f32x16 Z = {};
+    // A wave in its matrix chain runs at raised issue priority, so the
+    // SIMD's other waves fill the gaps with their VALU work (latent
+    // interpolation, ReLU conversions, tap sums) instead of contending with
+    // it; the chain itself is one dependent sequence per layer.
+    __builtin_amdgcn_s_setprio(1);
     // layer 1: 64 x 16 by 16 x 32 (k 0..7 latents, 8..10 bias terms)
     f32x16 D1[2];
 #pragma unroll
@@ -570,6 +575,7 @@ __device__ __forceinline__ f32x16 mlp_batch(const bf16x8& B1, const bf16x8 (&A1)
     f32x16 D3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AB3, ONES, Z, 0, 0, 0);
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) D3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A3[kb], B3[kb], D3, 0, 0, 0);
+    __builtin_amdgcn_s_setprio(0);
     return D3;
 }
 
