@@ -444,15 +444,34 @@ __device__ __forceinline__ bool det_leaves(const GridView& g, const int (&base)[
         lo[a] = base[a] >> 3;   // leaf coordinate of the first tap (floor for negatives)
         nb[a] = ((base[a] + NT - 1) >> 3) != lo[a];
     }
+    // the walks in lock step, without branches: the root entries of all
+    // leaves are loaded together, then their node entries (a leaf that is
+    // not needed, or outside the domain, loads entry 0 and is discarded), so
+    // a query waits for two loads instead of two per leaf
+    bool use[8];
+    uint32_t roff[8], child[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const bool used = (!(k & 1) || nb[0]) && (!(k & 2) || nb[1]) && (!(k & 4) || nb[2]);
-        int x = (lo[0] + (k & 1)) * 8, y = (lo[1] + ((k >> 1) & 1)) * 8, z = (lo[2] + (k >> 2)) * 8;
-        leaf[k] = used && in_domain(g, x, y, z) ? grid_leaf(g, x, y, z) : -1;
+        const int x = (lo[0] + (k & 1)) * 8, y = (lo[1] + ((k >> 1) & 1)) * 8, z = (lo[2] + (k >> 2)) * 8;
+        use[k] = used && in_domain(g, x, y, z);
+        roff[k] = vgpr_u32(use[k] ? (uint32_t)(((z >> 7) * g.ry + (y >> 7)) * g.rx + (x >> 7)) : 0u);
+        child[k] = ((((uint32_t)z >> 3) & 15u) * 16u + (((uint32_t)y >> 3) & 15u)) * 16u + (((uint32_t)x >> 3) & 15u);
+    }
+    int32_t node[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) node[k] = table_load(g.root, roff[k]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        use[k] = use[k] && node[k] >= 0;
+        leaf[k] = table_load(g.nodes, vgpr_u32(use[k] ? (uint32_t)node[k] * 4096u + child[k] : 0u));
     }
     bool live = false;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) live = live || leaf[k] >= 0;
+    for (int k = 0; k < 8; ++k) {
+        leaf[k] = use[k] ? leaf[k] : -1;
+        live = live || leaf[k] >= 0;
+    }
     return live;
 }
 
