@@ -55,17 +55,32 @@ __device__ __forceinline__ float cross_norm2(V3 a, V3 b)
     return cx * cx + cy * cy + cz * cz;
 }
 
+// The shading arithmetic uses the hardware's reciprocal, square root and
+// reciprocal square root (about one ulp each) instead of correctly rounded
+// division and square root sequences: the shaded value is already sensitive
+// to the binary32 rounding of the half vector at the 1e-5 level, and no
+// decision of the filter depends on it.
+__device__ __forceinline__ float frcp(float x)
+{
+    return __builtin_amdgcn_rcpf(x);
+}
+
+__device__ __forceinline__ float fsqrt(float x)
+{
+    return __builtin_amdgcn_sqrtf(x);
+}
+
 // Smith Lambda of GGX: (-1 + sqrt(1 + alpha^2 tan^2)) / 2.
 __device__ __forceinline__ float lambda_ggx(V3 n, V3 w, float nw, float a2)
 {
-    float tan2 = cross_norm2(n, w) / (nw * nw);
-    return 0.5f * (-1.0f + sqrtf(1.0f + a2 * tan2));
+    float tan2 = cross_norm2(n, w) * frcp(nw * nw);
+    return 0.5f * (-1.0f + fsqrt(1.0f + a2 * tan2));
 }
 
 // f^ for one material, directions in the tangent frame.
 __device__ __forceinline__ void shade(const Material& m, V3 wo, V3 wi, float (&f)[3])
 {
-    V3 n = {m.nx, m.ny, sqrtf(fmaxf(0.0f, 1.0f - m.nx * m.nx - m.ny * m.ny))};
+    V3 n = {m.nx, m.ny, fsqrt(fmaxf(0.0f, 1.0f - m.nx * m.nx - m.ny * m.ny))};
     float alpha = fmaxf(m.rough * m.rough, 1e-3f), a2 = alpha * alpha;
     float no = dot(n, wo), ni = dot(n, wi);
     if (!(no > 0.0f) || !(ni > 0.0f)) {
@@ -73,17 +88,17 @@ __device__ __forceinline__ void shade(const Material& m, V3 wo, V3 wi, float (&f
         return;
     }
     V3 h = {wo.x + wi.x, wo.y + wi.y, wo.z + wi.z};
-    float il = 1.0f / sqrtf(dot(h, h));
+    float il = __builtin_amdgcn_rsqf(dot(h, h));
     h.x *= il;
     h.y *= il;
     h.z *= il;
     float nh = dot(n, h);
     float den = nh * nh * a2 + cross_norm2(n, h);
-    float D = a2 * INV_PI / (den * den);
-    float G2 = 1.0f / (1.0f + lambda_ggx(n, wo, no, a2) + lambda_ggx(n, wi, ni, a2));
+    float D = a2 * INV_PI * frcp(den * den);
+    float G2 = frcp(1.0f + lambda_ggx(n, wo, no, a2) + lambda_ggx(n, wi, ni, a2));
     float x = 1.0f - dot(wi, h), x2 = x * x;
     float F = 0.04f + 0.96f * (x2 * x2 * x);
-    float spec = D * G2 * F / (4.0f * no * ni);
+    float spec = D * G2 * F * frcp(4.0f * no * ni);
 #pragma unroll
     for (int c = 0; c < 3; ++c) f[c] = (m.albedo[c] * INV_PI + spec) * ni;
 }
