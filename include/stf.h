@@ -329,8 +329,10 @@ stf_status stf_filter_moments(const stf_texture* tex, const float* queries_dev, 
  * Only levels 0..2 are reachable by the level rule; further levels are
  * stored but unused.  out_rgb_dev: n x 3 binary32.  out_index_dev: NULL or,
  * in stochastic mode, n x 3 int32 (x, y, level).  Results are binary32
- * evaluations of the formulas above (no bit-exactness is promised for the
- * shaded values; the sampled tap is exact). */
+ * evaluations of the formulas above, reciprocals and square roots by the
+ * hardware's approximations (about one ulp each); no bit-exactness is
+ * promised for the shaded values (they agree with a binary64 evaluation to
+ * 1e-4 relative + 1e-6 absolute), the sampled tap is exact. */
 stf_status stf_shade_filter(const stf_texture* material, const float* shade_queries_dev, int64_t n,
                             stf_filter_kind filter, stf_shade_mode mode, uint64_t seed,
                             float* out_rgb_dev, int32_t* out_index_dev, void* hip_stream);
