@@ -565,7 +565,9 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __res
             if constexpr (GMODE == GAUSS_FIS) {
                 const double r = sqrt(-2.0 * log(1.0 - u0));
                 const double a = 6.28318530717958647692 * u1;
-                const double xs = xe + sg * (r * cos(a)), ys = ye + sg * (r * sin(a));
+                double sa, ca;
+                sincos(a, &sa, &ca);   // one argument reduction for both
+                const double xs = xe + sg * (r * ca), ys = ye + sg * (r * sa);
                 sx = (int)fmin(fmax(floor(xs + 0.5), -1.0), (double)S.w());
                 sy = (int)fmin(fmax(floor(ys + 0.5), -1.0), (double)S.h());
             } else {
