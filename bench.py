@@ -398,7 +398,9 @@ def run_dct(args, torch, stf, synth):
                                        ("stoch_keys", stf.STF_CUBIC_KEYS, stf.STF_STOCHASTIC, 16, q),
                                        ("det_keys", stf.STF_CUBIC_KEYS, stf.STF_DETERMINISTIC, 16, q),
                                        ("stoch_linear_random_uv", stf.STF_LINEAR, stf.STF_STOCHASTIC, 4, q_rand),
-                                       ("det_linear_random_uv", stf.STF_LINEAR, stf.STF_DETERMINISTIC, 4, q_rand)):
+                                       ("det_linear_random_uv", stf.STF_LINEAR, stf.STF_DETERMINISTIC, 4, q_rand),
+                                       ("stoch_cubic_random_uv", stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 16, q_rand),
+                                       ("det_cubic_random_uv", stf.STF_CUBIC_BSPLINE, stf.STF_DETERMINISTIC, 16, q_rand)):
         decodes = (2 if filt in stf.POSITIVIZED_FILTERS else 1) if mode == stf.STF_STOCHASTIC else taps
         wall, kern = time_launches(lambda: stf.stf_filter(tex, qq, filt, mode, 11, out), args.steps, args.warmup,
                                    torch)

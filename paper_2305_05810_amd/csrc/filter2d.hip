@@ -678,11 +678,12 @@ void launch2d_kind(const Src& S, const float* q, int32_t n, int mode, uint32_t k
                                key, out, idx, order, scatter);
     } else {
         if constexpr (Src::DECODES && KIND != KIND_LINEAR) {
-            if (order) {   // a sorted stream of a decoded source: the 16 taps of neighbours share decodes
-                hipLaunchKernelGGL((k_tex2d_det_staged<Src, KIND>), grid, block, 0, stream, S, q, n, out, order,
-                                   scatter);
-                return;
-            }
+            // a decoded source: neighbouring queries of a sorted stream or of
+            // a frame in pixel order share most of their 16 taps, so a block
+            // decodes its tap box once when the box is small enough (the
+            // kernel decides per block and otherwise decodes per tap)
+            hipLaunchKernelGGL((k_tex2d_det_staged<Src, KIND>), grid, block, 0, stream, S, q, n, out, order, scatter);
+            return;
         }
         hipLaunchKernelGGL((k_tex2d_deterministic<Src, KIND>), grid, block, 0, stream, S, q, n, out, order, scatter);
     }
