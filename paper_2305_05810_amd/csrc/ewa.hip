@@ -261,7 +261,7 @@ __global__ __launch_bounds__(BLOCK) void k_ewa(EwaLevels P, EwaLut lut_in, const
         }
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) out[(int64_t)i * C + c] = v[c];
+    for (int c = 0; c < C; ++c) __builtin_nontemporal_store(v[c], out + (int64_t)i * C + c);   // streamed out
     if (STOCH && idx) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) idx[3 * (int64_t)i + k] = ix[k];

