@@ -119,7 +119,10 @@ __global__ __launch_bounds__(BLOCK) void k_shade(Levels L, const float* __restri
 {
     int32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
-    const float* r = q + 9 * (int64_t)i;
+    const float* e = q + 9 * (int64_t)i;
+    float r[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) r[k] = __builtin_nontemporal_load(e + k);   // streamed in
     float u = r[0], v = r[1], s = r[2];
     V3 wo = {r[3], r[4], r[5]}, wi = {r[6], r[7], r[8]};
     int l = (int)(s >= 1.41421354f) + (int)(s >= 2.82842708f);
