@@ -606,9 +606,9 @@ __device__ __forceinline__ float det_unscale(float acc)
 // need the waves to hide their latency, and the tap rows of a query are
 // loaded in two halves to fit.  (FP8 decoding needs more registers: 4 waves.)
 template <int FMT, int KIND>
-__global__ __launch_bounds__(BLOCK, FMT == FP8_E4M3 ? 4 : 8) void k_grid_deterministic(GridView g, const float* __restrict__ q, int32_t n,
-                                                                 float* __restrict__ out,
-                                                                 const int32_t* __restrict__ order, int scatter)
+__global__ __launch_bounds__(BLOCK, FMT == FP8_E4M3 ? 4 : 8) void k_grid_deterministic(
+    GridView g, const float* __restrict__ q, int32_t n, float* __restrict__ out, const int32_t* __restrict__ order,
+    int scatter)
 {
     int32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
