@@ -145,7 +145,8 @@ def test_dct_sorted_stream_staged_decode(dev, fname, gf, of, W, H, C):
     """A Morton-sorted stream: deterministic bicubic blocks decode the texels
     of their taps once into LDS (blocks whose taps span too many texels decode
     per tap).  Values within the bar of the oracle, and bit for bit those of
-    the unsorted call (which decodes per tap)."""
+    the unsorted call (uniform uv: its blocks' boxes are too large to stage,
+    so every tap is decoded on its own)."""
     tex = _texture(H, W, C, seed=W + 7)
     words = stf.stf_dct_encode(tex)
     t = stf.stf_create_dct_texture2d(W, H, C, words)
@@ -161,4 +162,32 @@ def test_dct_sorted_stream_staged_decode(dev, fname, gf, of, W, H, C):
     A = _abs_terms(words).astype(np.float32)
     dscale, _ = oracle.filter2d(A, oracle.F32, uv, of, oracle.DET_ABS)
     assert np.all((np.isnan(gd) & np.isnan(od)) | (np.abs(gd - od) <= REL * dscale)), fname
+    t.destroy()
+
+
+@pytest.mark.parametrize("fname,gf,of", FILTERS[1:])
+def test_dct_frame_order_staged_decode(dev, fname, gf, of):
+    """A frame in pixel order magnifying the texture: each block's 256 pixels
+    cover a small texel box, so deterministic bicubic / Keys / Mitchell blocks
+    decode that box once into LDS.  The same queries shuffled (no block box
+    fits, every tap decoded on its own) give the same bits, and both meet the
+    oracle's bar."""
+    W, H, C = 96, 80, 9
+    tex = _texture(H, W, C, seed=W + 11)
+    words = stf.stf_dct_encode(tex)
+    t = stf.stf_create_dct_texture2d(W, H, C, words)
+    fw, fh = 4 * W, 4 * H
+    ys, xs = np.mgrid[0:fh, 0:fw]
+    uv = np.stack([(xs + 0.37) / fw, (ys + 0.61) / fh], axis=-1).reshape(-1, 2).astype(np.float32)
+    perm = np.random.default_rng(12).permutation(uv.shape[0])
+    framed, _ = stf.filter(t, torch.from_numpy(uv).to(dev), gf, stf.STF_DETERMINISTIC, 0)
+    shuffled, _ = stf.filter(t, torch.from_numpy(uv[perm]).to(dev), gf, stf.STF_DETERMINISTIC, 0)
+    back = torch.empty_like(shuffled)
+    back[torch.from_numpy(perm).to(dev)] = shuffled
+    assert torch.equal(framed, back), fname
+    gd = framed.cpu().numpy().astype(np.float64)
+    od, _ = oracle.dct_filter2d(words, uv, of, oracle.DET)
+    A = _abs_terms(words).astype(np.float32)
+    dscale, _ = oracle.filter2d(A, oracle.F32, uv, of, oracle.DET_ABS)
+    assert np.all(np.abs(gd - od) <= REL * dscale), fname
     t.destroy()
