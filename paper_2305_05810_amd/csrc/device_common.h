@@ -156,20 +156,20 @@ __device__ __forceinline__ float dec_bf16(uint16_t h)
     return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
 
+// OCP E4M3 "FN": bias 7, subnormals m * 2^-9, no infinity, S.1111.111 NaN.
+// gfx950's conversion instruction implements exactly this format: for all 256
+// codes it returns the same binary32 bits as the definition (sign, exponent
+// e - 7 + 127 for e >= 1, m * 2^-9 for e = 0) and a NaN for the two NaN codes.
+// `sel` picks the byte of q (a constant 0..3).
+template <int sel = 0>
+__device__ __forceinline__ float dec_e4m3_byte(uint32_t q)
+{
+    return __builtin_amdgcn_cvt_f32_fp8((int)q, sel);
+}
+
 __device__ __forceinline__ float dec_e4m3(uint32_t q)
 {
-    // OCP E4M3 "FN": bias 7, subnormals m * 2^-9, no infinity, S.1111.111 NaN.
-    uint32_t mag = q & 0x7fu;
-    uint32_t sign = (q & 0x80u) << 24;
-    float v;
-    if (mag >= 8u) {
-        // normal: exponent field e >= 1 -> binary32 exponent e - 7 + 127
-        v = __builtin_bit_cast(float, (mag << 20) + (120u << 23));
-        if (mag == 0x7fu) v = __builtin_nanf("");
-    } else {
-        v = (float)mag * 0x1p-9f;
-    }
-    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) | sign);
+    return dec_e4m3_byte<0>(q);
 }
 
 __device__ __forceinline__ float dec_u8(uint32_t v)

@@ -422,10 +422,16 @@ __device__ __forceinline__ void window_taps(const uint2& c0, const uint2& c1, in
     // p in 0..7: tap j is byte p + j of the 16-byte window
     const uint32_t lo = (p & 4) ? c0.y : c0.x, hi = (p & 4) ? c1.x : c0.y;
     const uint32_t wd = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(p & 3) * 8u);
+    if constexpr (FMT == FP8_E4M3) {
+        t[0] = dec_e4m3_byte<0>(wd);
+        t[1] = dec_e4m3_byte<1>(wd);
+        if constexpr (NT == 4) {
+            t[2] = dec_e4m3_byte<2>(wd);
+            t[3] = dec_e4m3_byte<3>(wd);
+        }
+    } else {
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const uint32_t b = (wd >> (8 * j)) & 0xffu;
-        t[j] = FMT == FP8_E4M3 ? dec_e4m3(b) : dec_u8(b);
+        for (int j = 0; j < NT; ++j) t[j] = dec_u8((wd >> (8 * j)) & 0xffu);
     }
 }
 
@@ -604,9 +610,9 @@ __device__ __forceinline__ float det_unscale(float acc)
 // Deterministic filtering from global memory, one query per thread, at 8
 // waves per SIMD (64 VGPRs): the dependent leaf walks of empty-space queries
 // need the waves to hide their latency, and the tap rows of a query are
-// loaded in two halves to fit.  (FP8 decoding needs more registers: 4 waves.)
+// loaded in two halves to fit.
 template <int FMT, int KIND>
-__global__ __launch_bounds__(BLOCK, FMT == FP8_E4M3 ? 4 : 8) void k_grid_deterministic(
+__global__ __launch_bounds__(BLOCK, 8) void k_grid_deterministic(
     GridView g, const float* __restrict__ q, int32_t n, float* __restrict__ out, const int32_t* __restrict__ order,
     int scatter)
 {

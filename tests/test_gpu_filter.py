@@ -75,6 +75,22 @@ def test_2d_parity(dev, tex2d_inputs, fmt, fname, gf, of):
     t.destroy()
 
 
+@pytest.mark.parametrize("fmt", ["fp8_e4m3", "u8"])
+def test_2d_every_8bit_code(dev, fmt):
+    # A 16 x 16 texture holding each of the 256 codes once (NaN codes
+    # included), read at the texel centres: every decode against the
+    # oracle's, bit for bit (NaN for NaN).
+    raw = np.arange(256, dtype=np.uint8).reshape(16, 16, 1)
+    t = stf.stf_create_texture2d(16, 16, 1, stf.FORMATS[fmt], [raw])
+    ys, xs = np.mgrid[0:16, 0:16]
+    uv = np.stack([(xs + 0.5) / 16, (ys + 0.5) / 16], axis=-1).reshape(-1, 2).astype(np.float32)
+    gv, gi = stf.filter(t, torch.from_numpy(uv).to(dev), stf.STF_LINEAR, stf.STF_STOCHASTIC, 5, want_index=True)
+    ov, oi = oracle.filter2d(raw, ORC_FMT[fmt], uv, oracle.LINEAR, oracle.STOCH, 5)
+    check_stochastic(gv.cpu().numpy(), gi.cpu().numpy(), ov, oi, fmt, f"every {fmt} code")
+    assert np.array_equal(oi[:, 1] * 16 + oi[:, 0], np.arange(256))   # each code read once
+    t.destroy()
+
+
 @pytest.mark.parametrize("channels", [1, 2, 3])
 def test_2d_channel_counts(dev, channels):
     tex = synth.texture2d(40, 24, channels, seed=3)
