@@ -172,9 +172,18 @@ __device__ __forceinline__ float dec_e4m3(uint32_t q)
     return dec_e4m3_byte<0>(q);
 }
 
+// v / 255 correctly rounded, for v = 0..255: the product with fl(1/255) and
+// one residual correction, e = v - q 255 and q + e fl(1/255) (each an FMA,
+// so rounded once), reaches the correctly rounded quotient for every one of
+// the 256 codes (checked in exact rational arithmetic), without a division
+// sequence.
 __device__ __forceinline__ float dec_u8(uint32_t v)
 {
-    return (float)v / 255.0f;   // correctly rounded binary32 division
+    constexpr float R = 0x1.010102p-8f;   // fl(1/255)
+    const float x = (float)v;             // exact
+    const float q = x * R;
+    const float e = __builtin_fmaf(-q, 255.0f, x);
+    return __builtin_fmaf(e, R, q);
 }
 
 template <int FMT>
