@@ -574,7 +574,7 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __res
                 // 5.5e-6 sigma texels of the binary64 offset (r <= 5.8).  A
                 // sample at least sigma 2^-14 from a texel edge therefore takes
                 // the same texel as the binary64 sample; nearer ones (about one
-                // query in 10^4 per unit sigma) redo the offset in binary64.
+                // query in 4,000 per unit sigma) redo the offset in binary64.
                 const float rf = sqrtf(-2.0f * logf(1.0f - u0f));
                 float sf, cf;
                 sincosf(6.28318530717958647692f * u1f, &sf, &cf);
