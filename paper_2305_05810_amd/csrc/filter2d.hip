@@ -545,6 +545,27 @@ __device__ __forceinline__ int gauss_pick(const double (&m)[4], double u)
     return j > last ? last : j;
 }
 
+// The discrete pick with binary32 weights, for sigma >= 1/4 (every weight is
+// then at least e^-32: none underflows and none is clamped).  Each weight is
+// within 1.5e-5 relative of its binary64 value (|exponent| <= 32, a few ulps
+// in d^2, 1/(2 sigma^2) and expf), so u * total and the cumulative sums lie
+// within 3e-5 total of theirs; where u * total is at least total 2^-12 from
+// every cumulative sum, the pick is the binary64 pick.  Returns -1 otherwise.
+__device__ __forceinline__ int gauss_pick_fast(float t, float inv2s2, float u)
+{
+    float m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float d = (float)(k - 1) - t;
+        m[k] = expf(-(d * d) * inv2s2);
+    }
+    const float c1 = m[0], c2 = m[0] + m[1], c3 = (m[0] + m[1]) + m[2];
+    const float total = c3 + m[3];
+    const float T = u * total;
+    if (fminf(fminf(fabsf(T - c1), fabsf(T - c2)), fabsf(T - c3)) < total * 0x1p-12f) return -1;
+    return (T >= c1) + (T >= c2) + (T >= c3);
+}
+
 template <class Src, int GMODE>
 __global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __restrict__ q, int32_t n, float sigma,
                                                        int32_t radius, uint32_t key, float* __restrict__ out,
@@ -595,11 +616,23 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __res
                 sy = (int)fmin(fmax(fy, -1.0), (double)S.h());
             } else {
                 const double inv2s2 = 1.0 / (2.0 * sg * sg);
-                double wx[4], wy[4];
-                gauss_discrete_weights(xe - floor(xe), inv2s2, wx);
-                gauss_discrete_weights(ye - floor(ye), inv2s2, wy);
-                sx = cx - 1 + gauss_pick(wx, u0);
-                sy = cy - 1 + gauss_pick(wy, u1);
+                int jx = -1, jy = -1;
+                if (sigma >= 0.25f) {
+                    jx = gauss_pick_fast(x - floorf(x), (float)inv2s2, u0f);
+                    jy = gauss_pick_fast(y - floorf(y), (float)inv2s2, u1f);
+                }
+                if (jx < 0) {
+                    double wx[4];
+                    gauss_discrete_weights(xe - floor(xe), inv2s2, wx);
+                    jx = gauss_pick(wx, u0);
+                }
+                if (jy < 0) {
+                    double wy[4];
+                    gauss_discrete_weights(ye - floor(ye), inv2s2, wy);
+                    jy = gauss_pick(wy, u1);
+                }
+                sx = cx - 1 + jx;
+                sy = cy - 1 + jy;
             }
             sx = clampi(sx, S.w() - 1);
             sy = clampi(sy, S.h() - 1);
