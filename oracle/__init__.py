@@ -39,6 +39,30 @@ def lib():
     return _lib
 
 
+class using_library:
+    """Context manager: every function of this module calls the library at
+    `path` (a separately built copy of the oracle's C sources) instead of
+    liboracle.so until the block ends.  The tests use it to check that a
+    pin fails when a mistake is planted in a copy of the oracle."""
+
+    def __init__(self, path: str):
+        self.path = path
+        self.saved = None
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        alt = C.CDLL(self.path)
+        _declare(alt)
+        _lib = alt
+        return alt
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
 def _p(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
 
@@ -95,6 +119,10 @@ def _declare(L):
     L.orc_fis_tap.argtypes, L.orc_fis_tap.restype = [i32, dbl, u64, u32, i32], i32
     L.orc_ewa_lut_value.argtypes, L.orc_ewa_lut_value.restype = [i32], C.c_float
     L.orc_ewa_lods.argtypes, L.orc_ewa_lods.restype = [vp, i64, i32, C.c_float, vp], i32
+    L.orc_ewa_weights.argtypes = [i32, i32, C.c_float, C.c_float, vp, vp, i64, vp, vp]
+    L.orc_ewa_weights.restype = i64
+    L.orc_ewa_listing_draws.argtypes = [i32, i32, C.c_float, C.c_float, vp, vp, u64, i64, vp]
+    L.orc_ewa_listing_draws.restype = i64
     L.orc_ewa_filter2d.argtypes = [vp, vp, vp, i32, i32, i32, vp, i64, C.c_float, i32, u64, vp, vp, i32]
     L.orc_ewa_filter2d.restype = i32
     L.orc_gauss_radius.argtypes, L.orc_gauss_radius.restype = [dbl], i32
@@ -122,6 +150,8 @@ def _declare_shade(L):
     L.orc_shade_eval.restype = None
     L.orc_ggx_D.argtypes = [vp, vp, dbl]
     L.orc_ggx_D.restype = dbl
+    L.orc_ggx_terms.argtypes = [vp, vp, vp, dbl, vp]
+    L.orc_ggx_terms.restype = None
     L.orc_shade_level.argtypes = [C.c_float, i32]
     L.orc_shade_level.restype = i32
 
@@ -331,6 +361,29 @@ def gauss_fis_positions(W: int, H: int, uv: np.ndarray, sigma: float, seed: int)
 # ----------------------------------------------------------------------------
 def ewa_lut(i: int) -> float:
     return lib().orc_ewa_lut_value(i)
+
+
+def ewa_weights(W: int, H: int, s: float, t: float, d0, d1):
+    """The taps of positive EWA weight on a W x H level for the query (s, t)
+    with derivative vectors d0, d1 (texture units): (xy int32 (k, 2), w
+    float32 (k,)) in scan order, coordinates not clamped."""
+    a = np.ascontiguousarray(d0, np.float32)
+    b = np.ascontiguousarray(d1, np.float32)
+    n = lib().orc_ewa_weights(W, H, float(np.float32(s)), float(np.float32(t)), _p(a), _p(b), 0, None, None)
+    xy = np.zeros((max(n, 1), 2), np.int32)
+    w = np.zeros(max(n, 1), np.float32)
+    lib().orc_ewa_weights(W, H, float(np.float32(s)), float(np.float32(t)), _p(a), _p(b), n, _p(xy), _p(w))
+    return xy[:n], w[:n]
+
+
+def ewa_listing_draws(W: int, H: int, s: float, t: float, d0, d1, seed: int, K: int) -> np.ndarray:
+    """K taps drawn by the supplement's single-uniform reservoir sampler
+    (distribution tests only): int32 (K, 2)."""
+    a = np.ascontiguousarray(d0, np.float32)
+    b = np.ascontiguousarray(d1, np.float32)
+    xy = np.zeros((K, 2), np.int32)
+    lib().orc_ewa_listing_draws(W, H, float(np.float32(s)), float(np.float32(t)), _p(a), _p(b), seed, K, _p(xy))
+    return xy
 
 
 def ewa_lods(q: np.ndarray, levels: int, max_aniso: float) -> np.ndarray:
@@ -557,6 +610,17 @@ def shade_eval(mat6, wo, wi) -> np.ndarray:
 
 def ggx_D(n, h, alpha: float) -> float:
     return lib().orc_ggx_D(_p(np.ascontiguousarray(n, np.float64)), _p(np.ascontiguousarray(h, np.float64)), alpha)
+
+
+def ggx_terms(n, wo, wi, alpha: float) -> dict:
+    """D(h), Lambda(wo), Lambda(wi), G2 and Schlick F of the GGX lobe used by
+    shade_eval, for unit vectors n, wo, wi."""
+    a = np.ascontiguousarray(n, np.float64)
+    b = np.ascontiguousarray(wo, np.float64)
+    c = np.ascontiguousarray(wi, np.float64)
+    out = np.zeros(5, np.float64)
+    lib().orc_ggx_terms(_p(a), _p(b), _p(c), float(alpha), _p(out))
+    return dict(D=out[0], lambda_o=out[1], lambda_i=out[2], G2=out[3], F=out[4])
 
 
 def shade_level(s: float, levels: int) -> int:

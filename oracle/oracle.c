@@ -61,10 +61,10 @@ enum { ORC_DET = 0, ORC_STOCH = 1, ORC_STOCH_REUSE = 2, ORC_DET_ABS = 3, ORC_STO
 /* Counter-based random numbers.                                             */
 /* The paper draws its per-lookup uniforms from white or blue noise (Results, */
 /* real-time section).  A counter-based generator makes the draw a pure       */
-/* function of (seed, query, axis): the one-round PCG hash "pcg" published by */
-/* Jarzynski and Olano (JCGT 9(3), 2020), chained as                          */
-/*   s = pcg(seed_lo ^ pcg(seed_hi)),  h_0 = pcg(s ^ qid),                   */
-/*   h_a = pcg(h_0 + a) for a >= 1,                                           */
+/* function of (seed, query, hash index): the one-round PCG hash "pcg"        */
+/* published by Jarzynski and Olano (JCGT 9(3), 2020), chained as             */
+/*   s = pcg(seed_lo ^ pcg(seed_hi)),  b = pcg(s ^ qid),                      */
+/*   h_a = pcg(b + a) for every hash index a >= 0 (a = 0, 1, 2: axes x, y, z),*/
 /*   u_a = (h_a >> 8) * 2^-24  in [0, 1 - 2^-24].                             */
 /* ------------------------------------------------------------------------ */
 uint32_t orc_pcg(uint32_t x)
@@ -81,8 +81,8 @@ uint32_t orc_seed_key(uint64_t seed)
 
 float orc_uniform(uint64_t seed, uint32_t qid, uint32_t axis)
 {
-    uint32_t h = orc_pcg(orc_seed_key(seed) ^ qid);
-    if (axis > 0) h = orc_pcg(h + axis);
+    uint32_t b = orc_pcg(orc_seed_key(seed) ^ qid);
+    uint32_t h = orc_pcg(b + axis);
     return (float)(h >> 8) * 0x1p-24f;
 }
 
@@ -234,22 +234,20 @@ static int orc_cell(float x, int* i, float* t)
 /*   Linear: the upper tap iff u < t (the strict comparison of the bilinear   */
 /*           listing; P(upper) = t, Eq. stochastic-lerp).                     */
 /*   Cubic:  breakpoints at the cumulative B-spline weights of Eq.            */
-/*           cubic-bspline, c1 = w0 = s^3/6, c3 = 1 - w3 = 1 - t^3/6 and      */
-/*           c2 = w0 + w1 = 1/2 - (3/4) d + d^3/3 with s = 1 - t, d = t - 1/2  */
-/*           (the polynomial w0 + w1 expanded about t = 1/2), evaluated as     */
-/*             c1 = ((s*s)*s)*K6,  c3 = 1 - ((t*t)*t)*K6,                    */
-/*             c2 = fma(d, fma(d*d, K3, -0.75), 0.5),                          */
-/*           K6 = fl32(1/6), K3 = fl32(1/3), each fma rounded once;            */
+/*           cubic-bspline, c1 = w0, c2 = w0 + w1, c3 = 1 - w3, with          */
+/*           w0 = s^3/6, w1 = (4 + 3 t^2 (t - 2))/6, w3 = t^3/6, s = 1 - t,    */
+/*           evaluated in binary32 as written, each operation rounded once:  */
+/*             c1 = ((s*s)*s)*K6,                                             */
+/*             c2 = c1 + (4 + (3*(t*t))*(t - 2))*K6,                          */
+/*             c3 = 1 - ((t*t)*t)*K6,          K6 = fl32(1/6);                */
 /*           j = [u>=c1] + [u>=c2] + [u>=c3].                                 */
 /* Returns the offset of the chosen tap from cell i (0/1 linear, -1..2 cubic).*/
 void orc_cubic_breakpoints(float t, float c[3])
 {
     const float K6 = 0x1.555556p-3f;   /* (float)(1/6) */
-    const float K3 = 0x1.555556p-2f;   /* (float)(1/3) */
     float s = 1.0f - t;
-    float d = t - 0.5f;
     c[0] = ((s * s) * s) * K6;
-    c[1] = fmaf(d, fmaf(d * d, K3, -0.75f), 0.5f);
+    c[1] = c[0] + (4.0f + (3.0f * (t * t)) * (t - 2.0f)) * K6;
     c[2] = 1.0f - ((t * t) * t) * K6;
 }
 
@@ -1154,7 +1152,9 @@ int orc_gauss_fis_positions(int W, int H, const float* uv, int64_t n, double sig
 /*   Level of detail lod = max(0, (levels - 1) + log2(shorter)) in binary64; */
 /*   deterministic: lerp(lod - floor(lod), EWA(floor), EWA(floor + 1));       */
 /*   stochastic: level floor(lod) + [u0 < lod - floor(lod)] (hash index 0).  */
-/*   Levels past the last read the last level.                              */
+/*   The pyramid ends at a single texel (level sizes max(1, W >> l)), and a  */
+/*   level at or past that last one yields that texel (pbrt's rule), so no   */
+/*   footprint, however large, makes the scan over a bounding box unbounded. */
 /*   EWA on level l (resolution W x H, binary32 as pbrt): st = (s W - 0.5,    */
 /*   t H - 0.5), d0 = dst0 (W, H), d1 = dst1 (W, H);                          */
 /*     A = (d0y^2 + d1y^2) + 1, B = -2 (d0x d0y + d1x d1y), C = (d0x^2 + d1x^2) + 1, */
@@ -1171,6 +1171,10 @@ int orc_gauss_fis_positions(int W, int H, const float* uv, int64_t n, double sig
 /*   running sum of R), then a tap of that row: T = u1 R, the first tap whose */
 /*   running sum exceeds T (the last tap with weight if none does).  One     */
 /*   pass over the box and one over a row; the value is that texel.          */
+/*   This draw is not the supplement's listing, which takes single taps by   */
+/*   reservoir sampling with one re-scaled uniform (orc_ewa_listing_draws    */
+/*   below); both draw tap (x, y) with probability w(x, y) / sum w, the row  */
+/*   rule with fresh uniforms and no divisions, so its outcome is unique.    */
 /* Values in binary64; the weights are the binary32 LUT values.              */
 /* ------------------------------------------------------------------------ */
 static float orc_ewa_lut[128];
@@ -1202,13 +1206,18 @@ static double orc_ewa_texel(const orc_ewa_tex* T, int l, int x, int y, int c)
     return orc_src_texel(&s, x, y, c);
 }
 
-/* EWA on one level: the deterministic value (per channel) and/or the drawn
- * tap. */
-static void orc_ewa_level(const orc_ewa_tex* T, int l, float s, float t, const float d0in[2], const float d1in[2],
-                          int stochastic, float u, uint64_t seed, uint32_t qid, double* out, int* tx, int* ty)
+/* The ellipse of one level in texel units (pbrt's construction, each
+ * binary32 operation rounded once in the order written) and its bounding box. */
+typedef struct orc_ellipse {
+    float stx, sty, A, B, C;
+    int s0, s1, t0, t1;
+} orc_ellipse;
+
+static orc_ellipse orc_ewa_ellipse(int W, int H, float s, float t, const float d0in[2], const float d1in[2])
 {
-    const int W = T->W[l], H = T->H[l];
-    float stx = s * (float)W - 0.5f, sty = t * (float)H - 0.5f;
+    orc_ellipse e;
+    e.stx = s * (float)W - 0.5f;
+    e.sty = t * (float)H - 0.5f;
     float d0x = d0in[0] * (float)W, d0y = d0in[1] * (float)H;
     float d1x = d1in[0] * (float)W, d1y = d1in[1] * (float)H;
     float A = (d0y * d0y + d1y * d1y) + 1.0f;
@@ -1221,25 +1230,117 @@ static void orc_ewa_level(const orc_ewa_tex* T, int l, float s, float t, const f
     float det = -(B * B) + 4.0f * A * Cc;
     float invDet = 1.0f / det;
     float us = sqrtf(fmaxf(det * Cc, 0.0f)), vs = sqrtf(fmaxf(A * det, 0.0f));
-    int s0 = (int)ceilf(stx - 2.0f * invDet * us), s1 = (int)floorf(stx + 2.0f * invDet * us);
-    int t0 = (int)ceilf(sty - 2.0f * invDet * vs), t1 = (int)floorf(sty + 2.0f * invDet * vs);
+    e.s0 = (int)ceilf(e.stx - 2.0f * invDet * us);
+    e.s1 = (int)floorf(e.stx + 2.0f * invDet * us);
+    e.t0 = (int)ceilf(e.sty - 2.0f * invDet * vs);
+    e.t1 = (int)floorf(e.sty + 2.0f * invDet * vs);
+    e.A = A;
+    e.B = B;
+    e.C = Cc;
+    return e;
+}
+
+/* The LUT weight of tap (is, it): 0 outside the ellipse (r2 >= 1). */
+static float orc_ewa_weight(const orc_ellipse* e, int is, int it)
+{
+    float ss = (float)is - e->stx, tt = (float)it - e->sty;
+    float r2 = (e->A * (ss * ss) + (e->B * ss) * tt) + e->C * (tt * tt);
+    if (!(r2 < 1.0f)) return 0.0f;
+    int idx = (int)(r2 * 128.0f);
+    if (idx > 127) idx = 127;
+    return orc_ewa_lut[idx];
+}
+
+/* The taps of positive weight of the ellipse on a W x H level, in scan order
+ * (rows t0..t1, each s0..s1; coordinates not clamped).  Writes at most cap
+ * taps (x, y pairs in xy, weights in w) and returns how many there are. */
+int64_t orc_ewa_weights(int W, int H, float s, float t, const float* d0, const float* d1, int64_t cap, int32_t* xy,
+                        float* w)
+{
+    orc_ewa_init();
+    orc_ellipse e = orc_ewa_ellipse(W, H, s, t, d0, d1);
+    int64_t n = 0;
+    for (int it = e.t0; it <= e.t1; ++it)
+        for (int is = e.s0; is <= e.s1; ++is) {
+            float wt = orc_ewa_weight(&e, is, it);
+            if (!(wt > 0.0f)) continue;
+            if (n < cap) {
+                xy[2 * n] = is;
+                xy[2 * n + 1] = it;
+                w[n] = wt;
+            }
+            ++n;
+        }
+    return n;
+}
+
+/* The supplement's own sampler ("Stochastic sampling of the EWA kernel"),
+ * for distribution tests only: one pass over the box in scan order with
+ * weighted reservoir sampling of single taps driven by one uniform u, which
+ * is re-scaled after every decision (u/p when the tap is taken, (u-p)/(1-p)
+ * otherwise, p = w / running sum, binary32), kept below 1 as in the
+ * reuse sampler above.  Draws K taps for one query, draw k with the
+ * uniform of query k, hash index 1.  Returns the number of taps in the box. */
+int64_t orc_ewa_listing_draws(int W, int H, float s, float t, const float* d0, const float* d1, uint64_t seed,
+                              int64_t K, int32_t* xy)
+{
+    orc_ewa_init();
+    orc_ellipse e = orc_ewa_ellipse(W, H, s, t, d0, d1);
+    int64_t taps = 0;
+    for (int64_t k = 0; k < K; ++k) {
+        float u = orc_uniform(seed, (uint32_t)k, 1), sum = 0.0f;
+        int cx = e.s0, cy = e.t0;
+        taps = 0;
+        for (int it = e.t0; it <= e.t1; ++it)
+            for (int is = e.s0; is <= e.s1; ++is) {
+                float wt = orc_ewa_weight(&e, is, it);
+                if (!(wt > 0.0f)) continue;
+                ++taps;
+                sum += wt;
+                float p = wt / sum;
+                if (u < p) {
+                    cx = is;
+                    cy = it;
+                    u = u / p;
+                } else {
+                    u = (u - p) / (1.0f - p);
+                }
+                if (!(u < 1.0f)) u = 0x1.fffffep-1f;
+                if (!(u >= 0.0f)) u = 0.0f;
+            }
+        xy[2 * k] = cx;
+        xy[2 * k + 1] = cy;
+    }
+    return taps;
+}
+
+/* EWA on one level: the deterministic value (per channel) and/or the drawn
+ * tap.  The last level of a full pyramid is a single texel, which is the
+ * value (and the tap) whatever the ellipse: pbrt reads it directly, so the
+ * work stays bounded for footprints larger than the texture. */
+static void orc_ewa_level(const orc_ewa_tex* T, int l, float s, float t, const float d0in[2], const float d1in[2],
+                          int stochastic, float u, uint64_t seed, uint32_t qid, double* out, int* tx, int* ty)
+{
+    if (l == T->levels - 1) {
+        if (stochastic) {
+            *tx = 0;
+            *ty = 0;
+        } else {
+            for (int c = 0; c < T->C; ++c) out[c] = orc_ewa_texel(T, l, 0, 0, c);
+        }
+        return;
+    }
+    const orc_ellipse e = orc_ewa_ellipse(T->W[l], T->H[l], s, t, d0in, d1in);
     if (!stochastic) {
         double acc[16] = {0};
         double wsum = 0.0;
-        for (int it = t0; it <= t1; ++it) {
-            float tt = (float)it - sty;
-            for (int is = s0; is <= s1; ++is) {
-                float ss = (float)is - stx;
-                float r2 = (A * (ss * ss) + (B * ss) * tt) + Cc * (tt * tt);
-                if (!(r2 < 1.0f)) continue;
-                int idx = (int)(r2 * 128.0f);
-                if (idx > 127) idx = 127;
-                float w = orc_ewa_lut[idx];
+        for (int it = e.t0; it <= e.t1; ++it)
+            for (int is = e.s0; is <= e.s1; ++is) {
+                float w = orc_ewa_weight(&e, is, it);
                 if (!(w > 0.0f)) continue;
                 wsum += (double)w;
                 for (int c = 0; c < T->C; ++c) acc[c] += (double)w * orc_ewa_texel(T, l, is, it, c);
             }
-        }
         for (int c = 0; c < T->C; ++c) out[c] = acc[c] / wsum;
         return;
     }
@@ -1248,33 +1349,23 @@ static void orc_ewa_level(const orc_ewa_tex* T, int l, float s, float t, const f
      * running sum of row sums), then a tap of that row by the cumulative rule
      * (T = u1 * R, the first tap whose running sum exceeds T) */
     float S = 0.0f, Rsel = 0.0f;
-    int rsel = t0, found = 0;
-    for (int it = t0; it <= t1; ++it) {
-        float tt = (float)it - sty, R = 0.0f;
-        for (int is = s0; is <= s1; ++is) {
-            float ss = (float)is - stx;
-            float r2 = (A * (ss * ss) + (B * ss) * tt) + Cc * (tt * tt);
-            if (!(r2 < 1.0f)) continue;
-            int idx = (int)(r2 * 128.0f);
-            if (idx > 127) idx = 127;
-            float w = orc_ewa_lut[idx];
+    int rsel = e.t0, found = 0;
+    for (int it = e.t0; it <= e.t1; ++it) {
+        float R = 0.0f;
+        for (int is = e.s0; is <= e.s1; ++is) {
+            float w = orc_ewa_weight(&e, is, it);
             if (w > 0.0f) R += w;
         }
         if (!(R > 0.0f)) continue;
         S += R;
-        if (orc_uniform(seed, qid, 16u + (uint32_t)(it - t0)) * S < R) { rsel = it; Rsel = R; found = 1; }
+        if (orc_uniform(seed, qid, 16u + (uint32_t)(it - e.t0)) * S < R) { rsel = it; Rsel = R; found = 1; }
     }
-    *tx = s0;
+    *tx = e.s0;
     *ty = rsel;
     if (!found) return;
-    float tt = (float)rsel - sty, Tq = u * Rsel, run = 0.0f;
-    for (int is = s0; is <= s1; ++is) {
-        float ss = (float)is - stx;
-        float r2 = (A * (ss * ss) + (B * ss) * tt) + Cc * (tt * tt);
-        if (!(r2 < 1.0f)) continue;
-        int idx = (int)(r2 * 128.0f);
-        if (idx > 127) idx = 127;
-        float w = orc_ewa_lut[idx];
+    float Tq = u * Rsel, run = 0.0f;
+    for (int is = e.s0; is <= e.s1; ++is) {
+        float w = orc_ewa_weight(&e, is, rsel);
         if (!(w > 0.0f)) continue;
         run += w;
         *tx = is;   /* the last tap with weight, if the running sum never exceeds T */
@@ -1323,6 +1414,7 @@ int orc_ewa_filter2d(const void* const* level_texels, const int* W, const int* H
     if (!level_texels || levels < 1 || C < 1 || C > 16 || n < 0 || !(max_aniso >= 1.0f) ||
         (mode != ORC_DET && mode != ORC_STOCH))
         return -1;
+    if (W[levels - 1] != 1 || H[levels - 1] != 1) return -1;   /* the pyramid must end at one texel */
     orc_ewa_init();
     orc_ewa_tex T = {level_texels, W, H, levels, C, fmt};
     int nt = orc_threads(nthreads);

@@ -85,6 +85,25 @@ double orc_ggx_D(const double* n, const double* h, double alpha)
     return a2 / (ORC_PI * den * den);
 }
 
+/* The terms of the GGX specular lobe at unit normal n and unit directions
+ * wo, wi (both above the surface): out = {D(h), Lambda(wo), Lambda(wi), G2,
+ * F} with h = normalize(wo + wi), the height-correlated Smith
+ * masking-shadowing G2 = 1 / (1 + Lambda(wo) + Lambda(wi)) (Heitz, "Understanding
+ * the Masking-Shadowing Function", JCGT 2014) and Schlick's Fresnel
+ * F = F0 + (1 - F0)(1 - wi.h)^5 with F0 = 0.04. */
+void orc_ggx_terms(const double* n, const double* wo, const double* wi, double alpha, double out[5])
+{
+    double a2 = alpha * alpha;
+    double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+    double hl = sqrt(dot3(h, h));
+    h[0] /= hl; h[1] /= hl; h[2] /= hl;
+    out[0] = orc_ggx_D(n, h, alpha);
+    out[1] = orc_lambda(n, wo, a2);
+    out[2] = orc_lambda(n, wi, a2);
+    out[3] = 1.0 / (1.0 + out[1] + out[2]);
+    out[4] = 0.04 + 0.96 * pow(1.0 - dot3(wi, h), 5.0);
+}
+
 /* f^ = (albedo/pi + D G2 F / (4 (n.wo)(n.wi))) (n.wi) for one material. */
 void orc_shade_eval(const double mat[6], const float* wo_f, const float* wi_f, double out[3])
 {
@@ -92,19 +111,15 @@ void orc_shade_eval(const double mat[6], const float* wo_f, const float* wi_f, d
     double nx = mat[4], ny = mat[5];
     double n[3] = {nx, ny, sqrt(fmax(0.0, 1.0 - nx * nx - ny * ny))};
     double r = mat[3];
-    double alpha = fmax(r * r, 1e-3), a2 = alpha * alpha;
+    double alpha = fmax(r * r, 1e-3);
     double no = dot3(n, wo), ni = dot3(n, wi);
     if (!(no > 0.0) || !(ni > 0.0)) {
         out[0] = out[1] = out[2] = 0.0;
         return;
     }
-    double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
-    double hl = sqrt(dot3(h, h));
-    h[0] /= hl; h[1] /= hl; h[2] /= hl;
-    double D = orc_ggx_D(n, h, alpha);
-    double G2 = 1.0 / (1.0 + orc_lambda(n, wo, a2) + orc_lambda(n, wi, a2));
-    double F = 0.04 + 0.96 * pow(1.0 - dot3(wi, h), 5.0);
-    double spec = D * G2 * F / (4.0 * no * ni);
+    double g[5];
+    orc_ggx_terms(n, wo, wi, alpha, g);
+    double spec = g[0] * g[3] * g[4] / (4.0 * no * ni);
     for (int c = 0; c < 3; ++c) out[c] = (mat[c] / ORC_PI + spec) * ni;
 }
 
