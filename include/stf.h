@@ -27,25 +27,27 @@
  *     Destroying a texture while work that reads it is still in flight on a
  *     stream is a caller error.
  *   - n == 0 is a valid no-op.  n must be < 2^31 per call.
- *   - Random numbers: the uniform for axis a of query q (its index within the
- *     call) is a pure function of (seed, q, a):
+ *   - Random numbers: the uniform of hash index a of query q (its index
+ *     within the call) is a pure function of (seed, q, a):
  *        pcg(x): state = x*747796405 + 2891336453;
  *                word  = ((state >> ((state >> 28) + 4)) ^ state) * 277803737;
  *                return (word >> 22) ^ word          (all arithmetic mod 2^32)
- *        s = pcg(lo32(seed) ^ pcg(hi32(seed)));  h0 = pcg(s ^ q);
- *        h_a = pcg(h0 + a) for a >= 1;  u_a = (h_a >> 8) * 2^-24
- *     (a = 0, 1, 2 for x, y, z), so results do not depend on launch shape,
- *     ordering or other work.
+ *        s = pcg(lo32(seed) ^ pcg(hi32(seed)));  b = pcg(s ^ q);
+ *        h_a = pcg(b + a) for every a >= 0;  u_a = (h_a >> 8) * 2^-24
+ *     (a = 0, 1, 2 for the axes x, y, z; other indices as each call states),
+ *     so results do not depend on launch shape, ordering or other work.
+ *     (Known answers: pcg(0) = 0x07bb2fe2, s = 0x30be035e for seed 0, and
+ *     u_0 = 0.551548481 for seed 0, q = 0.)
  *   - Tap choice (stochastic mode), per axis, with i = floor(x), t = x - i in
  *     binary32:  linear: upper tap i+1 iff u < t, else i.  Cubic: with
- *     s = 1-t, d = t - 0.5, K6 = 0x1.555556p-3f, K3 = 0x1.555556p-2f:
- *     c1 = ((s*s)*s)*K6, c2 = fma(d, fma(d*d, K3, -0.75), 0.5),
- *     c3 = fma(-((t*t)*t), K6, 1), tap = i - 1 + [u >= c1] + [u >= c2] +
- *     [u >= c3] -- the cumulative B-spline weights.  Every operation is a
- *     single binary32 rounding (each fma rounded once), so the chosen tap is
- *     reproducible bit for bit.  ("Sampling arrays", section "Sampling
- *     Techniques", applied per axis as in section "B-Spline and Anisotropic
- *     Filters".)
+ *     s = 1-t and K6 = 0x1.555556p-3f (binary32 1/6):
+ *     c1 = ((s*s)*s)*K6, c2 = c1 + (4 + (3*(t*t))*(t - 2))*K6,
+ *     c3 = 1 - ((t*t)*t)*K6, tap = i - 1 + [u >= c1] + [u >= c2] +
+ *     [u >= c3] -- the cumulative B-spline weights w0, w0 + w1, 1 - w3.
+ *     Every operation is a single binary32 rounding (no fused multiply-add),
+ *     so the chosen tap is reproducible bit for bit.  ("Sampling arrays",
+ *     section "Sampling Techniques", applied per axis as in section
+ *     "B-Spline and Anisotropic Filters".)
  *   - A query coordinate that is NaN, infinite, or of magnitude >= 2^24 after
  *     the raster transform yields NaN in every output channel and INT32_MIN
  *     in every index component.  It is not an error.
@@ -215,23 +217,34 @@ stf_status stf_filter_gaussian(const stf_texture* tex, const float* queries_dev,
  * Anisotropic Filters"; supplement, "Stochastic sampling of the EWA kernel",
  * after pbrt's EWA lookup).  Each query is 6 binary32: (s, t) in [0, 1] and
  * the texture-space derivatives (ds/dx, dt/dx, ds/dy, dt/dy).
+ *   - The texture must hold the full pyramid: its last level is 1x1
+ *     (STF_E_INVALID otherwise).
  *   - The longer derivative vector is the major axis; the shorter one is
  *     raised to longer / max_anisotropy if needed (binary32).
  *   - lod = max(0, (levels - 1) + log2(shorter)) (binary64).
- *   - Deterministic: lerp(lod - floor(lod), EWA(floor(lod)), EWA(floor(lod)
- *     + 1)); EWA on a level = sum w t / sum w over its texels with
+ *   - EWA on a level = over the texels of the ellipse's bounding box with
  *     r2 = A ss^2 + B ss tt + C tt^2 < 1 (pbrt's ellipse coefficients in
- *     texels), w = LUT[min(floor(128 r2), 127)], LUT[i] = exp(-2 i/127) -
- *     exp(-2).
- *   - Stochastic: level floor(lod) + [u0 < lod - floor(lod)], then one texel
- *     drawn with probability w / sum w (the first in row-major scan order
- *     whose running binary32 sum exceeds u1 sum w): one texel read per
- *     lookup.
+ *     texels), weights w = LUT[min(floor(128 r2), 127)], LUT[i] =
+ *     exp(-2 i/127) - exp(-2).  On the last level (one texel) it is that
+ *     texel, read directly (pbrt's rule), so a footprint larger than the
+ *     texture costs one read.
+ *   - Deterministic: lerp(lod - floor(lod), EWA(floor(lod)), EWA(floor(lod)
+ *     + 1)) with EWA = sum w t / sum w (levels clamped to the last).
+ *   - Stochastic: level l = floor(lod) + [u_0 < lod - floor(lod)] (clamped
+ *     to the last), then one texel drawn with probability w / sum w: a row
+ *     k of the box by weighted reservoir sampling over the binary32 row sums
+ *     R_k in scan order (row k replaces the choice iff u_(16+k) S < R_k, S
+ *     the running sum), then within that row the first texel whose running
+ *     binary32 sum exceeds u_1 R (the last texel of positive weight if none
+ *     does).  u_a is hash index a of the query.  One texel read per lookup.
  *   - A zero footprint reads bilinearly from level 0 (stochastic: the linear
- *     draw); levels past the last read the last; taps are clamped.
+ *     draw with hash indices 2, 3); taps are clamped.
+ * Work per query is bounded: the ellipse is scanned only where its minor
+ * axis spans fewer than 4 texels, so its box holds O(max_anisotropy) taps.
  * Queries with a non-finite or |value| >= 65536 entry give NaN.
- * max_anisotropy in [1, 1024].  out_index_dev: NULL or (stochastic) n x 3
- * int32 (x, y, level).  Binary32 accumulation. */
+ * max_anisotropy in [1, 64] (the real-time implementation's maximum).
+ * out_index_dev: NULL or (stochastic) n x 3 int32 (x, y, level).  Binary32
+ * accumulation. */
 stf_status stf_filter_ewa(const stf_texture* tex, const float* queries_dev, int64_t n, float max_anisotropy,
                           stf_mode mode, uint64_t seed, float* out_dev, int32_t* out_index_dev, void* hip_stream);
 

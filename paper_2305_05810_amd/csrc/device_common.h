@@ -5,8 +5,8 @@
 // Every file that includes this header is compiled with -ffp-contract=off, so
 // each binary32 expression below rounds after every operation exactly as
 // written; fused multiply-adds appear only where __builtin_fmaf is spelled out
-// (the cubic breakpoints, pinned with them, and deterministic accumulation,
-// which carries a stated tolerance instead of bit-exactness).
+// (deterministic accumulation, which carries a stated tolerance instead of
+// bit-exactness, and a few conversions whose results are exact).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,10 +37,11 @@ __host__ __device__ __forceinline__ uint32_t seed_key(uint64_t seed)
     return pcg((uint32_t)seed ^ pcg((uint32_t)(seed >> 32)));
 }
 
-// Uniforms in [0, 1 - 2^-24] on the 2^-24 grid.  Axis 0 of query q uses
-// h0 = pcg(key ^ q) itself; axis a >= 1 uses pcg(h0 + a).  The kernels work
-// with m = u * 2^24 = h >> 8, an integer held exactly in binary32, and compare
-// it with breakpoints scaled by 2^24; scaling by a power of two is exact, so
+// Uniforms in [0, 1 - 2^-24] on the 2^-24 grid.  Query q has the base hash
+// b = pcg(key ^ q); its hash index a (a = 0, 1, 2 for the axes x, y, z; other
+// indices for further draws) uses h_a = pcg(b + a).  The kernels work with
+// m = u * 2^24 = h >> 8, an integer held exactly in binary32, and compare it
+// with breakpoints scaled by 2^24; scaling by a power of two is exact, so
 // every comparison has the same outcome as u against the unscaled breakpoint.
 __device__ __forceinline__ float hash_m(uint32_t h)
 {
@@ -52,21 +53,33 @@ __device__ __forceinline__ float hash_uniform(uint32_t h)
     return hash_m(h) * 0x1p-24f;
 }
 
-__device__ __forceinline__ float axis_uniform(uint32_t h0, uint32_t a)
+__device__ __forceinline__ float axis_uniform(uint32_t b, uint32_t a)
 {
-    return hash_uniform(a == 0 ? h0 : pcg(h0 + a));
+    return hash_uniform(pcg(b + a));
 }
 
-// pcg(h0 + 1) and pcg(h0 + 2) sharing the first multiply:
-// (h0 + a) * M + C = (h0 * M + C) + a * M.
-__device__ __forceinline__ void pcg_next2(uint32_t h0, uint32_t& h1, uint32_t& h2)
+// The hash of index a from base = b * M + C (the state of pcg(b)):
+// (b + a) * M + C = base + a * M (mod 2^32), so the indices of one query
+// share the first multiply.
+__device__ __forceinline__ uint32_t pcg_from_base(uint32_t base, uint32_t a)
 {
-    uint32_t base = h0 * 747796405u + 2891336453u;
-    uint32_t s1 = base + 747796405u, s2 = base + 2u * 747796405u;
-    uint32_t w1 = ((s1 >> ((s1 >> 28u) + 4u)) ^ s1) * 277803737u;
-    uint32_t w2 = ((s2 >> ((s2 >> 28u) + 4u)) ^ s2) * 277803737u;
-    h1 = (w1 >> 22u) ^ w1;
-    h2 = (w2 >> 22u) ^ w2;
+    const uint32_t state = base + a * 747796405u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+__device__ __forceinline__ uint32_t pcg_base(uint32_t b)
+{
+    return b * 747796405u + 2891336453u;
+}
+
+// pcg(b), pcg(b + 1), pcg(b + 2) with one shared multiply.
+__device__ __forceinline__ void pcg_axes3(uint32_t b, uint32_t& h0, uint32_t& h1, uint32_t& h2)
+{
+    const uint32_t base = pcg_base(b);
+    h0 = pcg_from_base(base, 0u);
+    h1 = pcg_from_base(base, 1u);
+    h2 = pcg_from_base(base, 2u);
 }
 
 // Cell of one binary32 coordinate: i = floor(x), t = x - floor(x).  Returns
@@ -103,19 +116,18 @@ __device__ __forceinline__ Cubic6 cubic6(float t)
     return w;
 }
 
-constexpr float K3 = 0x1.555556p-2f;   // (float)(1/3)
 constexpr float TWO24 = 16777216.0f;
 
 // Tap offset from cell i chosen by the uniform on one axis ("sampling
 // arrays": the first tap whose cumulative weight exceeds u).  m = u * 2^24.
 //   linear: +1 iff u < t (strict comparison), else 0;
 //   cubic:  -1 + [u >= c1] + [u >= c2] + [u >= c3] at the cumulative
-//           B-spline weights c1 = ((s*s)*s)*K6, c2 = fma(d, fma(d*d, K3,
-//           -0.75), 0.5), c3 = 1 - ((t*t)*t)*K6 (s = 1 - t, d = t - 1/2),
-//           each operation one binary32 rounding.  Since c1 <= c2 <= c3 for
-//           every binary32 t in [0, 1), the sum equals (u >= c2 ? 1 : -1) +
-//           [u >= c_side] with c_side = c3 above c2 and c1 below it, and only
-//           that one side breakpoint is evaluated (from r = t or r = s).
+//           B-spline weights c1 = w0 = ((s*s)*s)*K6, c2 = c1 + w1 with
+//           w1 = (4 + (3*(t*t))*(t - 2))*K6, and c3 = 1 - w3 =
+//           1 - ((t*t)*t)*K6 (s = 1 - t), each operation one binary32
+//           rounding.  Since c1 <= c2 <= c3 for every binary32 t in [0, 1),
+//           the sum equals (u >= c2 ? 1 : -1) + [u >= c_side] with c_side =
+//           c3 above c2 and c1 below it.
 __device__ __forceinline__ int choose_linear_m(float t, float m)
 {
     return (m < t * TWO24) ? 1 : 0;
@@ -123,13 +135,12 @@ __device__ __forceinline__ int choose_linear_m(float t, float m)
 
 __device__ __forceinline__ int choose_cubic_m(float t, float m)
 {
-    constexpr float K6S = K6 * TWO24, K3S = K3 * TWO24;
-    float d = t - 0.5f;
-    float c2 = __builtin_fmaf(d, __builtin_fmaf(d * d, K3S, -0.75f * TWO24), 0.5f * TWO24);
-    bool hi = m >= c2;
-    float r = hi ? t : 1.0f - t;
-    float r3 = ((r * r) * r) * K6S;
-    float side = hi ? TWO24 - r3 : r3;
+    constexpr float K6S = K6 * TWO24;
+    const float s = 1.0f - t;
+    const float c1 = ((s * s) * s) * K6S;
+    const float c2 = c1 + (4.0f + (3.0f * (t * t)) * (t - 2.0f)) * K6S;
+    const bool hi = m >= c2;
+    const float side = hi ? TWO24 - ((t * t) * t) * K6S : c1;
     return (hi ? 1 : -1) + (int)(m >= side);
 }
 

@@ -19,7 +19,10 @@
 //    exp(-2).  The stochastic tap: a row by weighted reservoir sampling over
 //    the row sums, then a tap of the row by the cumulative rule (ewa_draw).
 //  - A zero footprint reads bilinearly from level 0 (stochastic: the linear
-//    draw with hash indices 2, 3); levels past the last read the last.
+//    draw with hash indices 2, 3).  The pyramid ends at one texel, and a
+//    level at or past that last one yields that texel (pbrt's rule): the
+//    ellipse is only scanned on levels where its minor axis spans fewer
+//    than 4 texels, so a query's box holds O(max_aniso) taps.
 // Taps are clamped to their level.
 #include <math.h>
 
@@ -138,9 +141,9 @@ __device__ __forceinline__ void ewa_mean(const TexLevel& L, const Ellipse& e, co
 // u_(16+k) * S < R_k, S the running sum of row sums), then a tap of that row
 // by the cumulative rule (T = u1 R, the first tap whose running sum exceeds
 // T).  One pass over the box and one over a single row.
-__device__ __forceinline__ void ewa_draw(const Ellipse& e, const float* lut, uint32_t h0, float u1, int& tx, int& ty)
+__device__ __forceinline__ void ewa_draw(const Ellipse& e, const float* lut, uint32_t b, float u1, int& tx, int& ty)
 {
-    const uint32_t base = h0 * 747796405u + 2891336453u;
+    const uint32_t base = pcg_base(b);
     float S = 0.0f, Rsel = 0.0f;
     int rsel = e.t0;
     bool found = false;
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(BLOCK) void k_ewa(EwaLevels P, EwaLut lut_in, const
             d1[1] *= scale;
             sh *= scale;
         }
-        const uint32_t h0 = pcg(key ^ (uint32_t)i);
+        const uint32_t b = pcg(key ^ (uint32_t)i);
         const int L = P.levels;
         if (!(sh > 0.0f)) {   // degenerate footprint: bilinear on level 0
             const TexLevel& T0 = P.level[0];
@@ -218,8 +221,8 @@ __global__ __launch_bounds__(BLOCK) void k_ewa(EwaLevels P, EwaLut lut_in, const
             cell_of(x, cx, tx);
             cell_of(y, cy, ty);
             if constexpr (STOCH) {
-                ix[0] = clampi(cx + choose_linear(tx, axis_uniform(h0, 2)), T0.w - 1);
-                ix[1] = clampi(cy + choose_linear(ty, axis_uniform(h0, 3)), T0.h - 1);
+                ix[0] = clampi(cx + choose_linear(tx, axis_uniform(b, 2)), T0.w - 1);
+                ix[1] = clampi(cy + choose_linear(ty, axis_uniform(b, 3)), T0.h - 1);
                 ix[2] = 0;
                 texel<FMT, C>(T0, ix[0], ix[1], v);
             } else {
@@ -241,22 +244,27 @@ __global__ __launch_bounds__(BLOCK) void k_ewa(EwaLevels P, EwaLut lut_in, const
             const int il = (int)floor(lod);
             const double frac = lod - (double)il;
             if constexpr (STOCH) {
-                int l = il + ((double)hash_uniform(h0) < frac ? 1 : 0);
+                int l = il + ((double)axis_uniform(b, 0) < frac ? 1 : 0);
                 l = l > L - 1 ? L - 1 : l;
-                const Ellipse e = ellipse(P.level[l], r[0], r[1], d0, d1);
-                int tx, ty;
-                ewa_draw(e, lut, h0, axis_uniform(h0, 1), tx, ty);
+                int tx = 0, ty = 0;
+                if (l < L - 1) ewa_draw(ellipse(P.level[l], r[0], r[1], d0, d1), lut, b, axis_uniform(b, 1), tx, ty);
                 ix[0] = clampi(tx, P.level[l].w - 1);
                 ix[1] = clampi(ty, P.level[l].h - 1);
                 ix[2] = l;
                 texel<FMT, C>(P.level[l], ix[0], ix[1], v);
             } else {
                 const int l0 = il < L ? il : L - 1, l1 = il + 1 < L ? il + 1 : L - 1;
-                float a[C], b[C];
-                ewa_mean<FMT, C>(P.level[l0], ellipse(P.level[l0], r[0], r[1], d0, d1), lut, a);
-                ewa_mean<FMT, C>(P.level[l1], ellipse(P.level[l1], r[0], r[1], d0, d1), lut, b);
+                float a[C], c1[C];
+                if (l0 < L - 1)
+                    ewa_mean<FMT, C>(P.level[l0], ellipse(P.level[l0], r[0], r[1], d0, d1), lut, a);
+                else
+                    texel<FMT, C>(P.level[l0], 0, 0, a);
+                if (l1 < L - 1)
+                    ewa_mean<FMT, C>(P.level[l1], ellipse(P.level[l1], r[0], r[1], d0, d1), lut, c1);
+                else
+                    texel<FMT, C>(P.level[l1], 0, 0, c1);
 #pragma unroll
-                for (int c = 0; c < C; ++c) v[c] = (float)((1.0 - frac) * (double)a[c] + frac * (double)b[c]);
+                for (int c = 0; c < C; ++c) v[c] = (float)((1.0 - frac) * (double)a[c] + frac * (double)c1[c]);
             }
         }
     }
@@ -304,8 +312,11 @@ extern "C" stf_status stf_filter_ewa(const stf_texture* tex, const float* querie
     if (!tex) return stf_fail(STF_E_INVALID, "texture is NULL");
     if (tex->kind != STF_KIND_TEX2D) return stf_fail(STF_E_INVALID, "stf_filter_ewa needs a 2D texture (with levels)");
     if (n < 0 || n > 0x7fffffff) return stf_fail(STF_E_INVALID, "n = %lld out of range", (long long)n);
-    if (!(max_anisotropy >= 1.0f && max_anisotropy <= 1024.0f))
-        return stf_fail(STF_E_INVALID, "max_anisotropy = %g out of range [1, 1024]", (double)max_anisotropy);
+    if (!(max_anisotropy >= 1.0f && max_anisotropy <= 64.0f))
+        return stf_fail(STF_E_INVALID, "max_anisotropy = %g out of range [1, 64]", (double)max_anisotropy);
+    if (tex->level[tex->levels - 1].w != 1 || tex->level[tex->levels - 1].h != 1)
+        return stf_fail(STF_E_INVALID, "stf_filter_ewa needs the full MIP pyramid (its last level %dx%d is not 1x1)",
+                        tex->level[tex->levels - 1].w, tex->level[tex->levels - 1].h);
     if (mode != STF_DETERMINISTIC && mode != STF_STOCHASTIC) return stf_fail(STF_E_INVALID, "unknown mode %d", (int)mode);
     if (mode == STF_DETERMINISTIC && out_index_dev)
         return stf_fail(STF_E_INVALID, "out_index_dev must be NULL in deterministic mode");

@@ -586,8 +586,8 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __res
     int sx = BAD_INDEX, sy = BAD_INDEX;
     if constexpr (GMODE == GAUSS_FIS || GMODE == GAUSS_DISCRETE) {
         if (ok) {
-            const uint32_t h0 = pcg(key ^ (uint32_t)i);
-            const float u0f = hash_uniform(h0), u1f = axis_uniform(h0, 1);
+            const uint32_t b = pcg(key ^ (uint32_t)i);
+            const float u0f = axis_uniform(b, 0), u1f = axis_uniform(b, 1);
             const double u0 = (double)u0f, u1 = (double)u1f;
             if constexpr (GMODE == GAUSS_FIS) {
                 // The offset is first formed in binary32.  1 - u0 is exact, and

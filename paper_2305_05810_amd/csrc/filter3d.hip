@@ -114,13 +114,14 @@ __device__ __forceinline__ void grid_stochastic_block(const GridView& g, const f
         int c0 = 0, c1 = 0, c2 = 0;
         float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f;
         fin[k] = cell_of(p[k][0], c0, t0) & cell_of(p[k][1], c1, t1) & cell_of(p[k][2], c2, t2);
-        uint32_t h0 = pcg(key ^ qid[k]), h1, h2;
-        pcg_next2(h0, h1, h2);
+        const uint32_t b = pcg(key ^ qid[k]);
+        uint32_t h0, h1, h2;
+        pcg_axes3(b, h0, h1, h2);
         float m0 = hash_m(h0), m1 = hash_m(h1), m2 = hash_m(h2);
         if constexpr (FIS) {
-            vx[k] = fis_tap<CUBIC>(p[k][0], h0, 0);
-            vy[k] = fis_tap<CUBIC>(p[k][1], h0, 1);
-            vz[k] = fis_tap<CUBIC>(p[k][2], h0, 2);
+            vx[k] = fis_tap<CUBIC>(p[k][0], b, 0);
+            vy[k] = fis_tap<CUBIC>(p[k][1], b, 1);
+            vz[k] = fis_tap<CUBIC>(p[k][2], b, 2);
         } else if constexpr (CUBIC) {
             vx[k] = c0 + choose_cubic_m(t0, m0);
             vy[k] = c1 + choose_cubic_m(t1, m1);

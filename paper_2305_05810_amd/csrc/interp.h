@@ -164,21 +164,17 @@ __device__ __forceinline__ int pick_negative(float n0, float n3, float N, float 
     return upper ? 2 : -1;
 }
 
-// The uniform of hash index a >= 1 of a query: pcg(h0 + a) with the first
-// multiply-add shared, (h0 + a) M + C = (h0 M + C) + a M (mod 2^32), where
-// base = h0 M + C.
+// The uniform of hash index a of a query, pcg(b + a), from base = pcg_base(b).
 __device__ __forceinline__ float uniform_from_base(uint32_t base, uint32_t a)
 {
-    const uint32_t state = base + a * 747796405u;
-    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
-    return hash_uniform((word >> 22u) ^ word);
+    return hash_uniform(pcg_from_base(base, a));
 }
 
-// Both draws of one query; h0 = pcg(key ^ qid) is the query's first hash.
+// Both draws of one query; b = pcg(key ^ qid) is the query's base hash.
 // All array indices are compile-time constants after unrolling; the pattern
 // picked at run time only steers selects.
 template <int D, int KIND>
-__device__ __forceinline__ PosDraw<D> positivized_draw(const float (&t)[D], uint32_t h0)
+__device__ __forceinline__ PosDraw<D> positivized_draw(const float (&t)[D], uint32_t b)
 {
     constexpr int NP = 1 << (D - 1);   // patterns per sign set
     float w[D][4], n0[D], n3[D], P[D], N[D];
@@ -195,7 +191,7 @@ __device__ __forceinline__ PosDraw<D> positivized_draw(const float (&t)[D], uint
         }
         N[a] = n0[a] + n3[a];
     }
-    const uint32_t base = h0 * 747796405u + 2891336453u;
+    const uint32_t base = pcg_base(b);
     PosDraw<D> r;
 #pragma unroll
     for (int set = 0; set < 2; ++set) {
@@ -206,11 +202,11 @@ __device__ __forceinline__ PosDraw<D> positivized_draw(const float (&t)[D], uint
 #pragma unroll
         for (int j = 1; j < NP; ++j) total += pm[j];
         const uint32_t ubase = set == 0 ? 0u : 5u, ucomp = set == 0 ? 4u : 8u;
-        const int b = pattern_bits<D>(set, cumulative_pick<NP>(pm, uniform_from_base(base, ucomp)));
+        const int pat = pattern_bits<D>(set, cumulative_pick<NP>(pm, uniform_from_base(base, ucomp)));
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const float u = ubase + a == 0 ? hash_uniform(h0) : uniform_from_base(base, ubase + (uint32_t)a);
-            const int o = ((b >> a) & 1) ? pick_negative(n0[a], n3[a], N[a], u) : pick_positive<KIND>(w[a], P[a], u);
+            const float u = uniform_from_base(base, ubase + (uint32_t)a);
+            const int o = ((pat >> a) & 1) ? pick_negative(n0[a], n3[a], N[a], u) : pick_positive<KIND>(w[a], P[a], u);
             if (set == 0) r.op[a] = o;
             else r.on[a] = o;
         }
@@ -232,10 +228,10 @@ __device__ __forceinline__ PosDraw<D> positivized_draw(const float (&t)[D], uint
 // grid), so the tap is a pure function of (x, seed, query).  Uniforms of axis
 // a: hash index a (tent); a, 4 + a, 8 + a (cubic).
 template <bool CUBIC>
-__device__ __forceinline__ int fis_tap(float x, uint32_t h0, int a)
+__device__ __forceinline__ int fis_tap(float x, uint32_t b, int a)
 {
-    const uint32_t base = h0 * 747796405u + 2891336453u;
-    auto u = [&](uint32_t k) { return (double)(k == 0 ? hash_uniform(h0) : uniform_from_base(base, k)); };
+    const uint32_t base = pcg_base(b);
+    auto u = [&](uint32_t k) { return (double)uniform_from_base(base, k); };
     double s;
     if constexpr (CUBIC)
         s = ((u((uint32_t)a) + u(4u + (uint32_t)a)) + u(8u + (uint32_t)a)) - 1.5;

@@ -496,13 +496,14 @@ __device__ __forceinline__ Decode locate(const InferArgs& a, int64_t qi, int tap
     d.fin = cell_of(x, cx, tx) & cell_of(y, cy, ty);
     d.w = 1.0f;
     if constexpr (STOCH) {
-        uint32_t h0 = pcg(a.key ^ (uint32_t)qi);
+        const uint32_t base = pcg_base(pcg(a.key ^ (uint32_t)qi));
+        const float mx = hash_m(pcg_from_base(base, 0u)), my = hash_m(pcg_from_base(base, 1u));
         if constexpr (CUBIC) {
-            d.sx = cx + choose_cubic_m(tx, hash_m(h0));
-            d.sy = cy + choose_cubic_m(ty, hash_m(pcg(h0 + 1u)));
+            d.sx = cx + choose_cubic_m(tx, mx);
+            d.sy = cy + choose_cubic_m(ty, my);
         } else {
-            d.sx = cx + choose_linear_m(tx, hash_m(h0));
-            d.sy = cy + choose_linear_m(ty, hash_m(pcg(h0 + 1u)));
+            d.sx = cx + choose_linear_m(tx, mx);
+            d.sy = cy + choose_linear_m(ty, my);
         }
     } else if constexpr (CUBIC) {
         int ta = tap % 4, tb = tap / 4;

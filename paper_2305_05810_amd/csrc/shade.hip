@@ -136,14 +136,16 @@ __global__ __launch_bounds__(BLOCK) void k_shade(Levels L, const float* __restri
     float f[3] = {__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
     if (ok) {
         if constexpr (MODE == STF_SHADE_STOCHASTIC) {
-            uint32_t h0 = pcg(key ^ (uint32_t)i);
+            const uint32_t b = pcg(key ^ (uint32_t)i);
+            const uint32_t base = pcg_base(b);
+            const float mx = hash_m(pcg_from_base(base, 0u)), my = hash_m(pcg_from_base(base, 1u));
             int sx, sy;
             if constexpr (CUBIC) {
-                sx = cx + choose_cubic_m(tx, hash_m(h0));
-                sy = cy + choose_cubic_m(ty, hash_m(pcg(h0 + 1u)));
+                sx = cx + choose_cubic_m(tx, mx);
+                sy = cy + choose_cubic_m(ty, my);
             } else {
-                sx = cx + choose_linear_m(tx, hash_m(h0));
-                sy = cy + choose_linear_m(ty, hash_m(pcg(h0 + 1u)));
+                sx = cx + choose_linear_m(tx, mx);
+                sy = cy + choose_linear_m(ty, my);
             }
             sx = clampi(sx, T.w - 1);
             sy = clampi(sy, T.h - 1);

@@ -69,14 +69,59 @@ def test_ewa_parity(dev, fmt, aniso):
 
 
 def test_ewa_argument_errors(dev):
-    t = stf.stf_create_texture2d(8, 8, 1, stf.STF_FMT_F32, [np.zeros((8, 8, 1), np.float32)])
+    lv = synth.mip_levels(np.zeros((8, 8, 1), np.float32))
+    t = stf.stf_create_texture2d(8, 8, 1, stf.STF_FMT_F32, lv)
     q = torch.zeros((4, 6), dtype=torch.float32, device=dev)
     out = torch.empty((4, 1), dtype=torch.float32, device=dev)
     idx = torch.empty((4, 3), dtype=torch.int32, device=dev)
     L = stf.lib()
+    assert L.stf_filter_ewa(t.handle, q.data_ptr(), 4, 8.0, 0, 0, out.data_ptr(), None, None) == stf.STF_OK
     assert L.stf_filter_ewa(t.handle, q.data_ptr(), 4, 0.5, 0, 0, out.data_ptr(), None, None) == stf.STF_E_INVALID
+    assert L.stf_filter_ewa(t.handle, q.data_ptr(), 4, 65.0, 0, 0, out.data_ptr(), None, None) == stf.STF_E_INVALID
     assert L.stf_filter_ewa(t.handle, q.data_ptr(), 4, 8.0, 0, 0, out.data_ptr(), idx.data_ptr(), None) == stf.STF_E_INVALID
     assert L.stf_filter_ewa(t.handle, q.data_ptr(), 4, 8.0, 5, 0, out.data_ptr(), None, None) == stf.STF_E_INVALID
     host = np.zeros((4, 6), np.float32)
     assert L.stf_filter_ewa(t.handle, host.ctypes.data, 4, 8.0, 0, 0, out.data_ptr(), None, None) == stf.STF_E_INVALID
+    torch.cuda.synchronize()
+    t.destroy()
+    # a pyramid that stops before 1x1 is refused
+    short = stf.stf_create_texture2d(8, 8, 1, stf.STF_FMT_F32, lv[:2])
+    assert L.stf_filter_ewa(short.handle, q.data_ptr(), 4, 8.0, 0, 0, out.data_ptr(), None, None) == stf.STF_E_INVALID
+    short.destroy()
+
+
+@pytest.mark.parametrize("mode", ["stoch", "det"])
+def test_ewa_footprints_larger_than_the_texture(dev, mode):
+    # Derivatives up to 1e4 texture widths select the last level (one texel),
+    # which is read directly: the work per query stays bounded and the result
+    # equals the oracle's (the coarsest texel; index (0, 0, last level)).
+    rng = np.random.default_rng(5)
+    base = rng.integers(0, 256, (64, 64, 4), dtype=np.uint8)
+    lv = synth.mip_levels(base)
+    t = stf.stf_create_texture2d(64, 64, 4, stf.STF_FMT_U8, lv)
+    n = 4096
+    q = np.zeros((n, 6), np.float32)
+    q[:, :2] = rng.random((n, 2))
+    scale = 10.0 ** rng.uniform(-0.5, 4.0, n)             # 0.3 .. 1e4 texture widths
+    ang = rng.random(n) * np.pi
+    q[:, 2], q[:, 3] = scale * np.cos(ang), scale * np.sin(ang)
+    q[:, 4], q[:, 5] = -0.5 * scale * np.sin(ang), 0.5 * scale * np.cos(ang)
+    qd = torch.from_numpy(q).to(dev)
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    L = len(lv)
+    if mode == "stoch":
+        idx = torch.empty((n, 3), dtype=torch.int32, device=dev)
+        stf.stf_filter_ewa(t, qd, 8.0, stf.STF_STOCHASTIC, 3, out, idx)
+        ov, oi = oracle.ewa_filter2d(lv, oracle.U8, q, 8.0, oracle.STOCH, seed=3)
+        gi = idx.cpu().numpy()
+        assert np.array_equal(gi, oi)
+        assert np.all(gi[scale >= 2.0] == [0, 0, L - 1])     # shorter axis = scale / 2 >= 1: lod >= L - 1
+        assert np.array_equal(out.cpu().numpy(), ov.astype(np.float32))
+    else:
+        stf.stf_filter_ewa(t, qd, 8.0, stf.STF_DETERMINISTIC, 0, out)
+        od, _ = oracle.ewa_filter2d(lv, oracle.U8, q, 8.0, oracle.DET)
+        gd = out.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(gd - od) <= 1e-6 * np.abs(od) + 1e-12)
+        top = lv[-1][0, 0].astype(np.float32) / np.float32(255)
+        assert np.array_equal(out.cpu().numpy()[scale >= 2.0], np.broadcast_to(top, (int((scale >= 2.0).sum()), 4)))
     t.destroy()
