@@ -466,7 +466,8 @@ stf_status stf_server_submit(stf_server* s, const stf_texture* tex, const float*
 /* *done = 1 once results are in place (STF_E_CANCELLED / STF_E_DEVICE if
  * the request was cancelled / failed). */
 stf_status stf_server_poll(stf_server* s, uint64_t ticket, int32_t* done);
-/* Blocks until done or timeout (STF_E_BUSY on timeout). */
+/* Blocks until done or timeout (STF_E_BUSY on timeout); timeout_s >= 0,
+ * values above 1e6 (or HUGE_VAL) wait without a deadline. */
 stf_status stf_server_wait(stf_server* s, uint64_t ticket, double timeout_s);
 /* A pending request is dropped at once; a resident one gets no further
  * chunks and is retired when its launches are done. */
@@ -478,7 +479,10 @@ stf_status stf_server_reset_stats(stf_server* s);
 
 /* Open-loop replay: submits reqs[k] at arrival_s seconds after the call
  * starts (arrivals non-decreasing), latency counted from that scheduled
- * time, waits for all (at most timeout_s) and releases them. */
+ * time, waits for all (at most timeout_s) and releases them.  If a submit
+ * fails or the time-out passes, the requests still outstanding are
+ * cancelled and the call returns (with the error) only once none of them
+ * can write to its out / out_index buffers any more. */
 typedef struct {
     const stf_texture* tex;
     const float* queries;

@@ -18,6 +18,7 @@
 // the next round.  A query's random draw depends only on (request seed,
 // index within the request), so every result equals what stf_filter returns
 // for the same request alone.
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -298,7 +299,10 @@ void worker_main(stf_server* s)
                 if (e == hipSuccess && r->idx_user)
                     e = hipMemcpyAsync(r->idx_user, r->idx_dev, (size_t)r->n * 4 * r->dims, kind, s->stream);
                 if (e == hipSuccess) e = hipEventRecord(r->done_ev, s->stream);
-                r->state = FINISHING;
+                {
+                    std::lock_guard<std::mutex> lk(s->mu);   // poll, wait and cancel read the state under the lock
+                    r->state = FINISHING;
+                }
                 finishing.push_back(r);
             }
             if (e == hipSuccess) e = hipEventRecord(s->round_ev[slot], s->stream);
@@ -484,11 +488,18 @@ stf_status stf_server_wait(stf_server* s, uint64_t ticket, double timeout_s)
 {
     stf_clear_error();
     if (!s) return stf_fail(STF_E_INVALID, "NULL argument");
+    if (!(timeout_s >= 0.0)) return stf_fail(STF_E_INVALID, "timeout_s = %g must be >= 0", timeout_s);
     std::unique_lock<std::mutex> lk(s->mu);
     Request* r = find_req(s, ticket);
     if (!r) return stf_fail(STF_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
-    auto deadline = Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(timeout_s));
-    bool ok = s->cv_done.wait_until(lk, deadline, [&] { return r->state >= DONE; });
+    bool ok;
+    if (timeout_s > 1e6) {   // longer than any clock arithmetic needs: wait without a deadline
+        s->cv_done.wait(lk, [&] { return r->state >= DONE; });
+        ok = true;
+    } else {
+        auto deadline = Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(timeout_s));
+        ok = s->cv_done.wait_until(lk, deadline, [&] { return r->state >= DONE; });
+    }
     if (!ok) return stf_fail(STF_E_BUSY, "request %llu not finished after %.3f s", (unsigned long long)ticket, timeout_s);
     if (r->state == CANCELLED) return stf_fail(STF_E_CANCELLED, "request %llu was cancelled", (unsigned long long)ticket);
     if (r->state == FAILED) return stf_fail(STF_E_DEVICE, "request failed: %s", s->error.c_str());
@@ -581,9 +592,23 @@ stf_status stf_server_replay(stf_server* s, const stf_serve_request* reqs, int64
         if (st != STF_OK) return st;
         if (k && reqs[k].arrival_s < reqs[k - 1].arrival_s) return stf_fail(STF_E_INVALID, "arrivals must not decrease");
     }
-    std::vector<uint64_t> tickets((size_t)count);
+    if (!(timeout_s >= 0.0)) return stf_fail(STF_E_INVALID, "timeout_s = %g must be >= 0", timeout_s);
+    std::vector<uint64_t> tickets;
+    tickets.reserve((size_t)count);
+    // On an error or a time-out the requests still outstanding are cancelled
+    // and waited for without a deadline before the call returns, so no copy
+    // into a caller's buffer can land after it (a cancelled request is
+    // retired once its last launch is done; one already copying its results
+    // finishes them).
+    auto quiesce = [&]() {
+        for (uint64_t t : tickets) (void)stf_server_cancel(s, t);
+        for (uint64_t t : tickets) (void)stf_server_wait(s, t, HUGE_VAL);
+        for (uint64_t t : tickets) (void)stf_server_release(s, t);
+    };
     double t0 = now_s();
-    for (int64_t k = 0; k < count; ++k) {
+    stf_status result = STF_OK;
+    std::string why;
+    for (int64_t k = 0; k < count && result == STF_OK; ++k) {
         double due = t0 + reqs[k].arrival_s;
         for (;;) {   // open loop: submit at the scheduled time; latency counts from it
             double dt = due - now_s();
@@ -591,18 +616,19 @@ stf_status stf_server_replay(stf_server* s, const stf_serve_request* reqs, int64
             if (dt > 200e-6) std::this_thread::sleep_for(std::chrono::duration<double>(dt - 100e-6));
         }
         std::lock_guard<std::mutex> lk(s->mu);
-        stf_status st = submit_locked(s, reqs[k].tex, reqs[k].queries, reqs[k].n, reqs[k].filter, reqs[k].seed,
-                                      reqs[k].out, reqs[k].out_index, flags, due, &tickets[k]);
-        if (st != STF_OK) return st;
+        uint64_t t = 0;
+        result = submit_locked(s, reqs[k].tex, reqs[k].queries, reqs[k].n, reqs[k].filter, reqs[k].seed,
+                               reqs[k].out, reqs[k].out_index, flags, due, &t);
+        if (result == STF_OK) tickets.push_back(t);
+        else why = stf_last_error();
     }
     double deadline = now_s() + timeout_s;
-    stf_status result = STF_OK;
-    for (int64_t k = 0; k < count; ++k) {
-        stf_status st = stf_server_wait(s, tickets[k], std::max(0.0, deadline - now_s()));
-        if (st != STF_OK && result == STF_OK) result = st;
+    for (size_t k = 0; k < tickets.size() && result == STF_OK; ++k) {
+        result = stf_server_wait(s, tickets[k], std::max(0.0, deadline - now_s()));
+        if (result != STF_OK) why = stf_last_error();
     }
-    for (int64_t k = 0; k < count; ++k) (void)stf_server_release(s, tickets[k]);
-    if (result != STF_OK) return stf_fail(result, "replay: not every request completed");
+    quiesce();
+    if (result != STF_OK) return stf_fail(result, "replay: not every request completed (%s)", why.c_str());
     return STF_OK;
 }
 

@@ -146,3 +146,23 @@ def test_open_loop_replay_reports_latency(dev, textures):
     assert st["completed"] == 400 and st["queries"] == sum(r[2] for r in reqs)
     assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
     srv.destroy()
+
+
+def test_replay_time_out_leaves_nothing_in_flight(dev, textures):
+    # A replay that times out cancels what is still outstanding and returns
+    # only once no request can write into its buffers any more: right after
+    # the call nothing is pending or resident, and every request either
+    # completed or was cancelled.
+    srv = stf.stf_server_create(64 << 20, 4, 4096)
+    tex, dims = textures[0]
+    pool = torch.from_numpy(_queries(dims, 1 << 20, np.random.default_rng(7))).to(dev)
+    outp = torch.empty((1 << 20, 1), dtype=torch.float32, device=dev)
+    reqs = [(tex, pool.data_ptr(), 1 << 20, stf.STF_CUBIC_BSPLINE, k, outp.data_ptr(), None, 0.0) for k in range(16)]
+    with pytest.raises(stf.STFError) as e:
+        stf.stf_server_replay(srv, reqs, stf.STF_SERVE_QUERIES_ON_DEVICE | stf.STF_SERVE_RESULTS_ON_DEVICE,
+                              timeout_s=0.0)
+    assert e.value.status == stf.STF_E_BUSY
+    st = stf.stf_server_stats(srv)
+    assert st["pending"] == 0 and st["resident"] == 0
+    assert st["completed"] + st["cancelled"] == 16 and st["cancelled"] > 0
+    srv.destroy()

@@ -254,7 +254,7 @@ def test_3d_unbiased_within_5_sigma(filt, mode):
     K = 6000
     s1 = np.zeros(16)
     for k in range(K):
-        v, _ = g.filter(p, filt, mode, seed=1000 + k, want_index=False)
+        v, _ = g.filter(p, filt, mode, seed=1000 + k, want_index=False, nthreads=1)   # 16 queries: one thread
         s1 += v
     mean, var = g.moments(p, filt)
     det, _ = g.filter(p, filt, oracle.DET)

@@ -100,7 +100,7 @@ def test_one_decode_per_lookup_is_unbiased(filt):
     s1 = np.zeros_like(det)
     s2 = np.zeros_like(det)
     for k in range(K):
-        v, _ = nt.filter(uv, filt, oracle.STOCH, seed=900 + k)
+        v, _ = nt.filter(uv, filt, oracle.STOCH, seed=900 + k, nthreads=1)
         s1 += v
         s2 += v * v
     mean = s1 / K

@@ -152,7 +152,7 @@ def test_stochastic_shading_is_unbiased(filt):
     K = 6000
     acc = np.zeros((12, 3))
     for k in range(K):
-        v, _ = mat.shade(recs, filt, oracle.SH_STOCH, seed=500 + k, want_index=False)
+        v, _ = mat.shade(recs, filt, oracle.SH_STOCH, seed=500 + k, want_index=False, nthreads=1)
         acc += v
     ref, _ = mat.shade(recs, filt, oracle.SH_FILTER_AFTER)
     assert np.allclose(mean, ref, rtol=1e-12, atol=1e-15)
