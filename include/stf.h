@@ -497,6 +497,19 @@ typedef struct {
 stf_status stf_server_replay(stf_server* s, const stf_serve_request* reqs, int64_t count, uint32_t flags,
                              double timeout_s);
 
+/* Staging counters, for tests and tuning.  The deterministic bicubic /
+ * tricubic kernels of sorted streams (stf_filter_ordered on a 3D grid) and
+ * of DCT textures decide per block of 256 queries whether to stage the
+ * texels of the block's tap box in LDS (when the box is small enough and
+ * each staged texel serves at least 4 taps) or to read taps from global
+ * memory.  stf_stage_counting(1) zeroes two device counters of the current
+ * device and makes those kernels count {blocks that staged, blocks} from
+ * then on; stf_stage_counting(0) stops counting (the default: nothing is
+ * counted).  stf_stage_counts synchronizes the device and reads them.  The
+ * counters are shared by every stream and thread using the device. */
+stf_status stf_stage_counting(int32_t on);
+stf_status stf_stage_counts(uint64_t* staged_blocks, uint64_t* blocks);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* stf_last_error(void);
 

@@ -114,6 +114,8 @@ def _declare(L):
     L.orc_dct_texel.argtypes, L.orc_dct_texel.restype = [vp, i32, i32, i32, i32, i32], dbl
     L.orc_dct_filter2d.argtypes = [vp, i32, i32, i32, vp, i64, i32, i32, u64, vp, vp, i32]
     L.orc_dct_filter2d.restype = i32
+    L.orc_dct_filter2d_at.argtypes = [vp, i32, i32, i32, vp, vp, i64, i32, i32, u64, vp, vp, i32]
+    L.orc_dct_filter2d_at.restype = i32
     L.orc_dct_moments2d.argtypes = [vp, i32, i32, i32, vp, i64, i32, vp, vp, i32]
     L.orc_dct_moments2d.restype = i32
     L.orc_fis_tap.argtypes, L.orc_fis_tap.restype = [i32, dbl, u64, u32, i32], i32
@@ -125,11 +127,17 @@ def _declare(L):
     L.orc_ewa_listing_draws.restype = i64
     L.orc_ewa_filter2d.argtypes = [vp, vp, vp, i32, i32, i32, vp, i64, C.c_float, i32, u64, vp, vp, i32]
     L.orc_ewa_filter2d.restype = i32
+    L.orc_ewa_filter2d_at.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, i64, C.c_float, i32, u64, vp, vp, i32]
+    L.orc_ewa_filter2d_at.restype = i32
     L.orc_gauss_radius.argtypes, L.orc_gauss_radius.restype = [dbl], i32
     L.orc_gauss_filter2d.argtypes = [vp, i32, i32, i32, i32, vp, i64, dbl, i32, u64, vp, vp, i32]
     L.orc_gauss_filter2d.restype = i32
     L.orc_dct_gauss_filter2d.argtypes = [vp, i32, i32, i32, vp, i64, dbl, i32, u64, vp, vp, i32]
     L.orc_dct_gauss_filter2d.restype = i32
+    L.orc_dct_gauss_filter2d_at.argtypes = [vp, i32, i32, i32, vp, vp, i64, dbl, i32, u64, vp, vp, i32]
+    L.orc_dct_gauss_filter2d_at.restype = i32
+    L.orc_gauss_fis_positions_at.argtypes = [i32, i32, vp, vp, i64, dbl, u64, vp]
+    L.orc_gauss_fis_positions_at.restype = i32
     L.orc_gauss_fis_positions.argtypes = [i32, i32, vp, i64, dbl, u64, vp]
     L.orc_gauss_fis_positions.restype = i32
     if hasattr(L, "orc_shade"):
@@ -336,23 +344,26 @@ def gauss_filter2d(tex: np.ndarray, fmt: int, uv: np.ndarray, sigma: float, gmod
 
 
 def dct_gauss_filter2d(blocks: np.ndarray, uv: np.ndarray, sigma: float, gmode: int, seed: int = 0,
-                       want_index: bool = True, nthreads: int = 0):
+                       want_index: bool = True, nthreads: int = 0, qids=None):
     b = np.ascontiguousarray(blocks, np.uint32)
     H, W, Ch = b.shape[0] * 8, b.shape[1] * 8, b.shape[2]
     uv = np.ascontiguousarray(uv, dtype=np.float32)
-    n = uv.shape[0]
+    qi = _qids(qids)
+    n = uv.shape[0] if qi is None else qi.shape[0]
     out = np.empty((n, Ch), np.float64)
     idx = np.empty((n, 2), np.int32) if (want_index and gmode in (G_FIS, G_DISCRETE)) else None
-    if lib().orc_dct_gauss_filter2d(_p(b), W, H, Ch, _p(uv), n, float(sigma), gmode, seed, _p(out), _p(idx),
-                                    nthreads) != 0:
+    if lib().orc_dct_gauss_filter2d_at(_p(b), W, H, Ch, _p(uv), _p(qi), n, float(sigma), gmode, seed, _p(out),
+                                       _p(idx), nthreads) != 0:
         raise ValueError("orc_dct_gauss_filter2d rejected its arguments")
     return out, idx
 
 
-def gauss_fis_positions(W: int, H: int, uv: np.ndarray, sigma: float, seed: int) -> np.ndarray:
+def gauss_fis_positions(W: int, H: int, uv: np.ndarray, sigma: float, seed: int, qids=None) -> np.ndarray:
     uv = np.ascontiguousarray(uv, dtype=np.float32)
-    pos = np.empty((uv.shape[0], 2), np.float64)
-    lib().orc_gauss_fis_positions(W, H, _p(uv), uv.shape[0], float(sigma), seed, _p(pos))
+    qi = _qids(qids)
+    n = uv.shape[0] if qi is None else qi.shape[0]
+    pos = np.empty((n, 2), np.float64)
+    lib().orc_gauss_fis_positions_at(W, H, _p(uv), _p(qi), n, float(sigma), seed, _p(pos))
     return pos
 
 
@@ -394,7 +405,7 @@ def ewa_lods(q: np.ndarray, levels: int, max_aniso: float) -> np.ndarray:
 
 
 def ewa_filter2d(levels, fmt: int, q: np.ndarray, max_aniso: float, mode: int, seed: int = 0,
-                 want_index: bool = True, nthreads: int = 0):
+                 want_index: bool = True, nthreads: int = 0, qids=None):
     """levels: list of (H_l, W_l, C) raw texel arrays; q: (n, 6) float32
     (s, t, ds/dx, dt/dx, ds/dy, dt/dy).  Returns values (n, C) and, in
     stochastic mode, indices (n, 3) = (x, y, level)."""
@@ -404,11 +415,12 @@ def ewa_filter2d(levels, fmt: int, q: np.ndarray, max_aniso: float, mode: int, s
     Hs = (C.c_int * len(lv))(*[a.shape[0] for a in lv])
     Ch = lv[0].shape[2]
     q = np.ascontiguousarray(q, np.float32)
-    n = q.shape[0]
+    qi = _qids(qids)
+    n = q.shape[0] if qi is None else qi.shape[0]
     out = np.empty((n, Ch))
     idx = np.empty((n, 3), np.int32) if (want_index and mode == STOCH) else None
-    if lib().orc_ewa_filter2d(ptrs, Ws, Hs, len(lv), Ch, fmt, _p(q), n, float(max_aniso), mode, seed, _p(out),
-                              _p(idx), nthreads) != 0:
+    if lib().orc_ewa_filter2d_at(ptrs, Ws, Hs, len(lv), Ch, fmt, _p(q), _p(qi), n, float(max_aniso), mode, seed,
+                                 _p(out), _p(idx), nthreads) != 0:
         raise ValueError("orc_ewa_filter2d rejected its arguments")
     return out, idx
 
@@ -454,16 +466,24 @@ def dct_decode_all(blocks: np.ndarray) -> np.ndarray:
     return out
 
 
+def _qids(qids):
+    return None if qids is None else np.ascontiguousarray(qids, np.int64)
+
+
 def dct_filter2d(blocks: np.ndarray, uv: np.ndarray, filt: int, mode: int, seed: int = 0, want_index: bool = True,
-                 nthreads: int = 0):
+                 nthreads: int = 0, qids=None):
+    """qids: optional indices of the queries of the batch uv to evaluate (as
+    members of the whole batch); results follow their order."""
     b = np.ascontiguousarray(blocks, np.uint32)
     H, W, Ch = b.shape[0] * 8, b.shape[1] * 8, b.shape[2]
     uv = np.ascontiguousarray(uv, dtype=np.float32)
-    n = uv.shape[0]
+    qi = _qids(qids)
+    n = uv.shape[0] if qi is None else qi.shape[0]
     out = np.empty((n, Ch), np.float64)
     idx = np.empty((n, index_width(filt, 2)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE, STOCH_FIS)) \
         else None
-    if lib().orc_dct_filter2d(_p(b), W, H, Ch, _p(uv), n, filt, mode, seed, _p(out), _p(idx), nthreads) != 0:
+    if lib().orc_dct_filter2d_at(_p(b), W, H, Ch, _p(uv), _p(qi), n, filt, mode, seed, _p(out), _p(idx),
+                                 nthreads) != 0:
         raise ValueError("orc_dct_filter2d rejected its arguments")
     return out, idx
 

@@ -639,15 +639,20 @@ static int orc_threads(int nthreads)
 
 int orc_max_threads(void) { return orc_threads(0); }
 
-static int orc_filter_src2d(const orc_src2d* src, const float* uv, int64_t n, int filter, int mode, uint64_t seed,
-                            double* out, int32_t* idx, int nthreads)
+/* Queries k = 0..n-1 of a batch, or, with qids, the queries qids[k] of a
+ * batch evaluated as members of it (a draw depends on the query's index);
+ * result k goes to out[k]. */
+static int orc_filter_src2d(const orc_src2d* src, const float* uv, const int64_t* qids, int64_t n, int filter,
+                            int mode, uint64_t seed, double* out, int32_t* idx, int nthreads)
 {
     if (mode < ORC_DET || mode > ORC_STOCH_FIS || (orc_positivized(filter) && mode == ORC_STOCH_FIS)) return -1;
     int nt = orc_threads(nthreads), iw = orc_index_width(filter, 2), C = src->C;
     (void)nt;
 #pragma omp parallel for schedule(static) num_threads(nt)
-    for (int64_t q = 0; q < n; ++q)
-        orc_query2d(src, uv + 2 * q, filter, mode, seed, (uint32_t)q, out + q * C, idx ? idx + iw * q : NULL);
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t q = qids ? qids[k] : k;
+        orc_query2d(src, uv + 2 * q, filter, mode, seed, (uint32_t)q, out + k * C, idx ? idx + iw * k : NULL);
+    }
     return 0;
 }
 
@@ -658,7 +663,16 @@ int orc_dct_filter2d(const uint32_t* blocks, int W, int H, int C, const float* u
     if (W <= 0 || H <= 0 || W % 8 || H % 8 || C <= 0 || C > 16 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL)
         return -1;
     orc_src2d src = {blocks, W, H, C, ORC_FMT_DCT};
-    return orc_filter_src2d(&src, uv, n, filter, mode, seed, out, idx, nthreads);
+    return orc_filter_src2d(&src, uv, NULL, n, filter, mode, seed, out, idx, nthreads);
+}
+
+int orc_dct_filter2d_at(const uint32_t* blocks, int W, int H, int C, const float* uv, const int64_t* qids, int64_t m,
+                        int filter, int mode, uint64_t seed, double* out, int32_t* idx, int nthreads)
+{
+    if (W <= 0 || H <= 0 || W % 8 || H % 8 || C <= 0 || C > 16 || m < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL)
+        return -1;
+    orc_src2d src = {blocks, W, H, C, ORC_FMT_DCT};
+    return orc_filter_src2d(&src, uv, qids, m, filter, mode, seed, out, idx, nthreads);
 }
 
 int orc_filter2d(const void* tex, int W, int H, int C, int fmt, const float* uv, int64_t n,
@@ -666,7 +680,7 @@ int orc_filter2d(const void* tex, int W, int H, int C, int fmt, const float* uv,
 {
     if (W <= 0 || H <= 0 || C <= 0 || C > 16 || n < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
     orc_src2d src = {tex, W, H, C, fmt};
-    return orc_filter_src2d(&src, uv, n, filter, mode, seed, out, idx, nthreads);
+    return orc_filter_src2d(&src, uv, NULL, n, filter, mode, seed, out, idx, nthreads);
 }
 
 /* Brute-force deterministic 2D filter: every texel of a 6x6 window around the
@@ -1098,15 +1112,17 @@ static void orc_gauss_query(const orc_src2d* src, const float* uv, double sigma,
     free(wx);
 }
 
-static int orc_gauss_src2d(const orc_src2d* src, const float* uv, int64_t n, double sigma, int gmode, uint64_t seed,
-                           double* out, int32_t* idx, int nthreads)
+static int orc_gauss_src2d(const orc_src2d* src, const float* uv, const int64_t* qids, int64_t n, double sigma,
+                           int gmode, uint64_t seed, double* out, int32_t* idx, int nthreads)
 {
     if (!(sigma > 0.0 && sigma <= 16.0) || gmode < ORC_G_FIS || gmode > ORC_G_DISCRETE_MEAN || n < 0) return -1;
     int nt = orc_threads(nthreads), C = src->C;
     (void)nt;
 #pragma omp parallel for schedule(static) num_threads(nt)
-    for (int64_t q = 0; q < n; ++q)
-        orc_gauss_query(src, uv + 2 * q, sigma, gmode, seed, (uint32_t)q, out + q * C, idx ? idx + 2 * q : NULL);
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t q = qids ? qids[k] : k;
+        orc_gauss_query(src, uv + 2 * q, sigma, gmode, seed, (uint32_t)q, out + k * C, idx ? idx + 2 * k : NULL);
+    }
     return 0;
 }
 
@@ -1115,7 +1131,7 @@ int orc_gauss_filter2d(const void* tex, int W, int H, int C, int fmt, const floa
 {
     if (W <= 0 || H <= 0 || C <= 0 || C > 16) return -1;
     orc_src2d src = {tex, W, H, C, fmt};
-    return orc_gauss_src2d(&src, uv, n, sigma, gmode, seed, out, idx, nthreads);
+    return orc_gauss_src2d(&src, uv, NULL, n, sigma, gmode, seed, out, idx, nthreads);
 }
 
 int orc_dct_gauss_filter2d(const uint32_t* blocks, int W, int H, int C, const float* uv, int64_t n, double sigma,
@@ -1123,18 +1139,35 @@ int orc_dct_gauss_filter2d(const uint32_t* blocks, int W, int H, int C, const fl
 {
     if (W <= 0 || H <= 0 || W % 8 || H % 8 || C <= 0 || C > 16) return -1;
     orc_src2d src = {blocks, W, H, C, ORC_FMT_DCT};
-    return orc_gauss_src2d(&src, uv, n, sigma, gmode, seed, out, idx, nthreads);
+    return orc_gauss_src2d(&src, uv, NULL, n, sigma, gmode, seed, out, idx, nthreads);
 }
 
-/* FIS sample positions (binary64) of a batch, for boundary-distance checks. */
-int orc_gauss_fis_positions(int W, int H, const float* uv, int64_t n, double sigma, uint64_t seed, double* pos)
+int orc_dct_gauss_filter2d_at(const uint32_t* blocks, int W, int H, int C, const float* uv, const int64_t* qids,
+                              int64_t m, double sigma, int gmode, uint64_t seed, double* out, int32_t* idx,
+                              int nthreads)
 {
-    for (int64_t q = 0; q < n; ++q) {
+    if (W <= 0 || H <= 0 || W % 8 || H % 8 || C <= 0 || C > 16) return -1;
+    orc_src2d src = {blocks, W, H, C, ORC_FMT_DCT};
+    return orc_gauss_src2d(&src, uv, qids, m, sigma, gmode, seed, out, idx, nthreads);
+}
+
+/* FIS sample positions (binary64) of a batch (or of its queries qids[k]),
+ * for boundary-distance checks. */
+int orc_gauss_fis_positions_at(int W, int H, const float* uv, const int64_t* qids, int64_t m, double sigma,
+                               uint64_t seed, double* pos)
+{
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t q = qids ? qids[k] : k;
         float x, y;
         orc_raster2d(uv + 2 * q, W, H, &x, &y);
-        orc_gauss_fis_position((double)x, (double)y, sigma, seed, (uint32_t)q, &pos[2 * q], &pos[2 * q + 1]);
+        orc_gauss_fis_position((double)x, (double)y, sigma, seed, (uint32_t)q, &pos[2 * k], &pos[2 * k + 1]);
     }
     return 0;
+}
+
+int orc_gauss_fis_positions(int W, int H, const float* uv, int64_t n, double sigma, uint64_t seed, double* pos)
+{
+    return orc_gauss_fis_positions_at(W, H, uv, NULL, n, sigma, seed, pos);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1407,9 +1440,9 @@ int orc_ewa_lods(const float* q, int64_t n, int levels, float max_aniso, double*
     return 0;
 }
 
-int orc_ewa_filter2d(const void* const* level_texels, const int* W, const int* H, int levels, int C, int fmt,
-                     const float* q, int64_t n, float max_aniso, int mode, uint64_t seed, double* out, int32_t* idx,
-                     int nthreads)
+int orc_ewa_filter2d_at(const void* const* level_texels, const int* W, const int* H, int levels, int C, int fmt,
+                        const float* q, const int64_t* qids, int64_t n, float max_aniso, int mode, uint64_t seed,
+                        double* out, int32_t* idx, int nthreads)
 {
     if (!level_texels || levels < 1 || C < 1 || C > 16 || n < 0 || !(max_aniso >= 1.0f) ||
         (mode != ORC_DET && mode != ORC_STOCH))
@@ -1421,7 +1454,8 @@ int orc_ewa_filter2d(const void* const* level_texels, const int* W, const int* H
     (void)nt;
 #pragma omp parallel for schedule(dynamic, 256) num_threads(nt)
     for (int64_t k = 0; k < n; ++k) {
-        const float* qk = q + 6 * k;
+        const int64_t qi = qids ? qids[k] : k;
+        const float* qk = q + 6 * qi;
         double* o = out + k * C;
         int32_t* ix = idx ? idx + 3 * k : NULL;
         int ok = 1;
@@ -1429,7 +1463,7 @@ int orc_ewa_filter2d(const void* const* level_texels, const int* W, const int* H
         if (!ok) { orc_nan_out(o, C, ix, 3); continue; }
         float d0[2], d1[2], sh;
         double lod = orc_ewa_axes(qk, levels, max_aniso, d0, d1, &sh);
-        uint32_t qid = (uint32_t)k;
+        uint32_t qid = (uint32_t)qi;
         if (!(sh > 0.0f)) {   /* degenerate footprint: bilinear on level 0 */
             orc_src2d s0 = {level_texels[0], W[0], H[0], C, fmt};
             float uv[2] = {qk[0], qk[1]};
@@ -1466,4 +1500,12 @@ int orc_ewa_filter2d(const void* const* level_texels, const int* W, const int* H
         }
     }
     return 0;
+}
+
+int orc_ewa_filter2d(const void* const* level_texels, const int* W, const int* H, int levels, int C, int fmt,
+                     const float* q, int64_t n, float max_aniso, int mode, uint64_t seed, double* out, int32_t* idx,
+                     int nthreads)
+{
+    return orc_ewa_filter2d_at(level_texels, W, H, levels, C, fmt, q, NULL, n, max_aniso, mode, seed, out, idx,
+                               nthreads);
 }

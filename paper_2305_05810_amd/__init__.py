@@ -80,9 +80,12 @@ def _declare(L):
     L.stf_filter_gaussian.argtypes = [vp, vp, i64, f32, i32, u64, vp, vp, vp]
     L.stf_filter_ewa.argtypes = [vp, vp, i64, f32, i32, u64, vp, vp, vp]
     L.stf_create_dct_texture2d.argtypes = [i32, i32, i32, vp, C.POINTER(vp)]
+    L.stf_stage_counting.argtypes = [i32]
+    L.stf_stage_counts.argtypes = [C.POINTER(u64), C.POINTER(u64)]
     for name in ("stf_create_texture2d", "stf_create_material2d", "stf_create_sparse_grid3d",
                  "stf_texture_bytes", "stf_filter", "stf_filter_moments", "stf_shade_filter", "stf_dct_encode",
-                 "stf_create_dct_texture2d", "stf_filter_gaussian", "stf_filter_ewa"):
+                 "stf_create_dct_texture2d", "stf_filter_gaussian", "stf_filter_ewa", "stf_stage_counting",
+                 "stf_stage_counts"):
         getattr(L, name).restype = i32
 
 
@@ -97,6 +100,17 @@ def stf_last_error() -> str:
 
 def stf_version() -> str:
     return lib().stf_version().decode()
+
+
+def stf_stage_counting(on: bool):
+    _check(lib().stf_stage_counting(1 if on else 0))
+
+
+def stf_stage_counts():
+    """(blocks that staged their taps in LDS, blocks) since counting began."""
+    a, b = C.c_uint64(), C.c_uint64()
+    _check(lib().stf_stage_counts(C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 class Texture:

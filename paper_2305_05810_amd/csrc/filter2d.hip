@@ -351,7 +351,7 @@ __device__ __forceinline__ int block_reduce_min(int v, int* red)
 template <class Src, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_tex2d_det_staged(Src S, const float* __restrict__ q, int32_t n,
                                                             float* __restrict__ out, const int32_t* __restrict__ order,
-                                                            int scatter)
+                                                            int scatter, unsigned long long* __restrict__ counters)
 {
     constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
     constexpr int CAP = Src::CAP;
@@ -385,7 +385,12 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_det_staged(Src S, const float* 
     float acc[CAP];
 #pragma unroll
     for (int c = 0; c < CAP; ++c) acc[c] = 0.0f;
-    if (nin && ntex * C <= STAGE_FLOATS && ntex * STAGE_REUSE <= (int64_t)nin * NT * NT) {
+    const bool stage = nin && ntex * C <= STAGE_FLOATS && ntex * STAGE_REUSE <= (int64_t)nin * NT * NT;
+    if (counters && threadIdx.x == 0) {   // {blocks that staged, blocks}, when counting is on
+        if (stage) atomicAdd(&counters[0], 1ull);
+        atomicAdd(&counters[1], 1ull);
+    }
+    if (stage) {
         for (int t = threadIdx.x; t < (int)ntex; t += BLOCK) {
             float v[CAP];
             S.load(x0 + t % ew, y0 + t / ew, v);
@@ -738,7 +743,8 @@ void launch2d_kind(const Src& S, const float* q, int32_t n, int mode, uint32_t k
             // a frame in pixel order share most of their 16 taps, so a block
             // decodes its tap box once when the box is small enough (the
             // kernel decides per block and otherwise decodes per tap)
-            hipLaunchKernelGGL((k_tex2d_det_staged<Src, KIND>), grid, block, 0, stream, S, q, n, out, order, scatter);
+            hipLaunchKernelGGL((k_tex2d_det_staged<Src, KIND>), grid, block, 0, stream, S, q, n, out, order, scatter,
+                               stage_counters());
             return;
         }
         hipLaunchKernelGGL((k_tex2d_deterministic<Src, KIND>), grid, block, 0, stream, S, q, n, out, order, scatter);

@@ -661,7 +661,7 @@ __device__ __forceinline__ int wave_max(int v)
 template <int FMT, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_grid_det_staged(GridView g, const float* __restrict__ q, int32_t n,
                                                            float* __restrict__ out, const int32_t* __restrict__ order,
-                                                           int scatter)
+                                                           int scatter, unsigned long long* __restrict__ counters)
 {
     constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
     __shared__ float tile[STAGE_VOXELS];
@@ -730,6 +730,10 @@ __global__ __launch_bounds__(BLOCK) void k_grid_det_staged(GridView g, const flo
         // staging pays only for the queries that read texels; the others
         // (empty space) sum the background either way
         stage = (int64_t)__syncthreads_count(taps) * NT * NT * NT >= vol * STAGE_REUSE;
+    }
+    if (counters && threadIdx.x == 0) {   // {blocks that staged, blocks}, when counting is on
+        if (stage) atomicAdd(&counters[0], 1ull);
+        atomicAdd(&counters[1], 1ull);
     }
     if (stage) {
         // voxel v = threadIdx.x + k BLOCK of the box, x fastest; its
@@ -872,7 +876,8 @@ void launch3d_kind(const GridView& g, const float* q, int32_t n, int mode, uint3
     } else {
         dim3 grid((n + BLOCK - 1) / BLOCK);
         if (order && KIND != KIND_LINEAR)   // a sorted stream: neighbouring queries share their 64 taps
-            hipLaunchKernelGGL((k_grid_det_staged<FMT, KIND>), grid, block, 0, stream, g, q, n, out, order, scatter);
+            hipLaunchKernelGGL((k_grid_det_staged<FMT, KIND>), grid, block, 0, stream, g, q, n, out, order, scatter,
+                               stage_counters());
         else
             hipLaunchKernelGGL((k_grid_deterministic<FMT, KIND>), grid, block, 0, stream, g, q, n, out, order, scatter);
     }

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -114,6 +115,21 @@ void stf_clear_error()
     g_last_error.clear();
 }
 
+// Staging counters {blocks that staged their taps in LDS, blocks} of the
+// staged deterministic kernels.  Each device holds its own copy of the array;
+// host code uses the address hipGetSymbolAddress returns on that device.
+static __device__ unsigned long long g_stage_count[2];
+static unsigned long long* g_stage_ptr[64];   // per device, while counting is on
+static std::mutex g_stage_mu;
+
+unsigned long long* stage_counters()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    return g_stage_ptr[dev];
+}
+
 extern "C" {
 
 const char* stf_last_error(void)
@@ -124,6 +140,40 @@ const char* stf_last_error(void)
 const char* stf_version(void)
 {
     return "stf 0.1 (gfx950)";
+}
+
+stf_status stf_stage_counting(int32_t on)
+{
+    stf_clear_error();
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return stf_fail(STF_E_DEVICE, "no current device");
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    if (!on) {
+        g_stage_ptr[dev] = nullptr;
+        return STF_OK;
+    }
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_stage_count));
+    if (e == hipSuccess) e = hipMemset(p, 0, sizeof(g_stage_count));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "staging counters: %s", hipGetErrorString(e));
+    g_stage_ptr[dev] = (unsigned long long*)p;
+    return STF_OK;
+}
+
+stf_status stf_stage_counts(uint64_t* staged_blocks, uint64_t* blocks)
+{
+    stf_clear_error();
+    if (!staged_blocks || !blocks) return stf_fail(STF_E_INVALID, "NULL argument");
+    void* p = nullptr;
+    unsigned long long h[2] = {0, 0};
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_stage_count));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(h, p, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "staging counters: %s", hipGetErrorString(e));
+    *staged_blocks = h[0];
+    *blocks = h[1];
+    return STF_OK;
 }
 
 stf_status stf_create_texture2d(int32_t width, int32_t height, int32_t channels, stf_format fmt, int32_t levels,

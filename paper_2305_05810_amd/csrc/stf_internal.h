@@ -85,6 +85,11 @@ inline bool valid_filter(int f)
 }
 void stf_clear_error();
 
+// Device address of the staging counters {staged blocks, blocks} of the
+// current device while counting is on (stf_stage_counting), else nullptr.
+// The staged deterministic kernels take it as an argument.
+unsigned long long* stage_counters();
+
 // Kernel launchers; each returns hipSuccess or the launch error.
 // order: NULL, or the caller-batch index of each (sorted) query, which keys
 // its random draw; scatter: results go to out[order[i]] instead of out[i].

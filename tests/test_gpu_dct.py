@@ -23,6 +23,17 @@ FILTERS = [("linear", stf.STF_LINEAR, oracle.LINEAR), ("bspline", stf.STF_CUBIC_
 REL = 1e-6
 
 
+def _staged(fn):
+    """(blocks that staged their taps in LDS, blocks) of the staged kernels
+    during fn()."""
+    stf.stf_stage_counting(True)
+    try:
+        fn()
+        return stf.stf_stage_counts()
+    finally:
+        stf.stf_stage_counting(False)
+
+
 def _abs_terms(words):
     """A(x, y, c) = sum_k |dequant_k * basis_k(x, y)| for every texel."""
     BH, BW, Ch = words.shape
@@ -152,10 +163,16 @@ def test_dct_sorted_stream_staged_decode(dev, fname, gf, of, W, H, C):
     t = stf.stf_create_dct_texture2d(W, H, C, words)
     uv = synth.uv_queries(30000, seed=W) * np.float32(1.1) - np.float32(0.05)
     q = torch.from_numpy(uv).to(dev)
-    ref, _ = stf.filter(t, q, gf, stf.STF_DETERMINISTIC, 0)
+    res = {}
+    staged, blocks = _staged(lambda: res.update(ref=stf.filter(t, q, gf, stf.STF_DETERMINISTIC, 0)[0]))
+    ref = res["ref"]
+    nblocks = 0 if gf == stf.STF_LINEAR else (uv.shape[0] + 255) // 256   # bilinear: never the staged kernel
+    assert blocks == nblocks and staged == 0                       # uniform uv: no block box fits
     sq, order = stf.sort_queries(t, q)
     out = torch.empty_like(ref)
-    stf.stf_filter_ordered(t, sq, order, gf, stf.STF_DETERMINISTIC, 0, out, None, stf.STF_ORDER_SCATTER)
+    staged, blocks = _staged(lambda: stf.stf_filter_ordered(t, sq, order, gf, stf.STF_DETERMINISTIC, 0, out, None,
+                                                            stf.STF_ORDER_SCATTER))
+    assert blocks == nblocks and (gf == stf.STF_LINEAR or staged > blocks // 2), (staged, blocks)   # sorted
     assert torch.equal(out.nan_to_num(-7), ref.nan_to_num(-7)), fname
     gd = out.cpu().numpy().astype(np.float64)
     od, _ = oracle.dct_filter2d(words, uv, of, oracle.DET)
@@ -180,8 +197,14 @@ def test_dct_frame_order_staged_decode(dev, fname, gf, of):
     ys, xs = np.mgrid[0:fh, 0:fw]
     uv = np.stack([(xs + 0.37) / fw, (ys + 0.61) / fh], axis=-1).reshape(-1, 2).astype(np.float32)
     perm = np.random.default_rng(12).permutation(uv.shape[0])
-    framed, _ = stf.filter(t, torch.from_numpy(uv).to(dev), gf, stf.STF_DETERMINISTIC, 0)
-    shuffled, _ = stf.filter(t, torch.from_numpy(uv[perm]).to(dev), gf, stf.STF_DETERMINISTIC, 0)
+    res = {}
+    staged, blocks = _staged(lambda: res.update(f=stf.filter(t, torch.from_numpy(uv).to(dev), gf,
+                                                             stf.STF_DETERMINISTIC, 0)[0]))
+    assert staged == blocks == uv.shape[0] // 256, (staged, blocks)   # every block of the frame stages
+    staged, blocks = _staged(lambda: res.update(s=stf.filter(t, torch.from_numpy(uv[perm]).to(dev), gf,
+                                                             stf.STF_DETERMINISTIC, 0)[0]))
+    assert staged == 0 and blocks == uv.shape[0] // 256, (staged, blocks)
+    framed, shuffled = res["f"], res["s"]
     back = torch.empty_like(shuffled)
     back[torch.from_numpy(perm).to(dev)] = shuffled
     assert torch.equal(framed, back), fname

@@ -18,7 +18,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-SIGMAS = [0.3, 0.5, 0.8, 2.5]
+SIGMAS = [0.2, 0.3, 0.5, 0.8, 2.5]   # 0.2 < 1/4: the discrete draw is binary64 only
 
 
 @pytest.fixture(scope="module")
@@ -76,6 +76,7 @@ def test_fis_on_dct_texture(dev):
 @pytest.mark.parametrize("sigma", SIGMAS)
 def test_gaussian_modes(dev, tex_inputs, sigma):
     tex, uv = tex_inputs
+    sigma = float(np.float32(sigma))   # the call takes binary32 sigma: the oracle gets the same value
     t = stf.stf_create_texture2d(72, 56, 4, stf.STF_FMT_F32, [tex])
     q = torch.from_numpy(uv).to(dev)
     n = uv.shape[0]
@@ -109,6 +110,37 @@ def test_gaussian_modes(dev, tex_inputs, sigma):
         err = np.abs(gd - od)
         ok = (np.isnan(gd) & np.isnan(od)) | (err <= 1e-6 * np.abs(od) + 1e-12)
         assert ok.all(), (gm, np.nanmax(err / np.maximum(np.abs(od), 1e-30)))
+    t.destroy()
+
+
+@pytest.mark.parametrize("sigma", [0.2, 0.8, 2.5])
+def test_gaussian_taps_at_scale(dev, sigma):
+    sigma = float(np.float32(sigma))   # the call takes binary32 sigma: the oracle gets the same value
+    # 4M queries on a small texture, so the draws that are redone in binary64
+    # (FIS: samples within sigma 2^-14 of a texel edge; discrete: u * total
+    # within total 2^-12 of a cumulative sum, or every draw for sigma < 1/4)
+    # occur hundreds to thousands of times; every tap must equal the
+    # oracle's binary64 decision except within 1e-9 of a boundary.
+    rng = np.random.default_rng(int(sigma * 100))
+    tex = rng.random((48, 40, 1)).astype(np.float32)
+    n = 1 << 22
+    uv = rng.random((n, 2), dtype=np.float32)
+    t = stf.stf_create_texture2d(40, 48, 1, stf.STF_FMT_F32, [tex])
+    q = torch.from_numpy(uv).to(dev)
+    out = torch.empty((n, 1), dtype=torch.float32, device=dev)
+    idx = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    stf.stf_filter_gaussian(t, q, sigma, stf.STF_GAUSS_FIS, 17, out, idx)
+    _, oi = oracle.gauss_filter2d(tex, oracle.F32, uv, sigma, oracle.G_FIS, 17)
+    pos = oracle.gauss_fis_positions(40, 48, uv, sigma, 17)
+    dist = np.abs(pos - (np.floor(pos + 0.5) + 0.5))
+    dist = np.minimum(dist, np.abs(pos - (np.floor(pos + 0.5) - 0.5)))
+    redone = np.any(dist < sigma * 2.0 ** -14, axis=1)
+    assert redone.sum() >= 100, int(redone.sum())        # the binary64 branch ran (about 1000 sigma times)
+    diff = np.any(idx.cpu().numpy() != oi, axis=1)
+    assert not np.any(diff & ~np.any(dist < 1e-9, axis=1)), int(diff.sum())
+    stf.stf_filter_gaussian(t, q, sigma, stf.STF_GAUSS_DISCRETE, 18, out, idx)
+    _, oi = oracle.gauss_filter2d(tex, oracle.F32, uv, sigma, oracle.G_DISCRETE, 18)
+    assert np.array_equal(idx.cpu().numpy(), oi)
     t.destroy()
 
 

@@ -70,10 +70,40 @@ def test_grid_sort_and_ordered_filter(dev, grid_case):
         # LDS (blocks whose taps span too wide a box read global memory);
         # both give the unsorted call's values bit for bit
         dref, _ = stf.filter(tex, q, filt, stf.STF_DETERMINISTIC, 0)
+        stf.stf_stage_counting(True)
         stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_DETERMINISTIC, 0, out, None, stf.STF_ORDER_SCATTER)
+        staged, blocks = stf.stf_stage_counts()
+        stf.stf_stage_counting(False)
+        # trilinear never takes the staged kernel; on this sparse grid most
+        # sorted blocks meet no stored leaf, and those do not stage
+        assert blocks == (0 if filt == stf.STF_LINEAR else (p.shape[0] + 255) // 256), (staged, blocks)
         assert torch.equal(out.nan_to_num(-7), dref.nan_to_num(-7))
         stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_DETERMINISTIC, 0, out, None, 0)
         assert torch.equal(out.nan_to_num(-7), dref[order.long()].nan_to_num(-7))
+    tex.destroy()
+
+
+def test_grid_sorted_dense_stream_stages(dev):
+    # every leaf of a 64^3 grid stored: the blocks of a Morton-sorted stream
+    # meet stored leaves and cover small boxes, so (nearly) all of them stage
+    # their taps in LDS (84% measured: blocks that straddle a jump of the Morton
+    # curve span wider boxes), and the results equal the unsorted call's bit for bit
+    rng = np.random.default_rng(21)
+    vals = rng.random((512, 8, 8, 8)).astype(np.float32)
+    org = np.stack(np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij"), -1).reshape(-1, 3)[:, ::-1]
+    tex = stf.stf_create_sparse_grid3d((64, 64, 64), stf.STF_FMT_F32, (8 * org).astype(np.int32), vals)
+    p = synth.uniform_box_queries((64, 64, 64), 200000, seed=22, margin=-2.0)
+    q = torch.from_numpy(p).to(dev)
+    sq, order = stf.sort_queries(tex, q)
+    for filt in (stf.STF_CUBIC_BSPLINE, stf.STF_CUBIC_KEYS):
+        dref, _ = stf.filter(tex, q, filt, stf.STF_DETERMINISTIC, 0)
+        out = torch.empty_like(dref)
+        stf.stf_stage_counting(True)
+        stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_DETERMINISTIC, 0, out, None, stf.STF_ORDER_SCATTER)
+        staged, blocks = stf.stf_stage_counts()
+        stf.stf_stage_counting(False)
+        assert blocks == (p.shape[0] + 255) // 256 and staged > 0.75 * blocks, (staged, blocks)
+        assert torch.equal(out, dref)
     tex.destroy()
 
 
