@@ -150,6 +150,8 @@ def run_grid(args, torch, stf, synth):
         drawn = 2 if filt in stf.POSITIVIZED_FILTERS else 1
         b_alg = 12 + 4 + (drawn * texel_b if mode == stf.STF_STOCHASTIC else taps * texel_b)
         res[name] = variant_stats(n, args.steps, wall, kern, b_alg)
+        if sort_info is not None:   # the sort and this filter, back to back
+            res[name]["end_to_end_ms_with_sort"] = sort_info["sort_ms"] + res[name]["ms_per_step"]
         log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel "
             f"{res[name]['kernel_ms_mean'] * 1e3:.1f} us, {res[name]['achieved_gbs']:.0f} GB/s algorithmic")
 

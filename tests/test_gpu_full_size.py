@@ -101,3 +101,18 @@ def test_full_size_interpolating_cubics(dev, workload, gf, of):
     sc, _ = og.filter_at(pts, qids, of, oracle.DET_ABS, 0)
     assert np.all(np.abs(d[qids] - od) <= 1e-6 * sc)
     tex.destroy()
+
+
+def test_full_size_sort(dev, workload):
+    # the benchmark's 16M ray queries sorted by leaf Morton code: the stable
+    # order of the keys (recomputed on the host) and the queries in that order
+    import test_gpu_sort as ts
+    grid, pts, _ = workload
+    tex = stf.stf_create_sparse_grid3d(DIMS, stf.STF_FMT_F32, grid.origins, grid.values)
+    q = torch.from_numpy(pts).to(dev)
+    sq, order = stf.sort_queries(tex, q)
+    o = order.cpu().numpy()
+    keys = ts._keys3d(pts, DIMS)
+    assert np.array_equal(o, np.argsort(keys, kind="stable"))
+    assert np.array_equal(sq.cpu().numpy(), pts[o])
+    tex.destroy()

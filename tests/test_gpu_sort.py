@@ -1,7 +1,8 @@
-"""Morton-ordered query streams: the sort returns a permutation whose keys
-(interleaved leaf / tile coordinates, recomputed here) do not decrease, and
-filtering the sorted stream reproduces stf_filter on the unsorted batch bit
-for bit (results scattered back) or in sorted order."""
+"""Morton-ordered query streams: the sort returns the stable order of the
+keys (interleaved leaf / tile coordinates clamped to the texture, recomputed
+here; non-finite queries last; equal keys in input order), and filtering the
+sorted stream reproduces stf_filter on the unsorted batch bit for bit
+(results scattered back) or in sorted order."""
 import numpy as np
 import pytest
 import torch
@@ -19,22 +20,35 @@ def _spread(v, bits, step):
     return out
 
 
-def _keys3d(p):
+def _bits(cells):
+    return int(np.ceil(np.log2(max(cells, 1)))) if cells > 1 else 0
+
+
+def _cells(x, shift, cells):
+    c = np.floor(np.clip(np.nan_to_num(x, nan=0.0, posinf=0.0, neginf=0.0), -1.0, 16777215.0)).astype(np.int64) >> shift
+    return np.clip(c, 0, cells - 1).astype(np.uint64)
+
+
+def _keys3d(p, dims):
+    # leaves per axis, Morton bits for the longest axis (at most 10: coarser cells beyond)
+    b = _bits(max((d + 7) // 8 for d in dims))
+    shift = 3 + max(0, b - 10)
+    b = min(b, 10)
+    cells = [(d + (1 << shift) - 1) >> shift for d in dims]
     fin = np.all(np.isfinite(p), axis=1)
-    c = np.floor(np.clip(np.nan_to_num(p, nan=0.0), -1.0, 16777215.0)).astype(np.int64) >> 3
-    c = np.clip(c, 0, 1023).astype(np.uint64)
-    k = _spread(c[:, 0], 10, 3) | (_spread(c[:, 1], 10, 3) << np.uint64(1)) | (_spread(c[:, 2], 10, 3) << np.uint64(2))
-    return np.where(fin, k, np.uint64(0xFFFFFFFF))
+    c = [_cells(p[:, a], shift, cells[a]) for a in range(3)]
+    k = _spread(c[0], b, 3) | (_spread(c[1], b, 3) << np.uint64(1)) | (_spread(c[2], b, 3) << np.uint64(2))
+    return np.where(fin, k, np.uint64(1) << np.uint64(3 * b))
 
 
 def _keys2d(uv, w, h):
     fin = np.all(np.isfinite(uv), axis=1)
     x = (uv[:, 0] * np.float32(w) - np.float32(0.5)).astype(np.float32)
     y = (uv[:, 1] * np.float32(h) - np.float32(0.5)).astype(np.float32)
-    cx = np.clip(np.floor(np.clip(np.nan_to_num(x), -1, 16777215)).astype(np.int64) >> 2, 0, 32767).astype(np.uint64)
-    cy = np.clip(np.floor(np.clip(np.nan_to_num(y), -1, 16777215)).astype(np.int64) >> 2, 0, 32767).astype(np.uint64)
-    k = _spread(cx, 15, 2) | (_spread(cy, 15, 2) << np.uint64(1))
-    return np.where(fin, k, np.uint64(0xFFFFFFFF))
+    cw, ch = (w + 3) // 4, (h + 3) // 4
+    b = _bits(max(cw, ch))
+    k = _spread(_cells(x, 2, cw), b, 2) | (_spread(_cells(y, 2, ch), b, 2) << np.uint64(1))
+    return np.where(fin, k, np.uint64(1) << np.uint64(2 * b))
 
 
 @pytest.fixture(scope="module")
@@ -46,8 +60,8 @@ def grid_case():
 
 
 def _check_order(keys, order, n):
-    assert np.array_equal(np.sort(order), np.arange(n))
-    assert np.all(np.diff(keys[order].astype(np.int64)) >= 0)
+    # the stable order: sorted keys, equal keys in input order
+    assert np.array_equal(order, np.argsort(keys, kind="stable")), int(np.sum(order != np.argsort(keys, kind="stable")))
 
 
 def test_grid_sort_and_ordered_filter(dev, grid_case):
@@ -56,7 +70,7 @@ def test_grid_sort_and_ordered_filter(dev, grid_case):
     q = torch.from_numpy(p).to(dev)
     sq, order = stf.sort_queries(tex, q)
     o = order.cpu().numpy()
-    _check_order(_keys3d(p), o, p.shape[0])
+    _check_order(_keys3d(p, g.dims), o, p.shape[0])
     assert np.array_equal(np.nan_to_num(sq.cpu().numpy(), nan=-9), np.nan_to_num(p[o], nan=-9))
     for filt in (stf.STF_LINEAR, stf.STF_CUBIC_BSPLINE, stf.STF_CUBIC_KEYS):
         ref, ridx = stf.filter(tex, q, filt, stf.STF_STOCHASTIC, 11, want_index=True)
@@ -142,6 +156,33 @@ def test_tex2d_sort_and_ordered_filter(dev):
         dref, _ = stf.filter(tex, q, filt, stf.STF_DETERMINISTIC, 0)
         stf.stf_filter_ordered(tex, sq, order, filt, stf.STF_DETERMINISTIC, 0, out, None, stf.STF_ORDER_SCATTER)
         assert torch.equal(out, dref)
+    tex.destroy()
+
+
+@pytest.mark.parametrize("case", ["one_pass_3d", "coarse_cells_3d", "three_passes_2d", "two_passes_2d"])
+def test_sort_key_widths(dev, case):
+    # key widths of 1 to 3 radix passes, and grids whose leaves per axis
+    # exceed 2^10 (Morton cells of 16 voxels): the stable order every time
+    rng = np.random.default_rng(7)
+    if case.endswith("3d"):
+        dims = (16, 16, 16) if case == "one_pass_3d" else (16384, 16, 24)
+        vals = rng.random((1, 8, 8, 8)).astype(np.float32)
+        tex = stf.stf_create_sparse_grid3d(dims, stf.STF_FMT_F32, np.zeros((1, 3), np.int32), vals)
+        p = synth.uniform_box_queries(dims, 100003, seed=8, margin=4.0)
+        p[7] = [np.inf, 1, 1]
+        p[11] = [np.nan, 2, 2]
+        keys = _keys3d(p, dims)
+    else:
+        w, h = (4096, 8) if case == "three_passes_2d" else (1000, 600)
+        tex = stf.stf_create_texture2d(w, h, 1, stf.STF_FMT_F32, [np.zeros((h, w, 1), np.float32)])
+        p = (rng.random((100003, 2)) * 1.2 - 0.1).astype(np.float32)
+        p[3] = [np.nan, 0.5]
+        keys = _keys2d(p, w, h)
+    q = torch.from_numpy(p).to(dev)
+    sq, order = stf.sort_queries(tex, q)
+    o = order.cpu().numpy()
+    _check_order(keys, o, p.shape[0])
+    assert np.array_equal(np.nan_to_num(sq.cpu().numpy(), nan=-9, posinf=-8), np.nan_to_num(p[o], nan=-9, posinf=-8))
     tex.destroy()
 
 
