@@ -286,14 +286,18 @@ stf_status stf_create_dct_texture2d(int32_t width, int32_t height, int32_t chann
 /* Device workspace (bytes) that stf_sort_queries needs for n queries. */
 stf_status stf_sort_workspace_bytes(int64_t n, size_t* bytes);
 
-/* Orders n queries of `tex` by the Morton code of their 8^3 leaf (3D grids)
- * or 4x4 texel tile (2D textures, level 0), so that queries touching the
- * same region run next to each other.  Writes order_dev[k] = the index in
- * queries_dev of the k-th query in that order (a permutation; ties keep
- * their input order; non-finite queries go last) and sorted_queries_dev[k]
- * = queries_dev[order_dev[k]].  workspace_dev: at least
- * stf_sort_workspace_bytes(n) bytes of device memory, 256-byte aligned,
- * used only during the call's stream work. */
+/* Orders n queries of `tex` by the Morton code of their cell, so that
+ * queries touching the same region run next to each other: the cell is the
+ * 8^3 leaf of a 3D grid (cells of 8 * 2^s voxels when a grid has more than
+ * 1024 leaves along an axis) or the 4x4 texel tile of level 0 of a 2D
+ * texture, cell coordinates clamped to the texture's cells (queries outside
+ * go with the border cells), b bits per axis where 2^b cells cover the
+ * longest axis.  Queries with a non-finite coordinate go last.  The sort is
+ * stable: equal keys keep their input order.  Writes order_dev[k] = the
+ * index in queries_dev of the k-th query in that order (a permutation) and
+ * sorted_queries_dev[k] = queries_dev[order_dev[k]].  workspace_dev: at
+ * least stf_sort_workspace_bytes(n) bytes of device memory, 256-byte
+ * aligned, used only during the call's stream work. */
 stf_status stf_sort_queries(const stf_texture* tex, const float* queries_dev, int64_t n,
                             float* sorted_queries_dev, int32_t* order_dev, void* workspace_dev,
                             size_t workspace_bytes, void* hip_stream);
