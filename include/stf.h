@@ -302,6 +302,24 @@ stf_status stf_sort_queries(const stf_texture* tex, const float* queries_dev, in
                             float* sorted_queries_dev, int32_t* order_dev, void* workspace_dev,
                             size_t workspace_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sort as stf_sort_queries, with the same results bit for bit, whose
+ * workspace is a fixed device array inside the library instead of a
+ * caller-provided buffer.  The call allocates nothing (no hipMalloc, no
+ * allocating library routine); the caller still provides the queries and
+ * the two outputs.
+ *   - n <= STF_SORT_NOALLOC_MAX_QUERIES (2^20); larger n gives STF_E_INVALID.
+ *   - The array takes 16.3 MB of device memory on each device the call runs
+ *     on, from the library's load until the process ends.
+ *   - Every call on a device uses that device's single array: calls that
+ *     overlap on one device (concurrent streams or host threads) race and
+ *     must be serialized by the caller.  The array keeps the last call's
+ *     contents; the sort needs no part of it cleared. */
+#define STF_SORT_NOALLOC_MAX_QUERIES (1 << 20)
+stf_status stf_sort_queries_noalloc(const stf_texture* tex, const float* queries_dev, int64_t n,
+                                    float* sorted_queries_dev, int32_t* order_dev, void* hip_stream);
+
 #define STF_ORDER_SCATTER 1u   /* results at out[order[k]] (the caller's order) */
 
 /* stf_filter on a sorted stream: query k of sorted_queries_dev is query

@@ -609,7 +609,8 @@ def _sort_lib():
         L.stf_sort_workspace_bytes.argtypes = [i64, C.POINTER(C.c_size_t)]
         L.stf_sort_queries.argtypes = [vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
         L.stf_filter_ordered.argtypes = [vp, vp, vp, i64, i32, i32, u64, vp, vp, u32, vp]
-        for name in ("stf_sort_workspace_bytes", "stf_sort_queries", "stf_filter_ordered"):
+        L.stf_sort_queries_noalloc.argtypes = [vp, vp, i64, vp, vp, vp]
+        for name in ("stf_sort_workspace_bytes", "stf_sort_queries", "stf_filter_ordered", "stf_sort_queries_noalloc"):
             getattr(L, name).restype = i32
         L._sort_declared = True
     return L
@@ -644,6 +645,21 @@ def stf_filter_ordered(tex: Texture, sorted_queries, order, filter: int, mode: i
                                           _dev_ptr(order, "order"), sorted_queries.shape[0], filter, mode,
                                           seed & (2 ** 64 - 1), _dev_ptr(out, "out"), _dev_ptr(out_index, "out_index"),
                                           flags, _stream(stream)))
+
+
+STF_SORT_NOALLOC_MAX_QUERIES = 1 << 20
+
+
+def stf_sort_queries_noalloc(tex: Texture, queries, sorted_queries, order, stream=None):
+    """The allocation-free sort (its workspace is a fixed device array of the
+    library; n <= STF_SORT_NOALLOC_MAX_QUERIES)."""
+    n = queries.shape[0]
+    _check_queries(tex, queries, n)
+    if sorted_queries.numel() < n * tex.dims or order.numel() < n:
+        raise ValueError("sorted_queries or order is too small")
+    _check(_sort_lib().stf_sort_queries_noalloc(tex.handle, _dev_ptr(queries, "queries"), n,
+                                                _dev_ptr(sorted_queries, "sorted_queries"),
+                                                _dev_ptr(order, "order"), _stream(stream)))
 
 
 def sort_queries(tex: Texture, queries, stream=None):

@@ -34,6 +34,7 @@
 //      consecutive positions of a digit's run.  The last pass writes the
 //      permutation and gathers the queries instead of (key, id) pairs.
 #include <algorithm>
+#include <mutex>
 
 #include "device_common.h"
 #include "stf_internal.h"
@@ -587,9 +588,61 @@ stf_status check_sort_args(const stf_texture* tex, const float* queries_dev, int
     return STF_OK;
 }
 
+// The allocation-free variant's workspace: a file-scope device array of a
+// fixed size, one copy per device, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it only stands for
+// the symbol); it uses the device address that hipGetSymbolAddress returns on
+// each device, looked up on the first call there.
+constexpr int64_t NOALLOC_MAX_QUERIES = STF_SORT_NOALLOC_MAX_QUERIES;   // from stf.h
+constexpr size_t NOALLOC_BYTES = (size_t)NOALLOC_MAX_QUERIES * 16 + ((size_t)NOALLOC_MAX_QUERIES / TILE) * MAX_R * 4 +
+                                 ((size_t)NOALLOC_MAX_QUERIES / TILE / CHUNK + 1) * MAX_R * 4 + 2 * MAX_R * 4 +
+                                 8 * 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static void* g_scratch_ptr[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// The device address of `scratch` on the current device (nullptr on failure).
+void* scratch_address(int* dev_out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    *dev_out = dev;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
+
+stf_status stf_sort_queries_noalloc(const stf_texture* tex, const float* queries_dev, int64_t n,
+                                    float* sorted_queries_dev, int32_t* order_dev, void* hip_stream)
+{
+    stf_clear_error();
+    if (n > NOALLOC_MAX_QUERIES)
+        return stf_fail(STF_E_INVALID, "n = %lld exceeds the %lld queries of the allocation-free sort's workspace",
+                        (long long)n, (long long)NOALLOC_MAX_QUERIES);
+    stf_status s = check_sort_args(tex, queries_dev, n, sorted_queries_dev, order_dev);
+    if (s != STF_OK || n == 0) return s;
+    if (work_bytes(n) > NOALLOC_BYTES) return stf_fail(STF_E_INVALID, "workspace layout exceeds the static array");
+    int dev = 0;
+    void* ws = scratch_address(&dev);
+    if (!ws) return stf_fail(STF_E_DEVICE, "hipGetSymbolAddress of the sort workspace failed");
+    hipError_t e = run_sort(tex, queries_dev, (int32_t)n, sorted_queries_dev, order_dev, carve(ws, n),
+                            (hipStream_t)hip_stream);
+    if (e != hipSuccess) return stf_fail(STF_E_DEVICE, "sorting failed: %s", hipGetErrorString(e));
+    return STF_OK;
+}
 
 stf_status stf_sort_workspace_bytes(int64_t n, size_t* bytes)
 {
