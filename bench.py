@@ -133,14 +133,6 @@ def run_grid(args, torch, stf, synth):
                 ("det_mitchell", stf.STF_CUBIC_MITCHELL, stf.STF_DETERMINISTIC, 64)]
     if args.only:
         variants = [v for v in variants if v[0] == args.only]
-    if args.copy_calibration:
-        # a plain device copy of known size, for scaling hardware byte counters
-        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"copy calibration: 3 x {a.numel() * 4} bytes read and written")
     res = {}
     seed = 0x5EED
     for name, filt, mode, taps in variants:
@@ -155,7 +147,7 @@ def run_grid(args, torch, stf, synth):
         log(f"{name}: {res[name]['lookups_per_s'] / 1e9:.2f} G lookups/s, kernel "
             f"{res[name]['kernel_ms_mean'] * 1e3:.1f} us, {res[name]['achieved_gbs']:.0f} GB/s algorithmic")
 
-    parity, cpu = {}, None
+    parity, cpu, quant = {}, None, {}
     if not args.no_check:
         import oracle
         ofmt = {"f32": oracle.F32, "f16": oracle.F16, "bf16": oracle.BF16, "fp8_e4m3": oracle.FP8_E4M3}[args.fmt]
@@ -164,6 +156,7 @@ def run_grid(args, torch, stf, synth):
         qids = np.sort(rng.choice(n, 1 << 16, replace=False))
         ofilts = {stf.STF_LINEAR: oracle.LINEAR, stf.STF_CUBIC_BSPLINE: oracle.CUBIC, stf.STF_CUBIC_KEYS: oracle.KEYS,
                   stf.STF_CUBIC_MITCHELL: oracle.MITCHELL}
+        sampled_gpu = {}
         for name, filt, mode, _ in variants:
             ofilt = ofilts[filt]
             if mode == stf.STF_STOCHASTIC and filt in stf.POSITIVIZED_FILTERS:
@@ -196,6 +189,7 @@ def run_grid(args, torch, stf, synth):
                 ov, oi = og.filter_at(pts, qids, ofilt, oracle.STOCH, seed)
                 parity[name] = dict(sampled=int(qids.size), index_mismatches=int(np.any(gi != oi, axis=1).sum()),
                                     value_mismatches=int((gv != ov.astype(np.float32)).sum()))
+                sampled_gpu[name] = gv
             else:
                 call(filt, mode, seed, out)
                 gv = out[:, 0].cpu().numpy()
@@ -204,6 +198,7 @@ def run_grid(args, torch, stf, synth):
                     inv[order.cpu().numpy()] = np.arange(n)
                     gv = gv[inv]
                 gv = gv[qids].astype(np.float64)
+                sampled_gpu[name] = gv
                 ov, _ = og.filter_at(pts, qids, ofilt, oracle.DET, 0)
                 scale, _ = og.filter_at(pts, qids, ofilt, oracle.DET_ABS, 0)   # sum |w_k t_k|
                 err = np.abs(gv - ov)
@@ -211,6 +206,21 @@ def run_grid(args, torch, stf, synth):
                 parity[name] = dict(sampled=int(qids.size), max_rel_err=float(rel.max()),
                                     within_1e6=bool(np.all(err <= 1e-6 * scale)))
             log(f"parity {name}: {parity[name]}")
+        if args.fmt != "f32":
+            # precision: the results from 16- / 8-bit texels against the FP64
+            # oracle on the binary32 grid they were rounded from
+            og32 = oracle.Grid(dims, oracle.F32, grid.origins, grid.values)
+            for name, filt, mode, _ in variants:
+                if name not in sampled_gpu or filt in stf.POSITIVIZED_FILTERS:
+                    continue
+                if mode == stf.STF_STOCHASTIC:
+                    ref, _ = og32.filter_at(pts, qids, ofilts[filt], oracle.STOCH, seed)
+                    scale = np.abs(ref)
+                else:
+                    ref, _ = og32.filter_at(pts, qids, ofilts[filt], oracle.DET, 0)
+                    scale, _ = og32.filter_at(pts, qids, ofilts[filt], oracle.DET_ABS, 0)
+                quant[name] = quantization_error(sampled_gpu[name], ref, scale)
+                log(f"{args.fmt} vs the FP64 oracle on the f32 grid, {name}: {quant[name]}")
         if not args.no_cpu and "stoch_cubic" in res:
             m = min(args.cpu_sample, n)
             sample = np.ascontiguousarray(pts[:m])
@@ -275,6 +285,7 @@ def run_grid(args, torch, stf, synth):
         "stream_only_empty_grid": stream_only,
         "sort": sort_info,
         "parity": parity,
+        "error_vs_f32_oracle": quant or None,
         "hbm_copy_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["achieved_gbs"] / HBM_PEAK_GBS,
@@ -322,9 +333,29 @@ def run_grid_medium(args, torch, stf, synth, grid, tex, raw, out, seed, texel_b)
         scale, _ = og.filter_at(mp, qids, oracle.CUBIC, oracle.DET_ABS, 0)
         par["det_within_1e6"] = bool(np.all(np.abs(gd - od) <= 1e-6 * scale))
         res["parity"] = par
+        if args.fmt != "f32":
+            og32 = oracle.Grid(grid.dims, oracle.F32, grid.origins, grid.values)
+            sref, _ = og32.filter_at(mp, qids, oracle.CUBIC, oracle.STOCH, seed)
+            dref, _ = og32.filter_at(mp, qids, oracle.CUBIC, oracle.DET, 0)
+            dscale, _ = og32.filter_at(mp, qids, oracle.CUBIC, oracle.DET_ABS, 0)
+            res["error_vs_f32_oracle"] = {"stoch_cubic": quantization_error(gv, sref, np.abs(sref)),
+                                          "det_cubic": quantization_error(gd, dref, dscale)}
+            log(f"in-medium {args.fmt} vs the FP64 oracle on the f32 grid: {res['error_vs_f32_oracle']}")
         log(f"in-medium parity: {par}")
     del qm
     return res
+
+
+def quantization_error(got, ref32, scale):
+    """Error of results from 16- or 8-bit texels against the FP64 oracle on
+    the binary32 texture (same queries, same taps): max abs, RMS, and the
+    max relative to the absolute scale (|value| for a drawn texel, sum
+    |w t| for the deterministic filter) over results with a non-zero scale."""
+    err = np.abs(got.astype(np.float64) - ref32)
+    live = scale > 0
+    return {"max_abs": float(err.max()), "rms": float(np.sqrt(np.mean(err ** 2))),
+            "max_rel": float(np.max(err[live] / scale[live])) if live.any() else 0.0,
+            "sampled": int(got.size)}
 
 
 def positivized_scale(oracle, og, pts, oi, ofilt):
@@ -762,7 +793,7 @@ def main():
     ap.add_argument("--neural-size", type=int, default=4096)
     ap.add_argument("--neural-steps", type=int, default=1000)
     ap.add_argument("--loads", type=float, nargs="+", default=[0.5e9, 1e9, 2e9])
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -774,6 +805,15 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain device copy of known size, for scaling hardware byte counters
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration: 3 x 268435456 bytes read and written")
     run = {"grid": run_grid, "tex2d": run_tex2d, "shade": run_shade, "neural": run_neural, "dct": run_dct, "gauss": run_gauss, "ewa": run_ewa,
            "serving": run_serving}[args.workload]
     line = run(args, torch, stf, synth)
