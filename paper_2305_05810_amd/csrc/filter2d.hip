@@ -679,22 +679,25 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __res
 #pragma unroll
         for (int c = 0; c < CAP; ++c) v[c] = ok ? acc[c] : __builtin_nanf("");
     } else {   // GAUSS_FIS_MEAN
+        // The x weights of the window are kept in LDS, one column per thread
+        // (a run-time sized array in registers would live in scratch); the y
+        // weights follow as running differences in the row loop.
+        __shared__ float wxs[GAUSS_MAX_TAPS][BLOCK];
         const int nt = 2 * radius + 2;
-        float wx[GAUSS_MAX_TAPS], wy[GAUSS_MAX_TAPS];
         double px = gauss_phi(((double)(cx - radius) - xe - 0.5) / sg);
         double py = gauss_phi(((double)(cy - radius) - ye - 0.5) / sg);
         for (int k = 0; k < nt; ++k) {
             const double qx = gauss_phi(((double)(cx - radius + k) - xe + 0.5) / sg);
-            const double qy = gauss_phi(((double)(cy - radius + k) - ye + 0.5) / sg);
-            wx[k] = (float)(qx - px);
-            wy[k] = (float)(qy - py);
+            wxs[k][threadIdx.x] = (float)(qx - px);
             px = qx;
-            py = qy;
         }
         float acc[CAP];
 #pragma unroll
         for (int c = 0; c < CAP; ++c) acc[c] = 0.0f;
         for (int b = 0; b < nt; ++b) {
+            const double qy = gauss_phi(((double)(cy - radius + b) - ye + 0.5) / sg);
+            const float wyb = (float)(qy - py);
+            py = qy;
             const int yy = clampi(cy - radius + b, S.h() - 1);
             float row[CAP];
 #pragma unroll
@@ -702,11 +705,12 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __res
             for (int a = 0; a < nt; ++a) {
                 float t[CAP];
                 S.load(clampi(cx - radius + a, S.w() - 1), yy, t);
+                const float wxa = wxs[a][threadIdx.x];
 #pragma unroll
-                for (int c = 0; c < CAP; ++c) row[c] = __builtin_fmaf(wx[a], t[c], row[c]);
+                for (int c = 0; c < CAP; ++c) row[c] = __builtin_fmaf(wxa, t[c], row[c]);
             }
 #pragma unroll
-            for (int c = 0; c < CAP; ++c) acc[c] = __builtin_fmaf(wy[b], row[c], acc[c]);
+            for (int c = 0; c < CAP; ++c) acc[c] = __builtin_fmaf(wyb, row[c], acc[c]);
         }
 #pragma unroll
         for (int c = 0; c < CAP; ++c) v[c] = ok ? acc[c] : __builtin_nanf("");

@@ -609,11 +609,18 @@ __device__ __forceinline__ float det_unscale(float acc)
 }
 
 // Deterministic filtering from global memory, one query per thread, at 8
-// waves per SIMD (64 VGPRs): the dependent leaf walks of empty-space queries
-// need the waves to hide their latency, and the tap rows of a query are
-// loaded in two halves to fit.
+// waves per SIMD (64 VGPRs) where that fits without spilling, else 7 (72
+// VGPRs; binary32 B-spline and Keys): the dependent leaf walks of
+// empty-space queries need the waves to hide their latency, and the tap rows
+// of a query are loaded in two halves to fit.
 template <int FMT, int KIND>
-__global__ __launch_bounds__(BLOCK, 8) void k_grid_deterministic(
+constexpr int det_waves()
+{
+    return (FMT == F32 && (KIND == KIND_BSPLINE || KIND == KIND_KEYS)) ? 7 : 8;
+}
+
+template <int FMT, int KIND>
+__global__ __launch_bounds__(BLOCK, (det_waves<FMT, KIND>())) void k_grid_deterministic(
     GridView g, const float* __restrict__ q, int32_t n, float* __restrict__ out, const int32_t* __restrict__ order,
     int scatter)
 {
