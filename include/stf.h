@@ -136,7 +136,12 @@ stf_status stf_create_texture2d(int32_t width, int32_t height, int32_t channels,
 /* Material texture for stf_shade_filter: 8-byte texels, bytes 0..2 albedo
  * RGB (UNORM8, linear), byte 3 roughness (UNORM8), bytes 4..5 and 6..7 the
  * tangent-space normal x and y as binary16.  Levels as for
- * stf_create_texture2d; level l must be supplied by the caller. */
+ * stf_create_texture2d; level l must be supplied by the caller.
+ * stf_filter, stf_sort_queries, stf_filter_gaussian and the server also read
+ * level 0 of a material as a 2D texture of six channels (albedo R, G, B,
+ * roughness, normal x, normal y; each decoded exactly: v / 255 and binary16
+ * widened), so a material is filtered before shading (Eq.
+ * traditional-lighting-integral) with every filter and mode of stf_filter. */
 stf_status stf_create_material2d(int32_t width, int32_t height, int32_t levels,
                                  const void* const* level_texels_host, stf_texture** out);
 
@@ -165,7 +170,8 @@ stf_status stf_texture_bytes(const stf_texture* tex, int64_t* bytes);
 /* Filter n queries.
  *   queries_dev:   n x 2 binary32 uv (2D textures, level 0) or n x 3 binary32
  *                  index-space positions (3D grids); 4-byte aligned.
- *   out_dev:       n x channels binary32 results (channels = 1 for grids).
+ *   out_dev:       n x channels binary32 results (channels = 1 for grids,
+ *                  6 for materials).
  *   out_index_dev: NULL, or (stochastic mode only) n x dims int32: the texel
  *                  that was read -- clamped (x, y) for 2D, (x, y, z) for 3D
  *                  (may lie outside the domain, which reads as background).
@@ -442,7 +448,7 @@ stf_status stf_ntex_filter(const stf_neural* nt, const float* queries_dev, int64
 /* Serving                                                                 */
 /* ---------------------------------------------------------------------- */
 /* A server batches stochastic lookup requests of any size against resident
- * textures (2D textures and 3D grids) as they arrive.  A worker thread
+ * textures (2D textures, materials and 3D grids) as they arrive.  A worker thread
  * admits requests in arrival order while fewer than max_resident are
  * resident and their device state fits in a memory_budget_bytes arena
  * (staged queries unless STF_SERVE_QUERIES_ON_DEVICE, results, indices),

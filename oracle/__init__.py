@@ -136,6 +136,10 @@ def _declare(L):
     L.orc_dct_gauss_filter2d.restype = i32
     L.orc_dct_gauss_filter2d_at.argtypes = [vp, i32, i32, i32, vp, vp, i64, dbl, i32, u64, vp, vp, i32]
     L.orc_dct_gauss_filter2d_at.restype = i32
+    L.orc_material_filter2d_at.argtypes = [vp, i32, i32, vp, vp, i64, i32, i32, u64, vp, vp, i32]
+    L.orc_material_filter2d_at.restype = i32
+    L.orc_material_gauss_filter2d_at.argtypes = [vp, i32, i32, vp, vp, i64, dbl, i32, u64, vp, vp, i32]
+    L.orc_material_gauss_filter2d_at.restype = i32
     L.orc_gauss_fis_positions_at.argtypes = [i32, i32, vp, vp, i64, dbl, u64, vp]
     L.orc_gauss_fis_positions_at.restype = i32
     L.orc_gauss_fis_positions.argtypes = [i32, i32, vp, i64, dbl, u64, vp]
@@ -485,6 +489,41 @@ def dct_filter2d(blocks: np.ndarray, uv: np.ndarray, filt: int, mode: int, seed:
     if lib().orc_dct_filter2d_at(_p(b), W, H, Ch, _p(uv), _p(qi), n, filt, mode, seed, _p(out), _p(idx),
                                  nthreads) != 0:
         raise ValueError("orc_dct_filter2d rejected its arguments")
+    return out, idx
+
+
+def material_filter2d(tex: np.ndarray, uv: np.ndarray, filt: int, mode: int, seed: int = 0,
+                      want_index: bool = True, nthreads: int = 0, qids=None):
+    """tex: (H, W, 8) uint8 material texels (albedo RGB, roughness UNORM8,
+    normal x, y binary16), filtered as six channels; qids as dct_filter2d."""
+    t = np.ascontiguousarray(tex, np.uint8)
+    H, W = t.shape[0], t.shape[1]
+    assert t.shape[2] == 8
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    qi = _qids(qids)
+    n = uv.shape[0] if qi is None else qi.shape[0]
+    out = np.empty((n, 6), np.float64)
+    idx = np.empty((n, index_width(filt, 2)), np.int32) if (want_index and mode in (STOCH, STOCH_REUSE, STOCH_FIS)) \
+        else None
+    if lib().orc_material_filter2d_at(_p(t), W, H, _p(uv), _p(qi), n, filt, mode, seed, _p(out), _p(idx),
+                                      nthreads) != 0:
+        raise ValueError("orc_material_filter2d rejected its arguments")
+    return out, idx
+
+
+def material_gauss_filter2d(tex: np.ndarray, uv: np.ndarray, sigma: float, gmode: int, seed: int = 0,
+                            want_index: bool = True, nthreads: int = 0, qids=None):
+    t = np.ascontiguousarray(tex, np.uint8)
+    H, W = t.shape[0], t.shape[1]
+    assert t.shape[2] == 8
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    qi = _qids(qids)
+    n = uv.shape[0] if qi is None else qi.shape[0]
+    out = np.empty((n, 6), np.float64)
+    idx = np.empty((n, 2), np.int32) if (want_index and gmode in (G_FIS, G_DISCRETE)) else None
+    if lib().orc_material_gauss_filter2d_at(_p(t), W, H, _p(uv), _p(qi), n, float(sigma), gmode, seed, _p(out),
+                                            _p(idx), nthreads) != 0:
+        raise ValueError("orc_material_gauss_filter2d rejected its arguments")
     return out, idx
 
 

@@ -508,21 +508,30 @@ int orc_fis_tap(int filter, double x, uint64_t seed, uint32_t qid, int a)
 /* ------------------------------------------------------------------------ */
 static int orc_clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-/* A 2D texel source: stored texels of a format, or DCT-compressed blocks
- * (dct.c).  Taps are clamped to the texture before they are read. */
+/* A 2D texel source: stored texels of a format, DCT-compressed blocks
+ * (dct.c), or 8-byte material texels (shade.c: albedo RGB, roughness, normal
+ * x and y, six channels).  Taps are clamped to the texture before they are
+ * read. */
 typedef struct orc_src2d {
     const void* tex;
-    int W, H, C, fmt;   /* fmt: a storage format, or ORC_FMT_DCT */
+    int W, H, C, fmt;   /* fmt: a storage format, ORC_FMT_DCT or ORC_FMT_MATERIAL */
 } orc_src2d;
 
 #define ORC_FMT_DCT 100
+#define ORC_FMT_MATERIAL 101
 double orc_dct_texel(const uint32_t* blocks, int W, int C, int x, int y, int c);
+void orc_material_decode(const uint8_t* texel, double out[6]);
 
 static double orc_src_texel(const orc_src2d* s, int x, int y, int c)
 {
     x = orc_clampi(x, 0, s->W - 1);
     y = orc_clampi(y, 0, s->H - 1);
     if (s->fmt == ORC_FMT_DCT) return orc_dct_texel((const uint32_t*)s->tex, s->W, s->C, x, y, c);
+    if (s->fmt == ORC_FMT_MATERIAL) {
+        double m[6];
+        orc_material_decode((const uint8_t*)s->tex + 8 * ((int64_t)y * s->W + x), m);
+        return m[c];
+    }
     return orc_decode(s->fmt, s->tex, ((int64_t)y * s->W + x) * s->C + c);
 }
 
@@ -672,6 +681,15 @@ int orc_dct_filter2d_at(const uint32_t* blocks, int W, int H, int C, const float
     if (W <= 0 || H <= 0 || W % 8 || H % 8 || C <= 0 || C > 16 || m < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL)
         return -1;
     orc_src2d src = {blocks, W, H, C, ORC_FMT_DCT};
+    return orc_filter_src2d(&src, uv, qids, m, filter, mode, seed, out, idx, nthreads);
+}
+
+/* Material textures (W x H texels of 8 bytes), filtered as six channels. */
+int orc_material_filter2d_at(const uint8_t* tex, int W, int H, const float* uv, const int64_t* qids, int64_t m,
+                             int filter, int mode, uint64_t seed, double* out, int32_t* idx, int nthreads)
+{
+    if (W <= 0 || H <= 0 || m < 0 || filter < ORC_LINEAR || filter > ORC_MITCHELL) return -1;
+    orc_src2d src = {tex, W, H, 6, ORC_FMT_MATERIAL};
     return orc_filter_src2d(&src, uv, qids, m, filter, mode, seed, out, idx, nthreads);
 }
 
@@ -1148,6 +1166,14 @@ int orc_dct_gauss_filter2d_at(const uint32_t* blocks, int W, int H, int C, const
 {
     if (W <= 0 || H <= 0 || W % 8 || H % 8 || C <= 0 || C > 16) return -1;
     orc_src2d src = {blocks, W, H, C, ORC_FMT_DCT};
+    return orc_gauss_src2d(&src, uv, qids, m, sigma, gmode, seed, out, idx, nthreads);
+}
+
+int orc_material_gauss_filter2d_at(const uint8_t* tex, int W, int H, const float* uv, const int64_t* qids, int64_t m,
+                                   double sigma, int gmode, uint64_t seed, double* out, int32_t* idx, int nthreads)
+{
+    if (W <= 0 || H <= 0) return -1;
+    orc_src2d src = {tex, W, H, 6, ORC_FMT_MATERIAL};
     return orc_gauss_src2d(&src, uv, qids, m, sigma, gmode, seed, out, idx, nthreads);
 }
 

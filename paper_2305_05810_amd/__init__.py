@@ -197,7 +197,7 @@ def stf_create_material2d(width: int, height: int, level_texels: Sequence[np.nda
     arr = (C.c_void_p * len(lv))(*[a.ctypes.data for a in lv])
     h = C.c_void_p()
     _check(lib().stf_create_material2d(width, height, len(lv), arr, C.byref(h)))
-    return Texture(h.value, "material", 3, 2)
+    return Texture(h.value, "material", 6, 2)   # filtered: albedo RGB, roughness, normal x, y
 
 
 def stf_create_sparse_grid3d(dims, fmt: int, leaf_origins: np.ndarray, leaf_values: np.ndarray,

@@ -62,6 +62,27 @@ struct DenseSrc {
     __device__ void load(int x, int y, float (&v)[CAP]) const { load_rgba<FMT, C>(L, x, y, v); }
 };
 
+// Material texels (8 bytes: albedo RGB UNORM8, roughness UNORM8, tangent
+// normal x and y binary16) of level 0, decoded exactly to six channels.
+struct MaterialSrc {
+    static constexpr int CAP = 6;
+    static constexpr bool DECODES = false;
+    TexLevel L;
+    __device__ int w() const { return L.w; }
+    __device__ int h() const { return L.h; }
+    __device__ int channels() const { return 6; }
+    __device__ void load(int x, int y, float (&v)[CAP]) const
+    {
+        const uint2 t = reinterpret_cast<const uint2*>(L.texels)[(int64_t)y * L.w + x];
+        v[0] = dec_u8(t.x & 0xffu);
+        v[1] = dec_u8((t.x >> 8) & 0xffu);
+        v[2] = dec_u8((t.x >> 16) & 0xffu);
+        v[3] = dec_u8(t.x >> 24);
+        v[4] = dec_f16((uint16_t)(t.y & 0xffffu));
+        v[5] = dec_f16((uint16_t)(t.y >> 16));
+    }
+};
+
 // DCT blocks: CAP words per block (a multiple of 4), C <= CAP channels used.
 template <int CAP_>
 struct DctSrc {
@@ -814,6 +835,7 @@ hipError_t with_dense(const stf_texture* t, F&& f)
 template <class F>
 hipError_t with_src(const stf_texture* t, F&& f)
 {
+    if (t->kind == STF_KIND_MATERIAL) return f(MaterialSrc{t->level[0]});
     if (t->kind == STF_KIND_DCT2D) {
         const TexLevel& L = t->level[0];
         const uint32_t* b = static_cast<const uint32_t*>(L.texels);
@@ -892,7 +914,7 @@ int32_t serve2d_queries_per_block()
 hipError_t launch_serve2d(const stf_texture* t, int filter, const ServeChunk* chunks, int32_t nchunks, int32_t nblocks,
                           hipStream_t s)
 {
-    if (t->kind != STF_KIND_TEX2D) return hipErrorInvalidValue;
+    if (t->kind != STF_KIND_TEX2D && t->kind != STF_KIND_MATERIAL) return hipErrorInvalidValue;
     return with_src(t, [&](auto S) {
         using Src = decltype(S);
         if (filter == STF_CUBIC_BSPLINE)

@@ -375,8 +375,8 @@ stf_status submit_locked(stf_server* s, const stf_texture* tex, const float* que
 stf_status validate_request(stf_server* s, const stf_texture* tex, const float* queries, int64_t n,
                             stf_filter_kind filter, float* out, uint32_t flags)
 {
-    if (!tex || (tex->kind != STF_KIND_GRID3D && tex->kind != STF_KIND_TEX2D))
-        return stf_fail(STF_E_INVALID, "requests need a 3D grid or a 2D texture");
+    if (!tex || (tex->kind != STF_KIND_GRID3D && tex->kind != STF_KIND_TEX2D && tex->kind != STF_KIND_MATERIAL))
+        return stf_fail(STF_E_INVALID, "requests need a 3D grid, a 2D texture or a material");
     if (n < 1 || n > 0x7fffffff) return stf_fail(STF_E_INVALID, "n = %lld out of range (1..2^31-1)", (long long)n);
     if (!valid_filter(filter)) return stf_fail(STF_E_INVALID, "unknown filter");
     if (filter != STF_LINEAR && filter != STF_CUBIC_BSPLINE)

@@ -220,7 +220,7 @@ stf_status stf_create_material2d(int32_t width, int32_t height, int32_t levels, 
     if (!t) return stf_fail(STF_E_OOM, "host allocation failed");
     t->kind = STF_KIND_MATERIAL;
     t->fmt = -1;
-    t->channels = 8;
+    t->channels = 6;   // filtered as albedo RGB, roughness, normal x, y
     (void)hipGetDevice(&t->device);
     stf_status s = create_levels(t, width, height, levels, level_texels_host, 8);
     if (s != STF_OK) {

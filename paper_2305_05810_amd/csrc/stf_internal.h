@@ -67,7 +67,7 @@ stf_status stf_fail(stf_status code, const char* fmt, ...);
 // Textures that stf_filter reads with 2D (uv) queries.
 inline bool is_2d_filterable(const stf_texture* t)
 {
-    return t->kind == STF_KIND_TEX2D || t->kind == STF_KIND_DCT2D;
+    return t->kind == STF_KIND_TEX2D || t->kind == STF_KIND_DCT2D || t->kind == STF_KIND_MATERIAL;
 }
 
 // Modes of stf_filter for a filter (filter importance sampling covers the

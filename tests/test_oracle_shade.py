@@ -159,3 +159,42 @@ def test_stochastic_shading_is_unbiased(filt):
     live = var > 1e-20
     z = (acc / K - mean)[live] / np.sqrt(var[live] / K)
     assert np.all(np.abs(z) < 5.0), np.abs(z).max()
+
+
+def _decode_material_np(lv0):
+    """The six channels of every texel, decoded in numpy from the field
+    layout (independent of the C decoder): v / 255 and binary16 widened."""
+    H, W = lv0.shape
+    d = np.empty((H, W, 6), np.float64)
+    d[..., 0:3] = lv0["albedo"] / 255.0
+    d[..., 3] = lv0["rough"] / 255.0
+    d[..., 4] = lv0["nx"].astype(np.float64)
+    d[..., 5] = lv0["ny"].astype(np.float64)
+    return d
+
+
+@pytest.mark.parametrize("filt", [oracle.LINEAR, oracle.CUBIC])
+def test_material_source_stochastic_reads_the_decoded_texel(filt):
+    """A sampled tap returns exactly the six decoded channels of its texel
+    (channel order, texel stride and both decodings pinned)."""
+    lv0 = np.ascontiguousarray(synth.material_levels(48, seed=61, levels=1)[0])
+    raw = lv0.view(np.uint8).reshape(48, 48, 8)
+    uv = synth.uv_queries(3000, seed=62) * np.float32(1.2) - np.float32(0.1)
+    dec = _decode_material_np(lv0)
+    for mode in (oracle.STOCH, oracle.STOCH_FIS):
+        v, idx = oracle.material_filter2d(raw, uv.astype(np.float32), filt, mode, seed=5)
+        assert np.array_equal(v, dec[idx[:, 1], idx[:, 0]])
+
+
+@pytest.mark.parametrize("filt", [oracle.LINEAR, oracle.CUBIC, oracle.KEYS, oracle.MITCHELL])
+def test_material_source_deterministic_matches_decoded_texture(filt):
+    """Deterministic filtering of the material equals filtering its decoded
+    channels stored as binary32 (within the rounding of the decode)."""
+    lv0 = np.ascontiguousarray(synth.material_levels(40, seed=63, levels=1)[0])
+    raw = lv0.view(np.uint8).reshape(40, 40, 8)
+    uv = (synth.uv_queries(2000, seed=64) * np.float32(1.2) - np.float32(0.1)).astype(np.float32)
+    dec32 = _decode_material_np(lv0).astype(np.float32)
+    got, _ = oracle.material_filter2d(raw, uv, filt, oracle.DET)
+    ref, _ = oracle.filter2d(dec32, oracle.F32, uv, filt, oracle.DET)
+    scale, _ = oracle.filter2d(np.abs(dec32), oracle.F32, uv, filt, oracle.DET_ABS)
+    assert np.all(np.abs(got - ref) <= 2 ** -23 * scale + 1e-300)
