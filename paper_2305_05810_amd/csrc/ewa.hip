@@ -107,13 +107,18 @@ __device__ __forceinline__ Ellipse ellipse(const TexLevel& L, float s, float t, 
     return e;
 }
 
+// The weight of tap (is, it), without a branch: the LUT index is clamped to
+// 0..127 (r2 is never negative beyond rounding, NaN converts to 0) and read
+// for every tap, then taps outside the ellipse select 0.  Every LUT entry is
+// >= +0, so adding a weight of +0 leaves a running sum's bits unchanged.
 __device__ __forceinline__ float ewa_weight(const Ellipse& e, const float* lut, int is, int it)
 {
     const float ss = (float)is - e.stx, tt = (float)it - e.sty;
     const float r2 = (e.A * (ss * ss) + (e.B * ss) * tt) + e.C * (tt * tt);
-    if (!(r2 < 1.0f)) return 0.0f;
     int idx = (int)(r2 * 128.0f);
-    return lut[idx > 127 ? 127 : idx];
+    idx = idx > 127 ? 127 : (idx < 0 ? 0 : idx);
+    const float w = lut[idx];
+    return r2 < 1.0f ? w : 0.0f;
 }
 
 template <int FMT, int C>
@@ -149,10 +154,7 @@ __device__ __forceinline__ void ewa_draw(const Ellipse& e, const float* lut, uin
     bool found = false;
     for (int it = e.t0; it <= e.t1; ++it) {
         float R = 0.0f;
-        for (int is = e.s0; is <= e.s1; ++is) {
-            const float w = ewa_weight(e, lut, is, it);
-            if (w > 0.0f) R += w;
-        }
+        for (int is = e.s0; is <= e.s1; ++is) R += ewa_weight(e, lut, is, it);   // +0 outside: same bits
         if (!(R > 0.0f)) continue;
         S += R;
         if (uniform_from_base(base, 16u + (uint32_t)(it - e.t0)) * S < R) {
@@ -175,105 +177,234 @@ __device__ __forceinline__ void ewa_draw(const Ellipse& e, const float* lut, uin
     }
 }
 
-template <int FMT, int C, bool STOCH>
-__global__ __launch_bounds__(BLOCK) void k_ewa(EwaLevels P, EwaLut lut_in, const float* __restrict__ q, int32_t n,
-                                               float max_aniso, uint32_t key, float* __restrict__ out,
-                                               int32_t* __restrict__ idx)
+// Loads query i and forms its axes (binary32): the longer derivative is d0,
+// the shorter d1 is raised to |d0| / max_aniso when it is shorter than that
+// (and not zero); sh = |d1|.  False for a record with a non-finite entry or
+// one of magnitude >= 65536.
+__device__ __forceinline__ bool ewa_axes(const float* __restrict__ q, int32_t i, float max_aniso, float (&r)[6],
+                                         float (&d0)[2], float (&d1)[2], float& sh)
+{
+#pragma unroll
+    for (int j = 0; j < 6; ++j) r[j] = q[6 * (int64_t)i + j];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) ok = ok && (__builtin_fabsf(r[j]) < 65536.0f);
+    if (!ok) return false;
+    d0[0] = r[2]; d0[1] = r[3];
+    d1[0] = r[4]; d1[1] = r[5];
+    if (d0[0] * d0[0] + d0[1] * d0[1] < d1[0] * d1[0] + d1[1] * d1[1]) {
+        const float a = d0[0], b = d0[1];
+        d0[0] = d1[0]; d0[1] = d1[1];
+        d1[0] = a; d1[1] = b;
+    }
+    const float longer = sqrtf(d0[0] * d0[0] + d0[1] * d0[1]);
+    sh = sqrtf(d1[0] * d1[0] + d1[1] * d1[1]);
+    if (sh * max_aniso < longer && sh > 0.0f) {
+        const float scale = longer / (sh * max_aniso);
+        d1[0] *= scale;
+        d1[1] *= scale;
+        sh *= scale;
+    }
+    return true;
+}
+
+__device__ __forceinline__ double ewa_lod(int levels, float sh)
+{
+    const double lod = (double)(levels - 1) + log2((double)sh);
+    return lod < 0.0 ? 0.0 : lod;
+}
+
+// Deterministic EWA: lerp of the EWA means of levels floor(lod) and
+// floor(lod) + 1 (a level at or past the last reads its single texel); a
+// zero footprint reads bilinearly from level 0.
+template <int FMT, int C>
+__global__ __launch_bounds__(BLOCK) void k_ewa_det(EwaLevels P, EwaLut lut_in, const float* __restrict__ q,
+                                                   int32_t n, float max_aniso, float* __restrict__ out)
 {
     __shared__ float lut[LUT_SIZE];
     for (int k = threadIdx.x; k < LUT_SIZE; k += BLOCK) lut[k] = lut_in.v[k];
     __syncthreads();
     const int32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
-    float r[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) r[j] = q[6 * (int64_t)i + j];
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) ok = ok && (__builtin_fabsf(r[j]) < 65536.0f);
+    float r[6], d0[2], d1[2], sh = 0.0f;
     float v[C];
-    int ix[3] = {BAD_INDEX, BAD_INDEX, BAD_INDEX};
-    if (!ok) {
+    if (!ewa_axes(q, i, max_aniso, r, d0, d1, sh)) {
 #pragma unroll
         for (int c = 0; c < C; ++c) v[c] = __builtin_nanf("");
+    } else if (!(sh > 0.0f)) {
+        const TexLevel& T0 = P.level[0];
+        const float x = r[0] * (float)T0.w - 0.5f, y = r[1] * (float)T0.h - 0.5f;
+        int cx = 0, cy = 0;
+        float tx = 0.0f, ty = 0.0f;
+        cell_of(x, cx, tx);
+        cell_of(y, cy, ty);
+        float a[C], b[C], c2[C], d[C];
+        texel<FMT, C>(T0, cx, cy, a);
+        texel<FMT, C>(T0, cx + 1, cy, b);
+        texel<FMT, C>(T0, cx, cy + 1, c2);
+        texel<FMT, C>(T0, cx + 1, cy + 1, d);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float r0 = __builtin_fmaf(tx, b[c], (1.0f - tx) * a[c]);
+            const float r1 = __builtin_fmaf(tx, d[c], (1.0f - tx) * c2[c]);
+            v[c] = __builtin_fmaf(ty, r1, (1.0f - ty) * r0);
+        }
     } else {
-        float d0[2] = {r[2], r[3]}, d1[2] = {r[4], r[5]};
-        if (d0[0] * d0[0] + d0[1] * d0[1] < d1[0] * d1[0] + d1[1] * d1[1]) {
-            const float a = d0[0], b = d0[1];
-            d0[0] = d1[0]; d0[1] = d1[1];
-            d1[0] = a; d1[1] = b;
-        }
-        const float longer = sqrtf(d0[0] * d0[0] + d0[1] * d0[1]);
-        float sh = sqrtf(d1[0] * d1[0] + d1[1] * d1[1]);
-        if (sh * max_aniso < longer && sh > 0.0f) {
-            const float scale = longer / (sh * max_aniso);
-            d1[0] *= scale;
-            d1[1] *= scale;
-            sh *= scale;
-        }
-        const uint32_t b = pcg(key ^ (uint32_t)i);
         const int L = P.levels;
-        if (!(sh > 0.0f)) {   // degenerate footprint: bilinear on level 0
-            const TexLevel& T0 = P.level[0];
-            const float x = r[0] * (float)T0.w - 0.5f, y = r[1] * (float)T0.h - 0.5f;
-            int cx = 0, cy = 0;
-            float tx = 0.0f, ty = 0.0f;
-            cell_of(x, cx, tx);
-            cell_of(y, cy, ty);
-            if constexpr (STOCH) {
+        const double lod = ewa_lod(L, sh);
+        const int il = (int)floor(lod);
+        const double frac = lod - (double)il;
+        const int l0 = il < L ? il : L - 1, l1 = il + 1 < L ? il + 1 : L - 1;
+        float a[C], c1[C];
+        if (l0 < L - 1)
+            ewa_mean<FMT, C>(P.level[l0], ellipse(P.level[l0], r[0], r[1], d0, d1), lut, a);
+        else
+            texel<FMT, C>(P.level[l0], 0, 0, a);
+        if (l1 < L - 1)
+            ewa_mean<FMT, C>(P.level[l1], ellipse(P.level[l1], r[0], r[1], d0, d1), lut, c1);
+        else
+            texel<FMT, C>(P.level[l1], 0, 0, c1);
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = (float)((1.0 - frac) * (double)a[c] + frac * (double)c1[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) __builtin_nontemporal_store(v[c], out + (int64_t)i * C + c);   // streamed out
+}
+
+// Stochastic EWA in two phases.  Phase 1 (a thread per query): the level
+// draw (hash index 0) and the ellipse of the drawn level; queries with no
+// ellipse to scan (non-finite, zero footprint, last level) finish here.
+// Neighbouring pixels draw different levels, whose boxes differ about 4x in
+// size, so a wave scanning its own queries' boxes idles about half its lanes.
+// Phase 2 regroups the block's scans by box height (a counting sort over LDS
+// slots; the slot a query lands in does not change its result) so that each
+// wave scans boxes of similar size, then draws the tap (ewa_draw) and reads it.
+constexpr int EWA_HEIGHT_KEYS = 64;   // box heights 0..62, 63 and more share the last key
+
+struct EwaScanSlots {
+    float stx[BLOCK], sty[BLOCK], A[BLOCK], B[BLOCK], C[BLOCK], u1[BLOCK];
+    int s0[BLOCK], s1[BLOCK], t0[BLOCK], t1[BLOCK], level[BLOCK], query[BLOCK];
+    uint32_t b[BLOCK];
+};
+
+template <int C>
+__device__ __forceinline__ void ewa_store(float* __restrict__ out, int32_t* __restrict__ idx, int32_t i,
+                                          const float (&v)[C], const int (&ix)[3])
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c) __builtin_nontemporal_store(v[c], out + (int64_t)i * C + c);   // streamed out
+    if (idx) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) idx[3 * (int64_t)i + k] = ix[k];
+    }
+}
+
+template <int FMT, int C>
+__global__ __launch_bounds__(BLOCK) void k_ewa_stoch(EwaLevels P, EwaLut lut_in, const float* __restrict__ q,
+                                                     int32_t n, float max_aniso, uint32_t key, float* __restrict__ out,
+                                                     int32_t* __restrict__ idx)
+{
+    __shared__ float lut[LUT_SIZE];
+    __shared__ int bucket[EWA_HEIGHT_KEYS];
+    __shared__ EwaScanSlots S;
+    for (int k = threadIdx.x; k < LUT_SIZE; k += BLOCK) lut[k] = lut_in.v[k];
+    if (threadIdx.x < EWA_HEIGHT_KEYS) bucket[threadIdx.x] = 0;
+    __syncthreads();
+
+    // phase 1
+    const int32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    bool scan = false;
+    Ellipse e{};
+    int l = 0;
+    uint32_t b = 0;
+    if (i < n) {
+        float r[6], d0[2], d1[2], sh = 0.0f;
+        float v[C];
+        int ix[3] = {BAD_INDEX, BAD_INDEX, BAD_INDEX};
+        if (!ewa_axes(q, i, max_aniso, r, d0, d1, sh)) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] = __builtin_nanf("");
+        } else {
+            b = pcg(key ^ (uint32_t)i);
+            const int L = P.levels;
+            if (!(sh > 0.0f)) {   // degenerate footprint: the bilinear draw on level 0
+                const TexLevel& T0 = P.level[0];
+                const float x = r[0] * (float)T0.w - 0.5f, y = r[1] * (float)T0.h - 0.5f;
+                int cx = 0, cy = 0;
+                float tx = 0.0f, ty = 0.0f;
+                cell_of(x, cx, tx);
+                cell_of(y, cy, ty);
                 ix[0] = clampi(cx + choose_linear(tx, axis_uniform(b, 2)), T0.w - 1);
                 ix[1] = clampi(cy + choose_linear(ty, axis_uniform(b, 3)), T0.h - 1);
                 ix[2] = 0;
                 texel<FMT, C>(T0, ix[0], ix[1], v);
             } else {
-                float a[C], b[C], c2[C], d[C];
-                texel<FMT, C>(T0, cx, cy, a);
-                texel<FMT, C>(T0, cx + 1, cy, b);
-                texel<FMT, C>(T0, cx, cy + 1, c2);
-                texel<FMT, C>(T0, cx + 1, cy + 1, d);
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const float r0 = __builtin_fmaf(tx, b[c], (1.0f - tx) * a[c]);
-                    const float r1 = __builtin_fmaf(tx, d[c], (1.0f - tx) * c2[c]);
-                    v[c] = __builtin_fmaf(ty, r1, (1.0f - ty) * r0);
+                const double lod = ewa_lod(L, sh);
+                const int il = (int)floor(lod);
+                const double frac = lod - (double)il;
+                l = il + ((double)axis_uniform(b, 0) < frac ? 1 : 0);
+                l = l > L - 1 ? L - 1 : l;
+                if (l < L - 1) {
+                    e = ellipse(P.level[l], r[0], r[1], d0, d1);
+                    scan = true;
+                } else {   // the last level: its single texel
+                    ix[0] = 0;
+                    ix[1] = 0;
+                    ix[2] = l;
+                    texel<FMT, C>(P.level[l], 0, 0, v);
                 }
             }
-        } else {
-            double lod = (double)(L - 1) + log2((double)sh);
-            lod = lod < 0.0 ? 0.0 : lod;
-            const int il = (int)floor(lod);
-            const double frac = lod - (double)il;
-            if constexpr (STOCH) {
-                int l = il + ((double)axis_uniform(b, 0) < frac ? 1 : 0);
-                l = l > L - 1 ? L - 1 : l;
-                int tx = 0, ty = 0;
-                if (l < L - 1) ewa_draw(ellipse(P.level[l], r[0], r[1], d0, d1), lut, b, axis_uniform(b, 1), tx, ty);
-                ix[0] = clampi(tx, P.level[l].w - 1);
-                ix[1] = clampi(ty, P.level[l].h - 1);
-                ix[2] = l;
-                texel<FMT, C>(P.level[l], ix[0], ix[1], v);
-            } else {
-                const int l0 = il < L ? il : L - 1, l1 = il + 1 < L ? il + 1 : L - 1;
-                float a[C], c1[C];
-                if (l0 < L - 1)
-                    ewa_mean<FMT, C>(P.level[l0], ellipse(P.level[l0], r[0], r[1], d0, d1), lut, a);
-                else
-                    texel<FMT, C>(P.level[l0], 0, 0, a);
-                if (l1 < L - 1)
-                    ewa_mean<FMT, C>(P.level[l1], ellipse(P.level[l1], r[0], r[1], d0, d1), lut, c1);
-                else
-                    texel<FMT, C>(P.level[l1], 0, 0, c1);
-#pragma unroll
-                for (int c = 0; c < C; ++c) v[c] = (float)((1.0 - frac) * (double)a[c] + frac * (double)c1[c]);
-            }
         }
+        if (!scan) ewa_store<C>(out, idx, i, v, ix);
     }
-#pragma unroll
-    for (int c = 0; c < C; ++c) __builtin_nontemporal_store(v[c], out + (int64_t)i * C + c);   // streamed out
-    if (STOCH && idx) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) idx[3 * (int64_t)i + k] = ix[k];
+
+    // phase 2: counting sort of the block's queries by box height
+    int k = 0;
+    if (scan) {
+        const int rows = e.t1 - e.t0 + 1;
+        k = rows < 0 ? 0 : (rows > EWA_HEIGHT_KEYS - 1 ? EWA_HEIGHT_KEYS - 1 : rows);
     }
+    const int rank = atomicAdd(&bucket[k], 1);
+    __syncthreads();
+    if (threadIdx.x < EWA_HEIGHT_KEYS) {   // wave 0: exclusive prefix of the bucket sizes
+        const int c = bucket[threadIdx.x];
+        int x = c;
+#pragma unroll
+        for (int d = 1; d < EWA_HEIGHT_KEYS; d <<= 1) {
+            const int y = __shfl_up(x, d, EWA_HEIGHT_KEYS);
+            if ((int)threadIdx.x >= d) x += y;
+        }
+        bucket[threadIdx.x] = x - c;
+    }
+    __syncthreads();
+    const int slot = bucket[k] + rank;   // a permutation of 0..BLOCK-1
+    S.query[slot] = scan ? i : -1;
+    if (scan) {
+        S.stx[slot] = e.stx; S.sty[slot] = e.sty;
+        S.A[slot] = e.A; S.B[slot] = e.B; S.C[slot] = e.C;
+        S.s0[slot] = e.s0; S.s1[slot] = e.s1; S.t0[slot] = e.t0; S.t1[slot] = e.t1;
+        S.level[slot] = l;
+        S.b[slot] = b;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int32_t j = S.query[t];
+    if (j < 0) return;
+    Ellipse f;
+    f.stx = S.stx[t]; f.sty = S.sty[t];
+    f.A = S.A[t]; f.B = S.B[t]; f.C = S.C[t];
+    f.s0 = S.s0[t]; f.s1 = S.s1[t]; f.t0 = S.t0[t]; f.t1 = S.t1[t];
+    const int lj = S.level[t];
+    const uint32_t bj = S.b[t];
+    int tx = 0, ty = 0;
+    ewa_draw(f, lut, bj, axis_uniform(bj, 1), tx, ty);
+    int ix[3];
+    ix[0] = clampi(tx, P.level[lj].w - 1);
+    ix[1] = clampi(ty, P.level[lj].h - 1);
+    ix[2] = lj;
+    float v[C];
+    texel<FMT, C>(P.level[lj], ix[0], ix[1], v);
+    ewa_store<C>(out, idx, j, v, ix);
 }
 
 template <int FMT, int C>
@@ -283,9 +414,9 @@ hipError_t launch_ewa_fc(const EwaLevels& P, const float* q, int32_t n, float ma
     static const EwaLut lut = make_lut();
     dim3 grid((n + BLOCK - 1) / BLOCK), block(BLOCK);
     if (mode == STF_STOCHASTIC)
-        hipLaunchKernelGGL((k_ewa<FMT, C, true>), grid, block, 0, s, P, lut, q, n, max_aniso, key, out, idx);
+        hipLaunchKernelGGL((k_ewa_stoch<FMT, C>), grid, block, 0, s, P, lut, q, n, max_aniso, key, out, idx);
     else
-        hipLaunchKernelGGL((k_ewa<FMT, C, false>), grid, block, 0, s, P, lut, q, n, max_aniso, key, out, idx);
+        hipLaunchKernelGGL((k_ewa_det<FMT, C>), grid, block, 0, s, P, lut, q, n, max_aniso, out);
     return hipGetLastError();
 }
 
