@@ -71,6 +71,19 @@ def time_launches(fn, steps, warmup, torch):
     return wall, kern_ms
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or None
+
+
 def base_line(args, value, unit, ms_per_step, dtype, config, higher=True):
     return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": higher, "scaling": "weak",
@@ -233,7 +246,7 @@ def run_grid(args, torch, stf, synth):
                 dt = time.perf_counter() - t1
                 if dt >= args.cpu_seconds:
                     break
-            cpu = dict(value=passes * m / dt, unit="lookups/s", cores=threads, kind="oracle",
+            cpu = dict(value=passes * m / dt, unit="lookups/s", cores=threads, kind="oracle", cpu_model=cpu_model(),
                        sample=f"{passes} pass(es) over {'all' if m == n else 'the first ' + str(m) + ' of the'} "
                               f"{n} queries of the batch, stochastic tricubic, FP64 C oracle with OpenMP, "
                               f"{dt:.2f} s in all")

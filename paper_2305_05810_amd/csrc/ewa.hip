@@ -107,18 +107,23 @@ __device__ __forceinline__ Ellipse ellipse(const TexLevel& L, float s, float t, 
     return e;
 }
 
-// The weight of tap (is, it), without a branch: the LUT index is clamped to
-// 0..127 (r2 is never negative beyond rounding, NaN converts to 0) and read
-// for every tap, then taps outside the ellipse select 0.  Every LUT entry is
-// >= +0, so adding a weight of +0 leaves a running sum's bits unchanged.
-__device__ __forceinline__ float ewa_weight(const Ellipse& e, const float* lut, int is, int it)
+// The weight of a tap whose quadratic form is r2, without a branch: the LUT
+// index is clamped to 0..127 (r2 is never negative beyond rounding, NaN
+// converts to 0) and read for every tap, then taps outside the ellipse
+// select 0.  Every LUT entry is >= +0, so adding a weight of +0 leaves a
+// running sum's bits unchanged.
+__device__ __forceinline__ float lut_weight(const float* lut, float r2)
 {
-    const float ss = (float)is - e.stx, tt = (float)it - e.sty;
-    const float r2 = (e.A * (ss * ss) + (e.B * ss) * tt) + e.C * (tt * tt);
     int idx = (int)(r2 * 128.0f);
     idx = idx > 127 ? 127 : (idx < 0 ? 0 : idx);
     const float w = lut[idx];
     return r2 < 1.0f ? w : 0.0f;
+}
+
+__device__ __forceinline__ float ewa_weight(const Ellipse& e, const float* lut, int is, int it)
+{
+    const float ss = (float)is - e.stx, tt = (float)it - e.sty;
+    return lut_weight(lut, (e.A * (ss * ss) + (e.B * ss) * tt) + e.C * (tt * tt));
 }
 
 template <int FMT, int C>
@@ -145,23 +150,36 @@ __device__ __forceinline__ void ewa_mean(const TexLevel& L, const Ellipse& e, co
 // the row sums R_k (binary32, scan order; row k replaces the choice iff
 // u_(16+k) * S < R_k, S the running sum of row sums), then a tap of that row
 // by the cumulative rule (T = u1 R, the first tap whose running sum exceeds
-// T).  One pass over the box and one over a single row.
+// T).  The box is scanned two rows at a time: a column's A ss^2 and B ss
+// serve both rows (each tap's r2 keeps its order of operations, so every
+// weight and every row sum has the bits of a row-by-row scan).
 __device__ __forceinline__ void ewa_draw(const Ellipse& e, const float* lut, uint32_t b, float u1, int& tx, int& ty)
 {
     const uint32_t base = pcg_base(b);
     float S = 0.0f, Rsel = 0.0f;
     int rsel = e.t0;
     bool found = false;
-    for (int it = e.t0; it <= e.t1; ++it) {
-        float R = 0.0f;
-        for (int is = e.s0; is <= e.s1; ++is) R += ewa_weight(e, lut, is, it);   // +0 outside: same bits
-        if (!(R > 0.0f)) continue;
+    auto offer = [&](int it, float R) {   // row `it` with sum R enters the reservoir
+        if (!(R > 0.0f)) return;
         S += R;
         if (uniform_from_base(base, 16u + (uint32_t)(it - e.t0)) * S < R) {
             rsel = it;
             Rsel = R;
             found = true;
         }
+    };
+    for (int it = e.t0; it <= e.t1; it += 2) {
+        const float ta = (float)it - e.sty, tb = (float)(it + 1) - e.sty;
+        const float ca = e.C * (ta * ta), cb = e.C * (tb * tb);
+        float Ra = 0.0f, Rb = 0.0f;
+        for (int is = e.s0; is <= e.s1; ++is) {
+            const float ss = (float)is - e.stx;
+            const float P = e.A * (ss * ss), Q = e.B * ss;
+            Ra += lut_weight(lut, (P + Q * ta) + ca);   // +0 outside: same bits
+            Rb += lut_weight(lut, (P + Q * tb) + cb);
+        }
+        offer(it, Ra);
+        if (it + 1 <= e.t1) offer(it + 1, Rb);
     }
     tx = e.s0;
     ty = rsel;
@@ -212,6 +230,29 @@ __device__ __forceinline__ double ewa_lod(int levels, float sh)
 {
     const double lod = (double)(levels - 1) + log2((double)sh);
     return lod < 0.0 ? 0.0 : lod;
+}
+
+// The stochastic level: floor(lod) + [u0 < lod - floor(lod)] with lod of
+// binary64 (ewa_lod), capped at the last level.  The hardware binary32 log2
+// (error below 1e-5 in lod here) settles both decisions -- the floor and the
+// comparison with u0 -- whenever lod, its fraction and u0 - fraction are more
+// than 1e-4 away from a decision boundary; the rest (about 5e-4 of the
+// queries) takes the binary64 path, so the level is the binary64 rule's.
+__device__ __forceinline__ int ewa_draw_level(int levels, float sh, float u0)
+{
+    const float lod32 = (float)(levels - 1) + __builtin_amdgcn_logf(sh);
+    const float fl = floorf(lod32), fr = lod32 - fl;
+    int l;
+    if (lod32 < -1e-4f) {
+        l = 0;
+    } else if (lod32 > 1e-4f && fr > 1e-4f && fr < 1.0f - 1e-4f && __builtin_fabsf(u0 - fr) > 1e-4f) {
+        l = (int)fl + (u0 < fr ? 1 : 0);
+    } else {
+        const double lod = ewa_lod(levels, sh);
+        const int il = (int)floor(lod);
+        l = il + ((double)u0 < lod - (double)il ? 1 : 0);
+    }
+    return l > levels - 1 ? levels - 1 : l;
 }
 
 // Deterministic EWA: lerp of the EWA means of levels floor(lod) and
@@ -339,11 +380,7 @@ __global__ __launch_bounds__(BLOCK) void k_ewa_stoch(EwaLevels P, EwaLut lut_in,
                 ix[2] = 0;
                 texel<FMT, C>(T0, ix[0], ix[1], v);
             } else {
-                const double lod = ewa_lod(L, sh);
-                const int il = (int)floor(lod);
-                const double frac = lod - (double)il;
-                l = il + ((double)axis_uniform(b, 0) < frac ? 1 : 0);
-                l = l > L - 1 ? L - 1 : l;
+                l = ewa_draw_level(L, sh, axis_uniform(b, 0));
                 if (l < L - 1) {
                     e = ellipse(P.level[l], r[0], r[1], d0, d1);
                     scan = true;
