@@ -487,7 +487,7 @@ struct Decode {
 };
 
 template <bool CUBIC, bool STOCH>
-__device__ __forceinline__ Decode locate(const InferArgs& a, int64_t qi, int tap, float2 uv)
+__device__ __forceinline__ Decode locate(const InferArgs& a, uint32_t qi, int tap, float2 uv)
 {
     Decode d;
     float x = uv.x * (float)a.W - 0.5f, y = uv.y * (float)a.H - 0.5f;
@@ -496,7 +496,7 @@ __device__ __forceinline__ Decode locate(const InferArgs& a, int64_t qi, int tap
     d.fin = cell_of(x, cx, tx) & cell_of(y, cy, ty);
     d.w = 1.0f;
     if constexpr (STOCH) {
-        const uint32_t base = pcg_base(pcg(a.key ^ (uint32_t)qi));
+        const uint32_t base = pcg_base(pcg(a.key ^ qi));
         const float mx = hash_m(pcg_from_base(base, 0u)), my = hash_m(pcg_from_base(base, 1u));
         if constexpr (CUBIC) {
             d.sx = cx + choose_cubic_m(tx, mx);
@@ -612,14 +612,15 @@ __device__ __forceinline__ float tap_sum(float v)
 // jd; weight them, sum the taps of each query and store.  A non-finite query
 // carries a NaN weight, so every channel it stores is NaN.
 template <int TAPS>
-__device__ __forceinline__ void emit(const InferArgs& a, const f32x16& D3, float w, int64_t qi, int tap, int h)
+__device__ __forceinline__ void emit(const InferArgs& a, const f32x16& D3, float w, uint32_t qi, int tap, int h)
 {
     float o[4] = {D3[0] * w, D3[1] * w, D3[2] * w, D3[3] * w};
 #pragma unroll
     for (int c = 0; c < 4; ++c) o[c] = tap_sum<TAPS>(o[c]);
     typedef float f32x4_nt __attribute__((ext_vector_type(4)));   // results are streamed out
-    if (qi < a.n && tap == 0)
-        __builtin_nontemporal_store((f32x4_nt){o[0], o[1], o[2], o[3]}, reinterpret_cast<f32x4_nt*>(a.out) + (qi * 2 + h));
+    if (qi < (uint32_t)a.n && tap == 0)
+        __builtin_nontemporal_store((f32x4_nt){o[0], o[1], o[2], o[3]},
+                                    reinterpret_cast<f32x4_nt*>(a.out) + (2 * (size_t)qi + h));
 }
 
 // Persistent waves; each handles pairs of 32-decode batches p = wave,
@@ -656,12 +657,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     // half: (1, 1, 1, 0, 0, 0, 0, 0) in bf16, as four 32-bit words.
     const uint32_t ONE_WORDS[4] = {0x3F803F80u, 0x00003F80u, 0u, 0u};
 
-    const int64_t npair = ((int64_t)a.n + QPP - 1) / QPP;
+    const int32_t npair = (int32_t)(((int64_t)a.n + QPP - 1) / QPP);
+    const uint32_t nq = (uint32_t)a.n;
     const int tap = lane % TAPS;
     const uint4* L = reinterpret_cast<const uint4*>(a.quad16);
-    auto load_uv = [&](int64_t p) {
-        int64_t qi = p * QPP + lane / TAPS;
-        return (p < npair && qi < a.n) ? reinterpret_cast<const float2*>(a.q)[qi] : make_float2(0.5f, 0.5f);
+    auto load_uv = [&](int32_t p) {
+        const uint32_t qi = (uint32_t)p * QPP + lane / TAPS;
+        return (p < npair && qi < nq) ? reinterpret_cast<const float2*>(a.q)[qi] : make_float2(0.5f, 0.5f);
     };
     // Every lane loads: the quad index is in the table for any query
     // (padding lanes carry uv = (0.5, 0.5)).
@@ -671,16 +673,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int k = 0; k < 4; ++k) v[k] = L[4 * (size_t)e + k];
     };
 
-    int64_t p = wave;
+    int32_t p = wave;
     float2 uv_next = load_uv(p + nwaves);
-    Decode cur = locate<CUBIC, STOCH>(a, p * QPP + lane / TAPS, tap, load_uv(p));
+    Decode cur = locate<CUBIC, STOCH>(a, (uint32_t)p * QPP + lane / TAPS, tap, load_uv(p));
     uint4 lat_cur[4];
     float wl_cur[4];
     load_lat(cur, lat_cur, wl_cur);
     for (; p < npair; p += nwaves) {
         // ---- stage the next two pairs
-        const float2 uv_after = load_uv(p + 2 * (int64_t)nwaves);
-        const Decode nxt = locate<CUBIC, STOCH>(a, (p + nwaves) * QPP + lane / TAPS, tap, uv_next);
+        const float2 uv_after = load_uv(p + 2 * nwaves);
+        const Decode nxt = locate<CUBIC, STOCH>(a, (uint32_t)(p + nwaves) * QPP + lane / TAPS, tap, uv_next);
         uint4 lat_nxt[4];
         float wl_nxt[4];
         load_lat(nxt, lat_nxt, wl_nxt);
@@ -718,7 +720,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const float wd = cur.fin ? cur.w : __builtin_nanf("");
         const uint32_t wb = __builtin_bit_cast(uint32_t, wd);
         const auto rw = __builtin_amdgcn_permlane32_swap(wb, wb, false, false);
-        const int64_t q0 = p * QPP + jd / TAPS;
+        const uint32_t q0 = (uint32_t)p * QPP + jd / TAPS;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const bf16x8 B1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(B1w[b]));
@@ -727,10 +729,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         }
         // selected texel of this lane's own decode (stochastic: one decode per query)
         if (STOCH && a.idx) {
-            const int64_t qi = p * QPP + lane;
-            if (qi < a.n) {
-                a.idx[2 * qi] = cur.fin ? cur.sx : BAD_INDEX;
-                a.idx[2 * qi + 1] = cur.fin ? cur.sy : BAD_INDEX;
+            const uint32_t qi = (uint32_t)p * QPP + lane;
+            if (qi < nq) {
+                a.idx[2 * (size_t)qi] = cur.fin ? cur.sx : BAD_INDEX;
+                a.idx[2 * (size_t)qi + 1] = cur.fin ? cur.sy : BAD_INDEX;
             }
         }
         cur = nxt;

@@ -154,9 +154,16 @@ def test_one_decode_per_lookup_is_unbiased(dev, trained, fname, gf, of):
         s1 += o
         s2 += o * o
     mean = (s1 / K).cpu().numpy()
-    var = np.maximum((s2 / K).cpu().numpy() - mean ** 2, 1e-12)
-    z = (mean - det.cpu().numpy()) / np.sqrt(var / K)
-    assert np.all(np.abs(z) < 5.0), np.abs(z).max()
+    rms = np.sqrt((s2 / K).cpu().numpy())
+    var = np.maximum((s2 / K).cpu().numpy() - mean ** 2, 0.0)
+    # 5 sigma of the mean of K draws, plus the binary32 rounding of the
+    # deterministic reference (at most 16 weighted taps: below 2e-6 of the
+    # taps' magnitude).  Taps whose bf16-rounded latents coincide decode to
+    # the same value, so their draws have no variance and only the rounding
+    # term remains.
+    bound = 5.0 * np.sqrt(var / K) + 2e-6 * rms
+    err = np.abs(mean - det.cpu().numpy())
+    assert np.all(err <= bound), (err / np.maximum(bound, 1e-30)).max()
 
 
 def test_neural_argument_errors(dev, small):
