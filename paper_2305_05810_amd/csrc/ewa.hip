@@ -319,13 +319,22 @@ __global__ __launch_bounds__(BLOCK) void k_ewa_det(EwaLevels P, EwaLut lut_in, c
 // size, so a wave scanning its own queries' boxes idles about half its lanes.
 // Phase 2 regroups the block's scans by box height (a counting sort over LDS
 // slots; the slot a query lands in does not change its result) so that each
-// wave scans boxes of similar size, then draws the tap (ewa_draw) and reads it.
+// wave scans boxes of similar size, then draws the tap (ewa_draw) and reads
+// it; the results go back through LDS to their queries' threads, which write
+// them in query order.
 constexpr int EWA_HEIGHT_KEYS = 64;   // box heights 0..62, 63 and more share the last key
 
 struct EwaScanSlots {
-    float stx[BLOCK], sty[BLOCK], A[BLOCK], B[BLOCK], C[BLOCK], u1[BLOCK];
+    float stx[BLOCK], sty[BLOCK], A[BLOCK], B[BLOCK], C[BLOCK];
     int s0[BLOCK], s1[BLOCK], t0[BLOCK], t1[BLOCK], level[BLOCK], query[BLOCK];
     uint32_t b[BLOCK];
+};
+
+// A scanned query's result, returned to the query's own thread.
+template <int C>
+struct EwaResults {
+    float v[BLOCK * C];
+    int ix[BLOCK], iy[BLOCK], il[BLOCK];
 };
 
 template <int C>
@@ -348,6 +357,7 @@ __global__ __launch_bounds__(BLOCK) void k_ewa_stoch(EwaLevels P, EwaLut lut_in,
     __shared__ float lut[LUT_SIZE];
     __shared__ int bucket[EWA_HEIGHT_KEYS];
     __shared__ EwaScanSlots S;
+    __shared__ EwaResults<C> R;
     for (int k = threadIdx.x; k < LUT_SIZE; k += BLOCK) lut[k] = lut_in.v[k];
     if (threadIdx.x < EWA_HEIGHT_KEYS) bucket[threadIdx.x] = 0;
     __syncthreads();
@@ -426,22 +436,36 @@ __global__ __launch_bounds__(BLOCK) void k_ewa_stoch(EwaLevels P, EwaLut lut_in,
     __syncthreads();
     const int t = threadIdx.x;
     const int32_t j = S.query[t];
-    if (j < 0) return;
-    Ellipse f;
-    f.stx = S.stx[t]; f.sty = S.sty[t];
-    f.A = S.A[t]; f.B = S.B[t]; f.C = S.C[t];
-    f.s0 = S.s0[t]; f.s1 = S.s1[t]; f.t0 = S.t0[t]; f.t1 = S.t1[t];
-    const int lj = S.level[t];
-    const uint32_t bj = S.b[t];
-    int tx = 0, ty = 0;
-    ewa_draw(f, lut, bj, axis_uniform(bj, 1), tx, ty);
-    int ix[3];
-    ix[0] = clampi(tx, P.level[lj].w - 1);
-    ix[1] = clampi(ty, P.level[lj].h - 1);
-    ix[2] = lj;
-    float v[C];
-    texel<FMT, C>(P.level[lj], ix[0], ix[1], v);
-    ewa_store<C>(out, idx, j, v, ix);
+    if (j >= 0) {
+        Ellipse f;
+        f.stx = S.stx[t]; f.sty = S.sty[t];
+        f.A = S.A[t]; f.B = S.B[t]; f.C = S.C[t];
+        f.s0 = S.s0[t]; f.s1 = S.s1[t]; f.t0 = S.t0[t]; f.t1 = S.t1[t];
+        const int lj = S.level[t];
+        const uint32_t bj = S.b[t];
+        int tx = 0, ty = 0;
+        ewa_draw(f, lut, bj, axis_uniform(bj, 1), tx, ty);
+        const int tx_c = clampi(tx, P.level[lj].w - 1), ty_c = clampi(ty, P.level[lj].h - 1);
+        float v[C];
+        texel<FMT, C>(P.level[lj], tx_c, ty_c, v);
+        // back to the query's own thread, so that the block's results are
+        // written in query order (one contiguous span, full lines)
+        const int o = j - (int32_t)blockIdx.x * BLOCK;
+#pragma unroll
+        for (int c = 0; c < C; ++c) R.v[o * C + c] = v[c];
+        R.ix[o] = tx_c;
+        R.iy[o] = ty_c;
+        R.il[o] = lj;
+    }
+    __syncthreads();
+    if (scan) {
+        const int o = threadIdx.x;
+        float v[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = R.v[o * C + c];
+        const int ix[3] = {R.ix[o], R.iy[o], R.il[o]};
+        ewa_store<C>(out, idx, i, v, ix);
+    }
 }
 
 template <int FMT, int C>
