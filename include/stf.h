@@ -450,12 +450,14 @@ stf_status stf_ntex_filter(const stf_neural* nt, const float* queries_dev, int64
 /* A server batches stochastic lookup requests of any size against resident
  * textures (2D textures, materials and 3D grids) as they arrive.  A worker thread
  * admits requests in arrival order while fewer than max_resident are
- * resident and their device state fits in a memory_budget_bytes arena
- * (staged queries unless STF_SERVE_QUERIES_ON_DEVICE, results, indices),
- * serves the next chunk (<= chunk_queries) of every resident request in each
- * round with one launch per (texture, filter), copies finished results to the
- * caller's buffer, and records each request's latency from its arrival to
- * the moment its results are in place.  Requests arriving while others run
+ * resident and their staged state fits in a memory_budget_bytes arena
+ * (queries unless STF_SERVE_QUERIES_ON_DEVICE; results and indices unless
+ * STF_SERVE_RESULTS_ON_DEVICE, in which case the kernels write them straight
+ * into the caller's out / out_index), serves the next chunk (<= chunk_queries)
+ * of every resident request in each round with one launch per (texture,
+ * filter), copies finished host results to the caller's buffer, and records
+ * each request's latency from its arrival to the moment its results are in
+ * place.  Requests arriving while others run
  * join the next round.  The random draw of a query depends only on (seed,
  * index within the request), so each request's results are bit-identical to
  * stf_filter(tex, queries, n, filter, STF_STOCHASTIC, seed, ...) alone.
@@ -476,6 +478,14 @@ typedef struct {
     double span_s;
 } stf_serve_stats;
 
+/* With a flag set, the buffers it names must be device memory of the
+ * request's size; submission rejects (STF_E_INVALID) a buffer that is not
+ * device memory or does not fit in the device allocation holding it (a
+ * buffer carved from a larger allocation is checked against that
+ * allocation only).
+ * Device results are written chunk by chunk in place, so a cancelled request
+ * may leave some of them written; host results are copied only on
+ * completion. */
 #define STF_SERVE_QUERIES_ON_DEVICE 1u   /* queries are device memory (else host) */
 #define STF_SERVE_RESULTS_ON_DEVICE 2u   /* out/out_index are device memory (else host) */
 

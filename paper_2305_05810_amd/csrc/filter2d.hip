@@ -701,15 +701,17 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __res
         for (int c = 0; c < CAP; ++c) v[c] = ok ? acc[c] : __builtin_nanf("");
     } else {   // GAUSS_FIS_MEAN
         // The x weights of the window are kept in LDS, one column per thread
-        // (a run-time sized array in registers would live in scratch); the y
-        // weights follow as running differences in the row loop.
-        __shared__ float wxs[GAUSS_MAX_TAPS][BLOCK];
+        // (a run-time sized array in registers would live in scratch), in
+        // 2R + 2 rows of BLOCK floats sized at launch, so that the block
+        // takes no more LDS than its radius needs; the y weights follow as
+        // running differences in the row loop.
+        extern __shared__ float wxs[];
         const int nt = 2 * radius + 2;
         double px = gauss_phi(((double)(cx - radius) - xe - 0.5) / sg);
         double py = gauss_phi(((double)(cy - radius) - ye - 0.5) / sg);
         for (int k = 0; k < nt; ++k) {
             const double qx = gauss_phi(((double)(cx - radius + k) - xe + 0.5) / sg);
-            wxs[k][threadIdx.x] = (float)(qx - px);
+            wxs[k * BLOCK + threadIdx.x] = (float)(qx - px);
             px = qx;
         }
         float acc[CAP];
@@ -726,7 +728,7 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __res
             for (int a = 0; a < nt; ++a) {
                 float t[CAP];
                 S.load(clampi(cx - radius + a, S.w() - 1), yy, t);
-                const float wxa = wxs[a][threadIdx.x];
+                const float wxa = wxs[a * BLOCK + threadIdx.x];
 #pragma unroll
                 for (int c = 0; c < CAP; ++c) row[c] = __builtin_fmaf(wxa, t[c], row[c]);
             }
@@ -870,7 +872,8 @@ hipError_t gauss2d_src(const Src& S, const float* q, int32_t n, float sigma, int
         break;
     case GAUSS_FIS_MEAN:
         if (2 * radius + 2 > GAUSS_MAX_TAPS) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_tex2d_gauss<Src, GAUSS_FIS_MEAN>), grid, block, 0, stream, S, q, n, sigma, radius, key,
+        hipLaunchKernelGGL((k_tex2d_gauss<Src, GAUSS_FIS_MEAN>), grid, block,
+                           (size_t)(2 * radius + 2) * BLOCK * sizeof(float), stream, S, q, n, sigma, radius, key,
                            out, idx);
         break;
     case GAUSS_DISCRETE:

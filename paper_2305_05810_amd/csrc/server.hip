@@ -151,6 +151,9 @@ struct stf_server {
     double t_first = 0.0, t_last = 0.0;
     int64_t n_rounds = 0;
     std::string error;
+    // device allocations already seen to hold flagged query / result buffers
+    std::mutex ranges_mu;
+    std::vector<std::pair<uintptr_t, size_t>> device_ranges;
 };
 
 namespace {
@@ -205,24 +208,35 @@ void worker_main(stf_server* s)
             }
             while (!s->pending.empty() && (int)s->resident.size() < s->cfg.max_resident) {
                 Request* r = s->pending.front();
-                size_t need = (size_t)r->n * ((r->flags & STF_SERVE_QUERIES_ON_DEVICE) ? 0 : 4 * r->dims) +
-                              (size_t)r->n * 4 * r->channels + 256 + (r->idx_user ? (size_t)r->n * 4 * r->dims + 256 : 0);
-                size_t off;
-                if (!s->arena.alloc(need, &off)) break;
+                // the arena stages host queries and host results only: device
+                // results are written in place by the kernels
+                const bool dev_q = r->flags & STF_SERVE_QUERIES_ON_DEVICE;
+                const bool dev_out = r->flags & STF_SERVE_RESULTS_ON_DEVICE;
+                const size_t need = (dev_q ? 0 : (size_t)r->n * 4 * r->dims + 256) +
+                                    (dev_out ? 0
+                                             : (size_t)r->n * 4 * r->channels + 256 +
+                                                   (r->idx_user ? (size_t)r->n * 4 * r->dims + 256 : 0));
+                size_t off = 0;
+                if (need && !s->arena.alloc(need, &off)) break;
                 s->pending.pop_front();
                 r->off = off;
                 r->bytes = need;
                 char* base = s->arena_dev + off;
                 size_t o = 0;
-                if (r->flags & STF_SERVE_QUERIES_ON_DEVICE) {
+                if (dev_q) {
                     r->q_dev = r->q_user;
                 } else {
                     r->q_dev = (const float*)base;
                     o += ((size_t)r->n * 4 * r->dims + 255) & ~(size_t)255;
                 }
-                r->out_dev = (float*)(base + o);
-                o += ((size_t)r->n * 4 * r->channels + 255) & ~(size_t)255;
-                r->idx_dev = r->idx_user ? (int32_t*)(base + o) : nullptr;
+                if (dev_out) {
+                    r->out_dev = r->out_user;
+                    r->idx_dev = r->idx_user;
+                } else {
+                    r->out_dev = (float*)(base + o);
+                    o += ((size_t)r->n * 4 * r->channels + 255) & ~(size_t)255;
+                    r->idx_dev = r->idx_user ? (int32_t*)(base + o) : nullptr;
+                }
                 r->state = RESIDENT;
                 s->resident.push_back(r);
                 admitted.push_back(r);
@@ -290,14 +304,17 @@ void worker_main(stf_server* s)
                         : launch_serve2d(g.tex, g.filter, dd + g.first, g.count, g.blocks, s->stream);
                 s->launches += 1;
             }
-            // results of requests finished in this round go to the caller's buffers
+            // results of requests finished in this round go to the caller's
+            // host buffers (device results are already in place)
             for (Request* r : round_reqs) {
                 if (r->next != r->n || e != hipSuccess) continue;
-                hipMemcpyKind kind = (r->flags & STF_SERVE_RESULTS_ON_DEVICE) ? hipMemcpyDeviceToDevice
-                                                                              : hipMemcpyDeviceToHost;
-                e = hipMemcpyAsync(r->out_user, r->out_dev, (size_t)r->n * 4 * r->channels, kind, s->stream);
-                if (e == hipSuccess && r->idx_user)
-                    e = hipMemcpyAsync(r->idx_user, r->idx_dev, (size_t)r->n * 4 * r->dims, kind, s->stream);
+                if (!(r->flags & STF_SERVE_RESULTS_ON_DEVICE)) {
+                    e = hipMemcpyAsync(r->out_user, r->out_dev, (size_t)r->n * 4 * r->channels,
+                                       hipMemcpyDeviceToHost, s->stream);
+                    if (e == hipSuccess && r->idx_user)
+                        e = hipMemcpyAsync(r->idx_user, r->idx_dev, (size_t)r->n * 4 * r->dims, hipMemcpyDeviceToHost,
+                                           s->stream);
+                }
                 if (e == hipSuccess) e = hipEventRecord(r->done_ev, s->stream);
                 {
                     std::lock_guard<std::mutex> lk(s->mu);   // poll, wait and cancel read the state under the lock
@@ -372,8 +389,38 @@ stf_status submit_locked(stf_server* s, const stf_texture* tex, const float* que
     return STF_OK;
 }
 
+// True if [p, p + bytes) lies in one device allocation.  Allocations seen
+// before are remembered, so a stream of requests into a few pools costs one
+// runtime query per pool.
+bool device_range(stf_server* s, const void* p, size_t bytes)
+{
+    const uintptr_t a = (uintptr_t)p;
+    {
+        std::lock_guard<std::mutex> lk(s->ranges_mu);
+        for (const auto& r : s->device_ranges)
+            if (a >= r.first && a - r.first <= r.second && bytes <= r.second - (a - r.first)) return true;
+    }
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess ||
+        (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
+        (void)hipGetLastError();
+        return false;
+    }
+    void* base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const uintptr_t b = (uintptr_t)base;
+    if (a < b || a - b > size || bytes > size - (a - b)) return false;
+    std::lock_guard<std::mutex> lk(s->ranges_mu);
+    if (s->device_ranges.size() < 64) s->device_ranges.push_back({b, size});
+    return true;
+}
+
 stf_status validate_request(stf_server* s, const stf_texture* tex, const float* queries, int64_t n,
-                            stf_filter_kind filter, float* out, uint32_t flags)
+                            stf_filter_kind filter, float* out, const int32_t* out_index, uint32_t flags)
 {
     if (!tex || (tex->kind != STF_KIND_GRID3D && tex->kind != STF_KIND_TEX2D && tex->kind != STF_KIND_MATERIAL))
         return stf_fail(STF_E_INVALID, "requests need a 3D grid, a 2D texture or a material");
@@ -385,12 +432,20 @@ stf_status validate_request(stf_server* s, const stf_texture* tex, const float* 
     if (flags & ~(uint32_t)(STF_SERVE_QUERIES_ON_DEVICE | STF_SERVE_RESULTS_ON_DEVICE))
         return stf_fail(STF_E_INVALID, "unknown flags 0x%x", flags);
     int dims = tex->kind == STF_KIND_GRID3D ? 3 : 2;
-    size_t need = (size_t)n * ((flags & STF_SERVE_QUERIES_ON_DEVICE) ? 0 : 4 * dims) + (size_t)n * 4 * tex->channels +
-                  (size_t)n * 4 * dims + 1024;
+    const bool dev_q = flags & STF_SERVE_QUERIES_ON_DEVICE, dev_out = flags & STF_SERVE_RESULTS_ON_DEVICE;
+    size_t need = (dev_q ? 0 : (size_t)n * 4 * dims) + (dev_out ? 0 : (size_t)n * 4 * tex->channels +
+                                                                        (size_t)n * 4 * dims) + 1024;
     if (need > (size_t)s->cfg.memory_budget_bytes)
         return stf_fail(STF_E_OOM, "request of %lld queries needs %zu bytes, more than the budget", (long long)n, need);
-    if ((uintptr_t)queries % ((flags & STF_SERVE_QUERIES_ON_DEVICE) && dims == 2 ? 8 : 4))
-        return stf_fail(STF_E_INVALID, "queries are misaligned");
+    if ((uintptr_t)queries % (dev_q && dims == 2 ? 8 : 4)) return stf_fail(STF_E_INVALID, "queries are misaligned");
+    if (dev_out && ((uintptr_t)out % 4 || (uintptr_t)out_index % 4))
+        return stf_fail(STF_E_INVALID, "out or out_index is misaligned");
+    if (dev_q && !device_range(s, queries, (size_t)n * 4 * dims))
+        return stf_fail(STF_E_INVALID, "STF_SERVE_QUERIES_ON_DEVICE: queries are not n x %d floats of device memory", dims);
+    if (dev_out && (!device_range(s, out, (size_t)n * 4 * tex->channels) ||
+                    (out_index && !device_range(s, out_index, (size_t)n * 4 * dims))))
+        return stf_fail(STF_E_INVALID, "STF_SERVE_RESULTS_ON_DEVICE: out / out_index are not device memory of the "
+                                       "request's size");
     return STF_OK;
 }
 
@@ -465,7 +520,7 @@ stf_status stf_server_submit(stf_server* s, const stf_texture* tex, const float*
 {
     stf_clear_error();
     if (!s || !ticket) return stf_fail(STF_E_INVALID, "NULL argument");
-    stf_status st = validate_request(s, tex, queries, n, filter, out, flags);
+    stf_status st = validate_request(s, tex, queries, n, filter, out, out_index, flags);
     if (st != STF_OK) return st;
     std::lock_guard<std::mutex> lk(s->mu);
     return submit_locked(s, tex, queries, n, filter, seed, out, out_index, flags, now_s(), ticket);
@@ -588,7 +643,8 @@ stf_status stf_server_replay(stf_server* s, const stf_serve_request* reqs, int64
     stf_clear_error();
     if (!s || (!reqs && count)) return stf_fail(STF_E_INVALID, "NULL argument");
     for (int64_t k = 0; k < count; ++k) {
-        stf_status st = validate_request(s, reqs[k].tex, reqs[k].queries, reqs[k].n, reqs[k].filter, reqs[k].out, flags);
+        stf_status st = validate_request(s, reqs[k].tex, reqs[k].queries, reqs[k].n, reqs[k].filter, reqs[k].out,
+                                         reqs[k].out_index, flags);
         if (st != STF_OK) return st;
         if (k && reqs[k].arrival_s < reqs[k - 1].arrival_s) return stf_fail(STF_E_INVALID, "arrivals must not decrease");
     }

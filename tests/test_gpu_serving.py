@@ -3,6 +3,8 @@ same lookups filtered alone (stf_filter) whatever else is in the mix;
 admission respects the memory budget and the resident limit; oversized
 requests are rejected; pending requests can be cancelled; the open-loop
 replay reports latency percentiles."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -165,4 +167,44 @@ def test_replay_time_out_leaves_nothing_in_flight(dev, textures):
     st = stf.stf_server_stats(srv)
     assert st["pending"] == 0 and st["resident"] == 0
     assert st["completed"] + st["cancelled"] == 16 and st["cancelled"] > 0
+    srv.destroy()
+
+
+def test_device_results_in_place_and_flag_checks(dev, textures):
+    # Device results are written in place: a request whose results alone
+    # would overflow a small arena is admitted when they live on the device,
+    # and its results equal stf_filter's.  Buffers flagged as device memory
+    # that are not are rejected at submission.
+    tex, dims = textures[2]   # 2D RGBA texture
+    n = 100000
+    q = _queries(dims, n, np.random.default_rng(8))
+    ref, ridx = _alone(dev, tex, q, stf.STF_CUBIC_BSPLINE, 17)
+    srv = stf.stf_server_create(1 << 16, 4, 8192)   # 64 KiB: far less than n x 16 B of results
+    qd = torch.from_numpy(q).to(dev)
+    out = torch.empty((n, tex.channels), dtype=torch.float32, device=dev)
+    idx = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    t = stf.stf_server_submit(srv, tex, qd, stf.STF_CUBIC_BSPLINE, 17, out, idx)
+    stf.stf_server_wait(srv, t)
+    assert np.array_equal(idx.cpu().numpy(), ridx)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    assert stf.stf_server_stats(srv)["peak_arena_bytes"] == 0
+    L = stf._srv_lib()
+    ticket = ctypes.c_uint64()
+    host_out = np.empty((n, tex.channels), np.float32)
+    host_q = np.ascontiguousarray(q)
+    both = stf.STF_SERVE_QUERIES_ON_DEVICE | stf.STF_SERVE_RESULTS_ON_DEVICE
+    # results flagged as device memory but on the host
+    assert L.stf_server_submit(srv.handle, tex.handle, qd.data_ptr(), n, stf.STF_LINEAR, 1,
+                               host_out.ctypes.data, None, both, ctypes.byref(ticket)) == stf.STF_E_INVALID
+    # queries flagged as device memory but on the host
+    assert L.stf_server_submit(srv.handle, tex.handle, host_q.ctypes.data, n, stf.STF_LINEAR, 1,
+                               out.data_ptr(), None, both, ctypes.byref(ticket)) == stf.STF_E_INVALID
+    # results far larger than the device allocation holding out (a small
+    # tensor comes from a 2 MiB block of torch's allocator; the check sees
+    # allocations, not tensors)
+    big = 1 << 20
+    qbig = torch.full((big, 2), 0.5, dtype=torch.float32, device=dev)
+    small = torch.empty(1024, dtype=torch.float32, device=dev)
+    assert L.stf_server_submit(srv.handle, tex.handle, qbig.data_ptr(), big, stf.STF_LINEAR, 1,
+                               small.data_ptr(), None, both, ctypes.byref(ticket)) == stf.STF_E_INVALID
     srv.destroy()
