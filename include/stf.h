@@ -141,7 +141,10 @@ stf_status stf_create_texture2d(int32_t width, int32_t height, int32_t channels,
  * level 0 of a material as a 2D texture of six channels (albedo R, G, B,
  * roughness, normal x, normal y; each decoded exactly: v / 255 and binary16
  * widened), so a material is filtered before shading (Eq.
- * traditional-lighting-integral) with every filter and mode of stf_filter. */
+ * traditional-lighting-integral) with every filter and mode of stf_filter.
+ * The caller passes row-major levels; the library stores each level in
+ * tiles of 4x4 texels (one 128-byte line per tile), padded to whole tiles,
+ * which stf_texture_bytes counts. */
 stf_status stf_create_material2d(int32_t width, int32_t height, int32_t levels,
                                  const void* const* level_texels_host, stf_texture** out);
 

@@ -63,7 +63,8 @@ struct DenseSrc {
 };
 
 // Material texels (8 bytes: albedo RGB UNORM8, roughness UNORM8, tangent
-// normal x and y binary16) of level 0, decoded exactly to six channels.
+// normal x and y binary16; stored in 4x4-texel tiles, material_index) of
+// level 0, decoded exactly to six channels.
 struct MaterialSrc {
     static constexpr int CAP = 6;
     static constexpr bool DECODES = false;
@@ -73,7 +74,7 @@ struct MaterialSrc {
     __device__ int channels() const { return 6; }
     __device__ void load(int x, int y, float (&v)[CAP]) const
     {
-        const uint2 t = reinterpret_cast<const uint2*>(L.texels)[(int64_t)y * L.w + x];
+        const uint2 t = reinterpret_cast<const uint2*>(L.texels)[material_index(x, y, L.w)];
         v[0] = dec_u8(t.x & 0xffu);
         v[1] = dec_u8((t.x >> 8) & 0xffu);
         v[2] = dec_u8((t.x >> 16) & 0xffu);

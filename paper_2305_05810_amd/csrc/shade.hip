@@ -149,7 +149,7 @@ __global__ __launch_bounds__(BLOCK) void k_shade(Levels L, const float* __restri
             }
             sx = clampi(sx, T.w - 1);
             sy = clampi(sy, T.h - 1);
-            shade(decode_material(tex[(int64_t)sy * T.w + sx]), wo, wi, f);
+            shade(decode_material(tex[material_index(sx, sy, T.w)]), wo, wi, f);
             if (idx) {
                 idx[3 * (int64_t)i] = sx;
                 idx[3 * (int64_t)i + 1] = sy;
@@ -173,9 +173,9 @@ __global__ __launch_bounds__(BLOCK) void k_shade(Levels L, const float* __restri
             uint2 texel[NT][NT];
 #pragma unroll
             for (int b = 0; b < NT; ++b) {
-                const int64_t row = (int64_t)clampi(cy + b, T.h - 1) * T.w;
+                const int yy = clampi(cy + b, T.h - 1);
 #pragma unroll
-                for (int a = 0; a < NT; ++a) texel[b][a] = tex[row + clampi(cx + a, T.w - 1)];
+                for (int a = 0; a < NT; ++a) texel[b][a] = tex[material_index(clampi(cx + a, T.w - 1), yy, T.w)];
             }
             float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll

@@ -5,7 +5,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
+#include <new>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -222,10 +224,36 @@ stf_status stf_create_material2d(int32_t width, int32_t height, int32_t levels, 
     t->fmt = -1;
     t->channels = 6;   // filtered as albedo RGB, roughness, normal x, y
     (void)hipGetDevice(&t->device);
-    stf_status s = create_levels(t, width, height, levels, level_texels_host, 8);
-    if (s != STF_OK) {
-        free_texture(t);
-        return s;
+    // each level re-laid out in 4x4-texel tiles (material_index), padded
+    // with zero texels to whole tiles
+    t->levels = levels;
+    t->bytes = 0;
+    for (int l = 0; l < levels; ++l) {
+        const int32_t w = std::max(width >> l, 1), h = std::max(height >> l, 1);
+        if (!level_texels_host[l]) {
+            free_texture(t);
+            return stf_fail(STF_E_INVALID, "level %d texels are NULL", l);
+        }
+        const size_t tiles = (size_t)((w + 3) / 4) * (size_t)((h + 3) / 4);
+        std::vector<uint64_t> tiled;
+        try {
+            tiled.assign(tiles * 16, 0);
+        } catch (const std::bad_alloc&) {
+            free_texture(t);
+            return stf_fail(STF_E_OOM, "host allocation of %zu bytes failed", tiles * 128);
+        }
+        const uint64_t* src = static_cast<const uint64_t*>(level_texels_host[l]);
+        for (int32_t y = 0; y < h; ++y)
+            for (int32_t x = 0; x < w; ++x) tiled[(size_t)material_index(x, y, w)] = src[(size_t)y * w + x];
+        stf_status s = upload(&t->level_alloc[l], tiled.data(), tiles * 128, "material level");
+        if (s != STF_OK) {
+            free_texture(t);
+            return s;
+        }
+        t->level[l].texels = t->level_alloc[l];
+        t->level[l].w = w;
+        t->level[l].h = h;
+        t->bytes += (int64_t)(tiles * 128);
     }
     *out = t;
     return STF_OK;

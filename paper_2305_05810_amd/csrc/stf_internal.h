@@ -13,9 +13,19 @@ constexpr int STF_MAX_LEVELS = 16;
 
 // Device view of one 2D level.
 struct TexLevel {
-    const void* texels;   // row-major, channels interleaved
+    const void* texels;   // row-major, channels interleaved (materials: 4x4 tiles, see material_index)
     int32_t w, h;
 };
+
+// Materials are stored in tiles of 4x4 texels (8 bytes each: one 128-byte
+// line per tile), tiles row-major over ceil(w/4) x ceil(h/4), texels
+// row-major within a tile: a 4x4 filter footprint touches 1-4 lines
+// (3.1 on average) instead of 4-8 rows of a row-major level.
+__host__ __device__ inline int64_t material_index(int x, int y, int w)
+{
+    const int tiles_w = (w + 3) >> 2;
+    return (((int64_t)(y >> 2) * tiles_w + (x >> 2)) << 4) + ((y & 3) << 2) + (x & 3);
+}
 
 // Device view of a sparse grid: root table -> internal nodes of 16^3 children
 // -> dense 8^3 leaves.  A root slot covers 128^3 voxels, a node child slot
