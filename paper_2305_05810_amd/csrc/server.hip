@@ -121,6 +121,7 @@ struct Request {
     hipEvent_t done_ev = nullptr;
     int64_t round = -1;       // round whose launch carries the request's last chunk
     int64_t last_round = -1;  // latest round that launched any chunk of the request
+    int32_t res_pos = -1;     // index in the server's resident list
 };
 
 constexpr int RING = 4;
@@ -151,9 +152,10 @@ struct stf_server {
     double t_first = 0.0, t_last = 0.0;
     int64_t n_rounds = 0;
     std::string error;
-    // device allocations already seen to hold flagged query / result buffers
-    std::mutex ranges_mu;
-    std::vector<std::pair<uintptr_t, size_t>> device_ranges;
+    // completion events of released requests, reused by later ones (creating
+    // and destroying one per request costs runtime work under the lock at
+    // tens of thousands of requests per second)
+    std::vector<hipEvent_t> event_pool;
 };
 
 namespace {
@@ -165,12 +167,32 @@ void record_failure(stf_server* s, const char* what, hipError_t e)
     s->error = buf;
 }
 
+// Removes r from the resident list in O(1) (the list's order does not
+// matter: a query's draw depends only on its request's seed and its index).
+void unlist_resident(stf_server* s, Request* r)
+{
+    // caller holds s->mu
+    const int32_t pos = r->res_pos;
+    if (pos < 0) return;
+    Request* last = s->resident.back();
+    s->resident[pos] = last;
+    last->res_pos = pos;
+    s->resident.pop_back();
+    r->res_pos = -1;
+}
+
 void retire(stf_server* s, Request* r, int state, double t)
 {
     // caller holds s->mu
     if (r->bytes) s->arena.release(r->off, r->bytes);
     r->bytes = 0;
     r->state = state;
+    // the event has served its purpose (the worker saw it complete, or the
+    // request never reached it): back to the pool for later requests
+    if (r->done_ev && s->event_pool.size() < 65536) {
+        s->event_pool.push_back(r->done_ev);
+        r->done_ev = nullptr;
+    }
     if (state == DONE) {
         s->completed += 1;
         s->queries += r->n;
@@ -187,7 +209,7 @@ void worker_main(stf_server* s)
 {
     (void)hipSetDevice(s->device);
     const int qpb3 = serve3d_queries_per_block(), qpb2 = serve2d_queries_per_block();
-    std::vector<Request*> finishing;
+    std::vector<Request*> finishing, still;
     for (;;) {
         std::vector<Request*> admitted;
         std::vector<Request*> round_reqs;
@@ -195,15 +217,15 @@ void worker_main(stf_server* s)
             std::unique_lock<std::mutex> lk(s->mu);
             // retire cancelled residents once no launch of theirs is in flight
             // (the stream is in order: a later round's event implies earlier ones)
-            for (auto it = s->resident.begin(); it != s->resident.end();) {
-                Request* r = *it;
+            for (size_t k = 0; k < s->resident.size();) {
+                Request* r = s->resident[k];
                 bool quiet = r->last_round < 0 || s->round - r->last_round >= RING ||
                              hipEventQuery(s->round_ev[r->last_round % RING]) == hipSuccess;
                 if (r->cancel && r->state == RESIDENT && quiet) {
+                    unlist_resident(s, r);   // the last entry moves to k
                     retire(s, r, CANCELLED, now_s());
-                    it = s->resident.erase(it);
                 } else {
-                    ++it;
+                    ++k;
                 }
             }
             while (!s->pending.empty() && (int)s->resident.size() < s->cfg.max_resident) {
@@ -238,6 +260,7 @@ void worker_main(stf_server* s)
                     r->idx_dev = r->idx_user ? (int32_t*)(base + o) : nullptr;
                 }
                 r->state = RESIDENT;
+                r->res_pos = (int32_t)s->resident.size();
                 s->resident.push_back(r);
                 admitted.push_back(r);
             }
@@ -329,7 +352,10 @@ void worker_main(stf_server* s)
         if (e != hipSuccess) {
             std::lock_guard<std::mutex> lk(s->mu);
             record_failure(s, "serving round failed", e);
-            for (Request* r : s->resident) retire(s, r, FAILED, now_s());
+            for (Request* r : s->resident) {
+                r->res_pos = -1;
+                retire(s, r, FAILED, now_s());
+            }
             s->resident.clear();
             finishing.clear();
             continue;
@@ -337,20 +363,20 @@ void worker_main(stf_server* s)
         // retire finished requests; block on the oldest one only when there is
         // nothing else to do
         bool idle = round_reqs.empty() && admitted.empty();
-        for (auto it = finishing.begin(); it != finishing.end();) {
-            Request* r = *it;
-            hipError_t q = idle && it == finishing.begin() ? hipEventSynchronize(r->done_ev) : hipEventQuery(r->done_ev);
+        still.clear();
+        for (size_t k = 0; k < finishing.size(); ++k) {
+            Request* r = finishing[k];
+            hipError_t q = idle && k == 0 ? hipEventSynchronize(r->done_ev) : hipEventQuery(r->done_ev);
             if (q == hipErrorNotReady) {
-                ++it;
+                still.push_back(r);
                 continue;
             }
             double t = now_s();
             std::lock_guard<std::mutex> lk(s->mu);
-            auto pos = std::find(s->resident.begin(), s->resident.end(), r);
-            if (pos != s->resident.end()) s->resident.erase(pos);
+            unlist_resident(s, r);
             retire(s, r, q == hipSuccess ? DONE : FAILED, t);
-            it = finishing.erase(it);
         }
+        finishing.swap(still);
     }
 }
 
@@ -366,7 +392,10 @@ stf_status submit_locked(stf_server* s, const stf_texture* tex, const float* que
 {
     Request* r = new (std::nothrow) Request();
     if (!r) return stf_fail(STF_E_OOM, "host allocation failed");
-    if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) {
+    if (!s->event_pool.empty()) {
+        r->done_ev = s->event_pool.back();
+        s->event_pool.pop_back();
+    } else if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) {
         delete r;
         return stf_fail(STF_E_DEVICE, "hipEventCreate failed");
     }
@@ -389,17 +418,19 @@ stf_status submit_locked(stf_server* s, const stf_texture* tex, const float* que
     return STF_OK;
 }
 
-// True if [p, p + bytes) lies in one device allocation.  Allocations seen
-// before are remembered, so a stream of requests into a few pools costs one
-// runtime query per pool.
-bool device_range(stf_server* s, const void* p, size_t bytes)
+// Device allocations (base, size) seen while validating one batch of
+// requests: the requests of a replay, whose buffers must all stay valid
+// until it returns, often share a few pools.  Nothing is remembered across
+// calls, since an allocation may be freed and its addresses reused.
+using RangeCache = std::vector<std::pair<uintptr_t, size_t>>;
+
+// True if [p, p + bytes) lies in one device allocation.
+bool device_range(const void* p, size_t bytes, RangeCache* cache)
 {
     const uintptr_t a = (uintptr_t)p;
-    {
-        std::lock_guard<std::mutex> lk(s->ranges_mu);
-        for (const auto& r : s->device_ranges)
+    if (cache)
+        for (const auto& r : *cache)
             if (a >= r.first && a - r.first <= r.second && bytes <= r.second - (a - r.first)) return true;
-    }
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, p) != hipSuccess ||
         (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
@@ -414,13 +445,13 @@ bool device_range(stf_server* s, const void* p, size_t bytes)
     }
     const uintptr_t b = (uintptr_t)base;
     if (a < b || a - b > size || bytes > size - (a - b)) return false;
-    std::lock_guard<std::mutex> lk(s->ranges_mu);
-    if (s->device_ranges.size() < 64) s->device_ranges.push_back({b, size});
+    if (cache && cache->size() < 64) cache->push_back({b, size});
     return true;
 }
 
 stf_status validate_request(stf_server* s, const stf_texture* tex, const float* queries, int64_t n,
-                            stf_filter_kind filter, float* out, const int32_t* out_index, uint32_t flags)
+                            stf_filter_kind filter, float* out, const int32_t* out_index, uint32_t flags,
+                            RangeCache* cache = nullptr)
 {
     if (!tex || (tex->kind != STF_KIND_GRID3D && tex->kind != STF_KIND_TEX2D && tex->kind != STF_KIND_MATERIAL))
         return stf_fail(STF_E_INVALID, "requests need a 3D grid, a 2D texture or a material");
@@ -440,10 +471,10 @@ stf_status validate_request(stf_server* s, const stf_texture* tex, const float* 
     if ((uintptr_t)queries % (dev_q && dims == 2 ? 8 : 4)) return stf_fail(STF_E_INVALID, "queries are misaligned");
     if (dev_out && ((uintptr_t)out % 4 || (uintptr_t)out_index % 4))
         return stf_fail(STF_E_INVALID, "out or out_index is misaligned");
-    if (dev_q && !device_range(s, queries, (size_t)n * 4 * dims))
+    if (dev_q && !device_range(queries, (size_t)n * 4 * dims, cache))
         return stf_fail(STF_E_INVALID, "STF_SERVE_QUERIES_ON_DEVICE: queries are not n x %d floats of device memory", dims);
-    if (dev_out && (!device_range(s, out, (size_t)n * 4 * tex->channels) ||
-                    (out_index && !device_range(s, out_index, (size_t)n * 4 * dims))))
+    if (dev_out && (!device_range(out, (size_t)n * 4 * tex->channels, cache) ||
+                    (out_index && !device_range(out_index, (size_t)n * 4 * dims, cache))))
         return stf_fail(STF_E_INVALID, "STF_SERVE_RESULTS_ON_DEVICE: out / out_index are not device memory of the "
                                        "request's size");
     return STF_OK;
@@ -503,9 +534,10 @@ void stf_server_destroy(stf_server* s)
     s->worker.join();
     (void)hipStreamSynchronize(s->stream);
     for (auto& kv : s->all) {
-        (void)hipEventDestroy(kv.second->done_ev);
+        if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);
         delete kv.second;
     }
+    for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
     for (int k = 0; k < RING; ++k) (void)hipEventDestroy(s->round_ev[k]);
     (void)hipFree(s->arena_dev);
     (void)hipHostFree(s->desc_host);
@@ -587,7 +619,7 @@ stf_status stf_server_release(stf_server* s, uint64_t ticket)
     if (!r) return stf_fail(STF_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
     if (r->state < DONE) return stf_fail(STF_E_BUSY, "request %llu is still in flight", (unsigned long long)ticket);
     s->all.erase(ticket);
-    (void)hipEventDestroy(r->done_ev);
+    if (r->done_ev) (void)hipEventDestroy(r->done_ev);   // retire returned it to the pool unless the pool was full
     delete r;
     return STF_OK;
 }
@@ -642,15 +674,24 @@ stf_status stf_server_replay(stf_server* s, const stf_serve_request* reqs, int64
 {
     stf_clear_error();
     if (!s || (!reqs && count)) return stf_fail(STF_E_INVALID, "NULL argument");
+    RangeCache ranges;
     for (int64_t k = 0; k < count; ++k) {
         stf_status st = validate_request(s, reqs[k].tex, reqs[k].queries, reqs[k].n, reqs[k].filter, reqs[k].out,
-                                         reqs[k].out_index, flags);
+                                         reqs[k].out_index, flags, &ranges);
         if (st != STF_OK) return st;
         if (k && reqs[k].arrival_s < reqs[k - 1].arrival_s) return stf_fail(STF_E_INVALID, "arrivals must not decrease");
     }
     if (!(timeout_s >= 0.0)) return stf_fail(STF_E_INVALID, "timeout_s = %g must be >= 0", timeout_s);
     std::vector<uint64_t> tickets;
     tickets.reserve((size_t)count);
+    {
+        // grown ahead: a rehash of the ticket table or a reallocation of the
+        // latency record while the requests stream in would stall submission
+        // and the worker (both under the lock) for milliseconds
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->all.reserve(s->all.size() + (size_t)count);
+        s->lat_ms.reserve(s->lat_ms.size() + (size_t)count);
+    }
     // On an error or a time-out the requests still outstanding are cancelled
     // and waited for without a deadline before the call returns, so no copy
     // into a caller's buffer can land after it (a cancelled request is
