@@ -110,3 +110,36 @@ def test_shade_material_errors(dev):
         stf.stf_shade_filter(grid, q, stf.STF_CUBIC_BSPLINE, stf.STF_SHADE_STOCHASTIC, 0, out)
     grid.destroy()
     mat.destroy()
+
+
+@pytest.mark.parametrize("W,H", [(37, 29), (5, 3), (1, 1)], ids=["37x29", "5x3", "1x1"])
+def test_shade_ragged_material(dev, W, H):
+    # level sizes that are not multiples of the 4x4 storage tile (padded on
+    # the device): every tap, including clamped ones at the ragged edges, reads
+    # the texel the oracle reads from the row-major levels
+    big = synth.material_levels(64, seed=33, levels=3)
+    lv = [np.ascontiguousarray(big[l][:max(H >> l, 1), :max(W >> l, 1)]) for l in range(3)]
+    mat = stf.stf_create_material2d(W, H, lv)
+    om_ = oracle.Material(lv)
+    recs = synth.shade_queries(20000, seed=34)
+    recs[:, 0:2] = recs[:, 0:2] * np.float32(1.2) - np.float32(0.1)
+    q = torch.from_numpy(recs).to(dev)
+    n = recs.shape[0]
+    for gm, om in ((stf.STF_SHADE_STOCHASTIC, oracle.SH_STOCH), (stf.STF_SHADE_AFTER_FILTER, oracle.SH_AFTER_FILTER),
+                   (stf.STF_FILTER_AFTER_SHADE, oracle.SH_FILTER_AFTER)):
+        out = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        idx = torch.empty((n, 3), dtype=torch.int32, device=dev) if gm == stf.STF_SHADE_STOCHASTIC else None
+        stf.stf_shade_filter(mat, q, stf.STF_CUBIC_BSPLINE, gm, 5, out, idx)
+        ov, oi = om_.shade(recs, oracle.CUBIC, om, 5)
+        if idx is not None:
+            assert np.array_equal(idx.cpu().numpy(), oi)
+        _check(out.cpu().numpy().astype(np.float64), ov, f"ragged {W}x{H} mode {gm}")
+    # the same level through the 2D filters (six channels)
+    raw = lv[0].view(np.uint8).reshape(H, W, 8)
+    uv = (synth.uv_queries(20000, seed=35) * np.float32(1.2) - np.float32(0.1)).astype(np.float32)
+    gv, gi = stf.filter(mat, torch.from_numpy(uv).to(dev), stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 6,
+                        want_index=True)
+    ov, oi = oracle.material_filter2d(raw, uv, oracle.CUBIC, oracle.STOCH, 6)
+    assert np.array_equal(gi.cpu().numpy(), oi)
+    assert np.array_equal(np.nan_to_num(gv.cpu().numpy(), nan=-7), np.nan_to_num(ov.astype(np.float32), nan=-7))
+    mat.destroy()
