@@ -22,6 +22,33 @@ __host__ __device__ constexpr int fmt_bytes(int fmt)
     return fmt == F32 ? 4 : (fmt == F16 || fmt == BF16) ? 2 : 1;
 }
 
+// Where voxel (x, y, z) of a leaf (each 0..7) lies among the leaf's 512
+// stored values: the leaf is kept in bricks of one 128-byte line -- 4x4x2
+// voxels of binary32, 8x4x2 of 16-bit values, 8x8x2 of 8-bit values --
+// x fastest within a brick, the bricks x, then y, then z.  A lookup whose
+// neighbours step along any axis then finds them in the same line more often
+// than in x-fastest rows.  The offset is the sum of one term per axis;
+// x-runs of 4 binary32 or 8 narrower values stay contiguous and 16- (8-)
+// byte aligned, so a row of taps is still read as whole chunks.
+__host__ __device__ constexpr uint32_t leaf_ox(int fmt, uint32_t x)
+{
+    return fmt == F32 ? (x >> 2) * 32u + (x & 3u) : x;
+}
+__host__ __device__ constexpr uint32_t leaf_oy(int fmt, uint32_t y)
+{
+    return fmt == F32 ? (y >> 2) * 64u + (y & 3u) * 4u : (fmt == F16 || fmt == BF16) ? (y >> 2) * 64u + (y & 3u) * 8u
+                                                                                      : y * 8u;
+}
+__host__ __device__ constexpr uint32_t leaf_oz(int fmt, uint32_t z)
+{
+    return fmt == F32 ? (z >> 1) * 128u + (z & 1u) * 16u
+                      : (fmt == F16 || fmt == BF16) ? (z >> 1) * 128u + (z & 1u) * 32u : z * 64u;
+}
+__host__ __device__ constexpr uint32_t leaf_offset(int fmt, uint32_t x, uint32_t y, uint32_t z)
+{
+    return leaf_ox(fmt, x) + leaf_oy(fmt, y) + leaf_oz(fmt, z);
+}
+
 // One-round PCG hash (Jarzynski & Olano, JCGT 2020).  Integer arithmetic
 // mod 2^32.
 __host__ __device__ __forceinline__ uint32_t pcg(uint32_t x)

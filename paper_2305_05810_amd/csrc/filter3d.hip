@@ -47,7 +47,7 @@ __device__ __forceinline__ float grid_voxel(const GridView& g, int x, int y, int
     if (!in_domain(g, x, y, z)) return g.background;
     int32_t leaf = grid_leaf(g, x, y, z);
     if (leaf < 0) return g.background;
-    return load_texel<FMT>(g.leaves, (int64_t)leaf * 512 + (((z & 7) * 8 + (y & 7)) * 8 + (x & 7)));
+    return load_texel<FMT>(g.leaves, (int64_t)leaf * 512 + leaf_offset(FMT, x & 7, y & 7, z & 7));
 }
 
 // ---------------------------------------------------------------------------
@@ -163,7 +163,7 @@ __device__ __forceinline__ void grid_stochastic_block(const GridView& g, const f
         if (__any(any)) {
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                uint32_t vox = ((((uint32_t)vz[k] & 7u) * 8u + ((uint32_t)vy[k] & 7u)) * 8u) + ((uint32_t)vx[k] & 7u);
+                uint32_t vox = leaf_offset(FMT, (uint32_t)vx[k] & 7u, (uint32_t)vy[k] & 7u, (uint32_t)vz[k] & 7u);
                 float t = leaf_value<FMT>(g.leaves, ok[k] ? (uint32_t)leaf[k] * 512u + vox : 0u);
                 v[k] = ok[k] ? t : g.background;
             }
@@ -238,7 +238,7 @@ __device__ __forceinline__ void grid_fetch(const GridView& g, const int (&vx)[T]
     if (!__any(any)) return;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
-        uint32_t vox = ((((uint32_t)vz[k] & 7u) * 8u + ((uint32_t)vy[k] & 7u)) * 8u) + ((uint32_t)vx[k] & 7u);
+        uint32_t vox = leaf_offset(FMT, (uint32_t)vx[k] & 7u, (uint32_t)vy[k] & 7u, (uint32_t)vz[k] & 7u);
         float t = leaf_value<FMT>(g.leaves, ok[k] ? (uint32_t)leaf[k] * 512u + vox : 0u);
         v[k] = ok[k] ? t : g.background;
     }
@@ -521,8 +521,8 @@ __device__ __forceinline__ float det_taps(const GridView& g, const int (&base)[3
         inx[k] = (unsigned)vx < (unsigned)g.dx;
         iny[k] = (unsigned)vy < (unsigned)g.dy;
         inz[k] = (unsigned)vz < (unsigned)g.dz;
-        oy[k] = (uint32_t)(vy & 7) * 8u;
-        oz[k] = (uint32_t)(vz & 7) * 64u;
+        oy[k] = leaf_oy(FMT, (uint32_t)(vy & 7));
+        oz[k] = leaf_oz(FMT, (uint32_t)(vz & 7));
     }
     // A row's taps are read as one window of two aligned chunks along x
     // (16 bytes each: half a leaf row of binary32, a whole row of 16-bit
@@ -537,6 +537,7 @@ __device__ __forceinline__ float det_taps(const GridView& g, const int (&base)[3
     const uint32_t xo0 = (uint32_t)(base[0] & 7 & ~(CV - 1));   // first chunk's offset in its leaf row
     const bool c1b = xo0 + CV == 8;                             // second chunk in the x-neighbour leaf
     const uint32_t xo1 = c1b ? 0u : xo0 + CV;
+    const uint32_t ox0 = leaf_ox(FMT, xo0), ox1 = leaf_ox(FMT, xo1);   // the chunks' places in the leaf
     const bool two = p + NT > CV;
     const char* __restrict__ leaves = reinterpret_cast<const char*>(g.leaves);
     // the leaves as values, so that selecting a row's pair stays a register
@@ -560,8 +561,8 @@ __device__ __forceinline__ float det_taps(const GridView& g, const int (&base)[3
             // the second half of the rows is addressed after the first half
             // is summed: half the loads in flight, half the registers
             const float gate = 2 * cz < NT ? 0.0f : acc;
-            const uint32_t a0 = vgpr_u32_after(ok0 ? ((uint32_t)la * 512u + roff + xo0) * TB : 0u, gate);
-            const uint32_t a1 = vgpr_u32_after((ok1 && two) ? ((uint32_t)l1 * 512u + roff + xo1) * TB : 0u, gate);
+            const uint32_t a0 = vgpr_u32_after(ok0 ? ((uint32_t)la * 512u + roff + ox0) * TB : 0u, gate);
+            const uint32_t a1 = vgpr_u32_after((ok1 && two) ? ((uint32_t)l1 * 512u + roff + ox1) * TB : 0u, gate);
             const Chunk v0 = *reinterpret_cast<const Chunk*>(leaves + a0);
             const Chunk v1 = *reinterpret_cast<const Chunk*>(leaves + a1);
             float t[NT];
@@ -753,7 +754,7 @@ __global__ __launch_bounds__(BLOCK) void k_grid_det_staged(GridView g, const flo
             const int32_t lf = slot_leaf[((vz >> 3) - l0[2]) * nl[1] * nl[0] + ((vy >> 3) - l0[1]) * nl[0] +
                                          (vx >> 3) - l0[0]];
             tile[v] = (lf >= 0 && in_domain(g, vx, vy, vz))
-                          ? load_texel<FMT>(g.leaves, (int64_t)lf * 512 + (((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7)))
+                          ? load_texel<FMT>(g.leaves, (int64_t)lf * 512 + leaf_offset(FMT, vx & 7, vy & 7, vz & 7))
                           : g.background;
             x += sx;
             y += sy;

@@ -314,7 +314,28 @@ stf_status stf_create_sparse_grid3d(int32_t dim_x, int32_t dim_y, int32_t dim_z,
     size_t leaf_bytes = (size_t)n_leaves * 512 * stf::fmt_bytes(fmt);
     stf_status s = upload(&t->grid_alloc[0], root.data(), root.size() * 4, "grid root");
     if (s == STF_OK) s = upload(&t->grid_alloc[1], nodes.empty() ? nullptr : nodes.data(), nodes.size() * 4, "grid nodes");
-    if (s == STF_OK) s = upload(&t->grid_alloc[2], n_leaves ? leaf_values_host : nullptr, leaf_bytes, "grid leaves");
+    if (s == STF_OK && n_leaves) {
+        // each leaf's values from x-fastest order into its bricks (leaf_offset)
+        const int tb = stf::fmt_bytes(fmt);
+        std::vector<uint8_t> bricked;
+        try {
+            bricked.resize(leaf_bytes);
+        } catch (const std::bad_alloc&) {
+            free_texture(t);
+            return stf_fail(STF_E_OOM, "host allocation of %zu bytes failed", leaf_bytes);
+        }
+        uint32_t where[512];
+        for (uint32_t v = 0; v < 512; ++v) where[v] = stf::leaf_offset(fmt, v & 7u, (v >> 3) & 7u, v >> 6);
+        const uint8_t* src = static_cast<const uint8_t*>(leaf_values_host);
+        for (int64_t k = 0; k < n_leaves; ++k) {
+            const uint8_t* ls = src + (size_t)k * 512 * tb;
+            uint8_t* ld = bricked.data() + (size_t)k * 512 * tb;
+            for (uint32_t v = 0; v < 512; ++v) memcpy(ld + (size_t)where[v] * tb, ls + (size_t)v * tb, tb);
+        }
+        s = upload(&t->grid_alloc[2], bricked.data(), leaf_bytes, "grid leaves");
+    } else if (s == STF_OK) {
+        s = upload(&t->grid_alloc[2], nullptr, 0, "grid leaves");
+    }
     if (s != STF_OK) {
         free_texture(t);
         return s;
