@@ -611,13 +611,13 @@ __device__ __forceinline__ float det_unscale(float acc)
 
 // Deterministic filtering from global memory, one query per thread, at 8
 // waves per SIMD (64 VGPRs) where that fits without spilling, else 7 (72
-// VGPRs; binary32 B-spline and Keys): the dependent leaf walks of
+// VGPRs; the binary32 cubics): the dependent leaf walks of
 // empty-space queries need the waves to hide their latency, and the tap rows
 // of a query are loaded in two halves to fit.
 template <int FMT, int KIND>
 constexpr int det_waves()
 {
-    return (FMT == F32 && (KIND == KIND_BSPLINE || KIND == KIND_KEYS)) ? 7 : 8;
+    return (FMT == F32 && KIND != KIND_LINEAR) ? 7 : 8;
 }
 
 template <int FMT, int KIND>
