@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the headline kernel (stochastic tricubic, binary32
 # grid, ray order), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain
 # copy; to be re-measured (and set to None) whenever that kernel changes.
-HEADLINE_TRAFFIC_BYTES = {("f32", "ray"): 389.1e6}
+HEADLINE_TRAFFIC_BYTES = {("f32", "ray"): 378.5e6}
 # the same for the DCT workload's stochastic bilinear kernel over the 4K frame
 # (uv in, 9 results out; the 12.6 MB of blocks mostly cache-resident)
 DCT_STOCH_LINEAR_TRAFFIC_BYTES = 412.1e6
