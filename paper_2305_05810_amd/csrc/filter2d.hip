@@ -370,10 +370,24 @@ __device__ __forceinline__ int block_reduce_min(int v, int* red)
     return r;
 }
 
+// Discrete Gaussian weights of the 4x4 window i-1..i+2 (binary64, unnormalised).
+__device__ __forceinline__ void gauss_discrete_weights(double t, double inv2s2, double (&w)[4])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double d = (double)(k - 1) - t;
+        w[k] = exp(-(d * d) * inv2s2);
+    }
+}
+
+// The discrete Gaussian mean (normalised 4x4 window) as a staged kind.
+constexpr int KIND_GAUSS_MEAN = 100;
+
 template <class Src, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_tex2d_det_staged(Src S, const float* __restrict__ q, int32_t n,
                                                             float* __restrict__ out, const int32_t* __restrict__ order,
-                                                            int scatter, unsigned long long* __restrict__ counters)
+                                                            int scatter, unsigned long long* __restrict__ counters,
+                                                            float sigma)
 {
     constexpr int NT = KIND == KIND_LINEAR ? 2 : 4;
     constexpr int CAP = Src::CAP;
@@ -391,8 +405,25 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_det_staged(Src S, const float* 
     float tx = 0.0f, ty = 0.0f;
     const bool ok = cell_of(x, cx, tx) & cell_of(y, cy, ty);
     float wx[4], wy[4];
-    cx += axis_weights_scaled<KIND>(tx, wx);
-    cy += axis_weights_scaled<KIND>(ty, wy);
+    if constexpr (KIND == KIND_GAUSS_MEAN) {
+        // as k_tex2d_gauss's discrete mean: binary64 weights, normalised, in binary32
+        const double sg = (double)sigma, inv2s2 = 1.0 / (2.0 * sg * sg);
+        const double xe = (double)x, ye = (double)y;
+        double dx[4], dy[4];
+        gauss_discrete_weights(xe - floor(xe), inv2s2, dx);
+        gauss_discrete_weights(ye - floor(ye), inv2s2, dy);
+        const double nx = ((dx[0] + dx[1]) + dx[2]) + dx[3], ny = ((dy[0] + dy[1]) + dy[2]) + dy[3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            wx[k] = (float)(dx[k] / nx);
+            wy[k] = (float)(dy[k] / ny);
+        }
+        cx -= 1;
+        cy -= 1;
+    } else {
+        cx += axis_weights_scaled<KIND>(tx, wx);
+        cy += axis_weights_scaled<KIND>(ty, wy);
+    }
     // box of the clamped taps of the block's queries (clamping is monotone)
     const bool in = live && ok;
     const int W1 = S.w() - 1, H1 = S.h() - 1;
@@ -552,15 +583,6 @@ constexpr int GAUSS_MAX_TAPS = 52;   // 2 R + 2 for sigma <= 4 (GAUSS_FIS_MEAN)
 __device__ __forceinline__ double gauss_phi(double z)
 {
     return 0.5 * erfc(-z * 0.70710678118654752440);
-}
-
-__device__ __forceinline__ void gauss_discrete_weights(double t, double inv2s2, double (&w)[4])
-{
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double d = (double)(k - 1) - t;
-        w[k] = exp(-(d * d) * inv2s2);
-    }
 }
 
 __device__ __forceinline__ int gauss_pick(const double (&m)[4], double u)
@@ -772,7 +794,7 @@ void launch2d_kind(const Src& S, const float* q, int32_t n, int mode, uint32_t k
             // decodes its tap box once when the box is small enough (the
             // kernel decides per block and otherwise decodes per tap)
             hipLaunchKernelGGL((k_tex2d_det_staged<Src, KIND>), grid, block, 0, stream, S, q, n, out, order, scatter,
-                               stage_counters());
+                               stage_counters(), 0.0f);
             return;
         }
         hipLaunchKernelGGL((k_tex2d_deterministic<Src, KIND>), grid, block, 0, stream, S, q, n, out, order, scatter);
@@ -882,8 +904,12 @@ hipError_t gauss2d_src(const Src& S, const float* q, int32_t n, float sigma, int
                            out, idx);
         break;
     case GAUSS_DISCRETE_MEAN:
-        hipLaunchKernelGGL((k_tex2d_gauss<Src, GAUSS_DISCRETE_MEAN>), grid, block, 0, stream, S, q, n, sigma, radius,
-                           key, out, idx);
+        if constexpr (Src::DECODES)   // decoded sources: each block decodes its taps' box once (when it pays)
+            hipLaunchKernelGGL((k_tex2d_det_staged<Src, KIND_GAUSS_MEAN>), grid, block, 0, stream, S, q, n, out,
+                               nullptr, 0, stage_counters(), sigma);
+        else
+            hipLaunchKernelGGL((k_tex2d_gauss<Src, GAUSS_DISCRETE_MEAN>), grid, block, 0, stream, S, q, n, sigma,
+                               radius, key, out, idx);
         break;
     default: return hipErrorInvalidValue;
     }

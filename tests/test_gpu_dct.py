@@ -214,3 +214,41 @@ def test_dct_frame_order_staged_decode(dev, fname, gf, of):
     dscale, _ = oracle.filter2d(A, oracle.F32, uv, of, oracle.DET_ABS)
     assert np.all(np.abs(gd - od) <= REL * dscale), fname
     t.destroy()
+
+
+@pytest.mark.parametrize("sigma", [0.3, 0.8])
+def test_dct_gaussian_discrete_mean_staged(dev, sigma):
+    """The discrete Gaussian mean (normalised 4x4 window) of a DCT texture over
+    a frame in pixel order: every block decodes its taps' box once into LDS;
+    shuffled, no block stages; both give the same bits and meet the oracle's
+    bar (1e-6 of sum |w| A over the window; the weights are positive)."""
+    sigma = float(np.float32(sigma))
+    W, H, C = 96, 80, 9
+    tex = _texture(H, W, C, seed=W + 13)
+    words = stf.stf_dct_encode(tex)
+    t = stf.stf_create_dct_texture2d(W, H, C, words)
+    fw, fh = 4 * W, 4 * H
+    ys, xs = np.mgrid[0:fh, 0:fw]
+    uv = np.stack([(xs + 0.29) / fw, (ys + 0.53) / fh], axis=-1).reshape(-1, 2).astype(np.float32)
+    perm = np.random.default_rng(14).permutation(uv.shape[0])
+    n = uv.shape[0]
+    res = {}
+
+    def run(key, u):
+        o = torch.empty((n, C), dtype=torch.float32, device=dev)
+        stf.stf_filter_gaussian(t, torch.from_numpy(u).to(dev), sigma, stf.STF_GAUSS_DISCRETE_MEAN, 0, o)
+        res[key] = o
+
+    staged, blocks = _staged(lambda: run("f", uv))
+    assert staged == blocks == n // 256, (staged, blocks)
+    staged, blocks = _staged(lambda: run("s", uv[perm]))
+    assert staged == 0 and blocks == n // 256, (staged, blocks)
+    back = torch.empty_like(res["s"])
+    back[torch.from_numpy(perm).to(dev)] = res["s"]
+    assert torch.equal(res["f"], back)
+    gd = res["f"].cpu().numpy().astype(np.float64)
+    od, _ = oracle.dct_gauss_filter2d(words, uv, sigma, oracle.G_DISCRETE_MEAN)
+    A = _abs_terms(words).astype(np.float32)
+    dscale, _ = oracle.gauss_filter2d(A, oracle.F32, uv, sigma, oracle.G_DISCRETE_MEAN)
+    assert np.all(np.abs(gd - od) <= REL * dscale + 1e-12)
+    t.destroy()
