@@ -126,22 +126,41 @@ __device__ __forceinline__ float ewa_weight(const Ellipse& e, const float* lut, 
     return lut_weight(lut, (e.A * (ss * ss) + (e.B * ss) * tt) + e.C * (tt * tt));
 }
 
+// The EWA mean of one level: sum w t / sum w over the taps of the box with
+// w > 0, two rows at a time (a column's A ss^2 and B ss serve both rows;
+// every weight keeps its order of operations, the sums interleave the two
+// rows' taps).
 template <int FMT, int C>
 __device__ __forceinline__ void ewa_mean(const TexLevel& L, const Ellipse& e, const float* lut, float (&v)[C])
 {
     float acc[C], wsum = 0.0f;
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-    for (int it = e.t0; it <= e.t1; ++it)
+    for (int it = e.t0; it <= e.t1; it += 2) {
+        const bool two = it + 1 <= e.t1;
+        const float ta = (float)it - e.sty, tb = (float)(it + 1) - e.sty;
+        const float ca = e.C * (ta * ta), cb = e.C * (tb * tb);
         for (int is = e.s0; is <= e.s1; ++is) {
-            const float w = ewa_weight(e, lut, is, it);
-            if (!(w > 0.0f)) continue;
-            float t[C];
-            texel<FMT, C>(L, is, it, t);
-            wsum += w;
+            const float ss = (float)is - e.stx;
+            const float P = e.A * (ss * ss), Q = e.B * ss;
+            const float wa = lut_weight(lut, (P + Q * ta) + ca);
+            const float wb = two ? lut_weight(lut, (P + Q * tb) + cb) : 0.0f;
+            if (wa > 0.0f) {
+                float t[C];
+                texel<FMT, C>(L, is, it, t);
+                wsum += wa;
 #pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] = __builtin_fmaf(w, t[c], acc[c]);
+                for (int c = 0; c < C; ++c) acc[c] = __builtin_fmaf(wa, t[c], acc[c]);
+            }
+            if (wb > 0.0f) {
+                float t[C];
+                texel<FMT, C>(L, is, it + 1, t);
+                wsum += wb;
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] = __builtin_fmaf(wb, t[c], acc[c]);
+            }
         }
+    }
 #pragma unroll
     for (int c = 0; c < C; ++c) v[c] = acc[c] / wsum;
 }
