@@ -36,13 +36,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the headline kernel (stochastic tricubic, binary32
-# grid, ray order), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain
-# copy; to be re-measured (and set to None) whenever that kernel changes.
-HEADLINE_TRAFFIC_BYTES = {("f32", "ray"): 378.5e6}
-# the same for the DCT workload's stochastic bilinear kernel over the 4K frame
-# (uv in, 9 results out; the 12.6 MB of blocks mostly cache-resident)
-DCT_STOCH_LINEAR_TRAFFIC_BYTES = 412.1e6
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a
+# plain copy, each with the sha256 (first 16 hex digits) of the kernel
+# sources the counters were taken on: a figure whose sources have changed
+# since is reported as null until the counters are taken again.
+KERNEL_SOURCES = {
+    "grid": ["filter3d.hip", "device_common.h", "interp.h", "stf_internal.h"],
+    "tex2d": ["filter2d.hip", "dct_decode.h", "device_common.h", "interp.h", "stf_internal.h"],
+}
+# the headline kernel (stochastic tricubic, binary32 grid, ray order)
+HEADLINE_TRAFFIC = {("f32", "ray"): (378.5e6, "grid", "613e7b250b4e1410")}
+# the DCT workload's stochastic bilinear kernel over the 4K frame (uv in, 9
+# results out; the 12.6 MB of blocks mostly cache-resident)
+DCT_STOCH_LINEAR_TRAFFIC = (412.2e6, "tex2d", "7d1317b050bfcc50")
+
+
+def sources_sha(kind):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, "paper_2305_05810_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(entry):
+    """The recorded traffic of a kernel, or None if its sources changed since."""
+    if entry is None:
+        return None
+    nbytes, kind, sha = entry
+    if sources_sha(kind) != sha:
+        log(f"traffic figure not reported: the {kind} kernel sources changed since the counters were taken")
+        return None
+    return nbytes
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 METRIC = "filtered lookups/s, stochastic vs deterministic tricubic, at stated error; p99 batch latency"
@@ -303,7 +329,7 @@ def run_grid(args, torch, stf, synth):
         "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": args.traffic if args.traffic is not None
-                     else HEADLINE_TRAFFIC_BYTES.get((args.fmt, args.order))},
+                     else measured_traffic(HEADLINE_TRAFFIC.get((args.fmt, args.order)))},
         "cpu_baseline": cpu,
     })
     tex.destroy()
@@ -500,7 +526,7 @@ def run_dct(args, torch, stf, synth):
                  # a cache-resident 12.6 MB table, as the grid's tree nodes are
                  "roofline": {"bound": "hbm", "achieved": stream_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": stream_gbs / HBM_PEAK_GBS, "stream_bytes_per_lookup": stream_b,
-                              "traffic": DCT_STOCH_LINEAR_TRAFFIC_BYTES},
+                              "traffic": measured_traffic(DCT_STOCH_LINEAR_TRAFFIC)},
                  "cpu_baseline": None})
     tex.destroy()
     return line
