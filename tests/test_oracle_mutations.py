@@ -14,6 +14,7 @@ import pytest
 import oracle
 from oracle import build as oracle_build
 import test_oracle_pins as pins
+import test_oracle_shade as shade_pins
 
 ORACLE_DIR = os.path.dirname(oracle.__file__)
 
@@ -52,6 +53,16 @@ MUTATIONS = {
         "oracle.c", [("c[1] = c[0] + (4.0f + (3.0f * (t * t)) * (t - 2.0f)) * K6;",
                       "c[1] = (4.0f + (3.0f * (t * t)) * (t - 2.0f)) * K6;")],
         pins.test_cubic_breakpoints_known_answers),
+    "material_normal_components_swapped": (
+        "shade.c", [("    out[4] = orc_h2d(hx);\n    out[5] = orc_h2d(hy);", "    out[4] = orc_h2d(hy);\n    out[5] = orc_h2d(hx);")],
+        lambda: shade_pins.test_material_source_stochastic_reads_the_decoded_texel(oracle.CUBIC)),
+    "material_unorm_over_256": (
+        "shade.c", [("out[0] = texel[0] / 255.0;", "out[0] = texel[0] / 256.0;")],
+        lambda: shade_pins.test_material_source_stochastic_reads_the_decoded_texel(oracle.LINEAR)),
+    "material_texels_transposed": (
+        "oracle.c", [("orc_material_decode((const uint8_t*)s->tex + 8 * ((int64_t)y * s->W + x), m);",
+                      "orc_material_decode((const uint8_t*)s->tex + 8 * ((int64_t)x * s->H + y), m);")],
+        lambda: shade_pins.test_material_source_deterministic_matches_decoded_texture(oracle.CUBIC)),
     "cubic_taps_not_centred": (
         "oracle.c", [("    int j = (u >= c[0]) + (u >= c[1]) + (u >= c[2]);\n    return j - 1;",
                       "    int j = (u >= c[0]) + (u >= c[1]) + (u >= c[2]);\n    return j;")],
