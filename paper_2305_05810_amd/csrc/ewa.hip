@@ -18,6 +18,11 @@
 //    < 1 weigh LUT[min(floor(128 r2), 127)], LUT[i] = exp(-2 i/127) -
 //    exp(-2).  The stochastic tap: a row by weighted reservoir sampling over
 //    the row sums, then a tap of the row by the cumulative rule (ewa_draw).
+//    The kernels keep 128 A, 128 B and 128 C, so that each tap forms 128 r2
+//    directly: every operation's result is 128 times the unscaled one,
+//    exactly (the scale is a power of two, and no intermediate comes near the
+//    subnormal or overflow range on a scanned level, where the coefficients
+//    are at most 1 in magnitude and the box at most a few hundred texels).
 //  - A zero footprint reads bilinearly from level 0 (stochastic: the linear
 //    draw with hash indices 2, 3).  The pyramid ends at one texel, and a
 //    level at or past that last one yields that texel (pbrt's rule): the
@@ -37,7 +42,7 @@ using namespace stf;
 namespace {
 
 constexpr int BLOCK = 256;
-constexpr int LUT_SIZE = 128;
+constexpr int LUT_SIZE = 129;   // 128 weights, then +0 for taps outside the ellipse
 
 struct EwaLevels {
     TexLevel level[STF_MAX_LEVELS];
@@ -51,7 +56,8 @@ struct EwaLut {
 EwaLut make_lut()
 {
     EwaLut L;
-    for (int i = 0; i < LUT_SIZE; ++i) L.v[i] = (float)(std::exp(-2.0 * i / 127.0) - std::exp(-2.0));
+    for (int i = 0; i < 128; ++i) L.v[i] = (float)(std::exp(-2.0 * i / 127.0) - std::exp(-2.0));
+    L.v[128] = 0.0f;
     return L;
 }
 
@@ -101,23 +107,26 @@ __device__ __forceinline__ Ellipse ellipse(const TexLevel& L, float s, float t, 
     e.s1 = (int)floorf(e.stx + 2.0f * invDet * us);
     e.t0 = (int)ceilf(e.sty - 2.0f * invDet * vs);
     e.t1 = (int)floorf(e.sty + 2.0f * invDet * vs);
-    e.A = A;
-    e.B = B;
-    e.C = C;
+    e.A = A * 128.0f;   // exact: the taps form 128 r2
+    e.B = B * 128.0f;
+    e.C = C * 128.0f;
     return e;
 }
 
-// The weight of a tap whose quadratic form is r2, without a branch: the LUT
-// index is clamped to 0..127 (r2 is never negative beyond rounding, NaN
-// converts to 0) and read for every tap, then taps outside the ellipse
-// select 0.  Every LUT entry is >= +0, so adding a weight of +0 leaves a
-// running sum's bits unchanged.
-__device__ __forceinline__ float lut_weight(const float* lut, float r2)
+// The weight of a tap whose quadratic form is r2, given r2s = 128 r2, without
+// a branch: min(r2s, 128) (NaN gives 128), then max with 0 (r2 is never
+// negative beyond rounding; trunc of a value in (-1, 0) is 0 as well),
+// truncated: 0..127 inside the ellipse, 128 -- the entry +0 -- outside.
+// Every LUT entry is >= +0, so adding a weight of +0 leaves a running sum's
+// bits unchanged.
+__device__ __forceinline__ int lut_index(float r2s)
 {
-    int idx = (int)(r2 * 128.0f);
-    idx = idx > 127 ? 127 : (idx < 0 ? 0 : idx);
-    const float w = lut[idx];
-    return r2 < 1.0f ? w : 0.0f;
+    return (int)fmaxf(fminf(r2s, 128.0f), 0.0f);
+}
+
+__device__ __forceinline__ float lut_weight(const float* lut, float r2s)
+{
+    return lut[lut_index(r2s)];
 }
 
 __device__ __forceinline__ float ewa_weight(const Ellipse& e, const float* lut, int is, int it)
@@ -190,13 +199,39 @@ __device__ __forceinline__ void ewa_draw(const Ellipse& e, const float* lut, uin
     for (int it = e.t0; it <= e.t1; it += 2) {
         const float ta = (float)it - e.sty, tb = (float)(it + 1) - e.sty;
         const float ca = e.C * (ta * ta), cb = e.C * (tb * tb);
+        // Two columns at a time, software-pipelined: the LUT indices of the
+        // next pair of columns are formed while this pair's four LDS reads
+        // are in flight.  A column past the box gets P = +inf, hence the
+        // weight +0, which leaves the sums' bits unchanged.
+        auto indices = [&](int is, int (&k)[4]) {
+            const float ss0 = (float)is - e.stx, ss1 = (float)(is + 1) - e.stx;
+            const float P0 = is <= e.s1 ? e.A * (ss0 * ss0) : __builtin_inff(), Q0 = e.B * ss0;
+            const float P1 = is + 1 <= e.s1 ? e.A * (ss1 * ss1) : __builtin_inff(), Q1 = e.B * ss1;
+            k[0] = lut_index((P0 + Q0 * ta) + ca);
+            k[1] = lut_index((P0 + Q0 * tb) + cb);
+            k[2] = lut_index((P1 + Q1 * ta) + ca);
+            k[3] = lut_index((P1 + Q1 * tb) + cb);
+        };
+        int k[4];
+        indices(e.s0, k);
+        float w0 = lut[k[0]], w1 = lut[k[1]], w2 = lut[k[2]], w3 = lut[k[3]];
         float Ra = 0.0f, Rb = 0.0f;
-        for (int is = e.s0; is <= e.s1; ++is) {
-            const float ss = (float)is - e.stx;
-            const float P = e.A * (ss * ss), Q = e.B * ss;
-            Ra += lut_weight(lut, (P + Q * ta) + ca);   // +0 outside: same bits
-            Rb += lut_weight(lut, (P + Q * tb) + cb);
+        for (int is = e.s0 + 2; is <= e.s1; is += 2) {
+            int kn[4];
+            indices(is, kn);
+            Ra += w0;   // column is - 2, then is - 1, of each row: scan order
+            Rb += w1;
+            Ra += w2;
+            Rb += w3;
+            w0 = lut[kn[0]];
+            w1 = lut[kn[1]];
+            w2 = lut[kn[2]];
+            w3 = lut[kn[3]];
         }
+        Ra += w0;
+        Rb += w1;
+        Ra += w2;
+        Rb += w3;
         offer(it, Ra);
         if (it + 1 <= e.t1) offer(it + 1, Rb);
     }
