@@ -250,7 +250,10 @@ stf_status stf_filter_gaussian(const stf_texture* tex, const float* queries_dev,
  *     draw with hash indices 2, 3); taps are clamped.
  * Work per query is bounded: the ellipse is scanned only where its minor
  * axis spans fewer than 4 texels, so its box holds O(max_anisotropy) taps.
- * Queries with a non-finite or |value| >= 65536 entry give NaN.
+ * Queries with a non-finite or |value| >= 65536 entry give NaN, and so do
+ * queries whose raster position on level 0, s W0 - 1/2 or t H0 - 1/2 in
+ * binary32, is not below 2^24 in magnitude (as for every 2D filter; indices
+ * INT32_MIN).
  * max_anisotropy in [1, 64] (the real-time implementation's maximum).
  * out_index_dev: NULL or (stochastic) n x 3 int32 (x, y, level).  Binary32
  * accumulation. */

@@ -1208,6 +1208,9 @@ int orc_gauss_fis_positions(int W, int H, const float* uv, int64_t n, double sig
 /*   scaled by longer / (shorter * max_aniso).  Binary32, each operation      */
 /*   rounded once (lengths sqrt(x*x + y*y)).  shorter == 0: bilinear on      */
 /*   level 0 (stochastic: the pinned linear draw with hash indices 2, 3).    */
+/*   A record with a non-finite entry, an entry of magnitude >= 65536, or a  */
+/*   level-0 raster position (s W0 - 0.5, t H0 - 0.5) of magnitude >= 2^24   */
+/*   (the bound of every 2D filter) yields NaN.                              */
 /*   Level of detail lod = max(0, (levels - 1) + log2(shorter)) in binary64; */
 /*   deterministic: lerp(lod - floor(lod), EWA(floor), EWA(floor + 1));       */
 /*   stochastic: level floor(lod) + [u0 < lod - floor(lod)] (hash index 0).  */
@@ -1486,6 +1489,11 @@ int orc_ewa_filter2d_at(const void* const* level_texels, const int* W, const int
         int32_t* ix = idx ? idx + 3 * k : NULL;
         int ok = 1;
         for (int j = 0; j < 6; ++j) ok &= isfinite(qk[j]) && fabsf(qk[j]) < 65536.0f;
+        if (ok) {   /* the raster bound of every 2D filter, on level 0 (the coarser levels' positions are no larger) */
+            float x0, y0;
+            orc_raster2d(qk, W[0], H[0], &x0, &y0);
+            ok = fabsf(x0) < 16777216.0f && fabsf(y0) < 16777216.0f;
+        }
         if (!ok) { orc_nan_out(o, C, ix, 3); continue; }
         float d0[2], d1[2], sh;
         double lod = orc_ewa_axes(qk, levels, max_aniso, d0, d1, &sh);

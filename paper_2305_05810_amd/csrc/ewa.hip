@@ -252,15 +252,20 @@ __device__ __forceinline__ void ewa_draw(const Ellipse& e, const float* lut, uin
 // Loads query i and forms its axes (binary32): the longer derivative is d0,
 // the shorter d1 is raised to |d0| / max_aniso when it is shorter than that
 // (and not zero); sh = |d1|.  False for a record with a non-finite entry or
-// one of magnitude >= 65536.
-__device__ __forceinline__ bool ewa_axes(const float* __restrict__ q, int32_t i, float max_aniso, float (&r)[6],
-                                         float (&d0)[2], float (&d1)[2], float& sh)
+// one of magnitude >= 65536, and for one whose raster position on level 0
+// (s W0 - 1/2, t H0 - 1/2) is not below 2^24 in magnitude, the bound of
+// every 2D filter: the coarser levels' positions are no larger, so every
+// cell, box bound and tap column of the query fits an int.
+__device__ __forceinline__ bool ewa_axes(const float* __restrict__ q, int32_t i, const TexLevel& L0,
+                                         float max_aniso, float (&r)[6], float (&d0)[2], float (&d1)[2], float& sh)
 {
 #pragma unroll
     for (int j = 0; j < 6; ++j) r[j] = q[6 * (int64_t)i + j];
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < 6; ++j) ok = ok && (__builtin_fabsf(r[j]) < 65536.0f);
+    ok = ok && __builtin_fabsf(r[0] * (float)L0.w - 0.5f) < 16777216.0f &&
+         __builtin_fabsf(r[1] * (float)L0.h - 0.5f) < 16777216.0f;
     if (!ok) return false;
     d0[0] = r[2]; d0[1] = r[3];
     d1[0] = r[4]; d1[1] = r[5];
@@ -323,7 +328,7 @@ __global__ __launch_bounds__(BLOCK) void k_ewa_det(EwaLevels P, EwaLut lut_in, c
     if (i >= n) return;
     float r[6], d0[2], d1[2], sh = 0.0f;
     float v[C];
-    if (!ewa_axes(q, i, max_aniso, r, d0, d1, sh)) {
+    if (!ewa_axes(q, i, P.level[0], max_aniso, r, d0, d1, sh)) {
 #pragma unroll
         for (int c = 0; c < C; ++c) v[c] = __builtin_nanf("");
     } else if (!(sh > 0.0f)) {
@@ -426,7 +431,7 @@ __global__ __launch_bounds__(BLOCK) void k_ewa_stoch(EwaLevels P, EwaLut lut_in,
         float r[6], d0[2], d1[2], sh = 0.0f;
         float v[C];
         int ix[3] = {BAD_INDEX, BAD_INDEX, BAD_INDEX};
-        if (!ewa_axes(q, i, max_aniso, r, d0, d1, sh)) {
+        if (!ewa_axes(q, i, P.level[0], max_aniso, r, d0, d1, sh)) {
 #pragma unroll
             for (int c = 0; c < C; ++c) v[c] = __builtin_nanf("");
         } else {

@@ -125,3 +125,49 @@ def test_ewa_footprints_larger_than_the_texture(dev, mode):
         top = lv[-1][0, 0].astype(np.float32) / np.float32(255)
         assert np.array_equal(out.cpu().numpy()[scale >= 2.0], np.broadcast_to(top, (int((scale >= 2.0).sum()), 4)))
     t.destroy()
+
+
+@pytest.mark.parametrize("mode", ["stoch", "det"])
+def test_ewa_raster_bound(dev, mode):
+    # Records around the level-0 raster bound 2^24 (s up to +-40000 on a
+    # 512-wide level 0, zero and small footprints, plus s spread over
+    # 32000..33000 where the bound falls): NaN and the bad index beyond it,
+    # the oracle's values and indices inside it.
+    rng = np.random.default_rng(8)
+    base = rng.integers(0, 256, (64, 512, 4), dtype=np.uint8)
+    lv = synth.mip_levels(base)
+    t = stf.stf_create_texture2d(512, 64, 4, stf.STF_FMT_U8, lv)
+    rows = []
+    for s in (32768.0, 32767.998046875, 40000.0, 30000.0):
+        for sign in (1.0, -1.0):
+            rows.append([sign * s, 0.25, 0.0, 0.0, 0.0, 0.0])
+            rows.append([sign * s, 0.25, 3.0 / 512, 1.0 / 512, -0.5 / 512, 1.5 / 512])
+    m = 2048
+    far = np.zeros((m, 6), np.float32)
+    far[:, 0] = rng.uniform(32000.0, 33000.0, m) * rng.choice([-1.0, 1.0], m)
+    far[:, 1] = rng.random(m)
+    far[:, 2:] = rng.normal(0.0, 2.0 / 512, (m, 4)) * (rng.random((m, 1)) < 0.75)
+    q = np.concatenate([np.array(rows, np.float32), far.astype(np.float32)])
+    n = q.shape[0]
+    x0 = q[:, 0] * np.float32(512) - np.float32(0.5)
+    beyond = np.abs(x0) >= np.float32(2.0 ** 24)
+    assert 100 < beyond.sum() < n - 100
+    qd = torch.from_numpy(q).to(dev)
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    if mode == "stoch":
+        idx = torch.empty((n, 3), dtype=torch.int32, device=dev)
+        stf.stf_filter_ewa(t, qd, 8.0, stf.STF_STOCHASTIC, 6, out, idx)
+        ov, oi = oracle.ewa_filter2d(lv, oracle.U8, q, 8.0, oracle.STOCH, seed=6)
+        gi = idx.cpu().numpy()
+        assert np.array_equal(gi, oi)
+        assert np.all(gi[beyond] == oracle.BAD_INDEX)
+        gv = out.cpu().numpy()
+        assert np.array_equal(np.isnan(gv), np.isnan(ov)) and np.all(np.isnan(gv[beyond]))
+        assert np.array_equal(gv[~beyond], ov[~beyond].astype(np.float32))
+    else:
+        stf.stf_filter_ewa(t, qd, 8.0, stf.STF_DETERMINISTIC, 0, out)
+        od, _ = oracle.ewa_filter2d(lv, oracle.U8, q, 8.0, oracle.DET)
+        gd = out.cpu().numpy().astype(np.float64)
+        assert np.array_equal(np.isnan(gd), np.isnan(od)) and np.all(np.isnan(gd[beyond]))
+        assert np.all(np.abs(gd[~beyond] - od[~beyond]) <= 1e-6 * np.abs(od[~beyond]) + 1e-12)
+    t.destroy()

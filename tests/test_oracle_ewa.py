@@ -118,3 +118,41 @@ def test_argument_checks(pyramid):
     q[0, 0] = np.nan
     v, idx = oracle.ewa_filter2d(pyramid, oracle.F32, q, 8.0, oracle.STOCH)
     assert np.all(np.isnan(v)) and np.all(idx == oracle.BAD_INDEX)
+
+
+def _far_records():
+    """EWA records on a 512-texel-wide level 0 around the raster bound 2^24:
+    s = 32768 gives s W0 - 1/2 = 2^24 - 1/2, which binary32 rounds (to even)
+    to 2^24 itself, so the record is out; the next float below, 32767.998046875,
+    gives 16777214.5 -> 16777214, which is in, while its mirror gives
+    -16777215.5 -> -2^24 (ties to even), which is out.  Each s comes with a
+    zero footprint and with a small ellipse, and mirrored to -s."""
+    rows = []
+    for s in (32768.0, 32767.998046875, 40000.0, 30000.0):
+        for sign in (1.0, -1.0):
+            rows.append([sign * s, 0.25, 0.0, 0.0, 0.0, 0.0])
+            rows.append([sign * s, 0.25, 3.0 / 512, 1.0 / 512, -0.5 / 512, 1.5 / 512])
+    q = np.array(rows, np.float32)
+    x0 = q[:, 0] * np.float32(512) - np.float32(0.5)          # binary32, as the filters form it
+    return q, np.abs(x0) >= np.float32(2.0 ** 24)
+
+
+def test_raster_bound_on_level_zero():
+    # A record whose level-0 raster position is 2^24 or more in magnitude has
+    # no integer cell (the rule of every 2D filter) and yields NaN with the
+    # bad index, whichever level it would draw; positions just inside the
+    # bound filter normally (on a constant texture: the constant; the taps
+    # clamp to the edge column of their level).
+    lv = synth.mip_levels(np.full((16, 512, 1), 0.625, np.float32))
+    q, out = _far_records()
+    assert out.tolist() == [True] * 4 + [False] * 2 + [True] * 6 + [False] * 4
+    for mode in (oracle.DET, oracle.STOCH):
+        v, idx = oracle.ewa_filter2d(lv, oracle.F32, q, 8.0, mode, seed=4)
+        assert np.all(np.isnan(v[out])) and not np.any(np.isnan(v[~out]))
+        assert np.all(v[~out] == 0.625)
+        if mode == oracle.STOCH:
+            assert np.all(idx[out] == oracle.BAD_INDEX)
+            ok = idx[~out]
+            w_l = np.array([max(1, 512 >> int(l)) for l in ok[:, 2]])
+            right = q[~out, 0] > 0
+            assert np.all(ok[right, 0] == w_l[right] - 1) and np.all(ok[~right, 0] == 0)
