@@ -336,8 +336,8 @@ __global__ __launch_bounds__(BLOCK) void k_ewa_det(EwaLevels P, EwaLut lut_in, c
         const float x = r[0] * (float)T0.w - 0.5f, y = r[1] * (float)T0.h - 0.5f;
         int cx = 0, cy = 0;
         float tx = 0.0f, ty = 0.0f;
-        cell_of(x, cx, tx);
-        cell_of(y, cy, ty);
+        (void)cell_of(x, cx, tx);   // inside the raster bound ewa_axes checked
+        (void)cell_of(y, cy, ty);
         float a[C], b[C], c2[C], d[C];
         texel<FMT, C>(T0, cx, cy, a);
         texel<FMT, C>(T0, cx + 1, cy, b);
@@ -442,8 +442,8 @@ __global__ __launch_bounds__(BLOCK) void k_ewa_stoch(EwaLevels P, EwaLut lut_in,
                 const float x = r[0] * (float)T0.w - 0.5f, y = r[1] * (float)T0.h - 0.5f;
                 int cx = 0, cy = 0;
                 float tx = 0.0f, ty = 0.0f;
-                cell_of(x, cx, tx);
-                cell_of(y, cy, ty);
+                (void)cell_of(x, cx, tx);   // inside the raster bound ewa_axes checked
+                (void)cell_of(y, cy, ty);
                 ix[0] = clampi(cx + choose_linear(tx, axis_uniform(b, 2)), T0.w - 1);
                 ix[1] = clampi(cy + choose_linear(ty, axis_uniform(b, 3)), T0.h - 1);
                 ix[2] = 0;
