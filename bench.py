@@ -43,12 +43,16 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = {
     "grid": ["filter3d.hip", "device_common.h", "interp.h", "stf_internal.h"],
     "tex2d": ["filter2d.hip", "dct_decode.h", "device_common.h", "interp.h", "stf_internal.h"],
+    "ewa": ["ewa.hip", "device_common.h", "interp.h", "stf_internal.h"],
 }
 # the headline kernel (stochastic tricubic, binary32 grid, ray order)
 HEADLINE_TRAFFIC = {("f32", "ray"): (378.5e6, "grid", "613e7b250b4e1410")}
 # the DCT workload's stochastic bilinear kernel over the 4K frame (uv in, 9
 # results out; the 12.6 MB of blocks mostly cache-resident)
 DCT_STOCH_LINEAR_TRAFFIC = (412.2e6, "tex2d", "7d1317b050bfcc50")
+# the EWA workload's stochastic kernel at max anisotropy 8 (24-byte records
+# in, 16-byte results out, one texel of the pyramid per lookup)
+EWA_STOCH_TRAFFIC = (536.7e6, "ewa", "7cfe900cd3e3c52a")
 
 
 def sources_sha(kind):
@@ -623,7 +627,7 @@ def run_ewa(args, torch, stf, synth):
                  "stochastic_over_deterministic_aniso64":
                      res["stoch_aniso64"]["lookups_per_s"] / res["det_aniso64"]["lookups_per_s"],
                  "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
+                              "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(EWA_STOCH_TRAFFIC)},
                  "cpu_baseline": None})
     tex.destroy()
     return line
