@@ -44,6 +44,8 @@ KERNEL_SOURCES = {
     "grid": ["filter3d.hip", "device_common.h", "interp.h", "stf_internal.h"],
     "tex2d": ["filter2d.hip", "dct_decode.h", "device_common.h", "interp.h", "stf_internal.h"],
     "ewa": ["ewa.hip", "device_common.h", "interp.h", "stf_internal.h"],
+    "shade": ["shade.hip", "device_common.h", "stf_internal.h"],
+    "neural": ["neural.hip", "device_common.h", "stf_internal.h"],
 }
 # the headline kernel (stochastic tricubic, binary32 grid, ray order)
 HEADLINE_TRAFFIC = {("f32", "ray"): (378.5e6, "grid", "613e7b250b4e1410")}
@@ -53,6 +55,18 @@ DCT_STOCH_LINEAR_TRAFFIC = (412.2e6, "tex2d", "7d1317b050bfcc50")
 # the EWA workload's stochastic kernel at max anisotropy 8 (24-byte records
 # in, 16-byte results out, one texel of the pyramid per lookup)
 EWA_STOCH_TRAFFIC = (536.7e6, "ewa", "7cfe900cd3e3c52a")
+# the Gaussian workload's FIS draw at sigma 0.5 on the DCT set (uv in, 9
+# results out, block lines mostly cache-resident)
+GAUSS_FIS_TRAFFIC = (416.4e6, "tex2d", "7d1317b050bfcc50")
+# the shading workload's filter-after-shade kernel (36-byte records, 16 taps
+# of the tiled material gathered per query, RGB out)
+SHADE_FAS_TRAFFIC = (3613.7e6, "shade", "2aeefab2f9320123")
+# the small 2D workload's stochastic bicubic (the 1 MiB texture fetched into
+# each XCD's L2 as its lookups touch it)
+TEX2D_STOCH_CUBIC_TRAFFIC = (6.90e6, "tex2d", "7d1317b050bfcc50")
+# the neural workload's deterministic bicubic decode (latent quads through the
+# caches, 8 channels out)
+NEURAL_DET_CUBIC_TRAFFIC = (5780.0e6, "neural", "afa71d1e5c1dbf5d")
 
 
 def sources_sha(kind):
@@ -442,7 +456,8 @@ def run_tex2d(args, torch, stf, synth):
     line.update({"variants": res,
                  "stochastic_over_deterministic": head["lookups_per_s"] / res["det_cubic"]["lookups_per_s"],
                  "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
+                              "frac": head["achieved_gbs"] / HBM_PEAK_GBS,
+                              "traffic": measured_traffic(TEX2D_STOCH_CUBIC_TRAFFIC)},
                  "cpu_baseline": None})
     tex.destroy()
     return line
@@ -582,7 +597,7 @@ def run_gauss(args, torch, stf, synth):
                  # streamed bytes only (uv in, results out), as on the DCT line
                  "roofline": {"bound": "hbm", "achieved": stream_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": stream_gbs / HBM_PEAK_GBS, "stream_bytes_per_lookup": stream_b,
-                              "traffic": None},
+                              "traffic": measured_traffic(GAUSS_FIS_TRAFFIC)},
                  "cpu_baseline": None})
     tex.destroy()
     return line
@@ -673,7 +688,7 @@ def run_shade(args, torch, stf, synth):
                  # material: the kernel waits on memory, not on its GGX arithmetic
                  "roofline": {"bound": "hbm", "achieved": fas["achieved_gbs"], "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": fas["achieved_gbs"] / HBM_PEAK_GBS,
-                              "traffic": None, "kernel": "filter_after_shade",
+                              "traffic": measured_traffic(SHADE_FAS_TRAFFIC), "kernel": "filter_after_shade",
                               "alu_tflops": fas["achieved_tflops"], "alu_peak_tflops": FP32_VECTOR_PEAK_TFLOPS},
                  "cpu_baseline": None})
     mat.destroy()
@@ -741,7 +756,7 @@ def run_neural(args, torch, stf, synth):
                  "psnr_db": 10 * np.log10(1.0 / mse),
                  "roofline": {"bound": "mfma", "achieved": head["achieved_tflops"], "peak": MFMA_BF16_PEAK_TFLOPS,
                               "unit": "TFLOP/s", "frac": head["achieved_tflops"] / MFMA_BF16_PEAK_TFLOPS,
-                              "traffic": None, "kernel": "det_cubic"},
+                              "traffic": measured_traffic(NEURAL_DET_CUBIC_TRAFFIC), "kernel": "det_cubic"},
                  "cpu_baseline": None})
     nt.destroy()
     return line
