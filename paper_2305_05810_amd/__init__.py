@@ -22,14 +22,15 @@ STF_FMT_F32, STF_FMT_F16, STF_FMT_BF16, STF_FMT_FP8_E4M3, STF_FMT_U8 = 0, 1, 2, 
 STF_LINEAR, STF_CUBIC_BSPLINE, STF_CUBIC_KEYS, STF_CUBIC_MITCHELL = 0, 1, 2, 3
 STF_GAUSS_FIS, STF_GAUSS_FIS_MEAN, STF_GAUSS_DISCRETE, STF_GAUSS_DISCRETE_MEAN = 0, 1, 2, 3
 POSITIVIZED_FILTERS = (STF_CUBIC_KEYS, STF_CUBIC_MITCHELL)
+STF_DETERMINISTIC, STF_STOCHASTIC, STF_STOCHASTIC_FIS = 0, 1, 2
+STF_SHADE_AFTER_FILTER, STF_FILTER_AFTER_SHADE, STF_SHADE_STOCHASTIC = 0, 1, 2
 
 
 def index_width(filter: int, dims: int) -> int:
     """int32 index entries per query in stochastic mode: the tap, or for the
     interpolating cubics the positive tap followed by the negative tap."""
     return 2 * dims if filter in POSITIVIZED_FILTERS else dims
-STF_DETERMINISTIC, STF_STOCHASTIC, STF_STOCHASTIC_FIS = 0, 1, 2
-STF_SHADE_AFTER_FILTER, STF_FILTER_AFTER_SHADE, STF_SHADE_STOCHASTIC = 0, 1, 2
+
 
 FORMATS = {"f32": STF_FMT_F32, "f16": STF_FMT_F16, "bf16": STF_FMT_BF16, "fp8_e4m3": STF_FMT_FP8_E4M3,
            "u8": STF_FMT_U8}
