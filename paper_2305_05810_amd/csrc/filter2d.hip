@@ -595,18 +595,22 @@ __device__ __forceinline__ int gauss_pick(const double (&m)[4], double u)
 }
 
 // The discrete pick with binary32 weights, for sigma >= 1/4 (every weight is
-// then at least e^-32: none underflows and none is clamped).  Each weight is
-// within 1.5e-5 relative of its binary64 value (|exponent| <= 32, a few ulps
-// in d^2, 1/(2 sigma^2) and expf), so u * total and the cumulative sums lie
-// within 3e-5 total of theirs; where u * total is at least total 2^-12 from
-// every cumulative sum, the pick is the binary64 pick.  Returns -1 otherwise.
+// then at least e^-32: none underflows and none is clamped).  A weight is
+// 2^(a log2 e) with a = -d^2 / (2 sigma^2), |a| <= 32, by the hardware's 2^x.
+// The exponent carries a few ulps from d^2, 1/(2 sigma^2) and the scaling by
+// log2 e (at most 1.4e-5 + 4.2e-6 absolute), and 2^x is within 8.5e-8
+// relative over [-64, 0] (measured on every binary32 value there against
+// binary64), so each weight is within 2e-5 relative of its binary64 value,
+// and u * total and the cumulative sums lie within 4e-5 total of theirs;
+// where u * total is at least total 2^-12 from every cumulative sum, the pick
+// is the binary64 pick.  Returns -1 otherwise.
 __device__ __forceinline__ int gauss_pick_fast(float t, float inv2s2, float u)
 {
     float m[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const float d = (float)(k - 1) - t;
-        m[k] = expf(-(d * d) * inv2s2);
+        m[k] = __builtin_amdgcn_exp2f((-(d * d) * inv2s2) * 1.44269504088896341f);
     }
     const float c1 = m[0], c2 = m[0] + m[1], c3 = (m[0] + m[1]) + m[2];
     const float total = c3 + m[3];
@@ -639,15 +643,20 @@ __global__ __launch_bounds__(BLOCK) void k_tex2d_gauss(Src S, const float* __res
             const float u0f = axis_uniform(b, 0), u1f = axis_uniform(b, 1);
             const double u0 = (double)u0f, u1 = (double)u1f;
             if constexpr (GMODE == GAUSS_FIS) {
-                // The offset is first formed in binary32.  1 - u0 is exact, and
-                // log, sqrt and sincos are within 2 ulp, so it lies within
-                // 5.5e-6 sigma texels of the binary64 offset (r <= 5.8).  A
-                // sample at least sigma 2^-14 from a texel edge therefore takes
-                // the same texel as the binary64 sample; nearer ones (about one
-                // query in 4,000 per unit sigma) redo the offset in binary64.
-                const float rf = sqrtf(-2.0f * logf(1.0f - u0f));
-                float sf, cf;
-                sincosf(6.28318530717958647692f * u1f, &sf, &cf);
+                // The offset is first formed in binary32 with the hardware's
+                // log2, square root, sine and cosine (the last two take the
+                // angle in turns, so u1 needs no scaling by 2 pi).  1 - u0 is
+                // exact, and over all 2^24 values a uniform can take, r is
+                // within 4.9e-7 of sqrt(-2 ln(1 - u0)) and the sine and cosine
+                // within 1.3e-7 of sin and cos(2 pi u1) (measured exhaustively
+                // against binary64), so with the products' rounding the offset
+                // lies within 2e-6 sigma texels of the binary64 offset
+                // (r <= 5.8).  A sample at least sigma 2^-14 from a texel edge
+                // therefore takes the same texel as the binary64 sample;
+                // nearer ones (about one query in 4,000 per unit sigma) redo
+                // the offset in binary64.
+                const float rf = __builtin_amdgcn_sqrtf(-1.38629436112f * __builtin_amdgcn_logf(1.0f - u0f));
+                const float sf = __builtin_amdgcn_sinf(u1f), cf = __builtin_amdgcn_cosf(u1f);
                 const double zx = (xe + (double)(sigma * (rf * cf))) + 0.5;
                 const double zy = (ye + (double)(sigma * (rf * sf))) + 0.5;
                 double fx = floor(zx), fy = floor(zy);
