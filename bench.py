@@ -51,19 +51,19 @@ KERNEL_SOURCES = {
 HEADLINE_TRAFFIC = {("f32", "ray"): (378.5e6, "grid", "613e7b250b4e1410")}
 # the DCT workload's stochastic bilinear kernel over the 4K frame (uv in, 9
 # results out; the 12.6 MB of blocks mostly cache-resident)
-DCT_STOCH_LINEAR_TRAFFIC = (412.2e6, "tex2d", "7d1317b050bfcc50")
+DCT_STOCH_LINEAR_TRAFFIC = (412.1e6, "tex2d", "228037f72afe4b2f")
 # the EWA workload's stochastic kernel at max anisotropy 8 (24-byte records
 # in, 16-byte results out, one texel of the pyramid per lookup)
 EWA_STOCH_TRAFFIC = (536.7e6, "ewa", "7cfe900cd3e3c52a")
 # the Gaussian workload's FIS draw at sigma 0.5 on the DCT set (uv in, 9
 # results out, block lines mostly cache-resident)
-GAUSS_FIS_TRAFFIC = (416.4e6, "tex2d", "7d1317b050bfcc50")
+GAUSS_FIS_TRAFFIC = (416.4e6, "tex2d", "228037f72afe4b2f")
 # the shading workload's filter-after-shade kernel (36-byte records, 16 taps
 # of the tiled material gathered per query, RGB out)
 SHADE_FAS_TRAFFIC = (3613.7e6, "shade", "2aeefab2f9320123")
 # the small 2D workload's stochastic bicubic (the 1 MiB texture fetched into
 # each XCD's L2 as its lookups touch it)
-TEX2D_STOCH_CUBIC_TRAFFIC = (6.90e6, "tex2d", "7d1317b050bfcc50")
+TEX2D_STOCH_CUBIC_TRAFFIC = (6.92e6, "tex2d", "228037f72afe4b2f")
 # the neural workload's deterministic bicubic decode (latent quads through the
 # caches, 8 channels out)
 NEURAL_DET_CUBIC_TRAFFIC = (5780.0e6, "neural", "afa71d1e5c1dbf5d")
