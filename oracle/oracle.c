@@ -489,7 +489,9 @@ int orc_positivized_wrs2d(int filter, double tx, double ty, double u, int* off_p
 /* draw of the degree n - 1 spline -- a box (one uniform minus 1/2) for the  */
 /* tent, a quadratic B-spline (three uniforms minus 3/2, the Cox-de Boor     */
 /* sum) for the cubic -- and the nearest texel floor(x' + 1/2) is read.      */
-/* Binary64, exact: x is binary32 and the uniforms lie on the 2^-24 grid.    */
+/* Binary64, summed in the order written: exact for |x| >= 2^-29 (x is       */
+/* binary32 and the uniforms lie on the 2^-24 grid); nearer 0 the sum x + s  */
+/* can round x's lowest bits away, and the tap is that of the rounded sum.   */
 /* Uniforms of axis a: hash index a (tent); a, 4 + a, 8 + a (cubic).         */
 /* ------------------------------------------------------------------------ */
 int orc_fis_tap(int filter, double x, uint64_t seed, uint32_t qid, int a)

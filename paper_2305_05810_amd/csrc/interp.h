@@ -224,19 +224,31 @@ __device__ __forceinline__ PosDraw<D> positivized_draw(const float (&t)[D], uint
 // Importance Sampling"): jitter the position by a draw of the B-spline one
 // degree lower -- a box (u - 1/2) for the tent, a quadratic B-spline (the sum
 // of three uniforms minus 3/2) for the cubic -- and read the nearest texel
-// floor(x' + 1/2).  Binary64 is exact here (binary32 x, uniforms on the 2^-24
-// grid), so the tap is a pure function of (x, seed, query).  Uniforms of axis
-// a: hash index a (tent); a, 4 + a, 8 + a (cubic).
+// floor(x' + 1/2), x' + 1/2 = x + s + 1/2 summed in binary64 in that order.
+// Uniforms of axis a: hash index a (tent); a, 4 + a, 8 + a (cubic).
+//
+// With the uniforms as integers m = u 2^24 and K their sum (one uniform for
+// the tent), s + 1/2 = K 2^-24 - c, c = 1 (cubic) or 0 (tent).  For |x| >=
+// 2^-29 the binary64 sum is exact (x is binary32, K 2^-24 lies on the 2^-24
+// grid and the result needs at most 53 bits), so the tap is floor(x + K 2^-24)
+// - c, formed in binary32 and integers: with Y = x 2^24 (exact) and H =
+// floor(x), R = floor(Y) - H 2^24 is an integer in [0, 2^24) that one fused
+// multiply-add gives exactly, and floor(x + K 2^-24) = H + floor((R + K) /
+// 2^24).  Below 2^-29 the binary64 sum can round x away, so it is evaluated
+// as written.
 template <bool CUBIC>
 __device__ __forceinline__ int fis_tap(float x, uint32_t b, int a)
 {
     const uint32_t base = pcg_base(b);
-    auto u = [&](uint32_t k) { return (double)uniform_from_base(base, k); };
-    double s;
-    if constexpr (CUBIC)
-        s = ((u((uint32_t)a) + u(4u + (uint32_t)a)) + u(8u + (uint32_t)a)) - 1.5;
-    else
-        s = u((uint32_t)a) - 0.5;
+    const uint32_t ua = (uint32_t)a;
+    auto m = [&](uint32_t k) { return pcg_from_base(base, k) >> 8; };
+    const uint32_t K = CUBIC ? (m(ua) + m(4u + ua)) + m(8u + ua) : m(ua);
+    if (__builtin_fabsf(x) >= 0x1p-29f) {
+        const float yi = __builtin_floorf(x * 16777216.0f), h = __builtin_floorf(x);
+        const uint32_t r = (uint32_t)__builtin_fmaf(h, -16777216.0f, yi);
+        return (int)h - (CUBIC ? 1 : 0) + (int)((r + K) >> 24);
+    }
+    const double s = (double)K * 0x1p-24 - (CUBIC ? 1.5 : 0.5);   // exact: the rounded sums of the uniforms are too
     return (int)__builtin_floor((double)x + s + 0.5);
 }
 

@@ -26,6 +26,11 @@ def tex_inputs():
     tex = synth.texture2d(72, 56, 4, seed=41)
     uv = synth.uv_queries(30000, seed=42) * np.float32(1.1) - np.float32(0.05)
     uv[:4] = [[np.nan, 0.5], [0.5, np.inf], [1e30, 0.5], [-0.7, 1.4]]
+    # raster positions near 0 (x = u 72 - 1/2): below 2^-29 the draw's binary64
+    # sum rounds x, at and above it the kernels take their exact integer path
+    h = np.float32(0.5 / 72)
+    uv[4:10, 0] = [h, np.nextafter(h, np.float32(0)), np.nextafter(h, np.float32(1)),
+                   h * np.float32(1 + 2 ** -20), h * np.float32(1 - 2 ** -20), h * np.float32(1 + 2 ** -10)]
     return tex, uv.astype(np.float32)
 
 
@@ -42,6 +47,10 @@ def test_fis_bspline_family_2d_and_3d(dev, tex_inputs, gf, of):
     g = synth.fbm_grid((64, 64, 64), base_period=16.0, seed=7)
     p = synth.uniform_box_queries(g.dims, 30000, seed=43, margin=3.0)
     p[:3] = [[np.nan, 1, 1], [1e9, 1, 1], [-0.5, -0.5, -0.5]]
+    # coordinates near 0, on both sides of 2^-29 (the exact integer path's bound)
+    tiny = np.array([1e-30, -1e-30, 2.0 ** -30, -2.0 ** -30, 2.0 ** -29, -2.0 ** -29, 3e-9, -3e-9, -1e-6, 0.0, -0.0,
+                     -2.0 ** -29 * (1 + 2.0 ** -23)], np.float32)
+    p[3:3 + 3 * len(tiny)] = np.repeat(tiny[:, None], 3, axis=1).repeat(3, axis=0)
     tg = stf.stf_create_sparse_grid3d(g.dims, stf.STF_FMT_F32, g.origins, g.values)
     og = oracle.Grid(g.dims, oracle.F32, g.origins, g.values)
     q = torch.from_numpy(p).to(dev)
