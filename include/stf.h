@@ -109,7 +109,9 @@ typedef enum {
                                 B-spline one degree lower (u - 1/2 for the tent; u_a + u_b + u_c - 3/2,
                                 a quadratic B-spline, for the cubic) and the nearest texel
                                 floor(x' + 1/2) read; the same tap distribution as STF_STOCHASTIC,
-                                no weights evaluated.  Decided in binary64 (exact). */
+                                no weights evaluated.  The tap is floor((x + s) + 1/2) evaluated in
+                                binary64 in that order: exact for |x| >= 2^-29, where the kernels
+                                form it in binary32 and integers with the same result. */
 } stf_mode;
 
 typedef enum {
