@@ -27,6 +27,48 @@ def workload():
     return grid, pts, qids
 
 
+@pytest.fixture(scope="module")
+def medium(workload):
+    """The in-medium stream of the same grid: 16,777,216 ray samples whose 4^3
+    tap blocks meet a stored leaf, so every lookup reads texels."""
+    grid = workload[0]
+    pts = synth.medium_ray_queries(grid, 1 << 24, seed=4)
+    rng = np.random.default_rng(13)
+    qids = np.sort(rng.choice(pts.shape[0], 1 << 16, replace=False))
+    return pts, qids
+
+
+@pytest.mark.parametrize("fmt", ["f32", "fp8_e4m3"])
+def test_full_size_in_medium(dev, workload, medium, fmt):
+    # The stream the in-medium benchmark line times, in the same single-call
+    # launch: every lookup walks to a leaf and reads stored texels.
+    grid = workload[0]
+    pts, qids = medium
+    raw = grid.encoded(fmt)
+    tex = stf.stf_create_sparse_grid3d(DIMS, stf.FORMATS[fmt], grid.origins, raw)
+    og = oracle.Grid(DIMS, ORC_FMT[fmt], grid.origins, raw)
+    n = pts.shape[0]
+    print(f"in-medium {fmt}: {n} queries, {qids.size} sampled", flush=True)
+    q = torch.from_numpy(pts).to(dev)
+    out = torch.empty((n, 1), dtype=torch.float32, device=dev)
+    idx = torch.empty((n, 3), dtype=torch.int32, device=dev)
+    seed = 0x5EED
+    for gf, of in ((stf.STF_CUBIC_BSPLINE, oracle.CUBIC), (stf.STF_LINEAR, oracle.LINEAR)):
+        stf.stf_filter(tex, q, gf, stf.STF_STOCHASTIC, seed, out, idx)
+        v = out[:, 0].cpu().numpy()
+        ix = idx.cpu().numpy()
+        ov, oi = og.filter_at(pts, qids, of, oracle.STOCH, seed)
+        assert np.array_equal(ix[qids], oi)
+        assert np.array_equal(v[qids], ov.astype(np.float32))
+        assert np.all(np.isfinite(v))
+        stf.stf_filter(tex, q, gf, stf.STF_DETERMINISTIC, 0, out)
+        d = out[:, 0].cpu().numpy().astype(np.float64)
+        od, _ = og.filter_at(pts, qids, of, oracle.DET, 0)
+        err = np.abs(d[qids] - od)
+        assert np.all(err <= 1e-6 * np.abs(od) + 1e-12), err.max()
+    tex.destroy()
+
+
 @pytest.mark.parametrize("fmt", ["f32", "f16", "bf16", "fp8_e4m3"])
 def test_full_size_parity(dev, workload, fmt):
     grid, pts, qids = workload
