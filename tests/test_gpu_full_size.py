@@ -1,5 +1,6 @@
 """Parity at the benchmark's full size: the 512^3 fBm grid with 16,777,216
-ray-ordered queries, in the same single-call launch the benchmark times.
+ray-ordered queries, and with the 16,777,216 samples of its in-medium stream,
+in the same single-call launches the benchmark times.
 The oracle recomputes 65,536 sampled queries (as members of the whole batch,
 since a query's draw depends on its index), index-exact and value-exact for
 the stochastic filters and within 1e-6 for the deterministic ones.  Properties
