@@ -3,8 +3,9 @@ through the C ABI against the FP64 oracle.
 
 Bar: FIS of the tent / cubic B-spline -- taps and values exactly equal to the
 oracle's (the tap is the binary64 floor(x + s + 1/2) on both sides; the
-kernels form it in binary32 and integers where that sum is exact, |x| >= 2^-29); Gaussian FIS and discrete sampling --
-taps equal to the oracle's except where the oracle's binary64 sample lies
+kernels form it in binary32 and integers where that sum is exact, |x| >=
+2^-29); Gaussian FIS and discrete sampling -- taps equal to the oracle's
+except where the oracle's binary64 sample lies
 within 1e-9 of a decision boundary (transcendental functions round
 differently on the two sides), values the texel at the tap; Gaussian means --
 within 1e-6 of the oracle relative to sum |w t| (= the value here: weights
