@@ -350,6 +350,11 @@ void worker_main(stf_server* s)
             s->n_rounds += 1;
         }
         if (e != hipSuccess) {
+            // let whatever the failed round did enqueue drain first, so that no
+            // launch or copy still writes into a caller's buffer after its
+            // request has been reported as failed
+            (void)hipStreamSynchronize(s->stream);
+            (void)hipGetLastError();
             std::lock_guard<std::mutex> lk(s->mu);
             record_failure(s, "serving round failed", e);
             for (Request* r : s->resident) {
