@@ -215,13 +215,19 @@ void worker_main(stf_server* s)
         std::vector<Request*> round_reqs;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            // retire cancelled residents once no launch of theirs is in flight
-            // (the stream is in order: a later round's event implies earlier ones)
+            // retire cancelled residents once no copy or launch of theirs is in
+            // flight (the stream is in order: a later event implies earlier work)
             for (size_t k = 0; k < s->resident.size();) {
                 Request* r = s->resident[k];
-                bool quiet = r->last_round < 0 || s->round - r->last_round >= RING ||
-                             hipEventQuery(s->round_ev[r->last_round % RING]) == hipSuccess;
-                if (r->cancel && r->state == RESIDENT && quiet) {
+                bool quiet = false;
+                if (r->cancel && r->state == RESIDENT) {
+                    if (r->last_round >= 0)   // launched: the event of its last round
+                        quiet = s->round - r->last_round >= RING ||
+                                hipEventQuery(s->round_ev[r->last_round % RING]) == hipSuccess;
+                    else   // admitted, never launched: only the staging copy of host queries, which done_ev marks
+                        quiet = (r->flags & STF_SERVE_QUERIES_ON_DEVICE) || hipEventQuery(r->done_ev) == hipSuccess;
+                }
+                if (quiet) {
                     unlist_resident(s, r);   // the last entry moves to k
                     retire(s, r, CANCELLED, now_s());
                 } else {
@@ -275,9 +281,14 @@ void worker_main(stf_server* s)
         }
         hipError_t e = hipSuccess;
         for (Request* r : admitted)
-            if (!(r->flags & STF_SERVE_QUERIES_ON_DEVICE) && e == hipSuccess)
+            if (!(r->flags & STF_SERVE_QUERIES_ON_DEVICE) && e == hipSuccess) {
                 e = hipMemcpyAsync((void*)r->q_dev, r->q_user, (size_t)r->n * 4 * r->dims, hipMemcpyHostToDevice,
                                    s->stream);
+                // marks the copy, so that a request cancelled before its first
+                // launch is retired (and its caller told) only once the copy
+                // has read the caller's queries
+                if (e == hipSuccess) e = hipEventRecord(r->done_ev, s->stream);
+            }
         if (!round_reqs.empty() && e == hipSuccess) {
             // at most two rounds in flight; the descriptor slot of round - RING is free
             int slot = (int)(s->round % RING);
