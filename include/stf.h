@@ -516,7 +516,9 @@ stf_status stf_server_poll(stf_server* s, uint64_t ticket, int32_t* done);
  * values above 1e6 (or HUGE_VAL) wait without a deadline. */
 stf_status stf_server_wait(stf_server* s, uint64_t ticket, double timeout_s);
 /* A pending request is dropped at once; a resident one gets no further
- * chunks and is retired when its launches are done. */
+ * chunks and is retired once none of its copies or launches is in flight
+ * (the staging copy of host queries included), so its buffers may be freed
+ * as soon as poll or wait reports it cancelled. */
 stf_status stf_server_cancel(stf_server* s, uint64_t ticket);
 /* Forget a finished request (its ticket becomes unknown). */
 stf_status stf_server_release(stf_server* s, uint64_t ticket);
