@@ -235,23 +235,37 @@ _DTYPES = {"queries": "float32", "sorted_queries": "float32", "sorted_out": "flo
            "positions": "int32", "sum": "float64", "sumsq": "float64", "workspace": "uint8"}
 
 
+_TORCH_DTYPES = None
+
+
 def _dev_ptr(t, name):
+    global _TORCH_DTYPES
     if t is None:
         return None
     if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
-    want = _DTYPES[name]
-    if str(t.dtype) != "torch." + want:
-        raise ValueError(f"{name} must be {want}, not {t.dtype}")
+    if _TORCH_DTYPES is None:
+        import torch
+        _TORCH_DTYPES = {k: getattr(torch, v) for k, v in _DTYPES.items()}
+    if t.dtype != _TORCH_DTYPES[name]:
+        raise ValueError(f"{name} must be {_DTYPES[name]}, not {t.dtype}")
     return t.data_ptr()
 
 
 def _stream(stream):
+    """The HIP stream to launch on: the given torch stream, else torch's
+    current stream on the current device (read as a raw handle when torch
+    offers that, which skips building a Stream object: ~0.3 instead of ~3 us
+    per call, which matters for small batches)."""
+    if stream is not None:
+        return stream.cuda_stream
     import torch
-    s = torch.cuda.current_stream() if stream is None else stream
-    return s.cuda_stream
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return raw(torch.cuda.current_device())
+    return torch.cuda.current_stream().cuda_stream
 
 
 def _check_queries(tex: Texture, queries, n: int):

@@ -308,3 +308,23 @@ def test_neural_ragged_batches(dev, n):
         assert np.abs(out.cpu().numpy() - od).max() < 1e-2
         assert _tail_ok(ob, n, FILL)
     nt.destroy()
+
+
+def test_binding_launches_on_the_current_stream(dev, grid):
+    # The binding reads torch's current stream as a raw handle; it must be the
+    # stream torch itself reports, also inside a stream context, and a batch
+    # launched there must be complete once that stream is synchronised.
+    _, t, _, p = grid
+    q = torch.from_numpy(np.ascontiguousarray(p[:4096])).to(dev)
+    assert stf._stream(None) == torch.cuda.current_stream().cuda_stream
+    ref = torch.empty((4096, 1), dtype=torch.float32, device=dev)
+    stf.stf_filter(t, q, stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 5, ref)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    out = torch.full((4096, 1), -1.0, dtype=torch.float32, device=dev)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        assert stf._stream(None) == side.cuda_stream
+        stf.stf_filter(t, q, stf.STF_CUBIC_BSPLINE, stf.STF_STOCHASTIC, 5, out)
+    side.synchronize()
+    assert torch.equal(torch.nan_to_num(out, nan=-7.0), torch.nan_to_num(ref, nan=-7.0))   # NaN for the fixture's non-finite queries
