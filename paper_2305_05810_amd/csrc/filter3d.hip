@@ -110,7 +110,6 @@ __device__ __forceinline__ void grid_stochastic_block(const GridView& g, const f
     uint32_t roff[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-        int32_t i = first + k * BLOCK;
         int c0 = 0, c1 = 0, c2 = 0;
         float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f;
         fin[k] = cell_of(p[k][0], c0, t0) & cell_of(p[k][1], c1, t1) & cell_of(p[k][2], c2, t2);
@@ -171,7 +170,6 @@ __device__ __forceinline__ void grid_stochastic_block(const GridView& g, const f
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-        int32_t i = first + k * BLOCK;
         if (!live[k]) continue;
         __builtin_nontemporal_store(fin[k] ? v[k] : __builtin_nanf(""), out + oi[k]);
         if (idx) {
