@@ -9,7 +9,6 @@ import torch
 from scipy import ndimage
 
 import oracle
-import synth
 
 
 def _small(seed=1, LW=4, W=16, scale=0.3):
